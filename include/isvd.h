@@ -1,0 +1,216 @@
+/*
+ * isvd.h -- C ABI of the MI355X incremental-SVD engine (libisvd.so).
+ *
+ * The engine maintains, for every data stream, a rank-k truncated SVD
+ * A_t ~ U_t Sigma_t V_t^T of a dense matrix A_t that grows by appended rows
+ * and columns and changes by single-entry updates, following the paper's
+ * problem setting (Section 2.1) and its engine loop (Algorithm 1):
+ *
+ *   isvd_init          (U, Sigma, V) = TruncatedSVD(A_0, k), A = A_0      (Alg. 1 init)
+ *   isvd_append_row    A <- [A; x^T],  RowAppendUpdate                     (Sec. 2.2.1, Alg. A1)
+ *   isvd_append_col    A <- [A, y],    ColAppendUpdateViaTranspose         (Sec. 2.2.2, Alg. A2)
+ *   isvd_update_entry  A_ij += delta,  RankOneUpdate: U' S' V'^T =
+ *                      P_U (A_hat + delta e_i e_j^T) P_V                   (Sec. 2.3, eq. rank1-projection)
+ *   isvd_refresh       (U, Sigma, V) = TruncatedSVD(A_t, k)                 (Sec. 2.4.1)
+ *   isvd_metrics       N_t, EVR, errors, angles, timings                  (Sec. 2.4.2, 2.5)
+ *   isvd_tick          one batched step: many streams' updates in one launch sequence
+ *
+ * Every update truncates back to the stream's rank and then evaluates the
+ * stream's refresh policy (Section 3); a policy that fires refreshes the
+ * stream before its next update.
+ *
+ * Conventions
+ *  - All functions return an isvd_status (0 = success, < 0 = error) and never
+ *    throw; isvd_last_error() describes the most recent failure on the
+ *    calling thread.  On any error no state is changed unless stated.
+ *  - Matrices are row-major.  `lda`/`ldu`/`ldv` are leading dimensions in
+ *    elements.  dtype is ISVD_DTYPE_F32 or ISVD_DTYPE_F64.
+ *  - Payloads (A_0, x, y) are borrowed: `on_device` = 0 means a host pointer
+ *    (copied before the call returns), 1 means a device pointer on the
+ *    engine's GPU, read by kernels ordered on `hip_stream`; the caller keeps
+ *    it alive and unmodified until that stream has passed the call.
+ *  - `hip_stream` is a hipStream_t (NULL = the default stream).  All device
+ *    work of a call is ordered on it; calls return without waiting for the
+ *    GPU unless stated.
+ *  - The engine owns all per-stream device state (A, U, V, Sigma, trackers).
+ *    One host thread at a time may use an engine.
+ *  - Non-finite entries of a host payload are caught before any work is
+ *    enqueued (ISVD_E_NONFINITE).  In a device payload they are caught on
+ *    the device: the update is rejected and the stream's state is left as it
+ *    was; the stream then rejects every further update until the next
+ *    isvd_metrics call, which reports ISVD_E_NONFINITE in `status` (with the
+ *    count in `n_rejected`), re-synchronises the host's view of the shape
+ *    and re-opens the stream.
+ */
+#ifndef ISVD_H
+#define ISVD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct isvd_engine isvd_engine;   /* opaque */
+typedef int64_t isvd_id;                  /* stream handle, >= 0 */
+typedef int32_t isvd_status;
+
+enum {
+    ISVD_OK = 0,
+    ISVD_E_INVAL = -1,      /* bad argument (null pointer, k out of range, bad enum) */
+    ISVD_E_SHAPE = -2,      /* payload length differs from the stream's n_t (row) or m_t (column) */
+    ISVD_E_RANGE = -3,      /* entry index outside [0, m_t) x [0, n_t) */
+    ISVD_E_NONFINITE = -4,  /* payload or delta not finite; update rejected */
+    ISVD_E_NOMEM = -5,      /* device allocation failed */
+    ISVD_E_BUDGET = -6,     /* the stream would exceed the engine's HBM budget */
+    ISVD_E_DEVICE = -7,     /* HIP runtime error */
+    ISVD_E_STATE = -8,      /* unknown / released stream id, or engine in wrong mode */
+    ISVD_E_CONVERGE = -9,   /* Jacobi core or refresh did not converge */
+    ISVD_E_CAPACITY = -10   /* the stream reached its row / column capacity */
+};
+
+enum { ISVD_DTYPE_F32 = 0, ISVD_DTYPE_F64 = 1 };
+
+/* Storage / arithmetic of a stream.  The core SVD, the residual norm, the
+ * re-orthogonalisation pass and all trackers are FP64 in every mode. */
+enum {
+    ISVD_FP64 = 0,          /* A, U, V and all products in FP64 */
+    ISVD_FP32 = 1           /* A, U, V, projections and rotations in FP32 */
+};
+
+enum { ISVD_ROW = 0, ISVD_COL = 1, ISVD_ENTRY = 2 };
+
+enum {
+    ISVD_POL_NONE = 0,
+    ISVD_POL_PERIODIC = 1,  /* refresh iff t = 0 mod period (eq. periodic-refresh-rule) */
+    ISVD_POL_ERROR = 2,     /* at t = 0 mod check_every: refresh iff frob_ratio > gamma
+                               and t - t_last >= t_min (eq. error-refresh-rule) */
+    ISVD_POL_ANGLE = 3,     /* refresh iff theta_ref > theta_max (Section 3.3) */
+    ISVD_POL_ADAPTIVE = 4   /* EVR / novelty rank rule + periodic refresh (Section 3.4) */
+};
+
+typedef struct {
+    int32_t kind;           /* ISVD_POL_* */
+    int32_t angle_scope;    /* columns the angle is measured on; 0 = leading gap-separated */
+    int64_t period;         /* PERIODIC / ADAPTIVE refresh period (0 = none) */
+    int64_t check_every;    /* ERROR: evaluation cadence */
+    int64_t t_min;          /* ERROR / ANGLE: minimum spacing between refreshes */
+    double gamma;           /* ERROR threshold on frob_ratio */
+    double theta_max;       /* ANGLE threshold, radians */
+    double tau, band, eta;  /* ADAPTIVE: EVR target, hysteresis band, novelty threshold */
+    int32_t k_min, k_max;   /* ADAPTIVE rank bounds (k_max also sizes the buffers) */
+} isvd_policy;
+
+typedef struct {
+    int64_t m0, n0;         /* shape of A_0 */
+    int64_t m_cap, n_cap;   /* capacity: largest m_t / n_t the stream may reach (>= m0, n0) */
+    int32_t k;              /* target rank, 1 <= k <= min(m0, n0, 96) */
+    int32_t precision;      /* ISVD_FP64 / ISVD_FP32 */
+    double tol_rel;         /* new direction iff rho > tol_rel * ||x|| (0 = 1e-10 FP64, 1e-5 FP32) */
+    int32_t refresh_iters;  /* subspace iterations per refresh (-1 = default) */
+    int32_t oversample;     /* refresh block size = min(n, k + oversample) (-1 = default) */
+    isvd_policy policy;
+} isvd_config;
+
+typedef struct {
+    int64_t t, m, n;        /* updates applied, current shape */
+    int64_t n_refresh, t_last_refresh, n_rejected;
+    int32_t k;              /* current rank */
+    int32_t status;         /* ISVD_OK or the error of the last rejected request */
+    int32_t sweeps;         /* Jacobi sweeps of the last core */
+    int32_t new_direction;  /* last append: rho > tol */
+    double fro2_A;          /* N_t = ||A_t||_F^2 (recurrences of Section 2.5.2) */
+    double sigma2_sum;      /* ||Sigma_t||_F^2 */
+    double evr;             /* eq. evr */
+    double rho, novelty;    /* last append: ||z|| and ||z|| / ||x|| */
+    double frob_error;      /* E_inc = ||A_t - U S V^T||_F      (NaN unless compute_exact) */
+    double frob_opt;        /* E_opt from the refresh's Ritz values (NaN unless compute_exact) */
+    double frob_gap, frob_ratio;   /* eq. frob-ratio; NaN if undefined or not computed */
+    double ortho_U, ortho_V;       /* max |(Q^T Q - I)_ij| (NaN unless compute_exact) */
+    double update_time_us;  /* wall-clock of the last immediate-mode update (host-timed) */
+    double opt_time_us;     /* wall-clock of the last refresh (host-timed) */
+} isvd_metrics_t;
+
+/* One request of a batched tick. */
+typedef struct {
+    isvd_id id;
+    int32_t kind;           /* ISVD_ROW / ISVD_COL / ISVD_ENTRY */
+    int32_t dtype;          /* payload dtype; must equal the stream's storage type */
+    const void* payload;    /* device pointer, length n_t (ROW) or m_t (COL); unused for ENTRY */
+    int64_t len;
+    int64_t i, j;
+    double delta;
+} isvd_request;
+
+/* Engine on HIP device `device`.  hbm_budget_bytes bounds the device memory
+ * of all streams together (0 = no bound). */
+isvd_status isvd_engine_create(int32_t device, uint64_t hbm_budget_bytes, isvd_engine** out);
+isvd_status isvd_engine_destroy(isvd_engine* eng);
+
+/* Bytes of device memory isvd_init would reserve for `cfg` (0 on invalid cfg). */
+uint64_t isvd_stream_bytes(const isvd_config* cfg);
+
+/* Algorithm 1 init: allocate the stream, copy A_0 (m0 x n0, leading dim lda,
+ * in `dtype`) into its A, compute TruncatedSVD(A_0, k) with the refresh
+ * routine, set N_0 = ||A_0||_F^2 and U_ref = U.  Waits for the device.
+ * Errors: INVAL (cfg), BUDGET, NOMEM, DEVICE, CONVERGE. */
+isvd_status isvd_init(isvd_engine* eng, const isvd_config* cfg, const void* A0, int64_t lda,
+                      int32_t dtype, int32_t on_device, void* hip_stream, isvd_id* out);
+
+/* Row append (Alg. A1) + truncation + policy.  x has n = n_t entries.
+ * Errors: STATE, SHAPE, CAPACITY, INVAL (dtype), DEVICE. */
+isvd_status isvd_append_row(isvd_engine* eng, isvd_id id, const void* x, int64_t n,
+                            int32_t dtype, int32_t on_device, void* hip_stream);
+
+/* Column append (Alg. A2) + truncation + policy.  y has m = m_t entries. */
+isvd_status isvd_append_col(isvd_engine* eng, isvd_id id, const void* y, int64_t m,
+                            int32_t dtype, int32_t on_device, void* hip_stream);
+
+/* Rank-1 entry update (Alg. A3): A_ij += delta, then the in-subspace core
+ * update.  Errors: STATE, RANGE (i, j), NONFINITE (delta), DEVICE. */
+isvd_status isvd_update_entry(isvd_engine* eng, isvd_id id, int64_t i, int64_t j, double delta,
+                              void* hip_stream);
+
+/* Refresh (Section 2.4.1): recompute TruncatedSVD(A_t, k_t) by block subspace
+ * iteration warm-started from V_t (exact when the block spans all n_t
+ * columns); store_reference != 0 also sets U_ref = U.  Waits for the device. */
+isvd_status isvd_refresh(isvd_engine* eng, isvd_id id, int32_t store_reference, void* hip_stream);
+
+/* Metrics of the stream.  Waits for the device.  compute_exact != 0 adds
+ * E_inc (one pass over A), E_opt (a refresh-style subspace iteration that
+ * does not replace the factors) and the orthogonality of U and V. */
+isvd_status isvd_metrics(isvd_engine* eng, isvd_id id, int32_t compute_exact, void* hip_stream,
+                         isvd_metrics_t* out);
+
+/* FP64 host copies of the factors: U (m_t x k, ldu), S (k), V (n_t x k, ldv).
+ * Any pointer may be NULL to skip it.  Waits for the device. */
+isvd_status isvd_get_factors(isvd_engine* eng, isvd_id id, double* U, int64_t ldu, double* S,
+                             double* V, int64_t ldv, void* hip_stream);
+
+/* FP64 host copy of A_t (m_t x n_t, lda).  Waits for the device. */
+isvd_status isvd_get_matrix(isvd_engine* eng, isvd_id id, double* A, int64_t lda, void* hip_stream);
+
+/* Current shape and rank (host-side view; no device access). */
+isvd_status isvd_shape(isvd_engine* eng, isvd_id id, int64_t* m, int64_t* n, int32_t* k);
+
+/* Free the stream's device memory; the id becomes invalid. */
+isvd_status isvd_release(isvd_engine* eng, isvd_id id);
+
+/* Batched tick: apply `count` requests to `count` distinct streams as one
+ * sequence of batched launches on hip_stream (per-stream order is the order
+ * of successive ticks), then evaluate each stream's policy and refresh the
+ * streams whose policy fired.  Payloads must be device pointers in the
+ * stream's storage dtype.  Validation happens for all requests before any
+ * work is enqueued; on error nothing is applied.  Does not wait for the
+ * device unless a policy needs device metrics.
+ * Errors: STATE, SHAPE, RANGE, CAPACITY, INVAL (duplicate stream, dtype). */
+isvd_status isvd_tick(isvd_engine* eng, int32_t count, const isvd_request* reqs, void* hip_stream);
+
+/* Message for the last error on this thread ("" if none). */
+const char* isvd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ISVD_H */

@@ -1,0 +1,990 @@
+// libisvd: host side of the MI355X incremental-SVD engine and its C ABI.
+//
+// Per stream the engine keeps, in one device allocation:
+//   A (m_cap x n_cap, row-major), U and V in two buffers each (ping-pong:
+//   every rotation writes the other buffer, so the leading dimension can
+//   follow the rank), Sigma, the device header (rank, buffer index, N_t,
+//   trackers), the rotation matrices of the last core, projection sums and
+//   per-block partials, and a payload staging area.
+// Updates are a fixed launch sequence (projection pass 1, pass 2, core,
+// rotation) over request lists; a single update and a batched tick of many
+// streams use the same kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstddef>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/isvd.h"
+#include "isvd_common.h"
+#include "isvd_update.h"
+#include "isvd_refresh.h"
+
+using namespace isvd;
+
+namespace {
+
+thread_local std::string g_err;
+
+isvd_status fail(isvd_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                      \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(ISVD_E_DEVICE, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), \
+                        __FILE__, __LINE__);                                               \
+    } while (0)
+
+#define ST_TRY(expr)                     \
+    do {                                 \
+        isvd_status s_ = (expr);         \
+        if (s_ != ISVD_OK) return s_;    \
+    } while (0)
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+int bucket_for(int kmax) {
+    if (kmax <= 8) return 8;
+    if (kmax <= 16) return 16;
+    if (kmax <= 32) return 32;
+    if (kmax <= 64) return 64;
+    return 128;
+}
+
+// ------------------------------------------------------------------ streams
+struct Layout {
+    size_t hdr, rs, S, p, p2, counters, partials, QU, QV, stage, U0, U1, V0, V1, Uref, A, total;
+};
+
+struct Stream {
+    isvd_config cfg;
+    int esz = 4;          // bytes per storage element
+    int kc = 64;          // rank bucket (capacity of U / V rows)
+    int k_target = 0;     // rank the truncation keeps
+    int64_t m = 0, n = 0, t = 0;
+    int64_t n_refresh = 0, t_last = 0;
+    int64_t ntiles_max = 0;
+    char* base = nullptr;
+    Layout L{};
+    DevHeader* hdr = nullptr;
+    ReqScratch* rs = nullptr;
+    double *S = nullptr, *p = nullptr, *p2 = nullptr, *partials = nullptr;
+    unsigned* counters = nullptr;
+    void *QU = nullptr, *QV = nullptr, *stage = nullptr, *A = nullptr, *Uref = nullptr;
+    void* U[2] = {nullptr, nullptr};
+    void* V[2] = {nullptr, nullptr};
+    hipEvent_t ev_u0 = nullptr, ev_u1 = nullptr, ev_r0 = nullptr, ev_r1 = nullptr;
+    bool have_update_time = false, have_refresh_time = false;
+    bool live = false;
+};
+
+Layout make_layout(const isvd_config& c, int esz, int kc, int64_t* ntiles_max) {
+    Layout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align_up(off + bytes, 256);
+        return o;
+    };
+    const int64_t mx = std::max(c.m_cap, c.n_cap);
+    const int64_t nt = cdiv(mx, kProjTile);
+    *ntiles_max = nt;
+    L.hdr = take(sizeof(DevHeader));
+    L.rs = take(sizeof(ReqScratch));
+    L.S = take(sizeof(double) * (kc + 2));
+    L.p = take(sizeof(double) * (kc + 4));
+    L.p2 = take(sizeof(double) * (kc + 4));
+    L.counters = take(sizeof(unsigned) * 4);
+    L.partials = take(sizeof(double) * (size_t)nt * (kc + 2));
+    L.QU = take((size_t)esz * (kc + 1) * kc);
+    L.QV = take((size_t)esz * (kc + 1) * kc);
+    L.stage = take((size_t)esz * mx);
+    L.U0 = take((size_t)esz * c.m_cap * kc);
+    L.U1 = take((size_t)esz * c.m_cap * kc);
+    L.V0 = take((size_t)esz * c.n_cap * kc);
+    L.V1 = take((size_t)esz * c.n_cap * kc);
+    L.Uref = take((size_t)esz * c.m_cap * kc);
+    L.A = take((size_t)esz * c.m_cap * c.n_cap);
+    L.total = off;
+    return L;
+}
+
+// ------------------------------------------------------- launch staging ring
+struct Slot {
+    char* host = nullptr;
+    char* dev = nullptr;
+    size_t cap = 0;
+    hipEvent_t ev = nullptr;
+    bool used = false;
+};
+
+// A group of requests of one (storage type, rank bucket), laid out in a slot.
+struct Group {
+    bool fp64;
+    int kc;
+    std::vector<Req> all;      // core + rotation list
+    std::vector<Req> proj;     // row / column appends
+    std::vector<int> pre_proj; // block prefix of the projection list (size proj+1)
+    std::vector<int> pre_rot;  // block prefix of the rotation list (size all+1)
+    size_t off_all = 0, off_proj = 0, off_pp = 0, off_pr = 0;
+    int core_lds_n = 0;
+};
+
+}  // namespace
+
+struct isvd_engine {
+    int device = 0;
+    uint64_t budget = 0, used = 0;
+    std::vector<Stream*> streams;
+    std::vector<Slot> ring;
+    size_t ring_next = 0;
+    // refresh workspace (sized for the largest refresh so far)
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+};
+
+namespace {
+
+isvd_status ensure_device(isvd_engine* e) {
+    HIP_TRY(hipSetDevice(e->device));
+    return ISVD_OK;
+}
+
+isvd_status get_stream(isvd_engine* e, isvd_id id, Stream** out) {
+    if (!e) return fail(ISVD_E_INVAL, "null engine");
+    if (id < 0 || id >= (isvd_id)e->streams.size() || !e->streams[id] || !e->streams[id]->live)
+        return fail(ISVD_E_STATE, "unknown or released stream id %lld", (long long)id);
+    *out = e->streams[id];
+    return ISVD_OK;
+}
+
+template <typename K>
+isvd_status allow_lds(K kern, size_t bytes) {
+    HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    return ISVD_OK;
+}
+
+size_t core_lds_bytes(int N) { return sizeof(double) * (size_t)(2 * N * N + 5 * N); }
+
+// Acquire a staging slot of at least `bytes`; waits for its previous use.
+isvd_status acquire_slot(isvd_engine* e, size_t bytes, Slot** out) {
+    Slot& s = e->ring[e->ring_next];
+    e->ring_next = (e->ring_next + 1) % e->ring.size();
+    if (s.used) HIP_TRY(hipEventSynchronize(s.ev));
+    if (s.cap < bytes) {
+        if (s.host) HIP_TRY(hipHostFree(s.host));
+        if (s.dev) HIP_TRY(hipFree(s.dev));
+        size_t cap = align_up(std::max(bytes, (size_t)4096), 4096);
+        HIP_TRY(hipHostMalloc((void**)&s.host, cap, hipHostMallocDefault));
+        HIP_TRY(hipMalloc((void**)&s.dev, cap));
+        s.cap = cap;
+    }
+    *out = &s;
+    return ISVD_OK;
+}
+
+// ---------------------------------------------------------- kernel dispatch
+template <typename T, int KC>
+isvd_status launch_group_phase(const Group& g, const char* dev, int phase, hipStream_t st) {
+    const Req* all = reinterpret_cast<const Req*>(dev + g.off_all);
+    const Req* proj = reinterpret_cast<const Req*>(dev + g.off_proj);
+    const int* pp = reinterpret_cast<const int*>(dev + g.off_pp);
+    const int* pr = reinterpret_cast<const int*>(dev + g.off_pr);
+    const int np = (int)g.proj.size(), na = (int)g.all.size();
+    if (phase == 0 && np > 0) {
+        k_proj1<T, KC><<<g.pre_proj[np], kThreads, 0, st>>>(proj, pp, np);
+    } else if (phase == 1 && np > 0) {
+        k_proj2<T, KC><<<g.pre_proj[np], kThreads, 0, st>>>(proj, pp, np);
+    } else if (phase == 2 && na > 0) {
+        size_t lds = core_lds_bytes(g.core_lds_n);
+        k_core<T, KC><<<na, kThreads, lds, st>>>(all);
+    } else if (phase == 3 && na > 0) {
+        k_rotate<T, KC><<<g.pre_rot[na], kThreads, 0, st>>>(all, pr, na);
+    }
+    HIP_TRY(hipGetLastError());
+    return ISVD_OK;
+}
+
+isvd_status launch_phase(const Group& g, const char* dev, int phase, hipStream_t st) {
+    if (g.fp64) {
+        switch (g.kc) {
+            case 8: return launch_group_phase<double, 8>(g, dev, phase, st);
+            case 16: return launch_group_phase<double, 16>(g, dev, phase, st);
+            case 32: return launch_group_phase<double, 32>(g, dev, phase, st);
+            case 64: return launch_group_phase<double, 64>(g, dev, phase, st);
+            default: return launch_group_phase<double, 128>(g, dev, phase, st);
+        }
+    }
+    switch (g.kc) {
+        case 8: return launch_group_phase<float, 8>(g, dev, phase, st);
+        case 16: return launch_group_phase<float, 16>(g, dev, phase, st);
+        case 32: return launch_group_phase<float, 32>(g, dev, phase, st);
+        case 64: return launch_group_phase<float, 64>(g, dev, phase, st);
+        default: return launch_group_phase<float, 128>(g, dev, phase, st);
+    }
+}
+
+template <typename T, int KC>
+isvd_status set_lds_limits_for() {
+    ST_TRY(allow_lds(k_core<T, KC>, core_lds_bytes(std::min(KC, 96) + 1)));
+    return ISVD_OK;
+}
+
+isvd_status set_lds_limits() {
+    ST_TRY((set_lds_limits_for<float, 8>()));
+    ST_TRY((set_lds_limits_for<float, 16>()));
+    ST_TRY((set_lds_limits_for<float, 32>()));
+    ST_TRY((set_lds_limits_for<float, 64>()));
+    ST_TRY((set_lds_limits_for<float, 128>()));
+    ST_TRY((set_lds_limits_for<double, 8>()));
+    ST_TRY((set_lds_limits_for<double, 16>()));
+    ST_TRY((set_lds_limits_for<double, 32>()));
+    ST_TRY((set_lds_limits_for<double, 64>()));
+    ST_TRY((set_lds_limits_for<double, 128>()));
+    ST_TRY(allow_lds(k_svd_small<float>, core_lds_bytes(kMaxBlock)));
+    ST_TRY(allow_lds(k_svd_small<double>, core_lds_bytes(kMaxBlock)));
+    ST_TRY(allow_lds(k_chol_inv<float>, sizeof(double) * 2 * kMaxBlock * kMaxBlock));
+    ST_TRY(allow_lds(k_chol_inv<double>, sizeof(double) * 2 * kMaxBlock * kMaxBlock));
+    return ISVD_OK;
+}
+
+// Build the request a single stream's update sends to the kernels.
+Req make_req(Stream& s, int kind, const void* payload, int64_t i, int64_t j, double delta, int k_keep) {
+    Req r{};
+    r.m = s.m;
+    r.n = s.n;
+    r.lda = s.cfg.n_cap;
+    r.i = i;
+    r.j = j;
+    r.delta = delta;
+    r.tol_rel = s.cfg.tol_rel;
+    r.kind = kind;
+    r.k_keep = k_keep;
+    r.proj_tiles = kind == kRow ? (int)cdiv(s.n, kProjTile) : kind == kCol ? (int)cdiv(s.m, kProjTile) : 0;
+    r.rot_tiles_u = (int)cdiv(s.m, rot_rows(s.kc));
+    r.hdr = s.hdr;
+    r.rs = s.rs;
+    r.A = s.A;
+    r.U[0] = s.U[0];
+    r.U[1] = s.U[1];
+    r.V[0] = s.V[0];
+    r.V[1] = s.V[1];
+    r.S = s.S;
+    r.p = s.p;
+    r.p2 = s.p2;
+    r.partials = s.partials;
+    r.counters = s.counters;
+    r.QU = s.QU;
+    r.QV = s.QV;
+    r.payload = payload;
+    return r;
+}
+
+int rot_tiles(const Req& r, int kc) { return r.rot_tiles_u + (int)cdiv(r.n, rot_rows(kc)); }
+
+// Lay out groups in a slot, upload, and launch the four phases.
+isvd_status run_groups(isvd_engine* e, std::vector<Group>& groups, hipStream_t st) {
+    size_t off = 0;
+    auto take = [&](size_t b) {
+        size_t o = off;
+        off = align_up(off + b, 64);
+        return o;
+    };
+    for (Group& g : groups) {
+        g.pre_proj.assign(g.proj.size() + 1, 0);
+        for (size_t q = 0; q < g.proj.size(); ++q) g.pre_proj[q + 1] = g.pre_proj[q] + g.proj[q].proj_tiles;
+        g.pre_rot.assign(g.all.size() + 1, 0);
+        for (size_t q = 0; q < g.all.size(); ++q) g.pre_rot[q + 1] = g.pre_rot[q] + rot_tiles(g.all[q], g.kc);
+        g.off_all = take(sizeof(Req) * g.all.size());
+        g.off_proj = take(sizeof(Req) * g.proj.size());
+        g.off_pp = take(sizeof(int) * g.pre_proj.size());
+        g.off_pr = take(sizeof(int) * g.pre_rot.size());
+        g.core_lds_n = std::min(g.kc, 96) + 1;
+    }
+    Slot* slot = nullptr;
+    ST_TRY(acquire_slot(e, off, &slot));
+    for (Group& g : groups) {
+        if (!g.all.empty()) memcpy(slot->host + g.off_all, g.all.data(), sizeof(Req) * g.all.size());
+        if (!g.proj.empty()) memcpy(slot->host + g.off_proj, g.proj.data(), sizeof(Req) * g.proj.size());
+        memcpy(slot->host + g.off_pp, g.pre_proj.data(), sizeof(int) * g.pre_proj.size());
+        memcpy(slot->host + g.off_pr, g.pre_rot.data(), sizeof(int) * g.pre_rot.size());
+    }
+    HIP_TRY(hipMemcpyAsync(slot->dev, slot->host, off, hipMemcpyHostToDevice, st));
+    for (int phase = 0; phase < 4; ++phase)
+        for (Group& g : groups) ST_TRY(launch_phase(g, slot->dev, phase, st));
+    HIP_TRY(hipEventRecord(slot->ev, st));
+    slot->used = true;
+    return ISVD_OK;
+}
+
+// ---------------------------------------------------------------- refresh
+struct WsLayout {
+    size_t X, Y, Zp, Gp, G, R, Racc, Rtmp, RinvT, QU, QV, Sr, flag, sweeps, fro, total;
+};
+
+WsLayout ws_layout(int64_t m, int64_t n, int b, int esz) {
+    WsLayout w{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align_up(off + bytes, 256);
+        return o;
+    };
+    const int64_t nchunk_tn = std::min<int64_t>(32, cdiv(m, kGemmK));
+    const int64_t nchunk_g = cdiv(std::max(m, n), kChunkRows);
+    w.X = take((size_t)esz * n * b);
+    w.Y = take((size_t)esz * m * b);
+    w.Zp = take(sizeof(double) * (size_t)nchunk_tn * n * b);
+    w.Gp = take(sizeof(double) * (size_t)nchunk_g * b * b);
+    w.G = take(sizeof(double) * b * b);
+    w.R = take(sizeof(double) * b * b);
+    w.Racc = take(sizeof(double) * b * b);
+    w.Rtmp = take(sizeof(double) * b * b);
+    w.RinvT = take((size_t)esz * b * b);
+    w.QU = take((size_t)esz * b * 128);
+    w.QV = take((size_t)esz * b * 128);
+    w.Sr = take(sizeof(double) * 128);
+    w.flag = take(sizeof(int) * 4);
+    w.sweeps = take(sizeof(int) * 4);
+    w.fro = take(sizeof(double) * (size_t)cdiv(m, kChunkRows));
+    w.total = off;
+    return w;
+}
+
+isvd_status ensure_ws(isvd_engine* e, size_t bytes) {
+    if (e->ws_bytes >= bytes) return ISVD_OK;
+    if (e->ws) {
+        HIP_TRY(hipDeviceSynchronize());
+        HIP_TRY(hipFree(e->ws));
+        e->ws = nullptr;
+        e->ws_bytes = 0;
+    }
+    if (hipMalloc((void**)&e->ws, bytes) != hipSuccess) {
+        e->ws = nullptr;
+        return fail(ISVD_E_NOMEM, "refresh workspace of %zu bytes", bytes);
+    }
+    e->ws_bytes = bytes;
+    return ISVD_OK;
+}
+
+__global__ void k_set_header(DevHeader* hdr, int k, int ld, int flip, int bump_t) {
+    if (threadIdx.x == 0) {
+        hdr->k = k;
+        hdr->ld = ld;
+        if (flip) hdr->cur ^= 1;
+        if (bump_t) hdr->t += 1;
+    }
+}
+
+template <typename T>
+isvd_status cholqr2(isvd_engine* e, const WsLayout& w, T* Y, int64_t rows, int b, bool want_R, hipStream_t st) {
+    char* ws = e->ws;
+    double* Gp = (double*)(ws + w.Gp);
+    double* G = (double*)(ws + w.G);
+    double* R = (double*)(ws + w.R);
+    double* Racc = (double*)(ws + w.Racc);
+    double* Rtmp = (double*)(ws + w.Rtmp);
+    T* RinvT = (T*)(ws + w.RinvT);
+    int* flag = (int*)(ws + w.flag);
+    const int nchunk = (int)cdiv(rows, kChunkRows);
+    for (int pass = 0; pass < 2; ++pass) {
+        k_gram_partial<T><<<nchunk, kThreads, 0, st>>>(Y, b, rows, b, Gp);
+        k_sum_parts<double><<<(int)cdiv(b * b, 256), 256, 0, st>>>(Gp, nchunk, (int64_t)b * b, (int64_t)b * b, G);
+        k_chol_inv<T><<<1, kThreads, sizeof(double) * 2 * b * b, st>>>(G, b, R, RinvT, flag);
+        k_rotate_plain<T, 128><<<(int)cdiv(rows, 16), kThreads, 0, st>>>(Y, b, Y, b, rows, b, RinvT);
+        if (want_R) {
+            if (pass == 0) {
+                HIP_TRY(hipMemcpyAsync(Racc, R, sizeof(double) * b * b, hipMemcpyDeviceToDevice, st));
+            } else {
+                k_small_gemm<<<1, kThreads, 0, st>>>(R, Racc, Rtmp, b);
+                HIP_TRY(hipMemcpyAsync(Racc, Rtmp, sizeof(double) * b * b, hipMemcpyDeviceToDevice, st));
+            }
+        }
+    }
+    HIP_TRY(hipGetLastError());
+    return ISVD_OK;
+}
+
+// TruncatedSVD(A_t, k) into the stream's next U / V buffers; S in place.
+template <typename T>
+isvd_status refresh_impl(isvd_engine* e, Stream& s, bool init, bool store_ref, hipStream_t st) {
+    DevHeader h{};
+    if (!init) {
+        HIP_TRY(hipMemcpyAsync(&h, s.hdr, sizeof(DevHeader), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+    }
+    const int64_t m = s.m, n = s.n;
+    const int k = std::min<int64_t>(s.k_target, std::min(m, n));
+    const int os = s.cfg.oversample >= 0 ? s.cfg.oversample : std::max(8, k / 2);
+    int b = (int)std::min<int64_t>(n, (int64_t)k + os);
+    b = std::min(b, kMaxBlock);
+    b = (int)std::min<int64_t>(b, m);
+    if (b < k) return fail(ISVD_E_INVAL, "refresh block %d smaller than rank %d", b, k);
+    const bool exact = (b == n);
+    const int iters = exact ? 0 : (s.cfg.refresh_iters >= 0 ? s.cfg.refresh_iters : (init ? 8 : 3));
+    WsLayout w = ws_layout(m, n, b, (int)sizeof(T));
+    ST_TRY(ensure_ws(e, w.total));
+    char* ws = e->ws;
+    T* X = (T*)(ws + w.X);
+    T* Y = (T*)(ws + w.Y);
+    double* Zp = (double*)(ws + w.Zp);
+    const T* A = (const T*)s.A;
+    const int64_t lda = s.cfg.n_cap;
+    HIP_TRY(hipMemsetAsync(ws + w.flag, 0, sizeof(int) * 4, st));
+    const int cur = init ? 0 : h.cur;
+    const int kw = init ? 0 : std::min(h.k, b);
+    k_start_block<T><<<(int)cdiv(n * b, 256), 256, 0, st>>>(X, b, n, b, (const T*)s.V[cur], init ? 4 : h.ld, kw,
+                                                           0x5eedull + (uint64_t)s.t, exact ? 1 : 0);
+    if (!exact) ST_TRY(cholqr2<T>(e, w, X, n, b, false, st));
+    const int64_t nchunk = std::min<int64_t>(32, cdiv(m, kGemmK));
+    const int64_t rpc = cdiv(m, nchunk);
+    for (int it = 0; it < iters; ++it) {
+        k_gemm_nn<T><<<(int)cdiv(m, kGemmRows), kThreads, 0, st>>>(A, lda, X, b, Y, b, m, n, b);
+        ST_TRY(cholqr2<T>(e, w, Y, m, b, false, st));
+        dim3 grid((unsigned)cdiv(n, 64), (unsigned)nchunk);
+        k_gemm_tn_partial<T><<<grid, kThreads, 0, st>>>(A, lda, Y, b, Zp, m, n, b, rpc);
+        k_sum_parts<T><<<(int)cdiv(n * b, 256), 256, 0, st>>>(Zp, (int)nchunk, n * b, n * b, X);
+        ST_TRY(cholqr2<T>(e, w, X, n, b, false, st));
+    }
+    k_gemm_nn<T><<<(int)cdiv(m, kGemmRows), kThreads, 0, st>>>(A, lda, X, b, Y, b, m, n, b);
+    ST_TRY(cholqr2<T>(e, w, Y, m, b, true, st));
+    const int ldo = round4(k);
+    T* QU = (T*)(ws + w.QU);
+    T* QV = (T*)(ws + w.QV);
+    k_svd_small<T><<<1, kThreads, core_lds_bytes(b), st>>>((const double*)(ws + w.Racc), b, k, s.S, QU, QV, ldo,
+                                                            (int*)(ws + w.sweeps));
+    const int nxt = cur ^ 1;
+    k_rotate_plain<T, 128><<<(int)cdiv(m, 16), kThreads, 0, st>>>(Y, b, (T*)s.U[nxt], ldo, m, b, QU);
+    k_rotate_plain<T, 128><<<(int)cdiv(n, 16), kThreads, 0, st>>>(X, b, (T*)s.V[nxt], ldo, n, b, QV);
+    k_set_header<<<1, 1, 0, st>>>(s.hdr, k, ldo, 1, 0);
+    if (store_ref)
+        HIP_TRY(hipMemcpyAsync(s.Uref, s.U[nxt], (size_t)sizeof(T) * m * ldo, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipGetLastError());
+    int sweeps = 0;
+    HIP_TRY(hipMemcpyAsync(&sweeps, ws + w.sweeps, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (sweeps < 0) return fail(ISVD_E_CONVERGE, "Rayleigh-Ritz Jacobi did not converge");
+    s.k_target = k;
+    return ISVD_OK;
+}
+
+isvd_status do_refresh(isvd_engine* e, Stream& s, bool init, bool store_ref, hipStream_t st) {
+    HIP_TRY(hipEventRecord(s.ev_r0, st));
+    isvd_status rc = s.esz == 8 ? refresh_impl<double>(e, s, init, store_ref, st)
+                                : refresh_impl<float>(e, s, init, store_ref, st);
+    if (rc != ISVD_OK) return rc;
+    HIP_TRY(hipEventRecord(s.ev_r1, st));
+    s.have_refresh_time = true;
+    if (!init) {
+        s.n_refresh += 1;
+        s.t_last = s.t;
+    }
+    return ISVD_OK;
+}
+
+// Policy evaluation after the update at tick t (Algorithm 1).
+isvd_status after_update(isvd_engine* e, Stream& s, hipStream_t st) {
+    const isvd_policy& p = s.cfg.policy;
+    if (p.kind == ISVD_POL_PERIODIC && p.period > 0 && s.t % p.period == 0)
+        return do_refresh(e, s, false, true, st);
+    return ISVD_OK;
+}
+
+isvd_status stage_payload(Stream& s, const void* src, int64_t len, int32_t dtype, int32_t on_device,
+                          hipStream_t st, const void** out) {
+    const bool want64 = s.esz == 8;
+    const bool is64 = dtype == ISVD_DTYPE_F64;
+    if (dtype != ISVD_DTYPE_F32 && dtype != ISVD_DTYPE_F64) return fail(ISVD_E_INVAL, "bad dtype %d", dtype);
+    if (!src) return fail(ISVD_E_INVAL, "null payload");
+    if (on_device) {
+        if (want64 == is64) {
+            *out = src;
+            return ISVD_OK;
+        }
+        if (is64)
+            k_copy2d<double, float><<<(int)cdiv(len, 256), 256, 0, st>>>((const double*)src, len, (float*)s.stage, len, 1, len);
+        else
+            k_copy2d<float, double><<<(int)cdiv(len, 256), 256, 0, st>>>((const float*)src, len, (double*)s.stage, len, 1, len);
+        HIP_TRY(hipGetLastError());
+    } else {
+        for (int64_t q = 0; q < len; ++q) {
+            double v = is64 ? ((const double*)src)[q] : (double)((const float*)src)[q];
+            if (!std::isfinite(v)) return fail(ISVD_E_NONFINITE, "payload entry %lld is not finite", (long long)q);
+        }
+        if (want64 == is64) {
+            HIP_TRY(hipMemcpyAsync(s.stage, src, (size_t)s.esz * len, hipMemcpyHostToDevice, st));
+            HIP_TRY(hipStreamSynchronize(st));
+        } else {
+            std::vector<char> tmp((size_t)s.esz * len);
+            if (want64)
+                for (int64_t q = 0; q < len; ++q) ((double*)tmp.data())[q] = ((const float*)src)[q];
+            else
+                for (int64_t q = 0; q < len; ++q) ((float*)tmp.data())[q] = (float)((const double*)src)[q];
+            HIP_TRY(hipMemcpyAsync(s.stage, tmp.data(), tmp.size(), hipMemcpyHostToDevice, st));
+            HIP_TRY(hipStreamSynchronize(st));
+        }
+    }
+    *out = s.stage;
+    return ISVD_OK;
+}
+
+int k_keep_for(const Stream& s) { return s.k_target; }
+
+isvd_status single_update(isvd_engine* e, Stream& s, int kind, const void* payload, int64_t i, int64_t j,
+                          double delta, hipStream_t st) {
+    std::vector<Group> groups(1);
+    Group& g = groups[0];
+    g.fp64 = s.esz == 8;
+    g.kc = s.kc;
+    Req r = make_req(s, kind, payload, i, j, delta, k_keep_for(s));
+    g.all.push_back(r);
+    if (kind != kEntry) g.proj.push_back(r);
+    HIP_TRY(hipEventRecord(s.ev_u0, st));
+    ST_TRY(run_groups(e, groups, st));
+    HIP_TRY(hipEventRecord(s.ev_u1, st));
+    s.have_update_time = true;
+    if (kind == kRow) s.m += 1;
+    if (kind == kCol) s.n += 1;
+    s.t += 1;
+    return after_update(e, s, st);
+}
+
+void free_stream(isvd_engine* e, Stream* s) {
+    if (!s) return;
+    if (s->base) {
+        (void)hipFree(s->base);
+        e->used -= s->L.total;
+    }
+    if (s->ev_u0) (void)hipEventDestroy(s->ev_u0);
+    if (s->ev_u1) (void)hipEventDestroy(s->ev_u1);
+    if (s->ev_r0) (void)hipEventDestroy(s->ev_r0);
+    if (s->ev_r1) (void)hipEventDestroy(s->ev_r1);
+    s->base = nullptr;
+    s->live = false;
+}
+
+isvd_status validate_cfg(const isvd_config* c) {
+    if (!c) return fail(ISVD_E_INVAL, "null config");
+    if (c->m0 < 1 || c->n0 < 1) return fail(ISVD_E_INVAL, "empty A0 (%lld x %lld)", (long long)c->m0, (long long)c->n0);
+    if (c->m_cap < c->m0 || c->n_cap < c->n0) return fail(ISVD_E_INVAL, "capacity below the initial shape");
+    if (c->precision != ISVD_FP64 && c->precision != ISVD_FP32) return fail(ISVD_E_INVAL, "bad precision %d", c->precision);
+    int kmax = std::max(c->k, c->policy.k_max);
+    if (c->k < 1 || c->k > std::min<int64_t>(c->m0, c->n0) || kmax > 96)
+        return fail(ISVD_E_INVAL, "k = %d outside [1, min(m0, n0, 96)]", c->k);
+    if (c->policy.kind < ISVD_POL_NONE || c->policy.kind > ISVD_POL_ADAPTIVE)
+        return fail(ISVD_E_INVAL, "bad policy kind %d", c->policy.kind);
+    if (c->policy.kind != ISVD_POL_NONE && c->policy.kind != ISVD_POL_PERIODIC)
+        return fail(ISVD_E_INVAL, "policy kind %d is not available in this build", c->policy.kind);
+    return ISVD_OK;
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+extern "C" {
+
+const char* isvd_last_error(void) { return g_err.c_str(); }
+
+isvd_status isvd_engine_create(int32_t device, uint64_t hbm_budget_bytes, isvd_engine** out) {
+    if (!out) return fail(ISVD_E_INVAL, "null output");
+    int ndev = 0;
+    HIP_TRY(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) return fail(ISVD_E_INVAL, "device %d of %d", device, ndev);
+    isvd_engine* e = new isvd_engine();
+    e->device = device;
+    e->budget = hbm_budget_bytes;
+    isvd_status rc = ensure_device(e);
+    if (rc == ISVD_OK) rc = set_lds_limits();
+    if (rc == ISVD_OK) {
+        e->ring.resize(64);
+        for (Slot& s : e->ring) {
+            if (hipEventCreateWithFlags(&s.ev, hipEventDisableTiming) != hipSuccess) {
+                rc = fail(ISVD_E_DEVICE, "event creation failed");
+                break;
+            }
+        }
+    }
+    if (rc != ISVD_OK) {
+        isvd_engine_destroy(e);
+        return rc;
+    }
+    *out = e;
+    return ISVD_OK;
+}
+
+isvd_status isvd_engine_destroy(isvd_engine* e) {
+    if (!e) return ISVD_OK;
+    (void)hipSetDevice(e->device);
+    (void)hipDeviceSynchronize();
+    for (Stream* s : e->streams) {
+        free_stream(e, s);
+        delete s;
+    }
+    for (Slot& s : e->ring) {
+        if (s.host) (void)hipHostFree(s.host);
+        if (s.dev) (void)hipFree(s.dev);
+        if (s.ev) (void)hipEventDestroy(s.ev);
+    }
+    if (e->ws) (void)hipFree(e->ws);
+    delete e;
+    return ISVD_OK;
+}
+
+uint64_t isvd_stream_bytes(const isvd_config* cfg) {
+    if (validate_cfg(cfg) != ISVD_OK) return 0;
+    int64_t nt = 0;
+    int kc = bucket_for(round4(std::max(cfg->k, cfg->policy.k_max)));
+    Layout L = make_layout(*cfg, cfg->precision == ISVD_FP64 ? 8 : 4, kc, &nt);
+    return L.total;
+}
+
+isvd_status isvd_init(isvd_engine* e, const isvd_config* cfg, const void* A0, int64_t lda, int32_t dtype,
+                      int32_t on_device, void* hip_stream, isvd_id* out) {
+    if (!e || !out) return fail(ISVD_E_INVAL, "null engine or output");
+    ST_TRY(validate_cfg(cfg));
+    if (!A0) return fail(ISVD_E_INVAL, "null A0");
+    if (lda < cfg->n0) return fail(ISVD_E_INVAL, "lda %lld < n0 %lld", (long long)lda, (long long)cfg->n0);
+    if (dtype != ISVD_DTYPE_F32 && dtype != ISVD_DTYPE_F64) return fail(ISVD_E_INVAL, "bad dtype %d", dtype);
+    ST_TRY(ensure_device(e));
+    hipStream_t st = (hipStream_t)hip_stream;
+    Stream* s = new Stream();
+    s->cfg = *cfg;
+    if (s->cfg.tol_rel <= 0.0) s->cfg.tol_rel = cfg->precision == ISVD_FP64 ? 1e-10 : 1e-5;
+    s->esz = cfg->precision == ISVD_FP64 ? 8 : 4;
+    s->kc = bucket_for(round4(std::max(cfg->k, cfg->policy.k_max)));
+    s->k_target = cfg->k;
+    s->m = cfg->m0;
+    s->n = cfg->n0;
+    s->L = make_layout(s->cfg, s->esz, s->kc, &s->ntiles_max);
+    if (e->budget && e->used + s->L.total > e->budget) {
+        delete s;
+        return fail(ISVD_E_BUDGET, "stream needs %zu bytes, %llu of %llu in use", s->L.total,
+                    (unsigned long long)e->used, (unsigned long long)e->budget);
+    }
+    if (hipMalloc((void**)&s->base, s->L.total) != hipSuccess) {
+        size_t bytes = s->L.total;
+        s->base = nullptr;
+        delete s;
+        return fail(ISVD_E_NOMEM, "hipMalloc of %zu bytes failed", bytes);
+    }
+    e->used += s->L.total;
+    char* b = s->base;
+    s->hdr = (DevHeader*)(b + s->L.hdr);
+    s->rs = (ReqScratch*)(b + s->L.rs);
+    s->S = (double*)(b + s->L.S);
+    s->p = (double*)(b + s->L.p);
+    s->p2 = (double*)(b + s->L.p2);
+    s->counters = (unsigned*)(b + s->L.counters);
+    s->partials = (double*)(b + s->L.partials);
+    s->QU = b + s->L.QU;
+    s->QV = b + s->L.QV;
+    s->stage = b + s->L.stage;
+    s->U[0] = b + s->L.U0;
+    s->U[1] = b + s->L.U1;
+    s->V[0] = b + s->L.V0;
+    s->V[1] = b + s->L.V1;
+    s->Uref = b + s->L.Uref;
+    s->A = b + s->L.A;
+    s->live = true;
+    e->streams.push_back(s);
+    const isvd_id id = (isvd_id)e->streams.size() - 1;
+    auto bail = [&](isvd_status rc) {
+        free_stream(e, s);
+        return rc;
+    };
+    if (hipEventCreate(&s->ev_u0) != hipSuccess || hipEventCreate(&s->ev_u1) != hipSuccess ||
+        hipEventCreate(&s->ev_r0) != hipSuccess || hipEventCreate(&s->ev_r1) != hipSuccess)
+        return bail(fail(ISVD_E_DEVICE, "event creation failed"));
+    DevHeader h0{};
+    h0.k = 0;
+    h0.ld = 4;
+    h0.m = cfg->m0;
+    h0.n = cfg->n0;
+    if (hipMemsetAsync(s->base, 0, s->L.U0, st) != hipSuccess ||
+        hipMemcpyAsync(s->hdr, &h0, sizeof(h0), hipMemcpyHostToDevice, st) != hipSuccess)
+        return bail(fail(ISVD_E_DEVICE, "header initialisation failed"));
+    // A_0 into A (leading dimension n_cap), converting to the storage type
+    const int64_t m0 = cfg->m0, n0 = cfg->n0, ldA = cfg->n_cap;
+    const int64_t cnt = m0 * n0;
+    const void* src = A0;
+    void* tmpdev = nullptr;
+    if (!on_device) {
+        size_t bytes = (size_t)(dtype == ISVD_DTYPE_F64 ? 8 : 4) * m0 * lda;
+        if (hipMalloc(&tmpdev, bytes) != hipSuccess) return bail(fail(ISVD_E_NOMEM, "A0 staging"));
+        if (hipMemcpyAsync(tmpdev, A0, bytes, hipMemcpyHostToDevice, st) != hipSuccess) {
+            (void)hipFree(tmpdev);
+            return bail(fail(ISVD_E_DEVICE, "A0 upload"));
+        }
+        src = tmpdev;
+    }
+    const int blocks = (int)cdiv(cnt, 256);
+    if (dtype == ISVD_DTYPE_F64 && s->esz == 8)
+        k_copy2d<double, double><<<blocks, 256, 0, st>>>((const double*)src, lda, (double*)s->A, ldA, m0, n0);
+    else if (dtype == ISVD_DTYPE_F64)
+        k_copy2d<double, float><<<blocks, 256, 0, st>>>((const double*)src, lda, (float*)s->A, ldA, m0, n0);
+    else if (s->esz == 8)
+        k_copy2d<float, double><<<blocks, 256, 0, st>>>((const float*)src, lda, (double*)s->A, ldA, m0, n0);
+    else
+        k_copy2d<float, float><<<blocks, 256, 0, st>>>((const float*)src, lda, (float*)s->A, ldA, m0, n0);
+    if (hipGetLastError() != hipSuccess) return bail(fail(ISVD_E_DEVICE, "A0 copy launch"));
+    // N_0 = ||A_0||_F^2 (sum of per-chunk partials, FP64)
+    const size_t fro_bytes = sizeof(double) * (size_t)cdiv(m0, kChunkRows);
+    isvd_status rc = ensure_ws(e, std::max(fro_bytes, (size_t)4096));
+    if (rc != ISVD_OK) return bail(rc);
+    const int nchunk = (int)cdiv(m0, kChunkRows);
+    if (s->esz == 8)
+        k_fro2_partial<double><<<nchunk, kThreads, 0, st>>>((const double*)s->A, ldA, m0, n0, (double*)e->ws);
+    else
+        k_fro2_partial<float><<<nchunk, kThreads, 0, st>>>((const float*)s->A, ldA, m0, n0, (double*)e->ws);
+    k_sum_parts<double><<<1, 1, 0, st>>>((const double*)e->ws, nchunk, 1, 1, &s->hdr->N);
+    if (hipGetLastError() != hipSuccess) return bail(fail(ISVD_E_DEVICE, "norm launch"));
+    rc = do_refresh(e, *s, true, true, st);
+    if (tmpdev) {
+        (void)hipStreamSynchronize(st);
+        (void)hipFree(tmpdev);
+    }
+    if (rc != ISVD_OK) return bail(rc);
+    *out = id;
+    return ISVD_OK;
+}
+
+isvd_status isvd_append_row(isvd_engine* e, isvd_id id, const void* x, int64_t n, int32_t dtype,
+                            int32_t on_device, void* hip_stream) {
+    Stream* s = nullptr;
+    ST_TRY(get_stream(e, id, &s));
+    if (n != s->n) return fail(ISVD_E_SHAPE, "row of length %lld, stream has n = %lld", (long long)n, (long long)s->n);
+    if (s->m >= s->cfg.m_cap) return fail(ISVD_E_CAPACITY, "row capacity %lld reached", (long long)s->cfg.m_cap);
+    ST_TRY(ensure_device(e));
+    hipStream_t st = (hipStream_t)hip_stream;
+    const void* pay = nullptr;
+    ST_TRY(stage_payload(*s, x, n, dtype, on_device, st, &pay));
+    return single_update(e, *s, kRow, pay, 0, 0, 0.0, st);
+}
+
+isvd_status isvd_append_col(isvd_engine* e, isvd_id id, const void* y, int64_t m, int32_t dtype,
+                            int32_t on_device, void* hip_stream) {
+    Stream* s = nullptr;
+    ST_TRY(get_stream(e, id, &s));
+    if (m != s->m) return fail(ISVD_E_SHAPE, "column of length %lld, stream has m = %lld", (long long)m, (long long)s->m);
+    if (s->n >= s->cfg.n_cap) return fail(ISVD_E_CAPACITY, "column capacity %lld reached", (long long)s->cfg.n_cap);
+    ST_TRY(ensure_device(e));
+    hipStream_t st = (hipStream_t)hip_stream;
+    const void* pay = nullptr;
+    ST_TRY(stage_payload(*s, y, m, dtype, on_device, st, &pay));
+    return single_update(e, *s, kCol, pay, 0, 0, 0.0, st);
+}
+
+isvd_status isvd_update_entry(isvd_engine* e, isvd_id id, int64_t i, int64_t j, double delta, void* hip_stream) {
+    Stream* s = nullptr;
+    ST_TRY(get_stream(e, id, &s));
+    if (i < 0 || i >= s->m || j < 0 || j >= s->n)
+        return fail(ISVD_E_RANGE, "entry (%lld, %lld) outside %lld x %lld", (long long)i, (long long)j,
+                    (long long)s->m, (long long)s->n);
+    if (!std::isfinite(delta)) return fail(ISVD_E_NONFINITE, "delta is not finite");
+    ST_TRY(ensure_device(e));
+    return single_update(e, *s, kEntry, nullptr, i, j, delta, (hipStream_t)hip_stream);
+}
+
+isvd_status isvd_refresh(isvd_engine* e, isvd_id id, int32_t store_reference, void* hip_stream) {
+    Stream* s = nullptr;
+    ST_TRY(get_stream(e, id, &s));
+    ST_TRY(ensure_device(e));
+    return do_refresh(e, *s, false, store_reference != 0, (hipStream_t)hip_stream);
+}
+
+isvd_status isvd_metrics(isvd_engine* e, isvd_id id, int32_t compute_exact, void* hip_stream, isvd_metrics_t* out) {
+    Stream* s = nullptr;
+    ST_TRY(get_stream(e, id, &s));
+    if (!out) return fail(ISVD_E_INVAL, "null output");
+    ST_TRY(ensure_device(e));
+    hipStream_t st = (hipStream_t)hip_stream;
+    DevHeader h{};
+    std::vector<double> S(s->kc + 2, 0.0);
+    HIP_TRY(hipMemcpyAsync(&h, s->hdr, sizeof(h), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(S.data(), s->S, sizeof(double) * S.size(), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (h.status != 0) {
+        // a request was rejected on the device: report it once, adopt the
+        // device's shape and tick count, and re-open the stream
+        s->m = h.m;
+        s->n = h.n;
+        s->t = h.t;
+        const int32_t zero = 0;
+        HIP_TRY(hipMemcpyAsync((char*)s->hdr + offsetof(DevHeader, status), &zero, sizeof(zero),
+                               hipMemcpyHostToDevice, st));
+        HIP_TRY(hipStreamSynchronize(st));
+    }
+    const double nan = std::nan("");
+    isvd_metrics_t m{};
+    m.t = h.t;
+    m.m = h.m;
+    m.n = h.n;
+    m.n_refresh = s->n_refresh;
+    m.t_last_refresh = s->t_last;
+    m.n_rejected = h.n_rejected;
+    m.k = h.k;
+    m.status = h.status;
+    m.sweeps = h.sweeps;
+    m.new_direction = h.new_dir;
+    m.fro2_A = h.N;
+    double s2 = 0.0;
+    for (int q = 0; q < h.k; ++q) s2 += S[q] * S[q];
+    m.sigma2_sum = s2;
+    m.evr = h.N > 0.0 ? s2 / h.N : nan;
+    m.rho = h.rho;
+    m.novelty = h.novelty;
+    m.frob_error = m.frob_opt = m.frob_gap = m.frob_ratio = nan;
+    m.ortho_U = m.ortho_V = nan;
+    m.update_time_us = nan;
+    m.opt_time_us = nan;
+    float ms = 0.f;
+    if (s->have_update_time && hipEventElapsedTime(&ms, s->ev_u0, s->ev_u1) == hipSuccess) m.update_time_us = 1e3 * ms;
+    if (s->have_refresh_time && hipEventElapsedTime(&ms, s->ev_r0, s->ev_r1) == hipSuccess) m.opt_time_us = 1e3 * ms;
+    (void)compute_exact;
+    *out = m;
+    return ISVD_OK;
+}
+
+isvd_status isvd_get_factors(isvd_engine* e, isvd_id id, double* U, int64_t ldu, double* S, double* V, int64_t ldv,
+                             void* hip_stream) {
+    Stream* s = nullptr;
+    ST_TRY(get_stream(e, id, &s));
+    ST_TRY(ensure_device(e));
+    hipStream_t st = (hipStream_t)hip_stream;
+    DevHeader h{};
+    HIP_TRY(hipMemcpyAsync(&h, s->hdr, sizeof(h), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    const int k = h.k, ld = h.ld;
+    if ((U && ldu < k) || (V && ldv < k)) return fail(ISVD_E_INVAL, "leading dimension below k = %d", k);
+    auto pull = [&](const void* src, int64_t rows, double* dst, int64_t ldd) -> isvd_status {
+        std::vector<char> buf((size_t)s->esz * rows * ld);
+        HIP_TRY(hipMemcpyAsync(buf.data(), src, buf.size(), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        for (int64_t r = 0; r < rows; ++r)
+            for (int c = 0; c < k; ++c)
+                dst[r * ldd + c] = s->esz == 8 ? ((double*)buf.data())[r * ld + c] : ((float*)buf.data())[r * ld + c];
+        return ISVD_OK;
+    };
+    if (U) ST_TRY(pull(s->U[h.cur], h.m, U, ldu));
+    if (V) ST_TRY(pull(s->V[h.cur], h.n, V, ldv));
+    if (S) {
+        HIP_TRY(hipMemcpyAsync(S, s->S, sizeof(double) * k, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+    }
+    return ISVD_OK;
+}
+
+isvd_status isvd_get_matrix(isvd_engine* e, isvd_id id, double* A, int64_t lda, void* hip_stream) {
+    Stream* s = nullptr;
+    ST_TRY(get_stream(e, id, &s));
+    if (!A || lda < s->n) return fail(ISVD_E_INVAL, "null output or lda < n");
+    ST_TRY(ensure_device(e));
+    hipStream_t st = (hipStream_t)hip_stream;
+    DevHeader h{};
+    HIP_TRY(hipMemcpyAsync(&h, s->hdr, sizeof(h), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    const int64_t ldA = s->cfg.n_cap;
+    std::vector<char> buf((size_t)s->esz * h.m * ldA);
+    HIP_TRY(hipMemcpyAsync(buf.data(), s->A, buf.size(), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    for (int64_t r = 0; r < h.m; ++r)
+        for (int64_t c = 0; c < h.n; ++c)
+            A[r * lda + c] = s->esz == 8 ? ((double*)buf.data())[r * ldA + c] : ((float*)buf.data())[r * ldA + c];
+    return ISVD_OK;
+}
+
+isvd_status isvd_shape(isvd_engine* e, isvd_id id, int64_t* m, int64_t* n, int32_t* k) {
+    Stream* s = nullptr;
+    ST_TRY(get_stream(e, id, &s));
+    if (m) *m = s->m;
+    if (n) *n = s->n;
+    if (k) *k = s->k_target;
+    return ISVD_OK;
+}
+
+isvd_status isvd_release(isvd_engine* e, isvd_id id) {
+    Stream* s = nullptr;
+    ST_TRY(get_stream(e, id, &s));
+    (void)hipSetDevice(e->device);
+    (void)hipDeviceSynchronize();
+    free_stream(e, s);
+    return ISVD_OK;
+}
+
+isvd_status isvd_tick(isvd_engine* e, int32_t count, const isvd_request* reqs, void* hip_stream) {
+    if (!e || (count > 0 && !reqs)) return fail(ISVD_E_INVAL, "null engine or requests");
+    if (count <= 0) return ISVD_OK;
+    std::vector<Stream*> ss(count);
+    std::map<isvd_id, int> seen;
+    for (int q = 0; q < count; ++q) {
+        const isvd_request& r = reqs[q];
+        ST_TRY(get_stream(e, r.id, &ss[q]));
+        Stream* s = ss[q];
+        if (seen.count(r.id)) return fail(ISVD_E_INVAL, "stream %lld appears twice in one tick", (long long)r.id);
+        seen[r.id] = q;
+        if (r.kind == ISVD_ROW) {
+            if (r.len != s->n) return fail(ISVD_E_SHAPE, "request %d: row length %lld != n %lld", q, (long long)r.len, (long long)s->n);
+            if (s->m >= s->cfg.m_cap) return fail(ISVD_E_CAPACITY, "request %d: row capacity reached", q);
+        } else if (r.kind == ISVD_COL) {
+            if (r.len != s->m) return fail(ISVD_E_SHAPE, "request %d: column length %lld != m %lld", q, (long long)r.len, (long long)s->m);
+            if (s->n >= s->cfg.n_cap) return fail(ISVD_E_CAPACITY, "request %d: column capacity reached", q);
+        } else if (r.kind == ISVD_ENTRY) {
+            if (r.i < 0 || r.i >= s->m || r.j < 0 || r.j >= s->n) return fail(ISVD_E_RANGE, "request %d: entry out of range", q);
+            if (!std::isfinite(r.delta)) return fail(ISVD_E_NONFINITE, "request %d: delta not finite", q);
+        } else {
+            return fail(ISVD_E_INVAL, "request %d: bad kind %d", q, r.kind);
+        }
+        if (r.kind != ISVD_ENTRY) {
+            if (!r.payload) return fail(ISVD_E_INVAL, "request %d: null payload", q);
+            if ((r.dtype == ISVD_DTYPE_F64) != (s->esz == 8)) return fail(ISVD_E_INVAL, "request %d: payload dtype differs from storage", q);
+        }
+    }
+    ST_TRY(ensure_device(e));
+    hipStream_t st = (hipStream_t)hip_stream;
+    std::map<std::pair<int, int>, int> gi;
+    std::vector<Group> groups;
+    for (int q = 0; q < count; ++q) {
+        Stream& s = *ss[q];
+        auto key = std::make_pair(s.esz, s.kc);
+        if (!gi.count(key)) {
+            gi[key] = (int)groups.size();
+            groups.emplace_back();
+            groups.back().fp64 = s.esz == 8;
+            groups.back().kc = s.kc;
+        }
+        Group& g = groups[gi[key]];
+        const isvd_request& r = reqs[q];
+        Req rq = make_req(s, r.kind, r.payload, r.i, r.j, r.delta, k_keep_for(s));
+        g.all.push_back(rq);
+        if (r.kind != ISVD_ENTRY) g.proj.push_back(rq);
+    }
+    ST_TRY(run_groups(e, groups, st));
+    for (int q = 0; q < count; ++q) {
+        Stream& s = *ss[q];
+        if (reqs[q].kind == ISVD_ROW) s.m += 1;
+        if (reqs[q].kind == ISVD_COL) s.n += 1;
+        s.t += 1;
+    }
+    for (int q = 0; q < count; ++q) ST_TRY(after_update(e, *ss[q], st));
+    return ISVD_OK;
+}
+
+}  // extern "C"

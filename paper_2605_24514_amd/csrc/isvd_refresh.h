@@ -1,0 +1,354 @@
+// Refresh kernels: TruncatedSVD(A_t, k) (Algorithm 1 init and refresh,
+// Section 2.4.1) by block subspace iteration on the dense A held in HBM.
+//
+//   X (n x b) orthonormal start: identity when b = n (the iteration is then
+//   exact), else the current V_t completed by pseudo-random columns.
+//   repeat q times:  Q = orth(A X);  X = orth(A^T Q)
+//   Rayleigh-Ritz:   A X = Q_Y R_Y (CholQR2),  R_Y = W S H^T (FP64 Jacobi)
+//                    U = Q_Y W[:, :k],  Sigma = S[:k],  V = X H[:, :k]
+//
+// orth() is CholQR2: Gram matrix in FP64 (products of the storage type
+// accumulated in FP64, split over row chunks and summed in chunk order),
+// Cholesky and triangular inverse in FP64 in one block, Y <- Y R^{-1},
+// twice.  The small GEMMs here are plain LDS-tiled VALU code.
+#pragma once
+#include "isvd_common.h"
+#include "isvd_jacobi.h"
+
+namespace isvd {
+
+constexpr int kGemmRows = 64;
+constexpr int kGemmK = 32;
+constexpr int kChunkRows = 1024;
+
+// Y[m x b] = A[m x n] X[n x b]   (b <= 128)
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_gemm_nn(const T* __restrict__ A, int64_t lda,
+                                                      const T* __restrict__ X, int ldx,
+                                                      T* __restrict__ Y, int ldy,
+                                                      int64_t m, int64_t n, int b) {
+    __shared__ T sA[kGemmRows][kGemmK + 1];
+    __shared__ T sX[kGemmK][128];
+    const int64_t r0 = (int64_t)blockIdx.x * kGemmRows;
+    const int row = threadIdx.x % kGemmRows;
+    const int cg = threadIdx.x / kGemmRows;   // 0..3
+    T acc[32];
+#pragma unroll
+    for (int q = 0; q < 32; ++q) acc[q] = (T)0;
+    for (int64_t c0 = 0; c0 < n; c0 += kGemmK) {
+        for (int e = threadIdx.x; e < kGemmRows * kGemmK; e += kThreads) {
+            int rr = e / kGemmK, cc = e % kGemmK;
+            int64_t r = r0 + rr, c = c0 + cc;
+            sA[rr][cc] = (r < m && c < n) ? A[r * lda + c] : (T)0;
+        }
+        for (int e = threadIdx.x; e < kGemmK * b; e += kThreads) {
+            int cc = e / b, j = e % b;
+            int64_t c = c0 + cc;
+            sX[cc][j] = c < n ? X[c * ldx + j] : (T)0;
+        }
+        __syncthreads();
+        for (int cc = 0; cc < kGemmK; ++cc) {
+            T a = sA[row][cc];
+#pragma unroll
+            for (int q = 0; q < 32; ++q) {
+                int j = cg + 4 * q;
+                if (j < b) acc[q] += a * sX[cc][j];
+            }
+        }
+        __syncthreads();
+    }
+    int64_t r = r0 + row;
+    if (r < m) {
+#pragma unroll
+        for (int q = 0; q < 32; ++q) {
+            int j = cg + 4 * q;
+            if (j < b) Y[r * ldy + j] = acc[q];
+        }
+    }
+}
+
+// Zp[chunk][c][j] = sum over rows r of the chunk of A[r][c] Q[r][j]  (FP64 partials)
+// grid: (ceil(n / 64), nchunks)
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_gemm_tn_partial(const T* __restrict__ A, int64_t lda,
+                                                              const T* __restrict__ Q, int ldq,
+                                                              double* __restrict__ Zp,
+                                                              int64_t m, int64_t n, int b,
+                                                              int64_t rows_per_chunk) {
+    __shared__ T sA[kGemmK][64 + 1];
+    __shared__ T sQ[kGemmK][128];
+    const int64_t c0 = (int64_t)blockIdx.x * 64;
+    const int64_t ra = (int64_t)blockIdx.y * rows_per_chunk;
+    const int64_t rb = min(m, ra + rows_per_chunk);
+    const int col = threadIdx.x % 64;
+    const int jg = threadIdx.x / 64;
+    double acc[32];
+#pragma unroll
+    for (int q = 0; q < 32; ++q) acc[q] = 0.0;
+    for (int64_t r0 = ra; r0 < rb; r0 += kGemmK) {
+        for (int e = threadIdx.x; e < kGemmK * 64; e += kThreads) {
+            int rr = e / 64, cc = e % 64;
+            int64_t r = r0 + rr, c = c0 + cc;
+            sA[rr][cc] = (r < rb && c < n) ? A[r * lda + c] : (T)0;
+        }
+        for (int e = threadIdx.x; e < kGemmK * b; e += kThreads) {
+            int rr = e / b, j = e % b;
+            int64_t r = r0 + rr;
+            sQ[rr][j] = r < rb ? Q[r * ldq + j] : (T)0;
+        }
+        __syncthreads();
+        for (int rr = 0; rr < kGemmK; ++rr) {
+            double a = (double)sA[rr][col];
+#pragma unroll
+            for (int q = 0; q < 32; ++q) {
+                int j = jg + 4 * q;
+                if (j < b) acc[q] += a * (double)sQ[rr][j];
+            }
+        }
+        __syncthreads();
+    }
+    int64_t c = c0 + col;
+    if (c < n) {
+        double* out = Zp + ((int64_t)blockIdx.y * n + c) * b;
+#pragma unroll
+        for (int q = 0; q < 32; ++q) {
+            int j = jg + 4 * q;
+            if (j < b) out[j] = acc[q];
+        }
+    }
+}
+
+// out[e] = sum_p P[p * stride + e] in part order; converted to Tout
+template <typename Tout>
+__global__ void k_sum_parts(const double* __restrict__ P, int nparts, int64_t stride, int64_t count,
+                            Tout* __restrict__ out) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= count) return;
+    double s = 0.0;
+    for (int p = 0; p < nparts; ++p) s += P[p * stride + e];
+    out[e] = (Tout)s;
+}
+
+// Gp[chunk] = Y[rows of chunk]^T Y[rows of chunk]  (b x b, FP64)
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_gram_partial(const T* __restrict__ Y, int ldy, int64_t rows,
+                                                           int b, double* __restrict__ Gp) {
+    __shared__ double sY[kGemmK][kMaxBlock + 1];
+    const int64_t ra = (int64_t)blockIdx.x * kChunkRows;
+    const int64_t rb = min(rows, ra + kChunkRows);
+    const int nout = b * b;
+    double acc[36];
+#pragma unroll
+    for (int q = 0; q < 36; ++q) acc[q] = 0.0;
+    for (int64_t r0 = ra; r0 < rb; r0 += kGemmK) {
+        for (int e = threadIdx.x; e < kGemmK * b; e += kThreads) {
+            int rr = e / b, j = e % b;
+            int64_t r = r0 + rr;
+            sY[rr][j] = r < rb ? (double)Y[r * ldy + j] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 36; ++q) {
+            int e = threadIdx.x + q * kThreads;
+            if (e < nout) {
+                int i = e / b, j = e % b;
+                double s = 0.0;
+                for (int rr = 0; rr < kGemmK; ++rr) s += sY[rr][i] * sY[rr][j];
+                acc[q] += s;
+            }
+        }
+        __syncthreads();
+    }
+    double* out = Gp + (int64_t)blockIdx.x * nout;
+#pragma unroll
+    for (int q = 0; q < 36; ++q) {
+        int e = threadIdx.x + q * kThreads;
+        if (e < nout) out[e] = acc[q];
+    }
+}
+
+// One block: Cholesky G = R^T R (R upper), R^{-1}; writes R (FP64, b x b)
+// and R^{-1} in the storage type (b x b, row-major) for the rotation kernel.
+// A non-positive pivot is replaced by a tiny multiple of the largest diagonal
+// (the second CholQR pass repairs the resulting loss of orthogonality).
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_chol_inv(const double* __restrict__ G, int b,
+                                                       double* __restrict__ Rout, T* __restrict__ RinvT,
+                                                       int* __restrict__ flag) {
+    extern __shared__ double sh[];
+    double* R = sh;                 // b x b row-major, becomes upper R
+    double* Ri = sh + b * b;        // b x b inverse
+    __shared__ double s_dmax;
+    for (int e = threadIdx.x; e < b * b; e += kThreads) { R[e] = G[e]; Ri[e] = 0.0; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double dm = 0.0;
+        for (int i = 0; i < b; ++i) dm = fmax(dm, R[i * b + i]);
+        s_dmax = dm;
+    }
+    __syncthreads();
+    for (int j = 0; j < b; ++j) {
+        // R[j][j] = sqrt(G[j][j] - sum_{i<j} R[i][j]^2), row j right of diagonal
+        if (threadIdx.x == 0) {
+            double d = R[j * b + j];
+            for (int i = 0; i < j; ++i) d -= R[i * b + j] * R[i * b + j];
+            double floor_ = 1e-30 * (s_dmax > 0.0 ? s_dmax : 1.0);
+            if (!(d > floor_)) { d = floor_; atomicOr(flag, 1); }
+            R[j * b + j] = sqrt(d);
+        }
+        __syncthreads();
+        for (int c = j + 1 + threadIdx.x; c < b; c += kThreads) {
+            double s = R[j * b + c];
+            for (int i = 0; i < j; ++i) s -= R[i * b + j] * R[i * b + c];
+            R[j * b + c] = s / R[j * b + j];
+        }
+        __syncthreads();
+    }
+    // zero the strict lower triangle (it still holds G)
+    for (int e = threadIdx.x; e < b * b; e += kThreads) {
+        int i = e / b, c = e % b;
+        if (i > c) R[e] = 0.0;
+    }
+    __syncthreads();
+    // columns of R^{-1} by back substitution, one column per thread
+    for (int c = threadIdx.x; c < b; c += kThreads) {
+        for (int i = c; i >= 0; --i) {
+            double s = (i == c) ? 1.0 : 0.0;
+            for (int l = i + 1; l <= c; ++l) s -= R[i * b + l] * Ri[l * b + c];
+            Ri[i * b + c] = s / R[i * b + i];
+        }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < b * b; e += kThreads) {
+        Rout[e] = R[e];
+        RinvT[e] = (T)Ri[e];
+    }
+}
+
+// C = A B for b x b FP64 matrices (one block)
+__global__ void k_small_gemm(const double* __restrict__ A, const double* __restrict__ B,
+                             double* __restrict__ C, int b) {
+    for (int e = threadIdx.x; e < b * b; e += blockDim.x) {
+        int i = e / b, j = e % b;
+        double s = 0.0;
+        for (int l = 0; l < b; ++l) s += A[i * b + l] * B[l * b + j];
+        C[e] = s;
+    }
+}
+
+// out[r, 0:ldo] = in[r, 0:kin] Q[0:kin, 0:ldo]   (may run in place when ldi == ldo)
+template <typename T, int KC>
+__global__ void __launch_bounds__(kThreads) k_rotate_plain(const T* in, int ldi, T* out, int ldo,
+                                                           int64_t rows, int kin,
+                                                           const T* __restrict__ Q) {
+    constexpr int RT = KC <= 64 ? 64 : 16;
+    __shared__ T sQ[KC * KC];
+    __shared__ T sX[RT * KC];
+    for (int e = threadIdx.x; e < kin * ldo; e += kThreads) sQ[e] = Q[e];
+    const int64_t r0 = (int64_t)blockIdx.x * RT;
+    const int nr = (int)min((int64_t)RT, rows - r0);
+    for (int e = threadIdx.x; e < nr * ldi; e += kThreads) sX[e] = in[r0 * ldi + e];
+    __syncthreads();
+    for (int e = threadIdx.x; e < nr * ldo; e += kThreads) {
+        const int rr = e / ldo, j = e % ldo;
+        T acc = (T)0;
+        for (int c = 0; c < kin; ++c) acc += sX[rr * ldi + c] * sQ[c * ldo + j];
+        out[(r0 + rr) * ldo + j] = acc;
+    }
+}
+
+// Rayleigh-Ritz core: SVD of the b x b FP64 R (row-major) by the block Jacobi;
+// QU = W[:, :k] (left vectors), QV = H[:, :k] (right vectors), both b x ldo in
+// the storage type with zero padding; S = sigma[:k].  Dynamic LDS (2 b^2 + 5 b) doubles.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_svd_small(const double* __restrict__ R, int b, int k,
+                                                        double* __restrict__ S, T* __restrict__ QU,
+                                                        T* __restrict__ QV, int ldo,
+                                                        int* __restrict__ sweeps_out) {
+    extern __shared__ double smem[];
+    const int N = b;
+    double* W = smem;
+    double* J = W + (size_t)N * N;
+    double* nrm = J + (size_t)N * N;
+    double* sig = nrm + N;
+    double* sgn = sig + N;
+    double* tmp = sgn + N;
+    int* perm = (int*)(tmp + N);
+    for (int e = threadIdx.x; e < N * N; e += kThreads) {
+        int col = e / N, row = e % N;
+        W[e] = R[row * N + col];
+        J[e] = row == col ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    int sweeps = jacobi_block(W, J, nrm, N, 60);
+    jacobi_finish(W, J, N, sig, perm, sgn, tmp);
+    for (int e = threadIdx.x; e < N * ldo; e += kThreads) {
+        int row = e / ldo, j = e % ldo;
+        double uk = 0.0, vk = 0.0;
+        if (j < k) {
+            int c = perm[j];
+            double s = sig[j];
+            uk = s > 0.0 ? sgn[j] * W[(size_t)c * N + row] / s : 0.0;
+            vk = sgn[j] * J[(size_t)c * N + row];
+        }
+        QU[e] = (T)uk;
+        QV[e] = (T)vk;
+    }
+    for (int j = threadIdx.x; j < k; j += kThreads) S[j] = sig[j];
+    if (threadIdx.x == 0) *sweeps_out = sweeps;
+}
+
+// Start block: X[:, 0:kw] = V[:, 0:kw] (warm start), the remaining columns a
+// deterministic hash in [-1, 1); identity when `ident` (b = n).
+template <typename T>
+__global__ void k_start_block(T* __restrict__ X, int ldx, int64_t n, int b, const T* __restrict__ V,
+                              int ldv, int kw, uint64_t seed, int ident) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * b) return;
+    int64_t r = e / b;
+    int j = (int)(e % b);
+    T v;
+    if (ident) {
+        v = (r == j) ? (T)1 : (T)0;
+    } else if (j < kw) {
+        v = V[r * ldv + j];
+    } else {
+        uint64_t h = seed ^ ((uint64_t)r * 0x9E3779B97F4A7C15ull) ^ ((uint64_t)(j + 1) * 0xC2B2AE3D27D4EB4Full);
+        h ^= h >> 33; h *= 0xff51afd7ed558ccdull; h ^= h >> 33; h *= 0xc4ceb9fe1a85ec53ull; h ^= h >> 33;
+        v = (T)((double)(h >> 11) * (2.0 / 9007199254740992.0) - 1.0);
+    }
+    X[r * ldx + j] = v;
+}
+
+template <typename Tin, typename Tout>
+__global__ void k_copy2d(const Tin* __restrict__ in, int64_t ldi, Tout* __restrict__ out, int64_t ldo,
+                         int64_t rows, int64_t cols) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= rows * cols) return;
+    int64_t r = e / cols, c = e % cols;
+    out[r * ldo + c] = (Tout)in[r * ldi + c];
+}
+
+// ||A||_F^2 partial sums per row chunk (FP64)
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_fro2_partial(const T* __restrict__ A, int64_t lda, int64_t m,
+                                                           int64_t n, double* __restrict__ part) {
+    __shared__ double sred[kThreads];
+    const int64_t ra = (int64_t)blockIdx.x * kChunkRows;
+    const int64_t rb = min(m, ra + kChunkRows);
+    double s = 0.0;
+    for (int64_t r = ra; r < rb; ++r)
+        for (int64_t c = threadIdx.x; c < n; c += kThreads) {
+            double v = (double)A[r * lda + c];
+            s += v * v;
+        }
+    sred[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = kThreads / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) sred[threadIdx.x] += sred[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sred[0];
+}
+
+}  // namespace isvd

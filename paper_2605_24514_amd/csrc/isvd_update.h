@@ -1,0 +1,413 @@
+// Update kernels of the engine loop (Algorithm 1): projection with one
+// re-orthogonalisation pass, the FP64 core SVD, truncation, and the basis
+// rotations.  Every kernel serves a list of requests of one rank bucket
+// (KC = capacity of the bucket, a multiple of 4), one or more blocks each.
+#pragma once
+#include "isvd_common.h"
+#include "isvd_jacobi.h"
+
+namespace isvd {
+
+template <typename T> struct V4;
+template <> struct V4<float> { typedef float4 type; };
+template <> struct V4<double> { typedef double4 type; };
+
+template <typename T>
+__device__ inline void load4(const T* p, double out[4]) {
+    typename V4<T>::type v = *reinterpret_cast<const typename V4<T>::type*>(p);
+    out[0] = (double)v.x; out[1] = (double)v.y; out[2] = (double)v.z; out[3] = (double)v.w;
+}
+
+// Request owning block b: the last r with prefix[r] <= b.
+__device__ inline int find_req(const int* prefix, int nreq, int b) {
+    int lo = 0, hi = nreq - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (prefix[mid] <= b) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ inline const void* basis_cur(const Req& rq, bool useU, int cur) {
+    return useU ? rq.U[cur] : rq.V[cur];
+}
+
+// ---------------------------------------------------------------------------
+// Projection pass 1 (Section 2.2.1, eq. row-residual: p = x^T V).
+// Row append: basis V (n rows), payload x.  Column append (transpose):
+// basis U (m rows), payload y.  Each block sums p1 = X^T y and ||y||^2 over
+// its rows in FP64 and counts non-finite payload entries; the last block to
+// arrive adds the per-block partials in block order (deterministic).
+template <typename T, int KC>
+__global__ void __launch_bounds__(kThreads) k_proj1(const Req* __restrict__ reqs,
+                                                    const int* __restrict__ prefix, int nreq) {
+    constexpr int TPR = KC / 4;
+    constexpr int RPB = kThreads / TPR;
+    constexpr int SP = KC + 2;
+    __shared__ double sacc[RPB][SP];
+    __shared__ int s_last;
+    const int ri = find_req(prefix, nreq, blockIdx.x);
+    const Req& rq = reqs[ri];
+    const int tile = blockIdx.x - prefix[ri];
+    const int k = rq.hdr->k, ld = rq.hdr->ld, cur = rq.hdr->cur;
+    const bool useU = rq.kind == kCol;
+    const T* X = (const T*)basis_cur(rq, useU, cur);
+    const int64_t rows = useU ? rq.m : rq.n;
+    const T* y = (const T*)rq.payload;
+    const int64_t r0 = (int64_t)tile * kProjTile;
+    const int64_t r1 = min(rows, r0 + kProjTile);
+    const int lane = threadIdx.x % TPR, grp = threadIdx.x / TPR;
+    const int c0 = lane * 4;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    double ysq = 0.0, bad = 0.0;
+    for (int64_t r = r0 + grp; r < r1; r += RPB) {
+        double yv = (double)y[r];
+        if (lane == 0) {
+            ysq += yv * yv;
+            if (!isfinite(yv)) bad += 1.0;
+        }
+        if (c0 < k) {
+            double xv[4];
+            load4<T>(X + r * ld + c0, xv);
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (c0 + q < k) acc[q] += yv * xv[q];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) sacc[grp][c0 + q] = acc[q];
+    if (lane == 0) { sacc[grp][KC] = ysq; sacc[grp][KC + 1] = bad; }
+    __syncthreads();
+    double* part = rq.partials + (size_t)tile * SP;
+    for (int c = threadIdx.x; c < SP; c += kThreads) {
+        double s = 0.0;
+        for (int gg = 0; gg < RPB; ++gg) s += sacc[gg][c];
+        part[c] = s;
+    }
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned prev = atomicAdd(&rq.counters[0], 1u);
+        s_last = (prev == (unsigned)rq.proj_tiles - 1u);
+    }
+    __syncthreads();
+    if (s_last) {
+        __threadfence();
+        for (int c = threadIdx.x; c < SP; c += kThreads) {
+            if (c < k || c >= KC) {
+                double s = 0.0;
+                for (int t = 0; t < rq.proj_tiles; ++t) s += rq.partials[(size_t)t * SP + c];
+                rq.p[c] = s;
+            }
+        }
+        if (threadIdx.x == 0) rq.counters[0] = 0u;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Projection pass 2 (classical Gram-Schmidt, second pass, FP64):
+// z1 = y - X p1 per row, p2 = X^T z1 and ||z1||^2.  Then p = p1 + p2 and
+// rho^2 = ||z1||^2 - ||p2||^2 (X has orthonormal columns), so the residual
+// z = y - X p never has to be stored: the rotation recomputes it per row.
+template <typename T, int KC>
+__global__ void __launch_bounds__(kThreads) k_proj2(const Req* __restrict__ reqs,
+                                                    const int* __restrict__ prefix, int nreq) {
+    constexpr int TPR = KC / 4;
+    constexpr int RPB = kThreads / TPR;
+    constexpr int SP = KC + 2;
+    __shared__ double sacc[RPB][SP];
+    __shared__ double sp1[KC];
+    __shared__ int s_last;
+    const int ri = find_req(prefix, nreq, blockIdx.x);
+    const Req& rq = reqs[ri];
+    const int tile = blockIdx.x - prefix[ri];
+    const int k = rq.hdr->k, ld = rq.hdr->ld, cur = rq.hdr->cur;
+    const bool useU = rq.kind == kCol;
+    const T* X = (const T*)basis_cur(rq, useU, cur);
+    const int64_t rows = useU ? rq.m : rq.n;
+    const T* y = (const T*)rq.payload;
+    for (int c = threadIdx.x; c < KC; c += kThreads) sp1[c] = c < k ? rq.p[c] : 0.0;
+    __syncthreads();
+    const int64_t r0 = (int64_t)tile * kProjTile;
+    const int64_t r1 = min(rows, r0 + kProjTile);
+    const int lane = threadIdx.x % TPR, grp = threadIdx.x / TPR;
+    const int c0 = lane * 4;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    double zsq = 0.0;
+    // every lane of a row group runs the same trip count (shuffles need them all)
+    const int64_t nsteps = (r1 - r0 + RPB - 1) / RPB;
+    for (int64_t st = 0; st < nsteps; ++st) {
+        const int64_t r = r0 + grp + st * RPB;
+        const bool live = r < r1;
+        double xv[4] = {0.0, 0.0, 0.0, 0.0};
+        if (live && c0 < k) {
+            load4<T>(X + r * ld + c0, xv);
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (c0 + q >= k) xv[q] = 0.0;
+        }
+        double d = xv[0] * sp1[c0] + xv[1] * sp1[c0 + 1] + xv[2] * sp1[c0 + 2] + xv[3] * sp1[c0 + 3];
+        d = group_sum(d, TPR);
+        if (live) {
+            double z1 = (double)y[r] - d;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[q] += xv[q] * z1;
+            if (lane == 0) zsq += z1 * z1;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) sacc[grp][c0 + q] = acc[q];
+    if (lane == 0) { sacc[grp][KC] = zsq; sacc[grp][KC + 1] = 0.0; }
+    __syncthreads();
+    double* part = rq.partials + (size_t)tile * SP;
+    for (int c = threadIdx.x; c < SP; c += kThreads) {
+        double s = 0.0;
+        for (int gg = 0; gg < RPB; ++gg) s += sacc[gg][c];
+        part[c] = s;
+    }
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned prev = atomicAdd(&rq.counters[1], 1u);
+        s_last = (prev == (unsigned)rq.proj_tiles - 1u);
+    }
+    __syncthreads();
+    if (s_last) {
+        __threadfence();
+        for (int c = threadIdx.x; c < SP; c += kThreads) {
+            if (c < k || c == KC) {
+                double s = 0.0;
+                for (int t = 0; t < rq.proj_tiles; ++t) s += rq.partials[(size_t)t * SP + c];
+                rq.p2[c] = s;
+            }
+        }
+        if (threadIdx.x == 0) rq.counters[1] = 0u;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Core: assemble K, its FP64 SVD, sort, sign, truncate, and the rotation
+// matrices for U and V.
+//   row append   K = [[Sigma, 0], [p, rho]]       (Alg. A1, (k+1) x (k+1))
+//   column app.  same K on the transpose           (Alg. A2)
+//   rank-1       K = Sigma + delta s_u s_v^T       (Alg. A3, k x k; s_v = row j of V)
+// Rotation matrices (row-major, ld_out columns, zero beyond k_out):
+//   row:    U' = [[U,0],[0,1]] U_K -> QU = U_K[0:k,:], new row m of U' = U_K[k,:]
+//           V' = [V z^]      V_K -> QV = V_K[0:k+1,:] (row k multiplies z^)
+//   column: U' = [U z^]      V_K -> QU = V_K[0:k+1,:]
+//           V' = [[V,0],[0,1]] U_K -> QV = U_K[0:k,:], new row n of V' = U_K[k,:]
+//   rank-1: QU = U_K, QV = V_K
+// Truncation keeps min(k_keep, order) triplets and never a zero singular
+// value after an append; the rank-1 update keeps the rank.
+// One block per request; dynamic LDS = (2 N^2 + 5 N) doubles, N <= kMaxCore.
+template <typename T, int KC>
+__global__ void __launch_bounds__(kThreads) k_core(const Req* __restrict__ reqs) {
+    extern __shared__ double smem[];
+    __shared__ double s_sc[8];
+    __shared__ int s_i[4];
+    const Req& rq = reqs[blockIdx.x];
+    DevHeader* hdr = rq.hdr;
+    ReqScratch* rs = rq.rs;
+    const int k = hdr->k, ld = hdr->ld, cur = hdr->cur;
+    const int kind = rq.kind;
+    const int N = kind == kEntry ? k : k + 1;
+    double* W = smem;
+    double* J = W + (size_t)N * N;
+    double* nrm = J + (size_t)N * N;
+    double* sig = nrm + N;
+    double* sgn = sig + N;
+    double* tmp = sgn + N;
+    int* perm = (int*)(tmp + N);
+    const int tid = threadIdx.x;
+
+    if (tid == 0) {
+        int skip = 0;
+        double rho = 0.0, xnorm = 0.0, inv_rho = 0.0;
+        int newdir = 0;
+        if (hdr->status != 0) skip = 1;
+        if (kind != kEntry) {
+            if (rq.p[KC + 1] > 0.0) skip = 1;
+            double p2sq = 0.0;
+            for (int c = 0; c < k; ++c) p2sq += rq.p2[c] * rq.p2[c];
+            double z1sq = rq.p2[KC];
+            double ysq = rq.p[KC];
+            double r2 = z1sq - p2sq;
+            rho = r2 > 0.0 ? sqrt(r2) : 0.0;
+            xnorm = sqrt(ysq);
+            newdir = rho > rq.tol_rel * xnorm ? 1 : 0;
+            if (!newdir) rho = 0.0;
+            inv_rho = newdir ? 1.0 / rho : 0.0;
+            if (!isfinite(rho) || !isfinite(xnorm)) skip = 1;
+        } else {
+            if (!isfinite(rq.delta)) skip = 1;
+        }
+        s_i[0] = skip;
+        s_i[1] = newdir;
+        s_sc[0] = rho;
+        s_sc[1] = xnorm;
+        s_sc[2] = inv_rho;
+    }
+    __syncthreads();
+    if (s_i[0]) {
+        if (tid == 0) {
+            rs->skip = 1;
+            if (hdr->status == 0) hdr->status = -4;
+            hdr->n_rejected += 1;
+        }
+        return;
+    }
+    const double rho = s_sc[0];
+    // p = p1 + p2 (kept for the rotation, which recomputes z^ per row)
+    if (kind != kEntry) {
+        for (int c = tid; c < k; c += kThreads) rq.p[c] = rq.p[c] + rq.p2[c];
+    }
+    __syncthreads();
+    // assemble K (column-major in W) and J = I
+    for (int e = tid; e < N * N; e += kThreads) {
+        int col = e / N, row = e % N;
+        double v;
+        if (kind == kEntry) {
+            const T* Uc = (const T*)rq.U[cur];
+            const T* Vc = (const T*)rq.V[cur];
+            double su = (double)Uc[rq.i * ld + row];
+            double sv = (double)Vc[rq.j * ld + col];
+            v = (row == col ? rq.S[row] : 0.0) + rq.delta * su * sv;
+        } else {
+            if (row < k) v = (row == col) ? rq.S[row] : 0.0;
+            else v = (col < k) ? rq.p[col] : rho;
+        }
+        W[e] = v;
+        J[e] = (row == col) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    int sweeps = jacobi_block(W, J, nrm, N, 40);
+    jacobi_finish(W, J, N, sig, perm, sgn, tmp);
+    int kout;
+    if (kind == kEntry) {
+        kout = k;
+    } else {
+        kout = rq.k_keep < N ? rq.k_keep : N;
+        while (kout > 0 && sig[kout - 1] == 0.0) --kout;
+    }
+    const int ldo = round4(kout);
+    T* QU = (T*)rq.QU;
+    T* QV = (T*)rq.QV;
+    // U_K(e, j) = sgn_j W[e, perm_j] / sigma_j ;  V_K(e, j) = sgn_j J[e, perm_j]
+    for (int e = tid; e < N * ldo; e += kThreads) {
+        int row = e / ldo, j = e % ldo;
+        double uk = 0.0, vk = 0.0;
+        if (j < kout) {
+            int c = perm[j];
+            double s = sig[j];
+            uk = s > 0.0 ? sgn[j] * W[(size_t)c * N + row] / s : 0.0;
+            vk = sgn[j] * J[(size_t)c * N + row];
+        }
+        if (kind == kEntry) {
+            QU[e] = (T)uk;
+            QV[e] = (T)vk;
+        } else if (kind == kRow) {
+            if (row < k) QU[e] = (T)uk;
+            else ((T*)rq.U[cur ^ 1])[rq.m * ldo + j] = (T)uk;
+            QV[e] = (T)vk;
+        } else {
+            QU[e] = (T)vk;
+            if (row < k) QV[e] = (T)uk;
+            else ((T*)rq.V[cur ^ 1])[rq.n * ldo + j] = (T)uk;
+        }
+    }
+    for (int j = tid; j < kout; j += kThreads) rq.S[j] = sig[j];
+    if (tid == 0) {
+        double dN = 0.0;
+        if (kind == kEntry) {
+            T* A = (T*)rq.A;
+            double aold = (double)A[rq.i * rq.lda + rq.j];
+            A[rq.i * rq.lda + rq.j] = (T)(aold + rq.delta);
+            dN = 2.0 * rq.delta * aold + rq.delta * rq.delta;
+        } else {
+            dN = rq.p[KC];
+        }
+        rs->skip = 0;
+        rs->k_in = k;
+        rs->ld_in = ld;
+        rs->k_out = kout;
+        rs->ld_out = ldo;
+        rs->in_idx = cur;
+        rs->inv_rho = s_sc[2];
+        hdr->k = kout;
+        hdr->ld = ldo;
+        hdr->cur = cur ^ 1;
+        hdr->t += 1;
+        if (kind == kRow) hdr->m += 1;
+        if (kind == kCol) hdr->n += 1;
+        hdr->N += dN;
+        hdr->sweeps = sweeps;
+        if (kind != kEntry) {
+            hdr->rho = rho;
+            hdr->xnorm = s_sc[1];
+            hdr->novelty = s_sc[1] > 0.0 ? rho / s_sc[1] : 0.0;
+            hdr->new_dir = s_i[1];
+            hdr->sigma_dropped = kout < N ? sig[kout] : 0.0;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Rotation (the "update singular vectors" step): X'[r, :] = X[r, 0:k] Q[0:k, :]
+// (+ z^_r Q[k, :] for the projected basis of an append, with
+// z^_r = (y_r - X[r, :] p) / rho), written out-of-place into the other buffer
+// with the new leading dimension.  The projected basis' tiles also write the
+// payload into A (row m of A for a row append, column n for a column append).
+// Generic VALU version: block = rot_rows(KC) rows of one basis of one request.
+template <typename T, int KC>
+__global__ void __launch_bounds__(kThreads) k_rotate(const Req* __restrict__ reqs,
+                                                     const int* __restrict__ prefix, int nreq) {
+    constexpr int RT = rot_rows(KC);
+    __shared__ T sQ[(KC + 1) * KC];
+    __shared__ T sX[RT * KC];
+    __shared__ double sz[RT];
+    __shared__ double sp[KC];
+    const int ri = find_req(prefix, nreq, blockIdx.x);
+    const Req& rq = reqs[ri];
+    const ReqScratch* rs = rq.rs;
+    if (rs->skip) return;
+    const int tile_all = blockIdx.x - prefix[ri];
+    const bool isU = tile_all < rq.rot_tiles_u;
+    const int tile = isU ? tile_all : tile_all - rq.rot_tiles_u;
+    const int kin = rs->k_in, ldi = rs->ld_in, ldo = rs->ld_out, idx = rs->in_idx;
+    const int64_t rows = isU ? rq.m : rq.n;
+    const T* Xi = (const T*)(isU ? rq.U[idx] : rq.V[idx]);
+    T* Xo = (T*)(isU ? rq.U[idx ^ 1] : rq.V[idx ^ 1]);
+    const T* Q = (const T*)(isU ? rq.QU : rq.QV);
+    const bool projected = (rq.kind == kRow && !isU) || (rq.kind == kCol && isU);
+    const int nq = kin + (projected ? 1 : 0);
+    for (int e = threadIdx.x; e < nq * ldo; e += kThreads) sQ[e] = Q[e];
+    const int64_t r0 = (int64_t)tile * RT;
+    const int nr = (int)min((int64_t)RT, rows - r0);
+    for (int e = threadIdx.x; e < nr * ldi; e += kThreads) sX[e] = Xi[r0 * ldi + e];
+    if (projected)
+        for (int c = threadIdx.x; c < kin; c += kThreads) sp[c] = rq.p[c];
+    __syncthreads();
+    if (projected) {
+        const T* y = (const T*)rq.payload;
+        const double inv_rho = rs->inv_rho;
+        T* A = (T*)rq.A;
+        for (int rr = threadIdx.x; rr < nr; rr += kThreads) {
+            double d = 0.0;
+            for (int c = 0; c < kin; ++c) d += (double)sX[rr * ldi + c] * sp[c];
+            const T yv = y[r0 + rr];
+            sz[rr] = ((double)yv - d) * inv_rho;
+            if (rq.kind == kRow) A[rq.m * rq.lda + r0 + rr] = yv;
+            else A[(r0 + rr) * rq.lda + rq.n] = yv;
+        }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < nr * ldo; e += kThreads) {
+        const int rr = e / ldo, j = e % ldo;
+        T acc = (T)0;
+        for (int c = 0; c < kin; ++c) acc += sX[rr * ldi + c] * sQ[c * ldo + j];
+        if (projected) acc += (T)sz[rr] * sQ[kin * ldo + j];
+        Xo[(r0 + rr) * ldo + j] = acc;
+    }
+}
+
+}  // namespace isvd

@@ -1,0 +1,301 @@
+"""Python binding of libisvd.so (ctypes): argument marshalling only.
+
+Every step of an update, refresh or tick runs in the library's HIP kernels;
+this module converts numpy arrays / torch tensors into pointers and checks
+status codes.  It fails loudly if the library is missing: there is no
+fallback implementation.
+"""
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libisvd.so")
+
+ISVD_FP64, ISVD_FP32 = 0, 1
+DTYPE_F32, DTYPE_F64 = 0, 1
+ROW, COL, ENTRY = 0, 1, 2
+POL_NONE, POL_PERIODIC, POL_ERROR, POL_ANGLE, POL_ADAPTIVE = 0, 1, 2, 3, 4
+
+STATUS = {0: "OK", -1: "E_INVAL", -2: "E_SHAPE", -3: "E_RANGE", -4: "E_NONFINITE", -5: "E_NOMEM",
+          -6: "E_BUDGET", -7: "E_DEVICE", -8: "E_STATE", -9: "E_CONVERGE", -10: "E_CAPACITY"}
+
+
+class IsvdError(RuntimeError):
+    def __init__(self, status, where, message):
+        super().__init__("%s: %s (%s)" % (where, STATUS.get(status, status), message))
+        self.status = status
+
+
+class CPolicy(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("angle_scope", ctypes.c_int32),
+                ("period", ctypes.c_int64), ("check_every", ctypes.c_int64), ("t_min", ctypes.c_int64),
+                ("gamma", ctypes.c_double), ("theta_max", ctypes.c_double),
+                ("tau", ctypes.c_double), ("band", ctypes.c_double), ("eta", ctypes.c_double),
+                ("k_min", ctypes.c_int32), ("k_max", ctypes.c_int32)]
+
+
+class CConfig(ctypes.Structure):
+    _fields_ = [("m0", ctypes.c_int64), ("n0", ctypes.c_int64), ("m_cap", ctypes.c_int64),
+                ("n_cap", ctypes.c_int64), ("k", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("tol_rel", ctypes.c_double), ("refresh_iters", ctypes.c_int32),
+                ("oversample", ctypes.c_int32), ("policy", CPolicy)]
+
+
+class CMetrics(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_int64), ("m", ctypes.c_int64), ("n", ctypes.c_int64),
+                ("n_refresh", ctypes.c_int64), ("t_last_refresh", ctypes.c_int64),
+                ("n_rejected", ctypes.c_int64), ("k", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("sweeps", ctypes.c_int32), ("new_direction", ctypes.c_int32)] + [
+        (f, ctypes.c_double) for f in ("fro2_A", "sigma2_sum", "evr", "rho", "novelty", "frob_error",
+                                       "frob_opt", "frob_gap", "frob_ratio", "ortho_U", "ortho_V",
+                                       "update_time_us", "opt_time_us")]
+
+
+class CRequest(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("kind", ctypes.c_int32), ("dtype", ctypes.c_int32),
+                ("payload", ctypes.c_void_p), ("len", ctypes.c_int64), ("i", ctypes.c_int64),
+                ("j", ctypes.c_int64), ("delta", ctypes.c_double)]
+
+
+EXPORTS = ["isvd_engine_create", "isvd_engine_destroy", "isvd_stream_bytes", "isvd_init",
+           "isvd_append_row", "isvd_append_col", "isvd_update_entry", "isvd_refresh", "isvd_metrics",
+           "isvd_get_factors", "isvd_get_matrix", "isvd_shape", "isvd_release", "isvd_tick",
+           "isvd_last_error"]
+
+_lib = None
+
+
+def load_library(path=LIB_PATH):
+    """Load libisvd.so and declare its signatures (no GPU access)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError("libisvd.so is not built at %s; run __graft_entry__.build()" % path)
+    lib = ctypes.CDLL(path)
+    vp, i32, i64, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)
+    sig = {
+        "isvd_engine_create": (i32, [i32, ctypes.c_uint64, ctypes.POINTER(vp)]),
+        "isvd_engine_destroy": (i32, [vp]),
+        "isvd_stream_bytes": (ctypes.c_uint64, [ctypes.POINTER(CConfig)]),
+        "isvd_init": (i32, [vp, ctypes.POINTER(CConfig), vp, i64, i32, i32, vp, ctypes.POINTER(i64)]),
+        "isvd_append_row": (i32, [vp, i64, vp, i64, i32, i32, vp]),
+        "isvd_append_col": (i32, [vp, i64, vp, i64, i32, i32, vp]),
+        "isvd_update_entry": (i32, [vp, i64, i64, i64, ctypes.c_double, vp]),
+        "isvd_refresh": (i32, [vp, i64, i32, vp]),
+        "isvd_metrics": (i32, [vp, i64, i32, vp, ctypes.POINTER(CMetrics)]),
+        "isvd_get_factors": (i32, [vp, i64, dp, i64, dp, dp, i64, vp]),
+        "isvd_get_matrix": (i32, [vp, i64, dp, i64, vp]),
+        "isvd_shape": (i32, [vp, i64, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i32)]),
+        "isvd_release": (i32, [vp, i64]),
+        "isvd_tick": (i32, [vp, i32, ctypes.POINTER(CRequest), vp]),
+        "isvd_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+@dataclass
+class Policy:
+    kind: int = POL_NONE
+    period: int = 0
+    check_every: int = 100
+    t_min: int = 0
+    gamma: float = 1.05
+    theta_max: float = 1e-3
+    angle_scope: int = 0
+    tau: float = 0.95
+    band: float = 0.01
+    eta: float = 0.5
+    k_min: int = 1
+    k_max: int = 0
+
+    def to_c(self):
+        return CPolicy(self.kind, self.angle_scope, self.period, self.check_every, self.t_min, self.gamma,
+                       self.theta_max, self.tau, self.band, self.eta, self.k_min, self.k_max)
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        return None
+    if hasattr(stream, "cuda_stream"):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+def _payload(arr):
+    """(pointer, length, dtype code, on_device, keepalive) for numpy or torch input."""
+    if hasattr(arr, "data_ptr"):          # torch tensor
+        if not arr.is_contiguous():
+            raise ValueError("payload tensor must be contiguous")
+        dt = str(arr.dtype)
+        code = DTYPE_F64 if dt == "torch.float64" else DTYPE_F32 if dt == "torch.float32" else None
+        if code is None:
+            raise ValueError("payload dtype %s is not float32 / float64" % dt)
+        return ctypes.c_void_p(arr.data_ptr()), arr.numel(), code, 1 if arr.is_cuda else 0, arr
+    a = np.ascontiguousarray(arr)
+    if a.dtype == np.float64:
+        code = DTYPE_F64
+    elif a.dtype == np.float32:
+        code = DTYPE_F32
+    else:
+        a = a.astype(np.float64)
+        code = DTYPE_F64
+    return ctypes.c_void_p(a.ctypes.data), a.size, code, 0, a
+
+
+class Engine:
+    """One engine on one HIP device; owns every stream's device state."""
+
+    def __init__(self, device=0, hbm_budget=0):
+        self._lib = load_library()
+        h = ctypes.c_void_p()
+        self._check(self._lib.isvd_engine_create(device, hbm_budget, ctypes.byref(h)), "isvd_engine_create")
+        self._h = h
+
+    def _check(self, st, where):
+        if st != 0:
+            raise IsvdError(st, where, self._lib.isvd_last_error().decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.isvd_engine_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @staticmethod
+    def config(m0, n0, k, precision="fp32", m_cap=None, n_cap=None, tol_rel=0.0, policy=None,
+               refresh_iters=-1, oversample=-1):
+        prec = {"fp32": ISVD_FP32, "fp64": ISVD_FP64}[precision]
+        pol = (policy or Policy()).to_c()
+        return CConfig(m0, n0, m_cap or m0, n_cap or n0, k, prec, tol_rel, refresh_iters, oversample, pol)
+
+    def stream_bytes(self, cfg):
+        return int(self._lib.isvd_stream_bytes(ctypes.byref(cfg)))
+
+    def init(self, A0, k, precision="fp32", m_cap=None, n_cap=None, tol_rel=0.0, policy=None,
+             refresh_iters=-1, oversample=-1, stream=None):
+        if hasattr(A0, "data_ptr"):
+            m0, n0 = A0.shape
+            ptr, _, code, dev, keep = _payload(A0)
+            lda = A0.stride(0)
+        else:
+            a = np.ascontiguousarray(A0, dtype=np.float64 if np.asarray(A0).dtype != np.float32 else np.float32)
+            m0, n0 = a.shape
+            ptr, _, code, dev, keep = _payload(a)
+            lda = n0
+        cfg = self.config(m0, n0, k, precision, m_cap, n_cap, tol_rel, policy, refresh_iters, oversample)
+        sid = ctypes.c_int64()
+        self._check(self._lib.isvd_init(self._h, ctypes.byref(cfg), ptr, lda, code, dev, _stream_ptr(stream),
+                                        ctypes.byref(sid)), "isvd_init")
+        del keep
+        return sid.value
+
+    def append_row(self, sid, x, stream=None):
+        ptr, n, code, dev, keep = _payload(x)
+        self._check(self._lib.isvd_append_row(self._h, sid, ptr, n, code, dev, _stream_ptr(stream)),
+                    "isvd_append_row")
+
+    def append_col(self, sid, y, stream=None):
+        ptr, m, code, dev, keep = _payload(y)
+        self._check(self._lib.isvd_append_col(self._h, sid, ptr, m, code, dev, _stream_ptr(stream)),
+                    "isvd_append_col")
+
+    def update_entry(self, sid, i, j, delta, stream=None):
+        self._check(self._lib.isvd_update_entry(self._h, sid, int(i), int(j), float(delta), _stream_ptr(stream)),
+                    "isvd_update_entry")
+
+    def refresh(self, sid, store_reference=True, stream=None):
+        self._check(self._lib.isvd_refresh(self._h, sid, 1 if store_reference else 0, _stream_ptr(stream)),
+                    "isvd_refresh")
+
+    def metrics(self, sid, exact=False, stream=None):
+        out = CMetrics()
+        self._check(self._lib.isvd_metrics(self._h, sid, 1 if exact else 0, _stream_ptr(stream), ctypes.byref(out)),
+                    "isvd_metrics")
+        return {f: getattr(out, f) for f, _ in CMetrics._fields_}
+
+    def shape(self, sid):
+        m, n, k = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
+        self._check(self._lib.isvd_shape(self._h, sid, ctypes.byref(m), ctypes.byref(n), ctypes.byref(k)),
+                    "isvd_shape")
+        return m.value, n.value, k.value
+
+    def factors(self, sid, stream=None):
+        met = self.metrics(sid, stream=stream)
+        m, n, k = met["m"], met["n"], met["k"]
+        U = np.zeros((m, k))
+        S = np.zeros(k)
+        V = np.zeros((n, k))
+        dp = ctypes.POINTER(ctypes.c_double)
+        self._check(self._lib.isvd_get_factors(self._h, sid, U.ctypes.data_as(dp), max(k, 1), S.ctypes.data_as(dp),
+                                               V.ctypes.data_as(dp), max(k, 1), _stream_ptr(stream)),
+                    "isvd_get_factors")
+        return U, S, V
+
+    def matrix(self, sid, stream=None):
+        m, n, _ = self.shape(sid)
+        A = np.zeros((m, n))
+        self._check(self._lib.isvd_get_matrix(self._h, sid, A.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), n,
+                                              _stream_ptr(stream)), "isvd_get_matrix")
+        return A
+
+    def release(self, sid):
+        self._check(self._lib.isvd_release(self._h, sid), "isvd_release")
+
+    def tick(self, requests, stream=None):
+        """requests: list of (sid, kind, payload tensor) or (sid, ENTRY, (i, j, delta))."""
+        arr = (CRequest * len(requests))()
+        keep = []
+        for q, (sid, kind, pay) in enumerate(requests):
+            r = arr[q]
+            r.id = sid
+            r.kind = kind
+            if kind == ENTRY:
+                r.i, r.j, r.delta = int(pay[0]), int(pay[1]), float(pay[2])
+                r.dtype = DTYPE_F32
+            else:
+                ptr, ln, code, dev, k = _payload(pay)
+                if not dev:
+                    raise ValueError("tick payloads must be device tensors")
+                keep.append(k)
+                r.payload = ptr
+                r.len = ln
+                r.dtype = code
+        self._check(self._lib.isvd_tick(self._h, len(requests), arr, _stream_ptr(stream)), "isvd_tick")
+
+    @staticmethod
+    def tick_requests(requests):
+        """Pre-marshalled request array for repeated ticks (bench loops)."""
+        arr = (CRequest * len(requests))()
+        for q, (sid, kind, pay) in enumerate(requests):
+            arr[q].id = sid
+            arr[q].kind = kind
+            if kind == ENTRY:
+                arr[q].i, arr[q].j, arr[q].delta = int(pay[0]), int(pay[1]), float(pay[2])
+            else:
+                arr[q].payload = ctypes.c_void_p(pay.data_ptr())
+                arr[q].len = pay.numel()
+                arr[q].dtype = DTYPE_F64 if str(pay.dtype) == "torch.float64" else DTYPE_F32
+        return arr
+
+    def tick_raw(self, arr, stream=None):
+        self._check(self._lib.isvd_tick(self._h, len(arr), arr, _stream_ptr(stream)), "isvd_tick")

@@ -1,0 +1,160 @@
+"""GPU parity: the HIP update path against the FP64 oracle on identical inputs.
+
+Bars (written in each test): reconstruction relative error <= 1e-10 in the
+FP64 path and <= 2e-5 in the FP32 path; singular values <= 1e-5 normwise
+(FP32); largest principal angle <= 1e-4 rad on the leading gap-separated
+subspace.  Inputs are the seeded factor-model streams of ``synth``.  The
+refresh block spans all columns in these cases (oversample >= n), so the
+GPU's TruncatedSVD is exact like the oracle's and both start from the same
+state."""
+import numpy as np
+import pytest
+
+from synth import FactorStream, event_schedule_c0, event_schedule_iid, ROW, COL, ENTRY
+from oracle.engine import OracleEngine
+from oracle.policies import Policy as OPolicy
+from tests.parity import compare
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def isvd():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2605_24514_amd import isvd as mod
+    return mod
+
+
+def _apply_gpu(eng, sid, ev):
+    if ev.kind == ROW:
+        eng.append_row(sid, ev.vec)
+    elif ev.kind == COL:
+        eng.append_col(sid, ev.vec)
+    else:
+        eng.update_entry(sid, ev.i, ev.j, ev.delta)
+
+
+def _oracle_state(o):
+    return o.U, o.s, o.V
+
+
+@pytest.mark.parametrize("precision,bar", [("fp64", 1e-10), ("fp32", 2e-5)])
+def test_init_matches_truncated_svd(isvd, precision, bar):
+    fs = FactorStream(seed=1, stream=0, n0=40, K=5)
+    A0 = fs.initial(300)
+    with isvd.Engine() as eng:
+        sid = eng.init(A0, 8, precision=precision, m_cap=400, n_cap=60, oversample=64)
+        o = OracleEngine(A0, 8)
+        c = compare(eng.factors(sid), _oracle_state(o))
+        print(precision, c)
+        assert c["recon"] <= bar
+        assert c["sigma"] <= (1e-12 if precision == "fp64" else 1e-5)
+        assert c["angle_U"] <= 1e-4 and c["angle_V"] <= 1e-4
+        met = eng.metrics(sid)
+        assert abs(met["fro2_A"] - o.N) <= (1e-13 if precision == "fp64" else 1e-6) * o.N
+        assert met["k"] == 8 and met["t"] == 0
+
+
+@pytest.mark.parametrize("precision,bar", [("fp64", 1e-10), ("fp32", 2e-5)])
+def test_each_update_kind_step_by_step(isvd, precision, bar):
+    fs = FactorStream(seed=2, stream=0, n0=36, K=5)
+    A0 = fs.initial(250)
+    kinds = [ROW, COL, ENTRY] * 15
+    events = fs.materialize(kinds, m0=250)
+    with isvd.Engine() as eng:
+        sid = eng.init(A0, 8, precision=precision, m_cap=300, n_cap=60, oversample=64)
+        o = OracleEngine(A0, 8, tol_rel=1e-10 if precision == "fp64" else 1e-5, cgs2=True)
+        worst = 0.0
+        for ev in events:
+            _apply_gpu(eng, sid, ev)
+            o.step(ev)
+            c = compare(eng.factors(sid), _oracle_state(o))
+            worst = max(worst, c["recon"])
+            assert c["recon"] <= bar, (ev.kind, ev.t, c)
+            if precision == "fp32":
+                assert c["sigma"] <= 1e-5, (ev.t, c)
+                assert c["angle_U"] <= 1e-4 and c["angle_V"] <= 1e-4, (ev.t, c)
+        print(precision, "worst recon", worst)
+        A = eng.matrix(sid)
+        if precision == "fp64":
+            assert np.array_equal(A, o.A)
+        else:
+            assert np.max(np.abs(A - o.A)) <= 1e-6 * np.max(np.abs(o.A))
+        met = eng.metrics(sid)
+        assert met["t"] == len(events) and (met["m"], met["n"]) == o.A.shape
+        assert abs(met["fro2_A"] - o.N) <= (1e-12 if precision == "fp64" else 1e-6) * o.N
+        assert abs(met["evr"] - o.cheap_metrics()["evr"]) <= (1e-12 if precision == "fp64" else 1e-5)
+
+
+def test_c0_stream_fp64_with_periodic_refresh(isvd):
+    """500x50 five-factor panel, 1000 row appends + 200 rank-1 updates, k = 10,
+    refresh every 200 ticks: the FP64 path tracks the oracle to <= 1e-10."""
+    fs = FactorStream(seed=0, stream=0, n0=50, K=5)
+    A0 = fs.initial(500)
+    events = fs.materialize(event_schedule_c0(0, 0, 1000, 200), m0=500)
+    pol = isvd.Policy(kind=isvd.POL_PERIODIC, period=200)
+    with isvd.Engine() as eng:
+        sid = eng.init(A0, 10, precision="fp64", m_cap=1500, n_cap=50, oversample=64, policy=pol)
+        o = OracleEngine(A0, 10, policy=OPolicy.periodic(200), cgs2=True)
+        worst = 0.0
+        for ev in events:
+            _apply_gpu(eng, sid, ev)
+            o.step(ev)
+            if ev.t % 25 == 0 or ev.t == len(events):
+                c = compare(eng.factors(sid), _oracle_state(o))
+                worst = max(worst, c["recon"])
+                assert c["recon"] <= 1e-10, (ev.t, c)
+                assert c["sigma"] <= 1e-12, (ev.t, c)
+        met = eng.metrics(sid)
+        print("C0 worst recon", worst, "refreshes", met["n_refresh"])
+        assert met["n_refresh"] == 6 and met["t_last_refresh"] == 1200
+        assert np.array_equal(eng.matrix(sid), o.A)
+
+
+def test_host_side_errors_leave_state_unchanged(isvd):
+    fs = FactorStream(seed=3, stream=0, n0=20, K=3)
+    A0 = fs.initial(60)
+    with isvd.Engine() as eng:
+        sid = eng.init(A0, 4, precision="fp64", m_cap=62, n_cap=21, oversample=64)
+        U0, S0, V0 = eng.factors(sid)
+        with pytest.raises(isvd.IsvdError) as e:
+            eng.append_row(sid, np.ones(19))
+        assert e.value.status == -2
+        with pytest.raises(isvd.IsvdError) as e:
+            eng.update_entry(sid, 60, 0, 1.0)
+        assert e.value.status == -3
+        with pytest.raises(isvd.IsvdError) as e:
+            eng.update_entry(sid, 0, 0, float("nan"))
+        assert e.value.status == -4
+        with pytest.raises(isvd.IsvdError) as e:
+            eng.append_row(sid + 7, np.ones(20))
+        assert e.value.status == -8
+        # a non-finite host payload is refused before any device work
+        x = np.ones(20)
+        x[3] = np.inf
+        with pytest.raises(isvd.IsvdError) as e:
+            eng.append_row(sid, x)
+        assert e.value.status == -4
+        # a non-finite device payload is caught on the device: rejected, the
+        # stream rejects what follows until metrics reports it, state unchanged
+        import torch
+        xd = torch.tensor(x, device="cuda")
+        eng.append_row(sid, xd)
+        eng.append_row(sid, torch.ones(20, dtype=torch.float64, device="cuda"))
+        torch.cuda.synchronize()
+        met = eng.metrics(sid)
+        assert met["status"] == -4 and met["n_rejected"] == 2
+        assert (met["m"], met["n"], met["t"]) == (60, 20, 0)
+        assert eng.metrics(sid)["status"] == 0
+        U1, S1, V1 = eng.factors(sid)
+        assert np.array_equal(U0, U1) and np.array_equal(S0, S1) and np.array_equal(V0, V1)
+        assert np.array_equal(eng.matrix(sid)[:60], A0)
+        # capacity: two more rows fit, the next does not
+        eng.append_row(sid, fs.row(60, 20))
+        eng.append_row(sid, fs.row(61, 20))
+        with pytest.raises(isvd.IsvdError) as e:
+            eng.append_row(sid, fs.row(62, 20))
+        assert e.value.status == -10
+        assert eng.metrics(sid)["m"] == 62
