@@ -1,0 +1,282 @@
+#!/usr/bin/env python3
+"""Batched rank-k update throughput of the incremental-SVD engine on one MI355X.
+
+Workload (one "step" = one tick): 512 independent factor-model streams with
+n ~ U{50..2000} columns, m ~ U{1000..50000} rows and rank k ~ U{8,16,32,64}
+(clamped to n), five factors (variances 4, 2, 1, 0.5, 0.25, noise 0.1); each
+tick appends one row to every stream.  The chosen form runs a tick as one
+batched launch sequence over all streams with FP32 storage, projections and
+rotations and an FP64 core; the plain form runs the same updates one stream
+per launch sequence in FP64.  Both start from the same factors (the FP64
+engine's TruncatedSVD of A_0; the FP32 engine is seeded with them) and apply
+the same rows, so the FP32 result is compared with the FP64 one at the end.
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np
+
+METRIC = "batched rank-k updates/sec + p99 tick latency vs plain path at rel err ≤2e-5"
+HBM_PEAK_GBS = 8000.0
+K_FACTORS = 5
+SEED = 3
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def stream_params(nstreams, seed=SEED):
+    """(m0, n0, k) per stream, drawn from Philox uniforms of the input generator."""
+    from synth import uniforms
+    u = uniforms(seed, 0xC3, 100, np.arange(nstreams), 3)
+    n = 50 + np.floor(u[:, 0] * 1951).astype(np.int64)
+    m = 1000 + np.floor(u[:, 1] * 49001).astype(np.int64)
+    k = np.array([8, 16, 32, 64])[np.minimum(np.floor(u[:, 2] * 4).astype(np.int64), 3)]
+    k = np.minimum(k, n)
+    return [(int(a), int(b), int(c)) for a, b, c in zip(m, n, k)]
+
+
+def rot_bytes(m, n, k, esz):
+    # rotation of one row append: read + write U (m x k) and V (n x k), read x, write the A row
+    return esz * (2 * m * k + 2 * n * k) + n * (esz + esz)
+
+
+def tick_bytes(m, n, k, esz):
+    # whole row append: the projected basis V is read once more, x once more for the projection
+    return rot_bytes(m, n, k, esz) + esz * n * k + esz * n
+
+
+def pctl(a, q):
+    return float(np.percentile(np.asarray(a), q))
+
+
+def cpu_baseline(params, seconds, torch):
+    """Time the FP64 oracle (as it stands) on a bounded sample of the workload."""
+    from threadpoolctl import threadpool_info
+    from oracle.engine import OracleEngine
+    from synth import device as sdev, ROW, Event
+    sample = list(range(min(8, len(params))))
+    rng = np.random.default_rng(0)
+    engines, rows = [], []
+    for s in sample:
+        m0, n0, k = params[s]
+        A = torch.empty((m0, n0), dtype=torch.float64, device="cuda")
+        sdev.rows_into(A, 0, m0, n0, SEED, s, K_FACTORS)
+        Ah = A.cpu().numpy()
+        del A
+        U, _ = np.linalg.qr(rng.standard_normal((m0, k)))
+        V, _ = np.linalg.qr(rng.standard_normal((n0, k)))
+        sig = np.sort(rng.uniform(1.0, 100.0, k))[::-1]
+        engines.append(OracleEngine.from_state(Ah, U, sig, V, cgs2=True))
+        R = torch.empty((64, n0), dtype=torch.float64, device="cuda")
+        sdev.rows_into(R, m0, 64, n0, SEED, s, K_FACTORS)
+        rows.append(R.cpu().numpy())
+    done, t0 = 0, time.perf_counter()
+    c0 = time.process_time()
+    r = 0
+    while True:
+        for q, eng in enumerate(engines):
+            eng.apply(Event(ROW, eng.t + 1, vec=rows[q][r % 64]))
+            done += 1
+        r += 1
+        if time.perf_counter() - t0 > seconds or r >= 64:
+            break
+    wall = time.perf_counter() - t0
+    cpu = time.process_time() - c0
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    mean_m = float(np.mean([params[s][0] for s in sample]))
+    return {"value": done / wall, "unit": "updates/s", "cores": int(threads), "kind": "oracle",
+            "sample": "%d row appends over the first %d streams of the workload (%d rounds, mean m %.0f), "
+                      "FP64 oracle engine loop incl. its dense A append; started from random orthonormal "
+                      "factors of each stream's shape (update cost does not depend on their values)"
+                      % (done, len(sample), r, mean_m),
+            "wall_s": wall, "cpu_s": cpu, "nproc": os.cpu_count()}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--streams", type=int, default=512)
+    ap.add_argument("--refresh-iters", type=int, default=2)
+    ap.add_argument("--compare-streams", type=int, default=32)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the streams are independent and would shard by stream across "
+              "GPUs with no communication; runs on %d GPUs are not part of this build" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2605_24514_amd import isvd
+    from synth import device as sdev
+    from tests.parity import compare
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev_stream = torch.cuda.Stream()
+    sp = dev_stream.cuda_stream
+    params = stream_params(args.streams)
+    W, K = args.warmup, args.steps
+    T = W + K
+    log("streams %d, ticks %d (+%d warmup)" % (len(params), K, W))
+
+    eng64 = isvd.Engine()
+    eng32 = isvd.Engine()
+    sid64, sid32 = [], []
+    t_init = time.perf_counter()
+    mmax = max(p[0] for p in params)
+    nmax = max(p[1] for p in params)
+    tmp = torch.empty(mmax * nmax, dtype=torch.float64, device="cuda")
+    with torch.cuda.stream(dev_stream):
+        for s, (m0, n0, k) in enumerate(params):
+            A0 = tmp[:m0 * n0].view(m0, n0)
+            sdev.rows_into(A0, 0, m0, n0, SEED, s, K_FACTORS, hip_stream=sp)
+            sid64.append(eng64.init(A0, k, "fp64", m_cap=m0 + T, n_cap=n0, refresh_iters=args.refresh_iters,
+                                    stream=dev_stream))
+            U, S, V = eng64.factors(sid64[-1], stream=dev_stream)
+            sid32.append(eng32.init_from_factors(A0, U, S, V, "fp32", m_cap=m0 + T, n_cap=n0, stream=dev_stream))
+            if s % 64 == 63:
+                log("  init %d/%d streams (%.1fs)" % (s + 1, len(params), time.perf_counter() - t_init))
+    del tmp
+    torch.cuda.synchronize()
+    init_s = time.perf_counter() - t_init
+    # row payloads for every tick, resident in HBM before timing
+    pay32, pay64 = [], []
+    for s, (m0, n0, k) in enumerate(params):
+        p64 = torch.empty((T, n0), dtype=torch.float64, device="cuda")
+        sdev.rows_into(p64, m0, T, n0, SEED, s, K_FACTORS)
+        pay64.append(p64)
+        pay32.append(p64.to(torch.float32))
+    torch.cuda.synchronize()
+    reqs = [isvd.Engine.tick_requests([(sid32[s], isvd.ROW, pay32[s][t]) for s in range(len(params))])
+            for t in range(T)]
+    log("init %.1fs; payloads ready" % init_s)
+
+    # ---------------------------------------------------- chosen form: batched FP32
+    for t in range(W):
+        eng32.tick_raw(reqs[t], stream=dev_stream)
+    torch.cuda.synchronize()
+    eng32.profile(True)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for q in range(K):
+        evs[q][0].record(dev_stream)
+        eng32.tick_raw(reqs[W + q], stream=dev_stream)
+        evs[q][1].record(dev_stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    eng32.profile(False)
+    tick_ms = [a.elapsed_time(b) for a, b in evs]
+    value = len(params) * K / wall
+    prof = eng32.profile_read()
+    log("batched FP32: %.0f updates/s, tick p50 %.3f ms p99 %.3f ms" % (value, pctl(tick_ms, 50), pctl(tick_ms, 99)))
+
+    # roofline of the dominant kernel: the rotation launch of the widest bucket
+    by_launch = {}
+    for r in prof:
+        by_launch.setdefault((r["phase"], r["kc"]), []).append(r["ms"])
+    phase_ms = {}
+    for (ph, kc), v in by_launch.items():
+        phase_ms.setdefault(ph, 0.0)
+        phase_ms[ph] += float(np.sum(v)) / K
+    kdom = max(kc for (ph, kc) in by_launch if ph == 3)
+    dom_ms = float(np.mean(by_launch[(3, kdom)]))
+    mid = W + (K - 1) / 2.0
+    bucket = lambda k: 8 if k <= 8 else 16 if k <= 16 else 32 if k <= 32 else 64 if k <= 64 else 128
+    dom_bytes = sum(rot_bytes(m0 + mid, n0, k, 4) for (m0, n0, k) in params if bucket(k) == kdom)
+    all_tick_bytes = sum(tick_bytes(m0 + mid, n0, k, 4) for (m0, n0, k) in params)
+    achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_rotate<float,%d>" % kdom, "launch_ms": round(dom_ms, 4),
+                "bytes_per_launch": int(dom_bytes)}
+    tick_gbs = all_tick_bytes / (float(np.mean(tick_ms)) * 1e-3) / 1e9
+
+    # ------------------------------------------------------- plain form: FP64, one stream per launch
+    plain = None
+    if not args.no_plain:
+        ptick = []
+        with torch.cuda.stream(dev_stream):
+            for t in range(T):
+                torch.cuda.synchronize()
+                a = time.perf_counter()
+                for s in range(len(params)):
+                    eng64.append_row(sid64[s], pay64[s][t], stream=dev_stream)
+                torch.cuda.synchronize()
+                ptick.append((time.perf_counter() - a) * 1e3)
+        pt = ptick[W:]
+        plain = {"value": len(params) * len(pt) / (np.sum(pt) * 1e-3), "unit": "updates/s",
+                 "p50_tick_ms": pctl(pt, 50), "p99_tick_ms": pctl(pt, 99), "dtype": "f64",
+                 "form": "one stream per launch sequence, FP64, no batching"}
+        log("plain FP64: %.0f updates/s, tick p50 %.2f ms p99 %.2f ms" % (plain["value"], plain["p50_tick_ms"],
+                                                                           plain["p99_tick_ms"]))
+
+    # ----------------------------------------------- accuracy of the FP32 result against FP64
+    err = None
+    if plain is not None and args.compare_streams > 0:
+        pick = np.linspace(0, len(params) - 1, min(args.compare_streams, len(params))).astype(int)
+        worst = {"recon": 0.0, "sigma": 0.0, "angle_U": 0.0, "angle_V": 0.0, "ortho_U": 0.0}
+        for s in pick:
+            c = compare(eng32.factors(sid32[s]), eng64.factors(sid64[s]))
+            for key in worst:
+                worst[key] = max(worst[key], c[key])
+        err = {k: float("%.3g" % v) for k, v in worst.items()}
+        err["streams_compared"] = int(len(pick))
+        log("FP32 vs FP64 after %d ticks: %s" % (T, err))
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(params, args.cpu_seconds, torch)
+        log("cpu oracle: %.1f updates/s on %d threads" % (cpu["value"], cpu["cores"]))
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "updates/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": round(float(np.mean(tick_ms)), 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "batched row-append tick over %d factor-model streams: n~U{50..2000}, "
+                               "m~U{1000..50000}, k~U{8,16,32,64}, 5 factors; FP32 storage, FP64 core"
+                               % len(params),
+                   "streams": len(params), "rows_total": int(sum(p[0] for p in params)),
+                   "cols_total": int(sum(p[1] for p in params))},
+        "p50_tick_ms": round(pctl(tick_ms, 50), 4),
+        "p99_tick_ms": round(pctl(tick_ms, 99), 4),
+        "plain_fp64": plain,
+        "speedup_vs_plain": round(value / plain["value"], 2) if plain else None,
+        "p99_vs_plain": round(plain["p99_tick_ms"] / pctl(tick_ms, 99), 2) if plain else None,
+        "error_vs_fp64": err,
+        "tick_algorithmic_GBps": round(tick_gbs, 1),
+        "phase_ms_per_tick": {["proj1", "proj2", "core", "rotate"][p]: round(v, 4) for p, v in sorted(phase_ms.items())},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "init_s": round(init_s, 1),
+    }
+    print(json.dumps(out), flush=True)
+    eng32.close()
+    eng64.close()
+
+
+if __name__ == "__main__":
+    main()

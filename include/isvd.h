@@ -157,6 +157,16 @@ uint64_t isvd_stream_bytes(const isvd_config* cfg);
 isvd_status isvd_init(isvd_engine* eng, const isvd_config* cfg, const void* A0, int64_t lda,
                       int32_t dtype, int32_t on_device, void* hip_stream, isvd_id* out);
 
+/* Like isvd_init, but the stream starts from the given factors instead of
+ * TruncatedSVD(A_0, k) (checkpoint restore; running two precisions from one
+ * state): U (m0 x k, ldu), S (k, non-increasing), V (n0 x k, ldv) are FP64
+ * host arrays, converted to the stream's storage type.  N_0 = ||A_0||_F^2
+ * and U_ref = U.  Waits for the device. */
+isvd_status isvd_init_from_factors(isvd_engine* eng, const isvd_config* cfg, const void* A0, int64_t lda,
+                                   int32_t dtype, int32_t on_device, const double* U, int64_t ldu,
+                                   const double* S, const double* V, int64_t ldv, void* hip_stream,
+                                   isvd_id* out);
+
 /* Row append (Alg. A1) + truncation + policy.  x has n = n_t entries.
  * Errors: STATE, SHAPE, CAPACITY, INVAL (dtype), DEVICE. */
 isvd_status isvd_append_row(isvd_engine* eng, isvd_id id, const void* x, int64_t n,
@@ -205,6 +215,25 @@ isvd_status isvd_release(isvd_engine* eng, isvd_id id);
  * device unless a policy needs device metrics.
  * Errors: STATE, SHAPE, RANGE, CAPACITY, INVAL (duplicate stream, dtype). */
 isvd_status isvd_tick(isvd_engine* eng, int32_t count, const isvd_request* reqs, void* hip_stream);
+
+/* GPU time of one kernel launch of the update sequence, collected while
+ * profiling is on (HIP events recorded around the launch on its stream). */
+typedef struct {
+    int32_t phase;          /* 0 projection pass 1, 1 projection pass 2, 2 core, 3 rotation */
+    int32_t kc;             /* rank bucket of the launch (capacity of its U / V rows) */
+    int32_t fp64;           /* 1 if the launch works on FP64 storage */
+    int32_t nreq;           /* requests served by the launch */
+    int64_t blocks;         /* blocks launched */
+    double ms;              /* GPU time */
+} isvd_launch_time;
+
+/* enable != 0: drop earlier records and start timing every update launch;
+ * enable == 0: stop. */
+isvd_status isvd_profile(isvd_engine* eng, int32_t enable);
+
+/* Copy up to `cap` records (oldest first) to `out`, the number available to
+ * *count.  Waits for the recorded launches to finish. */
+isvd_status isvd_profile_read(isvd_engine* eng, isvd_launch_time* out, int32_t cap, int32_t* count);
 
 /* Message for the last error on this thread ("" if none). */
 const char* isvd_last_error(void);

@@ -36,6 +36,27 @@ class OracleEngine:
         self.last_novelty = float("nan")
         self.refresh_ticks = []
 
+    @classmethod
+    def from_state(cls, A, U, s, V, tol_rel=1e-10, policy=None, cgs2=False):
+        """Start from a given state (A_t, U, Sigma, V) instead of TruncatedSVD(A_0, k)."""
+        eng = cls.__new__(cls)
+        eng.A = np.array(A, dtype=np.float64, copy=True)
+        eng.k = len(s)
+        eng.policy = policy or Policy()
+        eng.k_max = eng.policy.k_max or eng.k
+        eng.tol_rel = tol_rel
+        eng.cgs2 = cgs2
+        eng.U, eng.s, eng.V = np.array(U, dtype=np.float64), np.array(s, dtype=np.float64), np.array(V, dtype=np.float64)
+        eng.N = float(np.sum(eng.A * eng.A))
+        eng.t = 0
+        eng.t_last = 0
+        eng.n_refresh = 0
+        eng.U_ref = eng.U.copy()
+        eng.grow_pending = False
+        eng.last_novelty = float("nan")
+        eng.refresh_ticks = []
+        return eng
+
     # ----------------------------------------------------------------- state
     @property
     def shape(self):

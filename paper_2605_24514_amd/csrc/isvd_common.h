@@ -5,11 +5,15 @@
 
 namespace isvd {
 
-constexpr int kThreads = 256;      // threads of every block
+constexpr int kThreads = 256;      // threads of most blocks
 constexpr int kProjTile = 256;     // basis rows per projection block
-// basis rows per rotation block (fewer for the widest bucket so that Q and
-// the row tile fit in LDS in FP64)
+// basis rows per rotation block: the FP32 MFMA kernel walks 512 rows per
+// block (4 waves x 16 rows x 8 steps) to amortise loading Q into registers;
+// the FP64 LDS kernel takes 64 rows (16 for the widest bucket, so that Q and
+// the row tile fit in LDS)
 __host__ __device__ constexpr int rot_rows(int kc) { return kc <= 64 ? 64 : 16; }
+constexpr int kMfmaRotRows = 512;
+__host__ __device__ constexpr int rot_rows_for(int kc, bool fp64) { return fp64 ? rot_rows(kc) : kMfmaRotRows; }
 constexpr int kMaxCore = 97;       // largest core order held in LDS (k <= 96)
 constexpr int kMaxBlock = 96;      // largest refresh block size b
 

@@ -149,8 +149,20 @@ struct Group {
 
 }  // namespace
 
+namespace {
+struct LaunchRec {
+    int32_t phase, kc, fp64, nreq;
+    int64_t blocks;
+    hipEvent_t b, e;
+};
+}  // namespace
+
 struct isvd_engine {
     int device = 0;
+    bool profiling = false;
+    std::vector<LaunchRec> prof;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
     uint64_t budget = 0, used = 0;
     std::vector<Stream*> streams;
     std::vector<Slot> ring;
@@ -182,7 +194,10 @@ isvd_status allow_lds(K kern, size_t bytes) {
     return ISVD_OK;
 }
 
-size_t core_lds_bytes(int N) { return sizeof(double) * (size_t)(2 * N * N + 5 * N); }
+// dynamic LDS of a core of order N in a bucket whose padded column stride is ldw
+size_t core_lds_bytes(int N, int ldw, bool with_j) {
+    return sizeof(double) * (size_t)((with_j ? 2 : 1) * N * ldw + (with_j ? 6 : 8) * N);
+}
 
 // Acquire a staging slot of at least `bytes`; waits for its previous use.
 isvd_status acquire_slot(isvd_engine* e, size_t bytes, Slot** out) {
@@ -214,10 +229,13 @@ isvd_status launch_group_phase(const Group& g, const char* dev, int phase, hipSt
     } else if (phase == 1 && np > 0) {
         k_proj2<T, KC><<<g.pre_proj[np], kThreads, 0, st>>>(proj, pp, np);
     } else if (phase == 2 && na > 0) {
-        size_t lds = core_lds_bytes(g.core_lds_n);
-        k_core<T, KC><<<na, kThreads, lds, st>>>(all);
+        size_t lds = core_lds_bytes(g.core_lds_n, CoreShape<KC>::J::LDW, sizeof(T) == 8);
+        k_core<T, KC><<<na, CoreShape<KC>::J::NT, lds, st>>>(all);
     } else if (phase == 3 && na > 0) {
-        k_rotate<T, KC><<<g.pre_rot[na], kThreads, 0, st>>>(all, pr, na);
+        if constexpr (sizeof(T) == 4)
+            k_rotate_mfma<KC><<<g.pre_rot[na], kThreads, 0, st>>>(all, pr, na);
+        else
+            k_rotate<T, KC><<<g.pre_rot[na], kThreads, 0, st>>>(all, pr, na);
     }
     HIP_TRY(hipGetLastError());
     return ISVD_OK;
@@ -244,7 +262,7 @@ isvd_status launch_phase(const Group& g, const char* dev, int phase, hipStream_t
 
 template <typename T, int KC>
 isvd_status set_lds_limits_for() {
-    ST_TRY(allow_lds(k_core<T, KC>, core_lds_bytes(std::min(KC, 96) + 1)));
+    ST_TRY(allow_lds(k_core<T, KC>, core_lds_bytes(CoreShape<KC>::NMAX, CoreShape<KC>::J::LDW, sizeof(T) == 8)));
     return ISVD_OK;
 }
 
@@ -259,8 +277,9 @@ isvd_status set_lds_limits() {
     ST_TRY((set_lds_limits_for<double, 32>()));
     ST_TRY((set_lds_limits_for<double, 64>()));
     ST_TRY((set_lds_limits_for<double, 128>()));
-    ST_TRY(allow_lds(k_svd_small<float>, core_lds_bytes(kMaxBlock)));
-    ST_TRY(allow_lds(k_svd_small<double>, core_lds_bytes(kMaxBlock)));
+    const size_t svd_lds = core_lds_bytes(kMaxBlock, JacobiShape<kMaxBlock + 1>::LDW, true);
+    ST_TRY(allow_lds(k_svd_small<float>, svd_lds));
+    ST_TRY(allow_lds(k_svd_small<double>, svd_lds));
     ST_TRY(allow_lds(k_chol_inv<float>, sizeof(double) * 2 * kMaxBlock * kMaxBlock));
     ST_TRY(allow_lds(k_chol_inv<double>, sizeof(double) * 2 * kMaxBlock * kMaxBlock));
     return ISVD_OK;
@@ -279,7 +298,7 @@ Req make_req(Stream& s, int kind, const void* payload, int64_t i, int64_t j, dou
     r.kind = kind;
     r.k_keep = k_keep;
     r.proj_tiles = kind == kRow ? (int)cdiv(s.n, kProjTile) : kind == kCol ? (int)cdiv(s.m, kProjTile) : 0;
-    r.rot_tiles_u = (int)cdiv(s.m, rot_rows(s.kc));
+    r.rot_tiles_u = (int)cdiv(s.m, rot_rows_for(s.kc, s.esz == 8));
     r.hdr = s.hdr;
     r.rs = s.rs;
     r.A = s.A;
@@ -298,7 +317,17 @@ Req make_req(Stream& s, int kind, const void* payload, int64_t i, int64_t j, dou
     return r;
 }
 
-int rot_tiles(const Req& r, int kc) { return r.rot_tiles_u + (int)cdiv(r.n, rot_rows(kc)); }
+int rot_tiles(const Req& r, int kc, bool fp64) { return r.rot_tiles_u + (int)cdiv(r.n, rot_rows_for(kc, fp64)); }
+
+isvd_status next_event(isvd_engine* e, hipEvent_t* out) {
+    if (e->ev_used == e->ev_pool.size()) {
+        hipEvent_t ev;
+        HIP_TRY(hipEventCreate(&ev));
+        e->ev_pool.push_back(ev);
+    }
+    *out = e->ev_pool[e->ev_used++];
+    return ISVD_OK;
+}
 
 // Lay out groups in a slot, upload, and launch the four phases.
 isvd_status run_groups(isvd_engine* e, std::vector<Group>& groups, hipStream_t st) {
@@ -312,7 +341,7 @@ isvd_status run_groups(isvd_engine* e, std::vector<Group>& groups, hipStream_t s
         g.pre_proj.assign(g.proj.size() + 1, 0);
         for (size_t q = 0; q < g.proj.size(); ++q) g.pre_proj[q + 1] = g.pre_proj[q] + g.proj[q].proj_tiles;
         g.pre_rot.assign(g.all.size() + 1, 0);
-        for (size_t q = 0; q < g.all.size(); ++q) g.pre_rot[q + 1] = g.pre_rot[q] + rot_tiles(g.all[q], g.kc);
+        for (size_t q = 0; q < g.all.size(); ++q) g.pre_rot[q + 1] = g.pre_rot[q] + rot_tiles(g.all[q], g.kc, g.fp64);
         g.off_all = take(sizeof(Req) * g.all.size());
         g.off_proj = take(sizeof(Req) * g.proj.size());
         g.off_pp = take(sizeof(int) * g.pre_proj.size());
@@ -328,8 +357,29 @@ isvd_status run_groups(isvd_engine* e, std::vector<Group>& groups, hipStream_t s
         memcpy(slot->host + g.off_pr, g.pre_rot.data(), sizeof(int) * g.pre_rot.size());
     }
     HIP_TRY(hipMemcpyAsync(slot->dev, slot->host, off, hipMemcpyHostToDevice, st));
-    for (int phase = 0; phase < 4; ++phase)
-        for (Group& g : groups) ST_TRY(launch_phase(g, slot->dev, phase, st));
+    for (int phase = 0; phase < 4; ++phase) {
+        for (Group& g : groups) {
+            const int np = (int)g.proj.size(), na = (int)g.all.size();
+            const int nreq = phase < 2 ? np : na;
+            if (nreq == 0) continue;
+            LaunchRec rec{};
+            if (e->profiling) {
+                ST_TRY(next_event(e, &rec.b));
+                ST_TRY(next_event(e, &rec.e));
+                HIP_TRY(hipEventRecord(rec.b, st));
+            }
+            ST_TRY(launch_phase(g, slot->dev, phase, st));
+            if (e->profiling) {
+                HIP_TRY(hipEventRecord(rec.e, st));
+                rec.phase = phase;
+                rec.kc = g.kc;
+                rec.fp64 = g.fp64 ? 1 : 0;
+                rec.nreq = nreq;
+                rec.blocks = phase < 2 ? g.pre_proj[np] : phase == 2 ? na : g.pre_rot[na];
+                e->prof.push_back(rec);
+            }
+        }
+    }
     HIP_TRY(hipEventRecord(slot->ev, st));
     slot->used = true;
     return ISVD_OK;
@@ -469,7 +519,7 @@ isvd_status refresh_impl(isvd_engine* e, Stream& s, bool init, bool store_ref, h
     const int ldo = round4(k);
     T* QU = (T*)(ws + w.QU);
     T* QV = (T*)(ws + w.QV);
-    k_svd_small<T><<<1, kThreads, core_lds_bytes(b), st>>>((const double*)(ws + w.Racc), b, k, s.S, QU, QV, ldo,
+    k_svd_small<T><<<1, JacobiShape<kMaxBlock + 1>::NT, core_lds_bytes(kMaxBlock, JacobiShape<kMaxBlock + 1>::LDW, true), st>>>((const double*)(ws + w.Racc), b, k, s.S, QU, QV, ldo,
                                                             (int*)(ws + w.sweeps));
     const int nxt = cur ^ 1;
     k_rotate_plain<T, 128><<<(int)cdiv(m, 16), kThreads, 0, st>>>(Y, b, (T*)s.U[nxt], ldo, m, b, QU);
@@ -644,7 +694,39 @@ isvd_status isvd_engine_destroy(isvd_engine* e) {
         if (s.ev) (void)hipEventDestroy(s.ev);
     }
     if (e->ws) (void)hipFree(e->ws);
+    for (hipEvent_t ev : e->ev_pool) (void)hipEventDestroy(ev);
     delete e;
+    return ISVD_OK;
+}
+
+isvd_status isvd_profile(isvd_engine* e, int32_t enable) {
+    if (!e) return fail(ISVD_E_INVAL, "null engine");
+    ST_TRY(ensure_device(e));
+    if (enable) {
+        HIP_TRY(hipDeviceSynchronize());
+        e->prof.clear();
+        e->ev_used = 0;
+    }
+    e->profiling = enable != 0;
+    return ISVD_OK;
+}
+
+isvd_status isvd_profile_read(isvd_engine* e, isvd_launch_time* out, int32_t cap, int32_t* count) {
+    if (!e || !count || (cap > 0 && !out)) return fail(ISVD_E_INVAL, "null argument");
+    ST_TRY(ensure_device(e));
+    *count = (int32_t)e->prof.size();
+    for (int32_t q = 0; q < cap && q < (int32_t)e->prof.size(); ++q) {
+        const LaunchRec& r = e->prof[q];
+        HIP_TRY(hipEventSynchronize(r.e));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, r.b, r.e));
+        out[q].phase = r.phase;
+        out[q].kc = r.kc;
+        out[q].fp64 = r.fp64;
+        out[q].nreq = r.nreq;
+        out[q].blocks = r.blocks;
+        out[q].ms = ms;
+    }
     return ISVD_OK;
 }
 
@@ -656,8 +738,37 @@ uint64_t isvd_stream_bytes(const isvd_config* cfg) {
     return L.total;
 }
 
-isvd_status isvd_init(isvd_engine* e, const isvd_config* cfg, const void* A0, int64_t lda, int32_t dtype,
-                      int32_t on_device, void* hip_stream, isvd_id* out) {
+struct GivenFactors {
+    const double *U, *S, *V;
+    int64_t ldu, ldv;
+};
+
+static isvd_status install_factors(Stream& s, const GivenFactors& f, hipStream_t st) {
+    const int k = s.k_target, ld = round4(k);
+    const int64_t m = s.m, n = s.n;
+    std::vector<char> bu((size_t)s.esz * m * ld, 0), bv((size_t)s.esz * n * ld, 0);
+    for (int64_t r = 0; r < m; ++r)
+        for (int c = 0; c < k; ++c) {
+            if (s.esz == 8) ((double*)bu.data())[r * ld + c] = f.U[r * f.ldu + c];
+            else ((float*)bu.data())[r * ld + c] = (float)f.U[r * f.ldu + c];
+        }
+    for (int64_t r = 0; r < n; ++r)
+        for (int c = 0; c < k; ++c) {
+            if (s.esz == 8) ((double*)bv.data())[r * ld + c] = f.V[r * f.ldv + c];
+            else ((float*)bv.data())[r * ld + c] = (float)f.V[r * f.ldv + c];
+        }
+    HIP_TRY(hipMemcpyAsync(s.U[1], bu.data(), bu.size(), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(s.V[1], bv.data(), bv.size(), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(s.Uref, bu.data(), bu.size(), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(s.S, f.S, sizeof(double) * k, hipMemcpyHostToDevice, st));
+    k_set_header<<<1, 1, 0, st>>>(s.hdr, k, ld, 1, 0);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(st));
+    return ISVD_OK;
+}
+
+static isvd_status init_common(isvd_engine* e, const isvd_config* cfg, const void* A0, int64_t lda, int32_t dtype,
+                               int32_t on_device, const GivenFactors* given, void* hip_stream, isvd_id* out) {
     if (!e || !out) return fail(ISVD_E_INVAL, "null engine or output");
     ST_TRY(validate_cfg(cfg));
     if (!A0) return fail(ISVD_E_INVAL, "null A0");
@@ -756,7 +867,7 @@ isvd_status isvd_init(isvd_engine* e, const isvd_config* cfg, const void* A0, in
         k_fro2_partial<float><<<nchunk, kThreads, 0, st>>>((const float*)s->A, ldA, m0, n0, (double*)e->ws);
     k_sum_parts<double><<<1, 1, 0, st>>>((const double*)e->ws, nchunk, 1, 1, &s->hdr->N);
     if (hipGetLastError() != hipSuccess) return bail(fail(ISVD_E_DEVICE, "norm launch"));
-    rc = do_refresh(e, *s, true, true, st);
+    rc = given ? install_factors(*s, *given, st) : do_refresh(e, *s, true, true, st);
     if (tmpdev) {
         (void)hipStreamSynchronize(st);
         (void)hipFree(tmpdev);
@@ -764,6 +875,22 @@ isvd_status isvd_init(isvd_engine* e, const isvd_config* cfg, const void* A0, in
     if (rc != ISVD_OK) return bail(rc);
     *out = id;
     return ISVD_OK;
+}
+
+isvd_status isvd_init(isvd_engine* e, const isvd_config* cfg, const void* A0, int64_t lda, int32_t dtype,
+                      int32_t on_device, void* hip_stream, isvd_id* out) {
+    return init_common(e, cfg, A0, lda, dtype, on_device, nullptr, hip_stream, out);
+}
+
+isvd_status isvd_init_from_factors(isvd_engine* e, const isvd_config* cfg, const void* A0, int64_t lda,
+                                   int32_t dtype, int32_t on_device, const double* U, int64_t ldu,
+                                   const double* S, const double* V, int64_t ldv, void* hip_stream,
+                                   isvd_id* out) {
+    if (!cfg || !U || !S || !V || ldu < cfg->k || ldv < cfg->k) return fail(ISVD_E_INVAL, "bad factor arguments");
+    for (int q = 0; q < cfg->k; ++q)
+        if (!(S[q] >= 0.0) || (q > 0 && S[q] > S[q - 1])) return fail(ISVD_E_INVAL, "S must be non-increasing and >= 0");
+    GivenFactors f{U, S, V, ldu, ldv};
+    return init_common(e, cfg, A0, lda, dtype, on_device, &f, hip_stream, out);
 }
 
 isvd_status isvd_append_row(isvd_engine* e, isvd_id id, const void* x, int64_t n, int32_t dtype,

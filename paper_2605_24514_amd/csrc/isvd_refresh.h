@@ -259,42 +259,43 @@ __global__ void __launch_bounds__(kThreads) k_rotate_plain(const T* in, int ldi,
 
 // Rayleigh-Ritz core: SVD of the b x b FP64 R (row-major) by the block Jacobi;
 // QU = W[:, :k] (left vectors), QV = H[:, :k] (right vectors), both b x ldo in
-// the storage type with zero padding; S = sigma[:k].  Dynamic LDS (2 b^2 + 5 b) doubles.
+// the storage type with zero padding; S = sigma[:k].  Dynamic LDS (2 b ldw + 6 b) doubles.
 template <typename T>
-__global__ void __launch_bounds__(kThreads) k_svd_small(const double* __restrict__ R, int b, int k,
+__global__ void __launch_bounds__(JacobiShape<kMaxBlock + 1>::NT) k_svd_small(const double* __restrict__ R, int b, int k,
                                                         double* __restrict__ S, T* __restrict__ QU,
                                                         T* __restrict__ QV, int ldo,
                                                         int* __restrict__ sweeps_out) {
     extern __shared__ double smem[];
     const int N = b;
+    const int ldw = JacobiShape<kMaxBlock + 1>::LDW;
     double* W = smem;
-    double* J = W + (size_t)N * N;
-    double* nrm = J + (size_t)N * N;
+    double* J = W + (size_t)N * ldw;
+    double* nrm = J + (size_t)N * ldw;
     double* sig = nrm + N;
     double* sgn = sig + N;
     double* tmp = sgn + N;
     int* perm = (int*)(tmp + N);
-    for (int e = threadIdx.x; e < N * N; e += kThreads) {
-        int col = e / N, row = e % N;
-        W[e] = R[row * N + col];
+    for (int e = threadIdx.x; e < N * ldw; e += blockDim.x) {
+        int col = e / ldw, row = e % ldw;
+        W[e] = row < N ? R[row * N + col] : 0.0;
         J[e] = row == col ? 1.0 : 0.0;
     }
     __syncthreads();
-    int sweeps = jacobi_block(W, J, nrm, N, 60);
-    jacobi_finish(W, J, N, sig, perm, sgn, tmp);
-    for (int e = threadIdx.x; e < N * ldo; e += kThreads) {
+    int sweeps = jacobi_block<kMaxBlock + 1, true>(W, J, N, ldw, 60);
+    jacobi_finish(W, J, N, ldw, sig, perm, sgn, tmp);
+    for (int e = threadIdx.x; e < N * ldo; e += blockDim.x) {
         int row = e / ldo, j = e % ldo;
         double uk = 0.0, vk = 0.0;
         if (j < k) {
             int c = perm[j];
             double s = sig[j];
-            uk = s > 0.0 ? sgn[j] * W[(size_t)c * N + row] / s : 0.0;
-            vk = sgn[j] * J[(size_t)c * N + row];
+            uk = s > 0.0 ? sgn[j] * W[(size_t)c * ldw + row] / s : 0.0;
+            vk = sgn[j] * J[(size_t)c * ldw + row];
         }
         QU[e] = (T)uk;
         QV[e] = (T)vk;
     }
-    for (int j = threadIdx.x; j < k; j += kThreads) S[j] = sig[j];
+    for (int j = threadIdx.x; j < k; j += blockDim.x) S[j] = sig[j];
     if (threadIdx.x == 0) *sweeps_out = sweeps;
 }
 

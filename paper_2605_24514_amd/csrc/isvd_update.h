@@ -199,9 +199,22 @@ __global__ void __launch_bounds__(kThreads) k_proj2(const Req* __restrict__ reqs
 //   rank-1: QU = U_K, QV = V_K
 // Truncation keeps min(k_keep, order) triplets and never a zero singular
 // value after an append; the rank-1 update keeps the rank.
-// One block per request; dynamic LDS = (2 N^2 + 5 N) doubles, N <= kMaxCore.
+// One-sided Jacobi rotates the columns of W = K; U_K = W diag(1/sigma).
+// FP64 storage accumulates the rotations (V_K = J).  FP32 storage does not:
+// V_K = K^T U_K diag(1/sigma), evaluated from K's sparsity in O(N^2); its
+// loss of orthogonality, about N eps64 sigma_1 / sigma_j, stays far below
+// FP32 rounding for every kept triplet.
+// One block per request; dynamic LDS = ((1 + WITH_J) N ldw + (WITH_J ? 6 : 8) N)
+// doubles with ldw the bucket's padded column stride, N <= kMaxCore.
+template <int KC>
+struct CoreShape {
+    static constexpr int NMAX = (KC < kMaxCore - 1 ? KC : kMaxCore - 1) + 1;
+    typedef JacobiShape<NMAX> J;
+};
+
 template <typename T, int KC>
-__global__ void __launch_bounds__(kThreads) k_core(const Req* __restrict__ reqs) {
+__global__ void __launch_bounds__(CoreShape<KC>::J::NT) k_core(const Req* __restrict__ reqs) {
+    constexpr bool WITH_J = sizeof(T) == 8;
     extern __shared__ double smem[];
     __shared__ double s_sc[8];
     __shared__ int s_i[4];
@@ -211,27 +224,30 @@ __global__ void __launch_bounds__(kThreads) k_core(const Req* __restrict__ reqs)
     const int k = hdr->k, ld = hdr->ld, cur = hdr->cur;
     const int kind = rq.kind;
     const int N = kind == kEntry ? k : k + 1;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int ldw = CoreShape<KC>::J::LDW;
     double* W = smem;
-    double* J = W + (size_t)N * N;
-    double* nrm = J + (size_t)N * N;
-    double* sig = nrm + N;
+    double* J = W + (size_t)N * ldw;                 // used only WITH_J
+    double* sS = J + (WITH_J ? (size_t)N * ldw : 0); // Sigma (k)
+    double* sp = sS + N;                           // p (row / column) or s_v (rank-1)
+    double* sig = sp + N;
     double* sgn = sig + N;
     double* tmp = sgn + N;
     int* perm = (int*)(tmp + N);
-    const int tid = threadIdx.x;
+    double* su = tmp + 2 * N;                      // s_u (rank-1, no J)
+    double* dcol = su + N;                         // s_u . W[:, c] (rank-1, no J)
 
     if (tid == 0) {
-        int skip = 0;
+        int skip = hdr->status != 0 ? 1 : 0;
         double rho = 0.0, xnorm = 0.0, inv_rho = 0.0;
         int newdir = 0;
-        if (hdr->status != 0) skip = 1;
         if (kind != kEntry) {
             if (rq.p[KC + 1] > 0.0) skip = 1;
             double p2sq = 0.0;
             for (int c = 0; c < k; ++c) p2sq += rq.p2[c] * rq.p2[c];
-            double z1sq = rq.p2[KC];
-            double ysq = rq.p[KC];
-            double r2 = z1sq - p2sq;
+            const double z1sq = rq.p2[KC];
+            const double ysq = rq.p[KC];
+            const double r2 = z1sq - p2sq;
             rho = r2 > 0.0 ? sqrt(r2) : 0.0;
             xnorm = sqrt(ysq);
             newdir = rho > rq.tol_rel * xnorm ? 1 : 0;
@@ -257,31 +273,77 @@ __global__ void __launch_bounds__(kThreads) k_core(const Req* __restrict__ reqs)
         return;
     }
     const double rho = s_sc[0];
-    // p = p1 + p2 (kept for the rotation, which recomputes z^ per row)
-    if (kind != kEntry) {
-        for (int c = tid; c < k; c += kThreads) rq.p[c] = rq.p[c] + rq.p2[c];
+    // p = p1 + p2 (also kept in global memory for the rotation, which recomputes z^ per row)
+    for (int c = tid; c < k; c += nt) {
+        sS[c] = rq.S[c];
+        if (kind != kEntry) {
+            const double pc = rq.p[c] + rq.p2[c];
+            sp[c] = pc;
+            rq.p[c] = pc;
+        } else {
+            if constexpr (!WITH_J) su[c] = (double)((const T*)rq.U[cur])[rq.i * ld + c];
+            sp[c] = (double)((const T*)rq.V[cur])[rq.j * ld + c];
+        }
     }
     __syncthreads();
-    // assemble K (column-major in W) and J = I
-    for (int e = tid; e < N * N; e += kThreads) {
-        int col = e / N, row = e % N;
-        double v;
+    // assemble K (column-major in W, zero padding rows) and J = I
+    for (int e = tid; e < N * ldw; e += nt) {
+        const int col = e / ldw, row = e % ldw;
+        double v = 0.0;
+        if (row >= N) {
+            W[e] = 0.0;
+            if constexpr (WITH_J) J[e] = 0.0;
+            continue;
+        }
         if (kind == kEntry) {
-            const T* Uc = (const T*)rq.U[cur];
-            const T* Vc = (const T*)rq.V[cur];
-            double su = (double)Uc[rq.i * ld + row];
-            double sv = (double)Vc[rq.j * ld + col];
-            v = (row == col ? rq.S[row] : 0.0) + rq.delta * su * sv;
+            const double uu = WITH_J ? (double)((const T*)rq.U[cur])[rq.i * ld + row] : su[row];
+            v = (row == col ? sS[row] : 0.0) + rq.delta * uu * sp[col];
         } else {
-            if (row < k) v = (row == col) ? rq.S[row] : 0.0;
-            else v = (col < k) ? rq.p[col] : rho;
+            if (row < k) v = (row == col) ? sS[row] : 0.0;
+            else v = (col < k) ? sp[col] : rho;
         }
         W[e] = v;
-        J[e] = (row == col) ? 1.0 : 0.0;
+        if constexpr (WITH_J) J[e] = (row == col) ? 1.0 : 0.0;
     }
     __syncthreads();
-    int sweeps = jacobi_block(W, J, nrm, N, 40);
-    jacobi_finish(W, J, N, sig, perm, sgn, tmp);
+    const int sweeps = jacobi_block<CoreShape<KC>::NMAX, WITH_J>(W, J, N, ldw, 40);
+    jacobi_sort(W, N, ldw, sig, perm, tmp);
+    if constexpr (!WITH_J) {
+        if (kind == kEntry) {
+            for (int c = tid; c < N; c += nt) {
+                double d = 0.0;
+                for (int i = 0; i < N; ++i) d += su[i] * W[(size_t)c * ldw + i];
+                dcol[c] = d;
+            }
+            __syncthreads();
+        }
+    }
+    // right singular vector entry e of column c of W (unsorted, unsigned)
+    auto vraw = [&](int e, int c) -> double {
+        if constexpr (WITH_J) {
+            return J[(size_t)c * ldw + e];
+        } else {
+            const double* w = W + (size_t)c * ldw;
+            const double s2 = tmp[c] * tmp[c];
+            if (!(s2 > 0.0)) return 0.0;
+            double kw;
+            if (kind == kEntry) kw = sS[e] * w[e] + rq.delta * sp[e] * dcol[c];
+            else if (e < k) kw = sS[e] * w[e] + sp[e] * w[k];
+            else kw = rho * w[k];
+            return kw / s2;
+        }
+    };
+    for (int jj = tid; jj < N; jj += nt) {
+        const int c = perm[jj];
+        int imax = 0;
+        double vmax = fabs(vraw(0, c));
+        for (int e = 1; e < N; ++e) {
+            const double a = fabs(vraw(e, c));
+            if (a > vmax) { vmax = a; imax = e; }
+        }
+        sgn[jj] = vraw(imax, c) < 0.0 ? -1.0 : 1.0;
+    }
+    __syncthreads();
     int kout;
     if (kind == kEntry) {
         kout = k;
@@ -292,15 +354,15 @@ __global__ void __launch_bounds__(kThreads) k_core(const Req* __restrict__ reqs)
     const int ldo = round4(kout);
     T* QU = (T*)rq.QU;
     T* QV = (T*)rq.QV;
-    // U_K(e, j) = sgn_j W[e, perm_j] / sigma_j ;  V_K(e, j) = sgn_j J[e, perm_j]
-    for (int e = tid; e < N * ldo; e += kThreads) {
-        int row = e / ldo, j = e % ldo;
+    // U_K(e, j) = sgn_j W[e, perm_j] / sigma_j ;  V_K(e, j) = sgn_j vraw(e, perm_j)
+    for (int e = tid; e < N * ldo; e += nt) {
+        const int row = e / ldo, j = e % ldo;
         double uk = 0.0, vk = 0.0;
         if (j < kout) {
-            int c = perm[j];
-            double s = sig[j];
-            uk = s > 0.0 ? sgn[j] * W[(size_t)c * N + row] / s : 0.0;
-            vk = sgn[j] * J[(size_t)c * N + row];
+            const int c = perm[j];
+            const double sv = sig[j];
+            uk = sv > 0.0 ? sgn[j] * W[(size_t)c * ldw + row] / sv : 0.0;
+            vk = sgn[j] * vraw(row, c);
         }
         if (kind == kEntry) {
             QU[e] = (T)uk;
@@ -315,12 +377,12 @@ __global__ void __launch_bounds__(kThreads) k_core(const Req* __restrict__ reqs)
             else ((T*)rq.V[cur ^ 1])[rq.n * ldo + j] = (T)uk;
         }
     }
-    for (int j = tid; j < kout; j += kThreads) rq.S[j] = sig[j];
+    for (int j = tid; j < kout; j += nt) rq.S[j] = sig[j];
     if (tid == 0) {
         double dN = 0.0;
         if (kind == kEntry) {
             T* A = (T*)rq.A;
-            double aold = (double)A[rq.i * rq.lda + rq.j];
+            const double aold = (double)A[rq.i * rq.lda + rq.j];
             A[rq.i * rq.lda + rq.j] = (T)(aold + rq.delta);
             dN = 2.0 * rq.delta * aold + rq.delta * rq.delta;
         } else {
@@ -407,6 +469,129 @@ __global__ void __launch_bounds__(kThreads) k_rotate(const Req* __restrict__ req
         for (int c = 0; c < kin; ++c) acc += sX[rr * ldi + c] * sQ[c * ldo + j];
         if (projected) acc += (T)sz[rr] * sQ[kin * ldo + j];
         Xo[(r0 + rr) * ldo + j] = acc;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// FP32 rotation on the matrix cores (v_mfma_f32_16x16x4f32): the same
+// X' = X Q (+ z^ Q[k, :]) as k_rotate.  A wave computes 16 output rows x KC
+// columns per step: lane l owns row l%16 and the contiguous k-range
+// [g*S, g*S+S) of it (g = l/16, S = KC/4), so its part of the row arrives
+// as float4 loads; the MFMA's k order is permuted to match (step s feeds
+// k = g*S + s of every lane group), and Q is held in registers in the same
+// permuted order for the whole block.  Output lane layout of the 16x16x4
+// FP32 instruction: D[4*(l/16) + r][l%16].  Products accumulate in FP32.
+typedef float mfma_v4f __attribute__((ext_vector_type(4)));
+
+template <int KC>
+__global__ void __launch_bounds__(kThreads) k_rotate_mfma(const Req* __restrict__ reqs,
+                                                          const int* __restrict__ prefix, int nreq) {
+    constexpr int S = KC / 4;                 // k-steps (and elements per lane)
+    constexpr int NB = KC >= 16 ? KC / 16 : 1;
+    constexpr int STEPS = kMfmaRotRows / (4 * 16);
+    const int ri = find_req(prefix, nreq, blockIdx.x);
+    const Req& rq = reqs[ri];
+    const ReqScratch* rs = rq.rs;
+    if (rs->skip) return;
+    const int tile_all = blockIdx.x - prefix[ri];
+    const bool isU = tile_all < rq.rot_tiles_u;
+    const int tile = isU ? tile_all : tile_all - rq.rot_tiles_u;
+    const int kin = rs->k_in, ldi = rs->ld_in, ldo = rs->ld_out, idx = rs->in_idx;
+    const int64_t rows = isU ? rq.m : rq.n;
+    const float* Xi = (const float*)(isU ? rq.U[idx] : rq.V[idx]);
+    float* Xo = (float*)(isU ? rq.U[idx ^ 1] : rq.V[idx ^ 1]);
+    const float* Q = (const float*)(isU ? rq.QU : rq.QV);
+    const bool projected = (rq.kind == kRow && !isU) || (rq.kind == kCol && isU);
+    const int l = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int g = l >> 4, col = l & 15;
+    // B operand: bq[nb][s] = Q[g*S + s][16 nb + col]
+    float bq[NB][S];
+    float qz[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+        const int j = 16 * nb + col;
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const int kk = g * S + s;
+            bq[nb][s] = (kk < kin && j < ldo) ? Q[kk * ldo + j] : 0.0f;
+        }
+        qz[nb] = (projected && j < ldo) ? Q[kin * ldo + j] : 0.0f;
+    }
+    double pk[S];
+    const float* y = (const float*)rq.payload;
+    const double inv_rho = rs->inv_rho;
+    if (projected) {
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const int kk = g * S + s;
+            pk[s] = kk < kin ? rq.p[kk] : 0.0;
+        }
+    }
+    const int64_t base = (int64_t)tile * kMfmaRotRows;
+    for (int st = 0; st < STEPS; ++st) {
+        const int64_t row0 = base + (int64_t)(st * 4 + wave) * 16;
+        if (row0 >= rows) break;
+        const int64_t r = row0 + (l & 15);
+        const bool live = r < rows;
+        float a[S];
+        if (live && g * S < ldi) {
+            const float* src = Xi + r * ldi + g * S;
+            if constexpr (S >= 4) {
+#pragma unroll
+                for (int s4 = 0; s4 < S / 4; ++s4) {
+                    const float4 v = *reinterpret_cast<const float4*>(src + 4 * s4);
+                    a[4 * s4 + 0] = v.x; a[4 * s4 + 1] = v.y; a[4 * s4 + 2] = v.z; a[4 * s4 + 3] = v.w;
+                }
+            } else {
+                const float2 v = *reinterpret_cast<const float2*>(src);
+                a[0] = v.x; a[1] = v.y;
+            }
+#pragma unroll
+            for (int s = 0; s < S; ++s)
+                if (g * S + s >= kin) a[s] = 0.0f;
+        } else {
+#pragma unroll
+            for (int s = 0; s < S; ++s) a[s] = 0.0f;
+        }
+        mfma_v4f acc[NB];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[nb] = (mfma_v4f){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb)
+                acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], bq[nb][s], acc[nb], 0, 0, 0);
+        if (projected) {
+            // z^ of this lane's row (row l%16 of the step), then spread to the output layout
+            double d = 0.0;
+#pragma unroll
+            for (int s = 0; s < S; ++s) d += (double)a[s] * pk[s];
+            d += __shfl_xor(d, 16);
+            d += __shfl_xor(d, 32);
+            float yv = live ? y[r] : 0.0f;
+            const float z = (float)(((double)yv - d) * inv_rho);
+            if (live && g == 0) {
+                float* A = (float*)rq.A;
+                if (rq.kind == kRow) A[rq.m * rq.lda + r] = yv;
+                else A[r * rq.lda + rq.n] = yv;
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const float zj = __shfl(z, 4 * g + j);
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) acc[nb][j] += zj * qz[nb];
+            }
+        }
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+            const int jc = 16 * nb + col;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int64_t ro = row0 + 4 * g + j;
+                if (ro < rows && jc < ldo) Xo[ro * ldo + jc] = acc[nb][j];
+            }
+        }
     }
 }
 

@@ -60,10 +60,15 @@ class CRequest(ctypes.Structure):
                 ("j", ctypes.c_int64), ("delta", ctypes.c_double)]
 
 
-EXPORTS = ["isvd_engine_create", "isvd_engine_destroy", "isvd_stream_bytes", "isvd_init",
+class CLaunchTime(ctypes.Structure):
+    _fields_ = [("phase", ctypes.c_int32), ("kc", ctypes.c_int32), ("fp64", ctypes.c_int32),
+                ("nreq", ctypes.c_int32), ("blocks", ctypes.c_int64), ("ms", ctypes.c_double)]
+
+
+EXPORTS = ["isvd_engine_create", "isvd_engine_destroy", "isvd_stream_bytes", "isvd_init", "isvd_init_from_factors",
            "isvd_append_row", "isvd_append_col", "isvd_update_entry", "isvd_refresh", "isvd_metrics",
            "isvd_get_factors", "isvd_get_matrix", "isvd_shape", "isvd_release", "isvd_tick",
-           "isvd_last_error"]
+           "isvd_profile", "isvd_profile_read", "isvd_last_error"]
 
 _lib = None
 
@@ -82,6 +87,8 @@ def load_library(path=LIB_PATH):
         "isvd_engine_destroy": (i32, [vp]),
         "isvd_stream_bytes": (ctypes.c_uint64, [ctypes.POINTER(CConfig)]),
         "isvd_init": (i32, [vp, ctypes.POINTER(CConfig), vp, i64, i32, i32, vp, ctypes.POINTER(i64)]),
+        "isvd_init_from_factors": (i32, [vp, ctypes.POINTER(CConfig), vp, i64, i32, i32, dp, i64, dp, dp, i64, vp,
+                                         ctypes.POINTER(i64)]),
         "isvd_append_row": (i32, [vp, i64, vp, i64, i32, i32, vp]),
         "isvd_append_col": (i32, [vp, i64, vp, i64, i32, i32, vp]),
         "isvd_update_entry": (i32, [vp, i64, i64, i64, ctypes.c_double, vp]),
@@ -92,6 +99,8 @@ def load_library(path=LIB_PATH):
         "isvd_shape": (i32, [vp, i64, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i32)]),
         "isvd_release": (i32, [vp, i64]),
         "isvd_tick": (i32, [vp, i32, ctypes.POINTER(CRequest), vp]),
+        "isvd_profile": (i32, [vp, i32]),
+        "isvd_profile_read": (i32, [vp, ctypes.POINTER(CLaunchTime), i32, ctypes.POINTER(i32)]),
         "isvd_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -209,6 +218,32 @@ class Engine:
         del keep
         return sid.value
 
+    def init_from_factors(self, A0, U, S, V, precision="fp32", m_cap=None, n_cap=None, tol_rel=0.0, policy=None,
+                          refresh_iters=-1, oversample=-1, stream=None):
+        """Start a stream from given FP64 factors (U m0 x k, S k, V n0 x k) and A0."""
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        S = np.ascontiguousarray(S, dtype=np.float64)
+        V = np.ascontiguousarray(V, dtype=np.float64)
+        k = S.shape[0]
+        if hasattr(A0, "data_ptr"):
+            m0, n0 = A0.shape
+            ptr, _, code, dev, keep = _payload(A0)
+            lda = A0.stride(0)
+        else:
+            a = np.ascontiguousarray(A0, dtype=np.float64 if np.asarray(A0).dtype != np.float32 else np.float32)
+            m0, n0 = a.shape
+            ptr, _, code, dev, keep = _payload(a)
+            lda = n0
+        cfg = self.config(m0, n0, k, precision, m_cap, n_cap, tol_rel, policy, refresh_iters, oversample)
+        sid = ctypes.c_int64()
+        dp = ctypes.POINTER(ctypes.c_double)
+        self._check(self._lib.isvd_init_from_factors(self._h, ctypes.byref(cfg), ptr, lda, code, dev,
+                                                     U.ctypes.data_as(dp), k, S.ctypes.data_as(dp),
+                                                     V.ctypes.data_as(dp), k, _stream_ptr(stream),
+                                                     ctypes.byref(sid)), "isvd_init_from_factors")
+        del keep
+        return sid.value
+
     def append_row(self, sid, x, stream=None):
         ptr, n, code, dev, keep = _payload(x)
         self._check(self._lib.isvd_append_row(self._h, sid, ptr, n, code, dev, _stream_ptr(stream)),
@@ -296,6 +331,16 @@ class Engine:
                 arr[q].len = pay.numel()
                 arr[q].dtype = DTYPE_F64 if str(pay.dtype) == "torch.float64" else DTYPE_F32
         return arr
+
+    def profile(self, enable=True):
+        self._check(self._lib.isvd_profile(self._h, 1 if enable else 0), "isvd_profile")
+
+    def profile_read(self):
+        cnt = ctypes.c_int32()
+        self._check(self._lib.isvd_profile_read(self._h, None, 0, ctypes.byref(cnt)), "isvd_profile_read")
+        arr = (CLaunchTime * max(cnt.value, 1))()
+        self._check(self._lib.isvd_profile_read(self._h, arr, cnt.value, ctypes.byref(cnt)), "isvd_profile_read")
+        return [{f: getattr(arr[q], f) for f, _ in CLaunchTime._fields_} for q in range(cnt.value)]
 
     def tick_raw(self, arr, stream=None):
         self._check(self._lib.isvd_tick(self._h, len(arr), arr, _stream_ptr(stream)), "isvd_tick")

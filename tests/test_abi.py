@@ -34,7 +34,8 @@ def test_struct_layouts_match_the_c_compiler(tmp_path):
     """Sizes and field offsets of the binding's structs equal what gcc lays out."""
     from paper_2605_24514_amd import isvd
     structs = {"isvd_policy": isvd.CPolicy, "isvd_config": isvd.CConfig,
-               "isvd_metrics_t": isvd.CMetrics, "isvd_request": isvd.CRequest}
+               "isvd_metrics_t": isvd.CMetrics, "isvd_request": isvd.CRequest,
+               "isvd_launch_time": isvd.CLaunchTime}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "isvd.h"', "int main(void) {"]
     for cname, cls in structs.items():
         lines.append('printf("%s %%zu\\n", sizeof(%s));' % (cname, cname))
