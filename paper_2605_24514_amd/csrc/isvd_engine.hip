@@ -160,6 +160,12 @@ struct LaunchRec {
 struct isvd_engine {
     int device = 0;
     bool profiling = false;
+    // side stream (default priority) so that rank buckets of one tick run
+    // concurrently: the long cores of the widest bucket overlap the other
+    // buckets' work
+    std::vector<hipStream_t> side;
+    std::vector<hipEvent_t> join;
+    hipEvent_t fork = nullptr;
     std::vector<LaunchRec> prof;
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
@@ -229,7 +235,7 @@ isvd_status launch_group_phase(const Group& g, const char* dev, int phase, hipSt
     } else if (phase == 1 && np > 0) {
         k_proj2<T, KC><<<g.pre_proj[np], kThreads, 0, st>>>(proj, pp, np);
     } else if (phase == 2 && na > 0) {
-        size_t lds = core_lds_bytes(g.core_lds_n, CoreShape<KC>::J::LDW, sizeof(T) == 8);
+        size_t lds = sizeof(double) * core_lds_doubles<KC, sizeof(T) == 8>();
         k_core<T, KC><<<na, CoreShape<KC>::J::NT, lds, st>>>(all);
     } else if (phase == 3 && na > 0) {
         if constexpr (sizeof(T) == 4)
@@ -262,7 +268,7 @@ isvd_status launch_phase(const Group& g, const char* dev, int phase, hipStream_t
 
 template <typename T, int KC>
 isvd_status set_lds_limits_for() {
-    ST_TRY(allow_lds(k_core<T, KC>, core_lds_bytes(CoreShape<KC>::NMAX, CoreShape<KC>::J::LDW, sizeof(T) == 8)));
+    ST_TRY(allow_lds(k_core<T, KC>, sizeof(double) * core_lds_doubles<KC, sizeof(T) == 8>()));
     return ISVD_OK;
 }
 
@@ -297,7 +303,9 @@ Req make_req(Stream& s, int kind, const void* payload, int64_t i, int64_t j, dou
     r.tol_rel = s.cfg.tol_rel;
     r.kind = kind;
     r.k_keep = k_keep;
-    r.proj_tiles = kind == kRow ? (int)cdiv(s.n, kProjTile) : kind == kCol ? (int)cdiv(s.m, kProjTile) : 0;
+    // row appends project inside the core block; column appends use the
+    // multi-block projection passes over U
+    r.proj_tiles = kind == kCol ? (int)cdiv(s.m, kProjTile) : 0;
     r.rot_tiles_u = (int)cdiv(s.m, rot_rows_for(s.kc, s.esz == 8));
     r.hdr = s.hdr;
     r.rs = s.rs;
@@ -357,8 +365,44 @@ isvd_status run_groups(isvd_engine* e, std::vector<Group>& groups, hipStream_t s
         memcpy(slot->host + g.off_pr, g.pre_rot.data(), sizeof(int) * g.pre_rot.size());
     }
     HIP_TRY(hipMemcpyAsync(slot->dev, slot->host, off, hipMemcpyHostToDevice, st));
+    // Two lanes: the caller's stream and one side stream (a process gets few
+    // hardware queues; more streams would share them and serialise).  Groups
+    // go to the lane with less estimated work, largest first; a lane runs its
+    // groups' phases in order.
+    const bool fan = groups.size() > 1;
+    std::vector<int> lane_of(groups.size(), 0);
+    if (fan) {
+        std::vector<double> cost(groups.size(), 0.0);
+        for (size_t gi = 0; gi < groups.size(); ++gi) {
+            const double kc = groups[gi].kc;
+            for (const Req& r : groups[gi].all)
+                cost[gi] += 2e-12 * kc * kc * kc * 64.0 + 1.0e-13 * kc * (double)(r.m + r.n);
+        }
+        std::vector<size_t> order(groups.size());
+        for (size_t gi = 0; gi < order.size(); ++gi) order[gi] = gi;
+        std::sort(order.begin(), order.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
+        double load[2] = {0.0, 0.0};
+        for (size_t gi : order) {
+            const int ln = load[0] <= load[1] ? 0 : 1;
+            lane_of[gi] = ln;
+            load[ln] += cost[gi];
+        }
+        if (e->side.empty()) {
+            hipStream_t sst;
+            hipEvent_t ev;
+            HIP_TRY(hipStreamCreateWithFlags(&sst, hipStreamNonBlocking));
+            HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+            e->side.push_back(sst);
+            e->join.push_back(ev);
+        }
+        if (!e->fork) HIP_TRY(hipEventCreateWithFlags(&e->fork, hipEventDisableTiming));
+        HIP_TRY(hipEventRecord(e->fork, st));
+        HIP_TRY(hipStreamWaitEvent(e->side[0], e->fork, 0));
+    }
     for (int phase = 0; phase < 4; ++phase) {
-        for (Group& g : groups) {
+        for (size_t gi = 0; gi < groups.size(); ++gi) {
+            Group& g = groups[gi];
+            hipStream_t gs = lane_of[gi] ? e->side[0] : st;
             const int np = (int)g.proj.size(), na = (int)g.all.size();
             const int nreq = phase < 2 ? np : na;
             if (nreq == 0) continue;
@@ -366,11 +410,11 @@ isvd_status run_groups(isvd_engine* e, std::vector<Group>& groups, hipStream_t s
             if (e->profiling) {
                 ST_TRY(next_event(e, &rec.b));
                 ST_TRY(next_event(e, &rec.e));
-                HIP_TRY(hipEventRecord(rec.b, st));
+                HIP_TRY(hipEventRecord(rec.b, gs));
             }
-            ST_TRY(launch_phase(g, slot->dev, phase, st));
+            ST_TRY(launch_phase(g, slot->dev, phase, gs));
             if (e->profiling) {
-                HIP_TRY(hipEventRecord(rec.e, st));
+                HIP_TRY(hipEventRecord(rec.e, gs));
                 rec.phase = phase;
                 rec.kc = g.kc;
                 rec.fp64 = g.fp64 ? 1 : 0;
@@ -379,6 +423,10 @@ isvd_status run_groups(isvd_engine* e, std::vector<Group>& groups, hipStream_t s
                 e->prof.push_back(rec);
             }
         }
+    }
+    if (fan) {
+        HIP_TRY(hipEventRecord(e->join[0], e->side[0]));
+        HIP_TRY(hipStreamWaitEvent(st, e->join[0], 0));
     }
     HIP_TRY(hipEventRecord(slot->ev, st));
     slot->used = true;
@@ -606,7 +654,7 @@ isvd_status single_update(isvd_engine* e, Stream& s, int kind, const void* paylo
     g.kc = s.kc;
     Req r = make_req(s, kind, payload, i, j, delta, k_keep_for(s));
     g.all.push_back(r);
-    if (kind != kEntry) g.proj.push_back(r);
+    if (kind == kCol) g.proj.push_back(r);
     HIP_TRY(hipEventRecord(s.ev_u0, st));
     ST_TRY(run_groups(e, groups, st));
     HIP_TRY(hipEventRecord(s.ev_u1, st));
@@ -695,6 +743,9 @@ isvd_status isvd_engine_destroy(isvd_engine* e) {
     }
     if (e->ws) (void)hipFree(e->ws);
     for (hipEvent_t ev : e->ev_pool) (void)hipEventDestroy(ev);
+    for (hipStream_t sst : e->side) (void)hipStreamDestroy(sst);
+    for (hipEvent_t ev : e->join) (void)hipEventDestroy(ev);
+    if (e->fork) (void)hipEventDestroy(e->fork);
     delete e;
     return ISVD_OK;
 }
@@ -1101,7 +1152,7 @@ isvd_status isvd_tick(isvd_engine* e, int32_t count, const isvd_request* reqs, v
         const isvd_request& r = reqs[q];
         Req rq = make_req(s, r.kind, r.payload, r.i, r.j, r.delta, k_keep_for(s));
         g.all.push_back(rq);
-        if (r.kind != ISVD_ENTRY) g.proj.push_back(rq);
+        if (r.kind == ISVD_COL) g.proj.push_back(rq);
     }
     ST_TRY(run_groups(e, groups, st));
     for (int q = 0; q < count; ++q) {

@@ -71,6 +71,8 @@ __device__ inline double dpp_group_sum(double v) {
 }
 
 // Returns the number of sweeps, or -1 if max_sweeps passed without convergence.
+// The rotation threshold is max(N eps, tol_min): a caller whose results are
+// rounded to a coarser type can stop at that type's accuracy.
 // The three dot products of a pair are computed afresh (closed-form norm
 // updates drift for columns much smaller than the others, and the drift can
 // keep rounding-level rotations alive indefinitely).  Each lane holds its
@@ -80,14 +82,14 @@ __device__ inline double dpp_group_sum(double v) {
 // WITH_J: accumulate the rotations into J (= I on entry); without it only W
 // is rotated.
 template <int NMAX, bool WITH_J>
-__device__ inline int jacobi_block(double* W, double* J, int N, int ldw, int max_sweeps) {
+__device__ inline int jacobi_block(double* W, double* J, int N, int ldw, int max_sweeps, double tol_min = 0.0) {
     typedef JacobiShape<NMAX> S;
     const int tid = threadIdx.x;
     const int Np = N + (N & 1);
     const int npairs = Np >> 1;
     const int g = tid / S::TPP;
     const int lane = tid % S::TPP;
-    const double tol = (double)N * 2.220446049250313e-16;
+    const double tol = fmax((double)N * 2.220446049250313e-16, tol_min);
     const double tol2 = tol * tol;
     __shared__ int s_rot[2];
     int sweeps = -1;

@@ -186,6 +186,101 @@ __global__ void __launch_bounds__(kThreads) k_proj2(const Req* __restrict__ reqs
 }
 
 // ---------------------------------------------------------------------------
+// In-block projection of a row append (both classical Gram-Schmidt passes),
+// run by the core's block itself: V (n x k) is small, so one block reads it
+// twice and no cross-block reduction is needed.  Same sums and FP64
+// accumulation as k_proj1 / k_proj2; results in LDS:
+//   out1[0..k) = p1, out1[KC] = ||x||^2, out1[KC+1] = non-finite count
+//   out2[0..k) = p2, out2[KC] = ||z1||^2
+// red: LDS scratch of (blockDim.x / (KC/4)) * (KC + 2) doubles.
+template <typename T, int KC>
+__device__ inline void block_project(const T* __restrict__ X, int ld, int k, const T* __restrict__ y,
+                                     int64_t rows, double* red, double* out1, double* out2) {
+    constexpr int LPR = KC / 4;
+    constexpr int SP = KC + 2;
+    constexpr int UNR = 8;                     // rows in flight per lane
+    const int nt = blockDim.x;
+    const int rps = nt / LPR;
+    const int lane = threadIdx.x % LPR, grp = threadIdx.x / LPR;
+    const int c0 = lane * 4;
+    const bool colok = c0 < k;
+    double cm[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) cm[q] = c0 + q < k ? 1.0 : 0.0;
+    for (int pass = 0; pass < 2; ++pass) {
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        double sq = 0.0, bad = 0.0;
+        double pp[4] = {0.0, 0.0, 0.0, 0.0};
+        if (pass == 1)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) pp[q] = c0 + q < k ? out1[c0 + q] : 0.0;
+        // every lane runs the same trip count (pass 2 shuffles across lanes)
+        for (int64_t b0 = 0; b0 < rows; b0 += (int64_t)rps * UNR) {
+            const int64_t base = b0 + grp;
+            double xv[UNR][4];
+            double yv[UNR];
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) {
+                const int64_t r = base + (int64_t)u * rps;
+                const bool live = r < rows;
+                if (live && colok) {
+                    load4<T>(X + r * ld + c0, xv[u]);
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) xv[u][q] = 0.0;
+                }
+                yv[u] = live ? (double)y[r] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) xv[u][q] *= cm[q];
+                if (pass == 0) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) acc[q] += yv[u] * xv[u][q];
+                    if (lane == 0) {
+                        sq += yv[u] * yv[u];
+                        if (!isfinite(yv[u])) bad += 1.0;
+                    }
+                }
+            }
+            if (pass == 1) {
+                double d[UNR];
+#pragma unroll
+                for (int u = 0; u < UNR; ++u)
+                    d[u] = xv[u][0] * pp[0] + xv[u][1] * pp[1] + xv[u][2] * pp[2] + xv[u][3] * pp[3];
+#pragma unroll
+                for (int o = LPR >> 1; o > 0; o >>= 1)
+#pragma unroll
+                    for (int u = 0; u < UNR; ++u) d[u] += __shfl_xor(d[u], o);
+#pragma unroll
+                for (int u = 0; u < UNR; ++u) {
+                    const bool live = base + (int64_t)u * rps < rows;
+                    const double z1 = live ? yv[u] - d[u] : 0.0;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) acc[q] += xv[u][q] * z1;
+                    if (lane == 0) sq += z1 * z1;
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) red[grp * SP + c0 + q] = acc[q];
+        if (lane == 0) {
+            red[grp * SP + KC] = sq;
+            red[grp * SP + KC + 1] = bad;
+        }
+        __syncthreads();
+        double* out = pass == 0 ? out1 : out2;
+        for (int c = threadIdx.x; c < SP; c += nt) {
+            double ssum = 0.0;
+            for (int g2 = 0; g2 < rps; ++g2) ssum += red[g2 * SP + c];
+            out[c] = ssum;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Core: assemble K, its FP64 SVD, sort, sign, truncate, and the rotation
 // matrices for U and V.
 //   row append   K = [[Sigma, 0], [p, rho]]       (Alg. A1, (k+1) x (k+1))
@@ -212,6 +307,13 @@ struct CoreShape {
     typedef JacobiShape<NMAX> J;
 };
 
+// dynamic LDS (doubles) of a core block of bucket KC
+template <int KC, bool WITH_J>
+__host__ __device__ constexpr size_t core_lds_doubles() {
+    return (size_t)(WITH_J ? 2 : 1) * CoreShape<KC>::NMAX * CoreShape<KC>::J::LDW +
+           (size_t)(WITH_J ? 6 : 8) * CoreShape<KC>::NMAX;
+}
+
 template <typename T, int KC>
 __global__ void __launch_bounds__(CoreShape<KC>::J::NT) k_core(const Req* __restrict__ reqs) {
     constexpr bool WITH_J = sizeof(T) == 8;
@@ -237,16 +339,30 @@ __global__ void __launch_bounds__(CoreShape<KC>::J::NT) k_core(const Req* __rest
     double* su = tmp + 2 * N;                      // s_u (rank-1, no J)
     double* dcol = su + N;                         // s_u . W[:, c] (rank-1, no J)
 
+    // projection sums: computed here for a row append (V is small), by the
+    // k_proj1 / k_proj2 launches for a column append (U can be large)
+    const double* src1 = rq.p;
+    const double* src2 = rq.p2;
+    if (kind == kRow) {
+        const size_t total = core_lds_doubles<KC, WITH_J>();
+        double* out1 = smem + total - 2 * (KC + 2);
+        double* out2 = out1 + (KC + 2);
+        block_project<T, KC>((const T*)rq.V[cur], ld, k, (const T*)rq.payload, rq.n, smem, out1, out2);
+        src1 = out1;
+        src2 = out2;
+    }
+    double pc = 0.0;
+    if (kind != kEntry && tid < k) pc = src1[tid] + src2[tid];
     if (tid == 0) {
         int skip = hdr->status != 0 ? 1 : 0;
         double rho = 0.0, xnorm = 0.0, inv_rho = 0.0;
         int newdir = 0;
         if (kind != kEntry) {
-            if (rq.p[KC + 1] > 0.0) skip = 1;
+            if (src1[KC + 1] > 0.0) skip = 1;
             double p2sq = 0.0;
-            for (int c = 0; c < k; ++c) p2sq += rq.p2[c] * rq.p2[c];
-            const double z1sq = rq.p2[KC];
-            const double ysq = rq.p[KC];
+            for (int c = 0; c < k; ++c) p2sq += src2[c] * src2[c];
+            const double z1sq = src2[KC];
+            const double ysq = src1[KC];
             const double r2 = z1sq - p2sq;
             rho = r2 > 0.0 ? sqrt(r2) : 0.0;
             xnorm = sqrt(ysq);
@@ -262,6 +378,7 @@ __global__ void __launch_bounds__(CoreShape<KC>::J::NT) k_core(const Req* __rest
         s_sc[0] = rho;
         s_sc[1] = xnorm;
         s_sc[2] = inv_rho;
+        s_sc[3] = kind != kEntry ? src1[KC] : 0.0;
     }
     __syncthreads();
     if (s_i[0]) {
@@ -277,7 +394,6 @@ __global__ void __launch_bounds__(CoreShape<KC>::J::NT) k_core(const Req* __rest
     for (int c = tid; c < k; c += nt) {
         sS[c] = rq.S[c];
         if (kind != kEntry) {
-            const double pc = rq.p[c] + rq.p2[c];
             sp[c] = pc;
             rq.p[c] = pc;
         } else {
@@ -306,7 +422,8 @@ __global__ void __launch_bounds__(CoreShape<KC>::J::NT) k_core(const Req* __rest
         if constexpr (WITH_J) J[e] = (row == col) ? 1.0 : 0.0;
     }
     __syncthreads();
-    const int sweeps = jacobi_block<CoreShape<KC>::NMAX, WITH_J>(W, J, N, ldw, 40);
+    // FP32 storage rounds U_K, V_K to 6e-8: columns orthogonal to 1e-10 suffice
+    const int sweeps = jacobi_block<CoreShape<KC>::NMAX, WITH_J>(W, J, N, ldw, 40, WITH_J ? 0.0 : 1e-10);
     jacobi_sort(W, N, ldw, sig, perm, tmp);
     if constexpr (!WITH_J) {
         if (kind == kEntry) {
@@ -386,7 +503,7 @@ __global__ void __launch_bounds__(CoreShape<KC>::J::NT) k_core(const Req* __rest
             A[rq.i * rq.lda + rq.j] = (T)(aold + rq.delta);
             dN = 2.0 * rq.delta * aold + rq.delta * rq.delta;
         } else {
-            dN = rq.p[KC];
+            dN = s_sc[3];
         }
         rs->skip = 0;
         rs->k_in = k;
@@ -474,21 +591,36 @@ __global__ void __launch_bounds__(kThreads) k_rotate(const Req* __restrict__ req
 
 // ---------------------------------------------------------------------------
 // FP32 rotation on the matrix cores (v_mfma_f32_16x16x4f32): the same
-// X' = X Q (+ z^ Q[k, :]) as k_rotate.  A wave computes 16 output rows x KC
-// columns per step: lane l owns row l%16 and the contiguous k-range
-// [g*S, g*S+S) of it (g = l/16, S = KC/4), so its part of the row arrives
-// as float4 loads; the MFMA's k order is permuted to match (step s feeds
-// k = g*S + s of every lane group), and Q is held in registers in the same
-// permuted order for the whole block.  Output lane layout of the 16x16x4
-// FP32 instruction: D[4*(l/16) + r][l%16].  Products accumulate in FP32.
+// X' = X Q (+ z^ Q[k, :]) as k_rotate.  A wave works on 16-row tiles; a
+// tile of U or V is contiguous in HBM (16 x ld floats), so it is loaded and
+// stored with contiguous dwordx4 accesses (64 lanes x 16 B per instruction)
+// and staged through LDS; the next tile's loads are issued before the
+// current tile's MFMAs.  MFMA operands: lane l owns row l%16 and the
+// contiguous k-range [g*S, g*S+S) (g = l/16, S = KC/4) of it, the MFMA's
+// k order is permuted to match (step s feeds k = g*S + s of every lane
+// group); Q sits in LDS in the same order.  Output lane layout of the
+// 16x16x4 FP32 instruction: D[4*(l/16) + r][l%16].  FP32 accumulation.
 typedef float mfma_v4f __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) const float gcfloat;
+typedef __attribute__((address_space(1))) float gfloat;
+typedef __attribute__((address_space(1))) const mfma_v4f gcf4;
+typedef __attribute__((address_space(1))) mfma_v4f gf4;
 
 template <int KC>
 __global__ void __launch_bounds__(kThreads) k_rotate_mfma(const Req* __restrict__ reqs,
                                                           const int* __restrict__ prefix, int nreq) {
     constexpr int S = KC / 4;                 // k-steps (and elements per lane)
     constexpr int NB = KC >= 16 ? KC / 16 : 1;
+    constexpr int NCOL = NB * 16;             // output columns computed
+    constexpr int XP = KC + 4;                // LDS row stride of X tiles (bank spread)
+    constexpr int OP = NCOL + 4;              // LDS row stride of output tiles
+    constexpr int QP = NCOL + 4;              // LDS row stride of Q
     constexpr int STEPS = kMfmaRotRows / (4 * 16);
+    constexpr int VPL = (16 * KC / 4 + 63) / 64;   // float4 per lane per tile (upper bound)
+    __shared__ float sQ[(KC + 1) * QP];
+    __shared__ float sX[4][16 * XP];
+    __shared__ float sO[4][16 * OP];
+    __shared__ double sp[KC];
     const int ri = find_req(prefix, nreq, blockIdx.x);
     const Req& rq = reqs[ri];
     const ReqScratch* rs = rq.rs;
@@ -498,100 +630,129 @@ __global__ void __launch_bounds__(kThreads) k_rotate_mfma(const Req* __restrict_
     const int tile = isU ? tile_all : tile_all - rq.rot_tiles_u;
     const int kin = rs->k_in, ldi = rs->ld_in, ldo = rs->ld_out, idx = rs->in_idx;
     const int64_t rows = isU ? rq.m : rq.n;
-    const float* Xi = (const float*)(isU ? rq.U[idx] : rq.V[idx]);
-    float* Xo = (float*)(isU ? rq.U[idx ^ 1] : rq.V[idx ^ 1]);
-    const float* Q = (const float*)(isU ? rq.QU : rq.QV);
+    gcfloat* Xi = (gcfloat*)(isU ? rq.U[idx] : rq.V[idx]);
+    gfloat* Xo = (gfloat*)(isU ? rq.U[idx ^ 1] : rq.V[idx ^ 1]);
+    gcfloat* Q = (gcfloat*)(isU ? rq.QU : rq.QV);
     const bool projected = (rq.kind == kRow && !isU) || (rq.kind == kCol && isU);
+    const int nq = kin + (projected ? 1 : 0);
+    for (int e = threadIdx.x; e < (KC + 1) * QP; e += kThreads) {
+        const int kk = e / QP, j = e % QP;
+        sQ[e] = (kk < nq && j < ldo) ? Q[kk * ldo + j] : 0.0f;
+    }
+    if (projected)
+        for (int c = threadIdx.x; c < KC; c += kThreads) sp[c] = c < kin ? rq.p[c] : 0.0;
+    __syncthreads();
     const int l = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int g = l >> 4, col = l & 15;
-    // B operand: bq[nb][s] = Q[g*S + s][16 nb + col]
-    float bq[NB][S];
-    float qz[NB];
+    // B operand in registers for the narrow buckets; from LDS for the wide
+    // ones, where registers for it would cost occupancy (measured slower)
+    constexpr bool BREG = NB * S <= 16;
+    float bq[BREG ? NB : 1][BREG ? S : 1];
+    if constexpr (BREG) {
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-        const int j = 16 * nb + col;
+        for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-        for (int s = 0; s < S; ++s) {
-            const int kk = g * S + s;
-            bq[nb][s] = (kk < kin && j < ldo) ? Q[kk * ldo + j] : 0.0f;
-        }
-        qz[nb] = (projected && j < ldo) ? Q[kin * ldo + j] : 0.0f;
+            for (int s4 = 0; s4 < S; ++s4) bq[nb][s4] = sQ[(g * S + s4) * QP + 16 * nb + col];
     }
-    double pk[S];
-    const float* y = (const float*)rq.payload;
-    const double inv_rho = rs->inv_rho;
-    if (projected) {
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-            const int kk = g * S + s;
-            pk[s] = kk < kin ? rq.p[kk] : 0.0;
-        }
-    }
+    float* sx = sX[wave];
+    float* so = sO[wave];
     const int64_t base = (int64_t)tile * kMfmaRotRows;
-    for (int st = 0; st < STEPS; ++st) {
-        const int64_t row0 = base + (int64_t)(st * 4 + wave) * 16;
-        if (row0 >= rows) break;
-        const int64_t r = row0 + (l & 15);
-        const bool live = r < rows;
-        float a[S];
-        if (live && g * S < ldi) {
-            const float* src = Xi + r * ldi + g * S;
-            if constexpr (S >= 4) {
+    const int ntile_vec_in = 4 * ldi;       // float4 per 16-row input tile
+    const int ntile_vec_out = 4 * ldo;
+    // prefetch of a tile into registers
+    mfma_v4f pre[VPL];
+    auto fetch = [&](int64_t row0, int nr) {
 #pragma unroll
-                for (int s4 = 0; s4 < S / 4; ++s4) {
-                    const float4 v = *reinterpret_cast<const float4*>(src + 4 * s4);
-                    a[4 * s4 + 0] = v.x; a[4 * s4 + 1] = v.y; a[4 * s4 + 2] = v.z; a[4 * s4 + 3] = v.w;
-                }
-            } else {
-                const float2 v = *reinterpret_cast<const float2*>(src);
-                a[0] = v.x; a[1] = v.y;
-            }
-#pragma unroll
-            for (int s = 0; s < S; ++s)
-                if (g * S + s >= kin) a[s] = 0.0f;
-        } else {
-#pragma unroll
-            for (int s = 0; s < S; ++s) a[s] = 0.0f;
+        for (int v = 0; v < VPL; ++v) {
+            const int f = l + 64 * v;
+            if (f < ntile_vec_in && 4 * f < nr * ldi) pre[v] = ((gcf4*)(Xi + row0 * ldi))[f];
+            else pre[v] = (mfma_v4f){0.f, 0.f, 0.f, 0.f};
         }
+    };
+    int64_t row0 = base + (int64_t)wave * 16;
+    int nr = row0 < rows ? (int)min((int64_t)16, rows - row0) : 0;
+    if (nr > 0) fetch(row0, nr);
+    const float* yv_base = (const float*)rq.payload;
+    const double inv_rho = rs->inv_rho;
+    for (int st = 0; st < STEPS; ++st) {
+        if (nr <= 0) break;
+        // registers -> LDS tile (row stride XP), zero columns >= kin
+#pragma unroll
+        for (int v = 0; v < VPL; ++v) {
+            const int f = l + 64 * v;
+            if (f < ntile_vec_in) {
+                const int e = 4 * f;
+                const int r = e / ldi, c = e % ldi;
+                float* d = sx + r * XP + c;
+                d[0] = c + 0 < kin ? pre[v][0] : 0.0f;
+                d[1] = c + 1 < kin ? pre[v][1] : 0.0f;
+                d[2] = c + 2 < kin ? pre[v][2] : 0.0f;
+                d[3] = c + 3 < kin ? pre[v][3] : 0.0f;
+            }
+        }
+        for (int c = ldi + l; c < KC; c += 64)          // columns beyond ld_in
+            for (int r = 0; r < 16; ++r) sx[r * XP + c] = 0.0f;
+        // next tile's loads in flight during this tile's MFMAs
+        const int64_t nrow0 = row0 + 64;
+        const int nnr = (st + 1 < STEPS && nrow0 < rows) ? (int)min((int64_t)16, rows - nrow0) : 0;
+        if (nnr > 0) fetch(nrow0, nnr);
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        float a[S];
+#pragma unroll
+        for (int s4 = 0; s4 < S; ++s4) a[s4] = sx[col * XP + g * S + s4];
         mfma_v4f acc[NB];
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) acc[nb] = (mfma_v4f){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int s = 0; s < S; ++s)
+        for (int s4 = 0; s4 < S; ++s4)
 #pragma unroll
-            for (int nb = 0; nb < NB; ++nb)
-                acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], bq[nb][s], acc[nb], 0, 0, 0);
+            for (int nb = 0; nb < NB; ++nb) {
+                float bv;
+                if constexpr (BREG) bv = bq[nb][s4];
+                else bv = sQ[(g * S + s4) * QP + 16 * nb + col];
+                acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s4], bv, acc[nb], 0, 0, 0);
+            }
         if (projected) {
-            // z^ of this lane's row (row l%16 of the step), then spread to the output layout
+            // z^ of this lane's row (row l%16 of the tile), spread to the output layout
             double d = 0.0;
 #pragma unroll
-            for (int s = 0; s < S; ++s) d += (double)a[s] * pk[s];
+            for (int s4 = 0; s4 < S; ++s4) d += (double)a[s4] * sp[g * S + s4];
             d += __shfl_xor(d, 16);
             d += __shfl_xor(d, 32);
-            float yv = live ? y[r] : 0.0f;
+            const bool live = col < nr;
+            const float yv = live ? yv_base[row0 + col] : 0.0f;
             const float z = (float)(((double)yv - d) * inv_rho);
             if (live && g == 0) {
-                float* A = (float*)rq.A;
-                if (rq.kind == kRow) A[rq.m * rq.lda + r] = yv;
-                else A[r * rq.lda + rq.n] = yv;
+                gfloat* A = (gfloat*)rq.A;
+                if (rq.kind == kRow) A[rq.m * rq.lda + row0 + col] = yv;
+                else A[(row0 + col) * rq.lda + rq.n] = yv;
             }
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const float zj = __shfl(z, 4 * g + j);
 #pragma unroll
-                for (int nb = 0; nb < NB; ++nb) acc[nb][j] += zj * qz[nb];
+                for (int nb = 0; nb < NB; ++nb) acc[nb][j] += zj * sQ[kin * QP + 16 * nb + col];
             }
         }
+        // accumulators -> LDS output tile -> contiguous stores
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-            const int jc = 16 * nb + col;
+        for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int64_t ro = row0 + 4 * g + j;
-                if (ro < rows && jc < ldo) Xo[ro * ldo + jc] = acc[nb][j];
-            }
+            for (int j = 0; j < 4; ++j) so[(4 * g + j) * OP + 16 * nb + col] = acc[nb][j];
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        for (int f = l; f < ntile_vec_out && 4 * f < nr * ldo; f += 64) {
+            const int e = 4 * f;
+            const int r = e / ldo, c = e % ldo;
+            const float* src = so + r * OP + c;
+            ((gf4*)(Xo + row0 * ldo))[f] = (mfma_v4f){src[0], src[1], src[2], src[3]};
         }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        row0 = nrow0;
+        nr = nnr;
     }
 }
 
