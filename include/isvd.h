@@ -86,7 +86,11 @@ enum {
     ISVD_POL_ERROR = 2,     /* at t = 0 mod check_every: refresh iff frob_ratio > gamma
                                and t - t_last >= t_min (eq. error-refresh-rule) */
     ISVD_POL_ANGLE = 3,     /* refresh iff theta_ref > theta_max (Section 3.3) */
-    ISVD_POL_ADAPTIVE = 4   /* EVR / novelty rank rule + periodic refresh (Section 3.4) */
+    ISVD_POL_ADAPTIVE = 4   /* EVR / novelty rank rule + periodic refresh (Section 3.4):
+                               grow by one on the next append when EVR < tau - band or
+                               the append had rho / ||x|| > eta; otherwise shrink by one
+                               when EVR without the last triplet >= tau + band; rank in
+                               [max(k_min, 1), k_max] */
 };
 
 typedef struct {
@@ -126,7 +130,7 @@ typedef struct {
     double frob_error;      /* E_inc = ||A_t - U S V^T||_F      (NaN unless compute_exact) */
     double frob_opt;        /* E_opt from the refresh's Ritz values (NaN unless compute_exact) */
     double frob_gap, frob_ratio;   /* eq. frob-ratio; NaN if undefined or not computed */
-    double ortho_U, ortho_V;       /* max |(Q^T Q - I)_ij| (NaN unless compute_exact) */
+    double ortho_U, ortho_V;       /* ||Q^T Q - I||_2 (NaN unless compute_exact) */
     double update_time_us;  /* wall-clock of the last immediate-mode update (host-timed) */
     double opt_time_us;     /* wall-clock of the last refresh (host-timed) */
 } isvd_metrics_t;
@@ -187,8 +191,12 @@ isvd_status isvd_update_entry(isvd_engine* eng, isvd_id id, int64_t i, int64_t j
 isvd_status isvd_refresh(isvd_engine* eng, isvd_id id, int32_t store_reference, void* hip_stream);
 
 /* Metrics of the stream.  Waits for the device.  compute_exact != 0 adds
- * E_inc (one pass over A), E_opt (a refresh-style subspace iteration that
- * does not replace the factors) and the orthogonality of U and V. */
+ * E_inc (one pass over A), E_opt = sqrt(||A||_F^2 - sum of the k leading
+ * squared Ritz values of a refresh-style subspace iteration that does not
+ * replace the factors; exact when the refresh block spans all columns, else
+ * an upper bound) and the orthogonality of U and V.  The error policy uses
+ * the same computation at its check ticks and commits that iteration's
+ * result as the refresh when it fires. */
 isvd_status isvd_metrics(isvd_engine* eng, isvd_id id, int32_t compute_exact, void* hip_stream,
                          isvd_metrics_t* out);
 

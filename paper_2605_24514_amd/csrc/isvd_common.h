@@ -32,9 +32,12 @@ struct DevHeader {
     int64_t n_rejected;
     double N;             // ||A_t||_F^2
     double rho, xnorm, novelty, sigma_dropped;
+    double sigma2;        // sum of the kept sigma^2
+    double sigma_last;    // smallest kept sigma
     int32_t sweeps;       // Jacobi sweeps of the last core (-1: sweep cap reached)
     int32_t new_dir;      // last append had rho > tol
-    int32_t pad[2];
+    int32_t last_kind;    // kind of the last applied update
+    int32_t pad;
 };
 
 // Written by the core kernel of a request, read by its rotation kernel.

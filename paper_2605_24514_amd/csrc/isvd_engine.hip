@@ -93,6 +93,8 @@ struct Stream {
     hipEvent_t ev_u0 = nullptr, ev_u1 = nullptr, ev_r0 = nullptr, ev_r1 = nullptr;
     bool have_update_time = false, have_refresh_time = false;
     bool live = false;
+    bool grow_pending = false;   // adaptive rank: the next append keeps one more triplet
+    double last_ratio = 0.0;     // error policy: frob_ratio at its last check
 };
 
 Layout make_layout(const isvd_config& c, int esz, int kc, int64_t* ntiles_max) {
@@ -176,6 +178,13 @@ struct isvd_engine {
     // refresh workspace (sized for the largest refresh so far)
     char* ws = nullptr;
     size_t ws_bytes = 0;
+    // exact-metrics workspace
+    char* mws = nullptr;
+    size_t mws_bytes = 0;
+    // pinned copies of the device headers of a tick's streams whose policy
+    // reads the trackers (one copy-back per tick)
+    DevHeader* hdrs_host = nullptr;
+    int hdr_cap = 0;
 };
 
 namespace {
@@ -204,6 +213,8 @@ isvd_status allow_lds(K kern, size_t bytes) {
 size_t core_lds_bytes(int N, int ldw, bool with_j) {
     return sizeof(double) * (size_t)((with_j ? 2 : 1) * N * ldw + (with_j ? 6 : 8) * N);
 }
+
+size_t sym_norm2_lds(int k) { return sizeof(double) * (size_t)((k + 1) * JacobiShape<kMaxBlock + 1>::LDW + k); }
 
 // Acquire a staging slot of at least `bytes`; waits for its previous use.
 isvd_status acquire_slot(isvd_engine* e, size_t bytes, Slot** out) {
@@ -286,6 +297,7 @@ isvd_status set_lds_limits() {
     const size_t svd_lds = core_lds_bytes(kMaxBlock, JacobiShape<kMaxBlock + 1>::LDW, true);
     ST_TRY(allow_lds(k_svd_small<float>, svd_lds));
     ST_TRY(allow_lds(k_svd_small<double>, svd_lds));
+    ST_TRY(allow_lds(k_sym_norm2, sym_norm2_lds(kMaxBlock)));
     ST_TRY(allow_lds(k_chol_inv<float>, sizeof(double) * 2 * kMaxBlock * kMaxBlock));
     ST_TRY(allow_lds(k_chol_inv<double>, sizeof(double) * 2 * kMaxBlock * kMaxBlock));
     return ISVD_OK;
@@ -462,7 +474,7 @@ WsLayout ws_layout(int64_t m, int64_t n, int b, int esz) {
     w.Sr = take(sizeof(double) * 128);
     w.flag = take(sizeof(int) * 4);
     w.sweeps = take(sizeof(int) * 4);
-    w.fro = take(sizeof(double) * (size_t)cdiv(m, kChunkRows));
+    w.fro = take(sizeof(double) * (size_t)cdiv(m, kFroRows));
     w.total = off;
     return w;
 }
@@ -521,9 +533,19 @@ isvd_status cholqr2(isvd_engine* e, const WsLayout& w, T* Y, int64_t rows, int b
     return ISVD_OK;
 }
 
-// TruncatedSVD(A_t, k) into the stream's next U / V buffers; S in place.
+// TruncatedSVD(A_t, k), in two steps so that a check of the error policy can
+// compute it, look at its Ritz values, and commit it only if the policy fires.
+struct RefreshPlan {
+    int k = 0, b = 0, ldo = 0, cur = 0;
+    int64_t m = 0, n = 0;
+    WsLayout w{};
+};
+
+// Block subspace iteration up to the Rayleigh-Ritz SVD: Ritz values in ws.Sr,
+// left / right rotations of the block in ws.QU / ws.QV, block bases in
+// ws.Y (Q_Y) and ws.X.  Nothing of the stream changes.
 template <typename T>
-isvd_status refresh_impl(isvd_engine* e, Stream& s, bool init, bool store_ref, hipStream_t st) {
+isvd_status refresh_compute(isvd_engine* e, Stream& s, bool init, hipStream_t st, RefreshPlan* plan) {
     DevHeader h{};
     if (!init) {
         HIP_TRY(hipMemcpyAsync(&h, s.hdr, sizeof(DevHeader), hipMemcpyDeviceToHost, st));
@@ -565,29 +587,94 @@ isvd_status refresh_impl(isvd_engine* e, Stream& s, bool init, bool store_ref, h
     k_gemm_nn<T><<<(int)cdiv(m, kGemmRows), kThreads, 0, st>>>(A, lda, X, b, Y, b, m, n, b);
     ST_TRY(cholqr2<T>(e, w, Y, m, b, true, st));
     const int ldo = round4(k);
-    T* QU = (T*)(ws + w.QU);
-    T* QV = (T*)(ws + w.QV);
-    k_svd_small<T><<<1, JacobiShape<kMaxBlock + 1>::NT, core_lds_bytes(kMaxBlock, JacobiShape<kMaxBlock + 1>::LDW, true), st>>>((const double*)(ws + w.Racc), b, k, s.S, QU, QV, ldo,
-                                                            (int*)(ws + w.sweeps));
-    const int nxt = cur ^ 1;
-    k_rotate_plain<T, 128><<<(int)cdiv(m, 16), kThreads, 0, st>>>(Y, b, (T*)s.U[nxt], ldo, m, b, QU);
-    k_rotate_plain<T, 128><<<(int)cdiv(n, 16), kThreads, 0, st>>>(X, b, (T*)s.V[nxt], ldo, n, b, QV);
-    k_set_header<<<1, 1, 0, st>>>(s.hdr, k, ldo, 1, 0);
+    k_svd_small<T><<<1, JacobiShape<kMaxBlock + 1>::NT,
+                     core_lds_bytes(kMaxBlock, JacobiShape<kMaxBlock + 1>::LDW, true), st>>>(
+        (const double*)(ws + w.Racc), b, k, (double*)(ws + w.Sr), (T*)(ws + w.QU), (T*)(ws + w.QV), ldo,
+        (int*)(ws + w.sweeps));
+    HIP_TRY(hipGetLastError());
+    plan->k = k;
+    plan->b = b;
+    plan->ldo = ldo;
+    plan->cur = cur;
+    plan->m = m;
+    plan->n = n;
+    plan->w = w;
+    return ISVD_OK;
+}
+
+// Header after a refresh: the rank is the number of Ritz values above
+// 8 b eps64 sigma_1 (at least one): directions the block does not resolve
+// (A of numerical rank below k) are left out, and appends bring the rank back.
+__global__ void k_commit_header(DevHeader* hdr, const double* S, int k, int ld, int b) {
+    if (threadIdx.x == 0) {
+        const double cut = 8.0 * b * 2.220446049250313e-16 * S[0];
+        int kr = 1;
+        while (kr < k && S[kr] > cut) ++kr;
+        double s2 = 0.0;
+        for (int j = 0; j < kr; ++j) s2 += S[j] * S[j];
+        hdr->k = kr;
+        hdr->ld = ld;
+        hdr->cur ^= 1;
+        hdr->sigma2 = s2;
+        hdr->sigma_last = S[kr - 1];
+    }
+}
+
+__global__ void k_sigma_trackers(DevHeader* hdr, const double* S, int k) {
+    if (threadIdx.x == 0) {
+        double s2 = 0.0;
+        for (int j = 0; j < k; ++j) s2 += S[j] * S[j];
+        hdr->sigma2 = s2;
+        hdr->sigma_last = k > 0 ? S[k - 1] : 0.0;
+    }
+}
+
+// Adaptive rank: drop the last triplet (columns past k are ignored by every kernel).
+__global__ void k_shrink(DevHeader* hdr, const double* S) {
+    if (threadIdx.x == 0 && hdr->k > 1) {
+        const int k = hdr->k - 1;
+        hdr->k = k;
+        hdr->sigma2 -= S[k] * S[k];
+        hdr->sigma_last = S[k - 1];
+    }
+}
+
+// Install the computed TruncatedSVD as the stream's state.
+template <typename T>
+isvd_status refresh_commit(isvd_engine* e, Stream& s, const RefreshPlan& plan, bool store_ref, hipStream_t st) {
+    char* ws = e->ws;
+    const WsLayout& w = plan.w;
+    const int nxt = plan.cur ^ 1;
+    HIP_TRY(hipMemcpyAsync(s.S, ws + w.Sr, sizeof(double) * plan.k, hipMemcpyDeviceToDevice, st));
+    k_rotate_plain<T, 128><<<(int)cdiv(plan.m, 16), kThreads, 0, st>>>((T*)(ws + w.Y), plan.b, (T*)s.U[nxt],
+                                                                      plan.ldo, plan.m, plan.b, (T*)(ws + w.QU));
+    k_rotate_plain<T, 128><<<(int)cdiv(plan.n, 16), kThreads, 0, st>>>((T*)(ws + w.X), plan.b, (T*)s.V[nxt],
+                                                                      plan.ldo, plan.n, plan.b, (T*)(ws + w.QV));
+    k_commit_header<<<1, 1, 0, st>>>(s.hdr, s.S, plan.k, plan.ldo, plan.b);
     if (store_ref)
-        HIP_TRY(hipMemcpyAsync(s.Uref, s.U[nxt], (size_t)sizeof(T) * m * ldo, hipMemcpyDeviceToDevice, st));
+        HIP_TRY(hipMemcpyAsync(s.Uref, s.U[nxt], (size_t)sizeof(T) * plan.m * plan.ldo, hipMemcpyDeviceToDevice,
+                               st));
     HIP_TRY(hipGetLastError());
     int sweeps = 0;
     HIP_TRY(hipMemcpyAsync(&sweeps, ws + w.sweeps, sizeof(int), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     if (sweeps < 0) return fail(ISVD_E_CONVERGE, "Rayleigh-Ritz Jacobi did not converge");
-    s.k_target = k;
+    s.k_target = plan.k;
     return ISVD_OK;
 }
 
-isvd_status do_refresh(isvd_engine* e, Stream& s, bool init, bool store_ref, hipStream_t st) {
+isvd_status do_refresh(isvd_engine* e, Stream& s, bool init, bool store_ref, hipStream_t st,
+                       const RefreshPlan* computed = nullptr) {
     HIP_TRY(hipEventRecord(s.ev_r0, st));
-    isvd_status rc = s.esz == 8 ? refresh_impl<double>(e, s, init, store_ref, st)
-                                : refresh_impl<float>(e, s, init, store_ref, st);
+    RefreshPlan plan;
+    isvd_status rc = ISVD_OK;
+    if (computed) {
+        plan = *computed;
+    } else {
+        rc = s.esz == 8 ? refresh_compute<double>(e, s, init, st, &plan) : refresh_compute<float>(e, s, init, st, &plan);
+        if (rc != ISVD_OK) return rc;
+    }
+    rc = s.esz == 8 ? refresh_commit<double>(e, s, plan, store_ref, st) : refresh_commit<float>(e, s, plan, store_ref, st);
     if (rc != ISVD_OK) return rc;
     HIP_TRY(hipEventRecord(s.ev_r1, st));
     s.have_refresh_time = true;
@@ -598,11 +685,143 @@ isvd_status do_refresh(isvd_engine* e, Stream& s, bool init, bool store_ref, hip
     return ISVD_OK;
 }
 
-// Policy evaluation after the update at tick t (Algorithm 1).
-isvd_status after_update(isvd_engine* e, Stream& s, hipStream_t st) {
+// ------------------------------------------------------------ exact metrics
+isvd_status ensure_mws(isvd_engine* e, size_t bytes) {
+    if (e->mws_bytes >= bytes) return ISVD_OK;
+    if (e->mws) {
+        HIP_TRY(hipDeviceSynchronize());
+        HIP_TRY(hipFree(e->mws));
+        e->mws = nullptr;
+        e->mws_bytes = 0;
+    }
+    if (hipMalloc((void**)&e->mws, bytes) != hipSuccess) {
+        e->mws = nullptr;
+        return fail(ISVD_E_NOMEM, "metrics workspace of %zu bytes", bytes);
+    }
+    e->mws_bytes = bytes;
+    return ISVD_OK;
+}
+
+struct Exact {
+    double fro2 = 0, e_inc = 0, e_opt = 0, gap = 0, ratio = 0, ortho_u = 0, ortho_v = 0;
+};
+
+// ||A||_F^2 and E_inc^2 (one residual pass over A), E_opt^2 = ||A||^2 minus the
+// sum of the leading k squared Ritz values of a refresh computed into the
+// workspace (left there for a commit; exact when its block spans all columns),
+// and max |Q^T Q - I| of U and V.
+template <typename T>
+isvd_status exact_metrics_t(isvd_engine* e, Stream& s, hipStream_t st, Exact* out, RefreshPlan* plan) {
+    ST_TRY(refresh_compute<T>(e, s, false, st, plan));
+    DevHeader h{};
+    HIP_TRY(hipMemcpyAsync(&h, s.hdr, sizeof(h), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    const int64_t m = h.m, n = h.n;
+    const int k = h.k, ld = h.ld;
+    const int64_t nfro = cdiv(m, kFroRows);
+    const int64_t nres = cdiv(m, 64) * cdiv(n, 64);
+    const int64_t ngu = cdiv(m, kChunkRows), ngv = cdiv(n, kChunkRows);
+    const size_t need = sizeof(double) * (size_t)(nfro + nres + (ngu + ngv) * k * k + 2 * k * k + 8);
+    ST_TRY(ensure_mws(e, need));
+    double* fro_p = (double*)e->mws;
+    double* res_p = fro_p + nfro;
+    double* gu_p = res_p + nres;
+    double* gv_p = gu_p + ngu * k * k;
+    double* GU = gv_p + ngv * k * k;
+    double* GV = GU + k * k;
+    double* scal = GV + k * k;
+    const T* A = (const T*)s.A;
+    const T* U = (const T*)s.U[h.cur];
+    const T* V = (const T*)s.V[h.cur];
+    const int64_t lda = s.cfg.n_cap;
+    k_fro2_partial<T><<<(int)nfro, kThreads, 0, st>>>(A, lda, m, n, fro_p);
+    k_sum_parts<double><<<1, 1, 0, st>>>(fro_p, (int)nfro, 1, 1, scal + 0);
+    dim3 rg((unsigned)cdiv(m, 64), (unsigned)cdiv(n, 64));
+    k_resid2_partial<T><<<rg, kThreads, 0, st>>>(A, lda, U, V, ld, s.S, m, n, k, res_p);
+    k_sum_parts<double><<<1, 1, 0, st>>>(res_p, (int)nres, 1, 1, scal + 1);
+    k_gram_partial<T><<<(int)ngu, kThreads, 0, st>>>(U, ld, m, k, gu_p);
+    k_sum_parts<double><<<(int)cdiv(k * k, 256), 256, 0, st>>>(gu_p, (int)ngu, (int64_t)k * k, (int64_t)k * k, GU);
+    k_gram_partial<T><<<(int)ngv, kThreads, 0, st>>>(V, ld, n, k, gv_p);
+    k_sum_parts<double><<<(int)cdiv(k * k, 256), 256, 0, st>>>(gv_p, (int)ngv, (int64_t)k * k, (int64_t)k * k, GV);
+    const int nt = JacobiShape<kMaxBlock + 1>::NT;
+    int* sw = (int*)(scal + 6);
+    k_sym_norm2<<<1, nt, sym_norm2_lds(k), st>>>(GU, k, scal + 2, sw);
+    k_sym_norm2<<<1, nt, sym_norm2_lds(k), st>>>(GV, k, scal + 3, sw + 1);
+    HIP_TRY(hipGetLastError());
+    std::vector<double> hs(7), sr(plan->k);
+    HIP_TRY(hipMemcpyAsync(hs.data(), scal, sizeof(double) * 7, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(sr.data(), e->ws + plan->w.Sr, sizeof(double) * plan->k, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    out->fro2 = hs[0];
+    out->e_inc = std::sqrt(std::max(hs[1], 0.0));
+    double top = 0.0;
+    for (int q = 0; q < plan->k; ++q) top += sr[q] * sr[q];
+    out->e_opt = std::sqrt(std::max(hs[0] - top, 0.0));
+    out->gap = out->e_inc - out->e_opt;
+    out->ratio = out->e_opt > 1e-14 * std::sqrt(hs[0]) ? out->e_inc / out->e_opt : std::nan("");
+    int sweeps[2];
+    std::memcpy(sweeps, &hs[6], sizeof(sweeps));
+    if (sweeps[0] < 0 || sweeps[1] < 0) return fail(ISVD_E_CONVERGE, "orthogonality norm did not converge");
+    out->ortho_u = hs[2];
+    out->ortho_v = hs[3];
+    return ISVD_OK;
+}
+
+isvd_status exact_metrics(isvd_engine* e, Stream& s, hipStream_t st, Exact* out, RefreshPlan* plan) {
+    return s.esz == 8 ? exact_metrics_t<double>(e, s, st, out, plan) : exact_metrics_t<float>(e, s, st, out, plan);
+}
+
+// ------------------------------------------------------------------ policies
+isvd_status read_header(Stream& s, hipStream_t st, DevHeader* h) {
+    HIP_TRY(hipMemcpyAsync(h, s.hdr, sizeof(DevHeader), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return ISVD_OK;
+}
+
+bool policy_needs_header(const Stream& s) { return s.cfg.policy.kind == ISVD_POL_ADAPTIVE; }
+
+// Policy evaluation after the update at tick t (Algorithm 1; Section 3).
+// `h` is the device header after the update when the policy needs it.
+isvd_status after_update(isvd_engine* e, Stream& s, hipStream_t st, const DevHeader* h) {
     const isvd_policy& p = s.cfg.policy;
-    if (p.kind == ISVD_POL_PERIODIC && p.period > 0 && s.t % p.period == 0)
-        return do_refresh(e, s, false, true, st);
+    if (p.kind == ISVD_POL_PERIODIC) {
+        if (p.period > 0 && s.t % p.period == 0) return do_refresh(e, s, false, true, st);
+        return ISVD_OK;
+    }
+    if (p.kind == ISVD_POL_ERROR) {
+        if (p.check_every <= 0 || s.t % p.check_every != 0 || s.t - s.t_last < p.t_min) return ISVD_OK;
+        Exact ex;
+        RefreshPlan plan;
+        ST_TRY(exact_metrics(e, s, st, &ex, &plan));
+        s.last_ratio = ex.ratio;
+        if (ex.ratio > p.gamma) return do_refresh(e, s, false, true, st, &plan);
+        return ISVD_OK;
+    }
+    if (p.kind == ISVD_POL_ADAPTIVE) {
+        DevHeader hh;
+        if (!h) {
+            ST_TRY(read_header(s, st, &hh));
+            h = &hh;
+        }
+        // the device decides how many triplets an append keeps; follow it
+        if (h->k > s.k_target) s.grow_pending = false;
+        s.k_target = h->k;
+        const int kmax = p.k_max > 0 ? p.k_max : s.cfg.k;
+        const int kmin = std::max(1, p.k_min);
+        const double s2 = h->sigma2, N = h->N;
+        const bool low = N > 0.0 && s2 / N < p.tau - p.band;
+        const bool novel = (h->last_kind == kRow || h->last_kind == kCol) && h->novelty > p.eta;
+        if (low || novel) {
+            if (s.k_target < kmax) s.grow_pending = true;
+        } else if (h->k > kmin && N > 0.0 && (s2 - h->sigma_last * h->sigma_last) / N >= p.tau + p.band) {
+            k_shrink<<<1, 1, 0, st>>>(s.hdr, s.S);
+            HIP_TRY(hipGetLastError());
+            s.k_target = h->k - 1;
+            s.grow_pending = false;
+        }
+        if (p.period > 0 && s.t % p.period == 0) return do_refresh(e, s, false, true, st);
+        return ISVD_OK;
+    }
     return ISVD_OK;
 }
 
@@ -644,7 +863,16 @@ isvd_status stage_payload(Stream& s, const void* src, int64_t len, int32_t dtype
     return ISVD_OK;
 }
 
-int k_keep_for(const Stream& s) { return s.k_target; }
+// Triplets an append keeps: one more than the rank while adaptive growth is
+// pending (the rank grows only if the append brings a new direction).
+int k_keep_for(const Stream& s, int kind) {
+    const isvd_policy& p = s.cfg.policy;
+    if (p.kind == ISVD_POL_ADAPTIVE && s.grow_pending && kind != kEntry) {
+        const int kmax = p.k_max > 0 ? p.k_max : s.cfg.k;
+        if (s.k_target < kmax) return s.k_target + 1;
+    }
+    return s.k_target;
+}
 
 isvd_status single_update(isvd_engine* e, Stream& s, int kind, const void* payload, int64_t i, int64_t j,
                           double delta, hipStream_t st) {
@@ -652,7 +880,7 @@ isvd_status single_update(isvd_engine* e, Stream& s, int kind, const void* paylo
     Group& g = groups[0];
     g.fp64 = s.esz == 8;
     g.kc = s.kc;
-    Req r = make_req(s, kind, payload, i, j, delta, k_keep_for(s));
+    Req r = make_req(s, kind, payload, i, j, delta, k_keep_for(s, kind));
     g.all.push_back(r);
     if (kind == kCol) g.proj.push_back(r);
     HIP_TRY(hipEventRecord(s.ev_u0, st));
@@ -662,7 +890,7 @@ isvd_status single_update(isvd_engine* e, Stream& s, int kind, const void* paylo
     if (kind == kRow) s.m += 1;
     if (kind == kCol) s.n += 1;
     s.t += 1;
-    return after_update(e, s, st);
+    return after_update(e, s, st, nullptr);
 }
 
 void free_stream(isvd_engine* e, Stream* s) {
@@ -689,8 +917,10 @@ isvd_status validate_cfg(const isvd_config* c) {
         return fail(ISVD_E_INVAL, "k = %d outside [1, min(m0, n0, 96)]", c->k);
     if (c->policy.kind < ISVD_POL_NONE || c->policy.kind > ISVD_POL_ADAPTIVE)
         return fail(ISVD_E_INVAL, "bad policy kind %d", c->policy.kind);
-    if (c->policy.kind != ISVD_POL_NONE && c->policy.kind != ISVD_POL_PERIODIC)
+    if (c->policy.kind == ISVD_POL_ANGLE)
         return fail(ISVD_E_INVAL, "policy kind %d is not available in this build", c->policy.kind);
+    if (c->policy.kind == ISVD_POL_ADAPTIVE && (c->policy.k_max > 0 && c->policy.k_max < c->k))
+        return fail(ISVD_E_INVAL, "adaptive rank: k_max %d below k %d", c->policy.k_max, c->k);
     return ISVD_OK;
 }
 
@@ -742,6 +972,8 @@ isvd_status isvd_engine_destroy(isvd_engine* e) {
         if (s.ev) (void)hipEventDestroy(s.ev);
     }
     if (e->ws) (void)hipFree(e->ws);
+    if (e->mws) (void)hipFree(e->mws);
+    if (e->hdrs_host) (void)hipHostFree(e->hdrs_host);
     for (hipEvent_t ev : e->ev_pool) (void)hipEventDestroy(ev);
     for (hipStream_t sst : e->side) (void)hipStreamDestroy(sst);
     for (hipEvent_t ev : e->join) (void)hipEventDestroy(ev);
@@ -813,6 +1045,7 @@ static isvd_status install_factors(Stream& s, const GivenFactors& f, hipStream_t
     HIP_TRY(hipMemcpyAsync(s.Uref, bu.data(), bu.size(), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(s.S, f.S, sizeof(double) * k, hipMemcpyHostToDevice, st));
     k_set_header<<<1, 1, 0, st>>>(s.hdr, k, ld, 1, 0);
+    k_sigma_trackers<<<1, 1, 0, st>>>(s.hdr, s.S, k);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(st));
     return ISVD_OK;
@@ -908,10 +1141,10 @@ static isvd_status init_common(isvd_engine* e, const isvd_config* cfg, const voi
         k_copy2d<float, float><<<blocks, 256, 0, st>>>((const float*)src, lda, (float*)s->A, ldA, m0, n0);
     if (hipGetLastError() != hipSuccess) return bail(fail(ISVD_E_DEVICE, "A0 copy launch"));
     // N_0 = ||A_0||_F^2 (sum of per-chunk partials, FP64)
-    const size_t fro_bytes = sizeof(double) * (size_t)cdiv(m0, kChunkRows);
+    const size_t fro_bytes = sizeof(double) * (size_t)cdiv(m0, kFroRows);
     isvd_status rc = ensure_ws(e, std::max(fro_bytes, (size_t)4096));
     if (rc != ISVD_OK) return bail(rc);
-    const int nchunk = (int)cdiv(m0, kChunkRows);
+    const int nchunk = (int)cdiv(m0, kFroRows);
     if (s->esz == 8)
         k_fro2_partial<double><<<nchunk, kThreads, 0, st>>>((const double*)s->A, ldA, m0, n0, (double*)e->ws);
     else
@@ -1036,7 +1269,17 @@ isvd_status isvd_metrics(isvd_engine* e, isvd_id id, int32_t compute_exact, void
     float ms = 0.f;
     if (s->have_update_time && hipEventElapsedTime(&ms, s->ev_u0, s->ev_u1) == hipSuccess) m.update_time_us = 1e3 * ms;
     if (s->have_refresh_time && hipEventElapsedTime(&ms, s->ev_r0, s->ev_r1) == hipSuccess) m.opt_time_us = 1e3 * ms;
-    (void)compute_exact;
+    if (compute_exact) {
+        Exact ex;
+        RefreshPlan plan;
+        ST_TRY(exact_metrics(e, *s, st, &ex, &plan));
+        m.frob_error = ex.e_inc;
+        m.frob_opt = ex.e_opt;
+        m.frob_gap = ex.gap;
+        m.frob_ratio = ex.ratio;
+        m.ortho_U = ex.ortho_u;
+        m.ortho_V = ex.ortho_v;
+    }
     *out = m;
     return ISVD_OK;
 }
@@ -1150,7 +1393,7 @@ isvd_status isvd_tick(isvd_engine* e, int32_t count, const isvd_request* reqs, v
         }
         Group& g = groups[gi[key]];
         const isvd_request& r = reqs[q];
-        Req rq = make_req(s, r.kind, r.payload, r.i, r.j, r.delta, k_keep_for(s));
+        Req rq = make_req(s, r.kind, r.payload, r.i, r.j, r.delta, k_keep_for(s, r.kind));
         g.all.push_back(rq);
         if (r.kind == ISVD_COL) g.proj.push_back(rq);
     }
@@ -1161,7 +1404,24 @@ isvd_status isvd_tick(isvd_engine* e, int32_t count, const isvd_request* reqs, v
         if (reqs[q].kind == ISVD_COL) s.n += 1;
         s.t += 1;
     }
-    for (int q = 0; q < count; ++q) ST_TRY(after_update(e, *ss[q], st));
+    // trackers of the streams whose policy reads them: one copy-back
+    int nh = 0;
+    for (int q = 0; q < count; ++q) nh += policy_needs_header(*ss[q]) ? 1 : 0;
+    if (nh > 0) {
+        if (e->hdr_cap < count) {
+            if (e->hdrs_host) HIP_TRY(hipHostFree(e->hdrs_host));
+            e->hdrs_host = nullptr;
+            e->hdr_cap = 0;
+            HIP_TRY(hipHostMalloc((void**)&e->hdrs_host, sizeof(DevHeader) * count, hipHostMallocDefault));
+            e->hdr_cap = count;
+        }
+        for (int q = 0; q < count; ++q)
+            if (policy_needs_header(*ss[q]))
+                HIP_TRY(hipMemcpyAsync(e->hdrs_host + q, ss[q]->hdr, sizeof(DevHeader), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+    }
+    for (int q = 0; q < count; ++q)
+        ST_TRY(after_update(e, *ss[q], st, policy_needs_header(*ss[q]) ? e->hdrs_host + q : nullptr));
     return ISVD_OK;
 }
 

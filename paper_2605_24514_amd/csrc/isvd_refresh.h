@@ -169,8 +169,13 @@ __global__ void __launch_bounds__(kThreads) k_gram_partial(const T* __restrict__
 
 // One block: Cholesky G = R^T R (R upper), R^{-1}; writes R (FP64, b x b)
 // and R^{-1} in the storage type (b x b, row-major) for the rotation kernel.
-// A non-positive pivot is replaced by a tiny multiple of the largest diagonal
-// (the second CholQR pass repairs the resulting loss of orthogonality).
+// Rank-deficient G (a block whose columns are linearly dependent, e.g. A of
+// rank below the block size): a column whose Schur-complement pivot is at
+// most 4 b eps64 times its own squared norm -- below what the FP64 Gram
+// resolves -- lies in the span of the columns before it and is dropped: its
+// row of R and its row and column of R^{-1} are zero, so the orthonormalised
+// block has a zero column there and Y = Q R still holds.  `flag` bit 0 is set
+// when a column was dropped.
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_chol_inv(const double* __restrict__ G, int b,
                                                        double* __restrict__ Rout, T* __restrict__ RinvT,
@@ -178,29 +183,31 @@ __global__ void __launch_bounds__(kThreads) k_chol_inv(const double* __restrict_
     extern __shared__ double sh[];
     double* R = sh;                 // b x b row-major, becomes upper R
     double* Ri = sh + b * b;        // b x b inverse
-    __shared__ double s_dmax;
+    __shared__ int s_drop[kMaxBlock];
     for (int e = threadIdx.x; e < b * b; e += kThreads) { R[e] = G[e]; Ri[e] = 0.0; }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        double dm = 0.0;
-        for (int i = 0; i < b; ++i) dm = fmax(dm, R[i * b + i]);
-        s_dmax = dm;
-    }
-    __syncthreads();
+    const double tol = 4.0 * b * 2.220446049250313e-16;
     for (int j = 0; j < b; ++j) {
         // R[j][j] = sqrt(G[j][j] - sum_{i<j} R[i][j]^2), row j right of diagonal
         if (threadIdx.x == 0) {
+            const double gjj = G[j * b + j];
             double d = R[j * b + j];
             for (int i = 0; i < j; ++i) d -= R[i * b + j] * R[i * b + j];
-            double floor_ = 1e-30 * (s_dmax > 0.0 ? s_dmax : 1.0);
-            if (!(d > floor_)) { d = floor_; atomicOr(flag, 1); }
-            R[j * b + j] = sqrt(d);
+            const int drop = (d > tol * gjj && gjj > 1e-300) ? 0 : 1;
+            s_drop[j] = drop;
+            R[j * b + j] = drop ? 0.0 : sqrt(d);
+            if (drop) atomicOr(flag, 1);
         }
         __syncthreads();
+        const bool drop = s_drop[j] != 0;
         for (int c = j + 1 + threadIdx.x; c < b; c += kThreads) {
-            double s = R[j * b + c];
-            for (int i = 0; i < j; ++i) s -= R[i * b + j] * R[i * b + c];
-            R[j * b + c] = s / R[j * b + j];
+            if (drop) {
+                R[j * b + c] = 0.0;
+            } else {
+                double s = R[j * b + c];
+                for (int i = 0; i < j; ++i) s -= R[i * b + j] * R[i * b + c];
+                R[j * b + c] = s / R[j * b + j];
+            }
         }
         __syncthreads();
     }
@@ -210,9 +217,12 @@ __global__ void __launch_bounds__(kThreads) k_chol_inv(const double* __restrict_
         if (i > c) R[e] = 0.0;
     }
     __syncthreads();
-    // columns of R^{-1} by back substitution, one column per thread
+    // columns of R^{-1} by back substitution, one column per thread; dropped
+    // rows and columns stay zero
     for (int c = threadIdx.x; c < b; c += kThreads) {
+        if (s_drop[c]) continue;
         for (int i = c; i >= 0; --i) {
+            if (s_drop[i]) continue;
             double s = (i == c) ? 1.0 : 0.0;
             for (int l = i + 1; l <= c; ++l) s -= R[i * b + l] * Ri[l * b + c];
             Ri[i * b + c] = s / R[i * b + i];
@@ -330,13 +340,15 @@ __global__ void k_copy2d(const Tin* __restrict__ in, int64_t ldi, Tout* __restri
     out[r * ldo + c] = (Tout)in[r * ldi + c];
 }
 
-// ||A||_F^2 partial sums per row chunk (FP64)
+constexpr int kFroRows = 16;    // rows per block of the norm / residual reductions
+
+// ||A||_F^2 partial sums per block of kFroRows rows (FP64)
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_fro2_partial(const T* __restrict__ A, int64_t lda, int64_t m,
                                                            int64_t n, double* __restrict__ part) {
     __shared__ double sred[kThreads];
-    const int64_t ra = (int64_t)blockIdx.x * kChunkRows;
-    const int64_t rb = min(m, ra + kChunkRows);
+    const int64_t ra = (int64_t)blockIdx.x * kFroRows;
+    const int64_t rb = min(m, ra + kFroRows);
     double s = 0.0;
     for (int64_t r = ra; r < rb; ++r)
         for (int64_t c = threadIdx.x; c < n; c += kThreads) {
@@ -350,6 +362,94 @@ __global__ void __launch_bounds__(kThreads) k_fro2_partial(const T* __restrict__
         __syncthreads();
     }
     if (threadIdx.x == 0) part[blockIdx.x] = sred[0];
+}
+
+// E_inc^2 = ||A - U diag(S) V^T||_F^2 partial sums (eq. frob-errors), formed
+// from the residual itself: grid (ceil(m/64), ceil(n/64)); a block forms its
+// 64 x 64 tile of U diag(S) V^T (k-loop in LDS chunks of 16), subtracts it
+// from A and sums the squares in FP64.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_resid2_partial(const T* __restrict__ A, int64_t lda,
+                                                             const T* __restrict__ U, const T* __restrict__ V,
+                                                             int ld, const double* __restrict__ S,
+                                                             int64_t m, int64_t n, int k,
+                                                             double* __restrict__ part) {
+    __shared__ T sU[64][17];
+    __shared__ T sV[64][17];
+    __shared__ double sred[kThreads];
+    const int64_t r0 = (int64_t)blockIdx.x * 64, c0 = (int64_t)blockIdx.y * 64;
+    const int tr = (threadIdx.x / 16) * 4, tc = (threadIdx.x % 16) * 4;
+    T acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = (T)0;
+    for (int l0 = 0; l0 < k; l0 += 16) {
+        for (int e = threadIdx.x; e < 64 * 16; e += kThreads) {
+            const int rr = e / 16, ll = e % 16;
+            const int64_t r = r0 + rr, c = c0 + rr;
+            const int l = l0 + ll;
+            sU[rr][ll] = (r < m && l < k) ? (T)((double)U[r * ld + l] * S[l]) : (T)0;
+            sV[rr][ll] = (c < n && l < k) ? V[c * ld + l] : (T)0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ll = 0; ll < 16; ++ll)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] += sU[tr + i][ll] * sV[tc + j][ll];
+        __syncthreads();
+    }
+    double s2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t r = r0 + tr + i, c = c0 + tc + j;
+            if (r < m && c < n) {
+                const double d = (double)A[r * lda + c] - (double)acc[i][j];
+                s2 += d * d;
+            }
+        }
+    sred[threadIdx.x] = s2;
+    __syncthreads();
+    for (int o = kThreads / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) sred[threadIdx.x] += sred[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = sred[0];
+}
+
+// ||G - I||_2 for a symmetric k x k G (an orthogonality residual Q^T Q - I):
+// one-sided Jacobi on E = G - I; the largest column norm of the result is the
+// largest |eigenvalue| of E.
+__global__ void __launch_bounds__(JacobiShape<kMaxBlock + 1>::NT) k_sym_norm2(const double* __restrict__ G, int k,
+                                                                            double* __restrict__ out,
+                                                                            int* __restrict__ sweeps_out) {
+    extern __shared__ double smem[];
+    const int ldw = JacobiShape<kMaxBlock + 1>::LDW;
+    // k + 1 columns: for odd k the idle pair of each round reads column k
+    double* W = smem;
+    double* red = W + (size_t)(k + 1) * ldw;
+    for (int e = threadIdx.x; e < (k + 1) * ldw; e += blockDim.x) {
+        const int col = e / ldw, row = e % ldw;
+        W[e] = (row < k && col < k) ? G[row * k + col] - (row == col ? 1.0 : 0.0) : 0.0;
+    }
+    __syncthreads();
+    const int sweeps = jacobi_block<kMaxBlock + 1, false>(W, nullptr, k, ldw, 60);
+    for (int c = threadIdx.x; c < k; c += blockDim.x) {
+        double s = 0.0;
+        for (int e = 0; e < k; ++e) s += W[(size_t)c * ldw + e] * W[(size_t)c * ldw + e];
+        red[c] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double mx = 0.0;
+        for (int c = 0; c < k; ++c) mx = fmax(mx, red[c]);
+        *out = sqrt(mx);
+        *sweeps_out = sweeps;
+    }
 }
 
 }  // namespace isvd

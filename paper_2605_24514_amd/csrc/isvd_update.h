@@ -520,6 +520,11 @@ __global__ void __launch_bounds__(CoreShape<KC>::J::NT) k_core(const Req* __rest
         if (kind == kCol) hdr->n += 1;
         hdr->N += dN;
         hdr->sweeps = sweeps;
+        hdr->last_kind = kind;
+        double s2 = 0.0;
+        for (int j = 0; j < kout; ++j) s2 += sig[j] * sig[j];
+        hdr->sigma2 = s2;
+        hdr->sigma_last = kout > 0 ? sig[kout - 1] : 0.0;
         if (kind != kEntry) {
             hdr->rho = rho;
             hdr->xnorm = s_sc[1];

@@ -158,3 +158,31 @@ def test_host_side_errors_leave_state_unchanged(isvd):
             eng.append_row(sid, fs.row(62, 20))
         assert e.value.status == -10
         assert eng.metrics(sid)["m"] == 62
+
+
+@pytest.mark.parametrize("precision,bar", [("fp64", 1e-12), ("fp32", 2e-6)])
+def test_rank_deficient_input(isvd, precision, bar):
+    """A_0 of rank 3 (40 x 30): the refresh's block is rank-deficient.  With
+    k = 3 the GPU matches the oracle; with k = 5 it keeps the numerical rank
+    (3) and an append outside the row space brings the rank to 4."""
+    rng = np.random.default_rng(7)
+    A0 = rng.standard_normal((40, 3)) @ rng.standard_normal((3, 30))
+    with isvd.Engine() as eng:
+        sid = eng.init(A0, 3, precision=precision, m_cap=50, n_cap=30, oversample=64)
+        o = OracleEngine(A0, 3)
+        c = compare(eng.factors(sid), _oracle_state(o))
+        assert c["recon"] <= bar and c["sigma"] <= bar, c
+        sid2 = eng.init(A0, 5, precision=precision, m_cap=50, n_cap=30, oversample=64)
+        met = eng.metrics(sid2, exact=True)
+        assert met["k"] == 3, met["k"]
+        assert np.all(np.isfinite([met["frob_error"], met["ortho_U"], met["ortho_V"]]))
+        assert met["frob_error"] <= 10 * bar * np.linalg.norm(A0)
+        U, S, V = eng.factors(sid2)
+        x = rng.standard_normal(30)
+        x -= V @ (V.T @ x)
+        eng.append_row(sid2, 50.0 * x)
+        U, S, V = eng.factors(sid2)
+        assert len(S) == 4
+        A1 = np.vstack([A0, 50.0 * x[None, :]])
+        assert np.linalg.norm(A1 - (U * S) @ V.T) <= 10 * bar * np.linalg.norm(A1)
+        assert np.abs(U.T @ U - np.eye(4)).max() <= 10 * bar
