@@ -133,6 +133,11 @@ typedef struct {
     double ortho_U, ortho_V;       /* ||Q^T Q - I||_2 (NaN unless compute_exact) */
     double update_time_us;  /* wall-clock of the last immediate-mode update (host-timed) */
     double opt_time_us;     /* wall-clock of the last refresh (host-timed) */
+    double angle_ref;       /* theta_ref, radians: largest principal angle between U_ref
+                               (stored at the last refresh) and U_t on U_ref's rows, on the
+                               angle scope (Section 2.4.2); tracked every update for
+                               ISVD_POL_ANGLE streams, formed directly with compute_exact,
+                               else NaN */
 } isvd_metrics_t;
 
 /* One request of a batched tick. */

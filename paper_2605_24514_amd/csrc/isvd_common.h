@@ -37,7 +37,11 @@ struct DevHeader {
     int32_t sweeps;       // Jacobi sweeps of the last core (-1: sweep cap reached)
     int32_t new_dir;      // last append had rho > tol
     int32_t last_kind;    // kind of the last applied update
+    int32_t ref_k;        // rank of U_ref (stored at the last refresh that kept a reference)
+    int32_t ref_ld;       // its leading dimension
     int32_t pad;
+    int64_t ref_m;        // its rows
+    double angle_ref;     // theta_ref (angle-threshold streams), radians
 };
 
 // Written by the core kernel of a request, read by its rotation kernel.

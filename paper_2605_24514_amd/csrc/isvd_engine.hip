@@ -26,6 +26,7 @@
 #include "isvd_common.h"
 #include "isvd_update.h"
 #include "isvd_refresh.h"
+#include "isvd_track.h"
 
 using namespace isvd;
 
@@ -70,7 +71,7 @@ int bucket_for(int kmax) {
 
 // ------------------------------------------------------------------ streams
 struct Layout {
-    size_t hdr, rs, S, p, p2, counters, partials, QU, QV, stage, U0, U1, V0, V1, Uref, A, total;
+    size_t hdr, rs, S, p, p2, counters, partials, QU, QV, stage, U0, U1, V0, V1, Uref, TM, TH, TP, A, total;
 };
 
 struct Stream {
@@ -88,12 +89,14 @@ struct Stream {
     double *S = nullptr, *p = nullptr, *p2 = nullptr, *partials = nullptr;
     unsigned* counters = nullptr;
     void *QU = nullptr, *QV = nullptr, *stage = nullptr, *A = nullptr, *Uref = nullptr;
+    double *TM = nullptr, *TH = nullptr, *TP = nullptr;   // angle trackers M, H and column-pass sums
     void* U[2] = {nullptr, nullptr};
     void* V[2] = {nullptr, nullptr};
     hipEvent_t ev_u0 = nullptr, ev_u1 = nullptr, ev_r0 = nullptr, ev_r1 = nullptr;
     bool have_update_time = false, have_refresh_time = false;
     bool live = false;
     bool grow_pending = false;   // adaptive rank: the next append keeps one more triplet
+    bool angle = false;          // angle-threshold policy: trackers follow every update
     double last_ratio = 0.0;     // error policy: frob_ratio at its last check
 };
 
@@ -123,6 +126,10 @@ Layout make_layout(const isvd_config& c, int esz, int kc, int64_t* ntiles_max) {
     L.V0 = take((size_t)esz * c.n_cap * kc);
     L.V1 = take((size_t)esz * c.n_cap * kc);
     L.Uref = take((size_t)esz * c.m_cap * kc);
+    const bool angle = c.policy.kind == ISVD_POL_ANGLE;
+    L.TM = take(angle ? sizeof(double) * kc * kc : 0);
+    L.TH = take(angle ? sizeof(double) * kc * kc : 0);
+    L.TP = take(angle ? sizeof(double) * (size_t)cdiv(c.m_cap, kTrackRows) * (2 * kc + 1) : 0);
     L.A = take((size_t)esz * c.m_cap * c.n_cap);
     L.total = off;
     return L;
@@ -298,6 +305,10 @@ isvd_status set_lds_limits() {
     ST_TRY(allow_lds(k_svd_small<float>, svd_lds));
     ST_TRY(allow_lds(k_svd_small<double>, svd_lds));
     ST_TRY(allow_lds(k_sym_norm2, sym_norm2_lds(kMaxBlock)));
+    ST_TRY(allow_lds(k_track<float>, sizeof(double) * 2 * kMaxCore * kMaxBlock));
+    ST_TRY(allow_lds(k_track<double>, sizeof(double) * 2 * kMaxCore * kMaxBlock));
+    ST_TRY(allow_lds(k_theta_tracks, sizeof(double) * theta_lds_doubles()));
+    ST_TRY(allow_lds(k_theta_direct, sizeof(double) * theta_lds_doubles()));
     ST_TRY(allow_lds(k_chol_inv<float>, sizeof(double) * 2 * kMaxBlock * kMaxBlock));
     ST_TRY(allow_lds(k_chol_inv<double>, sizeof(double) * 2 * kMaxBlock * kMaxBlock));
     return ISVD_OK;
@@ -442,6 +453,83 @@ isvd_status run_groups(isvd_engine* e, std::vector<Group>& groups, hipStream_t s
     }
     HIP_TRY(hipEventRecord(slot->ev, st));
     slot->used = true;
+    return ISVD_OK;
+}
+
+// Tracker work of the angle-policy streams of one launch sequence.
+Track make_track(const Stream& s, int kind, const void* payload) {
+    Track t{};
+    t.hdr = s.hdr;
+    t.rs = s.rs;
+    t.kind = kind;
+    t.scope = s.cfg.policy.angle_scope;
+    t.tiles = kind == kCol ? (int)std::max<int64_t>(1, cdiv(s.m, kTrackRows)) : 0;
+    t.kc = s.kc;
+    t.Uref = s.Uref;
+    t.U[0] = s.U[0];
+    t.U[1] = s.U[1];
+    t.QU = s.QU;
+    t.p = s.p;
+    t.S = s.S;
+    t.payload = payload;
+    t.M = s.TM;
+    t.H = s.TH;
+    t.part = s.TP;
+    return t;
+}
+
+template <typename T>
+isvd_status launch_tracks(const char* dev, size_t off_all, size_t off_col, size_t off_pre, int nall, int ncol,
+                          int col_blocks, hipStream_t st) {
+    const Track* all = reinterpret_cast<const Track*>(dev + off_all);
+    if (ncol > 0)
+        k_track_col<T><<<col_blocks, kThreads, 0, st>>>(reinterpret_cast<const Track*>(dev + off_col),
+                                                       reinterpret_cast<const int*>(dev + off_pre), ncol);
+    k_track<T><<<nall, kThreads, sizeof(double) * 2 * kMaxCore * kMaxBlock, st>>>(all);
+    k_theta_tracks<<<nall, kThreads, sizeof(double) * theta_lds_doubles(), st>>>(all);
+    HIP_TRY(hipGetLastError());
+    return ISVD_OK;
+}
+
+// Runs after the update kernels on `st`: M, H through each update's rotation
+// and theta_ref into the headers.  tracks[q] pairs with fp64[q].
+isvd_status run_tracks(isvd_engine* e, const std::vector<Track>& tracks, const std::vector<char>& fp64,
+                       hipStream_t st) {
+    if (tracks.empty()) return ISVD_OK;
+    for (int pass = 0; pass < 2; ++pass) {
+        std::vector<Track> all, col;
+        for (size_t q = 0; q < tracks.size(); ++q)
+            if ((fp64[q] != 0) == (pass == 1)) {
+                all.push_back(tracks[q]);
+                if (tracks[q].kind == kCol) col.push_back(tracks[q]);
+            }
+        if (all.empty()) continue;
+        std::vector<int> pre(col.size() + 1, 0);
+        for (size_t q = 0; q < col.size(); ++q) pre[q + 1] = pre[q] + col[q].tiles;
+        size_t off = 0;
+        auto take = [&](size_t b) {
+            size_t o = off;
+            off = align_up(off + b, 64);
+            return o;
+        };
+        const size_t o_all = take(sizeof(Track) * all.size());
+        const size_t o_col = take(sizeof(Track) * std::max<size_t>(1, col.size()));
+        const size_t o_pre = take(sizeof(int) * pre.size());
+        Slot* slot = nullptr;
+        ST_TRY(acquire_slot(e, off, &slot));
+        memcpy(slot->host + o_all, all.data(), sizeof(Track) * all.size());
+        if (!col.empty()) memcpy(slot->host + o_col, col.data(), sizeof(Track) * col.size());
+        memcpy(slot->host + o_pre, pre.data(), sizeof(int) * pre.size());
+        HIP_TRY(hipMemcpyAsync(slot->dev, slot->host, off, hipMemcpyHostToDevice, st));
+        if (pass == 1)
+            ST_TRY(launch_tracks<double>(slot->dev, o_all, o_col, o_pre, (int)all.size(), (int)col.size(),
+                                         pre.back(), st));
+        else
+            ST_TRY(launch_tracks<float>(slot->dev, o_all, o_col, o_pre, (int)all.size(), (int)col.size(),
+                                        pre.back(), st));
+        HIP_TRY(hipEventRecord(slot->ev, st));
+        slot->used = true;
+    }
     return ISVD_OK;
 }
 
@@ -639,6 +727,56 @@ __global__ void k_shrink(DevHeader* hdr, const double* S) {
     }
 }
 
+isvd_status ensure_mws(isvd_engine* e, size_t bytes);
+
+// M = U_ref^T U[0:m_ref, :] and H = U[0:m_ref, :]^T U[0:m_ref, :] formed
+// directly (one pass over U_ref and U's reference rows), written with row
+// stride ldo into M / H (device, when not null); with theta != nullptr also
+// theta_ref into *theta (host; waits for the device).  Used by exact metrics
+// and after a refresh that keeps the old reference.
+template <typename T>
+isvd_status direct_trackers_t(isvd_engine* e, Stream& s, hipStream_t st, double* theta, double* M, double* H,
+                              int ldo) {
+    DevHeader h{};
+    HIP_TRY(hipMemcpyAsync(&h, s.hdr, sizeof(h), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    const int k = h.k, kref = h.ref_k;
+    const int64_t mref = std::min<int64_t>(h.ref_m, h.m);
+    const int64_t chunk = 1024;
+    const int64_t nch = std::max<int64_t>(1, cdiv(mref, chunk));
+    const size_t need = sizeof(double) * (size_t)(nch * (kref * k + k * k) + kref * k + k * k + 8);
+    ST_TRY(ensure_mws(e, need));
+    double* cp = (double*)e->mws;
+    double* hp = cp + nch * kref * k;
+    double* Md = hp + nch * k * k;
+    double* Hd = Md + kref * k;
+    const T* U = (const T*)s.U[h.cur];
+    k_cross_partial<T><<<(int)nch, kThreads, 0, st>>>((const T*)s.Uref, h.ref_ld, kref, U, h.ld, k, mref, chunk, cp);
+    k_cross_partial<T><<<(int)nch, kThreads, 0, st>>>(U, h.ld, k, U, h.ld, k, mref, chunk, hp);
+    k_sum_parts<double><<<(int)cdiv(kref * k, 256), 256, 0, st>>>(cp, (int)nch, (int64_t)kref * k,
+                                                                 (int64_t)kref * k, Md);
+    k_sum_parts<double><<<(int)cdiv(k * k, 256), 256, 0, st>>>(hp, (int)nch, (int64_t)k * k, (int64_t)k * k, Hd);
+    double* thd = Hd + k * k;
+    if (theta)
+        k_theta_direct<<<1, kThreads, sizeof(double) * theta_lds_doubles(), st>>>(
+            Md, Hd, k, kref, s.S, s.cfg.policy.kind == ISVD_POL_ANGLE ? s.cfg.policy.angle_scope : 0, thd);
+    if (M) {
+        k_copy2d<double, double><<<(int)cdiv(kref * k, 256), 256, 0, st>>>(Md, k, M, ldo, kref, k);
+        k_copy2d<double, double><<<(int)cdiv(k * k, 256), 256, 0, st>>>(Hd, k, H, ldo, k, k);
+    }
+    HIP_TRY(hipGetLastError());
+    if (theta) {
+        HIP_TRY(hipMemcpyAsync(theta, thd, sizeof(double), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+    }
+    return ISVD_OK;
+}
+
+isvd_status direct_trackers(isvd_engine* e, Stream& s, hipStream_t st, double* theta, double* M, double* H, int ldo) {
+    return s.esz == 8 ? direct_trackers_t<double>(e, s, st, theta, M, H, ldo)
+                      : direct_trackers_t<float>(e, s, st, theta, M, H, ldo);
+}
+
 // Install the computed TruncatedSVD as the stream's state.
 template <typename T>
 isvd_status refresh_commit(isvd_engine* e, Stream& s, const RefreshPlan& plan, bool store_ref, hipStream_t st) {
@@ -651,9 +789,13 @@ isvd_status refresh_commit(isvd_engine* e, Stream& s, const RefreshPlan& plan, b
     k_rotate_plain<T, 128><<<(int)cdiv(plan.n, 16), kThreads, 0, st>>>((T*)(ws + w.X), plan.b, (T*)s.V[nxt],
                                                                       plan.ldo, plan.n, plan.b, (T*)(ws + w.QV));
     k_commit_header<<<1, 1, 0, st>>>(s.hdr, s.S, plan.k, plan.ldo, plan.b);
-    if (store_ref)
+    if (store_ref) {
         HIP_TRY(hipMemcpyAsync(s.Uref, s.U[nxt], (size_t)sizeof(T) * plan.m * plan.ldo, hipMemcpyDeviceToDevice,
                                st));
+        k_track_reset<<<1, kThreads, 0, st>>>(s.hdr, s.TM, s.TH, s.kc);
+    } else if (s.TM) {
+        ST_TRY(direct_trackers(e, s, st, nullptr, s.TM, s.TH, s.kc));
+    }
     HIP_TRY(hipGetLastError());
     int sweeps = 0;
     HIP_TRY(hipMemcpyAsync(&sweeps, ws + w.sweeps, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -778,7 +920,9 @@ isvd_status read_header(Stream& s, hipStream_t st, DevHeader* h) {
     return ISVD_OK;
 }
 
-bool policy_needs_header(const Stream& s) { return s.cfg.policy.kind == ISVD_POL_ADAPTIVE; }
+bool policy_needs_header(const Stream& s) {
+    return s.cfg.policy.kind == ISVD_POL_ADAPTIVE || s.cfg.policy.kind == ISVD_POL_ANGLE;
+}
 
 // Policy evaluation after the update at tick t (Algorithm 1; Section 3).
 // `h` is the device header after the update when the policy needs it.
@@ -795,6 +939,16 @@ isvd_status after_update(isvd_engine* e, Stream& s, hipStream_t st, const DevHea
         ST_TRY(exact_metrics(e, s, st, &ex, &plan));
         s.last_ratio = ex.ratio;
         if (ex.ratio > p.gamma) return do_refresh(e, s, false, true, st, &plan);
+        return ISVD_OK;
+    }
+    if (p.kind == ISVD_POL_ANGLE) {
+        if (s.t - s.t_last < std::max<int64_t>(p.t_min, 1)) return ISVD_OK;
+        DevHeader hh;
+        if (!h) {
+            ST_TRY(read_header(s, st, &hh));
+            h = &hh;
+        }
+        if (h->angle_ref > p.theta_max) return do_refresh(e, s, false, true, st);
         return ISVD_OK;
     }
     if (p.kind == ISVD_POL_ADAPTIVE) {
@@ -885,6 +1039,7 @@ isvd_status single_update(isvd_engine* e, Stream& s, int kind, const void* paylo
     if (kind == kCol) g.proj.push_back(r);
     HIP_TRY(hipEventRecord(s.ev_u0, st));
     ST_TRY(run_groups(e, groups, st));
+    if (s.angle) ST_TRY(run_tracks(e, {make_track(s, kind, payload)}, {(char)(s.esz == 8)}, st));
     HIP_TRY(hipEventRecord(s.ev_u1, st));
     s.have_update_time = true;
     if (kind == kRow) s.m += 1;
@@ -917,8 +1072,8 @@ isvd_status validate_cfg(const isvd_config* c) {
         return fail(ISVD_E_INVAL, "k = %d outside [1, min(m0, n0, 96)]", c->k);
     if (c->policy.kind < ISVD_POL_NONE || c->policy.kind > ISVD_POL_ADAPTIVE)
         return fail(ISVD_E_INVAL, "bad policy kind %d", c->policy.kind);
-    if (c->policy.kind == ISVD_POL_ANGLE)
-        return fail(ISVD_E_INVAL, "policy kind %d is not available in this build", c->policy.kind);
+    if (c->policy.kind == ISVD_POL_ANGLE && c->policy.angle_scope < 0)
+        return fail(ISVD_E_INVAL, "negative angle scope");
     if (c->policy.kind == ISVD_POL_ADAPTIVE && (c->policy.k_max > 0 && c->policy.k_max < c->k))
         return fail(ISVD_E_INVAL, "adaptive rank: k_max %d below k %d", c->policy.k_max, c->k);
     return ISVD_OK;
@@ -1046,6 +1201,7 @@ static isvd_status install_factors(Stream& s, const GivenFactors& f, hipStream_t
     HIP_TRY(hipMemcpyAsync(s.S, f.S, sizeof(double) * k, hipMemcpyHostToDevice, st));
     k_set_header<<<1, 1, 0, st>>>(s.hdr, k, ld, 1, 0);
     k_sigma_trackers<<<1, 1, 0, st>>>(s.hdr, s.S, k);
+    k_track_reset<<<1, kThreads, 0, st>>>(s.hdr, s.TM, s.TH, s.kc);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(st));
     return ISVD_OK;
@@ -1066,6 +1222,7 @@ static isvd_status init_common(isvd_engine* e, const isvd_config* cfg, const voi
     s->esz = cfg->precision == ISVD_FP64 ? 8 : 4;
     s->kc = bucket_for(round4(std::max(cfg->k, cfg->policy.k_max)));
     s->k_target = cfg->k;
+    s->angle = cfg->policy.kind == ISVD_POL_ANGLE;
     s->m = cfg->m0;
     s->n = cfg->n0;
     s->L = make_layout(s->cfg, s->esz, s->kc, &s->ntiles_max);
@@ -1097,6 +1254,11 @@ static isvd_status init_common(isvd_engine* e, const isvd_config* cfg, const voi
     s->V[0] = b + s->L.V0;
     s->V[1] = b + s->L.V1;
     s->Uref = b + s->L.Uref;
+    if (cfg->policy.kind == ISVD_POL_ANGLE) {
+        s->TM = (double*)(b + s->L.TM);
+        s->TH = (double*)(b + s->L.TH);
+        s->TP = (double*)(b + s->L.TP);
+    }
     s->A = b + s->L.A;
     s->live = true;
     e->streams.push_back(s);
@@ -1264,6 +1426,7 @@ isvd_status isvd_metrics(isvd_engine* e, isvd_id id, int32_t compute_exact, void
     m.novelty = h.novelty;
     m.frob_error = m.frob_opt = m.frob_gap = m.frob_ratio = nan;
     m.ortho_U = m.ortho_V = nan;
+    m.angle_ref = s->angle ? h.angle_ref : nan;
     m.update_time_us = nan;
     m.opt_time_us = nan;
     float ms = 0.f;
@@ -1279,6 +1442,7 @@ isvd_status isvd_metrics(isvd_engine* e, isvd_id id, int32_t compute_exact, void
         m.frob_ratio = ex.ratio;
         m.ortho_U = ex.ortho_u;
         m.ortho_V = ex.ortho_v;
+        ST_TRY(direct_trackers(e, *s, st, &m.angle_ref, nullptr, nullptr, 0));
     }
     *out = m;
     return ISVD_OK;
@@ -1398,6 +1562,14 @@ isvd_status isvd_tick(isvd_engine* e, int32_t count, const isvd_request* reqs, v
         if (r.kind == ISVD_COL) g.proj.push_back(rq);
     }
     ST_TRY(run_groups(e, groups, st));
+    std::vector<Track> tracks;
+    std::vector<char> tfp;
+    for (int q = 0; q < count; ++q)
+        if (ss[q]->angle) {
+            tracks.push_back(make_track(*ss[q], reqs[q].kind, reqs[q].payload));
+            tfp.push_back(ss[q]->esz == 8);
+        }
+    ST_TRY(run_tracks(e, tracks, tfp, st));
     for (int q = 0; q < count; ++q) {
         Stream& s = *ss[q];
         if (reqs[q].kind == ISVD_ROW) s.m += 1;

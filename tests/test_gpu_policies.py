@@ -183,3 +183,58 @@ def test_adaptive_rank_in_batched_ticks(isvd):
         for q in range(3):
             c = compare(eng.factors(sids[q]), (os_[q].U, os_[q].s, os_[q].V))
             assert c["recon"] <= 1e-10, (q, c)
+
+
+@pytest.mark.parametrize("precision,bar", [("fp64", 1e-9), ("fp32", 2e-5)])
+def test_angle_trackers_match_direct_and_oracle(isvd, precision, bar):
+    """theta_ref tracked through every update (rows, columns, entries) against
+    the same angle formed directly on the GPU and the oracle's (Section 2.4.2),
+    with a threshold that never fires."""
+    fs = FactorStream(seed=6, stream=0, n0=40, K=5)
+    A0 = fs.initial(300)
+    evs = fs.materialize([ROW, COL, ENTRY, ROW] * 15, m0=300)
+    pol = isvd.Policy(kind=isvd.POL_ANGLE, theta_max=10.0, t_min=1)
+    o = OracleEngine(A0, 8, tol_rel=1e-10 if precision == "fp64" else 1e-5, cgs2=True)
+    with isvd.Engine() as eng:
+        sid = eng.init(A0, 8, precision=precision, m_cap=400, n_cap=80, oversample=64, policy=pol)
+        assert eng.metrics(sid)["angle_ref"] == 0.0
+        for ev in evs:
+            _apply_gpu(eng, sid, ev)
+            o.step(ev)
+            if ev.t % 5 != 0:
+                continue
+            tracked = eng.metrics(sid)["angle_ref"]
+            direct = eng.metrics(sid, exact=True)["angle_ref"]
+            ref = o.angle_ref(0)
+            print(precision, ev.t, tracked, direct, ref)
+            assert abs(tracked - ref) <= bar, (ev.t, tracked, ref)
+            assert abs(direct - ref) <= bar, (ev.t, direct, ref)
+        assert eng.metrics(sid)["n_refresh"] == 0
+
+
+def test_angle_policy_fires_at_the_oracles_ticks(isvd):
+    A0, events = _c0_events()
+    events = events[:400]
+    theta_max = 2e-4
+    o = OracleEngine(A0, 10, policy=OPolicy.angle(theta_max=theta_max), cgs2=True)
+    # the oracle's angles keep away from the threshold
+    for ev in events:
+        o.apply(ev)
+        if o.t - o.t_last >= 1:
+            assert abs(o.angle_ref(0) - theta_max) > 1e-9, ev.t
+        if o.decide(ev.kind):
+            o.refresh(store_reference=True)
+            o.refresh_ticks.append(o.t)
+    assert 3 <= len(o.refresh_ticks) <= 20, o.refresh_ticks
+    pol = isvd.Policy(kind=isvd.POL_ANGLE, theta_max=theta_max, t_min=1)
+    with isvd.Engine() as eng:
+        sid = eng.init(A0, 10, precision="fp64", m_cap=1000, n_cap=50, oversample=64, policy=pol)
+        seen = []
+        for ev in events:
+            _apply_gpu(eng, sid, ev)
+            met = eng.metrics(sid)
+            if met["t_last_refresh"] == ev.t and met["n_refresh"] > len(seen):
+                seen.append(ev.t)
+                assert met["angle_ref"] == 0.0
+        print("oracle", o.refresh_ticks, "gpu", seen)
+        assert seen == o.refresh_ticks
