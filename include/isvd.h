@@ -248,6 +248,26 @@ isvd_status isvd_profile(isvd_engine* eng, int32_t enable);
  * *count.  Waits for the recorded launches to finish. */
 isvd_status isvd_profile_read(isvd_engine* eng, isvd_launch_time* out, int32_t cap, int32_t* count);
 
+/* Block shapes of the FP32 matrix-core rotation: variant v runs
+ * {rows per block, 16-row tiles per wave step, prefetch of the next step} =
+ * 0: {256, 1, yes}, 1: {512, 1, yes} (default), 2: {1024, 1, yes},
+ * 3: {1024, 2, no}, 4: {2048, 2, no}. */
+#define ISVD_ROT_VARIANTS 5
+
+/* Tile autotuner.  For each rank bucket of the FP32 matrix-core rotation
+ * (8, 16, 32, 64), times every variant on a synthetic batch of 64 bases of
+ * 32768 x bucket (plus 1024 x bucket) -- about 1.1 GB of HBM for the widest
+ * bucket, allocated for the call and freed before it returns -- and keeps
+ * the fastest for later launches.  variant_out (4 entries, may be NULL)
+ * receives the choices, ms_out (4 x ISVD_ROT_VARIANTS entries, bucket major,
+ * may be NULL) the mean time of one launch per variant.  Waits for the
+ * device.  Errors: NOMEM, DEVICE. */
+isvd_status isvd_autotune(isvd_engine* eng, void* hip_stream, int32_t* variant_out, double* ms_out);
+
+/* Use variant (0 .. ISVD_ROT_VARIANTS-1) for the FP32 rotation of bucket kc
+ * (8, 16, 32, 64).  Errors: INVAL. */
+isvd_status isvd_set_rotation_variant(isvd_engine* eng, int32_t kc, int32_t variant);
+
 /* Message for the last error on this thread ("" if none). */
 const char* isvd_last_error(void);
 

@@ -13,11 +13,37 @@ constexpr int kProjTile = 256;     // basis rows per projection block
 // the row tile fit in LDS)
 __host__ __device__ constexpr int rot_rows(int kc) { return kc <= 64 ? 64 : 16; }
 constexpr int kMfmaRotRows = 512;
-__host__ __device__ constexpr int rot_rows_for(int kc, bool fp64) { return fp64 ? rot_rows(kc) : kMfmaRotRows; }
+// Block shapes of the FP32 matrix-core rotation (autotuned per rank bucket):
+// rows per block, 16-row tiles per wave step, next-step prefetch.
+struct RotVariant { int rows, rt, pf; };
+constexpr int kRotVariants = 5;
+constexpr RotVariant kRotVariant[kRotVariants] = {{256, 1, 1}, {512, 1, 1}, {1024, 1, 1}, {1024, 2, 0}, {2048, 2, 0}};
 constexpr int kMaxCore = 97;       // largest core order held in LDS (k <= 96)
 constexpr int kMaxBlock = 96;      // largest refresh block size b
 
 __host__ __device__ inline int round4(int k) { return (k + 3) & ~3; }
+
+// HBM layout of every basis (U, V, U_ref; leading dimension ld = a multiple
+// of 4 >= k): 16-row tiles of 16 ld elements each; inside a tile, panels of
+// 16 columns, and inside a panel the 4-column groups one after another, each
+// holding its 16 rows x 4 columns row by row.  Element (r, c) lives at
+//   (r / 16) 16 ld + (c / 16) 256 + ((c % 16) / 4) 64 + (r % 16) 4 + c % 4.
+// Four consecutive columns c0..c0+3 (c0 % 4 == 0) of a row are contiguous
+// (16 B in FP32), and one 4-column group of a 16-row tile is 64 contiguous
+// elements: a wave reads it with one dwordx4 per lane (lane = group-local
+// row + 16 x group), which is the matrix-core operand layout of the FP32
+// rotation.  A tile is contiguous, so tiles are copied as blocks; buffers
+// hold whole tiles (rows rounded up to 16).
+__host__ __device__ inline int64_t uvo(int64_t r, int c, int ld) {
+    return (r >> 4) * 16 * (int64_t)ld + (c >> 4) * 256 + ((c & 15) >> 2) * 64 + (r & 15) * 4 + (c & 3);
+}
+// (row, column) inside a tile of element e of that tile
+__host__ __device__ inline void uv_tile_rc(int e, int* r, int* c) {
+    const int rem = e & 255;
+    *r = (rem & 63) >> 2;
+    *c = (e >> 8) * 16 + (rem >> 6) * 4 + (rem & 3);
+}
+__host__ __device__ inline int64_t round16(int64_t m) { return (m + 15) & ~(int64_t)15; }
 
 // Device-resident state of one stream (single source of truth for rank and
 // buffer index, so that batched launches never need the host's view of k).

@@ -121,11 +121,12 @@ Layout make_layout(const isvd_config& c, int esz, int kc, int64_t* ntiles_max) {
     L.QU = take((size_t)esz * (kc + 1) * kc);
     L.QV = take((size_t)esz * (kc + 1) * kc);
     L.stage = take((size_t)esz * mx);
-    L.U0 = take((size_t)esz * c.m_cap * kc);
-    L.U1 = take((size_t)esz * c.m_cap * kc);
-    L.V0 = take((size_t)esz * c.n_cap * kc);
-    L.V1 = take((size_t)esz * c.n_cap * kc);
-    L.Uref = take((size_t)esz * c.m_cap * kc);
+    // bases hold whole 16-row tiles
+    L.U0 = take((size_t)esz * round16(c.m_cap) * kc);
+    L.U1 = take((size_t)esz * round16(c.m_cap) * kc);
+    L.V0 = take((size_t)esz * round16(c.n_cap) * kc);
+    L.V1 = take((size_t)esz * round16(c.n_cap) * kc);
+    L.Uref = take((size_t)esz * round16(c.m_cap) * kc);
     const bool angle = c.policy.kind == ISVD_POL_ANGLE;
     L.TM = take(angle ? sizeof(double) * kc * kc : 0);
     L.TH = take(angle ? sizeof(double) * kc * kc : 0);
@@ -148,6 +149,8 @@ struct Slot {
 struct Group {
     bool fp64;
     int kc;
+    int rows = 0;              // rotation rows per block
+    int var = 1;               // FP32 rotation block shape (kRotVariant index)
     std::vector<Req> all;      // core + rotation list
     std::vector<Req> proj;     // row / column appends
     std::vector<int> pre_proj; // block prefix of the projection list (size proj+1)
@@ -192,6 +195,10 @@ struct isvd_engine {
     // reads the trackers (one copy-back per tick)
     DevHeader* hdrs_host = nullptr;
     int hdr_cap = 0;
+    // block shape (kRotVariant index) of the FP32 matrix-core rotation per
+    // rank bucket (8, 16, 32, 64; the widest bucket uses the LDS-staged
+    // kernel), chosen by isvd_autotune
+    int rot_var_f32[4] = {1, 1, 1, 1};
 };
 
 namespace {
@@ -256,10 +263,21 @@ isvd_status launch_group_phase(const Group& g, const char* dev, int phase, hipSt
         size_t lds = sizeof(double) * core_lds_doubles<KC, sizeof(T) == 8>();
         k_core<T, KC><<<na, CoreShape<KC>::J::NT, lds, st>>>(all);
     } else if (phase == 3 && na > 0) {
-        if constexpr (sizeof(T) == 4)
-            k_rotate_mfma<KC><<<g.pre_rot[na], kThreads, 0, st>>>(all, pr, na);
-        else
-            k_rotate<T, KC><<<g.pre_rot[na], kThreads, 0, st>>>(all, pr, na);
+        const int nb = g.pre_rot[na];
+        if constexpr (sizeof(T) == 4 && KC <= 64) {
+            static_assert(kRotVariants == 5, "variant dispatch");
+            switch (g.var) {
+                case 0: k_rotate_mfma_t<KC, 256, 1, true><<<nb, kThreads, 0, st>>>(all, pr, na); break;
+                case 2: k_rotate_mfma_t<KC, 1024, 1, true><<<nb, kThreads, 0, st>>>(all, pr, na); break;
+                case 3: k_rotate_mfma_t<KC, 1024, 2, false><<<nb, kThreads, 0, st>>>(all, pr, na); break;
+                case 4: k_rotate_mfma_t<KC, 2048, 2, false><<<nb, kThreads, 0, st>>>(all, pr, na); break;
+                default: k_rotate_mfma_t<KC, 512, 1, true><<<nb, kThreads, 0, st>>>(all, pr, na); break;
+            }
+        } else if constexpr (sizeof(T) == 4) {
+            k_rotate_mfma<KC><<<nb, kThreads, 0, st>>>(all, pr, na);
+        } else {
+            k_rotate<T, KC><<<nb, kThreads, 0, st>>>(all, pr, na);
+        }
     }
     HIP_TRY(hipGetLastError());
     return ISVD_OK;
@@ -315,7 +333,19 @@ isvd_status set_lds_limits() {
 }
 
 // Build the request a single stream's update sends to the kernels.
-Req make_req(Stream& s, int kind, const void* payload, int64_t i, int64_t j, double delta, int k_keep) {
+int bucket_index(int kc) { return kc <= 8 ? 0 : kc <= 16 ? 1 : kc <= 32 ? 2 : kc <= 64 ? 3 : 4; }
+
+// rows per rotation block of a bucket
+int var_for(const isvd_engine* e, int kc, bool fp64) { return (fp64 || kc > 64) ? 1 : e->rot_var_f32[bucket_index(kc)]; }
+
+int rows_for(const isvd_engine* e, int kc, bool fp64) {
+    if (fp64) return rot_rows(kc);
+    if (kc > 64) return kMfmaRotRows;
+    return kRotVariant[var_for(e, kc, fp64)].rows;
+}
+
+Req make_req(const isvd_engine* e, Stream& s, int kind, const void* payload, int64_t i, int64_t j, double delta,
+             int k_keep) {
     Req r{};
     r.m = s.m;
     r.n = s.n;
@@ -329,7 +359,7 @@ Req make_req(Stream& s, int kind, const void* payload, int64_t i, int64_t j, dou
     // row appends project inside the core block; column appends use the
     // multi-block projection passes over U
     r.proj_tiles = kind == kCol ? (int)cdiv(s.m, kProjTile) : 0;
-    r.rot_tiles_u = (int)cdiv(s.m, rot_rows_for(s.kc, s.esz == 8));
+    r.rot_tiles_u = (int)cdiv(s.m, rows_for(e, s.kc, s.esz == 8));
     r.hdr = s.hdr;
     r.rs = s.rs;
     r.A = s.A;
@@ -348,7 +378,7 @@ Req make_req(Stream& s, int kind, const void* payload, int64_t i, int64_t j, dou
     return r;
 }
 
-int rot_tiles(const Req& r, int kc, bool fp64) { return r.rot_tiles_u + (int)cdiv(r.n, rot_rows_for(kc, fp64)); }
+int rot_tiles(const Req& r, int rows) { return r.rot_tiles_u + (int)cdiv(r.n, rows); }
 
 isvd_status next_event(isvd_engine* e, hipEvent_t* out) {
     if (e->ev_used == e->ev_pool.size()) {
@@ -372,7 +402,7 @@ isvd_status run_groups(isvd_engine* e, std::vector<Group>& groups, hipStream_t s
         g.pre_proj.assign(g.proj.size() + 1, 0);
         for (size_t q = 0; q < g.proj.size(); ++q) g.pre_proj[q + 1] = g.pre_proj[q] + g.proj[q].proj_tiles;
         g.pre_rot.assign(g.all.size() + 1, 0);
-        for (size_t q = 0; q < g.all.size(); ++q) g.pre_rot[q + 1] = g.pre_rot[q] + rot_tiles(g.all[q], g.kc, g.fp64);
+        for (size_t q = 0; q < g.all.size(); ++q) g.pre_rot[q + 1] = g.pre_rot[q] + rot_tiles(g.all[q], g.rows);
         g.off_all = take(sizeof(Req) * g.all.size());
         g.off_proj = take(sizeof(Req) * g.proj.size());
         g.off_pp = take(sizeof(int) * g.pre_proj.size());
@@ -583,6 +613,17 @@ isvd_status ensure_ws(isvd_engine* e, size_t bytes) {
     return ISVD_OK;
 }
 
+// deterministic values in [-1, 1) (autotuner inputs)
+__global__ void k_fill_hash(float* x, int64_t n, uint32_t seed) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t h = (uint32_t)e * 2654435761u ^ seed;
+        h ^= h >> 15;
+        h *= 2246822519u;
+        h ^= h >> 13;
+        x[e] = (float)((double)h * (2.0 / 4294967296.0) - 1.0);
+    }
+}
+
 __global__ void k_set_header(DevHeader* hdr, int k, int ld, int flip, int bump_t) {
     if (threadIdx.x == 0) {
         hdr->k = k;
@@ -784,13 +825,13 @@ isvd_status refresh_commit(isvd_engine* e, Stream& s, const RefreshPlan& plan, b
     const WsLayout& w = plan.w;
     const int nxt = plan.cur ^ 1;
     HIP_TRY(hipMemcpyAsync(s.S, ws + w.Sr, sizeof(double) * plan.k, hipMemcpyDeviceToDevice, st));
-    k_rotate_plain<T, 128><<<(int)cdiv(plan.m, 16), kThreads, 0, st>>>((T*)(ws + w.Y), plan.b, (T*)s.U[nxt],
+    k_rotate_plain<T, 128, true><<<(int)cdiv(plan.m, 16), kThreads, 0, st>>>((T*)(ws + w.Y), plan.b, (T*)s.U[nxt],
                                                                       plan.ldo, plan.m, plan.b, (T*)(ws + w.QU));
-    k_rotate_plain<T, 128><<<(int)cdiv(plan.n, 16), kThreads, 0, st>>>((T*)(ws + w.X), plan.b, (T*)s.V[nxt],
+    k_rotate_plain<T, 128, true><<<(int)cdiv(plan.n, 16), kThreads, 0, st>>>((T*)(ws + w.X), plan.b, (T*)s.V[nxt],
                                                                       plan.ldo, plan.n, plan.b, (T*)(ws + w.QV));
     k_commit_header<<<1, 1, 0, st>>>(s.hdr, s.S, plan.k, plan.ldo, plan.b);
     if (store_ref) {
-        HIP_TRY(hipMemcpyAsync(s.Uref, s.U[nxt], (size_t)sizeof(T) * plan.m * plan.ldo, hipMemcpyDeviceToDevice,
+        HIP_TRY(hipMemcpyAsync(s.Uref, s.U[nxt], (size_t)sizeof(T) * round16(plan.m) * plan.ldo, hipMemcpyDeviceToDevice,
                                st));
         k_track_reset<<<1, kThreads, 0, st>>>(s.hdr, s.TM, s.TH, s.kc);
     } else if (s.TM) {
@@ -881,9 +922,9 @@ isvd_status exact_metrics_t(isvd_engine* e, Stream& s, hipStream_t st, Exact* ou
     dim3 rg((unsigned)cdiv(m, 64), (unsigned)cdiv(n, 64));
     k_resid2_partial<T><<<rg, kThreads, 0, st>>>(A, lda, U, V, ld, s.S, m, n, k, res_p);
     k_sum_parts<double><<<1, 1, 0, st>>>(res_p, (int)nres, 1, 1, scal + 1);
-    k_gram_partial<T><<<(int)ngu, kThreads, 0, st>>>(U, ld, m, k, gu_p);
+    k_gram_partial<T, true><<<(int)ngu, kThreads, 0, st>>>(U, ld, m, k, gu_p);
     k_sum_parts<double><<<(int)cdiv(k * k, 256), 256, 0, st>>>(gu_p, (int)ngu, (int64_t)k * k, (int64_t)k * k, GU);
-    k_gram_partial<T><<<(int)ngv, kThreads, 0, st>>>(V, ld, n, k, gv_p);
+    k_gram_partial<T, true><<<(int)ngv, kThreads, 0, st>>>(V, ld, n, k, gv_p);
     k_sum_parts<double><<<(int)cdiv(k * k, 256), 256, 0, st>>>(gv_p, (int)ngv, (int64_t)k * k, (int64_t)k * k, GV);
     const int nt = JacobiShape<kMaxBlock + 1>::NT;
     int* sw = (int*)(scal + 6);
@@ -1034,7 +1075,9 @@ isvd_status single_update(isvd_engine* e, Stream& s, int kind, const void* paylo
     Group& g = groups[0];
     g.fp64 = s.esz == 8;
     g.kc = s.kc;
-    Req r = make_req(s, kind, payload, i, j, delta, k_keep_for(s, kind));
+    g.rows = rows_for(e, g.kc, g.fp64);
+    g.var = var_for(e, g.kc, g.fp64);
+    Req r = make_req(e, s, kind, payload, i, j, delta, k_keep_for(s, kind));
     g.all.push_back(r);
     if (kind == kCol) g.proj.push_back(r);
     HIP_TRY(hipEventRecord(s.ev_u0, st));
@@ -1149,6 +1192,114 @@ isvd_status isvd_profile(isvd_engine* e, int32_t enable) {
     return ISVD_OK;
 }
 
+isvd_status isvd_set_rotation_variant(isvd_engine* e, int32_t kc, int32_t variant) {
+    if (!e) return fail(ISVD_E_INVAL, "null engine");
+    if (kc != 8 && kc != 16 && kc != 32 && kc != 64) return fail(ISVD_E_INVAL, "bucket %d is not tunable", kc);
+    if (variant < 0 || variant >= kRotVariants) return fail(ISVD_E_INVAL, "variant %d not supported", variant);
+    e->rot_var_f32[bucket_index(kc)] = variant;
+    return ISVD_OK;
+}
+
+isvd_status isvd_autotune(isvd_engine* e, void* hip_stream, int32_t* variant_out, double* ms_out) {
+    if (!e) return fail(ISVD_E_INVAL, "null engine");
+    ST_TRY(ensure_device(e));
+    hipStream_t st = (hipStream_t)hip_stream;
+    const int nreq = 64;
+    const int64_t m = 32768, n = 1024;
+    const int kcs[4] = {8, 16, 32, 64};
+    for (int bi = 0; bi < 4; ++bi) {
+        const int kc = kcs[bi];
+        // per request: U0, U1 (m x kc), V0, V1 (n x kc), QU, QV ((kc + 1) x kc), scratch
+        const size_t ub = align_up(sizeof(float) * m * kc, 256), vb = align_up(sizeof(float) * n * kc, 256);
+        const size_t qb = align_up(sizeof(float) * (kc + 1) * kc, 256), sb = align_up(sizeof(ReqScratch), 256);
+        const size_t per = 2 * ub + 2 * vb + 2 * qb + sb;
+        char* buf = nullptr;
+        if (hipMalloc((void**)&buf, per * nreq) != hipSuccess) return fail(ISVD_E_NOMEM, "autotune buffers");
+        auto cleanup = [&]() { (void)hipFree(buf); };
+        const int64_t nfl = (int64_t)(per * nreq / sizeof(float));
+        k_fill_hash<<<(int)std::min<int64_t>(cdiv(nfl, 256), 65535), 256, 0, st>>>((float*)buf, nfl, 0x9e37u + kc);
+        std::vector<ReqScratch> scr(nreq);
+        std::vector<Req> reqs(nreq);
+        for (int q = 0; q < nreq; ++q) {
+            char* b = buf + per * q;
+            ReqScratch& r = scr[q];
+            r.skip = 0;
+            r.k_in = r.ld_in = r.k_out = r.ld_out = kc;
+            r.in_idx = 0;
+            r.inv_rho = 0.0;
+            Req& rq = reqs[q];
+            rq = Req{};
+            rq.m = m;
+            rq.n = n;
+            rq.kind = kEntry;
+            rq.U[0] = b;
+            rq.U[1] = b + ub;
+            rq.V[0] = b + 2 * ub;
+            rq.V[1] = b + 2 * ub + vb;
+            rq.QU = b + 2 * ub + 2 * vb;
+            rq.QV = b + 2 * ub + 2 * vb + qb;
+            rq.rs = (ReqScratch*)(b + 2 * ub + 2 * vb + 2 * qb);
+        }
+        for (int q = 0; q < nreq; ++q)
+            if (hipMemcpyAsync(reqs[q].rs, &scr[q], sizeof(ReqScratch), hipMemcpyHostToDevice, st) != hipSuccess) {
+                cleanup();
+                return fail(ISVD_E_DEVICE, "autotune upload");
+            }
+        double best = 1e30;
+        int best_var = e->rot_var_f32[bi];
+        for (int ci = 0; ci < kRotVariants; ++ci) {
+            Group g{};
+            g.fp64 = false;
+            g.kc = kc;
+            g.var = ci;
+            g.rows = kRotVariant[ci].rows;
+            for (Req rq : reqs) {
+                rq.rot_tiles_u = (int)cdiv(m, g.rows);
+                g.all.push_back(rq);
+            }
+            g.pre_proj.assign(1, 0);
+            g.pre_rot.assign(nreq + 1, 0);
+            for (int q = 0; q < nreq; ++q) g.pre_rot[q + 1] = g.pre_rot[q] + rot_tiles(g.all[q], g.rows);
+            const size_t off_all = 0, off_pr = align_up(sizeof(Req) * nreq, 64);
+            const size_t bytes = off_pr + sizeof(int) * (nreq + 1);
+            g.off_all = off_all;
+            g.off_pr = off_pr;
+            Slot* slot = nullptr;
+            isvd_status rc = acquire_slot(e, bytes, &slot);
+            if (rc != ISVD_OK) { cleanup(); return rc; }
+            memcpy(slot->host + off_all, g.all.data(), sizeof(Req) * nreq);
+            memcpy(slot->host + off_pr, g.pre_rot.data(), sizeof(int) * (nreq + 1));
+            hipEvent_t e0, e1;
+            if (hipMemcpyAsync(slot->dev, slot->host, bytes, hipMemcpyHostToDevice, st) != hipSuccess ||
+                hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+                cleanup();
+                return fail(ISVD_E_DEVICE, "autotune launch set-up");
+            }
+            const int reps = 6;
+            for (int w = 0; w < 2; ++w) rc = launch_phase(g, slot->dev, 3, st);
+            (void)hipEventRecord(e0, st);
+            for (int w = 0; w < reps && rc == ISVD_OK; ++w) rc = launch_phase(g, slot->dev, 3, st);
+            (void)hipEventRecord(e1, st);
+            (void)hipEventRecord(slot->ev, st);
+            slot->used = true;
+            float ms = 0.f;
+            if (rc == ISVD_OK && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                rc = fail(ISVD_E_DEVICE, "autotune timing");
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            if (rc != ISVD_OK) { cleanup(); return rc; }
+            const double per_launch = ms / reps;
+            if (ms_out) ms_out[bi * kRotVariants + ci] = per_launch;
+            if (per_launch < best) { best = per_launch; best_var = ci; }
+        }
+        HIP_TRY(hipStreamSynchronize(st));
+        cleanup();
+        e->rot_var_f32[bi] = best_var;
+        if (variant_out) variant_out[bi] = best_var;
+    }
+    return ISVD_OK;
+}
+
 isvd_status isvd_profile_read(isvd_engine* e, isvd_launch_time* out, int32_t cap, int32_t* count) {
     if (!e || !count || (cap > 0 && !out)) return fail(ISVD_E_INVAL, "null argument");
     ST_TRY(ensure_device(e));
@@ -1184,16 +1335,17 @@ struct GivenFactors {
 static isvd_status install_factors(Stream& s, const GivenFactors& f, hipStream_t st) {
     const int k = s.k_target, ld = round4(k);
     const int64_t m = s.m, n = s.n;
-    std::vector<char> bu((size_t)s.esz * m * ld, 0), bv((size_t)s.esz * n * ld, 0);
+    // tiled basis layout, whole tiles, zero padding
+    std::vector<char> bu((size_t)s.esz * round16(m) * ld, 0), bv((size_t)s.esz * round16(n) * ld, 0);
     for (int64_t r = 0; r < m; ++r)
         for (int c = 0; c < k; ++c) {
-            if (s.esz == 8) ((double*)bu.data())[r * ld + c] = f.U[r * f.ldu + c];
-            else ((float*)bu.data())[r * ld + c] = (float)f.U[r * f.ldu + c];
+            if (s.esz == 8) ((double*)bu.data())[uvo(r, c, ld)] = f.U[r * f.ldu + c];
+            else ((float*)bu.data())[uvo(r, c, ld)] = (float)f.U[r * f.ldu + c];
         }
     for (int64_t r = 0; r < n; ++r)
         for (int c = 0; c < k; ++c) {
-            if (s.esz == 8) ((double*)bv.data())[r * ld + c] = f.V[r * f.ldv + c];
-            else ((float*)bv.data())[r * ld + c] = (float)f.V[r * f.ldv + c];
+            if (s.esz == 8) ((double*)bv.data())[uvo(r, c, ld)] = f.V[r * f.ldv + c];
+            else ((float*)bv.data())[uvo(r, c, ld)] = (float)f.V[r * f.ldv + c];
         }
     HIP_TRY(hipMemcpyAsync(s.U[1], bu.data(), bu.size(), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(s.V[1], bv.data(), bv.size(), hipMemcpyHostToDevice, st));
@@ -1460,12 +1612,13 @@ isvd_status isvd_get_factors(isvd_engine* e, isvd_id id, double* U, int64_t ldu,
     const int k = h.k, ld = h.ld;
     if ((U && ldu < k) || (V && ldv < k)) return fail(ISVD_E_INVAL, "leading dimension below k = %d", k);
     auto pull = [&](const void* src, int64_t rows, double* dst, int64_t ldd) -> isvd_status {
-        std::vector<char> buf((size_t)s->esz * rows * ld);
+        std::vector<char> buf((size_t)s->esz * round16(rows) * ld);
         HIP_TRY(hipMemcpyAsync(buf.data(), src, buf.size(), hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
         for (int64_t r = 0; r < rows; ++r)
             for (int c = 0; c < k; ++c)
-                dst[r * ldd + c] = s->esz == 8 ? ((double*)buf.data())[r * ld + c] : ((float*)buf.data())[r * ld + c];
+                dst[r * ldd + c] = s->esz == 8 ? ((double*)buf.data())[uvo(r, c, ld)]
+                                               : ((float*)buf.data())[uvo(r, c, ld)];
         return ISVD_OK;
     };
     if (U) ST_TRY(pull(s->U[h.cur], h.m, U, ldu));
@@ -1554,10 +1707,12 @@ isvd_status isvd_tick(isvd_engine* e, int32_t count, const isvd_request* reqs, v
             groups.emplace_back();
             groups.back().fp64 = s.esz == 8;
             groups.back().kc = s.kc;
+            groups.back().rows = rows_for(e, s.kc, s.esz == 8);
+            groups.back().var = var_for(e, s.kc, s.esz == 8);
         }
         Group& g = groups[gi[key]];
         const isvd_request& r = reqs[q];
-        Req rq = make_req(s, r.kind, r.payload, r.i, r.j, r.delta, k_keep_for(s, r.kind));
+        Req rq = make_req(e, s, r.kind, r.payload, r.i, r.j, r.delta, k_keep_for(s, r.kind));
         g.all.push_back(rq);
         if (r.kind == ISVD_COL) g.proj.push_back(rq);
     }

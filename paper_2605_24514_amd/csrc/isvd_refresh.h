@@ -129,8 +129,9 @@ __global__ void k_sum_parts(const double* __restrict__ P, int nparts, int64_t st
     out[e] = (Tout)s;
 }
 
-// Gp[chunk] = Y[rows of chunk]^T Y[rows of chunk]  (b x b, FP64)
-template <typename T>
+// Gp[chunk] = Y[rows of chunk]^T Y[rows of chunk]  (b x b, FP64); Y row-major,
+// or in the tiled basis layout when TILED
+template <typename T, bool TILED = false>
 __global__ void __launch_bounds__(kThreads) k_gram_partial(const T* __restrict__ Y, int ldy, int64_t rows,
                                                            int b, double* __restrict__ Gp) {
     __shared__ double sY[kGemmK][kMaxBlock + 1];
@@ -144,7 +145,7 @@ __global__ void __launch_bounds__(kThreads) k_gram_partial(const T* __restrict__
         for (int e = threadIdx.x; e < kGemmK * b; e += kThreads) {
             int rr = e / b, j = e % b;
             int64_t r = r0 + rr;
-            sY[rr][j] = r < rb ? (double)Y[r * ldy + j] : 0.0;
+            sY[rr][j] = r < rb ? (double)Y[TILED ? uvo(r, j, ldy) : r * ldy + j] : 0.0;
         }
         __syncthreads();
 #pragma unroll
@@ -246,8 +247,9 @@ __global__ void k_small_gemm(const double* __restrict__ A, const double* __restr
     }
 }
 
-// out[r, 0:ldo] = in[r, 0:kin] Q[0:kin, 0:ldo]   (may run in place when ldi == ldo)
-template <typename T, int KC>
+// out[r, 0:ldo] = in[r, 0:kin] Q[0:kin, 0:ldo]   (may run in place when ldi == ldo);
+// `in` row-major, `out` row-major or, when TILED_OUT, in the tiled basis layout
+template <typename T, int KC, bool TILED_OUT = false>
 __global__ void __launch_bounds__(kThreads) k_rotate_plain(const T* in, int ldi, T* out, int ldo,
                                                            int64_t rows, int kin,
                                                            const T* __restrict__ Q) {
@@ -263,7 +265,7 @@ __global__ void __launch_bounds__(kThreads) k_rotate_plain(const T* in, int ldi,
         const int rr = e / ldo, j = e % ldo;
         T acc = (T)0;
         for (int c = 0; c < kin; ++c) acc += sX[rr * ldi + c] * sQ[c * ldo + j];
-        out[(r0 + rr) * ldo + j] = acc;
+        out[TILED_OUT ? uvo(r0 + rr, j, ldo) : (r0 + rr) * ldo + j] = acc;
     }
 }
 
@@ -322,7 +324,7 @@ __global__ void k_start_block(T* __restrict__ X, int ldx, int64_t n, int b, cons
     if (ident) {
         v = (r == j) ? (T)1 : (T)0;
     } else if (j < kw) {
-        v = V[r * ldv + j];
+        v = V[uvo(r, j, ldv)];
     } else {
         uint64_t h = seed ^ ((uint64_t)r * 0x9E3779B97F4A7C15ull) ^ ((uint64_t)(j + 1) * 0xC2B2AE3D27D4EB4Full);
         h ^= h >> 33; h *= 0xff51afd7ed558ccdull; h ^= h >> 33; h *= 0xc4ceb9fe1a85ec53ull; h ^= h >> 33;
@@ -389,8 +391,8 @@ __global__ void __launch_bounds__(kThreads) k_resid2_partial(const T* __restrict
             const int rr = e / 16, ll = e % 16;
             const int64_t r = r0 + rr, c = c0 + rr;
             const int l = l0 + ll;
-            sU[rr][ll] = (r < m && l < k) ? (T)((double)U[r * ld + l] * S[l]) : (T)0;
-            sV[rr][ll] = (c < n && l < k) ? V[c * ld + l] : (T)0;
+            sU[rr][ll] = (r < m && l < k) ? (T)((double)U[uvo(r, l, ld)] * S[l]) : (T)0;
+            sV[rr][ll] = (c < n && l < k) ? V[uvo(c, l, ld)] : (T)0;
         }
         __syncthreads();
 #pragma unroll

@@ -84,7 +84,7 @@ __global__ void __launch_bounds__(kThreads) k_track_col(const Track* __restrict_
                 const int64_t r = rb + rr;
                 double d = 0.0;
                 if (r < r1)
-                    for (int c = q; c < kin; c += 4) d += (double)U[r * ldi + c] * sp[c];
+                    for (int c = q; c < kin; c += 4) d += (double)U[uvo(r, c, ldi)] * sp[c];
                 d += __shfl_xor(d, 1);
                 d += __shfl_xor(d, 2);
                 if (q == 0) sz[rr] = r < r1 ? ((double)y[r] - d) * inv_rho : 0.0;
@@ -92,9 +92,9 @@ __global__ void __launch_bounds__(kThreads) k_track_col(const Track* __restrict_
             __syncthreads();
             const int nr = (int)min((int64_t)64, r1 - rb);
             if (t < kref) {
-                for (int rr = 0; rr < nr; ++rr) acc += (double)Ur[(rb + rr) * ldr + t] * sz[rr];
+                for (int rr = 0; rr < nr; ++rr) acc += (double)Ur[uvo(rb + rr, t, ldr)] * sz[rr];
             } else if (t >= 128 && t - 128 < kin) {
-                for (int rr = 0; rr < nr; ++rr) acc += (double)U[(rb + rr) * ldi + (t - 128)] * sz[rr];
+                for (int rr = 0; rr < nr; ++rr) acc += (double)U[uvo(rb + rr, t - 128, ldi)] * sz[rr];
             } else if (t == kThreads - 1) {
                 for (int rr = 0; rr < nr; ++rr) acc += sz[rr] * sz[rr];
             }
@@ -295,7 +295,8 @@ __global__ void __launch_bounds__(kThreads) k_theta_direct(const double* M, cons
     if (threadIdx.x == 0) *out = th;
 }
 
-// Gp[chunk] = X[rows of chunk]^T Y[rows of chunk]  (kx x ky, FP64, row stride ky)
+// Gp[chunk] = X[rows of chunk]^T Y[rows of chunk]  (kx x ky, FP64, row stride ky);
+// X and Y in the tiled basis layout
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_cross_partial(const T* __restrict__ X, int ldx, int kx,
                                                             const T* __restrict__ Y, int ldy, int ky, int64_t rows,
@@ -312,8 +313,8 @@ __global__ void __launch_bounds__(kThreads) k_cross_partial(const T* __restrict_
         for (int e = threadIdx.x; e < 16 * kMaxBlock; e += kThreads) {
             const int rr = e / kMaxBlock, c = e % kMaxBlock;
             const int64_t r = r0 + rr;
-            sX[rr][c] = (r < rb && c < kx) ? (double)X[r * ldx + c] : 0.0;
-            sY[rr][c] = (r < rb && c < ky) ? (double)Y[r * ldy + c] : 0.0;
+            sX[rr][c] = (r < rb && c < kx) ? (double)X[uvo(r, c, ldx)] : 0.0;
+            sY[rr][c] = (r < rb && c < ky) ? (double)Y[uvo(r, c, ldy)] : 0.0;
         }
         __syncthreads();
 #pragma unroll

@@ -68,7 +68,7 @@ __global__ void __launch_bounds__(kThreads) k_proj1(const Req* __restrict__ reqs
         }
         if (c0 < k) {
             double xv[4];
-            load4<T>(X + r * ld + c0, xv);
+            load4<T>(X + uvo(r, c0, ld), xv);
 #pragma unroll
             for (int q = 0; q < 4; ++q)
                 if (c0 + q < k) acc[q] += yv * xv[q];
@@ -141,7 +141,7 @@ __global__ void __launch_bounds__(kThreads) k_proj2(const Req* __restrict__ reqs
         const bool live = r < r1;
         double xv[4] = {0.0, 0.0, 0.0, 0.0};
         if (live && c0 < k) {
-            load4<T>(X + r * ld + c0, xv);
+            load4<T>(X + uvo(r, c0, ld), xv);
 #pragma unroll
             for (int q = 0; q < 4; ++q)
                 if (c0 + q >= k) xv[q] = 0.0;
@@ -224,7 +224,7 @@ __device__ inline void block_project(const T* __restrict__ X, int ld, int k, con
                 const int64_t r = base + (int64_t)u * rps;
                 const bool live = r < rows;
                 if (live && colok) {
-                    load4<T>(X + r * ld + c0, xv[u]);
+                    load4<T>(X + uvo(r, c0, ld), xv[u]);
                 } else {
 #pragma unroll
                     for (int q = 0; q < 4; ++q) xv[u][q] = 0.0;
@@ -397,8 +397,8 @@ __global__ void __launch_bounds__(CoreShape<KC>::J::NT) k_core(const Req* __rest
             sp[c] = pc;
             rq.p[c] = pc;
         } else {
-            if constexpr (!WITH_J) su[c] = (double)((const T*)rq.U[cur])[rq.i * ld + c];
-            sp[c] = (double)((const T*)rq.V[cur])[rq.j * ld + c];
+            if constexpr (!WITH_J) su[c] = (double)((const T*)rq.U[cur])[uvo(rq.i, c, ld)];
+            sp[c] = (double)((const T*)rq.V[cur])[uvo(rq.j, c, ld)];
         }
     }
     __syncthreads();
@@ -412,7 +412,7 @@ __global__ void __launch_bounds__(CoreShape<KC>::J::NT) k_core(const Req* __rest
             continue;
         }
         if (kind == kEntry) {
-            const double uu = WITH_J ? (double)((const T*)rq.U[cur])[rq.i * ld + row] : su[row];
+            const double uu = WITH_J ? (double)((const T*)rq.U[cur])[uvo(rq.i, row, ld)] : su[row];
             v = (row == col ? sS[row] : 0.0) + rq.delta * uu * sp[col];
         } else {
             if (row < k) v = (row == col) ? sS[row] : 0.0;
@@ -486,12 +486,12 @@ __global__ void __launch_bounds__(CoreShape<KC>::J::NT) k_core(const Req* __rest
             QV[e] = (T)vk;
         } else if (kind == kRow) {
             if (row < k) QU[e] = (T)uk;
-            else ((T*)rq.U[cur ^ 1])[rq.m * ldo + j] = (T)uk;
+            else ((T*)rq.U[cur ^ 1])[uvo(rq.m, j, ldo)] = (T)uk;
             QV[e] = (T)vk;
         } else {
             QU[e] = (T)vk;
             if (row < k) QV[e] = (T)uk;
-            else ((T*)rq.V[cur ^ 1])[rq.n * ldo + j] = (T)uk;
+            else ((T*)rq.V[cur ^ 1])[uvo(rq.n, j, ldo)] = (T)uk;
         }
     }
     for (int j = tid; j < kout; j += nt) rq.S[j] = sig[j];
@@ -565,9 +565,10 @@ __global__ void __launch_bounds__(kThreads) k_rotate(const Req* __restrict__ req
     const bool projected = (rq.kind == kRow && !isU) || (rq.kind == kCol && isU);
     const int nq = kin + (projected ? 1 : 0);
     for (int e = threadIdx.x; e < nq * ldo; e += kThreads) sQ[e] = Q[e];
-    const int64_t r0 = (int64_t)tile * RT;
+    const int64_t r0 = (int64_t)tile * RT;              // a multiple of 16: whole tiles
     const int nr = (int)min((int64_t)RT, rows - r0);
-    for (int e = threadIdx.x; e < nr * ldi; e += kThreads) sX[e] = Xi[r0 * ldi + e];
+    const int ntl = (nr + 15) & ~15;                     // rows of the tiles loaded
+    for (int e = threadIdx.x; e < ntl * ldi; e += kThreads) sX[e] = Xi[r0 * ldi + e];
     if (projected)
         for (int c = threadIdx.x; c < kin; c += kThreads) sp[c] = rq.p[c];
     __syncthreads();
@@ -577,7 +578,7 @@ __global__ void __launch_bounds__(kThreads) k_rotate(const Req* __restrict__ req
         T* A = (T*)rq.A;
         for (int rr = threadIdx.x; rr < nr; rr += kThreads) {
             double d = 0.0;
-            for (int c = 0; c < kin; ++c) d += (double)sX[rr * ldi + c] * sp[c];
+            for (int c = 0; c < kin; ++c) d += (double)sX[uvo(rr, c, ldi)] * sp[c];
             const T yv = y[r0 + rr];
             sz[rr] = ((double)yv - d) * inv_rho;
             if (rq.kind == kRow) A[rq.m * rq.lda + r0 + rr] = yv;
@@ -588,9 +589,9 @@ __global__ void __launch_bounds__(kThreads) k_rotate(const Req* __restrict__ req
     for (int e = threadIdx.x; e < nr * ldo; e += kThreads) {
         const int rr = e / ldo, j = e % ldo;
         T acc = (T)0;
-        for (int c = 0; c < kin; ++c) acc += sX[rr * ldi + c] * sQ[c * ldo + j];
+        for (int c = 0; c < kin; ++c) acc += sX[uvo(rr, c, ldi)] * sQ[c * ldo + j];
         if (projected) acc += (T)sz[rr] * sQ[kin * ldo + j];
-        Xo[(r0 + rr) * ldo + j] = acc;
+        Xo[uvo(r0 + rr, j, ldo)] = acc;
     }
 }
 
@@ -671,7 +672,8 @@ __global__ void __launch_bounds__(kThreads) k_rotate_mfma(const Req* __restrict_
 #pragma unroll
         for (int v = 0; v < VPL; ++v) {
             const int f = l + 64 * v;
-            if (f < ntile_vec_in && 4 * f < nr * ldi) pre[v] = ((gcf4*)(Xi + row0 * ldi))[f];
+            // a whole 16-row tile (contiguous); rows past the basis are not stored
+            if (f < ntile_vec_in && nr > 0) pre[v] = ((gcf4*)(Xi + row0 * ldi))[f];
             else pre[v] = (mfma_v4f){0.f, 0.f, 0.f, 0.f};
         }
     };
@@ -687,8 +689,8 @@ __global__ void __launch_bounds__(kThreads) k_rotate_mfma(const Req* __restrict_
         for (int v = 0; v < VPL; ++v) {
             const int f = l + 64 * v;
             if (f < ntile_vec_in) {
-                const int e = 4 * f;
-                const int r = e / ldi, c = e % ldi;
+                int r, c;
+                uv_tile_rc(4 * f, &r, &c);
                 float* d = sx + r * XP + c;
                 d[0] = c + 0 < kin ? pre[v][0] : 0.0f;
                 d[1] = c + 1 < kin ? pre[v][1] : 0.0f;
@@ -748,9 +750,10 @@ __global__ void __launch_bounds__(kThreads) k_rotate_mfma(const Req* __restrict_
             for (int j = 0; j < 4; ++j) so[(4 * g + j) * OP + 16 * nb + col] = acc[nb][j];
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-        for (int f = l; f < ntile_vec_out && 4 * f < nr * ldo; f += 64) {
-            const int e = 4 * f;
-            const int r = e / ldo, c = e % ldo;
+        for (int f = l; f < ntile_vec_out; f += 64) {
+            int r, c;
+            uv_tile_rc(4 * f, &r, &c);
+            if (r >= nr) continue;
             const float* src = so + r * OP + c;
             ((gf4*)(Xo + row0 * ldo))[f] = (mfma_v4f){src[0], src[1], src[2], src[3]};
         }
@@ -758,6 +761,146 @@ __global__ void __launch_bounds__(kThreads) k_rotate_mfma(const Req* __restrict_
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         row0 = nrow0;
         nr = nnr;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// FP32 rotation on the matrix cores, transposed: X'^T = Q^T X^T with
+// v_mfma_f32_16x16x4f32 (lane l: A[l%16][l/16], B[l/16][l%16],
+// D[4(l/16)+r][l%16]).  Q^T is the A operand and stays in registers for all
+// of a wave's row tiles.  X is the B operand: with the tiled basis layout,
+// the q-th 16-column panel of a 16-row tile is 256 contiguous floats and
+// lane l takes one float4 of it -- row l%16, columns 16 q + 4 (l/16) + 0..3 --
+// so each load instruction reads 1 KB contiguous; the MFMA k order follows
+// (step s: k = 16 (s/4) + 4 (l/16) + s%4).  The accumulators hold, for row
+// l%16, the four output columns 16 nb + 4 (l/16) + r, which is again one
+// float4 of the output tile's panel nb: stores are 1 KB contiguous too.  No
+// LDS staging.  ROWS rows per block; a wave takes RT consecutive 16-row tiles
+// per step (RT independent accumulator sets); with PF the next step's loads
+// are issued before the current step's MFMAs.
+template <int KC, int ROWS, int RT, bool PF>
+__global__ void __launch_bounds__(kThreads) k_rotate_mfma_t(const Req* __restrict__ reqs,
+                                                            const int* __restrict__ prefix, int nreq) {
+    constexpr int NQ = (KC + 15) / 16;           // panels (loads per lane per tile)
+    constexpr int STEPS = 4 * NQ;                // MFMA k-steps per output block
+    constexpr int NB = NQ;                       // 16-column output blocks
+    constexpr int SROWS = 64 * RT;               // rows per block step (4 waves)
+    constexpr int TSTEPS = ROWS / SROWS;
+    __shared__ double sp[16 * NQ];
+    __shared__ float sqz[16 * NB];
+    const int ri = find_req(prefix, nreq, blockIdx.x);
+    const Req& rq = reqs[ri];
+    const ReqScratch* rs = rq.rs;
+    if (rs->skip) return;
+    const int tile_all = blockIdx.x - prefix[ri];
+    const bool isU = tile_all < rq.rot_tiles_u;
+    const int tile = isU ? tile_all : tile_all - rq.rot_tiles_u;
+    const int kin = rs->k_in, ldi = rs->ld_in, ldo = rs->ld_out, idx = rs->in_idx;
+    const int64_t rows = isU ? rq.m : rq.n;
+    gcfloat* Xi = (gcfloat*)(isU ? rq.U[idx] : rq.V[idx]);
+    gfloat* Xo = (gfloat*)(isU ? rq.U[idx ^ 1] : rq.V[idx ^ 1]);
+    gcfloat* Q = (gcfloat*)(isU ? rq.QU : rq.QV);
+    const bool projected = (rq.kind == kRow && !isU) || (rq.kind == kCol && isU);
+    if (projected) {
+        for (int c = threadIdx.x; c < 16 * NQ; c += kThreads) sp[c] = c < kin ? rq.p[c] : 0.0;
+        for (int c = threadIdx.x; c < 16 * NB; c += kThreads) sqz[c] = c < ldo ? Q[kin * ldo + c] : 0.0f;
+    }
+    const int l = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int g = l >> 4, n = l & 15;
+    // Q^T in registers: qa[nb][s] = Q[k(s)][16 nb + n]
+    float qa[NB][STEPS];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int s4 = 0; s4 < STEPS; ++s4) {
+            const int k = 16 * (s4 >> 2) + 4 * g + (s4 & 3);
+            const int c = 16 * nb + n;
+            qa[nb][s4] = (k < kin && c < ldo) ? Q[k * ldo + c] : 0.0f;
+        }
+    __syncthreads();
+    mfma_v4f b[RT][NQ], bn[PF ? RT : 1][NQ];
+    // the B operand of a step's tiles: panel q, 4-column group g, row n (zero
+    // past the basis' rows or columns)
+    auto fetch = [&](int64_t s0, mfma_v4f (*dst)[NQ]) {
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) {
+            const int64_t t0 = s0 + 16 * rt;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                if (t0 + n < rows && 16 * q + 4 * g < ldi)
+                    dst[rt][q] = *(gcf4*)(Xi + t0 * ldi + 256 * q + 64 * g + 4 * n);
+                else
+                    dst[rt][q] = (mfma_v4f){0.f, 0.f, 0.f, 0.f};
+            }
+        }
+    };
+    const float* yv_base = (const float*)rq.payload;
+    const double inv_rho = rs->inv_rho;
+    int64_t row0 = (int64_t)tile * ROWS + wave * 16 * RT;
+    fetch(row0, b);
+#pragma unroll 1
+    for (int t = 0; t < TSTEPS; ++t) {
+        if (row0 >= rows) break;
+        const int64_t nrow0 = row0 + SROWS;
+        if constexpr (PF) {
+            if (t + 1 < TSTEPS) fetch(nrow0, bn);
+        }
+        mfma_v4f acc[RT][NB];
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) acc[rt][nb] = (mfma_v4f){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s4 = 0; s4 < STEPS; ++s4)
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt) {
+                const float bv = b[rt][s4 >> 2][s4 & 3];
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb)
+                    acc[rt][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(qa[nb][s4], bv, acc[rt][nb], 0, 0, 0);
+            }
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) {
+            const int64_t t0 = row0 + 16 * rt;
+            const int64_t row = t0 + n;
+            const bool live = row < rows;
+            if (projected) {
+                // z^ of this lane's row: (y - X p) / rho, the dot in FP64 over
+                // the lane's k values, then across the four lane groups
+                double d = 0.0;
+#pragma unroll
+                for (int s4 = 0; s4 < STEPS; ++s4)
+                    d += (double)b[rt][s4 >> 2][s4 & 3] * sp[16 * (s4 >> 2) + 4 * g + (s4 & 3)];
+                d += __shfl_xor(d, 16);
+                d += __shfl_xor(d, 32);
+                const float yv = live ? yv_base[row] : 0.0f;
+                const float z = (float)(((double)yv - d) * inv_rho);
+                if (live && g == 0) {
+                    gfloat* A = (gfloat*)rq.A;
+                    if (rq.kind == kRow) A[rq.m * rq.lda + row] = yv;
+                    else A[row * rq.lda + rq.n] = yv;
+                }
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) acc[rt][nb][r] += z * sqz[16 * nb + 4 * g + r];
+            }
+            if (live) {
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb)
+                    if (16 * nb + 4 * g < ldo) *(gf4*)(Xo + t0 * ldo + 256 * nb + 64 * g + 4 * n) = acc[rt][nb];
+            }
+        }
+        if constexpr (PF) {
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) b[rt][q] = bn[rt][q];
+        } else {
+            if (t + 1 < TSTEPS) fetch(nrow0, b);
+        }
+        row0 = nrow0;
     }
 }
 

@@ -65,10 +65,13 @@ class CLaunchTime(ctypes.Structure):
                 ("nreq", ctypes.c_int32), ("blocks", ctypes.c_int64), ("ms", ctypes.c_double)]
 
 
+# FP32 rotation block shapes: (rows per block, 16-row tiles per wave step, prefetch)
+ROT_VARIANTS = [(256, 1, True), (512, 1, True), (1024, 1, True), (1024, 2, False), (2048, 2, False)]
+
 EXPORTS = ["isvd_engine_create", "isvd_engine_destroy", "isvd_stream_bytes", "isvd_init", "isvd_init_from_factors",
            "isvd_append_row", "isvd_append_col", "isvd_update_entry", "isvd_refresh", "isvd_metrics",
            "isvd_get_factors", "isvd_get_matrix", "isvd_shape", "isvd_release", "isvd_tick",
-           "isvd_profile", "isvd_profile_read", "isvd_last_error"]
+           "isvd_profile", "isvd_profile_read", "isvd_autotune", "isvd_set_rotation_variant", "isvd_last_error"]
 
 _lib = None
 
@@ -101,6 +104,8 @@ def load_library(path=LIB_PATH):
         "isvd_tick": (i32, [vp, i32, ctypes.POINTER(CRequest), vp]),
         "isvd_profile": (i32, [vp, i32]),
         "isvd_profile_read": (i32, [vp, ctypes.POINTER(CLaunchTime), i32, ctypes.POINTER(i32)]),
+        "isvd_autotune": (i32, [vp, vp, ctypes.POINTER(i32), dp]),
+        "isvd_set_rotation_variant": (i32, [vp, i32, i32]),
         "isvd_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -341,6 +346,19 @@ class Engine:
         arr = (CLaunchTime * max(cnt.value, 1))()
         self._check(self._lib.isvd_profile_read(self._h, arr, cnt.value, ctypes.byref(cnt)), "isvd_profile_read")
         return [{f: getattr(arr[q], f) for f, _ in CLaunchTime._fields_} for q in range(cnt.value)]
+
+    def autotune(self, stream=None):
+        """Time the FP32 rotation's block shapes per rank bucket and keep the
+        fastest.  Returns {bucket: (variant chosen, [ms per launch of each variant])};
+        ROT_VARIANTS lists the shapes."""
+        var = (ctypes.c_int32 * 4)()
+        ms = (ctypes.c_double * (4 * len(ROT_VARIANTS)))()
+        self._check(self._lib.isvd_autotune(self._h, _stream_ptr(stream), var, ms), "isvd_autotune")
+        nv = len(ROT_VARIANTS)
+        return {kc: (var[b], [ms[nv * b + c] for c in range(nv)]) for b, kc in enumerate((8, 16, 32, 64))}
+
+    def set_rotation_variant(self, kc, variant):
+        self._check(self._lib.isvd_set_rotation_variant(self._h, kc, variant), "isvd_set_rotation_variant")
 
     def tick_raw(self, arr, stream=None):
         self._check(self._lib.isvd_tick(self._h, len(arr), arr, _stream_ptr(stream)), "isvd_tick")

@@ -101,3 +101,31 @@ def test_tick_validation_rejects_whole_tick(env):
             eng.tick([(a, isvd.ROW, good), (a, isvd.ROW, good)])
         assert e.value.status == -1
         assert eng.metrics(a)["t"] == 0 and eng.metrics(b)["t"] == 0
+
+
+def test_rotation_block_shapes_give_identical_results(env):
+    """Every autotuner candidate of the FP32 rotation does each row's
+    arithmetic in the same order, so results are bitwise equal across them;
+    the rows cover several blocks of every shape and a ragged last tile."""
+    torch, isvd = env
+    T = 6
+    shapes = [(2500, 40, 8), (2100, 50, 16), (1700, 60, 32), (3000, 70, 64), (2049, 33, 20)]
+    kinds = [ROW, COL, ENTRY, ROW, COL, ROW]
+    data = []
+    for s, (m0, n0, k) in enumerate(shapes):
+        fs = FactorStream(seed=8, stream=s, n0=n0, K=5)
+        data.append((fs.initial(m0), k, fs.materialize(kinds, m0=m0)))
+    results = []
+    for variant in range(len(isvd.ROT_VARIANTS)):
+        with isvd.Engine() as eng:
+            for kc in (8, 16, 32, 64):
+                eng.set_rotation_variant(kc, variant)
+            sids = [eng.init(A0, k, "fp32", m_cap=A0.shape[0] + T, n_cap=A0.shape[1] + T, oversample=8)
+                    for A0, k, _ in data]
+            for t in range(T):
+                eng.tick([_req(torch, isvd, sid, evs[t]) for sid, (_, _, evs) in zip(sids, data)])
+            results.append([eng.factors(sid) for sid in sids])
+    for variant in range(1, len(results)):
+        for q in range(len(shapes)):
+            for a, b in zip(results[0][q], results[variant][q]):
+                assert np.array_equal(a, b), (variant, q)
