@@ -92,10 +92,9 @@ struct Req {
     void* U[2];
     void* V[2];
     double* S;            // singular values (k_cap + 1)
-    double* p;            // pass-1 sums: p1[0..k), ||y||^2 at [kc], non-finite count at [kc+1]
-    double* p2;           // pass-2 sums: p2[0..k), ||z1||^2 at [kc]
-    double* partials;     // per-block partial sums, stride kc + 2
-    unsigned* counters;   // arrival counters of the two projection passes
+    double* p;            // projection coefficients p = p1 + p2 of an append (written by the core)
+    double* partials;     // projection pass 1: per-block partial sums, stride kc + 2
+    double* partials2;    // projection pass 2: the same
     void* QU;             // (k_in + 1) x ld_out rotation of U (row-major)
     void* QV;             // (k_in + 1) x ld_out rotation of V
     const void* payload;  // x (length n) or y (length m), storage type

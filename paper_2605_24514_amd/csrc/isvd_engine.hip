@@ -71,7 +71,7 @@ int bucket_for(int kmax) {
 
 // ------------------------------------------------------------------ streams
 struct Layout {
-    size_t hdr, rs, S, p, p2, counters, partials, QU, QV, stage, U0, U1, V0, V1, Uref, TM, TH, TP, A, total;
+    size_t hdr, rs, S, p, partials, partials2, QU, QV, stage, U0, U1, V0, V1, Uref, TM, TH, TP, A, total;
 };
 
 struct Stream {
@@ -86,8 +86,7 @@ struct Stream {
     Layout L{};
     DevHeader* hdr = nullptr;
     ReqScratch* rs = nullptr;
-    double *S = nullptr, *p = nullptr, *p2 = nullptr, *partials = nullptr;
-    unsigned* counters = nullptr;
+    double *S = nullptr, *p = nullptr, *partials = nullptr, *partials2 = nullptr;
     void *QU = nullptr, *QV = nullptr, *stage = nullptr, *A = nullptr, *Uref = nullptr;
     double *TM = nullptr, *TH = nullptr, *TP = nullptr;   // angle trackers M, H and column-pass sums
     void* U[2] = {nullptr, nullptr};
@@ -115,9 +114,8 @@ Layout make_layout(const isvd_config& c, int esz, int kc, int64_t* ntiles_max) {
     L.rs = take(sizeof(ReqScratch));
     L.S = take(sizeof(double) * (kc + 2));
     L.p = take(sizeof(double) * (kc + 4));
-    L.p2 = take(sizeof(double) * (kc + 4));
-    L.counters = take(sizeof(unsigned) * 4);
     L.partials = take(sizeof(double) * (size_t)nt * (kc + 2));
+    L.partials2 = take(sizeof(double) * (size_t)nt * (kc + 2));
     L.QU = take((size_t)esz * (kc + 1) * kc);
     L.QV = take((size_t)esz * (kc + 1) * kc);
     L.stage = take((size_t)esz * mx);
@@ -256,9 +254,9 @@ isvd_status launch_group_phase(const Group& g, const char* dev, int phase, hipSt
     const int* pr = reinterpret_cast<const int*>(dev + g.off_pr);
     const int np = (int)g.proj.size(), na = (int)g.all.size();
     if (phase == 0 && np > 0) {
-        k_proj1<T, KC><<<g.pre_proj[np], kThreads, 0, st>>>(proj, pp, np);
+        k_proj<T, KC, 1><<<g.pre_proj[np], kThreads, 0, st>>>(proj, pp, np);
     } else if (phase == 1 && np > 0) {
-        k_proj2<T, KC><<<g.pre_proj[np], kThreads, 0, st>>>(proj, pp, np);
+        k_proj<T, KC, 2><<<g.pre_proj[np], kThreads, 0, st>>>(proj, pp, np);
     } else if (phase == 2 && na > 0) {
         size_t lds = sizeof(double) * core_lds_doubles<KC, sizeof(T) == 8>();
         k_core<T, KC><<<na, CoreShape<KC>::J::NT, lds, st>>>(all);
@@ -356,9 +354,8 @@ Req make_req(const isvd_engine* e, Stream& s, int kind, const void* payload, int
     r.tol_rel = s.cfg.tol_rel;
     r.kind = kind;
     r.k_keep = k_keep;
-    // row appends project inside the core block; column appends use the
-    // multi-block projection passes over U
-    r.proj_tiles = kind == kCol ? (int)cdiv(s.m, kProjTile) : 0;
+    // appends: projection passes over row tiles of V (row) or U (column)
+    r.proj_tiles = kind == kCol ? (int)cdiv(s.m, kProjTile) : kind == kRow ? (int)cdiv(s.n, kProjTile) : 0;
     r.rot_tiles_u = (int)cdiv(s.m, rows_for(e, s.kc, s.esz == 8));
     r.hdr = s.hdr;
     r.rs = s.rs;
@@ -369,9 +366,8 @@ Req make_req(const isvd_engine* e, Stream& s, int kind, const void* payload, int
     r.V[1] = s.V[1];
     r.S = s.S;
     r.p = s.p;
-    r.p2 = s.p2;
     r.partials = s.partials;
-    r.counters = s.counters;
+    r.partials2 = s.partials2;
     r.QU = s.QU;
     r.QV = s.QV;
     r.payload = payload;
@@ -1079,7 +1075,7 @@ isvd_status single_update(isvd_engine* e, Stream& s, int kind, const void* paylo
     g.var = var_for(e, g.kc, g.fp64);
     Req r = make_req(e, s, kind, payload, i, j, delta, k_keep_for(s, kind));
     g.all.push_back(r);
-    if (kind == kCol) g.proj.push_back(r);
+    if (kind != kEntry) g.proj.push_back(r);
     HIP_TRY(hipEventRecord(s.ev_u0, st));
     ST_TRY(run_groups(e, groups, st));
     if (s.angle) ST_TRY(run_tracks(e, {make_track(s, kind, payload)}, {(char)(s.esz == 8)}, st));
@@ -1395,9 +1391,8 @@ static isvd_status init_common(isvd_engine* e, const isvd_config* cfg, const voi
     s->rs = (ReqScratch*)(b + s->L.rs);
     s->S = (double*)(b + s->L.S);
     s->p = (double*)(b + s->L.p);
-    s->p2 = (double*)(b + s->L.p2);
-    s->counters = (unsigned*)(b + s->L.counters);
     s->partials = (double*)(b + s->L.partials);
+    s->partials2 = (double*)(b + s->L.partials2);
     s->QU = b + s->L.QU;
     s->QV = b + s->L.QV;
     s->stage = b + s->L.stage;
@@ -1714,7 +1709,7 @@ isvd_status isvd_tick(isvd_engine* e, int32_t count, const isvd_request* reqs, v
         const isvd_request& r = reqs[q];
         Req rq = make_req(e, s, r.kind, r.payload, r.i, r.j, r.delta, k_keep_for(s, r.kind));
         g.all.push_back(rq);
-        if (r.kind == ISVD_COL) g.proj.push_back(rq);
+        if (r.kind != ISVD_ENTRY) g.proj.push_back(rq);
     }
     ST_TRY(run_groups(e, groups, st));
     std::vector<Track> tracks;

@@ -37,11 +37,12 @@ __host__ __device__ inline int lds_stride(int N) { return N <= 92 ? (N + 27) / 3
 // Block shape of a core of order up to NMAX: pairs of TPP lanes, the block
 // just large enough for all pairs of one round.  Few lanes per pair keep the
 // per-round work that every lane repeats (the rotation angle, the lane
-// reductions) off most of the SIMD slots.
-template <int NMAX>
+// reductions) off most of the SIMD slots; more lanes per pair shorten each
+// lane's serial dot products and rotations (a round's latency).
+template <int NMAX, int TPP_ = 4>
 struct JacobiShape {
     static constexpr int NPAIRS = (NMAX + 1) / 2;
-    static constexpr int TPP = 4;
+    static constexpr int TPP = TPP_;
     static constexpr int EPT = (NMAX + TPP - 1) / TPP;              // elements per lane
     static constexpr int NT = ((NPAIRS * TPP + 63) / 64) * 64;      // threads per block
     // column stride of every core in the bucket: covers EPT * TPP elements,
@@ -78,12 +79,12 @@ __device__ inline double dpp_group_sum(double v) {
 // keep rounding-level rotations alive indefinitely).  Each lane holds its
 // EPT elements of the pair's columns in registers for the round: all LDS
 // loads issue before the arithmetic.  W and J have column stride
-// ldw = JacobiShape<NMAX>::LDW with zero rows from N up to the stride.
+// ldw = JacobiShape<NMAX, TPP>::LDW with zero rows from N up to the stride.
 // WITH_J: accumulate the rotations into J (= I on entry); without it only W
 // is rotated.
-template <int NMAX, bool WITH_J>
+template <int NMAX, bool WITH_J, int TPP = 4>
 __device__ inline int jacobi_block(double* W, double* J, int N, int ldw, int max_sweeps, double tol_min = 0.0) {
-    typedef JacobiShape<NMAX> S;
+    typedef JacobiShape<NMAX, TPP> S;
     const int tid = threadIdx.x;
     const int Np = N + (N & 1);
     const int npairs = Np >> 1;

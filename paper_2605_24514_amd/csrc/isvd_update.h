@@ -33,91 +33,26 @@ __device__ inline const void* basis_cur(const Req& rq, bool useU, int cur) {
 }
 
 // ---------------------------------------------------------------------------
-// Projection pass 1 (Section 2.2.1, eq. row-residual: p = x^T V).
-// Row append: basis V (n rows), payload x.  Column append (transpose):
-// basis U (m rows), payload y.  Each block sums p1 = X^T y and ||y||^2 over
-// its rows in FP64 and counts non-finite payload entries; the last block to
-// arrive adds the per-block partials in block order (deterministic).
-template <typename T, int KC>
-__global__ void __launch_bounds__(kThreads) k_proj1(const Req* __restrict__ reqs,
-                                                    const int* __restrict__ prefix, int nreq) {
-    constexpr int TPR = KC / 4;
-    constexpr int RPB = kThreads / TPR;
+// Projection (Section 2.2.1, eq. row-residual) with one classical
+// Gram-Schmidt re-orthogonalisation pass, over row tiles of the projected
+// basis X (V for a row append, U for a column append) with payload y:
+//   pass 1: p1 = X^T y, ||y||^2 and the count of non-finite y entries
+//   pass 2: z1 = y - X p1 per row, p2 = X^T z1, ||z1||^2
+// Then p = p1 + p2 and rho^2 = ||z1||^2 - ||p2||^2 (X has orthonormal
+// columns), so the residual z = y - X p never has to be stored: the rotation
+// recomputes it per row.  Each block writes its FP64 partial sums (stride
+// KC + 2: [0, k) the projection, [KC] the squared norm, [KC + 1] the
+// non-finite count); the next launch adds the partials in block order
+// (deterministic, independent of the batch), so no block waits for another.
+template <typename T, int KC, int PASS>
+__global__ void __launch_bounds__(kThreads) k_proj(const Req* __restrict__ reqs, const int* __restrict__ prefix,
+                                                   int nreq) {
+    constexpr int TPR = KC / 4;                  // lanes per row (4 columns each)
+    constexpr int RPB = kThreads / TPR;          // rows per block step
     constexpr int SP = KC + 2;
-    __shared__ double sacc[RPB][SP];
-    __shared__ int s_last;
-    const int ri = find_req(prefix, nreq, blockIdx.x);
-    const Req& rq = reqs[ri];
-    const int tile = blockIdx.x - prefix[ri];
-    const int k = rq.hdr->k, ld = rq.hdr->ld, cur = rq.hdr->cur;
-    const bool useU = rq.kind == kCol;
-    const T* X = (const T*)basis_cur(rq, useU, cur);
-    const int64_t rows = useU ? rq.m : rq.n;
-    const T* y = (const T*)rq.payload;
-    const int64_t r0 = (int64_t)tile * kProjTile;
-    const int64_t r1 = min(rows, r0 + kProjTile);
-    const int lane = threadIdx.x % TPR, grp = threadIdx.x / TPR;
-    const int c0 = lane * 4;
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    double ysq = 0.0, bad = 0.0;
-    for (int64_t r = r0 + grp; r < r1; r += RPB) {
-        double yv = (double)y[r];
-        if (lane == 0) {
-            ysq += yv * yv;
-            if (!isfinite(yv)) bad += 1.0;
-        }
-        if (c0 < k) {
-            double xv[4];
-            load4<T>(X + uvo(r, c0, ld), xv);
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                if (c0 + q < k) acc[q] += yv * xv[q];
-        }
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) sacc[grp][c0 + q] = acc[q];
-    if (lane == 0) { sacc[grp][KC] = ysq; sacc[grp][KC + 1] = bad; }
-    __syncthreads();
-    double* part = rq.partials + (size_t)tile * SP;
-    for (int c = threadIdx.x; c < SP; c += kThreads) {
-        double s = 0.0;
-        for (int gg = 0; gg < RPB; ++gg) s += sacc[gg][c];
-        part[c] = s;
-    }
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned prev = atomicAdd(&rq.counters[0], 1u);
-        s_last = (prev == (unsigned)rq.proj_tiles - 1u);
-    }
-    __syncthreads();
-    if (s_last) {
-        __threadfence();
-        for (int c = threadIdx.x; c < SP; c += kThreads) {
-            if (c < k || c >= KC) {
-                double s = 0.0;
-                for (int t = 0; t < rq.proj_tiles; ++t) s += rq.partials[(size_t)t * SP + c];
-                rq.p[c] = s;
-            }
-        }
-        if (threadIdx.x == 0) rq.counters[0] = 0u;
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Projection pass 2 (classical Gram-Schmidt, second pass, FP64):
-// z1 = y - X p1 per row, p2 = X^T z1 and ||z1||^2.  Then p = p1 + p2 and
-// rho^2 = ||z1||^2 - ||p2||^2 (X has orthonormal columns), so the residual
-// z = y - X p never has to be stored: the rotation recomputes it per row.
-template <typename T, int KC>
-__global__ void __launch_bounds__(kThreads) k_proj2(const Req* __restrict__ reqs,
-                                                    const int* __restrict__ prefix, int nreq) {
-    constexpr int TPR = KC / 4;
-    constexpr int RPB = kThreads / TPR;
-    constexpr int SP = KC + 2;
+    constexpr int UNR = 4;                       // row steps in flight per lane
     __shared__ double sacc[RPB][SP];
     __shared__ double sp1[KC];
-    __shared__ int s_last;
     const int ri = find_req(prefix, nreq, blockIdx.x);
     const Req& rq = reqs[ri];
     const int tile = blockIdx.x - prefix[ri];
@@ -126,157 +61,83 @@ __global__ void __launch_bounds__(kThreads) k_proj2(const Req* __restrict__ reqs
     const T* X = (const T*)basis_cur(rq, useU, cur);
     const int64_t rows = useU ? rq.m : rq.n;
     const T* y = (const T*)rq.payload;
-    for (int c = threadIdx.x; c < KC; c += kThreads) sp1[c] = c < k ? rq.p[c] : 0.0;
-    __syncthreads();
+    if (PASS == 2) {
+        // p1: pass 1's partials in block order
+        for (int c = threadIdx.x; c < KC; c += kThreads) {
+            double s1 = 0.0;
+            if (c < k)
+                for (int t = 0; t < rq.proj_tiles; ++t) s1 += rq.partials[(size_t)t * SP + c];
+            sp1[c] = s1;
+        }
+        __syncthreads();
+    }
     const int64_t r0 = (int64_t)tile * kProjTile;
     const int64_t r1 = min(rows, r0 + kProjTile);
     const int lane = threadIdx.x % TPR, grp = threadIdx.x / TPR;
     const int c0 = lane * 4;
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    double zsq = 0.0;
-    // every lane of a row group runs the same trip count (shuffles need them all)
-    const int64_t nsteps = (r1 - r0 + RPB - 1) / RPB;
-    for (int64_t st = 0; st < nsteps; ++st) {
-        const int64_t r = r0 + grp + st * RPB;
-        const bool live = r < r1;
-        double xv[4] = {0.0, 0.0, 0.0, 0.0};
-        if (live && c0 < k) {
-            load4<T>(X + uvo(r, c0, ld), xv);
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                if (c0 + q >= k) xv[q] = 0.0;
-        }
-        double d = xv[0] * sp1[c0] + xv[1] * sp1[c0 + 1] + xv[2] * sp1[c0 + 2] + xv[3] * sp1[c0 + 3];
-        d = group_sum(d, TPR);
-        if (live) {
-            double z1 = (double)y[r] - d;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) acc[q] += xv[q] * z1;
-            if (lane == 0) zsq += z1 * z1;
-        }
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) sacc[grp][c0 + q] = acc[q];
-    if (lane == 0) { sacc[grp][KC] = zsq; sacc[grp][KC + 1] = 0.0; }
-    __syncthreads();
-    double* part = rq.partials + (size_t)tile * SP;
-    for (int c = threadIdx.x; c < SP; c += kThreads) {
-        double s = 0.0;
-        for (int gg = 0; gg < RPB; ++gg) s += sacc[gg][c];
-        part[c] = s;
-    }
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned prev = atomicAdd(&rq.counters[1], 1u);
-        s_last = (prev == (unsigned)rq.proj_tiles - 1u);
-    }
-    __syncthreads();
-    if (s_last) {
-        __threadfence();
-        for (int c = threadIdx.x; c < SP; c += kThreads) {
-            if (c < k || c == KC) {
-                double s = 0.0;
-                for (int t = 0; t < rq.proj_tiles; ++t) s += rq.partials[(size_t)t * SP + c];
-                rq.p2[c] = s;
-            }
-        }
-        if (threadIdx.x == 0) rq.counters[1] = 0u;
-    }
-}
-
-// ---------------------------------------------------------------------------
-// In-block projection of a row append (both classical Gram-Schmidt passes),
-// run by the core's block itself: V (n x k) is small, so one block reads it
-// twice and no cross-block reduction is needed.  Same sums and FP64
-// accumulation as k_proj1 / k_proj2; results in LDS:
-//   out1[0..k) = p1, out1[KC] = ||x||^2, out1[KC+1] = non-finite count
-//   out2[0..k) = p2, out2[KC] = ||z1||^2
-// red: LDS scratch of (blockDim.x / (KC/4)) * (KC + 2) doubles.
-template <typename T, int KC>
-__device__ inline void block_project(const T* __restrict__ X, int ld, int k, const T* __restrict__ y,
-                                     int64_t rows, double* red, double* out1, double* out2) {
-    constexpr int LPR = KC / 4;
-    constexpr int SP = KC + 2;
-    constexpr int UNR = 8;                     // rows in flight per lane
-    const int nt = blockDim.x;
-    const int rps = nt / LPR;
-    const int lane = threadIdx.x % LPR, grp = threadIdx.x / LPR;
-    const int c0 = lane * 4;
-    const bool colok = c0 < k;
     double cm[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) cm[q] = c0 + q < k ? 1.0 : 0.0;
-    for (int pass = 0; pass < 2; ++pass) {
-        double acc[4] = {0.0, 0.0, 0.0, 0.0};
-        double sq = 0.0, bad = 0.0;
-        double pp[4] = {0.0, 0.0, 0.0, 0.0};
-        if (pass == 1)
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    double sq = 0.0, bad = 0.0;
+    // every lane of a row group runs the same trip count (pass 2 shuffles)
+    for (int64_t b0 = r0; b0 < r1; b0 += (int64_t)RPB * UNR) {
+        double xv[UNR][4], yv[UNR];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) pp[q] = c0 + q < k ? out1[c0 + q] : 0.0;
-        // every lane runs the same trip count (pass 2 shuffles across lanes)
-        for (int64_t b0 = 0; b0 < rows; b0 += (int64_t)rps * UNR) {
-            const int64_t base = b0 + grp;
-            double xv[UNR][4];
-            double yv[UNR];
-#pragma unroll
-            for (int u = 0; u < UNR; ++u) {
-                const int64_t r = base + (int64_t)u * rps;
-                const bool live = r < rows;
-                if (live && colok) {
-                    load4<T>(X + uvo(r, c0, ld), xv[u]);
-                } else {
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) xv[u][q] = 0.0;
-                }
-                yv[u] = live ? (double)y[r] : 0.0;
-            }
-#pragma unroll
-            for (int u = 0; u < UNR; ++u) {
+        for (int u = 0; u < UNR; ++u) {
+            const int64_t r = b0 + grp + (int64_t)u * RPB;
+            const bool live = r < r1;
+            if (live && c0 < k) {
+                load4<T>(X + uvo(r, c0, ld), xv[u]);
 #pragma unroll
                 for (int q = 0; q < 4; ++q) xv[u][q] *= cm[q];
-                if (pass == 0) {
+            } else {
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) acc[q] += yv[u] * xv[u][q];
-                    if (lane == 0) {
-                        sq += yv[u] * yv[u];
-                        if (!isfinite(yv[u])) bad += 1.0;
-                    }
+                for (int q = 0; q < 4; ++q) xv[u][q] = 0.0;
+            }
+            yv[u] = live ? (double)y[r] : 0.0;
+        }
+        if (PASS == 1) {
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[q] += yv[u] * xv[u][q];
+                if (lane == 0) {
+                    sq += yv[u] * yv[u];
+                    if (!isfinite(yv[u])) bad += 1.0;
                 }
             }
-            if (pass == 1) {
-                double d[UNR];
+        } else {
+            double d[UNR];
 #pragma unroll
-                for (int u = 0; u < UNR; ++u)
-                    d[u] = xv[u][0] * pp[0] + xv[u][1] * pp[1] + xv[u][2] * pp[2] + xv[u][3] * pp[3];
+            for (int u = 0; u < UNR; ++u)
+                d[u] = xv[u][0] * sp1[c0] + xv[u][1] * sp1[c0 + 1] + xv[u][2] * sp1[c0 + 2] + xv[u][3] * sp1[c0 + 3];
 #pragma unroll
-                for (int o = LPR >> 1; o > 0; o >>= 1)
+            for (int o = TPR >> 1; o > 0; o >>= 1)
 #pragma unroll
-                    for (int u = 0; u < UNR; ++u) d[u] += __shfl_xor(d[u], o);
+                for (int u = 0; u < UNR; ++u) d[u] += __shfl_xor(d[u], o);
 #pragma unroll
-                for (int u = 0; u < UNR; ++u) {
-                    const bool live = base + (int64_t)u * rps < rows;
-                    const double z1 = live ? yv[u] - d[u] : 0.0;
+            for (int u = 0; u < UNR; ++u) {
+                const bool live = b0 + grp + (int64_t)u * RPB < r1;
+                const double z1 = live ? yv[u] - d[u] : 0.0;
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) acc[q] += xv[u][q] * z1;
-                    if (lane == 0) sq += z1 * z1;
-                }
+                for (int q = 0; q < 4; ++q) acc[q] += xv[u][q] * z1;
+                if (lane == 0) sq += z1 * z1;
             }
         }
+    }
 #pragma unroll
-        for (int q = 0; q < 4; ++q) red[grp * SP + c0 + q] = acc[q];
-        if (lane == 0) {
-            red[grp * SP + KC] = sq;
-            red[grp * SP + KC + 1] = bad;
-        }
-        __syncthreads();
-        double* out = pass == 0 ? out1 : out2;
-        for (int c = threadIdx.x; c < SP; c += nt) {
-            double ssum = 0.0;
-            for (int g2 = 0; g2 < rps; ++g2) ssum += red[g2 * SP + c];
-            out[c] = ssum;
-        }
-        __syncthreads();
+    for (int q = 0; q < 4; ++q) sacc[grp][c0 + q] = acc[q];
+    if (lane == 0) {
+        sacc[grp][KC] = sq;
+        sacc[grp][KC + 1] = bad;
+    }
+    __syncthreads();
+    double* part = (PASS == 1 ? rq.partials : rq.partials2) + (size_t)tile * SP;
+    for (int c = threadIdx.x; c < SP; c += kThreads) {
+        double s1 = 0.0;
+        for (int gg = 0; gg < RPB; ++gg) s1 += sacc[gg][c];
+        part[c] = s1;
     }
 }
 
@@ -304,7 +165,9 @@ __device__ inline void block_project(const T* __restrict__ X, int ld, int k, con
 template <int KC>
 struct CoreShape {
     static constexpr int NMAX = (KC < kMaxCore - 1 ? KC : kMaxCore - 1) + 1;
-    typedef JacobiShape<NMAX> J;
+    // eight lanes per pair for the 33- and 65-column cores (shorter rounds);
+    // the widest keeps four so that its FP64 core and J fit in LDS
+    typedef JacobiShape<NMAX, (KC == 32 || KC == 64) ? 8 : 4> J;
 };
 
 // dynamic LDS (doubles) of a core block of bucket KC
@@ -339,17 +202,20 @@ __global__ void __launch_bounds__(CoreShape<KC>::J::NT) k_core(const Req* __rest
     double* su = tmp + 2 * N;                      // s_u (rank-1, no J)
     double* dcol = su + N;                         // s_u . W[:, c] (rank-1, no J)
 
-    // projection sums: computed here for a row append (V is small), by the
-    // k_proj1 / k_proj2 launches for a column append (U can be large)
-    const double* src1 = rq.p;
-    const double* src2 = rq.p2;
-    if (kind == kRow) {
-        const size_t total = core_lds_doubles<KC, WITH_J>();
-        double* out1 = smem + total - 2 * (KC + 2);
-        double* out2 = out1 + (KC + 2);
-        block_project<T, KC>((const T*)rq.V[cur], ld, k, (const T*)rq.payload, rq.n, smem, out1, out2);
-        src1 = out1;
-        src2 = out2;
+    // projection sums of an append: the k_proj partials added in block order
+    const size_t total = core_lds_doubles<KC, WITH_J>();
+    double* src1 = smem + total - 2 * (KC + 2);
+    double* src2 = src1 + (KC + 2);
+    if (kind != kEntry) {
+        for (int c = tid; c < 2 * (KC + 2); c += nt) {
+            const int cc = c < KC + 2 ? c : c - (KC + 2);
+            const double* part = c < KC + 2 ? rq.partials : rq.partials2;
+            double s1 = 0.0;
+            if (cc < k || cc >= KC)
+                for (int t = 0; t < rq.proj_tiles; ++t) s1 += part[(size_t)t * (KC + 2) + cc];
+            (c < KC + 2 ? src1 : src2)[cc] = s1;
+        }
+        __syncthreads();
     }
     double pc = 0.0;
     if (kind != kEntry && tid < k) pc = src1[tid] + src2[tid];
@@ -423,7 +289,8 @@ __global__ void __launch_bounds__(CoreShape<KC>::J::NT) k_core(const Req* __rest
     }
     __syncthreads();
     // FP32 storage rounds U_K, V_K to 6e-8: columns orthogonal to 1e-10 suffice
-    const int sweeps = jacobi_block<CoreShape<KC>::NMAX, WITH_J>(W, J, N, ldw, 40, WITH_J ? 0.0 : 1e-10);
+    const int sweeps =
+        jacobi_block<CoreShape<KC>::NMAX, WITH_J, CoreShape<KC>::J::TPP>(W, J, N, ldw, 40, WITH_J ? 0.0 : 1e-10);
     jacobi_sort(W, N, ldw, sig, perm, tmp);
     if constexpr (!WITH_J) {
         if (kind == kEntry) {
