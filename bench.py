@@ -28,6 +28,7 @@ METRIC = "batched rank-k updates/sec + p99 tick latency vs plain path at rel err
 HBM_PEAK_GBS = 8000.0
 K_FACTORS = 5
 SEED = 3
+PROF_TICKS = 20      # extra profiled ticks (per-launch times) after the comparison
 
 
 def log(*a):
@@ -48,6 +49,11 @@ def stream_params(nstreams, seed=SEED):
 def rot_bytes(m, n, k, esz):
     # rotation of one row append: read + write U (m x k) and V (n x k), read x, write the A row
     return esz * (2 * m * k + 2 * n * k) + n * (esz + esz)
+
+
+def rot_u_bytes(m, k, esz):
+    # U's rotation in a row append: read + write U (m x k)
+    return esz * 2 * m * k
 
 
 def tick_bytes(m, n, k, esz):
@@ -113,6 +119,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-pipeline", action="store_true", help="join every tick's U rotations before the next tick")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the streams are independent and would shard by stream across "
@@ -147,7 +154,8 @@ def main():
             sid64.append(eng64.init(A0, k, "fp64", m_cap=m0 + T, n_cap=n0, refresh_iters=args.refresh_iters,
                                     stream=dev_stream))
             U, S, V = eng64.factors(sid64[-1], stream=dev_stream)
-            sid32.append(eng32.init_from_factors(A0, U, S, V, "fp32", m_cap=m0 + T, n_cap=n0, stream=dev_stream))
+            sid32.append(eng32.init_from_factors(A0, U, S, V, "fp32", m_cap=m0 + T + PROF_TICKS, n_cap=n0,
+                                                 stream=dev_stream))
             if s % 64 == 63:
                 log("  init %d/%d streams (%.1fs)" % (s + 1, len(params), time.perf_counter() - t_init))
     del tmp
@@ -166,45 +174,32 @@ def main():
     log("init %.1fs; payloads ready" % init_s)
 
     # ---------------------------------------------------- chosen form: batched FP32
+    eng32.set_pipelining(not args.no_pipeline)
+    tune = eng32.autotune(stream=dev_stream)
+    log("rotation autotune (bucket: variant): %s" % {kc: v for kc, (v, _) in tune.items()})
+    rot_lane = torch.cuda.ExternalStream(eng32.rotation_stream())
     for t in range(W):
         eng32.tick_raw(reqs[t], stream=dev_stream)
+    eng32.sync(stream=dev_stream)
     torch.cuda.synchronize()
-    eng32.profile(True)
+    # per tick: start on the caller's stream, end when the engine's rotation
+    # stream (which finishes every tick) has passed it
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for q in range(K):
         evs[q][0].record(dev_stream)
         eng32.tick_raw(reqs[W + q], stream=dev_stream)
-        evs[q][1].record(dev_stream)
+        evs[q][1].record(rot_lane)
+    eng32.sync(stream=dev_stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    eng32.profile(False)
     tick_ms = [a.elapsed_time(b) for a, b in evs]
     value = len(params) * K / wall
-    prof = eng32.profile_read()
-    log("batched FP32: %.0f updates/s, tick p50 %.3f ms p99 %.3f ms" % (value, pctl(tick_ms, 50), pctl(tick_ms, 99)))
+    log("batched FP32: %.0f updates/s, tick latency p50 %.3f ms p99 %.3f ms" % (value, pctl(tick_ms, 50),
+                                                                                 pctl(tick_ms, 99)))
 
-    # roofline of the dominant kernel: the rotation launch of the widest bucket
-    by_launch = {}
-    for r in prof:
-        by_launch.setdefault((r["phase"], r["kc"]), []).append(r["ms"])
-    phase_ms = {}
-    for (ph, kc), v in by_launch.items():
-        phase_ms.setdefault(ph, 0.0)
-        phase_ms[ph] += float(np.sum(v)) / K
-    kdom = max(kc for (ph, kc) in by_launch if ph == 3)
-    dom_ms = float(np.mean(by_launch[(3, kdom)]))
-    mid = W + (K - 1) / 2.0
-    bucket = lambda k: 8 if k <= 8 else 16 if k <= 16 else 32 if k <= 32 else 64 if k <= 64 else 128
-    dom_bytes = sum(rot_bytes(m0 + mid, n0, k, 4) for (m0, n0, k) in params if bucket(k) == kdom)
-    all_tick_bytes = sum(tick_bytes(m0 + mid, n0, k, 4) for (m0, n0, k) in params)
-    achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_rotate<float,%d>" % kdom, "launch_ms": round(dom_ms, 4),
-                "bytes_per_launch": int(dom_bytes)}
-    tick_gbs = all_tick_bytes / (float(np.mean(tick_ms)) * 1e-3) / 1e9
+
 
     # ------------------------------------------------------- plain form: FP64, one stream per launch
     plain = None
@@ -238,6 +233,40 @@ def main():
         err["streams_compared"] = int(len(pick))
         log("FP32 vs FP64 after %d ticks: %s" % (T, err))
 
+    # per-launch GPU times from a separate profiled pass of PROF_TICKS more
+    # ticks (after the comparison; the events around each launch add a little
+    # time of their own)
+    eng32.profile(True)
+    for q in range(PROF_TICKS):
+        eng32.tick_raw(reqs[W + q % K], stream=dev_stream)
+    eng32.sync(stream=dev_stream)
+    torch.cuda.synchronize()
+    eng32.profile(False)
+    prof = eng32.profile_read()
+    Kp = PROF_TICKS
+    # roofline of the dominant kernel: the rotation launch of the widest bucket
+    by_launch = {}
+    for r in prof:
+        by_launch.setdefault((r["phase"], r["kc"]), []).append(r["ms"])
+    phase_ms = {}
+    for (ph, kc), v in by_launch.items():
+        phase_ms.setdefault(ph, 0.0)
+        phase_ms[ph] += float(np.sum(v)) / Kp
+    # dominant kernel: the U rotation of the widest bucket (HBM-bound)
+    kdom = max(kc for (ph, kc) in by_launch if ph == 3)
+    dom_ms = float(np.mean(by_launch[(3, kdom)]))
+    mid = W + K + (Kp - 1) / 2.0
+    bucket = lambda k: 8 if k <= 8 else 16 if k <= 16 else 32 if k <= 32 else 64 if k <= 64 else 128
+    dom_bytes = sum(rot_u_bytes(m0 + mid, k, 4) for (m0, n0, k) in params if bucket(k) == kdom)
+    mid_all = W + (K - 1) / 2.0
+    all_tick_bytes = sum(tick_bytes(m0 + mid_all, n0, k, 4) for (m0, n0, k) in params)
+    achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_rotate_mfma_t<%d> (U rotation, variant %d)" % (kdom, tune[kdom][0] if kdom in tune else -1),
+                "launch_ms": round(dom_ms, 4), "bytes_per_launch": int(dom_bytes)}
+    tick_gbs = all_tick_bytes / (wall / K) / 1e9
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(params, args.cpu_seconds, torch)
@@ -250,7 +279,7 @@ def main():
         "n_gpus": 1,
         "steps": K,
         "warmup": W,
-        "ms_per_step": round(float(np.mean(tick_ms)), 4),
+        "ms_per_step": round(wall / K * 1e3, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -268,7 +297,8 @@ def main():
         "p99_vs_plain": round(plain["p99_tick_ms"] / pctl(tick_ms, 99), 2) if plain else None,
         "error_vs_fp64": err,
         "tick_algorithmic_GBps": round(tick_gbs, 1),
-        "phase_ms_per_tick": {["proj1", "proj2", "core", "rotate"][p]: round(v, 4) for p, v in sorted(phase_ms.items())},
+        "phase_ms_per_tick": {["proj1", "proj2", "core", "rotate_U", "rotate_V"][p]: round(v, 4)
+                              for p, v in sorted(phase_ms.items())},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "init_s": round(init_s, 1),

@@ -226,13 +226,36 @@ isvd_status isvd_release(isvd_engine* eng, isvd_id id);
  * stream's storage dtype.  Validation happens for all requests before any
  * work is enqueued; on error nothing is applied.  Does not wait for the
  * device unless a policy needs device metrics.
+ * Pipelining: the U rotations run on the engine's rotation stream.  When
+ * every request is a row append of a stream without a refresh policy, they
+ * may still run after hip_stream has passed the call, overlapping the next
+ * tick's projections and cores; every call that reads or replaces stream
+ * state (metrics, factors, matrix, refresh, single updates, a tick that
+ * reads U) first orders its stream after them, and isvd_sync does so
+ * explicitly.  Otherwise the tick joins them into hip_stream before
+ * returning.  Row payloads are not read by U rotations.
  * Errors: STATE, SHAPE, RANGE, CAPACITY, INVAL (duplicate stream, dtype). */
 isvd_status isvd_tick(isvd_engine* eng, int32_t count, const isvd_request* reqs, void* hip_stream);
+
+/* Order hip_stream after every U rotation still pending on the engine's
+ * rotation stream (see isvd_tick).  Does not wait on the host. */
+isvd_status isvd_sync(isvd_engine* eng, void* hip_stream);
+
+/* enable != 0 (the default): row-append ticks may leave their U rotations
+ * pending (see isvd_tick) for throughput; 0: every tick joins them before
+ * returning, for the shortest tick latency. */
+isvd_status isvd_set_pipelining(isvd_engine* eng, int32_t enable);
+
+/* The engine's rotation stream (a hipStream_t), e.g. to record an event
+ * after the last tick's work: everything of a tick is done when that stream
+ * has passed it. */
+isvd_status isvd_rotation_stream(isvd_engine* eng, void** out);
 
 /* GPU time of one kernel launch of the update sequence, collected while
  * profiling is on (HIP events recorded around the launch on its stream). */
 typedef struct {
-    int32_t phase;          /* 0 projection pass 1, 1 projection pass 2, 2 core, 3 rotation */
+    int32_t phase;          /* 0 projection pass 1, 1 projection pass 2, 2 core,
+                               3 rotation of U, 4 rotation of V */
     int32_t kc;             /* rank bucket of the launch (capacity of its U / V rows) */
     int32_t fp64;           /* 1 if the launch works on FP64 storage */
     int32_t nreq;           /* requests served by the launch */

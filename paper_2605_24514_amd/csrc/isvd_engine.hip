@@ -72,6 +72,7 @@ int bucket_for(int kmax) {
 // ------------------------------------------------------------------ streams
 struct Layout {
     size_t hdr, rs, S, p, partials, partials2, QU, QV, stage, U0, U1, V0, V1, Uref, TM, TH, TP, A, total;
+    size_t rs_b, p_b, q_b;   // bytes of one copy of the double-buffered rs, p and QU / QV
 };
 
 struct Stream {
@@ -85,9 +86,15 @@ struct Stream {
     char* base = nullptr;
     Layout L{};
     DevHeader* hdr = nullptr;
-    ReqScratch* rs = nullptr;
-    double *S = nullptr, *p = nullptr, *partials = nullptr, *partials2 = nullptr;
-    void *QU = nullptr, *QV = nullptr, *stage = nullptr, *A = nullptr, *Uref = nullptr;
+    // per-update scratch read by the rotations, double-buffered by the parity
+    // of the stream's update count: a U rotation may still run while the
+    // stream's next core writes the other copy
+    ReqScratch* rs[2] = {nullptr, nullptr};
+    double* p[2] = {nullptr, nullptr};
+    void* QU[2] = {nullptr, nullptr};
+    void* QV[2] = {nullptr, nullptr};
+    double *S = nullptr, *partials = nullptr, *partials2 = nullptr;
+    void *stage = nullptr, *A = nullptr, *Uref = nullptr;
     double *TM = nullptr, *TH = nullptr, *TP = nullptr;   // angle trackers M, H and column-pass sums
     void* U[2] = {nullptr, nullptr};
     void* V[2] = {nullptr, nullptr};
@@ -111,13 +118,16 @@ Layout make_layout(const isvd_config& c, int esz, int kc, int64_t* ntiles_max) {
     const int64_t nt = cdiv(mx, kProjTile);
     *ntiles_max = nt;
     L.hdr = take(sizeof(DevHeader));
-    L.rs = take(sizeof(ReqScratch));
+    L.rs_b = align_up(sizeof(ReqScratch), 256);
+    L.rs = take(2 * L.rs_b);
     L.S = take(sizeof(double) * (kc + 2));
-    L.p = take(sizeof(double) * (kc + 4));
+    L.p_b = align_up(sizeof(double) * (kc + 4), 256);
+    L.p = take(2 * L.p_b);
     L.partials = take(sizeof(double) * (size_t)nt * (kc + 2));
     L.partials2 = take(sizeof(double) * (size_t)nt * (kc + 2));
-    L.QU = take((size_t)esz * (kc + 1) * kc);
-    L.QV = take((size_t)esz * (kc + 1) * kc);
+    L.q_b = align_up((size_t)esz * (kc + 1) * kc, 256);
+    L.QU = take(2 * L.q_b);
+    L.QV = take(2 * L.q_b);
     L.stage = take((size_t)esz * mx);
     // bases hold whole 16-row tiles
     L.U0 = take((size_t)esz * round16(c.m_cap) * kc);
@@ -152,8 +162,10 @@ struct Group {
     std::vector<Req> all;      // core + rotation list
     std::vector<Req> proj;     // row / column appends
     std::vector<int> pre_proj; // block prefix of the projection list (size proj+1)
-    std::vector<int> pre_rot;  // block prefix of the rotation list (size all+1)
-    size_t off_all = 0, off_proj = 0, off_pp = 0, off_pr = 0;
+    std::vector<int> pre_rot;  // block prefix of the rotation list, U and V (size all+1)
+    std::vector<int> pre_rotU; // ... U tiles only
+    std::vector<int> pre_rotV; // ... V tiles only
+    size_t off_all = 0, off_proj = 0, off_pp = 0, off_pr = 0, off_pru = 0, off_prv = 0;
     int core_lds_n = 0;
 };
 
@@ -170,12 +182,29 @@ struct LaunchRec {
 struct isvd_engine {
     int device = 0;
     bool profiling = false;
-    // side stream (default priority) so that rank buckets of one tick run
-    // concurrently: the long cores of the widest bucket overlap the other
-    // buckets' work
-    std::vector<hipStream_t> side;
-    std::vector<hipEvent_t> join;
-    hipEvent_t fork = nullptr;
+    // Rotation lane (a stream of default priority): the U rotations of a
+    // tick run there, each after its group's core, while the caller's
+    // stream goes on with the next group and -- for ticks of row appends
+    // only -- with the next tick's projections and cores.  The next core of
+    // a stream needs V, Sigma and the header, never U, and writes the other
+    // copy of the double-buffered scratch.  rot_pending: the lane has work
+    // that no caller stream waits for yet; every call that reads or replaces
+    // U first orders the caller's stream after it (join).
+    hipStream_t rot_lane = nullptr;
+    // second update lane: the rank buckets up to 32 run their projections,
+    // cores and V rotations there, concurrently with the wider buckets on the
+    // caller's stream (the assignment depends on the bucket only, so a
+    // stream's updates stay on one lane)
+    hipStream_t lane_b = nullptr;
+    hipEvent_t ev_fork = nullptr;      // the tick's request upload is done
+    hipEvent_t ev_b_end = nullptr;     // lane b's part of a tick is done
+    std::vector<hipEvent_t> ev_core;   // per group of a tick: its core is done
+    hipEvent_t ev_main = nullptr;      // the caller-stream part of a tick is done
+    hipEvent_t ev_rot = nullptr;       // join point of the rotation lane
+    hipEvent_t ev_tick_end[2] = {nullptr, nullptr};   // by tick parity
+    uint64_t ticks = 0;
+    bool rot_pending = false;
+    bool pipelining = true;            // isvd_set_pipelining
     std::vector<LaunchRec> prof;
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
@@ -251,7 +280,6 @@ isvd_status launch_group_phase(const Group& g, const char* dev, int phase, hipSt
     const Req* all = reinterpret_cast<const Req*>(dev + g.off_all);
     const Req* proj = reinterpret_cast<const Req*>(dev + g.off_proj);
     const int* pp = reinterpret_cast<const int*>(dev + g.off_pp);
-    const int* pr = reinterpret_cast<const int*>(dev + g.off_pr);
     const int np = (int)g.proj.size(), na = (int)g.all.size();
     if (phase == 0 && np > 0) {
         k_proj<T, KC, 1><<<g.pre_proj[np], kThreads, 0, st>>>(proj, pp, np);
@@ -260,21 +288,25 @@ isvd_status launch_group_phase(const Group& g, const char* dev, int phase, hipSt
     } else if (phase == 2 && na > 0) {
         size_t lds = sizeof(double) * core_lds_doubles<KC, sizeof(T) == 8>();
         k_core<T, KC><<<na, CoreShape<KC>::J::NT, lds, st>>>(all);
-    } else if (phase == 3 && na > 0) {
-        const int nb = g.pre_rot[na];
+    } else if (phase >= 3 && na > 0) {
+        // 3: U tiles, 4: V tiles, 5: both
+        const int part = phase == 3 ? 1 : phase == 4 ? 2 : 0;
+        const int* pr = reinterpret_cast<const int*>(dev + (part == 1 ? g.off_pru : part == 2 ? g.off_prv : g.off_pr));
+        const int nb = (part == 1 ? g.pre_rotU : part == 2 ? g.pre_rotV : g.pre_rot)[na];
+        if (nb == 0) return ISVD_OK;
         if constexpr (sizeof(T) == 4 && KC <= 64) {
             static_assert(kRotVariants == 5, "variant dispatch");
             switch (g.var) {
-                case 0: k_rotate_mfma_t<KC, 256, 1, true><<<nb, kThreads, 0, st>>>(all, pr, na); break;
-                case 2: k_rotate_mfma_t<KC, 1024, 1, true><<<nb, kThreads, 0, st>>>(all, pr, na); break;
-                case 3: k_rotate_mfma_t<KC, 1024, 2, false><<<nb, kThreads, 0, st>>>(all, pr, na); break;
-                case 4: k_rotate_mfma_t<KC, 2048, 2, false><<<nb, kThreads, 0, st>>>(all, pr, na); break;
-                default: k_rotate_mfma_t<KC, 512, 1, true><<<nb, kThreads, 0, st>>>(all, pr, na); break;
+                case 0: k_rotate_mfma_t<KC, 256, 1, true><<<nb, kThreads, 0, st>>>(all, pr, na, part); break;
+                case 2: k_rotate_mfma_t<KC, 1024, 1, true><<<nb, kThreads, 0, st>>>(all, pr, na, part); break;
+                case 3: k_rotate_mfma_t<KC, 1024, 2, false><<<nb, kThreads, 0, st>>>(all, pr, na, part); break;
+                case 4: k_rotate_mfma_t<KC, 2048, 2, false><<<nb, kThreads, 0, st>>>(all, pr, na, part); break;
+                default: k_rotate_mfma_t<KC, 512, 1, true><<<nb, kThreads, 0, st>>>(all, pr, na, part); break;
             }
         } else if constexpr (sizeof(T) == 4) {
-            k_rotate_mfma<KC><<<nb, kThreads, 0, st>>>(all, pr, na);
+            k_rotate_mfma<KC><<<nb, kThreads, 0, st>>>(all, pr, na, part);
         } else {
-            k_rotate<T, KC><<<nb, kThreads, 0, st>>>(all, pr, na);
+            k_rotate<T, KC><<<nb, kThreads, 0, st>>>(all, pr, na, part);
         }
     }
     HIP_TRY(hipGetLastError());
@@ -357,19 +389,20 @@ Req make_req(const isvd_engine* e, Stream& s, int kind, const void* payload, int
     // appends: projection passes over row tiles of V (row) or U (column)
     r.proj_tiles = kind == kCol ? (int)cdiv(s.m, kProjTile) : kind == kRow ? (int)cdiv(s.n, kProjTile) : 0;
     r.rot_tiles_u = (int)cdiv(s.m, rows_for(e, s.kc, s.esz == 8));
+    const int par = (int)(s.t & 1);
     r.hdr = s.hdr;
-    r.rs = s.rs;
+    r.rs = s.rs[par];
     r.A = s.A;
     r.U[0] = s.U[0];
     r.U[1] = s.U[1];
     r.V[0] = s.V[0];
     r.V[1] = s.V[1];
     r.S = s.S;
-    r.p = s.p;
+    r.p = s.p[par];
     r.partials = s.partials;
     r.partials2 = s.partials2;
-    r.QU = s.QU;
-    r.QV = s.QV;
+    r.QU = s.QU[par];
+    r.QV = s.QV[par];
     r.payload = payload;
     return r;
 }
@@ -386,8 +419,63 @@ isvd_status next_event(isvd_engine* e, hipEvent_t* out) {
     return ISVD_OK;
 }
 
-// Lay out groups in a slot, upload, and launch the four phases.
-isvd_status run_groups(isvd_engine* e, std::vector<Group>& groups, hipStream_t st) {
+isvd_status ensure_lanes(isvd_engine* e) {
+    if (e->rot_lane) return ISVD_OK;
+    HIP_TRY(hipStreamCreateWithFlags(&e->rot_lane, hipStreamNonBlocking));
+    HIP_TRY(hipStreamCreateWithFlags(&e->lane_b, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&e->ev_fork, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&e->ev_b_end, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&e->ev_main, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&e->ev_rot, hipEventDisableTiming));
+    for (int q = 0; q < 2; ++q) HIP_TRY(hipEventCreateWithFlags(&e->ev_tick_end[q], hipEventDisableTiming));
+    return ISVD_OK;
+}
+
+// Order `st` after everything queued on the rotation lane.
+isvd_status join(isvd_engine* e, hipStream_t st) {
+    if (!e->rot_pending) return ISVD_OK;
+    HIP_TRY(hipEventRecord(e->ev_rot, e->rot_lane));
+    HIP_TRY(hipStreamWaitEvent(st, e->ev_rot, 0));
+    e->rot_pending = false;
+    return ISVD_OK;
+}
+
+isvd_status launch_recorded(isvd_engine* e, const Group& g, const char* dev, int phase, hipStream_t gs) {
+    LaunchRec rec{};
+    if (e->profiling) {
+        ST_TRY(next_event(e, &rec.b));
+        ST_TRY(next_event(e, &rec.e));
+        HIP_TRY(hipEventRecord(rec.b, gs));
+    }
+    ST_TRY(launch_phase(g, dev, phase, gs));
+    if (e->profiling) {
+        HIP_TRY(hipEventRecord(rec.e, gs));
+        const int np = (int)g.proj.size(), na = (int)g.all.size();
+        rec.phase = phase;
+        rec.kc = g.kc;
+        rec.fp64 = g.fp64 ? 1 : 0;
+        rec.nreq = phase < 2 ? np : na;
+        rec.blocks = phase < 2 ? g.pre_proj[np] : phase == 2 ? na : phase == 3 ? g.pre_rotU[na] : g.pre_rotV[na];
+        e->prof.push_back(rec);
+    }
+    return ISVD_OK;
+}
+
+// Lay out groups in a slot, upload, and launch one tick (or one immediate
+// update).  Per group, on its update lane (the caller's stream for buckets
+// of 64 and wider, lane b for the others): the two projection passes, the
+// core, then V's rotation; on the rotation lane, after the group's core,
+// U's rotation (lane b's groups first: their cores finish earlier).
+// pipelined: the caller's stream is not made to wait for the U rotations (a
+// later join does); otherwise it is joined at the end.  The rotation lane
+// never runs more than one tick behind: a tick's first launch waits for the
+// lane's end of the tick before last, whose scratch copy this tick's cores
+// overwrite.
+isvd_status run_groups(isvd_engine* e, std::vector<Group>& groups, hipStream_t st, bool pipelined) {
+    ST_TRY(ensure_lanes(e));
+    std::sort(groups.begin(), groups.end(), [](const Group& a, const Group& b) {
+        return a.kc != b.kc ? a.kc > b.kc : (a.fp64 && !b.fp64);
+    });
     size_t off = 0;
     auto take = [&](size_t b) {
         size_t o = off;
@@ -397,96 +485,84 @@ isvd_status run_groups(isvd_engine* e, std::vector<Group>& groups, hipStream_t s
     for (Group& g : groups) {
         g.pre_proj.assign(g.proj.size() + 1, 0);
         for (size_t q = 0; q < g.proj.size(); ++q) g.pre_proj[q + 1] = g.pre_proj[q] + g.proj[q].proj_tiles;
-        g.pre_rot.assign(g.all.size() + 1, 0);
-        for (size_t q = 0; q < g.all.size(); ++q) g.pre_rot[q + 1] = g.pre_rot[q] + rot_tiles(g.all[q], g.rows);
-        g.off_all = take(sizeof(Req) * g.all.size());
+        const size_t na = g.all.size();
+        g.pre_rot.assign(na + 1, 0);
+        g.pre_rotU.assign(na + 1, 0);
+        g.pre_rotV.assign(na + 1, 0);
+        for (size_t q = 0; q < na; ++q) {
+            const int tu = g.all[q].rot_tiles_u, tv = (int)cdiv(g.all[q].n, g.rows);
+            g.pre_rot[q + 1] = g.pre_rot[q] + tu + tv;
+            g.pre_rotU[q + 1] = g.pre_rotU[q] + tu;
+            g.pre_rotV[q + 1] = g.pre_rotV[q] + tv;
+        }
+        g.off_all = take(sizeof(Req) * na);
         g.off_proj = take(sizeof(Req) * g.proj.size());
         g.off_pp = take(sizeof(int) * g.pre_proj.size());
-        g.off_pr = take(sizeof(int) * g.pre_rot.size());
+        g.off_pr = take(sizeof(int) * (na + 1));
+        g.off_pru = take(sizeof(int) * (na + 1));
+        g.off_prv = take(sizeof(int) * (na + 1));
         g.core_lds_n = std::min(g.kc, 96) + 1;
     }
     Slot* slot = nullptr;
     ST_TRY(acquire_slot(e, off, &slot));
     for (Group& g : groups) {
-        if (!g.all.empty()) memcpy(slot->host + g.off_all, g.all.data(), sizeof(Req) * g.all.size());
+        const size_t na = g.all.size();
+        if (na) memcpy(slot->host + g.off_all, g.all.data(), sizeof(Req) * na);
         if (!g.proj.empty()) memcpy(slot->host + g.off_proj, g.proj.data(), sizeof(Req) * g.proj.size());
         memcpy(slot->host + g.off_pp, g.pre_proj.data(), sizeof(int) * g.pre_proj.size());
-        memcpy(slot->host + g.off_pr, g.pre_rot.data(), sizeof(int) * g.pre_rot.size());
+        memcpy(slot->host + g.off_pr, g.pre_rot.data(), sizeof(int) * (na + 1));
+        memcpy(slot->host + g.off_pru, g.pre_rotU.data(), sizeof(int) * (na + 1));
+        memcpy(slot->host + g.off_prv, g.pre_rotV.data(), sizeof(int) * (na + 1));
     }
+    if (e->ticks >= 2) HIP_TRY(hipStreamWaitEvent(st, e->ev_tick_end[e->ticks & 1], 0));
     HIP_TRY(hipMemcpyAsync(slot->dev, slot->host, off, hipMemcpyHostToDevice, st));
-    // Two lanes: the caller's stream and one side stream (a process gets few
-    // hardware queues; more streams would share them and serialise).  Groups
-    // go to the lane with less estimated work, largest first; a lane runs its
-    // groups' phases in order.
-    const bool fan = groups.size() > 1;
-    std::vector<int> lane_of(groups.size(), 0);
-    if (fan) {
-        std::vector<double> cost(groups.size(), 0.0);
+    while (e->ev_core.size() < groups.size()) {
+        hipEvent_t ev;
+        HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        e->ev_core.push_back(ev);
+    }
+    bool use_b = false;
+    for (const Group& g : groups) use_b = use_b || g.kc < 64;
+    if (use_b) {
+        HIP_TRY(hipEventRecord(e->ev_fork, st));
+        HIP_TRY(hipStreamWaitEvent(e->lane_b, e->ev_fork, 0));
+    }
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+        const Group& g = groups[gi];
+        hipStream_t ln = g.kc >= 64 ? st : e->lane_b;
+        for (int phase = 0; phase < 3; ++phase) ST_TRY(launch_recorded(e, g, slot->dev, phase, ln));
+        HIP_TRY(hipEventRecord(e->ev_core[gi], ln));
+        ST_TRY(launch_recorded(e, g, slot->dev, 4, ln));
+    }
+    for (int pass = 0; pass < 2; ++pass)
         for (size_t gi = 0; gi < groups.size(); ++gi) {
-            const double kc = groups[gi].kc;
-            for (const Req& r : groups[gi].all)
-                cost[gi] += 2e-12 * kc * kc * kc * 64.0 + 1.0e-13 * kc * (double)(r.m + r.n);
+            const Group& g = groups[gi];
+            if ((g.kc < 64) != (pass == 0)) continue;
+            HIP_TRY(hipStreamWaitEvent(e->rot_lane, e->ev_core[gi], 0));
+            ST_TRY(launch_recorded(e, g, slot->dev, 3, e->rot_lane));
         }
-        std::vector<size_t> order(groups.size());
-        for (size_t gi = 0; gi < order.size(); ++gi) order[gi] = gi;
-        std::sort(order.begin(), order.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
-        double load[2] = {0.0, 0.0};
-        for (size_t gi : order) {
-            const int ln = load[0] <= load[1] ? 0 : 1;
-            lane_of[gi] = ln;
-            load[ln] += cost[gi];
-        }
-        if (e->side.empty()) {
-            hipStream_t sst;
-            hipEvent_t ev;
-            HIP_TRY(hipStreamCreateWithFlags(&sst, hipStreamNonBlocking));
-            HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-            e->side.push_back(sst);
-            e->join.push_back(ev);
-        }
-        if (!e->fork) HIP_TRY(hipEventCreateWithFlags(&e->fork, hipEventDisableTiming));
-        HIP_TRY(hipEventRecord(e->fork, st));
-        HIP_TRY(hipStreamWaitEvent(e->side[0], e->fork, 0));
+    // the tick ends on the rotation lane once every lane is through it
+    HIP_TRY(hipEventRecord(e->ev_main, st));
+    HIP_TRY(hipStreamWaitEvent(e->rot_lane, e->ev_main, 0));
+    if (use_b) {
+        HIP_TRY(hipEventRecord(e->ev_b_end, e->lane_b));
+        HIP_TRY(hipStreamWaitEvent(e->rot_lane, e->ev_b_end, 0));
     }
-    for (int phase = 0; phase < 4; ++phase) {
-        for (size_t gi = 0; gi < groups.size(); ++gi) {
-            Group& g = groups[gi];
-            hipStream_t gs = lane_of[gi] ? e->side[0] : st;
-            const int np = (int)g.proj.size(), na = (int)g.all.size();
-            const int nreq = phase < 2 ? np : na;
-            if (nreq == 0) continue;
-            LaunchRec rec{};
-            if (e->profiling) {
-                ST_TRY(next_event(e, &rec.b));
-                ST_TRY(next_event(e, &rec.e));
-                HIP_TRY(hipEventRecord(rec.b, gs));
-            }
-            ST_TRY(launch_phase(g, slot->dev, phase, gs));
-            if (e->profiling) {
-                HIP_TRY(hipEventRecord(rec.e, gs));
-                rec.phase = phase;
-                rec.kc = g.kc;
-                rec.fp64 = g.fp64 ? 1 : 0;
-                rec.nreq = nreq;
-                rec.blocks = phase < 2 ? g.pre_proj[np] : phase == 2 ? na : g.pre_rot[na];
-                e->prof.push_back(rec);
-            }
-        }
-    }
-    if (fan) {
-        HIP_TRY(hipEventRecord(e->join[0], e->side[0]));
-        HIP_TRY(hipStreamWaitEvent(st, e->join[0], 0));
-    }
-    HIP_TRY(hipEventRecord(slot->ev, st));
+    HIP_TRY(hipEventRecord(slot->ev, e->rot_lane));
     slot->used = true;
+    HIP_TRY(hipEventRecord(e->ev_tick_end[e->ticks & 1], e->rot_lane));
+    e->ticks += 1;
+    e->rot_pending = true;
+    if (!pipelined) ST_TRY(join(e, st));
     return ISVD_OK;
 }
 
 // Tracker work of the angle-policy streams of one launch sequence.
 Track make_track(const Stream& s, int kind, const void* payload) {
+    const int par = (int)(s.t & 1);
     Track t{};
     t.hdr = s.hdr;
-    t.rs = s.rs;
+    t.rs = s.rs[par];
     t.kind = kind;
     t.scope = s.cfg.policy.angle_scope;
     t.tiles = kind == kCol ? (int)std::max<int64_t>(1, cdiv(s.m, kTrackRows)) : 0;
@@ -494,8 +570,8 @@ Track make_track(const Stream& s, int kind, const void* payload) {
     t.Uref = s.Uref;
     t.U[0] = s.U[0];
     t.U[1] = s.U[1];
-    t.QU = s.QU;
-    t.p = s.p;
+    t.QU = s.QU[par];
+    t.p = s.p[par];
     t.S = s.S;
     t.payload = payload;
     t.M = s.TM;
@@ -1076,8 +1152,9 @@ isvd_status single_update(isvd_engine* e, Stream& s, int kind, const void* paylo
     Req r = make_req(e, s, kind, payload, i, j, delta, k_keep_for(s, kind));
     g.all.push_back(r);
     if (kind != kEntry) g.proj.push_back(r);
+    ST_TRY(join(e, st));
     HIP_TRY(hipEventRecord(s.ev_u0, st));
-    ST_TRY(run_groups(e, groups, st));
+    ST_TRY(run_groups(e, groups, st, false));
     if (s.angle) ST_TRY(run_tracks(e, {make_track(s, kind, payload)}, {(char)(s.esz == 8)}, st));
     HIP_TRY(hipEventRecord(s.ev_u1, st));
     s.have_update_time = true;
@@ -1169,9 +1246,15 @@ isvd_status isvd_engine_destroy(isvd_engine* e) {
     if (e->mws) (void)hipFree(e->mws);
     if (e->hdrs_host) (void)hipHostFree(e->hdrs_host);
     for (hipEvent_t ev : e->ev_pool) (void)hipEventDestroy(ev);
-    for (hipStream_t sst : e->side) (void)hipStreamDestroy(sst);
-    for (hipEvent_t ev : e->join) (void)hipEventDestroy(ev);
-    if (e->fork) (void)hipEventDestroy(e->fork);
+    for (hipEvent_t ev : e->ev_core) (void)hipEventDestroy(ev);
+    if (e->ev_main) (void)hipEventDestroy(e->ev_main);
+    if (e->ev_fork) (void)hipEventDestroy(e->ev_fork);
+    if (e->ev_b_end) (void)hipEventDestroy(e->ev_b_end);
+    if (e->lane_b) (void)hipStreamDestroy(e->lane_b);
+    if (e->ev_rot) (void)hipEventDestroy(e->ev_rot);
+    for (hipEvent_t ev : e->ev_tick_end)
+        if (ev) (void)hipEventDestroy(ev);
+    if (e->rot_lane) (void)hipStreamDestroy(e->rot_lane);
     delete e;
     return ISVD_OK;
 }
@@ -1185,6 +1268,26 @@ isvd_status isvd_profile(isvd_engine* e, int32_t enable) {
         e->ev_used = 0;
     }
     e->profiling = enable != 0;
+    return ISVD_OK;
+}
+
+isvd_status isvd_sync(isvd_engine* e, void* hip_stream) {
+    if (!e) return fail(ISVD_E_INVAL, "null engine");
+    ST_TRY(ensure_device(e));
+    return join(e, (hipStream_t)hip_stream);
+}
+
+isvd_status isvd_set_pipelining(isvd_engine* e, int32_t enable) {
+    if (!e) return fail(ISVD_E_INVAL, "null engine");
+    e->pipelining = enable != 0;
+    return ISVD_OK;
+}
+
+isvd_status isvd_rotation_stream(isvd_engine* e, void** out) {
+    if (!e || !out) return fail(ISVD_E_INVAL, "null argument");
+    ST_TRY(ensure_device(e));
+    ST_TRY(ensure_lanes(e));
+    *out = (void*)e->rot_lane;
     return ISVD_OK;
 }
 
@@ -1272,9 +1375,9 @@ isvd_status isvd_autotune(isvd_engine* e, void* hip_stream, int32_t* variant_out
                 return fail(ISVD_E_DEVICE, "autotune launch set-up");
             }
             const int reps = 6;
-            for (int w = 0; w < 2; ++w) rc = launch_phase(g, slot->dev, 3, st);
+            for (int w = 0; w < 2; ++w) rc = launch_phase(g, slot->dev, 5, st);
             (void)hipEventRecord(e0, st);
-            for (int w = 0; w < reps && rc == ISVD_OK; ++w) rc = launch_phase(g, slot->dev, 3, st);
+            for (int w = 0; w < reps && rc == ISVD_OK; ++w) rc = launch_phase(g, slot->dev, 5, st);
             (void)hipEventRecord(e1, st);
             (void)hipEventRecord(slot->ev, st);
             slot->used = true;
@@ -1388,13 +1491,15 @@ static isvd_status init_common(isvd_engine* e, const isvd_config* cfg, const voi
     e->used += s->L.total;
     char* b = s->base;
     s->hdr = (DevHeader*)(b + s->L.hdr);
-    s->rs = (ReqScratch*)(b + s->L.rs);
+    for (int q = 0; q < 2; ++q) {
+        s->rs[q] = (ReqScratch*)(b + s->L.rs + q * s->L.rs_b);
+        s->p[q] = (double*)(b + s->L.p + q * s->L.p_b);
+        s->QU[q] = b + s->L.QU + q * s->L.q_b;
+        s->QV[q] = b + s->L.QV + q * s->L.q_b;
+    }
     s->S = (double*)(b + s->L.S);
-    s->p = (double*)(b + s->L.p);
     s->partials = (double*)(b + s->L.partials);
     s->partials2 = (double*)(b + s->L.partials2);
-    s->QU = b + s->L.QU;
-    s->QV = b + s->L.QV;
     s->stage = b + s->L.stage;
     s->U[0] = b + s->L.U0;
     s->U[1] = b + s->L.U1;
@@ -1527,6 +1632,7 @@ isvd_status isvd_refresh(isvd_engine* e, isvd_id id, int32_t store_reference, vo
     Stream* s = nullptr;
     ST_TRY(get_stream(e, id, &s));
     ST_TRY(ensure_device(e));
+    ST_TRY(join(e, (hipStream_t)hip_stream));
     return do_refresh(e, *s, false, store_reference != 0, (hipStream_t)hip_stream);
 }
 
@@ -1536,6 +1642,7 @@ isvd_status isvd_metrics(isvd_engine* e, isvd_id id, int32_t compute_exact, void
     if (!out) return fail(ISVD_E_INVAL, "null output");
     ST_TRY(ensure_device(e));
     hipStream_t st = (hipStream_t)hip_stream;
+    ST_TRY(join(e, st));
     DevHeader h{};
     std::vector<double> S(s->kc + 2, 0.0);
     HIP_TRY(hipMemcpyAsync(&h, s->hdr, sizeof(h), hipMemcpyDeviceToHost, st));
@@ -1601,6 +1708,7 @@ isvd_status isvd_get_factors(isvd_engine* e, isvd_id id, double* U, int64_t ldu,
     ST_TRY(get_stream(e, id, &s));
     ST_TRY(ensure_device(e));
     hipStream_t st = (hipStream_t)hip_stream;
+    ST_TRY(join(e, st));
     DevHeader h{};
     HIP_TRY(hipMemcpyAsync(&h, s->hdr, sizeof(h), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -1631,6 +1739,7 @@ isvd_status isvd_get_matrix(isvd_engine* e, isvd_id id, double* A, int64_t lda, 
     if (!A || lda < s->n) return fail(ISVD_E_INVAL, "null output or lda < n");
     ST_TRY(ensure_device(e));
     hipStream_t st = (hipStream_t)hip_stream;
+    ST_TRY(join(e, st));
     DevHeader h{};
     HIP_TRY(hipMemcpyAsync(&h, s->hdr, sizeof(h), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -1658,6 +1767,7 @@ isvd_status isvd_release(isvd_engine* e, isvd_id id) {
     ST_TRY(get_stream(e, id, &s));
     (void)hipSetDevice(e->device);
     (void)hipDeviceSynchronize();
+    e->rot_pending = false;
     free_stream(e, s);
     return ISVD_OK;
 }
@@ -1692,6 +1802,16 @@ isvd_status isvd_tick(isvd_engine* e, int32_t count, const isvd_request* reqs, v
     }
     ST_TRY(ensure_device(e));
     hipStream_t st = (hipStream_t)hip_stream;
+    // row appends of streams without a refresh policy pipeline with the
+    // next tick; anything that reads U (column appends, entry updates,
+    // trackers) waits for the pending U rotations, and a policy may refresh
+    bool reads_u = false, pipelined = true;
+    for (int q = 0; q < count; ++q) {
+        if (reqs[q].kind != ISVD_ROW || ss[q]->angle) reads_u = true;
+        if (reqs[q].kind != ISVD_ROW || ss[q]->cfg.policy.kind != ISVD_POL_NONE) pipelined = false;
+    }
+    pipelined = pipelined && e->pipelining;
+    if (reads_u) ST_TRY(join(e, st));
     std::map<std::pair<int, int>, int> gi;
     std::vector<Group> groups;
     for (int q = 0; q < count; ++q) {
@@ -1711,7 +1831,7 @@ isvd_status isvd_tick(isvd_engine* e, int32_t count, const isvd_request* reqs, v
         g.all.push_back(rq);
         if (r.kind != ISVD_ENTRY) g.proj.push_back(rq);
     }
-    ST_TRY(run_groups(e, groups, st));
+    ST_TRY(run_groups(e, groups, st, pipelined));
     std::vector<Track> tracks;
     std::vector<char> tfp;
     for (int q = 0; q < count; ++q)

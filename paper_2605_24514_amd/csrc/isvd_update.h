@@ -409,9 +409,11 @@ __global__ void __launch_bounds__(CoreShape<KC>::J::NT) k_core(const Req* __rest
 // with the new leading dimension.  The projected basis' tiles also write the
 // payload into A (row m of A for a row append, column n for a column append).
 // Generic VALU version: block = rot_rows(KC) rows of one basis of one request.
+// Every rotation kernel takes `part`: 0 = the tiles of U then V of each
+// request, 1 = U's tiles only, 2 = V's tiles only (prefix over those tiles).
 template <typename T, int KC>
 __global__ void __launch_bounds__(kThreads) k_rotate(const Req* __restrict__ reqs,
-                                                     const int* __restrict__ prefix, int nreq) {
+                                                     const int* __restrict__ prefix, int nreq, int part) {
     constexpr int RT = rot_rows(KC);
     __shared__ T sQ[(KC + 1) * KC];
     __shared__ T sX[RT * KC];
@@ -422,8 +424,8 @@ __global__ void __launch_bounds__(kThreads) k_rotate(const Req* __restrict__ req
     const ReqScratch* rs = rq.rs;
     if (rs->skip) return;
     const int tile_all = blockIdx.x - prefix[ri];
-    const bool isU = tile_all < rq.rot_tiles_u;
-    const int tile = isU ? tile_all : tile_all - rq.rot_tiles_u;
+    const bool isU = part == 1 || (part == 0 && tile_all < rq.rot_tiles_u);
+    const int tile = (part != 0 || isU) ? tile_all : tile_all - rq.rot_tiles_u;
     const int kin = rs->k_in, ldi = rs->ld_in, ldo = rs->ld_out, idx = rs->in_idx;
     const int64_t rows = isU ? rq.m : rq.n;
     const T* Xi = (const T*)(isU ? rq.U[idx] : rq.V[idx]);
@@ -481,7 +483,7 @@ typedef __attribute__((address_space(1))) mfma_v4f gf4;
 
 template <int KC>
 __global__ void __launch_bounds__(kThreads) k_rotate_mfma(const Req* __restrict__ reqs,
-                                                          const int* __restrict__ prefix, int nreq) {
+                                                          const int* __restrict__ prefix, int nreq, int part) {
     constexpr int S = KC / 4;                 // k-steps (and elements per lane)
     constexpr int NB = KC >= 16 ? KC / 16 : 1;
     constexpr int NCOL = NB * 16;             // output columns computed
@@ -499,8 +501,8 @@ __global__ void __launch_bounds__(kThreads) k_rotate_mfma(const Req* __restrict_
     const ReqScratch* rs = rq.rs;
     if (rs->skip) return;
     const int tile_all = blockIdx.x - prefix[ri];
-    const bool isU = tile_all < rq.rot_tiles_u;
-    const int tile = isU ? tile_all : tile_all - rq.rot_tiles_u;
+    const bool isU = part == 1 || (part == 0 && tile_all < rq.rot_tiles_u);
+    const int tile = (part != 0 || isU) ? tile_all : tile_all - rq.rot_tiles_u;
     const int kin = rs->k_in, ldi = rs->ld_in, ldo = rs->ld_out, idx = rs->in_idx;
     const int64_t rows = isU ? rq.m : rq.n;
     gcfloat* Xi = (gcfloat*)(isU ? rq.U[idx] : rq.V[idx]);
@@ -647,7 +649,7 @@ __global__ void __launch_bounds__(kThreads) k_rotate_mfma(const Req* __restrict_
 // are issued before the current step's MFMAs.
 template <int KC, int ROWS, int RT, bool PF>
 __global__ void __launch_bounds__(kThreads) k_rotate_mfma_t(const Req* __restrict__ reqs,
-                                                            const int* __restrict__ prefix, int nreq) {
+                                                            const int* __restrict__ prefix, int nreq, int part) {
     constexpr int NQ = (KC + 15) / 16;           // panels (loads per lane per tile)
     constexpr int STEPS = 4 * NQ;                // MFMA k-steps per output block
     constexpr int NB = NQ;                       // 16-column output blocks
@@ -660,8 +662,8 @@ __global__ void __launch_bounds__(kThreads) k_rotate_mfma_t(const Req* __restric
     const ReqScratch* rs = rq.rs;
     if (rs->skip) return;
     const int tile_all = blockIdx.x - prefix[ri];
-    const bool isU = tile_all < rq.rot_tiles_u;
-    const int tile = isU ? tile_all : tile_all - rq.rot_tiles_u;
+    const bool isU = part == 1 || (part == 0 && tile_all < rq.rot_tiles_u);
+    const int tile = (part != 0 || isU) ? tile_all : tile_all - rq.rot_tiles_u;
     const int kin = rs->k_in, ldi = rs->ld_in, ldo = rs->ld_out, idx = rs->in_idx;
     const int64_t rows = isU ? rq.m : rq.n;
     gcfloat* Xi = (gcfloat*)(isU ? rq.U[idx] : rq.V[idx]);

@@ -71,7 +71,7 @@ ROT_VARIANTS = [(256, 1, True), (512, 1, True), (1024, 1, True), (1024, 2, False
 EXPORTS = ["isvd_engine_create", "isvd_engine_destroy", "isvd_stream_bytes", "isvd_init", "isvd_init_from_factors",
            "isvd_append_row", "isvd_append_col", "isvd_update_entry", "isvd_refresh", "isvd_metrics",
            "isvd_get_factors", "isvd_get_matrix", "isvd_shape", "isvd_release", "isvd_tick",
-           "isvd_profile", "isvd_profile_read", "isvd_autotune", "isvd_set_rotation_variant", "isvd_last_error"]
+           "isvd_profile", "isvd_profile_read", "isvd_autotune", "isvd_set_rotation_variant", "isvd_sync", "isvd_rotation_stream", "isvd_set_pipelining", "isvd_last_error"]
 
 _lib = None
 
@@ -106,6 +106,9 @@ def load_library(path=LIB_PATH):
         "isvd_profile_read": (i32, [vp, ctypes.POINTER(CLaunchTime), i32, ctypes.POINTER(i32)]),
         "isvd_autotune": (i32, [vp, vp, ctypes.POINTER(i32), dp]),
         "isvd_set_rotation_variant": (i32, [vp, i32, i32]),
+        "isvd_sync": (i32, [vp, vp]),
+        "isvd_set_pipelining": (i32, [vp, i32]),
+        "isvd_rotation_stream": (i32, [vp, ctypes.POINTER(vp)]),
         "isvd_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -359,6 +362,20 @@ class Engine:
 
     def set_rotation_variant(self, kc, variant):
         self._check(self._lib.isvd_set_rotation_variant(self._h, kc, variant), "isvd_set_rotation_variant")
+
+    def sync(self, stream=None):
+        """Order `stream` after the U rotations still pending from pipelined ticks."""
+        self._check(self._lib.isvd_sync(self._h, _stream_ptr(stream)), "isvd_sync")
+
+    def set_pipelining(self, enable):
+        self._check(self._lib.isvd_set_pipelining(self._h, 1 if enable else 0), "isvd_set_pipelining")
+
+    def rotation_stream(self):
+        """Handle (int) of the engine's rotation stream; wrap it with
+        torch.cuda.ExternalStream to record events after a tick's last work."""
+        out = ctypes.c_void_p()
+        self._check(self._lib.isvd_rotation_stream(self._h, ctypes.byref(out)), "isvd_rotation_stream")
+        return out.value or 0
 
     def tick_raw(self, arr, stream=None):
         self._check(self._lib.isvd_tick(self._h, len(arr), arr, _stream_ptr(stream)), "isvd_tick")
