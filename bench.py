@@ -61,6 +61,30 @@ def tick_bytes(m, n, k, esz):
     return rot_bytes(m, n, k, esz) + esz * n * k + esz * n
 
 
+PMC_RECORD = os.path.join(ROOT, "profiles", "rotate_u_kc64_tick512_pmc.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2605_24514_amd", "csrc", f) for f in ("isvd_common.h", "isvd_update.h")]
+
+
+def recorded_traffic_ratio():
+    """HBM traffic / algorithmic bytes of the dominant kernel from the committed
+    counter record, or None once the kernel sources differ from the profiled ones."""
+    import hashlib
+    try:
+        text = open(PMC_RECORD).read()
+    except OSError:
+        return None
+    ratio = sha = None
+    for line in text.splitlines():
+        if line.startswith("traffic_over_algorithmic:"):
+            ratio = float(line.split(":")[1])
+        if line.startswith("kernel_source_sha256:"):
+            sha = line.split(":")[1].strip()
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    return ratio if (ratio is not None and sha == h.hexdigest()) else None
+
+
 def pctl(a, q):
     return float(np.percentile(np.asarray(a), q))
 
@@ -120,6 +144,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-pipeline", action="store_true", help="join every tick's U rotations before the next tick")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one plain 1 GiB device copy (reference for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the streams are independent and would shard by stream across "
@@ -262,10 +288,22 @@ def main():
     all_tick_bytes = sum(tick_bytes(m0 + mid_all, n0, k, 4) for (m0, n0, k) in params)
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": (int(recorded_traffic_ratio() * dom_bytes)
+                            if recorded_traffic_ratio() is not None and kdom == 64 else None),
+                "traffic_note": "HBM bytes per launch: rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated, "
+                                "ratio to algorithmic bytes from profiles/rotate_u_kc64_tick512_pmc.md",
                 "kernel": "k_rotate_mfma_t<%d> (U rotation, variant %d)" % (kdom, tune[kdom][0] if kdom in tune else -1),
                 "launch_ms": round(dom_ms, 4), "bytes_per_launch": int(dom_bytes)}
     tick_gbs = all_tick_bytes / (wall / K) / 1e9
+    if args.calibrate_copy:
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy: %d bytes read, %d bytes written" % (src.numel() * 4, dst.numel() * 4))
+        del src, dst
 
     cpu = None
     if not args.no_cpu:
