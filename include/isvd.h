@@ -291,6 +291,78 @@ isvd_status isvd_autotune(isvd_engine* eng, void* hip_stream, int32_t* variant_o
  * (8, 16, 32, 64).  Errors: INVAL. */
 isvd_status isvd_set_rotation_variant(isvd_engine* eng, int32_t kc, int32_t variant);
 
+/* ------------------------------------------------------------------ serving
+ * A server schedules update requests of many streams onto one engine:
+ * requests queue per stream in arrival order; each scheduling step retires
+ * streams whose lifetime is complete, admits waiting streams in FIFO order
+ * while their footprint (isvd_stream_bytes) fits the HBM budget, and
+ * launches one tick of the oldest queued request of every admitted stream
+ * (continuous batching: requests that arrive while ticks run on the device
+ * join the next tick; up to max_inflight ticks overlap on the device).
+ * A request whose length or indices no longer fit its stream completes at
+ * once with ISVD_E_SHAPE and is not part of a tick.  Times are seconds on
+ * the server's host clock (isvd_server_clock); completion times come from
+ * an event after each tick's last work.  One host thread per server. */
+typedef struct isvd_server isvd_server;   /* opaque */
+
+typedef struct {
+    uint64_t hbm_budget;    /* bytes the admitted streams may hold (0 = no limit) */
+    int32_t max_batch;      /* most requests per tick (0 = no limit) */
+    int32_t max_inflight;   /* ticks on the device before a step waits for the oldest (>= 1) */
+} isvd_server_config;
+
+typedef struct {
+    int64_t req;            /* id from isvd_server_submit */
+    int64_t ticket;         /* stream ticket */
+    int32_t kind;           /* ISVD_ROW / ISVD_COL / ISVD_ENTRY */
+    int32_t status;         /* ISVD_OK or the error of the request */
+    double arrival_s;       /* as submitted */
+    double admit_s;         /* when its stream was admitted */
+    double launch_s;        /* when its tick was launched */
+    double done_s;          /* when its tick had finished on the device */
+} isvd_completion;
+
+typedef struct {
+    int64_t waiting, admitted, retired;   /* streams */
+    int64_t queued;                        /* requests not yet launched */
+    uint64_t hbm_used;                     /* footprint of the admitted streams */
+    int32_t inflight_ticks, pad;
+} isvd_server_stats_t;
+
+/* hip_stream: the stream the server's ticks and admissions run on. */
+isvd_status isvd_server_create(isvd_engine* eng, const isvd_server_config* cfg, void* hip_stream,
+                               isvd_server** out);
+isvd_status isvd_server_destroy(isvd_server* srv);
+double isvd_server_clock(isvd_server* srv);
+const char* isvd_server_error(isvd_server* srv);
+
+/* Register a stream (admitted later by isvd_init with this config and A0, a
+ * device pointer the caller keeps valid until then); lifetime = requests
+ * after whose completion the stream is released (0 = kept).  *ticket names
+ * the stream in the server.  Errors: INVAL, BUDGET (larger than the budget). */
+isvd_status isvd_server_add_stream(isvd_server* srv, const isvd_config* cfg, const void* A0, int64_t lda,
+                                   int32_t dtype, int64_t lifetime, int64_t* ticket);
+
+/* Queue a request (its id field is ignored; payloads are device pointers
+ * kept valid until the request completes).  Errors: INVAL, STATE. */
+isvd_status isvd_server_submit(isvd_server* srv, int64_t ticket, const isvd_request* req, double arrival_s,
+                               int64_t* req_id);
+
+/* One scheduling step (see above); *launched = requests in the tick launched. */
+isvd_status isvd_server_step(isvd_server* srv, int32_t* launched);
+
+/* Wait for every launched tick and stamp its requests. */
+isvd_status isvd_server_drain(isvd_server* srv);
+
+/* Move up to cap completion records (oldest first) to out; *count = moved. */
+isvd_status isvd_server_poll(isvd_server* srv, isvd_completion* out, int32_t cap, int32_t* count);
+
+isvd_status isvd_server_stats(isvd_server* srv, isvd_server_stats_t* out);
+
+/* Engine stream id of a ticket (-1 before admission) and its state
+ * (0 waiting, 1 admitted, 2 retired). */
+isvd_status isvd_server_stream(isvd_server* srv, int64_t ticket, isvd_id* id, int32_t* state);
+
 /* Message for the last error on this thread ("" if none). */
 const char* isvd_last_error(void);
 

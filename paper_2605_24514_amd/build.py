@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libisvd.so")
-SOURCES = [os.path.join(CSRC, "isvd_engine.hip")]
+SOURCES = [os.path.join(CSRC, "isvd_engine.hip"), os.path.join(CSRC, "isvd_serve.hip")]
 HEADERS = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")] + [
     os.path.join(ROOT, "include", "isvd.h")]
 

@@ -60,6 +60,22 @@ class CRequest(ctypes.Structure):
                 ("j", ctypes.c_int64), ("delta", ctypes.c_double)]
 
 
+class CServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_uint64), ("max_batch", ctypes.c_int32), ("max_inflight", ctypes.c_int32)]
+
+
+class CCompletion(ctypes.Structure):
+    _fields_ = [("req", ctypes.c_int64), ("ticket", ctypes.c_int64), ("kind", ctypes.c_int32),
+                ("status", ctypes.c_int32), ("arrival_s", ctypes.c_double), ("admit_s", ctypes.c_double),
+                ("launch_s", ctypes.c_double), ("done_s", ctypes.c_double)]
+
+
+class CServerStats(ctypes.Structure):
+    _fields_ = [("waiting", ctypes.c_int64), ("admitted", ctypes.c_int64), ("retired", ctypes.c_int64),
+                ("queued", ctypes.c_int64), ("hbm_used", ctypes.c_uint64), ("inflight_ticks", ctypes.c_int32),
+                ("pad", ctypes.c_int32)]
+
+
 class CLaunchTime(ctypes.Structure):
     _fields_ = [("phase", ctypes.c_int32), ("kc", ctypes.c_int32), ("fp64", ctypes.c_int32),
                 ("nreq", ctypes.c_int32), ("blocks", ctypes.c_int64), ("ms", ctypes.c_double)]
@@ -71,7 +87,10 @@ ROT_VARIANTS = [(256, 1, True), (512, 1, True), (1024, 1, True), (1024, 2, False
 EXPORTS = ["isvd_engine_create", "isvd_engine_destroy", "isvd_stream_bytes", "isvd_init", "isvd_init_from_factors",
            "isvd_append_row", "isvd_append_col", "isvd_update_entry", "isvd_refresh", "isvd_metrics",
            "isvd_get_factors", "isvd_get_matrix", "isvd_shape", "isvd_release", "isvd_tick",
-           "isvd_profile", "isvd_profile_read", "isvd_autotune", "isvd_set_rotation_variant", "isvd_sync", "isvd_rotation_stream", "isvd_set_pipelining", "isvd_last_error"]
+           "isvd_profile", "isvd_profile_read", "isvd_autotune", "isvd_set_rotation_variant", "isvd_sync", "isvd_rotation_stream", "isvd_set_pipelining",
+           "isvd_server_create", "isvd_server_destroy", "isvd_server_clock", "isvd_server_error",
+           "isvd_server_add_stream", "isvd_server_submit", "isvd_server_step", "isvd_server_drain",
+           "isvd_server_poll", "isvd_server_stats", "isvd_server_stream", "isvd_last_error"]
 
 _lib = None
 
@@ -108,6 +127,17 @@ def load_library(path=LIB_PATH):
         "isvd_set_rotation_variant": (i32, [vp, i32, i32]),
         "isvd_sync": (i32, [vp, vp]),
         "isvd_set_pipelining": (i32, [vp, i32]),
+        "isvd_server_create": (i32, [vp, ctypes.POINTER(CServerConfig), vp, ctypes.POINTER(vp)]),
+        "isvd_server_destroy": (i32, [vp]),
+        "isvd_server_clock": (ctypes.c_double, [vp]),
+        "isvd_server_error": (ctypes.c_char_p, [vp]),
+        "isvd_server_add_stream": (i32, [vp, ctypes.POINTER(CConfig), vp, i64, i32, i64, ctypes.POINTER(i64)]),
+        "isvd_server_submit": (i32, [vp, i64, ctypes.POINTER(CRequest), ctypes.c_double, ctypes.POINTER(i64)]),
+        "isvd_server_step": (i32, [vp, ctypes.POINTER(i32)]),
+        "isvd_server_drain": (i32, [vp]),
+        "isvd_server_poll": (i32, [vp, ctypes.POINTER(CCompletion), i32, ctypes.POINTER(i32)]),
+        "isvd_server_stats": (i32, [vp, ctypes.POINTER(CServerStats)]),
+        "isvd_server_stream": (i32, [vp, i64, ctypes.POINTER(i64), ctypes.POINTER(i32)]),
         "isvd_rotation_stream": (i32, [vp, ctypes.POINTER(vp)]),
         "isvd_last_error": (ctypes.c_char_p, []),
     }
@@ -379,3 +409,100 @@ class Engine:
 
     def tick_raw(self, arr, stream=None):
         self._check(self._lib.isvd_tick(self._h, len(arr), arr, _stream_ptr(stream)), "isvd_tick")
+
+
+class Server:
+    """Serving loop over an Engine (continuous batching, HBM-budget admission);
+    scheduling runs in the library (isvd_server_*)."""
+
+    def __init__(self, engine, hbm_budget=0, max_batch=0, max_inflight=2, stream=None):
+        self._eng = engine
+        self._lib = engine._lib
+        cfg = CServerConfig(int(hbm_budget), int(max_batch), int(max_inflight))
+        h = ctypes.c_void_p()
+        self._check(self._lib.isvd_server_create(engine._h, ctypes.byref(cfg), _stream_ptr(stream), ctypes.byref(h)),
+                    "isvd_server_create")
+        self._h = h
+        self._keep = {}
+
+    def _check(self, st, where):
+        if st != 0:
+            msg = self._lib.isvd_server_error(self._h).decode() if getattr(self, "_h", None) else ""
+            raise IsvdError(st, where, msg or self._lib.isvd_last_error().decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.isvd_server_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def clock(self):
+        return float(self._lib.isvd_server_clock(self._h))
+
+    def add_stream(self, A0, k, precision="fp32", m_cap=None, n_cap=None, lifetime=0, policy=None, tol_rel=0.0,
+                   refresh_iters=-1, oversample=-1):
+        """A0: a device tensor kept alive by the server until the stream is admitted."""
+        m0, n0 = A0.shape
+        ptr, _, code, dev, keep = _payload(A0)
+        if not dev:
+            raise ValueError("A0 must be a device tensor")
+        cfg = Engine.config(m0, n0, k, precision, m_cap, n_cap, tol_rel, policy, refresh_iters, oversample)
+        t = ctypes.c_int64()
+        self._check(self._lib.isvd_server_add_stream(self._h, ctypes.byref(cfg), ptr, A0.stride(0), code,
+                                                     int(lifetime), ctypes.byref(t)), "isvd_server_add_stream")
+        self._keep[("A0", t.value)] = keep
+        return t.value
+
+    def submit(self, ticket, kind, payload, arrival_s):
+        """payload: device tensor (row / column) or (i, j, delta) for an entry update."""
+        r = CRequest()
+        r.kind = kind
+        if kind == ENTRY:
+            r.i, r.j, r.delta = int(payload[0]), int(payload[1]), float(payload[2])
+            r.dtype = DTYPE_F32
+        else:
+            ptr, ln, code, dev, keep = _payload(payload)
+            if not dev:
+                raise ValueError("payloads must be device tensors")
+            r.payload = ptr
+            r.len = ln
+            r.dtype = code
+        rid = ctypes.c_int64()
+        self._check(self._lib.isvd_server_submit(self._h, int(ticket), ctypes.byref(r), float(arrival_s),
+                                                 ctypes.byref(rid)), "isvd_server_submit")
+        if kind != ENTRY:
+            self._keep[rid.value] = keep
+        return rid.value
+
+    def step(self):
+        n = ctypes.c_int32()
+        self._check(self._lib.isvd_server_step(self._h, ctypes.byref(n)), "isvd_server_step")
+        return n.value
+
+    def drain(self):
+        self._check(self._lib.isvd_server_drain(self._h), "isvd_server_drain")
+
+    def poll(self, cap=1 << 16):
+        arr = (CCompletion * cap)()
+        n = ctypes.c_int32()
+        self._check(self._lib.isvd_server_poll(self._h, arr, cap, ctypes.byref(n)), "isvd_server_poll")
+        out = [{f: getattr(arr[q], f) for f, _ in CCompletion._fields_} for q in range(n.value)]
+        for c in out:
+            self._keep.pop(c["req"], None)
+        return out
+
+    def stats(self):
+        st = CServerStats()
+        self._check(self._lib.isvd_server_stats(self._h, ctypes.byref(st)), "isvd_server_stats")
+        return {f: getattr(st, f) for f, _ in CServerStats._fields_ if f != "pad"}
+
+    def stream(self, ticket):
+        sid, state = ctypes.c_int64(), ctypes.c_int32()
+        self._check(self._lib.isvd_server_stream(self._h, int(ticket), ctypes.byref(sid), ctypes.byref(state)),
+                    "isvd_server_stream")
+        return sid.value, state.value

@@ -11,7 +11,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def _declared():
     text = open(os.path.join(ROOT, "include", "isvd.h")).read()
-    decl = r"^\s*(?:isvd_status|uint64_t|const char\*)\s+(isvd_[a-z_]+)\s*\("
+    decl = r"^\s*(?:isvd_status|uint64_t|double|const char\*)\s+(isvd_[a-z_]+)\s*\("
     return sorted(set(re.findall(decl, text, flags=re.M)))
 
 
@@ -35,7 +35,8 @@ def test_struct_layouts_match_the_c_compiler(tmp_path):
     from paper_2605_24514_amd import isvd
     structs = {"isvd_policy": isvd.CPolicy, "isvd_config": isvd.CConfig,
                "isvd_metrics_t": isvd.CMetrics, "isvd_request": isvd.CRequest,
-               "isvd_launch_time": isvd.CLaunchTime}
+               "isvd_launch_time": isvd.CLaunchTime, "isvd_server_config": isvd.CServerConfig,
+               "isvd_completion": isvd.CCompletion, "isvd_server_stats_t": isvd.CServerStats}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "isvd.h"', "int main(void) {"]
     for cname, cls in structs.items():
         lines.append('printf("%s %%zu\\n", sizeof(%s));' % (cname, cname))
