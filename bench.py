@@ -14,6 +14,7 @@ the same rows, so the FP32 result is compared with the FP64 one at the end.
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
 import argparse
+import ctypes
 import json
 import os
 import sys
@@ -132,6 +133,108 @@ def cpu_baseline(params, seconds, torch):
             "wall_s": wall, "cpu_s": cpu, "nproc": os.cpu_count()}
 
 
+def serve_main(args):
+    """Serving run: streams of the batched workload's sizes arrive as requests
+    (Poisson, mixed row / column / entry updates, per-stream policies) and are
+    admitted under an HBM budget; prints one JSON line."""
+    import torch
+    from paper_2605_24514_amd import isvd
+    from synth import device as sdev, uniforms
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    N, L, rate = args.serve_streams, args.serve_lifetime, args.serve_rate
+    params = stream_params(N, seed=7)
+    u = uniforms(7, 0xC4, 101, np.arange(N), 1)[:, 0]
+    pol_kind = np.minimum((u * 4).astype(int), 3)
+    policies = [isvd.Policy(kind=isvd.POL_PERIODIC, period=500),
+                isvd.Policy(kind=isvd.POL_ERROR, gamma=1.05, check_every=100, t_min=100),
+                isvd.Policy(kind=isvd.POL_ANGLE, theta_max=1e-3, t_min=1),
+                isvd.Policy(kind=isvd.POL_ADAPTIVE, tau=0.95, band=0.01, eta=0.5, k_min=1, period=500)]
+    rng = np.random.default_rng(17)
+    dev_stream = torch.cuda.Stream()
+    eng = isvd.Engine()
+    srv = isvd.Server(eng, hbm_budget=int(args.serve_budget_gb * 1e9), max_inflight=2, stream=dev_stream)
+    log("serving: %d streams, lifetime %d, %.0f requests/s, budget %.0f GB" % (N, L, rate, args.serve_budget_gb))
+    A0s, tickets, rows_pool, cols, reqs, arrivals, owner = [], [], [], [], [], [], []
+    for s, (m0, n0, k) in enumerate(params):
+        A0 = torch.empty((m0, n0), dtype=torch.float32, device="cuda")
+        sdev.rows_into(A0, 0, m0, n0, SEED, s, K_FACTORS)
+        A0s.append(A0)
+        pk = int(pol_kind[s])
+        kk = min(k, n0)
+        tickets.append(srv.add_stream(A0, kk, m_cap=m0 + L, n_cap=n0 + L, lifetime=L, policy=policies[pk],
+                                      refresh_iters=1))
+        R = torch.empty((16, n0 + L), dtype=torch.float32, device="cuda")
+        sdev.rows_into(R, m0, 16, n0 + L, SEED, s, K_FACTORS)
+        rows_pool.append(R)
+        cols.append(torch.randn(m0 + L, dtype=torch.float32, device="cuda"))
+        kinds = rng.choice([0, 1, 2], size=L, p=[0.7, 0.15, 0.15])
+        t = np.cumsum(rng.exponential(N / rate, size=L))
+        m, n = m0, n0
+        for q in range(L):
+            r = isvd.CRequest()
+            r.kind = int(kinds[q])
+            if r.kind == isvd.ROW:
+                r.payload = ctypes.c_void_p(rows_pool[-1][q % 16].data_ptr())
+                r.len, r.dtype = n, isvd.DTYPE_F32
+                m += 1
+            elif r.kind == isvd.COL:
+                r.payload = ctypes.c_void_p(cols[-1].data_ptr())
+                r.len, r.dtype = m, isvd.DTYPE_F32
+                n += 1
+            else:
+                r.i, r.j, r.delta = int(rng.integers(m)), int(rng.integers(n)), float(rng.normal(0, 0.5))
+                r.dtype = isvd.DTYPE_F32
+            reqs.append(r)
+            arrivals.append(t[q])
+            owner.append(tickets[-1])
+    torch.cuda.synchronize()
+    order = np.argsort(np.asarray(arrivals), kind="stable")
+    arr = np.asarray(arrivals)[order]
+    own = np.asarray(owner, dtype=np.int64)[order]
+    creq = (isvd.CRequest * len(order))(*[reqs[i] for i in order])
+    total = len(order)
+    log("serving: %d requests prepared" % total)
+    t_start = srv.clock()
+    pos, done = 0, []
+    last = time.perf_counter()
+    while len(done) < total:
+        now = srv.clock() - t_start
+        hi = int(np.searchsorted(arr, now, side="right"))
+        if hi > pos:
+            sub = (isvd.CRequest * (hi - pos)).from_buffer(creq, pos * ctypes.sizeof(isvd.CRequest))
+            srv.submit_many(own[pos:hi], sub, arr[pos:hi] + t_start)
+            pos = hi
+        srv.step()
+        done += srv.poll()
+        if pos >= total and srv.stats()["queued"] == 0:
+            srv.drain()
+            done += srv.poll()
+        if time.perf_counter() - last > 10:
+            last = time.perf_counter()
+            log("  %d / %d requests done, %s" % (len(done), total, srv.stats()))
+    wall = srv.clock() - t_start
+    ok = [c for c in done if c["status"] == 0]
+    lat = np.array([c["done_s"] - c["arrival_s"] for c in ok]) * 1e3
+    wait = np.array([max(0.0, c["admit_s"] - c["arrival_s"]) for c in ok]) * 1e3
+    served = np.array([c["done_s"] - max(c["arrival_s"], c["admit_s"]) for c in ok]) * 1e3
+    out = {"metric": "serving updates/s with p50/p99 arrival-to-completion latency (mixed requests, "
+                     "per-stream policies, HBM-budget admission)",
+           "value": round(len(ok) / wall, 1), "unit": "updates/s", "n_gpus": 1, "higher_is_better": True,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "serving loop: %d factor-model streams (n~U{50..2000}, m~U{1000..50000}, "
+                                  "k~U{8,16,32,64}), %d requests each, 70/15/15 row/column/entry, Poisson "
+                                  "arrivals at %.0f/s aggregate, policies uniform over periodic 500 / error 1.05 / "
+                                  "angle 1e-3 / adaptive 0.95, budget %.0f GB" % (N, L, rate, args.serve_budget_gb),
+                      "streams": N, "lifetime": L},
+           "requests": total, "completed_ok": len(ok), "wall_s": round(wall, 3),
+           "latency_ms": {"p50": round(pctl(lat, 50), 3), "p99": round(pctl(lat, 99), 3)},
+           "after_admission_ms": {"p50": round(pctl(served, 50), 3), "p99": round(pctl(served, 99), 3)},
+           "admission_wait_ms": {"p50": round(pctl(wait, 50), 3), "p99": round(pctl(wait, 99), 3)}}
+    print(json.dumps(out), flush=True)
+    srv.close()
+    eng.close()
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -146,7 +249,15 @@ def main():
     ap.add_argument("--no-pipeline", action="store_true", help="join every tick's U rotations before the next tick")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (reference for hardware byte counters)")
+    ap.add_argument("--serve", action="store_true", help="run the serving loop instead of the batched tick")
+    ap.add_argument("--serve-streams", type=int, default=1024)
+    ap.add_argument("--serve-lifetime", type=int, default=200)
+    ap.add_argument("--serve-rate", type=float, default=200000.0)
+    ap.add_argument("--serve-budget-gb", type=float, default=50.0)
     args = ap.parse_args()
+    if args.serve and args.gpus == 1:
+        serve_main(args)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: the streams are independent and would shard by stream across "
               "GPUs with no communication; runs on %d GPUs are not part of this build" % args.gpus,

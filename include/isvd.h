@@ -348,6 +348,11 @@ isvd_status isvd_server_add_stream(isvd_server* srv, const isvd_config* cfg, con
 isvd_status isvd_server_submit(isvd_server* srv, int64_t ticket, const isvd_request* req, double arrival_s,
                                int64_t* req_id);
 
+/* isvd_server_submit for count requests (tickets[q], reqs[q], arrival_s[q]);
+ * req_ids may be NULL.  Stops at the first error (earlier ones stay queued). */
+isvd_status isvd_server_submit_many(isvd_server* srv, int32_t count, const int64_t* tickets,
+                                    const isvd_request* reqs, const double* arrival_s, int64_t* req_ids);
+
 /* One scheduling step (see above); *launched = requests in the tick launched. */
 isvd_status isvd_server_step(isvd_server* srv, int32_t* launched);
 

@@ -1,7 +1,7 @@
 // libisvd: host side of the MI355X incremental-SVD engine and its C ABI.
 //
 // Per stream the engine keeps, in one device allocation:
-//   A (m_cap x n_cap, row-major), U and V in two buffers each (ping-pong:
+//   A (m_cap x round4(n_cap), row-major), U and V in two buffers each (ping-pong:
 //   every rotation writes the other buffer, so the leading dimension can
 //   follow the rank), Sigma, the device header (rank, buffer index, N_t,
 //   trackers), the rotation matrices of the last core, projection sums and
@@ -106,6 +106,10 @@ struct Stream {
     double last_ratio = 0.0;     // error policy: frob_ratio at its last check
 };
 
+// Leading dimension of A: n_cap rounded up to a multiple of 4, so that rows
+// start 16-byte aligned (vector loads in the refresh products).
+inline int64_t lda_of(const isvd_config& c) { return (c.n_cap + 3) & ~(int64_t)3; }
+
 Layout make_layout(const isvd_config& c, int esz, int kc, int64_t* ntiles_max) {
     Layout L{};
     size_t off = 0;
@@ -139,7 +143,7 @@ Layout make_layout(const isvd_config& c, int esz, int kc, int64_t* ntiles_max) {
     L.TM = take(angle ? sizeof(double) * kc * kc : 0);
     L.TH = take(angle ? sizeof(double) * kc * kc : 0);
     L.TP = take(angle ? sizeof(double) * (size_t)cdiv(c.m_cap, kTrackRows) * (2 * kc + 1) : 0);
-    L.A = take((size_t)esz * c.m_cap * c.n_cap);
+    L.A = take((size_t)esz * c.m_cap * lda_of(c));
     L.total = off;
     return L;
 }
@@ -379,7 +383,7 @@ Req make_req(const isvd_engine* e, Stream& s, int kind, const void* payload, int
     Req r{};
     r.m = s.m;
     r.n = s.n;
-    r.lda = s.cfg.n_cap;
+    r.lda = lda_of(s.cfg);
     r.i = i;
     r.j = j;
     r.delta = delta;
@@ -649,7 +653,7 @@ WsLayout ws_layout(int64_t m, int64_t n, int b, int esz) {
         return o;
     };
     const int64_t nchunk_tn = std::min<int64_t>(32, cdiv(m, kGemmK));
-    const int64_t nchunk_g = cdiv(std::max(m, n), kChunkRows);
+    const int64_t nchunk_g = cdiv(std::max(m, n), kGramRows);
     w.X = take((size_t)esz * n * b);
     w.Y = take((size_t)esz * m * b);
     w.Zp = take(sizeof(double) * (size_t)nchunk_tn * n * b);
@@ -715,12 +719,19 @@ isvd_status cholqr2(isvd_engine* e, const WsLayout& w, T* Y, int64_t rows, int b
     double* Rtmp = (double*)(ws + w.Rtmp);
     T* RinvT = (T*)(ws + w.RinvT);
     int* flag = (int*)(ws + w.flag);
-    const int nchunk = (int)cdiv(rows, kChunkRows);
+    const int nchunk = (int)cdiv(rows, kGramRows);
     for (int pass = 0; pass < 2; ++pass) {
-        k_gram_partial<T><<<nchunk, kThreads, 0, st>>>(Y, b, rows, b, Gp);
+        k_gram_mfma<T><<<nchunk, kThreads, 0, st>>>(Y, b, rows, b, Gp);
         k_sum_parts<double><<<(int)cdiv(b * b, 256), 256, 0, st>>>(Gp, nchunk, (int64_t)b * b, (int64_t)b * b, G);
-        k_chol_inv<T><<<1, kThreads, sizeof(double) * 2 * b * b, st>>>(G, b, R, RinvT, flag);
-        k_rotate_plain<T, 128><<<(int)cdiv(rows, 16), kThreads, 0, st>>>(Y, b, Y, b, rows, b, RinvT);
+        k_chol_inv<T><<<1, kCholThreads, sizeof(double) * 2 * b * b, st>>>(G, b, R, RinvT, flag);
+        if constexpr (sizeof(T) == 4) {
+            if (b % 4 == 0)
+                k_gemm_nn_mfma<<<(int)cdiv(rows, 128), kThreads, 0, st>>>(Y, b, RinvT, b, Y, b, rows, b, b);
+            else
+                k_rotate_plain<T, 128><<<(int)cdiv(rows, 16), kThreads, 0, st>>>(Y, b, Y, b, rows, b, RinvT);
+        } else {
+            k_rotate_plain<T, 128><<<(int)cdiv(rows, 16), kThreads, 0, st>>>(Y, b, Y, b, rows, b, RinvT);
+        }
         if (want_R) {
             if (pass == 0) {
                 HIP_TRY(hipMemcpyAsync(Racc, R, sizeof(double) * b * b, hipMemcpyDeviceToDevice, st));
@@ -732,6 +743,15 @@ isvd_status cholqr2(isvd_engine* e, const WsLayout& w, T* Y, int64_t rows, int b
     }
     HIP_TRY(hipGetLastError());
     return ISVD_OK;
+}
+
+// Y = A X: matrix cores for FP32 storage, FP64 VALU tiles for FP64
+template <typename T>
+void gemm_nn(const T* A, int64_t lda, const T* X, T* Y, int64_t m, int64_t n, int b, hipStream_t st) {
+    if constexpr (sizeof(T) == 4)
+        k_gemm_nn_mfma<<<(int)cdiv(m, 128), kThreads, 0, st>>>(A, lda, X, b, Y, b, m, n, b);
+    else
+        k_gemm_nn<T><<<(int)cdiv(m, kGemmRows), kThreads, 0, st>>>(A, lda, X, b, Y, b, m, n, b);
 }
 
 // TruncatedSVD(A_t, k), in two steps so that a check of the error policy can
@@ -768,7 +788,7 @@ isvd_status refresh_compute(isvd_engine* e, Stream& s, bool init, hipStream_t st
     T* Y = (T*)(ws + w.Y);
     double* Zp = (double*)(ws + w.Zp);
     const T* A = (const T*)s.A;
-    const int64_t lda = s.cfg.n_cap;
+    const int64_t lda = lda_of(s.cfg);
     HIP_TRY(hipMemsetAsync(ws + w.flag, 0, sizeof(int) * 4, st));
     const int cur = init ? 0 : h.cur;
     const int kw = init ? 0 : std::min(h.k, b);
@@ -778,14 +798,17 @@ isvd_status refresh_compute(isvd_engine* e, Stream& s, bool init, hipStream_t st
     const int64_t nchunk = std::min<int64_t>(32, cdiv(m, kGemmK));
     const int64_t rpc = cdiv(m, nchunk);
     for (int it = 0; it < iters; ++it) {
-        k_gemm_nn<T><<<(int)cdiv(m, kGemmRows), kThreads, 0, st>>>(A, lda, X, b, Y, b, m, n, b);
+        gemm_nn<T>(A, lda, X, Y, m, n, b, st);
         ST_TRY(cholqr2<T>(e, w, Y, m, b, false, st));
         dim3 grid((unsigned)cdiv(n, 64), (unsigned)nchunk);
-        k_gemm_tn_partial<T><<<grid, kThreads, 0, st>>>(A, lda, Y, b, Zp, m, n, b, rpc);
+        if constexpr (sizeof(T) == 4)
+            k_gemm_tn_mfma<<<grid, kThreads, 0, st>>>(A, lda, Y, b, Zp, m, n, b, rpc);
+        else
+            k_gemm_tn_partial<T><<<grid, kThreads, 0, st>>>(A, lda, Y, b, Zp, m, n, b, rpc);
         k_sum_parts<T><<<(int)cdiv(n * b, 256), 256, 0, st>>>(Zp, (int)nchunk, n * b, n * b, X);
         ST_TRY(cholqr2<T>(e, w, X, n, b, false, st));
     }
-    k_gemm_nn<T><<<(int)cdiv(m, kGemmRows), kThreads, 0, st>>>(A, lda, X, b, Y, b, m, n, b);
+    gemm_nn<T>(A, lda, X, Y, m, n, b, st);
     ST_TRY(cholqr2<T>(e, w, Y, m, b, true, st));
     const int ldo = round4(k);
     k_svd_small<T><<<1, JacobiShape<kMaxBlock + 1>::NT,
@@ -975,7 +998,7 @@ isvd_status exact_metrics_t(isvd_engine* e, Stream& s, hipStream_t st, Exact* ou
     const int k = h.k, ld = h.ld;
     const int64_t nfro = cdiv(m, kFroRows);
     const int64_t nres = cdiv(m, 64) * cdiv(n, 64);
-    const int64_t ngu = cdiv(m, kChunkRows), ngv = cdiv(n, kChunkRows);
+    const int64_t ngu = cdiv(m, kGramRows), ngv = cdiv(n, kGramRows);
     const size_t need = sizeof(double) * (size_t)(nfro + nres + (ngu + ngv) * k * k + 2 * k * k + 8);
     ST_TRY(ensure_mws(e, need));
     double* fro_p = (double*)e->mws;
@@ -988,15 +1011,15 @@ isvd_status exact_metrics_t(isvd_engine* e, Stream& s, hipStream_t st, Exact* ou
     const T* A = (const T*)s.A;
     const T* U = (const T*)s.U[h.cur];
     const T* V = (const T*)s.V[h.cur];
-    const int64_t lda = s.cfg.n_cap;
+    const int64_t lda = lda_of(s.cfg);
     k_fro2_partial<T><<<(int)nfro, kThreads, 0, st>>>(A, lda, m, n, fro_p);
     k_sum_parts<double><<<1, 1, 0, st>>>(fro_p, (int)nfro, 1, 1, scal + 0);
     dim3 rg((unsigned)cdiv(m, 64), (unsigned)cdiv(n, 64));
     k_resid2_partial<T><<<rg, kThreads, 0, st>>>(A, lda, U, V, ld, s.S, m, n, k, res_p);
     k_sum_parts<double><<<1, 1, 0, st>>>(res_p, (int)nres, 1, 1, scal + 1);
-    k_gram_partial<T, true><<<(int)ngu, kThreads, 0, st>>>(U, ld, m, k, gu_p);
+    k_gram_mfma<T, true><<<(int)ngu, kThreads, 0, st>>>(U, ld, m, k, gu_p);
     k_sum_parts<double><<<(int)cdiv(k * k, 256), 256, 0, st>>>(gu_p, (int)ngu, (int64_t)k * k, (int64_t)k * k, GU);
-    k_gram_partial<T, true><<<(int)ngv, kThreads, 0, st>>>(V, ld, n, k, gv_p);
+    k_gram_mfma<T, true><<<(int)ngv, kThreads, 0, st>>>(V, ld, n, k, gv_p);
     k_sum_parts<double><<<(int)cdiv(k * k, 256), 256, 0, st>>>(gv_p, (int)ngv, (int64_t)k * k, (int64_t)k * k, GV);
     const int nt = JacobiShape<kMaxBlock + 1>::NT;
     int* sw = (int*)(scal + 6);
@@ -1530,8 +1553,8 @@ static isvd_status init_common(isvd_engine* e, const isvd_config* cfg, const voi
     if (hipMemsetAsync(s->base, 0, s->L.U0, st) != hipSuccess ||
         hipMemcpyAsync(s->hdr, &h0, sizeof(h0), hipMemcpyHostToDevice, st) != hipSuccess)
         return bail(fail(ISVD_E_DEVICE, "header initialisation failed"));
-    // A_0 into A (leading dimension n_cap), converting to the storage type
-    const int64_t m0 = cfg->m0, n0 = cfg->n0, ldA = cfg->n_cap;
+    // A_0 into A (leading dimension lda_of), converting to the storage type
+    const int64_t m0 = cfg->m0, n0 = cfg->n0, ldA = lda_of(*cfg);
     const int64_t cnt = m0 * n0;
     const void* src = A0;
     void* tmpdev = nullptr;
@@ -1743,7 +1766,7 @@ isvd_status isvd_get_matrix(isvd_engine* e, isvd_id id, double* A, int64_t lda, 
     DevHeader h{};
     HIP_TRY(hipMemcpyAsync(&h, s->hdr, sizeof(h), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
-    const int64_t ldA = s->cfg.n_cap;
+    const int64_t ldA = lda_of(s->cfg);
     std::vector<char> buf((size_t)s->esz * h.m * ldA);
     HIP_TRY(hipMemcpyAsync(buf.data(), s->A, buf.size(), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));

@@ -20,6 +20,7 @@ namespace isvd {
 constexpr int kGemmRows = 64;
 constexpr int kGemmK = 32;
 constexpr int kChunkRows = 1024;
+constexpr int kCholThreads = 1024;   // threads of the one-block Cholesky
 
 // Y[m x b] = A[m x n] X[n x b]   (b <= 128)
 template <typename T>
@@ -118,6 +119,208 @@ __global__ void __launch_bounds__(kThreads) k_gemm_tn_partial(const T* __restric
     }
 }
 
+// ---------------------------------------------------------------------------
+// Matrix-core versions of the refresh products (b <= 96 columns).
+// v_mfma_f32_16x16x4f32 / v_mfma_f64_16x16x4f64 lane layout: A[l%16][l/16],
+// B[l/16][l%16]; FP32 D[4(l/16)+r][l%16], FP64 D[4r+l/16][l%16].
+typedef float mm_v4f __attribute__((ext_vector_type(4)));
+typedef double mm_v4d __attribute__((ext_vector_type(4)));
+constexpr int kMmK = 32;         // k-chunk staged in LDS
+constexpr int kGramRows = 256;   // rows per block of the Gram partials
+
+// Y[m x b] = A[m x n] X[n x b], FP32 in and FP32 accumulation.  A wave owns
+// 32 rows (two 16-row MFMA blocks) and streams them across k on its own (no
+// LDS, no block barriers): per 16-column slab, lane l loads one float4 of A
+// per row block -- row l%16, columns k0 + 4 (l/16) + 0..3, 1 KB per wave
+// instruction -- and the MFMA k order follows (step s takes column
+// k0 + 4 (l/16) + s); X (small, cache-resident) is read in the same order
+// as the B operand and shared by both row blocks.  lda % 4 == 0.  Y may be
+// A itself (ldy == lda): a wave reads all of its rows before it writes them.
+__global__ void __launch_bounds__(kThreads) k_gemm_nn_mfma(const float* A, int64_t lda,
+                                                           const float* __restrict__ X, int ldx,
+                                                           float* Y, int ldy,
+                                                           int64_t m, int64_t n, int b) {
+    typedef __attribute__((address_space(1))) const mm_v4f gc4;
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int g = l >> 4, c16 = l & 15;
+    const int64_t r0 = ((int64_t)blockIdx.x * 4 + w) * 32;
+    if (r0 >= m) return;
+    const int nb = (b + 15) / 16;
+    mm_v4f acc[2][6];
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int q = 0; q < 6; ++q) acc[rb][q] = (mm_v4f){0.f, 0.f, 0.f, 0.f};
+    for (int64_t k0 = 0; k0 < n; k0 += 16) {
+        const int64_t kc = k0 + 4 * g;
+        mm_v4f a[2];
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb) {
+            const int64_t row = r0 + 16 * rb + c16;
+            a[rb] = (mm_v4f){0.f, 0.f, 0.f, 0.f};
+            if (row < m && kc < n) {
+                a[rb] = *(gc4*)(A + row * lda + kc);
+                // columns past n (row padding) are not part of A
+#pragma unroll
+                for (int s4 = 0; s4 < 4; ++s4)
+                    if (kc + s4 >= n) a[rb][s4] = 0.f;
+            }
+        }
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+            const int64_t kk = kc + s4;
+            float xv[6];
+#pragma unroll
+            for (int q = 0; q < 6; ++q) {
+                const int j = 16 * q + c16;
+                xv[q] = (q < nb && kk < n && j < b) ? X[kk * ldx + j] : 0.f;
+            }
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+                for (int q = 0; q < 6; ++q)
+                    if (q < nb) acc[rb][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][s4], xv[q], acc[rb][q], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            if (q >= nb) continue;
+            const int col = 16 * q + c16;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t row = r0 + 16 * rb + 4 * g + r;
+                if (row < m && col < b) Y[row * ldy + col] = acc[rb][q][r];
+            }
+        }
+}
+
+// Zp[chunk][c][j] = sum over the chunk's rows r of A[r][c] Q[r][j], computed
+// as Z^T = Q^T A on the matrix cores (A operand Q^T, B operand A): per
+// 4-row slab, lane l loads one float4 of A -- row r0 + l/16, columns
+// c0 + 4 (l%16) + 0..3 (4 rows x 256 B per wave instruction) -- and feeds
+// element j to the MFMA of column set j (columns c0 + 4 n + j).  A block
+// covers 64 columns; its four waves take interleaved slabs of the chunk and
+// are summed in a fixed order through LDS; FP32 accumulation within the
+// chunk, FP64 partials out.  grid (ceil(n / 64), chunks); lda % 4 == 0.
+__global__ void __launch_bounds__(kThreads) k_gemm_tn_mfma(const float* __restrict__ A, int64_t lda,
+                                                           const float* __restrict__ Q, int ldq,
+                                                           double* __restrict__ Zp, int64_t m, int64_t n, int b,
+                                                           int64_t rows_per_chunk) {
+    typedef __attribute__((address_space(1))) const mm_v4f gc4;
+    __shared__ float red[64][kMaxBlock + 1];
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int g = l >> 4, c16 = l & 15;
+    const int64_t c0 = (int64_t)blockIdx.x * 64;
+    const int64_t ra = (int64_t)blockIdx.y * rows_per_chunk;
+    const int64_t rb = min(m, ra + rows_per_chunk);
+    const int nb = (b + 15) / 16;
+    const int64_t cc = c0 + 4 * c16;
+    mm_v4f acc[6][4];
+#pragma unroll
+    for (int q = 0; q < 6; ++q)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[q][j] = (mm_v4f){0.f, 0.f, 0.f, 0.f};
+    for (int64_t s0 = ra + 4 * w; s0 < rb; s0 += 16) {
+        const int64_t row = s0 + g;
+        mm_v4f a = (mm_v4f){0.f, 0.f, 0.f, 0.f};
+        if (row < rb && cc < n) {
+            a = *(gc4*)(A + row * lda + cc);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (cc + j >= n) a[j] = 0.f;
+        }
+        float yv[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            const int jj = 16 * q + c16;
+            yv[q] = (q < nb && row < rb && jj < b) ? Q[row * ldq + jj] : 0.f;
+        }
+#pragma unroll
+        for (int q = 0; q < 6; ++q)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (q < nb) acc[q][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(yv[q], a[j], acc[q][j], 0, 0, 0);
+    }
+    // acc[q][j][r] = Z[c0 + 4 c16 + j][16 q + 4 g + r]; waves summed in order
+    for (int ww = 0; ww < 4; ++ww) {
+        if (w == ww) {
+#pragma unroll
+            for (int q = 0; q < 6; ++q) {
+                if (q >= nb) continue;
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int jj = 16 * q + 4 * g + r;
+                        float& d = red[4 * c16 + j][jj];
+                        d = (ww == 0 ? 0.f : d) + acc[q][j][r];
+                    }
+            }
+        }
+        __syncthreads();
+    }
+    for (int e = threadIdx.x; e < 64 * b; e += kThreads) {
+        const int ci = e / b, jj = e % b;
+        const int64_t c = c0 + ci;
+        if (c < n) Zp[((int64_t)blockIdx.y * n + c) * b + jj] = (double)red[ci][jj];
+    }
+}
+
+// Gp[block] = Y[rows of block]^T Y[rows of block] (b x b) on the FP64 matrix
+// cores: the storage-type products are exact in FP64 and accumulate in FP64.
+// kGramRows rows per block, staged 64 at a time; wave w owns the output
+// 16 x 16 blocks w, w + 4, ... of the (b/16)^2.  Y row-major, or in the
+// tiled basis layout when TILED.
+template <typename T, bool TILED = false>
+__global__ void __launch_bounds__(kThreads) k_gram_mfma(const T* __restrict__ Y, int ldy, int64_t rows, int b,
+                                                        double* __restrict__ Gp) {
+    __shared__ double sY[64][kMaxBlock + 1];
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int nb = (b + 15) / 16, nblk = nb * nb;
+    const int64_t ra = (int64_t)blockIdx.x * kGramRows;
+    const int64_t rb = min(rows, ra + kGramRows);
+    mm_v4d acc[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) acc[t] = (mm_v4d){0.0, 0.0, 0.0, 0.0};
+    for (int64_t r0 = ra; r0 < rb; r0 += 64) {
+        for (int e = threadIdx.x; e < 64 * kMaxBlock; e += kThreads) {
+            const int rr = e / kMaxBlock, j = e % kMaxBlock;
+            const int64_t r = r0 + rr;
+            sY[rr][j] = (r < rb && j < b) ? (double)Y[TILED ? uvo(r, j, ldy) : r * ldy + j] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int kk = 0; kk < 16; ++kk) {
+            const int rr = 4 * kk + (l >> 4);
+#pragma unroll
+            for (int t = 0; t < 9; ++t) {
+                const int q = w + 4 * t;
+                if (q < nblk) {
+                    const int ib = q / nb, jb = q % nb;
+                    acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(sY[rr][16 * ib + (l & 15)], sY[rr][16 * jb + (l & 15)],
+                                                                  acc[t], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    double* out = Gp + (int64_t)blockIdx.x * b * b;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        const int q = w + 4 * t;
+        if (q >= nblk) continue;
+        const int ib = q / nb, jb = q % nb;
+        const int col = 16 * jb + (l & 15);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = 16 * ib + 4 * r + (l >> 4);
+            if (row < b && col < b) out[row * b + col] = acc[t][r];
+        }
+    }
+}
+
 // out[e] = sum_p P[p * stride + e] in part order; converted to Tout
 template <typename Tout>
 __global__ void k_sum_parts(const double* __restrict__ P, int nparts, int64_t stride, int64_t count,
@@ -177,60 +380,73 @@ __global__ void __launch_bounds__(kThreads) k_gram_partial(const T* __restrict__
 // row of R and its row and column of R^{-1} are zero, so the orthonormalised
 // block has a zero column there and Y = Q R still holds.  `flag` bit 0 is set
 // when a column was dropped.
+// Right-looking: step j takes the pivot, scales row j and updates the
+// trailing upper triangle with all threads; R^{-1} row by row from the
+// bottom, each step's entries in parallel.  Launched with kCholThreads.
 template <typename T>
-__global__ void __launch_bounds__(kThreads) k_chol_inv(const double* __restrict__ G, int b,
+__global__ void __launch_bounds__(kCholThreads) k_chol_inv(const double* __restrict__ G, int b,
                                                        double* __restrict__ Rout, T* __restrict__ RinvT,
                                                        int* __restrict__ flag) {
     extern __shared__ double sh[];
-    double* R = sh;                 // b x b row-major, becomes upper R
+    double* R = sh;                 // b x b row-major: the upper triangle becomes R
     double* Ri = sh + b * b;        // b x b inverse
     __shared__ int s_drop[kMaxBlock];
-    for (int e = threadIdx.x; e < b * b; e += kThreads) { R[e] = G[e]; Ri[e] = 0.0; }
+    __shared__ double s_piv;
+    for (int e = threadIdx.x; e < b * b; e += blockDim.x) { R[e] = G[e]; Ri[e] = 0.0; }
     __syncthreads();
     const double tol = 4.0 * b * 2.220446049250313e-16;
     for (int j = 0; j < b; ++j) {
-        // R[j][j] = sqrt(G[j][j] - sum_{i<j} R[i][j]^2), row j right of diagonal
         if (threadIdx.x == 0) {
             const double gjj = G[j * b + j];
-            double d = R[j * b + j];
-            for (int i = 0; i < j; ++i) d -= R[i * b + j] * R[i * b + j];
+            const double d = R[j * b + j];           // G_jj minus the updates of steps < j
             const int drop = (d > tol * gjj && gjj > 1e-300) ? 0 : 1;
             s_drop[j] = drop;
-            R[j * b + j] = drop ? 0.0 : sqrt(d);
+            s_piv = drop ? 0.0 : sqrt(d);
             if (drop) atomicOr(flag, 1);
         }
         __syncthreads();
+        const double piv = s_piv;
         const bool drop = s_drop[j] != 0;
-        for (int c = j + 1 + threadIdx.x; c < b; c += kThreads) {
-            if (drop) {
-                R[j * b + c] = 0.0;
-            } else {
-                double s = R[j * b + c];
-                for (int i = 0; i < j; ++i) s -= R[i * b + j] * R[i * b + c];
-                R[j * b + c] = s / R[j * b + j];
+        // row j: R[j][c] = S[j][c] / piv (zero when dropped)
+        for (int c = j + threadIdx.x; c < b; c += blockDim.x)
+            R[j * b + c] = drop ? 0.0 : (c == j ? piv : R[j * b + c] / piv);
+        __syncthreads();
+        if (!drop) {
+            // trailing update of the upper triangle: S[i][c] -= R[j][i] R[j][c], j < i <= c
+            const int t = b - j - 1;
+            for (int e = threadIdx.x; e < t * t; e += blockDim.x) {
+                const int i = j + 1 + e / t, c = j + 1 + e % t;
+                if (c >= i) R[i * b + c] -= R[j * b + i] * R[j * b + c];
             }
         }
         __syncthreads();
     }
     // zero the strict lower triangle (it still holds G)
-    for (int e = threadIdx.x; e < b * b; e += kThreads) {
-        int i = e / b, c = e % b;
+    for (int e = threadIdx.x; e < b * b; e += blockDim.x) {
+        const int i = e / b, c = e % b;
         if (i > c) R[e] = 0.0;
     }
     __syncthreads();
-    // columns of R^{-1} by back substitution, one column per thread; dropped
-    // rows and columns stay zero
-    for (int c = threadIdx.x; c < b; c += kThreads) {
-        if (s_drop[c]) continue;
-        for (int i = c; i >= 0; --i) {
-            if (s_drop[i]) continue;
-            double s = (i == c) ? 1.0 : 0.0;
-            for (int l = i + 1; l <= c; ++l) s -= R[i * b + l] * Ri[l * b + c];
-            Ri[i * b + c] = s / R[i * b + i];
+    // R^{-1}, rows from the bottom: Ri[i][c] = -(sum_{i<l<=c} R[i][l] Ri[l][c]) / R[i][i],
+    // Ri[i][i] = 1 / R[i][i]; dropped rows and columns stay zero
+    for (int i = b - 1; i >= 0; --i) {
+        if (!s_drop[i]) {
+            const double rii = R[i * b + i];
+            for (int c = i + threadIdx.x; c < b; c += blockDim.x) {
+                if (s_drop[c]) continue;
+                double s0 = 0.0, s1 = 0.0;
+                int l = i + 1;
+                for (; l + 1 <= c; l += 2) {
+                    s0 += R[i * b + l] * Ri[l * b + c];
+                    s1 += R[i * b + l + 1] * Ri[(l + 1) * b + c];
+                }
+                if (l <= c) s0 += R[i * b + l] * Ri[l * b + c];
+                Ri[i * b + c] = (c == i ? 1.0 : -(s0 + s1)) / rii;
+            }
         }
+        __syncthreads();
     }
-    __syncthreads();
-    for (int e = threadIdx.x; e < b * b; e += kThreads) {
+    for (int e = threadIdx.x; e < b * b; e += blockDim.x) {
         Rout[e] = R[e];
         RinvT[e] = (T)Ri[e];
     }

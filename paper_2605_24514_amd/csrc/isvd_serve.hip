@@ -207,6 +207,18 @@ isvd_status isvd_server_submit(isvd_server* s, int64_t ticket, const isvd_reques
     return ISVD_OK;
 }
 
+isvd_status isvd_server_submit_many(isvd_server* s, int32_t count, const int64_t* tickets, const isvd_request* reqs,
+                                    const double* arrival_s, int64_t* req_ids) {
+    if (!s || count < 0 || (count > 0 && (!tickets || !reqs || !arrival_s))) return sfail(s, ISVD_E_INVAL, "null argument");
+    for (int32_t q = 0; q < count; ++q) {
+        int64_t id = -1;
+        isvd_status rc = isvd_server_submit(s, tickets[q], &reqs[q], arrival_s[q], &id);
+        if (rc != ISVD_OK) return rc;
+        if (req_ids) req_ids[q] = id;
+    }
+    return ISVD_OK;
+}
+
 isvd_status isvd_server_step(isvd_server* s, int32_t* launched) {
     if (!s) return ISVD_E_INVAL;
     if (launched) *launched = 0;

@@ -89,7 +89,7 @@ EXPORTS = ["isvd_engine_create", "isvd_engine_destroy", "isvd_stream_bytes", "is
            "isvd_get_factors", "isvd_get_matrix", "isvd_shape", "isvd_release", "isvd_tick",
            "isvd_profile", "isvd_profile_read", "isvd_autotune", "isvd_set_rotation_variant", "isvd_sync", "isvd_rotation_stream", "isvd_set_pipelining",
            "isvd_server_create", "isvd_server_destroy", "isvd_server_clock", "isvd_server_error",
-           "isvd_server_add_stream", "isvd_server_submit", "isvd_server_step", "isvd_server_drain",
+           "isvd_server_add_stream", "isvd_server_submit", "isvd_server_submit_many", "isvd_server_step", "isvd_server_drain",
            "isvd_server_poll", "isvd_server_stats", "isvd_server_stream", "isvd_last_error"]
 
 _lib = None
@@ -133,6 +133,8 @@ def load_library(path=LIB_PATH):
         "isvd_server_error": (ctypes.c_char_p, [vp]),
         "isvd_server_add_stream": (i32, [vp, ctypes.POINTER(CConfig), vp, i64, i32, i64, ctypes.POINTER(i64)]),
         "isvd_server_submit": (i32, [vp, i64, ctypes.POINTER(CRequest), ctypes.c_double, ctypes.POINTER(i64)]),
+        "isvd_server_submit_many": (i32, [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(CRequest),
+                                          ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]),
         "isvd_server_step": (i32, [vp, ctypes.POINTER(i32)]),
         "isvd_server_drain": (i32, [vp]),
         "isvd_server_poll": (i32, [vp, ctypes.POINTER(CCompletion), i32, ctypes.POINTER(i32)]),
@@ -478,6 +480,18 @@ class Server:
         if kind != ENTRY:
             self._keep[rid.value] = keep
         return rid.value
+
+    def submit_many(self, tickets, reqs, arrivals):
+        """tickets: int64 array, reqs: a CRequest array (payloads kept alive by the
+        caller until completion), arrivals: float64 array."""
+        t = np.ascontiguousarray(tickets, dtype=np.int64)
+        a = np.ascontiguousarray(arrivals, dtype=np.float64)
+        n = len(t)
+        if n == 0:
+            return
+        self._check(self._lib.isvd_server_submit_many(
+            self._h, n, t.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), reqs,
+            a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), None), "isvd_server_submit_many")
 
     def step(self):
         n = ctypes.c_int32()
