@@ -75,7 +75,11 @@ enum { ISVD_DTYPE_F32 = 0, ISVD_DTYPE_F64 = 1 };
  * re-orthogonalisation pass and all trackers are FP64 in every mode. */
 enum {
     ISVD_FP64 = 0,          /* A, U, V and all products in FP64 */
-    ISVD_FP32 = 1           /* A, U, V, projections and rotations in FP32 */
+    ISVD_FP32 = 1,          /* A, U, V, projections and rotations in FP32 */
+    ISVD_BF16ROT = 2        /* as ISVD_FP32, but the U / V rotations of ranks up to 64 on the
+                               BF16 matrix cores (operands rounded to BF16, FP32 accumulation):
+                               faster, with an orthogonality drift of about 2^-8 per update
+                               that refreshes repair */
 };
 
 enum { ISVD_ROW = 0, ISVD_COL = 1, ISVD_ENTRY = 2 };
@@ -109,7 +113,7 @@ typedef struct {
     int64_t m0, n0;         /* shape of A_0 */
     int64_t m_cap, n_cap;   /* capacity: largest m_t / n_t the stream may reach (>= m0, n0) */
     int32_t k;              /* target rank, 1 <= k <= min(m0, n0, 96) */
-    int32_t precision;      /* ISVD_FP64 / ISVD_FP32 */
+    int32_t precision;      /* ISVD_FP64 / ISVD_FP32 / ISVD_BF16ROT */
     double tol_rel;         /* new direction iff rho > tol_rel * ||x|| (0 = 1e-10 FP64, 1e-5 FP32) */
     int32_t refresh_iters;  /* subspace iterations per refresh (-1 = default) */
     int32_t oversample;     /* refresh block size = min(n, k + oversample) (-1 = default) */

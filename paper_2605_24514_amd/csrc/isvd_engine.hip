@@ -78,6 +78,7 @@ struct Layout {
 struct Stream {
     isvd_config cfg;
     int esz = 4;          // bytes per storage element
+    bool bf16 = false;    // rotations on the BF16 matrix cores
     int kc = 64;          // rank bucket (capacity of U / V rows)
     int k_target = 0;     // rank the truncation keeps
     int64_t m = 0, n = 0, t = 0;
@@ -160,6 +161,7 @@ struct Slot {
 // A group of requests of one (storage type, rank bucket), laid out in a slot.
 struct Group {
     bool fp64;
+    bool bf16 = false;         // FP32 storage, BF16 rotation products
     int kc;
     int rows = 0;              // rotation rows per block
     int var = 1;               // FP32 rotation block shape (kRotVariant index)
@@ -300,6 +302,11 @@ isvd_status launch_group_phase(const Group& g, const char* dev, int phase, hipSt
         if (nb == 0) return ISVD_OK;
         if constexpr (sizeof(T) == 4 && KC <= 64) {
             static_assert(kRotVariants == 5, "variant dispatch");
+            if (g.bf16) {
+                k_rotate_mfma_t<KC, 512, 1, true, true><<<nb, kThreads, 0, st>>>(all, pr, na, part);
+                HIP_TRY(hipGetLastError());
+                return ISVD_OK;
+            }
             switch (g.var) {
                 case 0: k_rotate_mfma_t<KC, 256, 1, true><<<nb, kThreads, 0, st>>>(all, pr, na, part); break;
                 case 2: k_rotate_mfma_t<KC, 1024, 1, true><<<nb, kThreads, 0, st>>>(all, pr, na, part); break;
@@ -1169,6 +1176,7 @@ isvd_status single_update(isvd_engine* e, Stream& s, int kind, const void* paylo
     std::vector<Group> groups(1);
     Group& g = groups[0];
     g.fp64 = s.esz == 8;
+    g.bf16 = s.bf16;
     g.kc = s.kc;
     g.rows = rows_for(e, g.kc, g.fp64);
     g.var = var_for(e, g.kc, g.fp64);
@@ -1205,7 +1213,8 @@ isvd_status validate_cfg(const isvd_config* c) {
     if (!c) return fail(ISVD_E_INVAL, "null config");
     if (c->m0 < 1 || c->n0 < 1) return fail(ISVD_E_INVAL, "empty A0 (%lld x %lld)", (long long)c->m0, (long long)c->n0);
     if (c->m_cap < c->m0 || c->n_cap < c->n0) return fail(ISVD_E_INVAL, "capacity below the initial shape");
-    if (c->precision != ISVD_FP64 && c->precision != ISVD_FP32) return fail(ISVD_E_INVAL, "bad precision %d", c->precision);
+    if (c->precision != ISVD_FP64 && c->precision != ISVD_FP32 && c->precision != ISVD_BF16ROT)
+        return fail(ISVD_E_INVAL, "bad precision %d", c->precision);
     int kmax = std::max(c->k, c->policy.k_max);
     if (c->k < 1 || c->k > std::min<int64_t>(c->m0, c->n0) || kmax > 96)
         return fail(ISVD_E_INVAL, "k = %d outside [1, min(m0, n0, 96)]", c->k);
@@ -1494,6 +1503,7 @@ static isvd_status init_common(isvd_engine* e, const isvd_config* cfg, const voi
     s->cfg = *cfg;
     if (s->cfg.tol_rel <= 0.0) s->cfg.tol_rel = cfg->precision == ISVD_FP64 ? 1e-10 : 1e-5;
     s->esz = cfg->precision == ISVD_FP64 ? 8 : 4;
+    s->bf16 = cfg->precision == ISVD_BF16ROT;
     s->kc = bucket_for(round4(std::max(cfg->k, cfg->policy.k_max)));
     s->k_target = cfg->k;
     s->angle = cfg->policy.kind == ISVD_POL_ANGLE;
@@ -1835,15 +1845,16 @@ isvd_status isvd_tick(isvd_engine* e, int32_t count, const isvd_request* reqs, v
     }
     pipelined = pipelined && e->pipelining;
     if (reads_u) ST_TRY(join(e, st));
-    std::map<std::pair<int, int>, int> gi;
+    std::map<std::pair<int, int>, int> gi;   // (storage size + BF16 flag, bucket)
     std::vector<Group> groups;
     for (int q = 0; q < count; ++q) {
         Stream& s = *ss[q];
-        auto key = std::make_pair(s.esz, s.kc);
+        auto key = std::make_pair(s.esz * 2 + (s.bf16 ? 1 : 0), s.kc);
         if (!gi.count(key)) {
             gi[key] = (int)groups.size();
             groups.emplace_back();
             groups.back().fp64 = s.esz == 8;
+            groups.back().bf16 = s.bf16;
             groups.back().kc = s.kc;
             groups.back().rows = rows_for(e, s.kc, s.esz == 8);
             groups.back().var = var_for(e, s.kc, s.esz == 8);

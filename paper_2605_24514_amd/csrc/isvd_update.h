@@ -476,6 +476,13 @@ __global__ void __launch_bounds__(kThreads) k_rotate(const Req* __restrict__ req
 // group); Q sits in LDS in the same order.  Output lane layout of the
 // 16x16x4 FP32 instruction: D[4*(l/16) + r][l%16].  FP32 accumulation.
 typedef float mfma_v4f __attribute__((ext_vector_type(4)));
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+
+// FP32 -> BF16 bits, rounded to nearest even (finite inputs)
+__device__ inline short to_bf16(float f) {
+    const unsigned u = __float_as_uint(f);
+    return (short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
 typedef __attribute__((address_space(1))) const float gcfloat;
 typedef __attribute__((address_space(1))) float gfloat;
 typedef __attribute__((address_space(1))) const mfma_v4f gcf4;
@@ -647,7 +654,11 @@ __global__ void __launch_bounds__(kThreads) k_rotate_mfma(const Req* __restrict_
 // LDS staging.  ROWS rows per block; a wave takes RT consecutive 16-row tiles
 // per step (RT independent accumulator sets); with PF the next step's loads
 // are issued before the current step's MFMAs.
-template <int KC, int ROWS, int RT, bool PF>
+// BF16: the products on the BF16 matrix cores (v_mfma_f32_16x16x16bf16_1k,
+// operands rounded to nearest BF16, FP32 accumulation): lane l holds the 4
+// k values 16 q + 4 (l/16) + 0..3 of a panel, which is exactly that
+// instruction's operand layout, so one MFMA covers a whole panel.
+template <int KC, int ROWS, int RT, bool PF, bool BF16 = false>
 __global__ void __launch_bounds__(kThreads) k_rotate_mfma_t(const Req* __restrict__ reqs,
                                                             const int* __restrict__ prefix, int nreq, int part) {
     constexpr int NQ = (KC + 15) / 16;           // panels (loads per lane per tile)
@@ -678,14 +689,17 @@ __global__ void __launch_bounds__(kThreads) k_rotate_mfma_t(const Req* __restric
     const int wave = threadIdx.x >> 6;
     const int g = l >> 4, n = l & 15;
     // Q^T in registers: qa[nb][s] = Q[k(s)][16 nb + n]
-    float qa[NB][STEPS];
+    float qa[NB][BF16 ? 1 : STEPS];
+    bf16x4 qb[NB][BF16 ? NQ : 1];
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
         for (int s4 = 0; s4 < STEPS; ++s4) {
             const int k = 16 * (s4 >> 2) + 4 * g + (s4 & 3);
             const int c = 16 * nb + n;
-            qa[nb][s4] = (k < kin && c < ldo) ? Q[k * ldo + c] : 0.0f;
+            const float v = (k < kin && c < ldo) ? Q[k * ldo + c] : 0.0f;
+            if constexpr (BF16) qb[nb][s4 >> 2][s4 & 3] = to_bf16(v);
+            else qa[nb][s4] = v;
         }
     __syncthreads();
     mfma_v4f b[RT][NQ], bn[PF ? RT : 1][NQ];
@@ -720,15 +734,29 @@ __global__ void __launch_bounds__(kThreads) k_rotate_mfma_t(const Req* __restric
         for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) acc[rt][nb] = (mfma_v4f){0.f, 0.f, 0.f, 0.f};
+        if constexpr (BF16) {
 #pragma unroll
-        for (int s4 = 0; s4 < STEPS; ++s4)
+            for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-            for (int rt = 0; rt < RT; ++rt) {
-                const float bv = b[rt][s4 >> 2][s4 & 3];
+                for (int q = 0; q < NQ; ++q) {
+                    bf16x4 xb;
 #pragma unroll
-                for (int nb = 0; nb < NB; ++nb)
-                    acc[rt][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(qa[nb][s4], bv, acc[rt][nb], 0, 0, 0);
-            }
+                    for (int j = 0; j < 4; ++j) xb[j] = to_bf16(b[rt][q][j]);
+#pragma unroll
+                    for (int nb = 0; nb < NB; ++nb)
+                        acc[rt][nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(qb[nb][q], xb, acc[rt][nb], 0, 0, 0);
+                }
+        } else {
+#pragma unroll
+            for (int s4 = 0; s4 < STEPS; ++s4)
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt) {
+                    const float bv = b[rt][s4 >> 2][s4 & 3];
+#pragma unroll
+                    for (int nb = 0; nb < NB; ++nb)
+                        acc[rt][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(qa[nb][s4], bv, acc[rt][nb], 0, 0, 0);
+                }
+        }
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt) {
             const int64_t t0 = row0 + 16 * rt;

@@ -14,7 +14,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libisvd.so")
 
-ISVD_FP64, ISVD_FP32 = 0, 1
+ISVD_FP64, ISVD_FP32, ISVD_BF16ROT = 0, 1, 2
 DTYPE_F32, DTYPE_F64 = 0, 1
 ROW, COL, ENTRY = 0, 1, 2
 POL_NONE, POL_PERIODIC, POL_ERROR, POL_ANGLE, POL_ADAPTIVE = 0, 1, 2, 3, 4
@@ -233,7 +233,7 @@ class Engine:
     @staticmethod
     def config(m0, n0, k, precision="fp32", m_cap=None, n_cap=None, tol_rel=0.0, policy=None,
                refresh_iters=-1, oversample=-1):
-        prec = {"fp32": ISVD_FP32, "fp64": ISVD_FP64}[precision]
+        prec = {"fp32": ISVD_FP32, "fp64": ISVD_FP64, "bf16rot": ISVD_BF16ROT}[precision]
         pol = (policy or Policy()).to_c()
         return CConfig(m0, n0, m_cap or m0, n_cap or n0, k, prec, tol_rel, refresh_iters, oversample, pol)
 

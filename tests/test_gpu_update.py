@@ -186,3 +186,33 @@ def test_rank_deficient_input(isvd, precision, bar):
         A1 = np.vstack([A0, 50.0 * x[None, :]])
         assert np.linalg.norm(A1 - (U * S) @ V.T) <= 10 * bar * np.linalg.norm(A1)
         assert np.abs(U.T @ U - np.eye(4)).max() <= 10 * bar
+
+
+def test_bf16_rotations_drift_and_refresh_repairs(isvd):
+    """The BF16 rotation option (FP32 storage, BF16 matrix-core products with
+    FP32 accumulation): its error against the FP64 oracle stays at the BF16
+    level over a mixed run, and a refresh (exact here: the block spans all
+    columns) brings it back to FP32 accuracy, since A itself is kept in FP32."""
+    fs = FactorStream(seed=9, stream=0, n0=60, K=5)
+    A0 = fs.initial(800)
+    events = fs.materialize([ROW, ROW, COL, ENTRY, ROW] * 6, m0=800)
+    o = OracleEngine(A0, 16, tol_rel=1e-5, cgs2=True)
+    with isvd.Engine() as eng:
+        sb = eng.init(A0, 16, precision="bf16rot", m_cap=900, n_cap=80, oversample=64)
+        sf = eng.init(A0, 16, precision="fp32", m_cap=900, n_cap=80, oversample=64)
+        for ev in events:
+            _apply_gpu(eng, sb, ev)
+            _apply_gpu(eng, sf, ev)
+            o.step(ev)
+        cb = compare(eng.factors(sb), _oracle_state(o))
+        cf = compare(eng.factors(sf), _oracle_state(o))
+        print("bf16", cb)
+        print("fp32", cf)
+        assert cf["recon"] <= 2e-5
+        assert cb["recon"] <= 3e-2 and cb["sigma"] <= 3e-2
+        assert cb["recon"] > cf["recon"]               # the option really runs in BF16
+        eng.refresh(sb)
+        o.refresh()
+        cr = compare(eng.factors(sb), _oracle_state(o))
+        print("bf16 after refresh", cr)
+        assert cr["recon"] <= 2e-5, cr
