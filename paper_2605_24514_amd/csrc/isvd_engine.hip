@@ -363,6 +363,7 @@ isvd_status set_lds_limits() {
     const size_t svd_lds = core_lds_bytes(kMaxBlock, JacobiShape<kMaxBlock + 1>::LDW, true);
     ST_TRY(allow_lds(k_svd_small<float>, svd_lds));
     ST_TRY(allow_lds(k_svd_small<double>, svd_lds));
+    ST_TRY(allow_lds(k_svd_small_noj<float>, sizeof(double) * svd_noj_lds_doubles()));
     ST_TRY(allow_lds(k_sym_norm2, sym_norm2_lds(kMaxBlock)));
     ST_TRY(allow_lds(k_track<float>, sizeof(double) * 2 * kMaxCore * kMaxBlock));
     ST_TRY(allow_lds(k_track<double>, sizeof(double) * 2 * kMaxCore * kMaxBlock));
@@ -818,7 +819,12 @@ isvd_status refresh_compute(isvd_engine* e, Stream& s, bool init, hipStream_t st
     gemm_nn<T>(A, lda, X, Y, m, n, b, st);
     ST_TRY(cholqr2<T>(e, w, Y, m, b, true, st));
     const int ldo = round4(k);
-    k_svd_small<T><<<1, JacobiShape<kMaxBlock + 1>::NT,
+    if constexpr (sizeof(T) == 4)
+        k_svd_small_noj<T><<<1, RRShape::NT, sizeof(double) * svd_noj_lds_doubles(), st>>>(
+            (const double*)(ws + w.Racc), b, k, (double*)(ws + w.Sr), (T*)(ws + w.QU), (T*)(ws + w.QV), ldo,
+            (int*)(ws + w.sweeps));
+    else
+        k_svd_small<T><<<1, JacobiShape<kMaxBlock + 1>::NT,
                      core_lds_bytes(kMaxBlock, JacobiShape<kMaxBlock + 1>::LDW, true), st>>>(
         (const double*)(ws + w.Racc), b, k, (double*)(ws + w.Sr), (T*)(ws + w.QU), (T*)(ws + w.QV), ldo,
         (int*)(ws + w.sweeps));

@@ -391,36 +391,40 @@ __global__ void __launch_bounds__(kCholThreads) k_chol_inv(const double* __restr
     double* R = sh;                 // b x b row-major: the upper triangle becomes R
     double* Ri = sh + b * b;        // b x b inverse
     __shared__ int s_drop[kMaxBlock];
-    __shared__ double s_piv;
+    __shared__ double s_dg[kMaxBlock];
     for (int e = threadIdx.x; e < b * b; e += blockDim.x) { R[e] = G[e]; Ri[e] = 0.0; }
     __syncthreads();
     const double tol = 4.0 * b * 2.220446049250313e-16;
+    // unscaled elimination (R holds the Schur complements S; row j of R is
+    // S_j / sqrt(S_jj) at the end): step j reads row j and updates rows below
+    // it only, so one barrier per step suffices
     for (int j = 0; j < b; ++j) {
+        const double gjj = G[j * b + j];
+        const double d = R[j * b + j];
+        const bool drop = !(d > tol * gjj && gjj > 1e-300);
         if (threadIdx.x == 0) {
-            const double gjj = G[j * b + j];
-            const double d = R[j * b + j];           // G_jj minus the updates of steps < j
-            const int drop = (d > tol * gjj && gjj > 1e-300) ? 0 : 1;
-            s_drop[j] = drop;
-            s_piv = drop ? 0.0 : sqrt(d);
+            s_drop[j] = drop ? 1 : 0;
             if (drop) atomicOr(flag, 1);
         }
-        __syncthreads();
-        const double piv = s_piv;
-        const bool drop = s_drop[j] != 0;
-        // row j: R[j][c] = S[j][c] / piv (zero when dropped)
-        for (int c = j + threadIdx.x; c < b; c += blockDim.x)
-            R[j * b + c] = drop ? 0.0 : (c == j ? piv : R[j * b + c] / piv);
-        __syncthreads();
         if (!drop) {
-            // trailing update of the upper triangle: S[i][c] -= R[j][i] R[j][c], j < i <= c
+            const double inv_d = 1.0 / d;
             const int t = b - j - 1;
             for (int e = threadIdx.x; e < t * t; e += blockDim.x) {
                 const int i = j + 1 + e / t, c = j + 1 + e % t;
-                if (c >= i) R[i * b + c] -= R[j * b + i] * R[j * b + c];
+                if (c >= i) R[i * b + c] -= R[j * b + i] * R[j * b + c] * inv_d;
             }
         }
         __syncthreads();
     }
+    // scale the rows (dropped ones to zero)
+    for (int j = threadIdx.x; j < b; j += blockDim.x) s_dg[j] = s_drop[j] ? 0.0 : sqrt(R[j * b + j]);
+    __syncthreads();
+    for (int e = threadIdx.x; e < b * b; e += blockDim.x) {
+        const int j = e / b, c = e % b;
+        if (c < j) continue;
+        R[e] = s_drop[j] ? 0.0 : R[e] / s_dg[j];
+    }
+    __syncthreads();
     // zero the strict lower triangle (it still holds G)
     for (int e = threadIdx.x; e < b * b; e += blockDim.x) {
         const int i = e / b, c = e % b;
@@ -525,6 +529,75 @@ __global__ void __launch_bounds__(JacobiShape<kMaxBlock + 1>::NT) k_svd_small(co
     }
     for (int j = threadIdx.x; j < k; j += blockDim.x) S[j] = sig[j];
     if (threadIdx.x == 0) *sweeps_out = sweeps;
+}
+
+// FP32-storage Rayleigh-Ritz core: the same SVD of R without accumulating the
+// rotations (half the LDS, so eight lanes per pair fit): W = R J with
+// orthogonal columns, U_K = W diag(1/sigma), and the right vectors from
+// R^T W = J diag(sigma^2), i.e. v_j = R^T w_j / sigma_j^2 (R re-read from
+// global memory).  Their loss of orthogonality, about b eps64 sigma_1 / sigma_j,
+// stays far below FP32 rounding for the kept triplets.
+typedef JacobiShape<kMaxBlock + 1, 8> RRShape;
+template <typename T>
+__global__ void __launch_bounds__(RRShape::NT) k_svd_small_noj(const double* __restrict__ R, int b, int k,
+                                                              double* __restrict__ S, T* __restrict__ QU,
+                                                              T* __restrict__ QV, int ldo,
+                                                              int* __restrict__ sweeps_out) {
+    extern __shared__ double smem[];
+    const int N = b;
+    const int ldw = RRShape::LDW;
+    double* W = smem;                                   // (N + 1) columns
+    double* sig = W + (size_t)(N + 1) * ldw;
+    double* sgn = sig + N;
+    double* tmp = sgn + N;
+    int* perm = (int*)(tmp + N);
+    double* vmax = tmp + 2 * N;                         // per output column: signed largest entry
+    for (int e = threadIdx.x; e < (N + 1) * ldw; e += blockDim.x) {
+        const int col = e / ldw, row = e % ldw;
+        W[e] = (row < N && col < N) ? R[row * N + col] : 0.0;
+    }
+    __syncthreads();
+    const int sweeps = jacobi_block<kMaxBlock + 1, false, 8>(W, nullptr, N, ldw, 60);
+    jacobi_sort(W, N, ldw, sig, perm, tmp);
+    // sign: the largest-magnitude entry of each right vector positive
+    for (int j = threadIdx.x; j < k; j += blockDim.x) {
+        const int c = perm[j];
+        const double s2 = sig[j] * sig[j];
+        double best = 0.0;
+        for (int e = 0; e < N; ++e) {
+            double v = 0.0;
+            for (int i = 0; i < N; ++i) v += R[i * N + e] * W[(size_t)c * ldw + i];
+            v = s2 > 0.0 ? v / s2 : 0.0;
+            if (fabs(v) > fabs(best)) best = v;
+        }
+        vmax[j] = best;
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < k; j += blockDim.x) sgn[j] = vmax[j] < 0.0 ? -1.0 : 1.0;
+    __syncthreads();
+    for (int e = threadIdx.x; e < N * ldo; e += blockDim.x) {
+        const int row = e / ldo, j = e % ldo;
+        double uk = 0.0, vk = 0.0;
+        if (j < k) {
+            const int c = perm[j];
+            const double s = sig[j];
+            if (s > 0.0) {
+                uk = sgn[j] * W[(size_t)c * ldw + row] / s;
+                double v = 0.0;
+                for (int i = 0; i < N; ++i) v += R[i * N + row] * W[(size_t)c * ldw + i];
+                vk = sgn[j] * v / (s * s);
+            }
+        }
+        QU[e] = (T)uk;
+        QV[e] = (T)vk;
+    }
+    for (int j = threadIdx.x; j < k; j += blockDim.x) S[j] = sig[j];
+    if (threadIdx.x == 0) *sweeps_out = sweeps;
+}
+
+// dynamic LDS of k_svd_small_noj for b <= kMaxBlock
+__host__ __device__ constexpr size_t svd_noj_lds_doubles() {
+    return (size_t)(kMaxBlock + 1) * RRShape::LDW + 6 * kMaxBlock;
 }
 
 // Start block: X[:, 0:kw] = V[:, 0:kw] (warm start), the remaining columns a
