@@ -369,8 +369,6 @@ isvd_status set_lds_limits() {
     ST_TRY(allow_lds(k_track<double>, sizeof(double) * 2 * kMaxCore * kMaxBlock));
     ST_TRY(allow_lds(k_theta_tracks, sizeof(double) * theta_lds_doubles()));
     ST_TRY(allow_lds(k_theta_direct, sizeof(double) * theta_lds_doubles()));
-    ST_TRY(allow_lds(k_chol_inv<float>, sizeof(double) * 2 * kMaxBlock * kMaxBlock));
-    ST_TRY(allow_lds(k_chol_inv<double>, sizeof(double) * 2 * kMaxBlock * kMaxBlock));
     return ISVD_OK;
 }
 
@@ -661,11 +659,13 @@ WsLayout ws_layout(int64_t m, int64_t n, int b, int esz) {
         return o;
     };
     const int64_t nchunk_tn = std::min<int64_t>(32, cdiv(m, kGemmK));
-    const int64_t nchunk_g = cdiv(std::max(m, n), kGramRows);
+    const int64_t nchunk_g = gram_parts_max(std::max(m, n));
     w.X = take((size_t)esz * n * b);
     w.Y = take((size_t)esz * m * b);
-    w.Zp = take(sizeof(double) * (size_t)nchunk_tn * n * b);
-    w.Gp = take(sizeof(double) * (size_t)nchunk_g * b * b);
+    const int64_t ncb = cdiv(n, kTnCols);
+    w.Zp = take(esz == 4 ? sizeof(float) * (size_t)tn_chunks(m, n) * ncb * kTnDump
+                         : sizeof(double) * (size_t)nchunk_tn * n * b);
+    w.Gp = take(sizeof(double) * (size_t)nchunk_g * gram_tiles(b) * 256);
     w.G = take(sizeof(double) * b * b);
     w.R = take(sizeof(double) * b * b);
     w.Racc = take(sizeof(double) * b * b);
@@ -717,8 +717,53 @@ __global__ void k_set_header(DevHeader* hdr, int k, int ld, int flip, int bump_t
     }
 }
 
+// Y = A X on the matrix cores (FP32); the kernels are specialised on the
+// number of 16-column tiles of X
+template <int RB>
+void gemm_nn_rb(const float* A, int64_t lda, const float* X, float* Y, int ldy, int64_t m, int64_t n, int b,
+                hipStream_t st) {
+    const int grid = (int)cdiv(m, 64 * RB);
+#define ISVD_NN(NB) k_gemm_nn_mfma<RB, NB><<<grid, kThreads, 0, st>>>(A, lda, X, Y, ldy, m, n, b)
+    switch ((b + 15) / 16) {
+        case 1: ISVD_NN(1); break;
+        case 2: ISVD_NN(2); break;
+        case 3: ISVD_NN(3); break;
+        case 4: ISVD_NN(4); break;
+        case 5: ISVD_NN(5); break;
+        default: ISVD_NN(6); break;
+    }
+#undef ISVD_NN
+}
+// X is n x b with leading dimension b
+void gemm_nn_f32(const float* A, int64_t lda, const float* X, float* Y, int ldy, int64_t m, int64_t n, int b,
+                 hipStream_t st) {
+    gemm_nn_rb<2>(A, lda, X, Y, ldy, m, n, b, st);
+}
+// partial dumps of Z = A^T Q on the matrix cores (FP32)
+// Q is m x b with leading dimension b
+void gemm_tn_f32(const float* A, int64_t lda, const float* Q, float* Zp, int64_t m, int64_t n, int b, int64_t nch,
+                 hipStream_t st) {
+    const dim3 grid((unsigned)cdiv(n, kTnCols), (unsigned)nch);
+    const int64_t rpc = cdiv(m, nch);
+#define ISVD_TN(NB) k_gemm_tn_mfma<NB><<<grid, kThreads, 0, st>>>(A, lda, Q, Zp, m, n, b, rpc)
+    switch ((b + 15) / 16) {
+        case 1: ISVD_TN(1); break;
+        case 2: ISVD_TN(2); break;
+        case 3: ISVD_TN(3); break;
+        case 4: ISVD_TN(4); break;
+        case 5: ISVD_TN(5); break;
+        default: ISVD_TN(6); break;
+    }
+#undef ISVD_TN
+}
+
+// Y <- Q with Y = Q R: `passes` CholQR passes (2 = CholQR2, orthonormal to
+// working precision; 1 leaves an orthogonality error of about kappa(Y) times
+// the storage epsilon, which is all an intermediate block of the subspace
+// iteration needs: only its span is used).
 template <typename T>
-isvd_status cholqr2(isvd_engine* e, const WsLayout& w, T* Y, int64_t rows, int b, bool want_R, hipStream_t st) {
+isvd_status cholqr(isvd_engine* e, const WsLayout& w, T* Y, int64_t rows, int b, bool want_R, int passes,
+                   hipStream_t st) {
     char* ws = e->ws;
     double* Gp = (double*)(ws + w.Gp);
     double* G = (double*)(ws + w.G);
@@ -727,14 +772,14 @@ isvd_status cholqr2(isvd_engine* e, const WsLayout& w, T* Y, int64_t rows, int b
     double* Rtmp = (double*)(ws + w.Rtmp);
     T* RinvT = (T*)(ws + w.RinvT);
     int* flag = (int*)(ws + w.flag);
-    const int nchunk = (int)cdiv(rows, kGramRows);
-    for (int pass = 0; pass < 2; ++pass) {
-        k_gram_mfma<T><<<nchunk, kThreads, 0, st>>>(Y, b, rows, b, Gp);
-        k_sum_parts<double><<<(int)cdiv(b * b, 256), 256, 0, st>>>(Gp, nchunk, (int64_t)b * b, (int64_t)b * b, G);
-        k_chol_inv<T><<<1, kCholThreads, sizeof(double) * 2 * b * b, st>>>(G, b, R, RinvT, flag);
+    const int nchunk = (int)gram_parts(rows);
+    for (int pass = 0; pass < passes; ++pass) {
+        k_gram_mfma<T><<<nchunk, kThreads, 0, st>>>(Y, b, rows, b, gram_rpb(rows), Gp);
+        k_gram_sum<<<(int)cdiv(gram_tiles(b) * 256, 32), 256, 0, st>>>(Gp, nchunk, b, G);
+        k_chol_inv<T><<<1, kCholThreads, 0, st>>>(G, b, R, RinvT, flag);
         if constexpr (sizeof(T) == 4) {
             if (b % 4 == 0)
-                k_gemm_nn_mfma<<<(int)cdiv(rows, 128), kThreads, 0, st>>>(Y, b, RinvT, b, Y, b, rows, b, b);
+                gemm_nn_f32(Y, b, RinvT, Y, b, rows, b, b, st);
             else
                 k_rotate_plain<T, 128><<<(int)cdiv(rows, 16), kThreads, 0, st>>>(Y, b, Y, b, rows, b, RinvT);
         } else {
@@ -744,7 +789,7 @@ isvd_status cholqr2(isvd_engine* e, const WsLayout& w, T* Y, int64_t rows, int b
             if (pass == 0) {
                 HIP_TRY(hipMemcpyAsync(Racc, R, sizeof(double) * b * b, hipMemcpyDeviceToDevice, st));
             } else {
-                k_small_gemm<<<1, kThreads, 0, st>>>(R, Racc, Rtmp, b);
+                k_small_gemm<<<(int)cdiv(b * b, 256), 256, 0, st>>>(R, Racc, Rtmp, b);
                 HIP_TRY(hipMemcpyAsync(Racc, Rtmp, sizeof(double) * b * b, hipMemcpyDeviceToDevice, st));
             }
         }
@@ -757,7 +802,7 @@ isvd_status cholqr2(isvd_engine* e, const WsLayout& w, T* Y, int64_t rows, int b
 template <typename T>
 void gemm_nn(const T* A, int64_t lda, const T* X, T* Y, int64_t m, int64_t n, int b, hipStream_t st) {
     if constexpr (sizeof(T) == 4)
-        k_gemm_nn_mfma<<<(int)cdiv(m, 128), kThreads, 0, st>>>(A, lda, X, b, Y, b, m, n, b);
+        gemm_nn_f32(A, lda, X, Y, b, m, n, b, st);
     else
         k_gemm_nn<T><<<(int)cdiv(m, kGemmRows), kThreads, 0, st>>>(A, lda, X, b, Y, b, m, n, b);
 }
@@ -802,22 +847,25 @@ isvd_status refresh_compute(isvd_engine* e, Stream& s, bool init, hipStream_t st
     const int kw = init ? 0 : std::min(h.k, b);
     k_start_block<T><<<(int)cdiv(n * b, 256), 256, 0, st>>>(X, b, n, b, (const T*)s.V[cur], init ? 4 : h.ld, kw,
                                                            0x5eedull + (uint64_t)s.t, exact ? 1 : 0);
-    if (!exact) ST_TRY(cholqr2<T>(e, w, X, n, b, false, st));
+    if (!exact) ST_TRY(cholqr<T>(e, w, X, n, b, false, iters > 0 ? 1 : 2, st));
     const int64_t nchunk = std::min<int64_t>(32, cdiv(m, kGemmK));
     const int64_t rpc = cdiv(m, nchunk);
     for (int it = 0; it < iters; ++it) {
         gemm_nn<T>(A, lda, X, Y, m, n, b, st);
-        ST_TRY(cholqr2<T>(e, w, Y, m, b, false, st));
-        dim3 grid((unsigned)cdiv(n, 64), (unsigned)nchunk);
-        if constexpr (sizeof(T) == 4)
-            k_gemm_tn_mfma<<<grid, kThreads, 0, st>>>(A, lda, Y, b, Zp, m, n, b, rpc);
-        else
+        ST_TRY(cholqr<T>(e, w, Y, m, b, false, 1, st));
+        if constexpr (sizeof(T) == 4) {
+            const int64_t ncb = cdiv(n, kTnCols), nch = tn_chunks(m, n), per = ncb * kTnDump;
+            gemm_tn_f32(A, lda, Y, (float*)Zp, m, n, b, nch, st);
+            k_tn_sum<<<(int)cdiv(per, 256), 256, 0, st>>>((const float*)Zp, (int)nch, per, n, b, X, b);
+        } else {
+            dim3 grid((unsigned)cdiv(n, 64), (unsigned)nchunk);
             k_gemm_tn_partial<T><<<grid, kThreads, 0, st>>>(A, lda, Y, b, Zp, m, n, b, rpc);
-        k_sum_parts<T><<<(int)cdiv(n * b, 256), 256, 0, st>>>(Zp, (int)nchunk, n * b, n * b, X);
-        ST_TRY(cholqr2<T>(e, w, X, n, b, false, st));
+            k_sum_parts<T><<<(int)cdiv(n * b, 256), 256, 0, st>>>(Zp, (int)nchunk, n * b, n * b, X);
+        }
+        ST_TRY(cholqr<T>(e, w, X, n, b, false, it + 1 == iters ? 2 : 1, st));
     }
     gemm_nn<T>(A, lda, X, Y, m, n, b, st);
-    ST_TRY(cholqr2<T>(e, w, Y, m, b, true, st));
+    ST_TRY(cholqr<T>(e, w, Y, m, b, true, 2, st));
     const int ldo = round4(k);
     if constexpr (sizeof(T) == 4)
         k_svd_small_noj<T><<<1, RRShape::NT, sizeof(double) * svd_noj_lds_doubles(), st>>>(
@@ -1011,14 +1059,15 @@ isvd_status exact_metrics_t(isvd_engine* e, Stream& s, hipStream_t st, Exact* ou
     const int k = h.k, ld = h.ld;
     const int64_t nfro = cdiv(m, kFroRows);
     const int64_t nres = cdiv(m, 64) * cdiv(n, 64);
-    const int64_t ngu = cdiv(m, kGramRows), ngv = cdiv(n, kGramRows);
-    const size_t need = sizeof(double) * (size_t)(nfro + nres + (ngu + ngv) * k * k + 2 * k * k + 8);
+    const int64_t ngu = gram_parts(m), ngv = gram_parts(n);
+    const int64_t gsz = (int64_t)gram_tiles(k) * 256;
+    const size_t need = sizeof(double) * (size_t)(nfro + nres + (ngu + ngv) * gsz + 2 * k * k + 8);
     ST_TRY(ensure_mws(e, need));
     double* fro_p = (double*)e->mws;
     double* res_p = fro_p + nfro;
     double* gu_p = res_p + nres;
-    double* gv_p = gu_p + ngu * k * k;
-    double* GU = gv_p + ngv * k * k;
+    double* gv_p = gu_p + ngu * gsz;
+    double* GU = gv_p + ngv * gsz;
     double* GV = GU + k * k;
     double* scal = GV + k * k;
     const T* A = (const T*)s.A;
@@ -1030,10 +1079,10 @@ isvd_status exact_metrics_t(isvd_engine* e, Stream& s, hipStream_t st, Exact* ou
     dim3 rg((unsigned)cdiv(m, 64), (unsigned)cdiv(n, 64));
     k_resid2_partial<T><<<rg, kThreads, 0, st>>>(A, lda, U, V, ld, s.S, m, n, k, res_p);
     k_sum_parts<double><<<1, 1, 0, st>>>(res_p, (int)nres, 1, 1, scal + 1);
-    k_gram_mfma<T, true><<<(int)ngu, kThreads, 0, st>>>(U, ld, m, k, gu_p);
-    k_sum_parts<double><<<(int)cdiv(k * k, 256), 256, 0, st>>>(gu_p, (int)ngu, (int64_t)k * k, (int64_t)k * k, GU);
-    k_gram_mfma<T, true><<<(int)ngv, kThreads, 0, st>>>(V, ld, n, k, gv_p);
-    k_sum_parts<double><<<(int)cdiv(k * k, 256), 256, 0, st>>>(gv_p, (int)ngv, (int64_t)k * k, (int64_t)k * k, GV);
+    k_gram_mfma<T, true><<<(int)ngu, kThreads, 0, st>>>(U, ld, m, k, gram_rpb(m), gu_p);
+    k_gram_sum<<<(int)cdiv(gsz, 32), 256, 0, st>>>(gu_p, (int)ngu, k, GU);
+    k_gram_mfma<T, true><<<(int)ngv, kThreads, 0, st>>>(V, ld, n, k, gram_rpb(n), gv_p);
+    k_gram_sum<<<(int)cdiv(gsz, 32), 256, 0, st>>>(gv_p, (int)ngv, k, GV);
     const int nt = JacobiShape<kMaxBlock + 1>::NT;
     int* sw = (int*)(scal + 6);
     k_sym_norm2<<<1, nt, sym_norm2_lds(k), st>>>(GU, k, scal + 2, sw);
@@ -1566,7 +1615,10 @@ static isvd_status init_common(isvd_engine* e, const isvd_config* cfg, const voi
     h0.ld = 4;
     h0.m = cfg->m0;
     h0.n = cfg->n0;
+    // A is zeroed whole: entries outside the current m x n stay zero (the
+    // refresh products read the padding columns of a row)
     if (hipMemsetAsync(s->base, 0, s->L.U0, st) != hipSuccess ||
+        hipMemsetAsync(s->A, 0, s->L.total - s->L.A, st) != hipSuccess ||
         hipMemcpyAsync(s->hdr, &h0, sizeof(h0), hipMemcpyHostToDevice, st) != hipSuccess)
         return bail(fail(ISVD_E_DEVICE, "header initialisation failed"));
     // A_0 into A (leading dimension lda_of), converting to the storage type

@@ -12,6 +12,7 @@
 // Cholesky and triangular inverse in FP64 in one block, Y <- Y R^{-1},
 // twice.  The small GEMMs here are plain LDS-tiled VALU code.
 #pragma once
+#include <algorithm>
 #include "isvd_common.h"
 #include "isvd_jacobi.h"
 
@@ -19,8 +20,6 @@ namespace isvd {
 
 constexpr int kGemmRows = 64;
 constexpr int kGemmK = 32;
-constexpr int kChunkRows = 1024;
-constexpr int kCholThreads = 1024;   // threads of the one-block Cholesky
 
 // Y[m x b] = A[m x n] X[n x b]   (b <= 128)
 template <typename T>
@@ -125,68 +124,140 @@ __global__ void __launch_bounds__(kThreads) k_gemm_tn_partial(const T* __restric
 // B[l/16][l%16]; FP32 D[4(l/16)+r][l%16], FP64 D[4r+l/16][l%16].
 typedef float mm_v4f __attribute__((ext_vector_type(4)));
 typedef double mm_v4d __attribute__((ext_vector_type(4)));
-constexpr int kMmK = 32;         // k-chunk staged in LDS
-constexpr int kGramRows = 256;   // rows per block of the Gram partials
 
-// Y[m x b] = A[m x n] X[n x b], FP32 in and FP32 accumulation.  A wave owns
-// 32 rows (two 16-row MFMA blocks) and streams them across k on its own (no
-// LDS, no block barriers): per 16-column slab, lane l loads one float4 of A
-// per row block -- row l%16, columns k0 + 4 (l/16) + 0..3, 1 KB per wave
-// instruction -- and the MFMA k order follows (step s takes column
-// k0 + 4 (l/16) + s); X (small, cache-resident) is read in the same order
-// as the B operand and shared by both row blocks.  lda % 4 == 0.  Y may be
-// A itself (ldy == lda): a wave reads all of its rows before it writes them.
-__global__ void __launch_bounds__(kThreads) k_gemm_nn_mfma(const float* A, int64_t lda,
-                                                           const float* __restrict__ X, int ldx,
+// Y[m x b] = A[m x n] X[n x b], FP32 in and FP32 accumulation (b <= 96).  A
+// wave owns RB 16-row MFMA blocks and runs over all of n; a block's four
+// waves share X, staged KCH rows at a time in double-buffered LDS, and each
+// wave prefetches its next KCH columns of A into registers while the matrix
+// cores work on the current ones (one barrier per chunk).  Per 16-column
+// slab lane l loads one float4 of A per row block -- row l%16, columns
+// k0 + 4 (l/16) + 0..3 -- and MFMA step s takes column k0 + 4 (l/16) + s, so
+// the B operand is X[k0 + 4 (l/16) + s][16 q + l%16] from LDS.  X is n x b
+// with leading dimension b.  lda % 4 == 0,
+// and A's columns in [n, round4(n)) must hold finite values (they are read
+// and multiplied by zero).
+// Y may be A itself (ldy == lda): a wave reads all of its rows before it
+// writes them.  grid ceil(m / (64 RB)).
+constexpr int kStageLd = kMaxBlock + 4;   // LDS row stride: the four lane groups hit disjoint banks
+// Copy of ROWS rows of a row-major FP32 matrix whose leading dimension
+// equals its width `cols` (<= W), so the rows form one contiguous run of
+// ROWS cols floats: thread t takes elements t, t + 256, ... of the run
+// (coalesced loads at fixed offsets from one base) and stores them at LDS
+// row stride kStageLd.  Elements past the end of the matrix are stored as
+// zero; LDS columns in [cols, W) are left as they are.  The LDS offsets do
+// not depend on the chunk and are computed once.
+template <int ROWS, int W>
+struct StageCopy {
+    static constexpr int PER = (ROWS * W + kThreads - 1) / kThreads;
+    int off[PER];
+    float v[PER];
+    __device__ void init(int cols) {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int e = threadIdx.x + kThreads * i;
+            off[i] = e < ROWS * cols ? (e / cols) * kStageLd + e % cols : -1;
+        }
+    }
+    // run: first element of the chunk's rows; rem: elements left in the matrix from there
+    __device__ void load(const float* __restrict__ run, int64_t rem) {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int e = threadIdx.x + kThreads * i;
+            v[i] = (off[i] >= 0 && e < rem) ? run[e] : 0.f;
+        }
+    }
+    __device__ void store(float* __restrict__ lds) const {
+#pragma unroll
+        for (int i = 0; i < PER; ++i)
+            if (off[i] >= 0) lds[off[i]] = v[i];
+    }
+};
+
+constexpr int kNnChunk = 16;   // default columns of A per pipeline stage
+template <int RB, int NB, int KCH = kNnChunk>
+__global__ void __launch_bounds__(kThreads, 2) k_gemm_nn_mfma(const float* A, int64_t lda,
+                                                           const float* __restrict__ X,
                                                            float* Y, int ldy,
                                                            int64_t m, int64_t n, int b) {
     typedef __attribute__((address_space(1))) const mm_v4f gc4;
+    constexpr int SL = KCH / 16;                         // 16-column slabs per chunk
+    constexpr int XW = 16 * NB;                                // staged columns of X
+    __shared__ float sX[2][KCH * kStageLd];
     const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int g = l >> 4, c16 = l & 15;
-    const int64_t r0 = ((int64_t)blockIdx.x * 4 + w) * 32;
-    if (r0 >= m) return;
-    const int nb = (b + 15) / 16;
-    mm_v4f acc[2][6];
+    const int64_t r0 = ((int64_t)blockIdx.x * 4 + w) * (16 * RB);
+    const int nch = (int)((n + KCH - 1) / KCH);
+    StageCopy<KCH, XW> xn;
+    xn.init(b);
+    mm_v4f an[RB][SL];
+    auto fetch = [&](int c) {
+        xn.load(X + (int64_t)c * KCH * b, (n - (int64_t)c * KCH) * b);
 #pragma unroll
-    for (int rb = 0; rb < 2; ++rb)
+        for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-        for (int q = 0; q < 6; ++q) acc[rb][q] = (mm_v4f){0.f, 0.f, 0.f, 0.f};
-    for (int64_t k0 = 0; k0 < n; k0 += 16) {
-        const int64_t kc = k0 + 4 * g;
-        mm_v4f a[2];
+            for (int sl = 0; sl < SL; ++sl) {
+                const int64_t row = r0 + 16 * rb + c16;
+                const int64_t kc = (int64_t)c * KCH + 16 * sl + 4 * g;
+                // columns in [n, round4(n)) are read too: they meet zero rows of
+                // the staged X, and A keeps them zero (finite) in its padding
+                mm_v4f v = (mm_v4f){0.f, 0.f, 0.f, 0.f};
+                if (row < m && kc < n) v = *(gc4*)(A + row * lda + kc);
+                an[rb][sl] = v;
+            }
+    };
+    auto stage = [&](int buf) { xn.store(sX[buf]); };
+    mm_v4f acc[RB][NB];
 #pragma unroll
-        for (int rb = 0; rb < 2; ++rb) {
-            const int64_t row = r0 + 16 * rb + c16;
-            a[rb] = (mm_v4f){0.f, 0.f, 0.f, 0.f};
-            if (row < m && kc < n) {
-                a[rb] = *(gc4*)(A + row * lda + kc);
-                // columns past n (row padding) are not part of A
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int q = 0; q < NB; ++q) acc[rb][q] = (mm_v4f){0.f, 0.f, 0.f, 0.f};
+    const bool active = r0 < m;
+    fetch(0);
+    stage(0);
+    __syncthreads();
+    for (int c = 0; c < nch; ++c) {
+        mm_v4f ac[RB][SL];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int sl = 0; sl < SL; ++sl) ac[rb][sl] = an[rb][sl];
+        if (c + 1 < nch) fetch(c + 1);
+        if (active) {
+            const float* xs = sX[c & 1];
+            // B operands one slab ahead of the products that use them; the
+            // scheduling barriers keep the compiler from pulling each read down
+            // next to its use (which would expose the LDS latency)
+            float xv[2][4][NB];
+            auto read_slab = [&](int sl, float (&d)[4][NB]) {
 #pragma unroll
                 for (int s4 = 0; s4 < 4; ++s4)
-                    if (kc + s4 >= n) a[rb][s4] = 0.f;
+#pragma unroll
+                    for (int q = 0; q < NB; ++q) d[s4][q] = xs[(16 * sl + 4 * g + s4) * kStageLd + 16 * q + c16];
+            };
+            read_slab(0, xv[0]);
+#pragma unroll
+            for (int sl = 0; sl < SL; ++sl) {
+                if (sl + 1 < SL) read_slab(sl + 1, xv[(sl + 1) & 1]);
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+                    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                        for (int q = 0; q < NB; ++q)
+                            acc[rb][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(ac[rb][sl][s4], xv[sl & 1][s4][q],
+                                                                              acc[rb][q], 0, 0, 0);
+                __builtin_amdgcn_sched_barrier(0);
             }
         }
-#pragma unroll
-        for (int s4 = 0; s4 < 4; ++s4) {
-            const int64_t kk = kc + s4;
-            float xv[6];
-#pragma unroll
-            for (int q = 0; q < 6; ++q) {
-                const int j = 16 * q + c16;
-                xv[q] = (q < nb && kk < n && j < b) ? X[kk * ldx + j] : 0.f;
-            }
-#pragma unroll
-            for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-                for (int q = 0; q < 6; ++q)
-                    if (q < nb) acc[rb][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][s4], xv[q], acc[rb][q], 0, 0, 0);
-        }
+        if (c + 1 < nch) stage((c + 1) & 1);
+        __syncthreads();
     }
+    if (!active) return;
 #pragma unroll
-    for (int rb = 0; rb < 2; ++rb)
+    for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-        for (int q = 0; q < 6; ++q) {
-            if (q >= nb) continue;
+        for (int q = 0; q < NB; ++q) {
             const int col = 16 * q + c16;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
@@ -196,129 +267,248 @@ __global__ void __launch_bounds__(kThreads) k_gemm_nn_mfma(const float* A, int64
         }
 }
 
-// Zp[chunk][c][j] = sum over the chunk's rows r of A[r][c] Q[r][j], computed
-// as Z^T = Q^T A on the matrix cores (A operand Q^T, B operand A): per
-// 4-row slab, lane l loads one float4 of A -- row r0 + l/16, columns
-// c0 + 4 (l%16) + 0..3 (4 rows x 256 B per wave instruction) -- and feeds
-// element j to the MFMA of column set j (columns c0 + 4 n + j).  A block
-// covers 64 columns; its four waves take interleaved slabs of the chunk and
-// are summed in a fixed order through LDS; FP32 accumulation within the
-// chunk, FP64 partials out.  grid (ceil(n / 64), chunks); lda % 4 == 0.
-__global__ void __launch_bounds__(kThreads) k_gemm_tn_mfma(const float* __restrict__ A, int64_t lda,
-                                                           const float* __restrict__ Q, int ldq,
-                                                           double* __restrict__ Zp, int64_t m, int64_t n, int b,
+// Partials of Z = A^T Q (n x b, b <= 96), computed as Z^T = Q^T A on the
+// matrix cores (A operand Q^T, B operand A).  Block (x, y) covers columns
+// [256 x, 256 x + 256) -- wave w the 64 from 256 x + 64 w -- over the rows
+// of chunk y.  The four waves share the chunk's rows of Q, staged 32 at a
+// time in double-buffered LDS; each wave prefetches its next 32 x 64 block
+// of A into registers.  Per 4-row slab lane l loads one float4 of A -- row
+// r0 + l/16, columns c0 + 4 (l%16) + 0..3 -- and feeds element j to the MFMA
+// of column set j (columns c0 + 4 n + j).  FP32 accumulation; each lane
+// stores its accumulators as they sit in the registers (96 floats per lane,
+// coalesced), and k_tn_sum adds the chunks in FP64 and scatters them to Z.
+// Q is m x b with leading dimension b; lda % 4 == 0.
+constexpr int kTnCols = 256;
+constexpr int kTnRows = 16;
+constexpr int kTnDump = 4 * 96 * 64;   // floats per block of the partial dump
+inline int64_t tn_chunks(int64_t m, int64_t n) {
+    const int64_t ncb = (n + kTnCols - 1) / kTnCols;
+    const int64_t want = (512 + ncb - 1) / ncb;
+    return std::max<int64_t>(1, std::min<int64_t>(want, (m + 2 * kTnRows - 1) / (2 * kTnRows)));
+}
+template <int NB, int RCH = kTnRows>
+__global__ void __launch_bounds__(kThreads, 2) k_gemm_tn_mfma(const float* __restrict__ A, int64_t lda,
+                                                           const float* __restrict__ Q,
+                                                           float* __restrict__ Zp, int64_t m, int64_t n, int b,
                                                            int64_t rows_per_chunk) {
     typedef __attribute__((address_space(1))) const mm_v4f gc4;
-    __shared__ float red[64][kMaxBlock + 1];
+    constexpr int SLABS = RCH / 4;
+    constexpr int QW = 16 * NB;
+    __shared__ float sQ[2][RCH * kStageLd];
     const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int g = l >> 4, c16 = l & 15;
-    const int64_t c0 = (int64_t)blockIdx.x * 64;
+    const int64_t cc = (int64_t)blockIdx.x * kTnCols + 64 * w + 4 * c16;
     const int64_t ra = (int64_t)blockIdx.y * rows_per_chunk;
     const int64_t rb = min(m, ra + rows_per_chunk);
-    const int nb = (b + 15) / 16;
-    const int64_t cc = c0 + 4 * c16;
-    mm_v4f acc[6][4];
+    const int nch = rb > ra ? (int)((rb - ra + RCH - 1) / RCH) : 0;
+    StageCopy<RCH, QW> qn;
+    qn.init(b);
+    mm_v4f an[SLABS];
+    auto fetch = [&](int c) {
+        const int64_t base = ra + (int64_t)c * RCH;
+        qn.load(Q + base * b, (rb - base) * b);
 #pragma unroll
-    for (int q = 0; q < 6; ++q)
+        for (int sl = 0; sl < SLABS; ++sl) {
+            const int64_t row = base + 4 * sl + g;
+            // columns in [n, round4(n)) only reach outputs that are never read
+            mm_v4f v = (mm_v4f){0.f, 0.f, 0.f, 0.f};
+            if (row < rb && cc < n) v = *(gc4*)(A + row * lda + cc);
+            an[sl] = v;
+        }
+    };
+    auto stage = [&](int buf) { qn.store(sQ[buf]); };
+    mm_v4f acc[NB][4];
+#pragma unroll
+    for (int q = 0; q < NB; ++q)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[q][j] = (mm_v4f){0.f, 0.f, 0.f, 0.f};
-    for (int64_t s0 = ra + 4 * w; s0 < rb; s0 += 16) {
-        const int64_t row = s0 + g;
-        mm_v4f a = (mm_v4f){0.f, 0.f, 0.f, 0.f};
-        if (row < rb && cc < n) {
-            a = *(gc4*)(A + row * lda + cc);
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                if (cc + j >= n) a[j] = 0.f;
-        }
-        float yv[6];
-#pragma unroll
-        for (int q = 0; q < 6; ++q) {
-            const int jj = 16 * q + c16;
-            yv[q] = (q < nb && row < rb && jj < b) ? Q[row * ldq + jj] : 0.f;
-        }
-#pragma unroll
-        for (int q = 0; q < 6; ++q)
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                if (q < nb) acc[q][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(yv[q], a[j], acc[q][j], 0, 0, 0);
+    if (nch > 0) {
+        fetch(0);
+        stage(0);
     }
-    // acc[q][j][r] = Z[c0 + 4 c16 + j][16 q + 4 g + r]; waves summed in order
-    for (int ww = 0; ww < 4; ++ww) {
-        if (w == ww) {
+    __syncthreads();
+    for (int c = 0; c < nch; ++c) {
+        mm_v4f ac[SLABS];
 #pragma unroll
-            for (int q = 0; q < 6; ++q) {
-                if (q >= nb) continue;
+        for (int sl = 0; sl < SLABS; ++sl) ac[sl] = an[sl];
+        if (c + 1 < nch) fetch(c + 1);
+        const float* qs = sQ[c & 1];
+        // A operands one slab ahead of their products (see k_gemm_nn_mfma)
+        float yv[2][NB];
+        auto read_slab = [&](int sl, float (&d)[NB]) {
+#pragma unroll
+            for (int q = 0; q < NB; ++q) d[q] = qs[(4 * sl + g) * kStageLd + 16 * q + c16];
+        };
+        read_slab(0, yv[0]);
+#pragma unroll
+        for (int sl = 0; sl < SLABS; ++sl) {
+            if (sl + 1 < SLABS) read_slab(sl + 1, yv[(sl + 1) & 1]);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int q = 0; q < NB; ++q)
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
+                    acc[q][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(yv[sl & 1][q], ac[sl][j], acc[q][j], 0, 0, 0);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        if (c + 1 < nch) stage((c + 1) & 1);
+        __syncthreads();
+    }
+    // acc[q][j][r] = Z[c0 + 4 (l%16) + j][16 q + 4 (l/16) + r]
+    float* out = Zp + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * kTnDump + (int64_t)w * 96 * 64 + l;
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int jj = 16 * q + 4 * g + r;
-                        float& d = red[4 * c16 + j][jj];
-                        d = (ww == 0 ? 0.f : d) + acc[q][j][r];
-                    }
+    for (int q = 0; q < NB; ++q)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) out[((q * 4 + j) * 4 + r) * 64] = acc[q][j][r];
+}
+
+// Z[c][jj] = sum over the nchunk partial dumps of k_gemm_tn_mfma, in chunk
+// order in FP64 (eight interleaved accumulators, added in a fixed order),
+// rounded once to FP32.  One thread per dump position (ncb kTnDump of them).
+__global__ void __launch_bounds__(256) k_tn_sum(const float* __restrict__ Zp, int nchunk, int64_t per_chunk,
+                                                int64_t n, int b, float* __restrict__ Z, int ldz) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= per_chunk) return;
+    const int lane = (int)(idx & 63), r = (int)((idx >> 6) & 3);
+    const int qj = (int)((idx >> 8) % 24);
+    const int64_t wq = idx / (96 * 64);
+    const int64_t c = wq * 64 + 4 * (lane & 15) + (qj & 3);
+    const int jj = 16 * (qj >> 2) + 4 * (lane >> 4) + r;
+    if (c >= n || jj >= b) return;
+    double s[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    const float* P = Zp + idx;
+    int p = 0;
+    for (; p + 8 <= nchunk; p += 8) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s[u] += (double)P[(int64_t)(p + u) * per_chunk];
+    }
+    for (; p < nchunk; ++p) s[0] += (double)P[(int64_t)p * per_chunk];
+    Z[c * ldz + jj] = (float)(((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7])));
+}
+
+// Gram matrix G = Y^T Y (b x b, b <= 96) on the FP64 matrix cores, in two
+// launches.  k_gram_mfma: block p takes rows [p rpb, (p + 1) rpb) (rpb a
+// multiple of 64, sized by gram_rpb so the grid covers the chip) and writes
+// the upper 16 x 16 tiles (ib <= jb, row-major over the upper triangle) of
+// its partial Y_p^T Y_p to Gp[p][tile][16 x 16]; the storage-type products
+// are exact in FP64 and accumulate in FP64.  Rows are staged 64 at a time
+// through LDS as FP64, the next stage prefetched into registers; wave w owns
+// tiles w, w + 4, ....  k_gram_sum adds the partials in a fixed order and
+// writes the full, exactly symmetric G.  Y row-major, or in the tiled basis
+// layout when TILED.
+constexpr int kGramStage = 64;
+inline int64_t gram_rpb(int64_t rows) {
+    const int64_t stages = (rows + kGramStage - 1) / kGramStage;
+    return kGramStage * std::max<int64_t>(1, (stages + 511) / 512);
+}
+inline int64_t gram_parts(int64_t rows) { return std::max<int64_t>(1, (rows + gram_rpb(rows) - 1) / gram_rpb(rows)); }
+// an upper bound of gram_parts(r) for every r <= rows
+inline int64_t gram_parts_max(int64_t rows) { return std::max<int64_t>(1, std::min<int64_t>(512, (rows + kGramStage - 1) / kGramStage)); }
+__host__ __device__ inline int gram_tiles(int b) { return ((b + 15) / 16) * ((b + 15) / 16 + 1) / 2; }
+__device__ inline void gram_tile(int t, int nb, int* ib, int* jb) {
+    int i = 0;
+    while (t >= nb - i) { t -= nb - i; ++i; }
+    *ib = i;
+    *jb = i + t;
+}
+
+template <typename T, bool TILED = false>
+__global__ void __launch_bounds__(kThreads) k_gram_mfma(const T* __restrict__ Y, int ldy, int64_t rows, int b,
+                                                        int64_t rpb, double* __restrict__ Gp) {
+    constexpr int PER = kGramStage * kMaxBlock / kThreads;   // staged elements per thread
+    __shared__ double sY[kGramStage][kMaxBlock + 1];
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int nb = (b + 15) / 16, ntile = gram_tiles(b);
+    int tib[6], tjb[6];
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+        const int t = w + 4 * s;
+        if (t < ntile) gram_tile(t, nb, &tib[s], &tjb[s]);
+        else tib[s] = tjb[s] = 0;
+    }
+    const int64_t ra = (int64_t)blockIdx.x * rpb;
+    const int64_t rb = min(rows, ra + rpb);
+    T pre[PER];
+    auto fetch = [&](int64_t r0) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = threadIdx.x + kThreads * q;
+            const int rr = e / kMaxBlock, j = e % kMaxBlock;
+            const int64_t r = r0 + rr;
+            pre[q] = (r < rb && j < b) ? Y[TILED ? uvo(r, j, ldy) : r * ldy + j] : (T)0;
+        }
+    };
+    mm_v4d acc[6];
+#pragma unroll
+    for (int s = 0; s < 6; ++s) acc[s] = (mm_v4d){0.0, 0.0, 0.0, 0.0};
+    fetch(ra);
+    for (int64_t r0 = ra; r0 < rb; r0 += kGramStage) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = threadIdx.x + kThreads * q;
+            sY[e / kMaxBlock][e % kMaxBlock] = (double)pre[q];
+        }
+        __syncthreads();
+        if (r0 + kGramStage < rb) fetch(r0 + kGramStage);
+#pragma unroll 4
+        for (int kk = 0; kk < kGramStage / 4; ++kk) {
+            const int rr = 4 * kk + (l >> 4);
+#pragma unroll
+            for (int s = 0; s < 6; ++s) {
+                if (w + 4 * s < ntile)
+                    acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(sY[rr][16 * tib[s] + (l & 15)],
+                                                                  sY[rr][16 * tjb[s] + (l & 15)], acc[s], 0, 0, 0);
             }
         }
         __syncthreads();
     }
-    for (int e = threadIdx.x; e < 64 * b; e += kThreads) {
-        const int ci = e / b, jj = e % b;
-        const int64_t c = c0 + ci;
-        if (c < n) Zp[((int64_t)blockIdx.y * n + c) * b + jj] = (double)red[ci][jj];
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+        const int t = w + 4 * s;
+        if (t >= ntile) continue;
+        double* out = Gp + ((int64_t)blockIdx.x * ntile + t) * 256;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) out[(4 * r + (l >> 4)) * 16 + (l & 15)] = acc[s][r];
     }
 }
 
-// Gp[block] = Y[rows of block]^T Y[rows of block] (b x b) on the FP64 matrix
-// cores: the storage-type products are exact in FP64 and accumulate in FP64.
-// kGramRows rows per block, staged 64 at a time; wave w owns the output
-// 16 x 16 blocks w, w + 4, ... of the (b/16)^2.  Y row-major, or in the
-// tiled basis layout when TILED.
-template <typename T, bool TILED = false>
-__global__ void __launch_bounds__(kThreads) k_gram_mfma(const T* __restrict__ Y, int ldy, int64_t rows, int b,
-                                                        double* __restrict__ Gp) {
-    __shared__ double sY[64][kMaxBlock + 1];
-    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int nb = (b + 15) / 16, nblk = nb * nb;
-    const int64_t ra = (int64_t)blockIdx.x * kGramRows;
-    const int64_t rb = min(rows, ra + kGramRows);
-    mm_v4d acc[9];
-#pragma unroll
-    for (int t = 0; t < 9; ++t) acc[t] = (mm_v4d){0.0, 0.0, 0.0, 0.0};
-    for (int64_t r0 = ra; r0 < rb; r0 += 64) {
-        for (int e = threadIdx.x; e < 64 * kMaxBlock; e += kThreads) {
-            const int rr = e / kMaxBlock, j = e % kMaxBlock;
-            const int64_t r = r0 + rr;
-            sY[rr][j] = (r < rb && j < b) ? (double)Y[TILED ? uvo(r, j, ldy) : r * ldy + j] : 0.0;
+// G = sum over the nparts partials of k_gram_mfma.  A block takes 32
+// consecutive tile entries; thread group g (of 8) adds partials g, g + 8, ...
+// in increasing order into four accumulators, and the groups' sums are added
+// in group order: the result does not depend on timing.
+__global__ void __launch_bounds__(256) k_gram_sum(const double* __restrict__ Gp, int nparts, int b,
+                                                  double* __restrict__ G) {
+    __shared__ double red[8][33];
+    const int nb = (b + 15) / 16, ntile = gram_tiles(b);
+    const int total = ntile * 256;
+    const int o = threadIdx.x & 31, g = threadIdx.x >> 5;
+    const int e = blockIdx.x * 32 + o;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    if (e < total) {
+        const double* P = Gp + e;
+        int p = g;
+        for (; p + 24 < nparts; p += 32) {
+            a0 += P[(int64_t)p * total];
+            a1 += P[(int64_t)(p + 8) * total];
+            a2 += P[(int64_t)(p + 16) * total];
+            a3 += P[(int64_t)(p + 24) * total];
         }
-        __syncthreads();
-#pragma unroll 4
-        for (int kk = 0; kk < 16; ++kk) {
-            const int rr = 4 * kk + (l >> 4);
-#pragma unroll
-            for (int t = 0; t < 9; ++t) {
-                const int q = w + 4 * t;
-                if (q < nblk) {
-                    const int ib = q / nb, jb = q % nb;
-                    acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(sY[rr][16 * ib + (l & 15)], sY[rr][16 * jb + (l & 15)],
-                                                                  acc[t], 0, 0, 0);
-                }
-            }
-        }
-        __syncthreads();
+        for (; p < nparts; p += 8) a0 += P[(int64_t)p * total];
     }
-    double* out = Gp + (int64_t)blockIdx.x * b * b;
+    red[g][o] = (a0 + a1) + (a2 + a3);
+    __syncthreads();
+    if (g != 0 || e >= total) return;
+    double s = 0.0;
 #pragma unroll
-    for (int t = 0; t < 9; ++t) {
-        const int q = w + 4 * t;
-        if (q >= nblk) continue;
-        const int ib = q / nb, jb = q % nb;
-        const int col = 16 * jb + (l & 15);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int row = 16 * ib + 4 * r + (l >> 4);
-            if (row < b && col < b) out[row * b + col] = acc[t][r];
-        }
-    }
+    for (int q = 0; q < 8; ++q) s += red[q][o];
+    int ib, jb;
+    gram_tile(e >> 8, nb, &ib, &jb);
+    const int a = 16 * ib + ((e & 255) >> 4), c = 16 * jb + (e & 15);
+    if (a >= b || c >= b || (ib == jb && a > c)) return;
+    G[a * b + c] = s;
+    G[c * b + a] = s;
 }
 
 // out[e] = sum_p P[p * stride + e] in part order; converted to Tout
@@ -332,45 +522,6 @@ __global__ void k_sum_parts(const double* __restrict__ P, int nparts, int64_t st
     out[e] = (Tout)s;
 }
 
-// Gp[chunk] = Y[rows of chunk]^T Y[rows of chunk]  (b x b, FP64); Y row-major,
-// or in the tiled basis layout when TILED
-template <typename T, bool TILED = false>
-__global__ void __launch_bounds__(kThreads) k_gram_partial(const T* __restrict__ Y, int ldy, int64_t rows,
-                                                           int b, double* __restrict__ Gp) {
-    __shared__ double sY[kGemmK][kMaxBlock + 1];
-    const int64_t ra = (int64_t)blockIdx.x * kChunkRows;
-    const int64_t rb = min(rows, ra + kChunkRows);
-    const int nout = b * b;
-    double acc[36];
-#pragma unroll
-    for (int q = 0; q < 36; ++q) acc[q] = 0.0;
-    for (int64_t r0 = ra; r0 < rb; r0 += kGemmK) {
-        for (int e = threadIdx.x; e < kGemmK * b; e += kThreads) {
-            int rr = e / b, j = e % b;
-            int64_t r = r0 + rr;
-            sY[rr][j] = r < rb ? (double)Y[TILED ? uvo(r, j, ldy) : r * ldy + j] : 0.0;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < 36; ++q) {
-            int e = threadIdx.x + q * kThreads;
-            if (e < nout) {
-                int i = e / b, j = e % b;
-                double s = 0.0;
-                for (int rr = 0; rr < kGemmK; ++rr) s += sY[rr][i] * sY[rr][j];
-                acc[q] += s;
-            }
-        }
-        __syncthreads();
-    }
-    double* out = Gp + (int64_t)blockIdx.x * nout;
-#pragma unroll
-    for (int q = 0; q < 36; ++q) {
-        int e = threadIdx.x + q * kThreads;
-        if (e < nout) out[e] = acc[q];
-    }
-}
-
 // One block: Cholesky G = R^T R (R upper), R^{-1}; writes R (FP64, b x b)
 // and R^{-1} in the storage type (b x b, row-major) for the rotation kernel.
 // Rank-deficient G (a block whose columns are linearly dependent, e.g. A of
@@ -380,91 +531,108 @@ __global__ void __launch_bounds__(kThreads) k_gram_partial(const T* __restrict__
 // row of R and its row and column of R^{-1} are zero, so the orthonormalised
 // block has a zero column there and Y = Q R still holds.  `flag` bit 0 is set
 // when a column was dropped.
-// Right-looking: step j takes the pivot, scales row j and updates the
-// trailing upper triangle with all threads; R^{-1} row by row from the
-// bottom, each step's entries in parallel.  Launched with kCholThreads.
+// Gaussian elimination of the augmented [G | I] (G = L D L^T): after step j
+// every row below j has its column-j entry eliminated, so the left half ends
+// as D L^T (row j = pivot d_j times row j of L^T) and the right half as
+// L^{-1}.  Then R = D^{-1/2} (D L^T) and R^{-1} = L^{-T} D^{-1/2}.  The
+// 96 x 192 augmented matrix lives in registers: thread (ty, tx) of a 16 x 16
+// grid owns rows ty + 16 p and columns tx + 16 q; step j publishes row j
+// through a double-buffered LDS row, so one barrier per step suffices.
+constexpr int kCholThreads = 256;
 template <typename T>
 __global__ void __launch_bounds__(kCholThreads) k_chol_inv(const double* __restrict__ G, int b,
                                                        double* __restrict__ Rout, T* __restrict__ RinvT,
                                                        int* __restrict__ flag) {
-    extern __shared__ double sh[];
-    double* R = sh;                 // b x b row-major: the upper triangle becomes R
-    double* Ri = sh + b * b;        // b x b inverse
+    constexpr int NP = kMaxBlock / 16, NQ = 2 * kMaxBlock / 16;
+    __shared__ double s_row[2][2 * kMaxBlock];
+    __shared__ double s_g[kMaxBlock];
+    __shared__ double s_d[kMaxBlock];
     __shared__ int s_drop[kMaxBlock];
-    __shared__ double s_dg[kMaxBlock];
-    for (int e = threadIdx.x; e < b * b; e += blockDim.x) { R[e] = G[e]; Ri[e] = 0.0; }
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    double g[NP][NQ];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        const int i = ty + 16 * p;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int c = tx + 16 * q;
+            if (q < NQ / 2)
+                g[p][q] = (i < b && c < b) ? G[i * b + c] : 0.0;
+            else
+                g[p][q] = (i < b && c - kMaxBlock == i) ? 1.0 : 0.0;
+        }
+    }
+    for (int j = threadIdx.x; j < b; j += blockDim.x) s_g[j] = G[j * b + j];
+    if (ty == 0) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) s_row[0][tx + 16 * q] = g[0][q];
+    }
     __syncthreads();
     const double tol = 4.0 * b * 2.220446049250313e-16;
-    // unscaled elimination (R holds the Schur complements S; row j of R is
-    // S_j / sqrt(S_jj) at the end): step j reads row j and updates rows below
-    // it only, so one barrier per step suffices
     for (int j = 0; j < b; ++j) {
-        const double gjj = G[j * b + j];
-        const double d = R[j * b + j];
+        const double* row = s_row[j & 1];
+        const double d = row[j], gjj = s_g[j];
         const bool drop = !(d > tol * gjj && gjj > 1e-300);
+        const double inv_d = drop ? 0.0 : 1.0 / d;
+        double rc[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) rc[q] = row[tx + 16 * q];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            const int i = ty + 16 * p;
+            const double f = i > j ? row[i] * inv_d : 0.0;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) g[p][q] -= f * rc[q];
+        }
         if (threadIdx.x == 0) {
+            s_d[j] = d;
             s_drop[j] = drop ? 1 : 0;
             if (drop) atomicOr(flag, 1);
         }
-        if (!drop) {
-            const double inv_d = 1.0 / d;
-            const int t = b - j - 1;
-            for (int e = threadIdx.x; e < t * t; e += blockDim.x) {
-                const int i = j + 1 + e / t, c = j + 1 + e % t;
-                if (c >= i) R[i * b + c] -= R[j * b + i] * R[j * b + c] * inv_d;
-            }
-        }
-        __syncthreads();
-    }
-    // scale the rows (dropped ones to zero)
-    for (int j = threadIdx.x; j < b; j += blockDim.x) s_dg[j] = s_drop[j] ? 0.0 : sqrt(R[j * b + j]);
-    __syncthreads();
-    for (int e = threadIdx.x; e < b * b; e += blockDim.x) {
-        const int j = e / b, c = e % b;
-        if (c < j) continue;
-        R[e] = s_drop[j] ? 0.0 : R[e] / s_dg[j];
-    }
-    __syncthreads();
-    // zero the strict lower triangle (it still holds G)
-    for (int e = threadIdx.x; e < b * b; e += blockDim.x) {
-        const int i = e / b, c = e % b;
-        if (i > c) R[e] = 0.0;
-    }
-    __syncthreads();
-    // R^{-1}, rows from the bottom: Ri[i][c] = -(sum_{i<l<=c} R[i][l] Ri[l][c]) / R[i][i],
-    // Ri[i][i] = 1 / R[i][i]; dropped rows and columns stay zero
-    for (int i = b - 1; i >= 0; --i) {
-        if (!s_drop[i]) {
-            const double rii = R[i * b + i];
-            for (int c = i + threadIdx.x; c < b; c += blockDim.x) {
-                if (s_drop[c]) continue;
-                double s0 = 0.0, s1 = 0.0;
-                int l = i + 1;
-                for (; l + 1 <= c; l += 2) {
-                    s0 += R[i * b + l] * Ri[l * b + c];
-                    s1 += R[i * b + l + 1] * Ri[(l + 1) * b + c];
+        const int jn = j + 1;
+        if (jn < b && ty == (jn & 15)) {
+#pragma unroll
+            for (int p = 0; p < NP; ++p)
+                if (p == (jn >> 4)) {
+#pragma unroll
+                    for (int q = 0; q < NQ; ++q) s_row[jn & 1][tx + 16 * q] = g[p][q];
                 }
-                if (l <= c) s0 += R[i * b + l] * Ri[l * b + c];
-                Ri[i * b + c] = (c == i ? 1.0 : -(s0 + s1)) / rii;
-            }
         }
         __syncthreads();
     }
-    for (int e = threadIdx.x; e < b * b; e += blockDim.x) {
-        Rout[e] = R[e];
-        RinvT[e] = (T)Ri[e];
+    // R = D^{-1/2} (D L^T) (upper, dropped rows zero); R^{-1}[c][i] = L^{-1}[i][c] / sqrt(d_i)
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        const int i = ty + 16 * p;
+        if (i >= b) continue;
+        const double sc = s_drop[i] ? 0.0 : 1.0 / sqrt(s_d[i]);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int c = tx + 16 * q;
+            if (q < NQ / 2) {
+                if (c < b) Rout[i * b + c] = c >= i ? g[p][q] * sc : 0.0;
+            } else {
+                const int cc = c - kMaxBlock;
+                if (cc < b) RinvT[cc * b + i] = (T)(g[p][q] * sc);
+            }
+        }
     }
 }
 
-// C = A B for b x b FP64 matrices (one block)
+// C = A B for b x b FP64 matrices, one output per thread (grid ceil(b^2 / blockDim))
 __global__ void k_small_gemm(const double* __restrict__ A, const double* __restrict__ B,
                              double* __restrict__ C, int b) {
-    for (int e = threadIdx.x; e < b * b; e += blockDim.x) {
-        int i = e / b, j = e % b;
-        double s = 0.0;
-        for (int l = 0; l < b; ++l) s += A[i * b + l] * B[l * b + j];
-        C[e] = s;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= b * b) return;
+    const int i = e / b, j = e % b;
+    double s0 = 0.0, s1 = 0.0;
+    int l = 0;
+    for (; l + 1 < b; l += 2) {
+        s0 += A[i * b + l] * B[l * b + j];
+        s1 += A[i * b + l + 1] * B[(l + 1) * b + j];
     }
+    if (l < b) s0 += A[i * b + l] * B[l * b + j];
+    C[e] = s0 + s1;
 }
 
 // out[r, 0:ldo] = in[r, 0:kin] Q[0:kin, 0:ldo]   (may run in place when ldi == ldo);
@@ -532,11 +700,14 @@ __global__ void __launch_bounds__(JacobiShape<kMaxBlock + 1>::NT) k_svd_small(co
 }
 
 // FP32-storage Rayleigh-Ritz core: the same SVD of R without accumulating the
-// rotations (half the LDS, so eight lanes per pair fit): W = R J with
-// orthogonal columns, U_K = W diag(1/sigma), and the right vectors from
-// R^T W = J diag(sigma^2), i.e. v_j = R^T w_j / sigma_j^2 (R re-read from
-// global memory).  Their loss of orthogonality, about b eps64 sigma_1 / sigma_j,
-// stays far below FP32 rounding for the kept triplets.
+// rotations (half the LDS, so eight lanes per pair fit).  The columns rotated
+// are those of R^T (for a triangular R the one-sided Jacobi needs fewer
+// sweeps on R^T than on R): W = R^T J with orthogonal columns w_j =
+// sigma_j v_j, so the right vectors are v_j = w_j / sigma_j and the left ones
+// u_j = R v_j / sigma_j = R w_j / sigma_j^2 (R re-read from global memory).
+// Their loss of orthogonality, about the rotation threshold (b eps64) times
+// sigma_1 / sigma_j, stays far below FP32 rounding for the kept triplets; a
+// coarser threshold would be amplified the same way, so the FP64 one stays.
 typedef JacobiShape<kMaxBlock + 1, 8> RRShape;
 template <typename T>
 __global__ void __launch_bounds__(RRShape::NT) k_svd_small_noj(const double* __restrict__ R, int b, int k,
@@ -552,24 +723,20 @@ __global__ void __launch_bounds__(RRShape::NT) k_svd_small_noj(const double* __r
     double* tmp = sgn + N;
     int* perm = (int*)(tmp + N);
     double* vmax = tmp + 2 * N;                         // per output column: signed largest entry
+    // column c of W = row c of R
     for (int e = threadIdx.x; e < (N + 1) * ldw; e += blockDim.x) {
         const int col = e / ldw, row = e % ldw;
-        W[e] = (row < N && col < N) ? R[row * N + col] : 0.0;
+        W[e] = (row < N && col < N) ? R[col * N + row] : 0.0;
     }
     __syncthreads();
     const int sweeps = jacobi_block<kMaxBlock + 1, false, 8>(W, nullptr, N, ldw, 60);
     jacobi_sort(W, N, ldw, sig, perm, tmp);
     // sign: the largest-magnitude entry of each right vector positive
     for (int j = threadIdx.x; j < k; j += blockDim.x) {
-        const int c = perm[j];
-        const double s2 = sig[j] * sig[j];
+        const double* w = W + (size_t)perm[j] * ldw;
         double best = 0.0;
-        for (int e = 0; e < N; ++e) {
-            double v = 0.0;
-            for (int i = 0; i < N; ++i) v += R[i * N + e] * W[(size_t)c * ldw + i];
-            v = s2 > 0.0 ? v / s2 : 0.0;
-            if (fabs(v) > fabs(best)) best = v;
-        }
+        for (int e = 0; e < N; ++e)
+            if (fabs(w[e]) > fabs(best)) best = w[e];
         vmax[j] = best;
     }
     __syncthreads();
@@ -579,13 +746,13 @@ __global__ void __launch_bounds__(RRShape::NT) k_svd_small_noj(const double* __r
         const int row = e / ldo, j = e % ldo;
         double uk = 0.0, vk = 0.0;
         if (j < k) {
-            const int c = perm[j];
+            const double* w = W + (size_t)perm[j] * ldw;
             const double s = sig[j];
             if (s > 0.0) {
-                uk = sgn[j] * W[(size_t)c * ldw + row] / s;
-                double v = 0.0;
-                for (int i = 0; i < N; ++i) v += R[i * N + row] * W[(size_t)c * ldw + i];
-                vk = sgn[j] * v / (s * s);
+                vk = sgn[j] * w[row] / s;
+                double u = 0.0;
+                for (int i = 0; i < N; ++i) u += R[row * N + i] * w[i];
+                uk = sgn[j] * u / (s * s);
             }
         }
         QU[e] = (T)uk;
