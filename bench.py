@@ -66,9 +66,10 @@ PMC_RECORD = os.path.join(ROOT, "profiles", "rotate_u_kc64_tick512_pmc.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2605_24514_amd", "csrc", f) for f in ("isvd_common.h", "isvd_update.h")]
 
 
-def recorded_traffic_ratio():
-    """HBM traffic / algorithmic bytes of the dominant kernel from the committed
-    counter record, or None once the kernel sources differ from the profiled ones."""
+def recorded_traffic_ratio(variant):
+    """HBM traffic / algorithmic bytes of the dominant kernel in rotation block
+    shape `variant`, from the committed counter record, or None once the kernel
+    sources differ from the profiled ones."""
     import hashlib
     try:
         text = open(PMC_RECORD).read()
@@ -76,7 +77,7 @@ def recorded_traffic_ratio():
         return None
     ratio = sha = None
     for line in text.splitlines():
-        if line.startswith("traffic_over_algorithmic:"):
+        if line.startswith("traffic_over_algorithmic_variant_%d:" % variant):
             ratio = float(line.split(":")[1])
         if line.startswith("kernel_source_sha256:"):
             sha = line.split(":")[1].strip()
@@ -235,6 +236,47 @@ def serve_main(args):
     eng.close()
 
 
+def refresh_main(args):
+    """Refresh run: TruncatedSVD(A_t, 64) of one 100000 x 2000 FP32 stream (20
+    factors) by block subspace iteration; prints one JSON line with the time
+    per refresh and the matrix-core rate of its A X / A^T Q products."""
+    import torch
+    from paper_2605_24514_amd import isvd
+    from synth import device as sdev
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    m, n, k, iters = 100000, 2000, 64, args.refresh_iters
+    st = torch.cuda.Stream()
+    A0 = torch.empty((m, n), dtype=torch.float32, device="cuda")
+    sdev.rows_into(A0, 0, m, n, SEED, 0, 20)
+    torch.cuda.synchronize()
+    with isvd.Engine() as eng:
+        sid = eng.init(A0, k, "fp32", refresh_iters=iters, stream=st)
+        for _ in range(args.warmup):
+            eng.refresh(sid, stream=st)
+        st.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ts = []
+        for _ in range(args.steps):
+            e0.record(st)
+            eng.refresh(sid, stream=st)
+            e1.record(st)
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        met = eng.metrics(sid, exact=True, stream=st)
+    b = min(n, k + max(8, k // 2), 96)
+    gemm_flop = 2.0 * m * n * b * (2 * iters + 1)      # iters x (A X, A^T Q) + final A X
+    ms = float(np.median(ts))
+    out = {"metric": "refresh time: TruncatedSVD(A_t, k) of one stream", "value": round(ms, 3), "unit": "ms",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": False, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": "one factor-model stream, A 100000 x 2000 FP32 (20 factors), k = 64, block "
+                                  "b = %d, %d subspace iterations, CholQR2 / FP64 Gram, FP64 Rayleigh-Ritz" % (b, iters)},
+           "ms_min": round(min(ts), 3), "ms_p99": round(pctl(ts, 99), 3),
+           "gemm_equivalent_tflops": round(gemm_flop / (ms * 1e-3) / 1e12, 1),
+           "frob_ratio": met["frob_ratio"], "ortho_U": met["ortho_U"], "ortho_V": met["ortho_V"]}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -250,6 +292,7 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (reference for hardware byte counters)")
     ap.add_argument("--serve", action="store_true", help="run the serving loop instead of the batched tick")
+    ap.add_argument("--refresh", action="store_true", help="time the refresh of one 100000 x 2000 stream instead")
     ap.add_argument("--serve-streams", type=int, default=1024)
     ap.add_argument("--serve-lifetime", type=int, default=200)
     ap.add_argument("--serve-rate", type=float, default=200000.0)
@@ -257,6 +300,9 @@ def main():
     args = ap.parse_args()
     if args.serve and args.gpus == 1:
         serve_main(args)
+        return
+    if args.refresh and args.gpus == 1:
+        refresh_main(args)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: the streams are independent and would shard by stream across "
@@ -398,10 +444,10 @@ def main():
     mid_all = W + (K - 1) / 2.0
     all_tick_bytes = sum(tick_bytes(m0 + mid_all, n0, k, 4) for (m0, n0, k) in params)
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
+    dom_ratio = recorded_traffic_ratio(tune[kdom][0]) if kdom in tune else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": (int(recorded_traffic_ratio() * dom_bytes)
-                            if recorded_traffic_ratio() is not None and kdom == 64 else None),
+                "traffic": (int(dom_ratio * dom_bytes) if dom_ratio is not None and kdom == 64 else None),
                 "traffic_note": "HBM bytes per launch: rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated, "
                                 "ratio to algorithmic bytes from profiles/rotate_u_kc64_tick512_pmc.md",
                 "kernel": "k_rotate_mfma_t<%d> (U rotation, variant %d)" % (kdom, tune[kdom][0] if kdom in tune else -1),

@@ -285,7 +285,9 @@ isvd_status isvd_profile_read(isvd_engine* eng, isvd_launch_time* out, int32_t c
  * (8, 16, 32, 64), times every variant on a synthetic batch of 64 bases of
  * 32768 x bucket (plus 1024 x bucket) -- about 1.1 GB of HBM for the widest
  * bucket, allocated for the call and freed before it returns -- and keeps
- * the fastest for later launches.  variant_out (4 entries, may be NULL)
+ * the fastest for later launches (a variant replaces an earlier, faster-so-far
+ * one only when it is at least 3% faster, so near-equal shapes resolve to
+ * the lower index and repeated tunings agree).  variant_out (4 entries, may be NULL)
  * receives the choices, ms_out (4 x ISVD_ROT_VARIANTS entries, bucket major,
  * may be NULL) the mean time of one launch per variant.  Waits for the
  * device.  Errors: NOMEM, DEVICE. */
