@@ -238,12 +238,29 @@ isvd_status isvd_release(isvd_engine* eng, isvd_id id);
  * reads U) first orders its stream after them, and isvd_sync does so
  * explicitly.  Otherwise the tick joins them into hip_stream before
  * returning.  Row payloads are not read by U rotations.
- * Errors: STATE, SHAPE, RANGE, CAPACITY, INVAL (duplicate stream, dtype). */
+ * Refreshes: the refreshes that a tick's policies fire (periodic, angle,
+ * adaptive) run concurrently on the engine's refresh lanes (streams of
+ * default priority, one host thread and one workspace per lane) and are not
+ * joined into hip_stream: a stream under refresh is busy (isvd_stream_busy)
+ * until its refresh is done, and every later call on that stream (a tick
+ * that includes it, a single update, metrics, factors, matrix, refresh)
+ * orders itself after it, so results do not depend on the overlap.  The
+ * error policy's checks run in the tick, on hip_stream.
+ * Errors: STATE, SHAPE, RANGE, CAPACITY, INVAL (duplicate stream, dtype),
+ * CONVERGE (a lane refresh of a stream in the tick did not converge). */
 isvd_status isvd_tick(isvd_engine* eng, int32_t count, const isvd_request* reqs, void* hip_stream);
 
 /* Order hip_stream after every U rotation still pending on the engine's
- * rotation stream (see isvd_tick).  Does not wait on the host. */
+ * rotation stream and every refresh queued on the refresh lanes (see
+ * isvd_tick).  Does not wait on the host. */
 isvd_status isvd_sync(isvd_engine* eng, void* hip_stream);
+
+/* *busy = 1 while a refresh fired by a tick still runs for stream id on a
+ * refresh lane, else 0 (does not wait).  A scheduler may leave busy streams
+ * out of the next tick, so that their refresh overlaps the other streams'
+ * updates.  Errors: STATE, INVAL, CONVERGE (the finished refresh did not
+ * converge). */
+isvd_status isvd_stream_busy(isvd_engine* eng, isvd_id id, int32_t* busy);
 
 /* enable != 0 (the default): row-append ticks may leave their U rotations
  * pending (see isvd_tick) for throughput; 0: every tick joins them before
@@ -251,8 +268,8 @@ isvd_status isvd_sync(isvd_engine* eng, void* hip_stream);
 isvd_status isvd_set_pipelining(isvd_engine* eng, int32_t enable);
 
 /* The engine's rotation stream (a hipStream_t), e.g. to record an event
- * after the last tick's work: everything of a tick is done when that stream
- * has passed it. */
+ * after the last tick's work: every update of a tick is done when that
+ * stream has passed it (refreshes it fired may still run; see isvd_tick). */
 isvd_status isvd_rotation_stream(isvd_engine* eng, void** out);
 
 /* GPU time of one kernel launch of the update sequence, collected while
@@ -303,8 +320,10 @@ isvd_status isvd_set_rotation_variant(isvd_engine* eng, int32_t kc, int32_t vari
  * streams whose lifetime is complete, admits waiting streams in FIFO order
  * while their footprint (isvd_stream_bytes) fits the HBM budget, and
  * launches one tick of the oldest queued request of every admitted stream
- * (continuous batching: requests that arrive while ticks run on the device
- * join the next tick; up to max_inflight ticks overlap on the device).
+ * that is not busy with a refresh (continuous batching: requests that
+ * arrive while ticks run on the device join the next tick; up to
+ * max_inflight ticks overlap on the device, and refreshes fired by a tick
+ * overlap the following ticks of the other streams).
  * A request whose length or indices no longer fit its stream completes at
  * once with ISVD_E_SHAPE and is not part of a tick.  Times are seconds on
  * the server's host clock (isvd_server_clock); completion times come from

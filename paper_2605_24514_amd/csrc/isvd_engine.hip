@@ -20,6 +20,9 @@
 #include <cstring>
 #include <map>
 #include <string>
+#include <thread>
+#include <vector>
+#include <thread>
 #include <vector>
 
 #include "../../include/isvd.h"
@@ -75,6 +78,18 @@ struct Layout {
     size_t rs_b, p_b, q_b;   // bytes of one copy of the double-buffered rs, p and QU / QV
 };
 
+constexpr int kMaxLiveStreams = 16384;   // capacity of an engine's header array
+
+// A refresh workspace.  A lane's buffer that has to grow is retired, not
+// freed (work queued on other lanes may still be running); retired buffers
+// are freed where every lane is known to be idle.
+struct WsBuf {
+    char* p = nullptr;
+    size_t bytes = 0;
+    bool defer_free = false;
+    std::vector<char*> retired;
+};
+
 struct Stream {
     isvd_config cfg;
     int esz = 4;          // bytes per storage element
@@ -86,7 +101,8 @@ struct Stream {
     int64_t ntiles_max = 0;
     char* base = nullptr;
     Layout L{};
-    DevHeader* hdr = nullptr;
+    DevHeader* hdr = nullptr;   // the stream's entry of the engine's header array
+    int slot = -1;              // its index there
     // per-update scratch read by the rotations, double-buffered by the parity
     // of the stream's update count: a U rotation may still run while the
     // stream's next core writes the other copy
@@ -100,6 +116,10 @@ struct Stream {
     void* U[2] = {nullptr, nullptr};
     void* V[2] = {nullptr, nullptr};
     hipEvent_t ev_u0 = nullptr, ev_u1 = nullptr, ev_r0 = nullptr, ev_r1 = nullptr;
+    // a refresh fired by a tick runs on a refresh lane, after which ev_ready
+    // fires; until then later work on the stream waits for it
+    hipEvent_t ev_ready = nullptr;
+    bool refreshing = false;
     bool have_update_time = false, have_refresh_time = false;
     bool live = false;
     bool grow_pending = false;   // adaptive rank: the next append keeps one more triplet
@@ -122,7 +142,6 @@ Layout make_layout(const isvd_config& c, int esz, int kc, int64_t* ntiles_max) {
     const int64_t mx = std::max(c.m_cap, c.n_cap);
     const int64_t nt = cdiv(mx, kProjTile);
     *ntiles_max = nt;
-    L.hdr = take(sizeof(DevHeader));
     L.rs_b = align_up(sizeof(ReqScratch), 256);
     L.rs = take(2 * L.rs_b);
     L.S = take(sizeof(double) * (kc + 2));
@@ -219,15 +238,29 @@ struct isvd_engine {
     std::vector<Slot> ring;
     size_t ring_next = 0;
     // refresh workspace (sized for the largest refresh so far)
-    char* ws = nullptr;
-    size_t ws_bytes = 0;
+    WsBuf ws;
     // exact-metrics workspace
     char* mws = nullptr;
     size_t mws_bytes = 0;
-    // pinned copies of the device headers of a tick's streams whose policy
-    // reads the trackers (one copy-back per tick)
-    DevHeader* hdrs_host = nullptr;
-    int hdr_cap = 0;
+    // refresh lanes: the refreshes that the policies of one tick fire run
+    // concurrently, each lane with its own stream (default priority) and
+    // workspace
+    struct RefreshLane {
+        hipStream_t st = nullptr;
+        hipEvent_t ev = nullptr;     // recorded after the lane's latest work
+        bool pending = false;        // work queued since the last join
+        WsBuf ws;
+    };
+    std::vector<RefreshLane> rlanes;
+    hipEvent_t ev_policies = nullptr;
+    int* dsweeps = nullptr;          // device: Rayleigh-Ritz sweep count per header slot
+    int* rsweeps = nullptr;          // pinned copy
+    // the device headers of all live streams, one array (a slot per stream),
+    // so that a tick reads them back with one copy into the pinned mirror
+    DevHeader* hdr_dev = nullptr;
+    DevHeader* hdr_mirror = nullptr;
+    int hdr_hi = 0;                  // slots [0, hdr_hi) have been handed out
+    std::vector<int> hdr_free;
     // block shape (kRotVariant index) of the FP32 matrix-core rotation per
     // rank bucket (8, 16, 32, 64; the widest bucket uses the LDS-staged
     // kernel), chosen by isvd_autotune
@@ -271,7 +304,8 @@ isvd_status acquire_slot(isvd_engine* e, size_t bytes, Slot** out) {
     if (s.cap < bytes) {
         if (s.host) HIP_TRY(hipHostFree(s.host));
         if (s.dev) HIP_TRY(hipFree(s.dev));
-        size_t cap = align_up(std::max(bytes, (size_t)4096), 4096);
+        // grow geometrically: ticks of varying size settle after a few allocations
+        size_t cap = align_up(std::max({bytes, 2 * s.cap, (size_t)65536}), 4096);
         HIP_TRY(hipHostMalloc((void**)&s.host, cap, hipHostMallocDefault));
         HIP_TRY(hipMalloc((void**)&s.dev, cap));
         s.cap = cap;
@@ -681,20 +715,32 @@ WsLayout ws_layout(int64_t m, int64_t n, int b, int esz) {
     return w;
 }
 
-isvd_status ensure_ws(isvd_engine* e, size_t bytes) {
-    if (e->ws_bytes >= bytes) return ISVD_OK;
-    if (e->ws) {
-        HIP_TRY(hipDeviceSynchronize());
-        HIP_TRY(hipFree(e->ws));
-        e->ws = nullptr;
-        e->ws_bytes = 0;
+isvd_status ensure_ws(WsBuf& w, size_t bytes) {
+    if (w.bytes >= bytes) return ISVD_OK;
+    if (w.p) {
+        if (w.defer_free) {
+            w.retired.push_back(w.p);
+        } else {
+            HIP_TRY(hipDeviceSynchronize());
+            HIP_TRY(hipFree(w.p));
+        }
+        w.p = nullptr;
+        w.bytes = 0;
     }
-    if (hipMalloc((void**)&e->ws, bytes) != hipSuccess) {
-        e->ws = nullptr;
-        return fail(ISVD_E_NOMEM, "refresh workspace of %zu bytes", bytes);
+    // some slack, so that streams of slowly growing size do not reallocate each time
+    const size_t want = bytes + bytes / 4;
+    if (hipMalloc((void**)&w.p, want) != hipSuccess) {
+        w.p = nullptr;
+        return fail(ISVD_E_NOMEM, "refresh workspace of %zu bytes", want);
     }
-    e->ws_bytes = bytes;
+    w.bytes = want;
     return ISVD_OK;
+}
+isvd_status ensure_ws(isvd_engine* e, size_t bytes) { return ensure_ws(e->ws, bytes); }
+
+void free_retired(WsBuf& w) {
+    for (char* q : w.retired) (void)hipFree(q);
+    w.retired.clear();
 }
 
 // deterministic values in [-1, 1) (autotuner inputs)
@@ -761,10 +807,11 @@ void gemm_tn_f32(const float* A, int64_t lda, const float* Q, float* Zp, int64_t
 // working precision; 1 leaves an orthogonality error of about kappa(Y) times
 // the storage epsilon, which is all an intermediate block of the subspace
 // iteration needs: only its span is used).
+// With want_R, *R_out receives where the product of the passes' R factors is
+// left (R_2 R_1 for two passes).
 template <typename T>
-isvd_status cholqr(isvd_engine* e, const WsLayout& w, T* Y, int64_t rows, int b, bool want_R, int passes,
-                   hipStream_t st) {
-    char* ws = e->ws;
+isvd_status cholqr(char* ws, const WsLayout& w, T* Y, int64_t rows, int b, bool want_R, int passes,
+                   hipStream_t st, const double** R_out = nullptr) {
     double* Gp = (double*)(ws + w.Gp);
     double* G = (double*)(ws + w.G);
     double* R = (double*)(ws + w.R);
@@ -776,7 +823,8 @@ isvd_status cholqr(isvd_engine* e, const WsLayout& w, T* Y, int64_t rows, int b,
     for (int pass = 0; pass < passes; ++pass) {
         k_gram_mfma<T><<<nchunk, kThreads, 0, st>>>(Y, b, rows, b, gram_rpb(rows), Gp);
         k_gram_sum<<<(int)cdiv(gram_tiles(b) * 256, 32), 256, 0, st>>>(Gp, nchunk, b, G);
-        k_chol_inv<T><<<1, kCholThreads, 0, st>>>(G, b, R, RinvT, flag);
+        // the first pass's R goes straight where the product needs it
+        k_chol_inv<T><<<1, kCholThreads, 0, st>>>(G, b, want_R && pass == 0 ? Racc : R, RinvT, flag);
         if constexpr (sizeof(T) == 4) {
             if (b % 4 == 0)
                 gemm_nn_f32(Y, b, RinvT, Y, b, rows, b, b, st);
@@ -785,15 +833,9 @@ isvd_status cholqr(isvd_engine* e, const WsLayout& w, T* Y, int64_t rows, int b,
         } else {
             k_rotate_plain<T, 128><<<(int)cdiv(rows, 16), kThreads, 0, st>>>(Y, b, Y, b, rows, b, RinvT);
         }
-        if (want_R) {
-            if (pass == 0) {
-                HIP_TRY(hipMemcpyAsync(Racc, R, sizeof(double) * b * b, hipMemcpyDeviceToDevice, st));
-            } else {
-                k_small_gemm<<<(int)cdiv(b * b, 256), 256, 0, st>>>(R, Racc, Rtmp, b);
-                HIP_TRY(hipMemcpyAsync(Racc, Rtmp, sizeof(double) * b * b, hipMemcpyDeviceToDevice, st));
-            }
-        }
+        if (want_R && pass == 1) k_small_gemm<<<(int)cdiv(b * b, 256), 256, 0, st>>>(R, Racc, Rtmp, b);
     }
+    if (want_R && R_out) *R_out = passes >= 2 ? Rtmp : Racc;
     HIP_TRY(hipGetLastError());
     return ISVD_OK;
 }
@@ -819,9 +861,13 @@ struct RefreshPlan {
 // left / right rotations of the block in ws.QU / ws.QV, block bases in
 // ws.Y (Q_Y) and ws.X.  Nothing of the stream changes.
 template <typename T>
-isvd_status refresh_compute(isvd_engine* e, Stream& s, bool init, hipStream_t st, RefreshPlan* plan) {
+isvd_status refresh_compute(isvd_engine* e, Stream& s, bool init, hipStream_t st, RefreshPlan* plan,
+                            const DevHeader* known = nullptr, int* sweeps_dev = nullptr, WsBuf* wk = nullptr) {
+    WsBuf& wb = wk ? *wk : e->ws;
     DevHeader h{};
-    if (!init) {
+    if (!init && known) {
+        h = *known;
+    } else if (!init) {
         HIP_TRY(hipMemcpyAsync(&h, s.hdr, sizeof(DevHeader), hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
     }
@@ -835,24 +881,24 @@ isvd_status refresh_compute(isvd_engine* e, Stream& s, bool init, hipStream_t st
     const bool exact = (b == n);
     const int iters = exact ? 0 : (s.cfg.refresh_iters >= 0 ? s.cfg.refresh_iters : (init ? 8 : 3));
     WsLayout w = ws_layout(m, n, b, (int)sizeof(T));
-    ST_TRY(ensure_ws(e, w.total));
-    char* ws = e->ws;
+    ST_TRY(ensure_ws(wb, w.total));
+    char* ws = wb.p;
     T* X = (T*)(ws + w.X);
     T* Y = (T*)(ws + w.Y);
     double* Zp = (double*)(ws + w.Zp);
     const T* A = (const T*)s.A;
     const int64_t lda = lda_of(s.cfg);
-    HIP_TRY(hipMemsetAsync(ws + w.flag, 0, sizeof(int) * 4, st));
     const int cur = init ? 0 : h.cur;
     const int kw = init ? 0 : std::min(h.k, b);
     k_start_block<T><<<(int)cdiv(n * b, 256), 256, 0, st>>>(X, b, n, b, (const T*)s.V[cur], init ? 4 : h.ld, kw,
-                                                           0x5eedull + (uint64_t)s.t, exact ? 1 : 0);
-    if (!exact) ST_TRY(cholqr<T>(e, w, X, n, b, false, iters > 0 ? 1 : 2, st));
+                                                           0x5eedull + (uint64_t)s.t, exact ? 1 : 0,
+                                                           (int*)(ws + w.flag));
+    if (!exact) ST_TRY(cholqr<T>(ws, w, X, n, b, false, iters > 0 ? 1 : 2, st));
     const int64_t nchunk = std::min<int64_t>(32, cdiv(m, kGemmK));
     const int64_t rpc = cdiv(m, nchunk);
     for (int it = 0; it < iters; ++it) {
         gemm_nn<T>(A, lda, X, Y, m, n, b, st);
-        ST_TRY(cholqr<T>(e, w, Y, m, b, false, 1, st));
+        ST_TRY(cholqr<T>(ws, w, Y, m, b, false, 1, st));
         if constexpr (sizeof(T) == 4) {
             const int64_t ncb = cdiv(n, kTnCols), nch = tn_chunks(m, n), per = ncb * kTnDump;
             gemm_tn_f32(A, lda, Y, (float*)Zp, m, n, b, nch, st);
@@ -862,20 +908,21 @@ isvd_status refresh_compute(isvd_engine* e, Stream& s, bool init, hipStream_t st
             k_gemm_tn_partial<T><<<grid, kThreads, 0, st>>>(A, lda, Y, b, Zp, m, n, b, rpc);
             k_sum_parts<T><<<(int)cdiv(n * b, 256), 256, 0, st>>>(Zp, (int)nchunk, n * b, n * b, X);
         }
-        ST_TRY(cholqr<T>(e, w, X, n, b, false, it + 1 == iters ? 2 : 1, st));
+        ST_TRY(cholqr<T>(ws, w, X, n, b, false, it + 1 == iters ? 2 : 1, st));
     }
     gemm_nn<T>(A, lda, X, Y, m, n, b, st);
-    ST_TRY(cholqr<T>(e, w, Y, m, b, true, 2, st));
+    const double* Rfin = nullptr;
+    ST_TRY(cholqr<T>(ws, w, Y, m, b, true, 2, st, &Rfin));
     const int ldo = round4(k);
     if constexpr (sizeof(T) == 4)
         k_svd_small_noj<T><<<1, RRShape::NT, sizeof(double) * svd_noj_lds_doubles(), st>>>(
-            (const double*)(ws + w.Racc), b, k, (double*)(ws + w.Sr), (T*)(ws + w.QU), (T*)(ws + w.QV), ldo,
-            (int*)(ws + w.sweeps));
+            Rfin, b, k, (double*)(ws + w.Sr), (T*)(ws + w.QU), (T*)(ws + w.QV), ldo,
+            sweeps_dev ? sweeps_dev : (int*)(ws + w.sweeps));
     else
         k_svd_small<T><<<1, JacobiShape<kMaxBlock + 1>::NT,
                      core_lds_bytes(kMaxBlock, JacobiShape<kMaxBlock + 1>::LDW, true), st>>>(
-        (const double*)(ws + w.Racc), b, k, (double*)(ws + w.Sr), (T*)(ws + w.QU), (T*)(ws + w.QV), ldo,
-        (int*)(ws + w.sweeps));
+        Rfin, b, k, (double*)(ws + w.Sr), (T*)(ws + w.QU), (T*)(ws + w.QV), ldo,
+        sweeps_dev ? sweeps_dev : (int*)(ws + w.sweeps));
     HIP_TRY(hipGetLastError());
     plan->k = k;
     plan->b = b;
@@ -890,7 +937,9 @@ isvd_status refresh_compute(isvd_engine* e, Stream& s, bool init, hipStream_t st
 // Header after a refresh: the rank is the number of Ritz values above
 // 8 b eps64 sigma_1 (at least one): directions the block does not resolve
 // (A of numerical rank below k) are left out, and appends bring the rank back.
-__global__ void k_commit_header(DevHeader* hdr, const double* S, int k, int ld, int b) {
+// Also copies the Ritz values Sr into the stream's S.
+__global__ void k_commit_header(DevHeader* hdr, double* S_out, const double* S, int k, int ld, int b) {
+    for (int j = threadIdx.x; j < k; j += blockDim.x) S_out[j] = S[j];
     if (threadIdx.x == 0) {
         const double cut = 8.0 * b * 2.220446049250313e-16 * S[0];
         int kr = 1;
@@ -915,13 +964,26 @@ __global__ void k_sigma_trackers(DevHeader* hdr, const double* S, int k) {
 }
 
 // Adaptive rank: drop the last triplet (columns past k are ignored by every kernel).
-__global__ void k_shrink(DevHeader* hdr, const double* S) {
-    if (threadIdx.x == 0 && hdr->k > 1) {
+__device__ inline void shrink_one(DevHeader* hdr, const double* S) {
+    if (hdr->k > 1) {
         const int k = hdr->k - 1;
         hdr->k = k;
         hdr->sigma2 -= S[k] * S[k];
         hdr->sigma_last = S[k - 1];
     }
+}
+__global__ void k_shrink(DevHeader* hdr, const double* S) {
+    if (threadIdx.x == 0) shrink_one(hdr, S);
+}
+// the shrinks of one tick, passed by value (thread i: stream i)
+constexpr int kShrinkBatch = 224;
+struct ShrinkList {
+    int n;
+    DevHeader* hdr[kShrinkBatch];
+    const double* S[kShrinkBatch];
+};
+__global__ void k_shrink_many(ShrinkList L) {
+    if ((int)threadIdx.x < L.n) shrink_one(L.hdr[threadIdx.x], L.S[threadIdx.x]);
 }
 
 isvd_status ensure_mws(isvd_engine* e, size_t bytes);
@@ -975,45 +1037,55 @@ isvd_status direct_trackers(isvd_engine* e, Stream& s, hipStream_t st, double* t
 }
 
 // Install the computed TruncatedSVD as the stream's state.
+// sweeps_deferred: the Rayleigh-Ritz sweep count went to a caller's slot,
+// which the caller checks (no wait here).
 template <typename T>
-isvd_status refresh_commit(isvd_engine* e, Stream& s, const RefreshPlan& plan, bool store_ref, hipStream_t st) {
-    char* ws = e->ws;
+isvd_status refresh_commit(isvd_engine* e, Stream& s, const RefreshPlan& plan, bool store_ref, hipStream_t st,
+                           bool sweeps_deferred = false, WsBuf* wk = nullptr) {
+    char* ws = wk ? wk->p : e->ws.p;
     const WsLayout& w = plan.w;
     const int nxt = plan.cur ^ 1;
-    HIP_TRY(hipMemcpyAsync(s.S, ws + w.Sr, sizeof(double) * plan.k, hipMemcpyDeviceToDevice, st));
-    k_rotate_plain<T, 128, true><<<(int)cdiv(plan.m, 16), kThreads, 0, st>>>((T*)(ws + w.Y), plan.b, (T*)s.U[nxt],
-                                                                      plan.ldo, plan.m, plan.b, (T*)(ws + w.QU));
+    // U = Q_Y W (also into U_ref when the reference is stored), V = X H
+    k_rotate_plain<T, 128, true><<<(int)cdiv(plan.m, 16), kThreads, 0, st>>>(
+        (T*)(ws + w.Y), plan.b, (T*)s.U[nxt], plan.ldo, plan.m, plan.b, (T*)(ws + w.QU),
+        store_ref ? (T*)s.Uref : nullptr);
     k_rotate_plain<T, 128, true><<<(int)cdiv(plan.n, 16), kThreads, 0, st>>>((T*)(ws + w.X), plan.b, (T*)s.V[nxt],
                                                                       plan.ldo, plan.n, plan.b, (T*)(ws + w.QV));
-    k_commit_header<<<1, 1, 0, st>>>(s.hdr, s.S, plan.k, plan.ldo, plan.b);
+    k_commit_header<<<1, 64, 0, st>>>(s.hdr, s.S, (const double*)(ws + w.Sr), plan.k, plan.ldo, plan.b);
     if (store_ref) {
-        HIP_TRY(hipMemcpyAsync(s.Uref, s.U[nxt], (size_t)sizeof(T) * round16(plan.m) * plan.ldo, hipMemcpyDeviceToDevice,
-                               st));
         k_track_reset<<<1, kThreads, 0, st>>>(s.hdr, s.TM, s.TH, s.kc);
     } else if (s.TM) {
         ST_TRY(direct_trackers(e, s, st, nullptr, s.TM, s.TH, s.kc));
     }
     HIP_TRY(hipGetLastError());
+    s.k_target = plan.k;
+    if (sweeps_deferred) return ISVD_OK;
     int sweeps = 0;
     HIP_TRY(hipMemcpyAsync(&sweeps, ws + w.sweeps, sizeof(int), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     if (sweeps < 0) return fail(ISVD_E_CONVERGE, "Rayleigh-Ritz Jacobi did not converge");
-    s.k_target = plan.k;
     return ISVD_OK;
 }
 
+// known: the stream's device header when the caller has it (saves a wait);
+// sweeps_dev: device slot for the Rayleigh-Ritz sweep count, which the
+// caller checks after the stream has run (without it this call waits).
 isvd_status do_refresh(isvd_engine* e, Stream& s, bool init, bool store_ref, hipStream_t st,
-                       const RefreshPlan* computed = nullptr) {
+                       const RefreshPlan* computed = nullptr, const DevHeader* known = nullptr,
+                       int* sweeps_dev = nullptr, WsBuf* wk = nullptr) {
     HIP_TRY(hipEventRecord(s.ev_r0, st));
     RefreshPlan plan;
     isvd_status rc = ISVD_OK;
     if (computed) {
         plan = *computed;
     } else {
-        rc = s.esz == 8 ? refresh_compute<double>(e, s, init, st, &plan) : refresh_compute<float>(e, s, init, st, &plan);
+        rc = s.esz == 8 ? refresh_compute<double>(e, s, init, st, &plan, known, sweeps_dev, wk)
+                        : refresh_compute<float>(e, s, init, st, &plan, known, sweeps_dev, wk);
         if (rc != ISVD_OK) return rc;
     }
-    rc = s.esz == 8 ? refresh_commit<double>(e, s, plan, store_ref, st) : refresh_commit<float>(e, s, plan, store_ref, st);
+    const bool deferred = sweeps_dev != nullptr && computed == nullptr;
+    rc = s.esz == 8 ? refresh_commit<double>(e, s, plan, store_ref, st, deferred, wk)
+                    : refresh_commit<float>(e, s, plan, store_ref, st, deferred, wk);
     if (rc != ISVD_OK) return rc;
     HIP_TRY(hipEventRecord(s.ev_r1, st));
     s.have_refresh_time = true;
@@ -1090,7 +1162,7 @@ isvd_status exact_metrics_t(isvd_engine* e, Stream& s, hipStream_t st, Exact* ou
     HIP_TRY(hipGetLastError());
     std::vector<double> hs(7), sr(plan->k);
     HIP_TRY(hipMemcpyAsync(hs.data(), scal, sizeof(double) * 7, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(sr.data(), e->ws + plan->w.Sr, sizeof(double) * plan->k, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(sr.data(), e->ws.p + plan->w.Sr, sizeof(double) * plan->k, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     out->fro2 = hs[0];
     out->e_inc = std::sqrt(std::max(hs[1], 0.0));
@@ -1124,10 +1196,27 @@ bool policy_needs_header(const Stream& s) {
 
 // Policy evaluation after the update at tick t (Algorithm 1; Section 3).
 // `h` is the device header after the update when the policy needs it.
-isvd_status after_update(isvd_engine* e, Stream& s, hipStream_t st, const DevHeader* h) {
+// Policy actions of one tick that its caller runs together.
+struct Deferred {
+    std::vector<Stream*> refresh;   // fired refreshes
+    std::vector<Stream*> shrink;    // adaptive-rank shrinks
+};
+
+// With `defer`, a refresh that the policy fires, or an adaptive shrink, is
+// appended to it (the caller runs the tick's actions together) instead of
+// running here.
+isvd_status after_update(isvd_engine* e, Stream& s, hipStream_t st, const DevHeader* h,
+                         Deferred* defer = nullptr) {
     const isvd_policy& p = s.cfg.policy;
+    auto refresh = [&]() -> isvd_status {
+        if (defer) {
+            defer->refresh.push_back(&s);
+            return ISVD_OK;
+        }
+        return do_refresh(e, s, false, true, st);
+    };
     if (p.kind == ISVD_POL_PERIODIC) {
-        if (p.period > 0 && s.t % p.period == 0) return do_refresh(e, s, false, true, st);
+        if (p.period > 0 && s.t % p.period == 0) return refresh();
         return ISVD_OK;
     }
     if (p.kind == ISVD_POL_ERROR) {
@@ -1146,7 +1235,7 @@ isvd_status after_update(isvd_engine* e, Stream& s, hipStream_t st, const DevHea
             ST_TRY(read_header(s, st, &hh));
             h = &hh;
         }
-        if (h->angle_ref > p.theta_max) return do_refresh(e, s, false, true, st);
+        if (h->angle_ref > p.theta_max) return refresh();
         return ISVD_OK;
     }
     if (p.kind == ISVD_POL_ADAPTIVE) {
@@ -1166,14 +1255,105 @@ isvd_status after_update(isvd_engine* e, Stream& s, hipStream_t st, const DevHea
         if (low || novel) {
             if (s.k_target < kmax) s.grow_pending = true;
         } else if (h->k > kmin && N > 0.0 && (s2 - h->sigma_last * h->sigma_last) / N >= p.tau + p.band) {
-            k_shrink<<<1, 1, 0, st>>>(s.hdr, s.S);
-            HIP_TRY(hipGetLastError());
+            if (defer) {
+                defer->shrink.push_back(&s);
+            } else {
+                k_shrink<<<1, 1, 0, st>>>(s.hdr, s.S);
+                HIP_TRY(hipGetLastError());
+            }
             s.k_target = h->k - 1;
             s.grow_pending = false;
         }
-        if (p.period > 0 && s.t % p.period == 0) return do_refresh(e, s, false, true, st);
+        if (p.period > 0 && s.t % p.period == 0) return refresh();
         return ISVD_OK;
     }
+    return ISVD_OK;
+}
+
+// The refreshes fired by one tick's policies, concurrently: refresh i runs on
+// lane i mod kRefreshLanes with the lane's workspace, after everything the
+// caller's stream holds so far (the tick and its policy actions); the caller's
+// stream then waits for the lanes.  The streams of `list` are distinct.
+constexpr int kRefreshLanes = 8;
+isvd_status refresh_batch(isvd_engine* e, const std::vector<Stream*>& list, hipStream_t st) {
+    const int cnt = (int)list.size();
+    if (e->rlanes.empty()) {
+        e->rlanes.resize(kRefreshLanes);
+        for (auto& l : e->rlanes) {
+            HIP_TRY(hipStreamCreateWithFlags(&l.st, hipStreamNonBlocking));
+            HIP_TRY(hipEventCreateWithFlags(&l.ev, hipEventDisableTiming));
+            l.ws.defer_free = true;
+        }
+        HIP_TRY(hipEventCreateWithFlags(&e->ev_policies, hipEventDisableTiming));
+        HIP_TRY(hipMalloc((void**)&e->dsweeps, sizeof(int) * kMaxLiveStreams));
+        HIP_TRY(hipHostMalloc((void**)&e->rsweeps, sizeof(int) * kMaxLiveStreams, hipHostMallocDefault));
+    }
+    // buffers retired by workspace growth go once their lane has drained
+    for (auto& l : e->rlanes)
+        if (!l.ws.retired.empty() && hipStreamQuery(l.st) == hipSuccess) free_retired(l.ws);
+    // headers after every policy action of the tick (one copy, one wait)
+    HIP_TRY(hipMemcpyAsync(e->hdr_mirror, e->hdr_dev, sizeof(DevHeader) * e->hdr_hi, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    HIP_TRY(hipEventRecord(e->ev_policies, st));
+    const int used = std::min(cnt, kRefreshLanes);
+    for (int l = 0; l < used; ++l) HIP_TRY(hipStreamWaitEvent(e->rlanes[l].st, e->ev_policies, 0));
+    // each lane's refreshes are queued by a host thread of its own (the
+    // launches of one refresh cost about as much host time as the device
+    // spends on a small stream); the streams are distinct, so the threads
+    // share no mutable state.  Nothing waits for the lanes here: a stream
+    // under refresh is marked, and later work on it waits for its ev_ready.
+    std::vector<isvd_status> rcs(used, ISVD_OK);
+    std::vector<std::string> msgs(used);
+    auto run_lane = [&](int l) {
+        (void)hipSetDevice(e->device);
+        auto& lane = e->rlanes[l];
+        for (int i = l; i < cnt && rcs[l] == ISVD_OK; i += kRefreshLanes) {
+            Stream& s = *list[i];
+            isvd_status rc = do_refresh(e, s, false, true, lane.st, nullptr, e->hdr_mirror + s.slot,
+                                        e->dsweeps + s.slot, &lane.ws);
+            if (rc == ISVD_OK &&
+                (hipMemcpyAsync(e->rsweeps + s.slot, e->dsweeps + s.slot, sizeof(int), hipMemcpyDeviceToHost,
+                                lane.st) != hipSuccess ||
+                 hipEventRecord(s.ev_ready, lane.st) != hipSuccess))
+                rc = fail(ISVD_E_DEVICE, "refresh lane bookkeeping failed");
+            if (rc == ISVD_OK) s.refreshing = true;
+            rcs[l] = rc;
+        }
+        if (rcs[l] != ISVD_OK) msgs[l] = isvd_last_error();
+    };
+    std::vector<std::thread> workers;
+    for (int l = 1; l < used; ++l) workers.emplace_back(run_lane, l);
+    run_lane(0);
+    for (auto& t : workers) t.join();
+    for (int l = 0; l < used; ++l) {
+        HIP_TRY(hipEventRecord(e->rlanes[l].ev, e->rlanes[l].st));
+        e->rlanes[l].pending = true;
+    }
+    for (int l = 0; l < used; ++l)
+        if (rcs[l] != ISVD_OK) return fail(rcs[l], "%s", msgs[l].c_str());
+    return ISVD_OK;
+}
+
+// A stream whose lane refresh has finished: check its Rayleigh-Ritz sweep count.
+isvd_status settle(isvd_engine* e, Stream& s, bool wait) {
+    if (!s.refreshing) return ISVD_OK;
+    if (wait) {
+        HIP_TRY(hipEventSynchronize(s.ev_ready));
+    } else if (hipEventQuery(s.ev_ready) != hipSuccess) {
+        return ISVD_OK;
+    }
+    s.refreshing = false;
+    if (e->rsweeps[s.slot] < 0) return fail(ISVD_E_CONVERGE, "Rayleigh-Ritz Jacobi did not converge");
+    return ISVD_OK;
+}
+
+// Work queued on `st` after this waits for every refresh lane.
+isvd_status join_refreshes(isvd_engine* e, hipStream_t st) {
+    for (auto& l : e->rlanes)
+        if (l.pending) {
+            HIP_TRY(hipStreamWaitEvent(st, l.ev, 0));
+            l.pending = false;
+        }
     return ISVD_OK;
 }
 
@@ -1238,6 +1418,8 @@ isvd_status single_update(isvd_engine* e, Stream& s, int kind, const void* paylo
     Req r = make_req(e, s, kind, payload, i, j, delta, k_keep_for(s, kind));
     g.all.push_back(r);
     if (kind != kEntry) g.proj.push_back(r);
+    ST_TRY(settle(e, s, false));
+    if (s.refreshing) HIP_TRY(hipStreamWaitEvent(st, s.ev_ready, 0));
     ST_TRY(join(e, st));
     HIP_TRY(hipEventRecord(s.ev_u0, st));
     ST_TRY(run_groups(e, groups, st, false));
@@ -1256,10 +1438,16 @@ void free_stream(isvd_engine* e, Stream* s) {
         (void)hipFree(s->base);
         e->used -= s->L.total;
     }
+    if (s->slot >= 0) {
+        e->hdr_free.push_back(s->slot);
+        s->slot = -1;
+        s->hdr = nullptr;
+    }
     if (s->ev_u0) (void)hipEventDestroy(s->ev_u0);
     if (s->ev_u1) (void)hipEventDestroy(s->ev_u1);
     if (s->ev_r0) (void)hipEventDestroy(s->ev_r0);
     if (s->ev_r1) (void)hipEventDestroy(s->ev_r1);
+    if (s->ev_ready) (void)hipEventDestroy(s->ev_ready);
     s->base = nullptr;
     s->live = false;
 }
@@ -1329,9 +1517,20 @@ isvd_status isvd_engine_destroy(isvd_engine* e) {
         if (s.dev) (void)hipFree(s.dev);
         if (s.ev) (void)hipEventDestroy(s.ev);
     }
-    if (e->ws) (void)hipFree(e->ws);
+    if (e->ws.p) (void)hipFree(e->ws.p);
+    free_retired(e->ws);
     if (e->mws) (void)hipFree(e->mws);
-    if (e->hdrs_host) (void)hipHostFree(e->hdrs_host);
+    if (e->hdr_dev) (void)hipFree(e->hdr_dev);
+    if (e->hdr_mirror) (void)hipHostFree(e->hdr_mirror);
+    for (auto& l : e->rlanes) {
+        if (l.ws.p) (void)hipFree(l.ws.p);
+        free_retired(l.ws);
+        if (l.ev) (void)hipEventDestroy(l.ev);
+        if (l.st) (void)hipStreamDestroy(l.st);
+    }
+    if (e->ev_policies) (void)hipEventDestroy(e->ev_policies);
+    if (e->dsweeps) (void)hipFree(e->dsweeps);
+    if (e->rsweeps) (void)hipHostFree(e->rsweeps);
     for (hipEvent_t ev : e->ev_pool) (void)hipEventDestroy(ev);
     for (hipEvent_t ev : e->ev_core) (void)hipEventDestroy(ev);
     if (e->ev_main) (void)hipEventDestroy(e->ev_main);
@@ -1361,7 +1560,18 @@ isvd_status isvd_profile(isvd_engine* e, int32_t enable) {
 isvd_status isvd_sync(isvd_engine* e, void* hip_stream) {
     if (!e) return fail(ISVD_E_INVAL, "null engine");
     ST_TRY(ensure_device(e));
+    ST_TRY(join_refreshes(e, (hipStream_t)hip_stream));
     return join(e, (hipStream_t)hip_stream);
+}
+
+isvd_status isvd_stream_busy(isvd_engine* e, isvd_id id, int32_t* busy) {
+    Stream* s = nullptr;
+    ST_TRY(get_stream(e, id, &s));
+    if (!busy) return fail(ISVD_E_INVAL, "null output");
+    ST_TRY(ensure_device(e));
+    ST_TRY(settle(e, *s, false));
+    *busy = s->refreshing ? 1 : 0;
+    return ISVD_OK;
 }
 
 isvd_status isvd_set_pipelining(isvd_engine* e, int32_t enable) {
@@ -1568,9 +1778,22 @@ static isvd_status init_common(isvd_engine* e, const isvd_config* cfg, const voi
     s->n = cfg->n0;
     s->L = make_layout(s->cfg, s->esz, s->kc, &s->ntiles_max);
     if (e->budget && e->used + s->L.total > e->budget) {
+        const size_t bytes = s->L.total;
         delete s;
-        return fail(ISVD_E_BUDGET, "stream needs %zu bytes, %llu of %llu in use", s->L.total,
+        return fail(ISVD_E_BUDGET, "stream needs %zu bytes, %llu of %llu in use", bytes,
                     (unsigned long long)e->used, (unsigned long long)e->budget);
+    }
+    if (!e->hdr_dev) {
+        if (hipMalloc((void**)&e->hdr_dev, sizeof(DevHeader) * kMaxLiveStreams) != hipSuccess ||
+            hipHostMalloc((void**)&e->hdr_mirror, sizeof(DevHeader) * kMaxLiveStreams, hipHostMallocDefault) !=
+                hipSuccess) {
+            delete s;
+            return fail(ISVD_E_NOMEM, "stream header array");
+        }
+    }
+    if (e->hdr_free.empty() && e->hdr_hi >= kMaxLiveStreams) {
+        delete s;
+        return fail(ISVD_E_NOMEM, "more than %d live streams", kMaxLiveStreams);
     }
     if (hipMalloc((void**)&s->base, s->L.total) != hipSuccess) {
         size_t bytes = s->L.total;
@@ -1580,7 +1803,13 @@ static isvd_status init_common(isvd_engine* e, const isvd_config* cfg, const voi
     }
     e->used += s->L.total;
     char* b = s->base;
-    s->hdr = (DevHeader*)(b + s->L.hdr);
+    if (!e->hdr_free.empty()) {
+        s->slot = e->hdr_free.back();
+        e->hdr_free.pop_back();
+    } else {
+        s->slot = e->hdr_hi++;
+    }
+    s->hdr = e->hdr_dev + s->slot;
     for (int q = 0; q < 2; ++q) {
         s->rs[q] = (ReqScratch*)(b + s->L.rs + q * s->L.rs_b);
         s->p[q] = (double*)(b + s->L.p + q * s->L.p_b);
@@ -1609,7 +1838,8 @@ static isvd_status init_common(isvd_engine* e, const isvd_config* cfg, const voi
         free_stream(e, s);
         return rc;
     };
-    if (hipEventCreate(&s->ev_u0) != hipSuccess || hipEventCreate(&s->ev_u1) != hipSuccess ||
+    if (hipEventCreateWithFlags(&s->ev_ready, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreate(&s->ev_u0) != hipSuccess || hipEventCreate(&s->ev_u1) != hipSuccess ||
         hipEventCreate(&s->ev_r0) != hipSuccess || hipEventCreate(&s->ev_r1) != hipSuccess)
         return bail(fail(ISVD_E_DEVICE, "event creation failed"));
     DevHeader h0{};
@@ -1653,10 +1883,10 @@ static isvd_status init_common(isvd_engine* e, const isvd_config* cfg, const voi
     if (rc != ISVD_OK) return bail(rc);
     const int nchunk = (int)cdiv(m0, kFroRows);
     if (s->esz == 8)
-        k_fro2_partial<double><<<nchunk, kThreads, 0, st>>>((const double*)s->A, ldA, m0, n0, (double*)e->ws);
+        k_fro2_partial<double><<<nchunk, kThreads, 0, st>>>((const double*)s->A, ldA, m0, n0, (double*)e->ws.p);
     else
-        k_fro2_partial<float><<<nchunk, kThreads, 0, st>>>((const float*)s->A, ldA, m0, n0, (double*)e->ws);
-    k_sum_parts<double><<<1, 1, 0, st>>>((const double*)e->ws, nchunk, 1, 1, &s->hdr->N);
+        k_fro2_partial<float><<<nchunk, kThreads, 0, st>>>((const float*)s->A, ldA, m0, n0, (double*)e->ws.p);
+    k_sum_parts<double><<<1, 1, 0, st>>>((const double*)e->ws.p, nchunk, 1, 1, &s->hdr->N);
     if (hipGetLastError() != hipSuccess) return bail(fail(ISVD_E_DEVICE, "norm launch"));
     rc = given ? install_factors(*s, *given, st) : do_refresh(e, *s, true, true, st);
     if (tmpdev) {
@@ -1725,6 +1955,7 @@ isvd_status isvd_refresh(isvd_engine* e, isvd_id id, int32_t store_reference, vo
     Stream* s = nullptr;
     ST_TRY(get_stream(e, id, &s));
     ST_TRY(ensure_device(e));
+    ST_TRY(settle(e, *s, true));
     ST_TRY(join(e, (hipStream_t)hip_stream));
     return do_refresh(e, *s, false, store_reference != 0, (hipStream_t)hip_stream);
 }
@@ -1735,6 +1966,7 @@ isvd_status isvd_metrics(isvd_engine* e, isvd_id id, int32_t compute_exact, void
     if (!out) return fail(ISVD_E_INVAL, "null output");
     ST_TRY(ensure_device(e));
     hipStream_t st = (hipStream_t)hip_stream;
+    ST_TRY(settle(e, *s, true));
     ST_TRY(join(e, st));
     DevHeader h{};
     std::vector<double> S(s->kc + 2, 0.0);
@@ -1801,6 +2033,7 @@ isvd_status isvd_get_factors(isvd_engine* e, isvd_id id, double* U, int64_t ldu,
     ST_TRY(get_stream(e, id, &s));
     ST_TRY(ensure_device(e));
     hipStream_t st = (hipStream_t)hip_stream;
+    ST_TRY(settle(e, *s, true));
     ST_TRY(join(e, st));
     DevHeader h{};
     HIP_TRY(hipMemcpyAsync(&h, s->hdr, sizeof(h), hipMemcpyDeviceToHost, st));
@@ -1832,6 +2065,7 @@ isvd_status isvd_get_matrix(isvd_engine* e, isvd_id id, double* A, int64_t lda, 
     if (!A || lda < s->n) return fail(ISVD_E_INVAL, "null output or lda < n");
     ST_TRY(ensure_device(e));
     hipStream_t st = (hipStream_t)hip_stream;
+    ST_TRY(settle(e, *s, true));
     ST_TRY(join(e, st));
     DevHeader h{};
     HIP_TRY(hipMemcpyAsync(&h, s->hdr, sizeof(h), hipMemcpyDeviceToHost, st));
@@ -1895,6 +2129,11 @@ isvd_status isvd_tick(isvd_engine* e, int32_t count, const isvd_request* reqs, v
     }
     ST_TRY(ensure_device(e));
     hipStream_t st = (hipStream_t)hip_stream;
+    // streams whose refresh still runs on a lane: the tick waits for those only
+    for (int q = 0; q < count; ++q) {
+        ST_TRY(settle(e, *ss[q], false));
+        if (ss[q]->refreshing) HIP_TRY(hipStreamWaitEvent(st, ss[q]->ev_ready, 0));
+    }
     // row appends of streams without a refresh policy pipeline with the
     // next tick; anything that reads U (column appends, entry updates,
     // trackers) waits for the pending U rotations, and a policy may refresh
@@ -1940,24 +2179,27 @@ isvd_status isvd_tick(isvd_engine* e, int32_t count, const isvd_request* reqs, v
         if (reqs[q].kind == ISVD_COL) s.n += 1;
         s.t += 1;
     }
-    // trackers of the streams whose policy reads them: one copy-back
+    // trackers of the streams whose policy reads them: one copy of the header array
     int nh = 0;
     for (int q = 0; q < count; ++q) nh += policy_needs_header(*ss[q]) ? 1 : 0;
     if (nh > 0) {
-        if (e->hdr_cap < count) {
-            if (e->hdrs_host) HIP_TRY(hipHostFree(e->hdrs_host));
-            e->hdrs_host = nullptr;
-            e->hdr_cap = 0;
-            HIP_TRY(hipHostMalloc((void**)&e->hdrs_host, sizeof(DevHeader) * count, hipHostMallocDefault));
-            e->hdr_cap = count;
-        }
-        for (int q = 0; q < count; ++q)
-            if (policy_needs_header(*ss[q]))
-                HIP_TRY(hipMemcpyAsync(e->hdrs_host + q, ss[q]->hdr, sizeof(DevHeader), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(e->hdr_mirror, e->hdr_dev, sizeof(DevHeader) * e->hdr_hi, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
     }
+    Deferred d;
     for (int q = 0; q < count; ++q)
-        ST_TRY(after_update(e, *ss[q], st, policy_needs_header(*ss[q]) ? e->hdrs_host + q : nullptr));
+        ST_TRY(after_update(e, *ss[q], st, policy_needs_header(*ss[q]) ? e->hdr_mirror + ss[q]->slot : nullptr, &d));
+    for (size_t i0 = 0; i0 < d.shrink.size(); i0 += kShrinkBatch) {
+        ShrinkList L{};
+        L.n = (int)std::min<size_t>(kShrinkBatch, d.shrink.size() - i0);
+        for (int i = 0; i < L.n; ++i) {
+            L.hdr[i] = d.shrink[i0 + i]->hdr;
+            L.S[i] = d.shrink[i0 + i]->S;
+        }
+        k_shrink_many<<<1, kShrinkBatch, 0, st>>>(L);
+        HIP_TRY(hipGetLastError());
+    }
+    if (!d.refresh.empty()) ST_TRY(refresh_batch(e, d.refresh, st));
     return ISVD_OK;
 }
 

@@ -636,11 +636,12 @@ __global__ void k_small_gemm(const double* __restrict__ A, const double* __restr
 }
 
 // out[r, 0:ldo] = in[r, 0:kin] Q[0:kin, 0:ldo]   (may run in place when ldi == ldo);
-// `in` row-major, `out` row-major or, when TILED_OUT, in the tiled basis layout
+// `in` row-major, `out` row-major or, when TILED_OUT, in the tiled basis layout;
+// out2 (optional) receives a second copy
 template <typename T, int KC, bool TILED_OUT = false>
 __global__ void __launch_bounds__(kThreads) k_rotate_plain(const T* in, int ldi, T* out, int ldo,
                                                            int64_t rows, int kin,
-                                                           const T* __restrict__ Q) {
+                                                           const T* __restrict__ Q, T* out2 = nullptr) {
     constexpr int RT = KC <= 64 ? 64 : 16;
     __shared__ T sQ[KC * KC];
     __shared__ T sX[RT * KC];
@@ -653,7 +654,9 @@ __global__ void __launch_bounds__(kThreads) k_rotate_plain(const T* in, int ldi,
         const int rr = e / ldo, j = e % ldo;
         T acc = (T)0;
         for (int c = 0; c < kin; ++c) acc += sX[rr * ldi + c] * sQ[c * ldo + j];
-        out[TILED_OUT ? uvo(r0 + rr, j, ldo) : (r0 + rr) * ldo + j] = acc;
+        const int64_t o = TILED_OUT ? uvo(r0 + rr, j, ldo) : (r0 + rr) * ldo + j;
+        out[o] = acc;
+        if (out2) out2[o] = acc;
     }
 }
 
@@ -768,11 +771,13 @@ __host__ __device__ constexpr size_t svd_noj_lds_doubles() {
 }
 
 // Start block: X[:, 0:kw] = V[:, 0:kw] (warm start), the remaining columns a
-// deterministic hash in [-1, 1); identity when `ident` (b = n).
+// deterministic hash in [-1, 1); identity when `ident` (b = n).  Also clears
+// the four flag words of the refresh.
 template <typename T>
 __global__ void k_start_block(T* __restrict__ X, int ldx, int64_t n, int b, const T* __restrict__ V,
-                              int ldv, int kw, uint64_t seed, int ident) {
+                              int ldv, int kw, uint64_t seed, int ident, int* __restrict__ flags) {
     int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < 4) flags[e] = 0;
     if (e >= n * b) return;
     int64_t r = e / b;
     int j = (int)(e % b);

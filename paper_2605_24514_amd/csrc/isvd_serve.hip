@@ -255,6 +255,12 @@ isvd_status isvd_server_step(isvd_server* s, int32_t* launched) {
         Ticket& t = s->tickets[ti];
         if (t.state != 1 || t.queue.empty()) continue;
         if (s->cfg.max_batch && (int)batch.size() >= s->cfg.max_batch) break;
+        // a stream whose refresh still runs waits for a later tick, so the
+        // refresh overlaps the other streams' updates
+        int32_t busy = 0;
+        isvd_status brc = isvd_stream_busy(s->eng, t.id, &busy);
+        if (brc != ISVD_OK) return sfail(s, brc, "refresh of a stream failed");
+        if (busy) continue;
         Pending p = t.queue.front();
         t.queue.pop_front();
         if (!shape_ok(s, t, p.r)) {

@@ -87,7 +87,7 @@ ROT_VARIANTS = [(256, 1, True), (512, 1, True), (1024, 1, True), (1024, 2, False
 EXPORTS = ["isvd_engine_create", "isvd_engine_destroy", "isvd_stream_bytes", "isvd_init", "isvd_init_from_factors",
            "isvd_append_row", "isvd_append_col", "isvd_update_entry", "isvd_refresh", "isvd_metrics",
            "isvd_get_factors", "isvd_get_matrix", "isvd_shape", "isvd_release", "isvd_tick",
-           "isvd_profile", "isvd_profile_read", "isvd_autotune", "isvd_set_rotation_variant", "isvd_sync", "isvd_rotation_stream", "isvd_set_pipelining",
+           "isvd_profile", "isvd_profile_read", "isvd_autotune", "isvd_set_rotation_variant", "isvd_sync", "isvd_stream_busy", "isvd_rotation_stream", "isvd_set_pipelining",
            "isvd_server_create", "isvd_server_destroy", "isvd_server_clock", "isvd_server_error",
            "isvd_server_add_stream", "isvd_server_submit", "isvd_server_submit_many", "isvd_server_step", "isvd_server_drain",
            "isvd_server_poll", "isvd_server_stats", "isvd_server_stream", "isvd_last_error"]
@@ -126,6 +126,7 @@ def load_library(path=LIB_PATH):
         "isvd_autotune": (i32, [vp, vp, ctypes.POINTER(i32), dp]),
         "isvd_set_rotation_variant": (i32, [vp, i32, i32]),
         "isvd_sync": (i32, [vp, vp]),
+        "isvd_stream_busy": (i32, [vp, i64, ctypes.POINTER(i32)]),
         "isvd_set_pipelining": (i32, [vp, i32]),
         "isvd_server_create": (i32, [vp, ctypes.POINTER(CServerConfig), vp, ctypes.POINTER(vp)]),
         "isvd_server_destroy": (i32, [vp]),
@@ -396,8 +397,15 @@ class Engine:
         self._check(self._lib.isvd_set_rotation_variant(self._h, kc, variant), "isvd_set_rotation_variant")
 
     def sync(self, stream=None):
-        """Order `stream` after the U rotations still pending from pipelined ticks."""
+        """Order `stream` after the U rotations still pending from pipelined ticks
+        and the refreshes still running on the refresh lanes."""
         self._check(self._lib.isvd_sync(self._h, _stream_ptr(stream)), "isvd_sync")
+
+    def busy(self, sid):
+        """True while a refresh fired by a tick still runs for stream `sid`."""
+        out = ctypes.c_int32(0)
+        self._check(self._lib.isvd_stream_busy(self._h, sid, ctypes.byref(out)), "isvd_stream_busy")
+        return bool(out.value)
 
     def set_pipelining(self, enable):
         self._check(self._lib.isvd_set_pipelining(self._h, 1 if enable else 0), "isvd_set_pipelining")
