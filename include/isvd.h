@@ -164,9 +164,14 @@ isvd_status isvd_engine_destroy(isvd_engine* eng);
 uint64_t isvd_stream_bytes(const isvd_config* cfg);
 
 /* Algorithm 1 init: allocate the stream, copy A_0 (m0 x n0, leading dim lda,
- * in `dtype`) into its A, compute TruncatedSVD(A_0, k) with the refresh
- * routine, set N_0 = ||A_0||_F^2 and U_ref = U.  Waits for the device.
- * Errors: INVAL (cfg), BUDGET, NOMEM, DEVICE, CONVERGE. */
+ * in `dtype`) into its A, set N_0 = ||A_0||_F^2, and compute
+ * TruncatedSVD(A_0, k) with the refresh routine, U_ref = U.  The copy and
+ * the norm are ordered on hip_stream; the SVD runs on one of the engine's
+ * refresh lanes after them, and the stream is busy (isvd_stream_busy) until
+ * it is done: every later call on the stream orders itself after it.  A
+ * host A_0 is copied before the call returns.  Does not wait for the SVD.
+ * Errors: INVAL (cfg), BUDGET, NOMEM, DEVICE; a Rayleigh-Ritz SVD that does
+ * not converge is reported (CONVERGE) by the next call on the stream. */
 isvd_status isvd_init(isvd_engine* eng, const isvd_config* cfg, const void* A0, int64_t lda,
                       int32_t dtype, int32_t on_device, void* hip_stream, isvd_id* out);
 
@@ -320,7 +325,8 @@ isvd_status isvd_set_rotation_variant(isvd_engine* eng, int32_t kc, int32_t vari
  * streams whose lifetime is complete, admits waiting streams in FIFO order
  * while their footprint (isvd_stream_bytes) fits the HBM budget, and
  * launches one tick of the oldest queued request of every admitted stream
- * that is not busy with a refresh (continuous batching: requests that
+ * that is not busy with a refresh, among the requests whose arrival time has
+ * passed (continuous batching: requests that
  * arrive while ticks run on the device join the next tick; up to
  * max_inflight ticks overlap on the device, and refreshes fired by a tick
  * overlap the following ticks of the other streams).

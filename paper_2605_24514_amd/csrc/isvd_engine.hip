@@ -252,6 +252,7 @@ struct isvd_engine {
         WsBuf ws;
     };
     std::vector<RefreshLane> rlanes;
+    int next_lane = 0;               // lane of the next stream-creation SVD
     hipEvent_t ev_policies = nullptr;
     int* dsweeps = nullptr;          // device: Rayleigh-Ritz sweep count per header slot
     int* rsweeps = nullptr;          // pinned copy
@@ -1117,12 +1118,41 @@ struct Exact {
     double fro2 = 0, e_inc = 0, e_opt = 0, gap = 0, ratio = 0, ortho_u = 0, ortho_v = 0;
 };
 
+// out = sum of P[0:n]: thread t adds a contiguous range in order, the ranges'
+// sums are added in a fixed tree order (one block of kThreads)
+__global__ void __launch_bounds__(kThreads) k_sum_block(const double* __restrict__ P, int64_t n, double* out) {
+    __shared__ double red[kThreads];
+    const int64_t per = (n + kThreads - 1) / kThreads;
+    const int64_t a = threadIdx.x * per, b = min(n, a + per);
+    double s0 = 0.0, s1 = 0.0;
+    int64_t i = a;
+    for (; i + 1 < b; i += 2) {
+        s0 += P[i];
+        s1 += P[i + 1];
+    }
+    if (i < b) s0 += P[i];
+    red[threadIdx.x] = s0 + s1;
+    __syncthreads();
+    for (int o = kThreads / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0];
+}
+
+__global__ void k_fill_scalars(double* d, int nd, double v, int* iv, int ni) {
+    if ((int)threadIdx.x < nd) d[threadIdx.x] = v;
+    if ((int)threadIdx.x < ni) iv[threadIdx.x] = 0;
+}
+
 // ||A||_F^2 and E_inc^2 (one residual pass over A), E_opt^2 = ||A||^2 minus the
 // sum of the leading k squared Ritz values of a refresh computed into the
 // workspace (left there for a commit; exact when its block spans all columns),
 // and max |Q^T Q - I| of U and V.
+// Without `ortho` (the error policy's check) the two orthogonality norms are
+// left out (reported as NaN).
 template <typename T>
-isvd_status exact_metrics_t(isvd_engine* e, Stream& s, hipStream_t st, Exact* out, RefreshPlan* plan) {
+isvd_status exact_metrics_t(isvd_engine* e, Stream& s, hipStream_t st, Exact* out, RefreshPlan* plan, bool ortho) {
     ST_TRY(refresh_compute<T>(e, s, false, st, plan));
     DevHeader h{};
     HIP_TRY(hipMemcpyAsync(&h, s.hdr, sizeof(h), hipMemcpyDeviceToHost, st));
@@ -1147,18 +1177,22 @@ isvd_status exact_metrics_t(isvd_engine* e, Stream& s, hipStream_t st, Exact* ou
     const T* V = (const T*)s.V[h.cur];
     const int64_t lda = lda_of(s.cfg);
     k_fro2_partial<T><<<(int)nfro, kThreads, 0, st>>>(A, lda, m, n, fro_p);
-    k_sum_parts<double><<<1, 1, 0, st>>>(fro_p, (int)nfro, 1, 1, scal + 0);
+    k_sum_block<<<1, kThreads, 0, st>>>(fro_p, nfro, scal + 0);
     dim3 rg((unsigned)cdiv(m, 64), (unsigned)cdiv(n, 64));
     k_resid2_partial<T><<<rg, kThreads, 0, st>>>(A, lda, U, V, ld, s.S, m, n, k, res_p);
-    k_sum_parts<double><<<1, 1, 0, st>>>(res_p, (int)nres, 1, 1, scal + 1);
-    k_gram_mfma<T, true><<<(int)ngu, kThreads, 0, st>>>(U, ld, m, k, gram_rpb(m), gu_p);
-    k_gram_sum<<<(int)cdiv(gsz, 32), 256, 0, st>>>(gu_p, (int)ngu, k, GU);
-    k_gram_mfma<T, true><<<(int)ngv, kThreads, 0, st>>>(V, ld, n, k, gram_rpb(n), gv_p);
-    k_gram_sum<<<(int)cdiv(gsz, 32), 256, 0, st>>>(gv_p, (int)ngv, k, GV);
-    const int nt = JacobiShape<kMaxBlock + 1>::NT;
+    k_sum_block<<<1, kThreads, 0, st>>>(res_p, nres, scal + 1);
     int* sw = (int*)(scal + 6);
-    k_sym_norm2<<<1, nt, sym_norm2_lds(k), st>>>(GU, k, scal + 2, sw);
-    k_sym_norm2<<<1, nt, sym_norm2_lds(k), st>>>(GV, k, scal + 3, sw + 1);
+    if (ortho) {
+        k_gram_mfma<T, true><<<(int)ngu, kThreads, 0, st>>>(U, ld, m, k, gram_rpb(m), gu_p);
+        k_gram_sum<<<(int)cdiv(gsz, 32), 256, 0, st>>>(gu_p, (int)ngu, k, GU);
+        k_gram_mfma<T, true><<<(int)ngv, kThreads, 0, st>>>(V, ld, n, k, gram_rpb(n), gv_p);
+        k_gram_sum<<<(int)cdiv(gsz, 32), 256, 0, st>>>(gv_p, (int)ngv, k, GV);
+        const int nt = JacobiShape<kMaxBlock + 1>::NT;
+        k_sym_norm2<<<1, nt, sym_norm2_lds(k), st>>>(GU, k, scal + 2, sw);
+        k_sym_norm2<<<1, nt, sym_norm2_lds(k), st>>>(GV, k, scal + 3, sw + 1);
+    } else {
+        k_fill_scalars<<<1, 64, 0, st>>>(scal + 2, 2, std::nan(""), sw, 2);
+    }
     HIP_TRY(hipGetLastError());
     std::vector<double> hs(7), sr(plan->k);
     HIP_TRY(hipMemcpyAsync(hs.data(), scal, sizeof(double) * 7, hipMemcpyDeviceToHost, st));
@@ -1179,8 +1213,10 @@ isvd_status exact_metrics_t(isvd_engine* e, Stream& s, hipStream_t st, Exact* ou
     return ISVD_OK;
 }
 
-isvd_status exact_metrics(isvd_engine* e, Stream& s, hipStream_t st, Exact* out, RefreshPlan* plan) {
-    return s.esz == 8 ? exact_metrics_t<double>(e, s, st, out, plan) : exact_metrics_t<float>(e, s, st, out, plan);
+isvd_status exact_metrics(isvd_engine* e, Stream& s, hipStream_t st, Exact* out, RefreshPlan* plan,
+                          bool ortho = true) {
+    return s.esz == 8 ? exact_metrics_t<double>(e, s, st, out, plan, ortho)
+                      : exact_metrics_t<float>(e, s, st, out, plan, ortho);
 }
 
 // ------------------------------------------------------------------ policies
@@ -1223,7 +1259,7 @@ isvd_status after_update(isvd_engine* e, Stream& s, hipStream_t st, const DevHea
         if (p.check_every <= 0 || s.t % p.check_every != 0 || s.t - s.t_last < p.t_min) return ISVD_OK;
         Exact ex;
         RefreshPlan plan;
-        ST_TRY(exact_metrics(e, s, st, &ex, &plan));
+        ST_TRY(exact_metrics(e, s, st, &ex, &plan, false));
         s.last_ratio = ex.ratio;
         if (ex.ratio > p.gamma) return do_refresh(e, s, false, true, st, &plan);
         return ISVD_OK;
@@ -1275,19 +1311,42 @@ isvd_status after_update(isvd_engine* e, Stream& s, hipStream_t st, const DevHea
 // caller's stream holds so far (the tick and its policy actions); the caller's
 // stream then waits for the lanes.  The streams of `list` are distinct.
 constexpr int kRefreshLanes = 8;
+isvd_status ensure_refresh_lanes(isvd_engine* e) {
+    if (!e->rlanes.empty()) return ISVD_OK;
+    e->rlanes.resize(kRefreshLanes);
+    for (auto& l : e->rlanes) {
+        HIP_TRY(hipStreamCreateWithFlags(&l.st, hipStreamNonBlocking));
+        HIP_TRY(hipEventCreateWithFlags(&l.ev, hipEventDisableTiming));
+        l.ws.defer_free = true;
+    }
+    HIP_TRY(hipEventCreateWithFlags(&e->ev_policies, hipEventDisableTiming));
+    HIP_TRY(hipMalloc((void**)&e->dsweeps, sizeof(int) * kMaxLiveStreams));
+    HIP_TRY(hipHostMalloc((void**)&e->rsweeps, sizeof(int) * kMaxLiveStreams, hipHostMallocDefault));
+    return ISVD_OK;
+}
+
+// The initial TruncatedSVD of a new stream on the next refresh lane, after
+// everything `st` holds (the copy of A_0 and its norm); the stream is busy
+// until it is done.
+isvd_status init_on_lane(isvd_engine* e, Stream& s, hipStream_t st) {
+    ST_TRY(ensure_refresh_lanes(e));
+    auto& lane = e->rlanes[e->next_lane];
+    e->next_lane = (e->next_lane + 1) % kRefreshLanes;
+    if (!lane.ws.retired.empty() && hipStreamQuery(lane.st) == hipSuccess) free_retired(lane.ws);
+    HIP_TRY(hipEventRecord(e->ev_policies, st));
+    HIP_TRY(hipStreamWaitEvent(lane.st, e->ev_policies, 0));
+    ST_TRY(do_refresh(e, s, true, true, lane.st, nullptr, nullptr, e->dsweeps + s.slot, &lane.ws));
+    HIP_TRY(hipMemcpyAsync(e->rsweeps + s.slot, e->dsweeps + s.slot, sizeof(int), hipMemcpyDeviceToHost, lane.st));
+    HIP_TRY(hipEventRecord(s.ev_ready, lane.st));
+    s.refreshing = true;
+    HIP_TRY(hipEventRecord(lane.ev, lane.st));
+    lane.pending = true;
+    return ISVD_OK;
+}
+
 isvd_status refresh_batch(isvd_engine* e, const std::vector<Stream*>& list, hipStream_t st) {
     const int cnt = (int)list.size();
-    if (e->rlanes.empty()) {
-        e->rlanes.resize(kRefreshLanes);
-        for (auto& l : e->rlanes) {
-            HIP_TRY(hipStreamCreateWithFlags(&l.st, hipStreamNonBlocking));
-            HIP_TRY(hipEventCreateWithFlags(&l.ev, hipEventDisableTiming));
-            l.ws.defer_free = true;
-        }
-        HIP_TRY(hipEventCreateWithFlags(&e->ev_policies, hipEventDisableTiming));
-        HIP_TRY(hipMalloc((void**)&e->dsweeps, sizeof(int) * kMaxLiveStreams));
-        HIP_TRY(hipHostMalloc((void**)&e->rsweeps, sizeof(int) * kMaxLiveStreams, hipHostMallocDefault));
-    }
+    ST_TRY(ensure_refresh_lanes(e));
     // buffers retired by workspace growth go once their lane has drained
     for (auto& l : e->rlanes)
         if (!l.ws.retired.empty() && hipStreamQuery(l.st) == hipSuccess) free_retired(l.ws);
@@ -1886,9 +1945,9 @@ static isvd_status init_common(isvd_engine* e, const isvd_config* cfg, const voi
         k_fro2_partial<double><<<nchunk, kThreads, 0, st>>>((const double*)s->A, ldA, m0, n0, (double*)e->ws.p);
     else
         k_fro2_partial<float><<<nchunk, kThreads, 0, st>>>((const float*)s->A, ldA, m0, n0, (double*)e->ws.p);
-    k_sum_parts<double><<<1, 1, 0, st>>>((const double*)e->ws.p, nchunk, 1, 1, &s->hdr->N);
+    k_sum_block<<<1, kThreads, 0, st>>>((const double*)e->ws.p, nchunk, &s->hdr->N);
     if (hipGetLastError() != hipSuccess) return bail(fail(ISVD_E_DEVICE, "norm launch"));
-    rc = given ? install_factors(*s, *given, st) : do_refresh(e, *s, true, true, st);
+    rc = given ? install_factors(*s, *given, st) : init_on_lane(e, *s, st);
     if (tmpdev) {
         (void)hipStreamSynchronize(st);
         (void)hipFree(tmpdev);

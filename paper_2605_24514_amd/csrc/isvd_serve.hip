@@ -254,6 +254,8 @@ isvd_status isvd_server_step(isvd_server* s, int32_t* launched) {
         const size_t ti = (s->rr + q) % nt;
         Ticket& t = s->tickets[ti];
         if (t.state != 1 || t.queue.empty()) continue;
+        // a request stamped with a later arrival time has not arrived yet
+        if (t.queue.front().arrival > tnow) continue;
         if (s->cfg.max_batch && (int)batch.size() >= s->cfg.max_batch) break;
         // a stream whose refresh still runs waits for a later tick, so the
         // refresh overlaps the other streams' updates
