@@ -242,7 +242,9 @@ isvd_status isvd_release(isvd_engine* eng, isvd_id id);
  * state (metrics, factors, matrix, refresh, single updates, a tick that
  * reads U) first orders its stream after them, and isvd_sync does so
  * explicitly.  Otherwise the tick joins them into hip_stream before
- * returning.  Row payloads are not read by U rotations.
+ * returning.  Every read of a payload is ordered before hip_stream's next
+ * operation (row payloads are not read by U rotations), so a payload may be
+ * freed or overwritten in hip_stream's order as soon as the call returns.
  * Refreshes: the refreshes that a tick's policies fire (periodic, angle,
  * adaptive) run concurrently on the engine's refresh lanes (streams of
  * default priority, one host thread and one workspace per lane) and are not

@@ -512,7 +512,9 @@ isvd_status launch_recorded(isvd_engine* e, const Group& g, const char* dev, int
 // core, then V's rotation; on the rotation lane, after the group's core,
 // U's rotation (lane b's groups first: their cores finish earlier).
 // pipelined: the caller's stream is not made to wait for the U rotations (a
-// later join does); otherwise it is joined at the end.  The rotation lane
+// later join does); otherwise it is joined at the end.  Lane b is always
+// joined into the caller's stream at the end of the tick: its launches read
+// the payloads, and no U rotation of a pipelined tick does.  The rotation lane
 // never runs more than one tick behind: a tick's first launch waits for the
 // lane's end of the tick before last, whose scratch copy this tick's cores
 // overwrite.
@@ -592,6 +594,10 @@ isvd_status run_groups(isvd_engine* e, std::vector<Group>& groups, hipStream_t s
     if (use_b) {
         HIP_TRY(hipEventRecord(e->ev_b_end, e->lane_b));
         HIP_TRY(hipStreamWaitEvent(e->rot_lane, e->ev_b_end, 0));
+        // lane b reads the caller's payloads (projections, V rotations): the
+        // caller's stream passes the tick only after them, so a payload freed
+        // in that stream's order is never overwritten while still being read
+        HIP_TRY(hipStreamWaitEvent(st, e->ev_b_end, 0));
     }
     HIP_TRY(hipEventRecord(slot->ev, e->rot_lane));
     slot->used = true;
