@@ -5,6 +5,7 @@
 #pragma once
 #include "isvd_common.h"
 #include "isvd_jacobi.h"
+#include "isvd_secular.h"
 
 namespace isvd {
 
@@ -160,8 +161,11 @@ __global__ void __launch_bounds__(kThreads) k_proj(const Req* __restrict__ reqs,
 // V_K = K^T U_K diag(1/sigma), evaluated from K's sparsity in O(N^2); its
 // loss of orthogonality, about N eps64 sigma_1 / sigma_j, stays far below
 // FP32 rounding for every kept triplet.
-// One block per request; dynamic LDS = ((1 + WITH_J) N ldw + (WITH_J ? 6 : 8) N)
-// doubles with ldw the bucket's padded column stride, N <= kMaxCore.
+// FP32 storage, appends, buckets up to 64: the secular-equation SVD of the
+// arrow-shaped K (isvd_secular.h) replaces the Jacobi sweeps whenever every
+// kept triplet has sigma >= 1e-4 sigma_1; it leaves V_K in J and W = K V_K.
+// One block per request; dynamic LDS = (matrices N ldw + small arrays) doubles
+// with ldw the bucket's padded column stride, N <= kMaxCore (core_lds_doubles).
 template <int KC>
 struct CoreShape {
     static constexpr int NMAX = (KC < kMaxCore - 1 ? KC : kMaxCore - 1) + 1;
@@ -170,19 +174,27 @@ struct CoreShape {
     typedef JacobiShape<NMAX, (KC == 32 || KC == 64) ? 8 : 4> J;
 };
 
+// the FP32 cores of buckets up to 64 can take the secular path
+template <int KC, bool WITH_J>
+__host__ __device__ constexpr bool core_secular() { return !WITH_J && KC <= 64; }
+
 // dynamic LDS (doubles) of a core block of bucket KC
 template <int KC, bool WITH_J>
 __host__ __device__ constexpr size_t core_lds_doubles() {
-    return (size_t)(WITH_J ? 2 : 1) * CoreShape<KC>::NMAX * CoreShape<KC>::J::LDW +
-           (size_t)(WITH_J ? 6 : 8) * CoreShape<KC>::NMAX;
+    constexpr bool SEC = core_secular<KC, WITH_J>();
+    return (size_t)((WITH_J || SEC) ? 2 : 1) * CoreShape<KC>::NMAX * CoreShape<KC>::J::LDW +
+           (size_t)(WITH_J ? 6 : 8) * CoreShape<KC>::NMAX +
+           (size_t)(SEC ? secular_scratch_doubles(CoreShape<KC>::NMAX) : 0);
 }
 
 template <typename T, int KC>
 __global__ void __launch_bounds__(CoreShape<KC>::J::NT) k_core(const Req* __restrict__ reqs) {
     constexpr bool WITH_J = sizeof(T) == 8;
+    constexpr bool SEC = core_secular<KC, WITH_J>();
     extern __shared__ double smem[];
     __shared__ double s_sc[8];
     __shared__ int s_i[4];
+    __shared__ int s_sec[4];
     const Req& rq = reqs[blockIdx.x];
     DevHeader* hdr = rq.hdr;
     ReqScratch* rs = rq.rs;
@@ -192,8 +204,8 @@ __global__ void __launch_bounds__(CoreShape<KC>::J::NT) k_core(const Req* __rest
     const int tid = threadIdx.x, nt = blockDim.x;
     const int ldw = CoreShape<KC>::J::LDW;
     double* W = smem;
-    double* J = W + (size_t)N * ldw;                 // used only WITH_J
-    double* sS = J + (WITH_J ? (size_t)N * ldw : 0); // Sigma (k)
+    double* J = W + (size_t)N * ldw;                 // V_K: WITH_J, or the secular path
+    double* sS = J + ((WITH_J || SEC) ? (size_t)N * ldw : 0); // Sigma (k)
     double* sp = sS + N;                           // p (row / column) or s_v (rank-1)
     double* sig = sp + N;
     double* sgn = sig + N;
@@ -201,6 +213,7 @@ __global__ void __launch_bounds__(CoreShape<KC>::J::NT) k_core(const Req* __rest
     int* perm = (int*)(tmp + N);
     double* su = tmp + 2 * N;                      // s_u (rank-1, no J)
     double* dcol = su + N;                         // s_u . W[:, c] (rank-1, no J)
+    double* xsec = dcol + N;                       // secular scratch
 
     // projection sums of an append: the k_proj partials added in block order
     const size_t total = core_lds_doubles<KC, WITH_J>();
@@ -288,9 +301,15 @@ __global__ void __launch_bounds__(CoreShape<KC>::J::NT) k_core(const Req* __rest
         if constexpr (WITH_J) J[e] = (row == col) ? 1.0 : 0.0;
     }
     __syncthreads();
+    bool use_sec = false;
+    if constexpr (SEC) {
+        if (kind != kEntry) use_sec = secular_append_core(sS, sp, rho, k, rq.k_keep < N ? rq.k_keep : N, W, J, ldw,
+                                                          xsec, s_sec);
+    }
     // FP32 storage rounds U_K, V_K to 6e-8: columns orthogonal to 1e-10 suffice
-    const int sweeps =
-        jacobi_block<CoreShape<KC>::NMAX, WITH_J, CoreShape<KC>::J::TPP>(W, J, N, ldw, 40, WITH_J ? 0.0 : 1e-10);
+    const int sweeps = use_sec ? 0
+                               : jacobi_block<CoreShape<KC>::NMAX, WITH_J, CoreShape<KC>::J::TPP>(
+                                     W, J, N, ldw, 40, WITH_J ? 0.0 : 1e-10);
     jacobi_sort(W, N, ldw, sig, perm, tmp);
     if constexpr (!WITH_J) {
         if (kind == kEntry) {
@@ -307,6 +326,7 @@ __global__ void __launch_bounds__(CoreShape<KC>::J::NT) k_core(const Req* __rest
         if constexpr (WITH_J) {
             return J[(size_t)c * ldw + e];
         } else {
+            if (use_sec) return J[(size_t)c * ldw + e];
             const double* w = W + (size_t)c * ldw;
             const double s2 = tmp[c] * tmp[c];
             if (!(s2 > 0.0)) return 0.0;
