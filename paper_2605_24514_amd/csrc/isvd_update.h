@@ -303,7 +303,7 @@ __global__ void __launch_bounds__(CoreShape<KC>::J::NT) k_core(const Req* __rest
     __syncthreads();
     bool use_sec = false;
     if constexpr (SEC) {
-        if (kind != kEntry) use_sec = secular_append_core(sS, sp, rho, k, rq.k_keep < N ? rq.k_keep : N, W, J, ldw,
+        if (kind != kEntry) use_sec = secular_append_core<CoreShape<KC>::NMAX, CoreShape<KC>::J::NT>(sS, sp, rho, k, rq.k_keep < N ? rq.k_keep : N, W, J, ldw,
                                                           xsec, s_sec);
     }
     // FP32 storage rounds U_K, V_K to 6e-8: columns orthogonal to 1e-10 suffice
