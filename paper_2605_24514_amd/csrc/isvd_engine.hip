@@ -169,10 +169,11 @@ Layout make_layout(const isvd_config& c, int esz, int kc, int64_t* ntiles_max) {
 }
 
 // ------------------------------------------------------- launch staging ring
+// One upload buffer of the request ring: a fixed-stride piece of the ring's
+// pinned host arena and of its device arena.
 struct Slot {
     char* host = nullptr;
     char* dev = nullptr;
-    size_t cap = 0;
     hipEvent_t ev = nullptr;
     bool used = false;
 };
@@ -237,6 +238,9 @@ struct isvd_engine {
     std::vector<Stream*> streams;
     std::vector<Slot> ring;
     size_t ring_next = 0;
+    char* ring_host = nullptr;         // pinned, ring.size() x ring_stride
+    char* ring_dev = nullptr;          // device, ring.size() x ring_stride
+    size_t ring_stride = 0;
     // refresh workspace (sized for the largest refresh so far)
     WsBuf ws;
     // exact-metrics workspace
@@ -298,19 +302,52 @@ size_t core_lds_bytes(int N, int ldw, bool with_j) {
 size_t sym_norm2_lds(int k) { return sizeof(double) * (size_t)((k + 1) * JacobiShape<kMaxBlock + 1>::LDW + k); }
 
 // Acquire a staging slot of at least `bytes`; waits for its previous use.
+// Upload of a slot: the GPU reads the pinned host arena directly.  A kernel
+// on the stream orders itself after that stream's waits on the device,
+// where an asynchronous copy behind a cross-stream wait was seen to hold
+// the calling thread until the wait resolved.
+__global__ void __launch_bounds__(256) k_upload(const uint4* __restrict__ src, uint4* __restrict__ dst, size_t n16) {
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n16; i += (size_t)gridDim.x * 256) dst[i] = src[i];
+}
+
+// bytes: a multiple of 16 (every slot layout ends on a 64-byte boundary)
+isvd_status upload_slot(const Slot* slot, size_t bytes, hipStream_t st) {
+    const size_t n16 = align_up(bytes, 16) / 16;
+    if (n16 == 0) return ISVD_OK;
+    const int blocks = (int)std::min<size_t>(cdiv(n16, 256), 64);
+    k_upload<<<blocks, 256, 0, st>>>(reinterpret_cast<const uint4*>(slot->host), reinterpret_cast<uint4*>(slot->dev),
+                                      n16);
+    HIP_TRY(hipGetLastError());
+    return ISVD_OK;
+}
+
 isvd_status acquire_slot(isvd_engine* e, size_t bytes, Slot** out) {
+    if (bytes > e->ring_stride) {
+        // every slot grows at once (geometrically, so a handful of times per
+        // engine): the slots still in flight drain first, then both arenas
+        // are replaced; a tick never allocates otherwise
+        for (Slot& s : e->ring)
+            if (s.used) {
+                HIP_TRY(hipEventSynchronize(s.ev));
+                s.used = false;
+            }
+        const size_t stride = align_up(std::max({2 * bytes, 2 * e->ring_stride, (size_t)65536}), 4096);
+        if (e->ring_host) HIP_TRY(hipHostFree(e->ring_host));
+        if (e->ring_dev) HIP_TRY(hipFree(e->ring_dev));
+        e->ring_host = e->ring_dev = nullptr;
+        e->ring_stride = 0;
+        for (Slot& s : e->ring) s.host = s.dev = nullptr;
+        HIP_TRY(hipHostMalloc((void**)&e->ring_host, stride * e->ring.size(), hipHostMallocDefault));
+        HIP_TRY(hipMalloc((void**)&e->ring_dev, stride * e->ring.size()));
+        e->ring_stride = stride;
+        for (size_t i = 0; i < e->ring.size(); ++i) {
+            e->ring[i].host = e->ring_host + i * stride;
+            e->ring[i].dev = e->ring_dev + i * stride;
+        }
+    }
     Slot& s = e->ring[e->ring_next];
     e->ring_next = (e->ring_next + 1) % e->ring.size();
     if (s.used) HIP_TRY(hipEventSynchronize(s.ev));
-    if (s.cap < bytes) {
-        if (s.host) HIP_TRY(hipHostFree(s.host));
-        if (s.dev) HIP_TRY(hipFree(s.dev));
-        // grow geometrically: ticks of varying size settle after a few allocations
-        size_t cap = align_up(std::max({bytes, 2 * s.cap, (size_t)65536}), 4096);
-        HIP_TRY(hipHostMalloc((void**)&s.host, cap, hipHostMallocDefault));
-        HIP_TRY(hipMalloc((void**)&s.dev, cap));
-        s.cap = cap;
-    }
     *out = &s;
     return ISVD_OK;
 }
@@ -562,7 +599,7 @@ isvd_status run_groups(isvd_engine* e, std::vector<Group>& groups, hipStream_t s
         memcpy(slot->host + g.off_prv, g.pre_rotV.data(), sizeof(int) * (na + 1));
     }
     if (e->ticks >= 2) HIP_TRY(hipStreamWaitEvent(st, e->ev_tick_end[e->ticks & 1], 0));
-    HIP_TRY(hipMemcpyAsync(slot->dev, slot->host, off, hipMemcpyHostToDevice, st));
+    ST_TRY(upload_slot(slot, off, st));
     while (e->ev_core.size() < groups.size()) {
         hipEvent_t ev;
         HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
@@ -673,7 +710,7 @@ isvd_status run_tracks(isvd_engine* e, const std::vector<Track>& tracks, const s
         memcpy(slot->host + o_all, all.data(), sizeof(Track) * all.size());
         if (!col.empty()) memcpy(slot->host + o_col, col.data(), sizeof(Track) * col.size());
         memcpy(slot->host + o_pre, pre.data(), sizeof(int) * pre.size());
-        HIP_TRY(hipMemcpyAsync(slot->dev, slot->host, off, hipMemcpyHostToDevice, st));
+        ST_TRY(upload_slot(slot, off, st));
         if (pass == 1)
             ST_TRY(launch_tracks<double>(slot->dev, o_all, o_col, o_pre, (int)all.size(), (int)col.size(),
                                          pre.back(), st));
@@ -1577,11 +1614,10 @@ isvd_status isvd_engine_destroy(isvd_engine* e) {
         free_stream(e, s);
         delete s;
     }
-    for (Slot& s : e->ring) {
-        if (s.host) (void)hipHostFree(s.host);
-        if (s.dev) (void)hipFree(s.dev);
+    for (Slot& s : e->ring)
         if (s.ev) (void)hipEventDestroy(s.ev);
-    }
+    if (e->ring_host) (void)hipHostFree(e->ring_host);
+    if (e->ring_dev) (void)hipFree(e->ring_dev);
     if (e->ws.p) (void)hipFree(e->ws.p);
     free_retired(e->ws);
     if (e->mws) (void)hipFree(e->mws);
