@@ -217,6 +217,11 @@ struct isvd_engine {
     // that no caller stream waits for yet; every call that reads or replaces
     // U first orders the caller's stream after it (join).
     hipStream_t rot_lane = nullptr;
+    // second rotation lane: the U rotations of the buckets below 64, so that
+    // they overlap the widest bucket's; the rotation lane joins it at the
+    // end of every tick, so waiting for the rotation lane covers both
+    hipStream_t rot_lane_b = nullptr;
+    hipEvent_t ev_rot_b = nullptr;     // rotation lane b's part of a tick is done
     // second update lane: the rank buckets up to 32 run their projections,
     // cores and V rotations there, concurrently with the wider buckets on the
     // caller's stream (the assignment depends on the bucket only, so a
@@ -505,6 +510,8 @@ isvd_status ensure_lanes(isvd_engine* e) {
     if (e->rot_lane) return ISVD_OK;
     HIP_TRY(hipStreamCreateWithFlags(&e->rot_lane, hipStreamNonBlocking));
     HIP_TRY(hipStreamCreateWithFlags(&e->lane_b, hipStreamNonBlocking));
+    HIP_TRY(hipStreamCreateWithFlags(&e->rot_lane_b, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&e->ev_rot_b, hipEventDisableTiming));
     HIP_TRY(hipEventCreateWithFlags(&e->ev_fork, hipEventDisableTiming));
     HIP_TRY(hipEventCreateWithFlags(&e->ev_b_end, hipEventDisableTiming));
     HIP_TRY(hipEventCreateWithFlags(&e->ev_main, hipEventDisableTiming));
@@ -546,8 +553,9 @@ isvd_status launch_recorded(isvd_engine* e, const Group& g, const char* dev, int
 // Lay out groups in a slot, upload, and launch one tick (or one immediate
 // update).  Per group, on its update lane (the caller's stream for buckets
 // of 64 and wider, lane b for the others): the two projection passes, the
-// core, then V's rotation; on the rotation lane, after the group's core,
-// U's rotation (lane b's groups first: their cores finish earlier).
+// core, then V's rotation; after the group's core, U's rotation on a
+// rotation lane (rotation lane b for the buckets below 64, the rotation lane
+// for the others, so the two overlap).
 // pipelined: the caller's stream is not made to wait for the U rotations (a
 // later join does); otherwise it is joined at the end.  Lane b is always
 // joined into the caller's stream at the end of the tick: its launches read
@@ -618,17 +626,18 @@ isvd_status run_groups(isvd_engine* e, std::vector<Group>& groups, hipStream_t s
         HIP_TRY(hipEventRecord(e->ev_core[gi], ln));
         ST_TRY(launch_recorded(e, g, slot->dev, 4, ln));
     }
-    for (int pass = 0; pass < 2; ++pass)
-        for (size_t gi = 0; gi < groups.size(); ++gi) {
-            const Group& g = groups[gi];
-            if ((g.kc < 64) != (pass == 0)) continue;
-            HIP_TRY(hipStreamWaitEvent(e->rot_lane, e->ev_core[gi], 0));
-            ST_TRY(launch_recorded(e, g, slot->dev, 3, e->rot_lane));
-        }
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+        const Group& g = groups[gi];
+        hipStream_t rl = g.kc >= 64 ? e->rot_lane : e->rot_lane_b;
+        HIP_TRY(hipStreamWaitEvent(rl, e->ev_core[gi], 0));
+        ST_TRY(launch_recorded(e, g, slot->dev, 3, rl));
+    }
     // the tick ends on the rotation lane once every lane is through it
     HIP_TRY(hipEventRecord(e->ev_main, st));
     HIP_TRY(hipStreamWaitEvent(e->rot_lane, e->ev_main, 0));
     if (use_b) {
+        HIP_TRY(hipEventRecord(e->ev_rot_b, e->rot_lane_b));
+        HIP_TRY(hipStreamWaitEvent(e->rot_lane, e->ev_rot_b, 0));
         HIP_TRY(hipEventRecord(e->ev_b_end, e->lane_b));
         HIP_TRY(hipStreamWaitEvent(e->rot_lane, e->ev_b_end, 0));
         // lane b reads the caller's payloads (projections, V rotations): the
@@ -1642,6 +1651,8 @@ isvd_status isvd_engine_destroy(isvd_engine* e) {
     for (hipEvent_t ev : e->ev_tick_end)
         if (ev) (void)hipEventDestroy(ev);
     if (e->rot_lane) (void)hipStreamDestroy(e->rot_lane);
+    if (e->ev_rot_b) (void)hipEventDestroy(e->ev_rot_b);
+    if (e->rot_lane_b) (void)hipStreamDestroy(e->rot_lane_b);
     delete e;
     return ISVD_OK;
 }
