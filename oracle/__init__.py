@@ -11,6 +11,8 @@ Contents, each following the paper step by step in FP64:
 * ``metrics``  -- N_t recurrences, EVR, E_inc / E_opt / gap / ratio, principal angles
 * ``policies`` -- periodic, error-threshold, angle-threshold, adaptive rank
 * ``engine``   -- the engine loop of Algorithm 1 with policy evaluation
+* ``finance``  -- causal de-meaning, low-rank covariances, portfolio volatility and
+                  the covariance / risk errors of the finance study (Section 5)
 
 Pins (tests/test_oracle_*.py): LAPACK's SVD via numpy on random, graded,
 rank-deficient inputs and the 2x2 closed form; Eckart-Young; untruncated
