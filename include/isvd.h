@@ -13,6 +13,9 @@
  *                      P_U (A_hat + delta e_i e_j^T) P_V                   (Sec. 2.3, eq. rank1-projection)
  *   isvd_refresh       (U, Sigma, V) = TruncatedSVD(A_t, k)                 (Sec. 2.4.1)
  *   isvd_metrics       N_t, EVR, errors, angles, timings                  (Sec. 2.4.2, 2.5)
+ *   isvd_causal_center expanding-mean centering of return rows          (Sec. 5.1)
+ *   isvd_covariance    low-rank covariance V diag(sigma^2) V^T / (t - 1)   (Sec. 5.3, eq. low-rank-covariances)
+ *   isvd_risk          portfolio volatility, risk and covariance errors   (Sec. 5.3, eqs. cov-error, portfolio-vol, risk-error)
  *   isvd_tick          one batched step: many streams' updates in one launch sequence
  *
  * Every update truncates back to the stream's rank and then evaluates the
@@ -213,6 +216,51 @@ isvd_status isvd_refresh(isvd_engine* eng, isvd_id id, int32_t store_reference, 
  * result as the refresh when it fires. */
 isvd_status isvd_metrics(isvd_engine* eng, isvd_id id, int32_t compute_exact, void* hip_stream,
                          isvd_metrics_t* out);
+
+/* ---- Factor readout of a returns stream (the paper's finance study, Sec. 5) ----
+ *
+ * Causal de-meaning (Sec. 5.1): for each column j in turn over the rows,
+ * mu_t = mu_{t-1} + (r_t - mu_{t-1}) / t and R_t = r_t - mu_t, so the first
+ * centred row is zero.  r: `rows` x n device rows (leading dimension n, dtype
+ * ISVD_DTYPE_F32 or ISVD_DTYPE_F64); out: device rows of the same shape and
+ * dtype receiving R_{t0+1} .. R_{t0+rows} (may be r itself); mu: device FP64
+ * n-vector holding mu_{t0} on entry (not read when t0 = 0) and
+ * mu_{t0+rows} on exit.  All arithmetic in FP64, one thread per column,
+ * rows in order, so the result does not depend on how the rows are split
+ * across calls.  Needs no engine; ordered on hip_stream.
+ * Errors: INVAL (null pointers, rows < 1, n < 1, t0 < 0, dtype), DEVICE. */
+isvd_status isvd_causal_center(const void* r, void* out, int64_t rows, int64_t n, int32_t dtype, double* mu,
+                               int64_t t0, void* hip_stream);
+
+/* Low-rank covariance of the stream's factors (eq. low-rank-covariances,
+ * the incremental one): cov = V diag(sigma_1^2 .. sigma_k^2) V^T / (m_t - 1),
+ * n_t x n_t, FP64, row-major with leading dimension ldc >= n_t, written to the
+ * device buffer cov (caller-owned).  Asynchronous: ordered on hip_stream
+ * after the stream's pending work (a refresh on a lane, pending U rotations);
+ * the kernel takes the rank from the device.  Errors: STATE (unknown id),
+ * INVAL (null cov, ldc < n_t, m_t < 2), DEVICE. */
+isvd_status isvd_covariance(isvd_engine* eng, isvd_id id, double* cov, int64_t ldc, void* hip_stream);
+
+typedef struct {
+    double vol_inc;   /* sqrt(w^T Sigma_inc,k w) from the stream's factors (eq. portfolio-vol) */
+    double vol_full;  /* the same from TruncatedSVD(A_t, k); NaN unless exact */
+    double err_risk;  /* |vol_inc - vol_full| / vol_full (eq. risk-error); NaN unless exact */
+    double err_cov;   /* ||Sigma_inc,k - Sigma_full,k||_F / ||Sigma_full,k||_F (eq. cov-error); NaN unless exact */
+} isvd_risk_t;
+
+/* Portfolio volatility of weights w (host FP64, n = n_t entries) under the
+ * stream's low-rank covariance.  exact != 0 also computes TruncatedSVD(A_t, k)
+ * by the refresh's subspace iteration (exact when the block spans all
+ * columns; nothing of the stream changes) and the two errors against it.
+ * err_cov comes from k x k products: with D = diag(sigma^2) / (m_t - 1),
+ * ||V1 D1 V1^T - V2 D2 V2^T||_F^2 = sum_ij d1_i d1_j (V1^T V1)_ij^2
+ * + sum_ij d2_i d2_j (V2^T V2)_ij^2 - 2 sum_ij d1_i d2_j (V1^T V2)_ij^2, in FP64;
+ * the three terms cancel down to err_cov^2, which leaves err_cov exact to
+ * about sqrt(k eps64) absolute (1e-7 at k = 64; the paper's errors range from
+ * 5e-4 up).  Waits for the device.
+ * Errors: STATE, SHAPE (n != n_t), INVAL (null w or out, m_t < 2), CONVERGE, DEVICE. */
+isvd_status isvd_risk(isvd_engine* eng, isvd_id id, const double* w, int64_t n, int32_t exact, isvd_risk_t* out,
+                      void* hip_stream);
 
 /* FP64 host copies of the factors: U (m_t x k, ldu), S (k), V (n_t x k, ldv).
  * Any pointer may be NULL to skip it.  Waits for the device. */

@@ -30,6 +30,7 @@
 #include "isvd_update.h"
 #include "isvd_refresh.h"
 #include "isvd_track.h"
+#include "isvd_finance.h"
 
 using namespace isvd;
 
@@ -2137,6 +2138,150 @@ isvd_status isvd_metrics(isvd_engine* e, isvd_id id, int32_t compute_exact, void
     }
     *out = m;
     return ISVD_OK;
+}
+
+isvd_status isvd_causal_center(const void* r, void* out, int64_t rows, int64_t n, int32_t dtype, double* mu,
+                               int64_t t0, void* hip_stream) {
+    if (!r || !out || !mu) return fail(ISVD_E_INVAL, "null rows, output or mean");
+    if (rows < 1 || n < 1 || t0 < 0) return fail(ISVD_E_INVAL, "rows %lld, n %lld, t0 %lld", (long long)rows,
+                                                 (long long)n, (long long)t0);
+    if (dtype != ISVD_DTYPE_F32 && dtype != ISVD_DTYPE_F64) return fail(ISVD_E_INVAL, "bad dtype %d", dtype);
+    hipStream_t st = (hipStream_t)hip_stream;
+    const int blocks = (int)cdiv(n, 256);
+    if (dtype == ISVD_DTYPE_F64)
+        k_causal_center<double><<<blocks, 256, 0, st>>>((const double*)r, (double*)out, rows, n, mu, t0);
+    else
+        k_causal_center<float><<<blocks, 256, 0, st>>>((const float*)r, (float*)out, rows, n, mu, t0);
+    HIP_TRY(hipGetLastError());
+    return ISVD_OK;
+}
+
+isvd_status isvd_covariance(isvd_engine* e, isvd_id id, double* cov, int64_t ldc, void* hip_stream) {
+    Stream* s = nullptr;
+    ST_TRY(get_stream(e, id, &s));
+    if (!cov) return fail(ISVD_E_INVAL, "null covariance buffer");
+    ST_TRY(ensure_device(e));
+    hipStream_t st = (hipStream_t)hip_stream;
+    // after the stream's queued work (a lane refresh, pending U rotations) on
+    // the GPU; the kernel reads rank and buffer from the device header
+    if (s->refreshing) HIP_TRY(hipStreamWaitEvent(st, s->ev_ready, 0));
+    ST_TRY(join(e, st));
+    const int64_t n = s->n;
+    if (ldc < n) return fail(ISVD_E_INVAL, "ldc %lld < n %lld", (long long)ldc, (long long)n);
+    if (s->m < 2) return fail(ISVD_E_INVAL, "covariance needs at least two rows");
+    dim3 grid((unsigned)cdiv(n, kCovTile), (unsigned)cdiv(n, kCovTile));
+    if (s->esz == 8)
+        k_lowrank_cov<double><<<grid, 256, 0, st>>>(s->hdr, (const double*)s->V[0], (const double*)s->V[1], s->S, n,
+                                                    cov, ldc);
+    else
+        k_lowrank_cov<float><<<grid, 256, 0, st>>>(s->hdr, (const float*)s->V[0], (const float*)s->V[1], s->S, n,
+                                                   cov, ldc);
+    HIP_TRY(hipGetLastError());
+    return ISVD_OK;
+}
+
+}  // extern "C"
+
+namespace {
+template <typename T>
+isvd_status risk_t(isvd_engine* e, Stream& s, const DevHeader& h, const double* w, bool exact, isvd_risk_t* out,
+                   hipStream_t st) {
+    const int64_t n = h.n;
+    const int k = h.k;
+    const double inv_t1 = 1.0 / (double)(h.m - 1);
+    // device scratch: w, y_inc, y_full, G_inc, G_full, C, then V_full (tiled)
+    const int kf_max = kMaxCore;
+    const size_t nd = (size_t)n + 2 * kf_max + 3 * (size_t)kf_max * kf_max;
+    const size_t vf_off = align_up(sizeof(double) * nd, 256);
+    const size_t vf_bytes = (size_t)s.esz * round16(n) * round4(kf_max);
+    ST_TRY(ensure_mws(e, vf_off + (exact ? vf_bytes : 0)));
+    double* dw = (double*)e->mws;
+    double* y_inc = dw + n;
+    double* y_full = y_inc + kf_max;
+    double* G_inc = y_full + kf_max;
+    double* G_full = G_inc + kf_max * kf_max;
+    double* Cx = G_full + kf_max * kf_max;
+    T* Vf = (T*)(e->mws + vf_off);
+    const T* Vi = (const T*)s.V[h.cur];
+    HIP_TRY(hipMemcpyAsync(dw, w, sizeof(double) * n, hipMemcpyHostToDevice, st));
+    k_vt_w<T><<<k, 256, 0, st>>>(Vi, h.ld, n, dw, y_inc);
+    HIP_TRY(hipGetLastError());
+    std::vector<double> si(k), yi(k);
+    HIP_TRY(hipMemcpyAsync(si.data(), s.S, sizeof(double) * k, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(yi.data(), y_inc, sizeof(double) * k, hipMemcpyDeviceToHost, st));
+    const double nan = std::nan("");
+    out->vol_full = out->err_risk = out->err_cov = nan;
+    if (!exact) {
+        HIP_TRY(hipStreamSynchronize(st));
+    } else {
+        // TruncatedSVD(A_t, k): the refresh's computation, V_full = X H as the
+        // refresh would commit it, but into scratch (the stream is unchanged)
+        RefreshPlan plan;
+        ST_TRY(refresh_compute<T>(e, s, false, st, &plan));
+        const char* ws = e->ws.p;
+        const int kf = plan.k;
+        k_rotate_plain<T, 128, true><<<(int)cdiv(plan.n, 16), kThreads, 0, st>>>(
+            (const T*)(ws + plan.w.X), plan.b, Vf, plan.ldo, plan.n, plan.b, (const T*)(ws + plan.w.QV));
+        k_vt_w<T><<<kf, 256, 0, st>>>(Vf, plan.ldo, n, dw, y_full);
+        k_cross<T, T><<<k, 128, 0, st>>>(Vi, h.ld, Vi, h.ld, n, k, G_inc);
+        k_cross<T, T><<<kf, 128, 0, st>>>(Vf, plan.ldo, Vf, plan.ldo, n, kf, G_full);
+        k_cross<T, T><<<k, 128, 0, st>>>(Vi, h.ld, Vf, plan.ldo, n, kf, Cx);
+        HIP_TRY(hipGetLastError());
+        std::vector<double> sf(kf), yf(kf), gi((size_t)k * k), gf((size_t)kf * kf), cx((size_t)k * kf);
+        int sweeps = 0;
+        HIP_TRY(hipMemcpyAsync(sf.data(), ws + plan.w.Sr, sizeof(double) * kf, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(yf.data(), y_full, sizeof(double) * kf, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(gi.data(), G_inc, sizeof(double) * gi.size(), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(gf.data(), G_full, sizeof(double) * gf.size(), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(cx.data(), Cx, sizeof(double) * cx.size(), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(&sweeps, ws + plan.w.sweeps, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if (sweeps < 0) return fail(ISVD_E_CONVERGE, "Rayleigh-Ritz Jacobi did not converge");
+        double vf2 = 0.0, nf2 = 0.0, ni2 = 0.0, x2 = 0.0;
+        for (int c = 0; c < kf; ++c) vf2 += sf[c] * sf[c] * inv_t1 * yf[c] * yf[c];
+        for (int i = 0; i < k; ++i)
+            for (int j = 0; j < k; ++j) {
+                const double g = gi[(size_t)i * k + j];
+                ni2 += (si[i] * si[i] * inv_t1) * (si[j] * si[j] * inv_t1) * g * g;
+            }
+        for (int i = 0; i < kf; ++i)
+            for (int j = 0; j < kf; ++j) {
+                const double g = gf[(size_t)i * kf + j];
+                nf2 += (sf[i] * sf[i] * inv_t1) * (sf[j] * sf[j] * inv_t1) * g * g;
+            }
+        for (int i = 0; i < k; ++i)
+            for (int j = 0; j < kf; ++j) {
+                const double c = cx[(size_t)i * kf + j];
+                x2 += (si[i] * si[i] * inv_t1) * (sf[j] * sf[j] * inv_t1) * c * c;
+            }
+        out->vol_full = std::sqrt(std::max(vf2, 0.0));
+        out->err_cov = nf2 > 0.0 ? std::sqrt(std::max(ni2 + nf2 - 2.0 * x2, 0.0)) / std::sqrt(nf2) : nan;
+    }
+    double vi2 = 0.0;
+    for (int c = 0; c < k; ++c) vi2 += si[c] * si[c] * inv_t1 * yi[c] * yi[c];
+    out->vol_inc = std::sqrt(std::max(vi2, 0.0));
+    if (exact) out->err_risk = out->vol_full > 0.0 ? std::fabs(out->vol_inc - out->vol_full) / out->vol_full : nan;
+    return ISVD_OK;
+}
+}  // namespace
+
+extern "C" {
+
+isvd_status isvd_risk(isvd_engine* e, isvd_id id, const double* w, int64_t n, int32_t exact, isvd_risk_t* out,
+                      void* hip_stream) {
+    Stream* s = nullptr;
+    ST_TRY(get_stream(e, id, &s));
+    if (!w || !out) return fail(ISVD_E_INVAL, "null weights or output");
+    ST_TRY(ensure_device(e));
+    hipStream_t st = (hipStream_t)hip_stream;
+    ST_TRY(settle(e, *s, true));
+    ST_TRY(join(e, st));
+    DevHeader h{};
+    ST_TRY(read_header(*s, st, &h));
+    if (n != h.n) return fail(ISVD_E_SHAPE, "weights length %lld != n %lld", (long long)n, (long long)h.n);
+    if (h.m < 2) return fail(ISVD_E_INVAL, "volatility needs at least two rows");
+    return s->esz == 8 ? risk_t<double>(e, *s, h, w, exact != 0, out, st)
+                       : risk_t<float>(e, *s, h, w, exact != 0, out, st);
 }
 
 isvd_status isvd_get_factors(isvd_engine* e, isvd_id id, double* U, int64_t ldu, double* S, double* V, int64_t ldv,

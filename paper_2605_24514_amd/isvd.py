@@ -81,6 +81,11 @@ class CLaunchTime(ctypes.Structure):
                 ("nreq", ctypes.c_int32), ("blocks", ctypes.c_int64), ("ms", ctypes.c_double)]
 
 
+class CRisk(ctypes.Structure):
+    _fields_ = [("vol_inc", ctypes.c_double), ("vol_full", ctypes.c_double), ("err_risk", ctypes.c_double),
+                ("err_cov", ctypes.c_double)]
+
+
 # FP32 rotation block shapes: (rows per block, 16-row tiles per wave step, prefetch)
 ROT_VARIANTS = [(256, 1, True), (512, 1, True), (1024, 1, True), (1024, 2, False), (2048, 2, False)]
 
@@ -90,7 +95,8 @@ EXPORTS = ["isvd_engine_create", "isvd_engine_destroy", "isvd_stream_bytes", "is
            "isvd_profile", "isvd_profile_read", "isvd_autotune", "isvd_set_rotation_variant", "isvd_sync", "isvd_stream_busy", "isvd_rotation_stream", "isvd_set_pipelining",
            "isvd_server_create", "isvd_server_destroy", "isvd_server_clock", "isvd_server_error",
            "isvd_server_add_stream", "isvd_server_submit", "isvd_server_submit_many", "isvd_server_step", "isvd_server_drain",
-           "isvd_server_poll", "isvd_server_stats", "isvd_server_stream", "isvd_last_error"]
+           "isvd_server_poll", "isvd_server_stats", "isvd_server_stream", "isvd_last_error",
+           "isvd_causal_center", "isvd_covariance", "isvd_risk"]
 
 _lib = None
 
@@ -116,6 +122,9 @@ def load_library(path=LIB_PATH):
         "isvd_update_entry": (i32, [vp, i64, i64, i64, ctypes.c_double, vp]),
         "isvd_refresh": (i32, [vp, i64, i32, vp]),
         "isvd_metrics": (i32, [vp, i64, i32, vp, ctypes.POINTER(CMetrics)]),
+        "isvd_causal_center": (i32, [vp, vp, i64, i64, i32, vp, i64, vp]),
+        "isvd_covariance": (i32, [vp, i64, vp, i64, vp]),
+        "isvd_risk": (i32, [vp, i64, dp, i64, i32, ctypes.POINTER(CRisk), vp]),
         "isvd_get_factors": (i32, [vp, i64, dp, i64, dp, dp, i64, vp]),
         "isvd_get_matrix": (i32, [vp, i64, dp, i64, vp]),
         "isvd_shape": (i32, [vp, i64, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i32)]),
@@ -199,6 +208,34 @@ def _payload(arr):
         a = a.astype(np.float64)
         code = DTYPE_F64
     return ctypes.c_void_p(a.ctypes.data), a.size, code, 0, a
+
+
+def causal_center(r, mu, t0, out=None, stream=None):
+    """Causal de-meaning (Section 5.1) of the return rows r (device tensor,
+    rows x n or n): R_t = r_t - mu_t with the expanding mean mu_t, t = t0 + 1, ...
+    mu: device float64 n-vector, the mean after t0 rows on entry (not read
+    when t0 = 0), updated in place.  Returns the centred rows (out, or a new
+    tensor of r's shape and dtype)."""
+    import torch
+    lib = load_library()
+    if not (hasattr(r, "data_ptr") and r.is_cuda and r.is_contiguous()):
+        raise ValueError("r must be a contiguous device tensor")
+    if not (hasattr(mu, "data_ptr") and mu.is_cuda and mu.dtype == torch.float64 and mu.is_contiguous()):
+        raise ValueError("mu must be a contiguous device float64 tensor")
+    n = r.shape[-1]
+    rows = r.numel() // n if n else 0
+    if mu.numel() != n:
+        raise ValueError("mu has %d entries, rows have %d" % (mu.numel(), n))
+    if out is None:
+        out = torch.empty_like(r)
+    code = DTYPE_F64 if r.dtype == torch.float64 else DTYPE_F32 if r.dtype == torch.float32 else None
+    if code is None or out.dtype != r.dtype or out.shape != r.shape or not out.is_contiguous():
+        raise ValueError("r and out must be float32 / float64 tensors of one shape and dtype")
+    st = lib.isvd_causal_center(ctypes.c_void_p(r.data_ptr()), ctypes.c_void_p(out.data_ptr()), rows, n, code,
+                                ctypes.c_void_p(mu.data_ptr()), int(t0), _stream_ptr(stream))
+    if st != 0:
+        raise IsvdError(st, "isvd_causal_center", lib.isvd_last_error().decode())
+    return out
 
 
 class Engine:
@@ -308,6 +345,29 @@ class Engine:
         self._check(self._lib.isvd_metrics(self._h, sid, 1 if exact else 0, _stream_ptr(stream), ctypes.byref(out)),
                     "isvd_metrics")
         return {f: getattr(out, f) for f, _ in CMetrics._fields_}
+
+    def covariance(self, sid, out=None, stream=None):
+        """Low-rank covariance V diag(sigma^2) V^T / (m - 1) of the stream
+        (Section 5.3) as an n x n float64 device tensor."""
+        import torch
+        _, n, _ = self.shape(sid)
+        if out is None:
+            out = torch.empty((n, n), dtype=torch.float64, device="cuda")
+        if out.dtype != torch.float64 or not out.is_cuda or out.dim() != 2 or out.stride(1) != 1:
+            raise ValueError("out must be a row-major float64 device matrix")
+        self._check(self._lib.isvd_covariance(self._h, sid, ctypes.c_void_p(out.data_ptr()), out.stride(0),
+                                              _stream_ptr(stream)), "isvd_covariance")
+        return out
+
+    def risk(self, sid, w, exact=False, stream=None):
+        """Portfolio volatility of weights w (Section 5.3); with exact also the
+        truncated SVD's volatility, the risk error and the covariance error."""
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        out = CRisk()
+        dp = ctypes.POINTER(ctypes.c_double)
+        self._check(self._lib.isvd_risk(self._h, sid, w.ctypes.data_as(dp), w.size, 1 if exact else 0,
+                                        ctypes.byref(out), _stream_ptr(stream)), "isvd_risk")
+        return {f: getattr(out, f) for f, _ in CRisk._fields_}
 
     def shape(self, sid):
         m, n, k = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
