@@ -372,6 +372,8 @@ def main():
     ap.add_argument("--serve", action="store_true", help="run the serving loop instead of the batched tick")
     ap.add_argument("--refresh", action="store_true", help="time the refresh of one 100000 x 2000 stream instead")
     ap.add_argument("--finance", action="store_true", help="time the finance readout of a 60-asset returns stream")
+    ap.add_argument("--explicit-u", action="store_true",
+                    help="rotate U on every row append (no deferred U = U0 W)")
     ap.add_argument("--serve-streams", type=int, default=1024)
     ap.add_argument("--serve-lifetime", type=int, default=200)
     ap.add_argument("--serve-rate", type=float, default=200000.0)
@@ -440,6 +442,9 @@ def main():
 
     # ---------------------------------------------------- chosen form: batched FP32
     eng32.set_pipelining(not args.no_pipeline)
+    # Brand's deferred left basis U = U0 W for the row appends (explicit U
+    # rotation every m / (8 k) appends, staggered over the streams)
+    eng32.set_deferred_u(not args.explicit_u, stream=dev_stream)
     tune = eng32.autotune(stream=dev_stream)
     log("rotation autotune (bucket: variant): %s" % {kc: v for kc, (v, _) in tune.items()})
     rot_lane = torch.cuda.ExternalStream(eng32.rotation_stream())
@@ -566,7 +571,9 @@ def main():
                                "m~U{1000..50000}, k~U{8,16,32,64}, 5 factors; FP32 storage, FP64 core"
                                % len(params),
                    "streams": len(params), "rows_total": int(sum(p[0] for p in params)),
-                   "cols_total": int(sum(p[1] for p in params))},
+                   "cols_total": int(sum(p[1] for p in params)),
+                   "left_basis": ("explicit: U rotated on every append" if args.explicit_u else
+                                  "deferred U = U0 W (Brand), explicit rotation every m/(8k) appends per stream")},
         "p50_tick_ms": round(pctl(tick_ms, 50), 4),
         "p99_tick_ms": round(pctl(tick_ms, 99), 4),
         "plain_fp64": plain,

@@ -322,6 +322,24 @@ isvd_status isvd_stream_busy(isvd_engine* eng, isvd_id id, int32_t* busy);
  * returning, for the shortest tick latency. */
 isvd_status isvd_set_pipelining(isvd_engine* eng, int32_t enable);
 
+/* Deferred U (Brand's factorised update of the left basis, U = U0 W, W a
+ * k x k FP64 matrix kept with W^-1): enable != 0 lets row appends of
+ * eligible streams (FP32 storage, rank up to 64, no angle / error / adaptive
+ * policy) change W alone -- the new row of U0 is b W'^-1 with b the new row of
+ * U, W' = W A with A the core's rotation restricted to the old rows -- instead
+ * of rotating all m rows of U (Alg. A1's U' = [[U, 0], [0, 1]] U_K, the same
+ * matrix in factored form).  V still rotates every append, in place.  An
+ * append that would change the rank or whose new row carries more than half
+ * of its column's weight rotates U explicitly (W folded into the rotation),
+ * and so does every (m / 8k)-th row append of a stream (at most every 256th),
+ * staggered across streams, which keeps W within a few percent of
+ * orthogonal.  Column appends, entry updates, factor read-back and exact
+ * metrics make U explicit first (one pass U0 W); a refresh resets W to I.
+ * 0 (the default) makes every deferred U explicit on hip_stream and rotates
+ * U on every append again.  Allocates the W buffers of existing eligible
+ * streams when enabling.  Errors: INVAL, DEVICE. */
+isvd_status isvd_set_deferred_u(isvd_engine* eng, int32_t enable, void* hip_stream);
+
 /* The engine's rotation stream (a hipStream_t), e.g. to record an event
  * after the last tick's work: every update of a tick is done when that
  * stream has passed it (refreshes it fired may still run; see isvd_tick). */

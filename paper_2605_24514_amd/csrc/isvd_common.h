@@ -65,7 +65,7 @@ struct DevHeader {
     int32_t last_kind;    // kind of the last applied update
     int32_t ref_k;        // rank of U_ref (stored at the last refresh that kept a reference)
     int32_t ref_ld;       // its leading dimension
-    int32_t pad;
+    int32_t wpar;         // deferred U: which of the two W / W^-1 buffers is current
     int64_t ref_m;        // its rows
     double angle_ref;     // theta_ref (angle-threshold streams), radians
 };
@@ -74,6 +74,7 @@ struct DevHeader {
 struct ReqScratch {
     int32_t skip;         // request rejected: the rotation writes nothing
     int32_t k_in, ld_in, k_out, ld_out, in_idx;
+    int32_t deferred;     // row append applied to W (U = U0 W): no U rotation, V rotates in place
     double inv_rho;       // 1 / rho, or 0 when the residual is not a new direction
 };
 
@@ -98,6 +99,13 @@ struct Req {
     void* QU;             // (k_in + 1) x ld_out rotation of U (row-major)
     void* QV;             // (k_in + 1) x ld_out rotation of V
     const void* payload;  // x (length n) or y (length m), storage type
+    // deferred U (Brand's U = U0 W): W and W^-1 (two buffers each, KC x KC
+    // FP64, row-major) when the stream keeps U that way, else null;
+    // defer: the host asks for this row append to be applied to W
+    double* Wd[2];
+    double* Wdi[2];
+    int32_t defer;
+    int32_t pad;
 };
 
 enum { kRow = 0, kCol = 1, kEntry = 2 };

@@ -121,6 +121,11 @@ struct Stream {
     // fires; until then later work on the stream waits for it
     hipEvent_t ev_ready = nullptr;
     bool refreshing = false;
+    // deferred U (U = U0 W): W, W^-1 (two parities each, kc x kc FP64) in one
+    // allocation; defer_pending = row appends asked to go to W since U was
+    // last explicit; defer_period = the appends between two explicit ones
+    double* wbuf = nullptr;
+    int64_t defer_pending = 0, defer_period = 1;
     bool have_update_time = false, have_refresh_time = false;
     bool live = false;
     bool grow_pending = false;   // adaptive rank: the next append keeps one more triplet
@@ -237,6 +242,7 @@ struct isvd_engine {
     uint64_t ticks = 0;
     bool rot_pending = false;
     bool pipelining = true;            // isvd_set_pipelining
+    bool defer_u = false;              // isvd_set_deferred_u
     std::vector<LaunchRec> prof;
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
@@ -492,10 +498,93 @@ Req make_req(const isvd_engine* e, Stream& s, int kind, const void* payload, int
     r.QU = s.QU[par];
     r.QV = s.QV[par];
     r.payload = payload;
+    if (s.wbuf && e->defer_u) {
+        const size_t w = (size_t)s.kc * s.kc;
+        r.Wd[0] = s.wbuf;
+        r.Wd[1] = s.wbuf + w;
+        r.Wdi[0] = s.wbuf + 2 * w;
+        r.Wdi[1] = s.wbuf + 3 * w;
+        // row appends go to W between explicit ones, every defer_period-th
+        // append rotates U (staggered over streams by their slot)
+        if (kind == kRow) {
+            r.defer = s.defer_pending + 1 < s.defer_period ? 1 : 0;
+            s.defer_pending = r.defer ? s.defer_pending + 1 : 0;
+        }
+    }
     return r;
 }
 
 int rot_tiles(const Req& r, int rows) { return r.rot_tiles_u + (int)cdiv(r.n, rows); }
+
+// ------------------------------------------------------------- deferred U
+// FP32 storage, rank buckets up to 64, no tracker and no rank-changing or
+// U-reading policy: row appends may go to W (U = U0 W) between explicit ones.
+bool defer_eligible(const Stream& s) {
+    const int pk = s.cfg.policy.kind;
+    return s.esz == 4 && !s.bf16 && s.kc <= 64 && !s.angle && (pk == ISVD_POL_NONE || pk == ISVD_POL_PERIODIC);
+}
+
+__global__ void __launch_bounds__(256) k_eye4(double* buf, int kc) {
+    const int w = kc * kc;
+    for (int e = blockIdx.x * 256 + threadIdx.x; e < 4 * w; e += gridDim.x * 256) {
+        const int q = e % w;
+        buf[e] = (q / kc == q % kc) ? 1.0 : 0.0;
+    }
+}
+
+// explicit rotations every defer_period-th row append: the appends in between
+// add about k / m each to the squared weight of W's smallest direction, so
+// m / (8 k) of them keep W within a few percent of orthogonal
+int64_t defer_period_for(const Stream& s) {
+    return std::max<int64_t>(1, std::min<int64_t>(256, s.m / (8 * (int64_t)s.kc)));
+}
+
+isvd_status ensure_wbuf(Stream& s, hipStream_t st) {
+    if (s.wbuf || !defer_eligible(s)) return ISVD_OK;
+    const size_t bytes = sizeof(double) * 4 * (size_t)s.kc * s.kc;
+    HIP_TRY(hipMalloc((void**)&s.wbuf, bytes));
+    k_eye4<<<(int)std::min<int64_t>(64, cdiv(4 * s.kc * s.kc, 256)), 256, 0, st>>>(s.wbuf, s.kc);
+    HIP_TRY(hipGetLastError());
+    s.defer_period = defer_period_for(s);
+    s.defer_pending = s.slot >= 0 ? (7 * (int64_t)s.slot) % s.defer_period : 0;
+    return ISVD_OK;
+}
+
+template <int KC>
+void launch_materialize(Stream& s, hipStream_t st) {
+    const size_t w = (size_t)KC * KC;
+    k_defer_materialize<float, KC><<<(int)cdiv(s.m, 32), 256, 0, st>>>(s.hdr, (float*)s.U[0], (float*)s.U[1], s.wbuf,
+                                                                       s.wbuf + w, s.m);
+}
+
+// Make U explicit (U0 W in place, W = I) before anything that
+// reads U: column appends, entry updates, factors, exact metrics.
+isvd_status defer_flush(Stream& s, hipStream_t st) {
+    if (!s.wbuf || s.defer_pending == 0) return ISVD_OK;
+    switch (s.kc) {
+        case 8: launch_materialize<8>(s, st); break;
+        case 16: launch_materialize<16>(s, st); break;
+        case 32: launch_materialize<32>(s, st); break;
+        default: launch_materialize<64>(s, st); break;
+    }
+    const size_t w = (size_t)s.kc * s.kc;
+    k_defer_reset<<<1, 256, 0, st>>>(s.hdr, s.wbuf, s.wbuf + w, s.wbuf + 2 * w, s.wbuf + 3 * w, s.kc, 0);
+    HIP_TRY(hipGetLastError());
+    s.defer_pending = 0;
+    s.defer_period = defer_period_for(s);
+    return ISVD_OK;
+}
+
+// A refresh writes U explicitly: W back to I.
+isvd_status defer_after_refresh(Stream& s, hipStream_t st) {
+    if (!s.wbuf) return ISVD_OK;
+    const size_t w = (size_t)s.kc * s.kc;
+    k_defer_reset<<<1, 256, 0, st>>>(s.hdr, s.wbuf, s.wbuf + w, s.wbuf + 2 * w, s.wbuf + 3 * w, s.kc, 0);
+    HIP_TRY(hipGetLastError());
+    s.defer_pending = 0;
+    s.defer_period = defer_period_for(s);
+    return ISVD_OK;
+}
 
 isvd_status next_event(isvd_engine* e, hipEvent_t* out) {
     if (e->ev_used == e->ev_pool.size()) {
@@ -1106,6 +1195,7 @@ isvd_status refresh_commit(isvd_engine* e, Stream& s, const RefreshPlan& plan, b
     k_rotate_plain<T, 128, true><<<(int)cdiv(plan.n, 16), kThreads, 0, st>>>((T*)(ws + w.X), plan.b, (T*)s.V[nxt],
                                                                       plan.ldo, plan.n, plan.b, (T*)(ws + w.QV));
     k_commit_header<<<1, 64, 0, st>>>(s.hdr, s.S, (const double*)(ws + w.Sr), plan.k, plan.ldo, plan.b);
+    ST_TRY(defer_after_refresh(s, st));
     if (store_ref) {
         k_track_reset<<<1, kThreads, 0, st>>>(s.hdr, s.TM, s.TH, s.kc);
     } else if (s.TM) {
@@ -1533,6 +1623,7 @@ isvd_status single_update(isvd_engine* e, Stream& s, int kind, const void* paylo
     ST_TRY(settle(e, s, false));
     if (s.refreshing) HIP_TRY(hipStreamWaitEvent(st, s.ev_ready, 0));
     ST_TRY(join(e, st));
+    if (kind != kRow) ST_TRY(defer_flush(s, st));
     HIP_TRY(hipEventRecord(s.ev_u0, st));
     ST_TRY(run_groups(e, groups, st, false));
     if (s.angle) ST_TRY(run_tracks(e, {make_track(s, kind, payload)}, {(char)(s.esz == 8)}, st));
@@ -1560,6 +1651,8 @@ void free_stream(isvd_engine* e, Stream* s) {
     if (s->ev_r0) (void)hipEventDestroy(s->ev_r0);
     if (s->ev_r1) (void)hipEventDestroy(s->ev_r1);
     if (s->ev_ready) (void)hipEventDestroy(s->ev_ready);
+    if (s->wbuf) (void)hipFree(s->wbuf);
+    s->wbuf = nullptr;
     s->base = nullptr;
     s->live = false;
 }
@@ -1684,6 +1777,24 @@ isvd_status isvd_stream_busy(isvd_engine* e, isvd_id id, int32_t* busy) {
     ST_TRY(ensure_device(e));
     ST_TRY(settle(e, *s, false));
     *busy = s->refreshing ? 1 : 0;
+    return ISVD_OK;
+}
+
+isvd_status isvd_set_deferred_u(isvd_engine* e, int32_t enable, void* hip_stream) {
+    if (!e) return fail(ISVD_E_INVAL, "null engine");
+    ST_TRY(ensure_device(e));
+    hipStream_t st = (hipStream_t)hip_stream;
+    ST_TRY(join(e, st));
+    for (Stream* s : e->streams) {
+        if (!s || !s->live) continue;
+        if (s->refreshing) HIP_TRY(hipStreamWaitEvent(st, s->ev_ready, 0));
+        if (enable) {
+            ST_TRY(ensure_wbuf(*s, st));
+        } else {
+            ST_TRY(defer_flush(*s, st));
+        }
+    }
+    e->defer_u = enable != 0;
     return ISVD_OK;
 }
 
@@ -2001,6 +2112,10 @@ static isvd_status init_common(isvd_engine* e, const isvd_config* cfg, const voi
         k_fro2_partial<float><<<nchunk, kThreads, 0, st>>>((const float*)s->A, ldA, m0, n0, (double*)e->ws.p);
     k_sum_block<<<1, kThreads, 0, st>>>((const double*)e->ws.p, nchunk, &s->hdr->N);
     if (hipGetLastError() != hipSuccess) return bail(fail(ISVD_E_DEVICE, "norm launch"));
+    if (e->defer_u) {
+        rc = ensure_wbuf(*s, st);
+        if (rc != ISVD_OK) return bail(rc);
+    }
     rc = given ? install_factors(*s, *given, st) : init_on_lane(e, *s, st);
     if (tmpdev) {
         (void)hipStreamSynchronize(st);
@@ -2081,6 +2196,7 @@ isvd_status isvd_metrics(isvd_engine* e, isvd_id id, int32_t compute_exact, void
     hipStream_t st = (hipStream_t)hip_stream;
     ST_TRY(settle(e, *s, true));
     ST_TRY(join(e, st));
+    if (compute_exact) ST_TRY(defer_flush(*s, st));
     DevHeader h{};
     std::vector<double> S(s->kc + 2, 0.0);
     HIP_TRY(hipMemcpyAsync(&h, s->hdr, sizeof(h), hipMemcpyDeviceToHost, st));
@@ -2292,6 +2408,7 @@ isvd_status isvd_get_factors(isvd_engine* e, isvd_id id, double* U, int64_t ldu,
     hipStream_t st = (hipStream_t)hip_stream;
     ST_TRY(settle(e, *s, true));
     ST_TRY(join(e, st));
+    ST_TRY(defer_flush(*s, st));
     DevHeader h{};
     HIP_TRY(hipMemcpyAsync(&h, s->hdr, sizeof(h), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -2401,6 +2518,8 @@ isvd_status isvd_tick(isvd_engine* e, int32_t count, const isvd_request* reqs, v
     }
     pipelined = pipelined && e->pipelining;
     if (reads_u) ST_TRY(join(e, st));
+    for (int q = 0; q < count; ++q)
+        if (reqs[q].kind != ISVD_ROW) ST_TRY(defer_flush(*ss[q], st));
     std::map<std::pair<int, int>, int> gi;   // (storage size + BF16 flag, bucket)
     std::vector<Group> groups;
     for (int q = 0; q < count; ++q) {

@@ -358,6 +358,26 @@ __global__ void __launch_bounds__(CoreShape<KC>::J::NT) k_core(const Req* __rest
     const int ldo = round4(kout);
     T* QU = (T*)rq.QU;
     T* QV = (T*)rq.QV;
+    // Deferred U (U = U0 W, Brand): a row append whose rank stays k and whose
+    // new row b = U_K[k, :k] has |b|^2 <= 1/2 is applied to W alone when the
+    // host asks for it; otherwise W is folded into the rotation of U.
+    bool wd = false, defer = false;
+    if constexpr (!WITH_J) {
+        wd = kind == kRow && rq.Wd[0] != nullptr;
+        if (wd) {
+            if (tid == 0) {
+                double bb = 0.0;
+                for (int j = 0; j < kout; ++j) {
+                    const double b = sig[j] > 0.0 ? sgn[j] * W[(size_t)perm[j] * ldw + k] / sig[j] : 0.0;
+                    bb += b * b;
+                }
+                s_i[2] = (rq.defer && kout == k && ldo == ld && bb <= 0.5) ? 1 : 0;
+                s_sc[4] = bb;
+            }
+            __syncthreads();
+            defer = s_i[2] != 0;
+        }
+    }
     // U_K(e, j) = sgn_j W[e, perm_j] / sigma_j ;  V_K(e, j) = sgn_j vraw(e, perm_j)
     for (int e = tid; e < N * ldo; e += nt) {
         const int row = e / ldo, j = e % ldo;
@@ -373,7 +393,7 @@ __global__ void __launch_bounds__(CoreShape<KC>::J::NT) k_core(const Req* __rest
             QV[e] = (T)vk;
         } else if (kind == kRow) {
             if (row < k) QU[e] = (T)uk;
-            else ((T*)rq.U[cur ^ 1])[uvo(rq.m, j, ldo)] = (T)uk;
+            else if (!defer) ((T*)rq.U[cur ^ 1])[uvo(rq.m, j, ldo)] = (T)uk;
             QV[e] = (T)vk;
         } else {
             QU[e] = (T)vk;
@@ -382,6 +402,67 @@ __global__ void __launch_bounds__(CoreShape<KC>::J::NT) k_core(const Req* __rest
         }
     }
     for (int j = tid; j < kout; j += nt) rq.S[j] = sig[j];
+    if constexpr (!WITH_J) {
+        if (wd) {
+            // W, W^-1: KC x KC row-major; A = U_K[0:k, 0:k] and b = U_K[k, 0:k]
+            // with A^T A + b^T b = I, so A^-1 = (I + b^T b / (1 - |b|^2)) A^T
+            const int wp = hdr->wpar;
+            const double* Wo = rq.Wd[wp];
+            const double* Wio = rq.Wdi[wp];
+            __syncthreads();
+            for (int j = tid; j < kout; j += nt) sgn[j] = sgn[j] / sig[j];
+            __syncthreads();
+            auto Aat = [&](int c, int j) { return sgn[j] * W[(size_t)perm[j] * ldw + c]; };
+            if (defer) {
+                // new row of U0: u0 = b A^-1 W^-1 = (b A^T) W^-1 / (1 - |b|^2)
+                const double bb = s_sc[4];
+                for (int c = tid; c < k; c += nt) {
+                    double a = 0.0;
+                    for (int j = 0; j < k; ++j) a += Aat(k, j) * Aat(c, j);
+                    su[c] = a;
+                }
+                __syncthreads();
+                for (int j = tid; j < ld; j += nt) {
+                    double a = 0.0;
+                    if (j < k) {
+                        for (int c = 0; c < k; ++c) a += su[c] * Wio[(size_t)c * KC + j];
+                        a /= 1.0 - bb;
+                        dcol[j] = a;
+                    }
+                    ((T*)rq.U[cur])[uvo(rq.m, j, ld)] = (T)a;
+                }
+                __syncthreads();
+                // W' = W A and (W A)^-1 = A^T W^-1 + b^T u0, into the other buffers
+                double* Wn = rq.Wd[wp ^ 1];
+                double* Win = rq.Wdi[wp ^ 1];
+                for (int e = tid; e < k * k; e += nt) {
+                    const int r = e / k, j = e - (e / k) * k;
+                    double a = 0.0, t = 0.0;
+                    for (int c = 0; c < k; ++c) {
+                        a += Wo[(size_t)r * KC + c] * Aat(c, j);
+                        t += Aat(c, r) * Wio[(size_t)c * KC + j];
+                    }
+                    Wn[(size_t)r * KC + j] = a;
+                    Win[(size_t)r * KC + j] = t + Aat(k, r) * dcol[j];
+                }
+            } else {
+                // explicit: U's rotation takes W A, and W, W^-1 return to I
+                for (int e = tid; e < k * ldo; e += nt) {
+                    const int r = e / ldo, j = e - (e / ldo) * ldo;
+                    double a = 0.0;
+                    if (j < kout)
+                        for (int c = 0; c < k; ++c) a += Wo[(size_t)r * KC + c] * Aat(c, j);
+                    QU[e] = (T)a;
+                }
+                __syncthreads();
+                for (int e = tid; e < KC * KC; e += nt) {
+                    const double v = (e / KC == e - (e / KC) * KC) ? 1.0 : 0.0;
+                    rq.Wd[wp][e] = v;
+                    rq.Wdi[wp][e] = v;
+                }
+            }
+        }
+    }
     if (tid == 0) {
         double dN = 0.0;
         if (kind == kEntry) {
@@ -399,9 +480,11 @@ __global__ void __launch_bounds__(CoreShape<KC>::J::NT) k_core(const Req* __rest
         rs->ld_out = ldo;
         rs->in_idx = cur;
         rs->inv_rho = s_sc[2];
+        rs->deferred = defer ? 1 : 0;
         hdr->k = kout;
         hdr->ld = ldo;
-        hdr->cur = cur ^ 1;
+        hdr->cur = defer ? cur : (cur ^ 1);
+        if (defer) hdr->wpar ^= 1;
         hdr->t += 1;
         if (kind == kRow) hdr->m += 1;
         if (kind == kCol) hdr->n += 1;
@@ -446,10 +529,12 @@ __global__ void __launch_bounds__(kThreads) k_rotate(const Req* __restrict__ req
     const int tile_all = blockIdx.x - prefix[ri];
     const bool isU = part == 1 || (part == 0 && tile_all < rq.rot_tiles_u);
     const int tile = (part != 0 || isU) ? tile_all : tile_all - rq.rot_tiles_u;
+    const bool deferred = rs->deferred != 0;   // deferred U: see k_rotate_mfma_t
+    if (isU && deferred) return;
     const int kin = rs->k_in, ldi = rs->ld_in, ldo = rs->ld_out, idx = rs->in_idx;
     const int64_t rows = isU ? rq.m : rq.n;
     const T* Xi = (const T*)(isU ? rq.U[idx] : rq.V[idx]);
-    T* Xo = (T*)(isU ? rq.U[idx ^ 1] : rq.V[idx ^ 1]);
+    T* Xo = (T*)(isU ? rq.U[idx ^ 1] : rq.V[deferred ? idx : idx ^ 1]);
     const T* Q = (const T*)(isU ? rq.QU : rq.QV);
     const bool projected = (rq.kind == kRow && !isU) || (rq.kind == kCol && isU);
     const int nq = kin + (projected ? 1 : 0);
@@ -530,10 +615,15 @@ __global__ void __launch_bounds__(kThreads) k_rotate_mfma(const Req* __restrict_
     const int tile_all = blockIdx.x - prefix[ri];
     const bool isU = part == 1 || (part == 0 && tile_all < rq.rot_tiles_u);
     const int tile = (part != 0 || isU) ? tile_all : tile_all - rq.rot_tiles_u;
+    // a row append applied to W (deferred U) rotates no U tile and V in
+    // place (same leading dimension; each row is read before it is written,
+    // by the same wave)
+    const bool deferred = rs->deferred != 0;
+    if (isU && deferred) return;
     const int kin = rs->k_in, ldi = rs->ld_in, ldo = rs->ld_out, idx = rs->in_idx;
     const int64_t rows = isU ? rq.m : rq.n;
     gcfloat* Xi = (gcfloat*)(isU ? rq.U[idx] : rq.V[idx]);
-    gfloat* Xo = (gfloat*)(isU ? rq.U[idx ^ 1] : rq.V[idx ^ 1]);
+    gfloat* Xo = (gfloat*)(isU ? rq.U[idx ^ 1] : rq.V[deferred ? idx : idx ^ 1]);
     gcfloat* Q = (gcfloat*)(isU ? rq.QU : rq.QV);
     const bool projected = (rq.kind == kRow && !isU) || (rq.kind == kCol && isU);
     const int nq = kin + (projected ? 1 : 0);
@@ -695,10 +785,15 @@ __global__ void __launch_bounds__(kThreads) k_rotate_mfma_t(const Req* __restric
     const int tile_all = blockIdx.x - prefix[ri];
     const bool isU = part == 1 || (part == 0 && tile_all < rq.rot_tiles_u);
     const int tile = (part != 0 || isU) ? tile_all : tile_all - rq.rot_tiles_u;
+    // a row append applied to W (deferred U) rotates no U tile and V in
+    // place (same leading dimension; each row is read before it is written,
+    // by the same wave)
+    const bool deferred = rs->deferred != 0;
+    if (isU && deferred) return;
     const int kin = rs->k_in, ldi = rs->ld_in, ldo = rs->ld_out, idx = rs->in_idx;
     const int64_t rows = isU ? rq.m : rq.n;
     gcfloat* Xi = (gcfloat*)(isU ? rq.U[idx] : rq.V[idx]);
-    gfloat* Xo = (gfloat*)(isU ? rq.U[idx ^ 1] : rq.V[idx ^ 1]);
+    gfloat* Xo = (gfloat*)(isU ? rq.U[idx ^ 1] : rq.V[deferred ? idx : idx ^ 1]);
     gcfloat* Q = (gcfloat*)(isU ? rq.QU : rq.QV);
     const bool projected = (rq.kind == kRow && !isU) || (rq.kind == kCol && isU);
     if (projected) {
@@ -819,6 +914,54 @@ __global__ void __launch_bounds__(kThreads) k_rotate_mfma_t(const Req* __restric
         }
         row0 = nrow0;
     }
+}
+
+// ---------------------------------------------------------------------------
+// Deferred U (U = U0 W): materialisation and reset.
+// k_defer_materialize: U[cur] <- U[cur] W[wpar][0:k, 0:k] in place (tiled,
+// same ld; columns k.. zero): rows are independent and each block stages its
+// 32 rows in LDS before writing them.  The buffer index stays, since V (rotated
+// in place by deferred appends) lives in the same one.  W staged in LDS (FP64).
+template <typename T, int KC>
+__global__ void __launch_bounds__(256) k_defer_materialize(const DevHeader* __restrict__ hdr, T* U0, T* U1,
+                                                           const double* W0, const double* W1, int64_t m) {
+    __shared__ double sW[KC * KC];
+    __shared__ double sX[32 * KC];
+    const int k = hdr->k, ld = hdr->ld, cur = hdr->cur;
+    const double* W = hdr->wpar ? W1 : W0;
+    T* X = cur ? U1 : U0;
+    T* Y = X;
+    for (int e = threadIdx.x; e < k * k; e += 256) sW[(e / k) * KC + e % k] = W[(size_t)(e / k) * KC + e % k];
+    const int64_t r0 = (int64_t)blockIdx.x * 32;
+    const int nr = (int)min((int64_t)32, m - r0);
+    for (int e = threadIdx.x; e < nr * k; e += 256) {
+        const int rr = e / k, c = e - (e / k) * k;
+        sX[rr * KC + c] = (double)X[uvo(r0 + rr, c, ld)];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < nr * ld; e += 256) {
+        const int rr = e / ld, j = e - (e / ld) * ld;
+        double a = 0.0;
+        if (j < k)
+            for (int c = 0; c < k; ++c) a += sX[rr * KC + c] * sW[c * KC + j];
+        Y[uvo(r0 + rr, j, ld)] = (T)a;
+    }
+}
+
+// After a materialisation or a refresh: W and W^-1 of the current parity back
+// to I (flip = 1 would also switch the current U / V buffers).
+__global__ void __launch_bounds__(256) k_defer_reset(DevHeader* hdr, double* W0, double* W1, double* Wi0, double* Wi1,
+                                                     int kc, int flip) {
+    const int wp = hdr->wpar;
+    double* W = wp ? W1 : W0;
+    double* Wi = wp ? Wi1 : Wi0;
+    for (int e = threadIdx.x; e < kc * kc; e += 256) {
+        const double v = (e / kc == e - (e / kc) * kc) ? 1.0 : 0.0;
+        W[e] = v;
+        Wi[e] = v;
+    }
+    __syncthreads();
+    if (flip && threadIdx.x == 0) hdr->cur ^= 1;
 }
 
 }  // namespace isvd

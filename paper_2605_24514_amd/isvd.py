@@ -96,7 +96,7 @@ EXPORTS = ["isvd_engine_create", "isvd_engine_destroy", "isvd_stream_bytes", "is
            "isvd_server_create", "isvd_server_destroy", "isvd_server_clock", "isvd_server_error",
            "isvd_server_add_stream", "isvd_server_submit", "isvd_server_submit_many", "isvd_server_step", "isvd_server_drain",
            "isvd_server_poll", "isvd_server_stats", "isvd_server_stream", "isvd_last_error",
-           "isvd_causal_center", "isvd_covariance", "isvd_risk"]
+           "isvd_causal_center", "isvd_covariance", "isvd_risk", "isvd_set_deferred_u"]
 
 _lib = None
 
@@ -137,6 +137,7 @@ def load_library(path=LIB_PATH):
         "isvd_sync": (i32, [vp, vp]),
         "isvd_stream_busy": (i32, [vp, i64, ctypes.POINTER(i32)]),
         "isvd_set_pipelining": (i32, [vp, i32]),
+        "isvd_set_deferred_u": (i32, [vp, i32, vp]),
         "isvd_server_create": (i32, [vp, ctypes.POINTER(CServerConfig), vp, ctypes.POINTER(vp)]),
         "isvd_server_destroy": (i32, [vp]),
         "isvd_server_clock": (ctypes.c_double, [vp]),
@@ -469,6 +470,12 @@ class Engine:
 
     def set_pipelining(self, enable):
         self._check(self._lib.isvd_set_pipelining(self._h, 1 if enable else 0), "isvd_set_pipelining")
+
+    def set_deferred_u(self, enable, stream=None):
+        """Brand's deferred left basis U = U0 W for the row appends of eligible
+        streams (see isvd_set_deferred_u in include/isvd.h)."""
+        self._check(self._lib.isvd_set_deferred_u(self._h, 1 if enable else 0, _stream_ptr(stream)),
+                    "isvd_set_deferred_u")
 
     def rotation_stream(self):
         """Handle (int) of the engine's rotation stream; wrap it with

@@ -1,0 +1,144 @@
+"""GPU parity of the deferred left basis (U = U0 W) against the FP64 oracle,
+which rotates U explicitly (Alg. A1).
+
+The deferred form holds the same matrix with different rounding, so it is
+held to the FP32 bars of the explicit path (reconstruction <= 2e-5,
+singular values <= 1e-5, principal angles <= 1e-4 rad on the gap-separated
+scope), plus U orthonormal to 1e-5.  Shapes are large enough (m >= 16 k...)
+that the flush period m / (8 k) leaves several row appends in a row on W,
+and narrow enough (n <= k + oversampling, at most 96) that the engine's
+initial TruncatedSVD is exact like the oracle's.
+"""
+import numpy as np
+import pytest
+
+from oracle.engine import OracleEngine
+from oracle.policies import Policy as OPolicy
+from synth import FactorStream, ROW, COL, ENTRY
+from tests.parity import compare
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def isvd():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2605_24514_amd import isvd as mod
+    return mod
+
+
+def _apply(eng, sid, ev):
+    if ev.kind == ROW:
+        eng.append_row(sid, ev.vec)
+    elif ev.kind == COL:
+        eng.append_col(sid, ev.vec)
+    else:
+        eng.update_entry(sid, ev.i, ev.j, ev.delta)
+
+
+def _check(eng, sid, o, where):
+    U, S, V = eng.factors(sid)
+    c = compare((U, S, V), (o.U, o.s, o.V))
+    assert c["recon"] <= 2e-5, (where, c)
+    assert c["sigma"] <= 1e-5, (where, c)
+    assert c["angle_U"] <= 1e-4 and c["angle_V"] <= 1e-4, (where, c)
+    assert np.abs(U.T @ U - np.eye(len(S))).max() <= 1e-5, where
+    return c
+
+
+@pytest.mark.parametrize("k", [8, 16, 32, 64])
+def test_single_stream_rows_then_mixed(isvd, k):
+    """40 row appends on W (factors read only at the end), then a column
+    append, an entry update and more rows (each making U explicit first)."""
+    n0 = min(k + 56, 96)
+    fs = FactorStream(seed=20 + k, stream=0, n0=n0, K=5)
+    m0 = 3000
+    A0 = fs.initial(m0)
+    kinds = [ROW] * 40 + [COL, ROW, ROW, ENTRY] + [ROW] * 20
+    events = fs.materialize(kinds, m0=m0)
+    o = OracleEngine(A0, k, tol_rel=1e-5, cgs2=True)
+    with isvd.Engine() as eng:
+        eng.set_deferred_u(True)
+        sid = eng.init(A0, k, "fp32", m_cap=m0 + 70, n_cap=n0 + 2, oversample=64)
+        for q, ev in enumerate(events):
+            _apply(eng, sid, ev)
+            o.step(ev)
+            if q == 39:
+                _check(eng, sid, o, "after 40 rows")
+        c = _check(eng, sid, o, "end")
+        met = eng.metrics(sid, exact=True)
+        oe = o.exact_metrics()
+        assert abs(met["frob_error"] - oe["frob_error"]) <= 1e-5 * np.sqrt(o.N)
+        print(k, c)
+
+
+def test_batched_ticks_match_explicit_and_oracle(isvd):
+    """48 streams over the four rank buckets, 60 row-append ticks: the
+    deferred engine against the explicit one and against the oracle."""
+    import torch
+    ks = (8, 16, 32, 64)
+    shapes = [(2000 + 400 * s, (40 if ks[s % 4] < 64 else 64) + 8 * (s % 5), ks[s % 4]) for s in range(48)]
+    T = 60
+    data = []
+    for s, (m0, n0, k) in enumerate(shapes):
+        fs = FactorStream(seed=31, stream=s, n0=n0, K=5)
+        data.append((fs.initial(m0), k, fs.materialize([ROW] * T, m0=m0)))
+    res = {}
+    for deferred in (True, False):
+        with isvd.Engine() as eng:
+            eng.set_deferred_u(deferred)
+            sids = [eng.init(A0, k, "fp32", m_cap=A0.shape[0] + T, n_cap=A0.shape[1], oversample=64)
+                    for A0, k, _ in data]
+            pays = [[torch.tensor(ev.vec, dtype=torch.float32, device="cuda") for ev in evs] for _, _, evs in data]
+            for t in range(T):
+                eng.tick([(sid, isvd.ROW, pays[q][t]) for q, sid in enumerate(sids)])
+            res[deferred] = [eng.factors(sid) for sid in sids]
+    for q in range(len(shapes)):
+        c = compare(res[True][q], res[False][q])
+        assert c["recon"] <= 2e-5 and c["sigma"] <= 1e-5, (q, c)
+    for q in (0, 5, 13, 27, 46):
+        A0, k, evs = data[q]
+        o = OracleEngine(A0, k, tol_rel=1e-5, cgs2=True)
+        for ev in evs:
+            o.step(ev)
+        c = compare(res[True][q], (o.U, o.s, o.V))
+        assert c["recon"] <= 2e-5 and c["sigma"] <= 1e-5, (q, c)
+        assert c["angle_U"] <= 1e-4 and c["angle_V"] <= 1e-4, (q, c)
+
+
+def test_periodic_refresh_resets_w(isvd):
+    fs = FactorStream(seed=41, stream=0, n0=60, K=5)
+    m0 = 2500
+    A0 = fs.initial(m0)
+    events = fs.materialize([ROW] * 75, m0=m0)
+    pol = isvd.Policy(kind=isvd.POL_PERIODIC, period=25)
+    o = OracleEngine(A0, 16, tol_rel=1e-5, cgs2=True, policy=OPolicy.periodic(25))
+    with isvd.Engine() as eng:
+        eng.set_deferred_u(True)
+        sid = eng.init(A0, 16, "fp32", m_cap=m0 + 80, n_cap=60, oversample=64, policy=pol)
+        for q, ev in enumerate(events):
+            _apply(eng, sid, ev)
+            o.step(ev)
+            if q in (30, 74):
+                _check(eng, sid, o, q)
+        assert eng.metrics(sid)["n_refresh"] == 3
+
+
+def test_disable_makes_u_explicit(isvd):
+    fs = FactorStream(seed=43, stream=0, n0=50, K=5)
+    A0 = fs.initial(4000)
+    events = fs.materialize([ROW] * 30 + [ROW] * 10, m0=4000)
+    o = OracleEngine(A0, 8, tol_rel=1e-5, cgs2=True)
+    with isvd.Engine() as eng:
+        eng.set_deferred_u(True)
+        sid = eng.init(A0, 8, "fp32", m_cap=4050, n_cap=50, oversample=64)
+        for ev in events[:30]:
+            _apply(eng, sid, ev)
+            o.step(ev)
+        eng.set_deferred_u(False)
+        for ev in events[30:]:
+            _apply(eng, sid, ev)
+            o.step(ev)
+        _check(eng, sid, o, "after disable")
