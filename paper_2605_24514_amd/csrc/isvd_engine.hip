@@ -642,7 +642,8 @@ isvd_status launch_recorded(isvd_engine* e, const Group& g, const char* dev, int
 
 // Lay out groups in a slot, upload, and launch one tick (or one immediate
 // update).  Per group, on its update lane (the caller's stream for buckets
-// of 64 and wider, lane b for the others): the two projection passes, the
+// of 64 and wider -- 32 and wider with deferred U --, lane b for the
+// others): the two projection passes, the
 // core, then V's rotation; after the group's core, U's rotation on a
 // rotation lane (rotation lane b for the buckets below 64, the rotation lane
 // for the others, so the two overlap).
@@ -703,15 +704,23 @@ isvd_status run_groups(isvd_engine* e, std::vector<Group>& groups, hipStream_t s
         HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
         e->ev_core.push_back(ev);
     }
-    bool use_b = false;
-    for (const Group& g : groups) use_b = use_b || g.kc < 64;
+    // update lanes: buckets of `split` and wider on the caller's stream, the
+    // others on lane b.  With deferred U the cores (W updates) dominate and
+    // the 32-column bucket joins the caller's stream; otherwise the U
+    // rotations do, and only the widest bucket stays there.
+    const int split = e->defer_u ? 32 : 64;
+    bool use_b = false, use_rb = false;
+    for (const Group& g : groups) {
+        use_b = use_b || g.kc < split;
+        use_rb = use_rb || g.kc < 64;
+    }
     if (use_b) {
         HIP_TRY(hipEventRecord(e->ev_fork, st));
         HIP_TRY(hipStreamWaitEvent(e->lane_b, e->ev_fork, 0));
     }
     for (size_t gi = 0; gi < groups.size(); ++gi) {
         const Group& g = groups[gi];
-        hipStream_t ln = g.kc >= 64 ? st : e->lane_b;
+        hipStream_t ln = g.kc >= split ? st : e->lane_b;
         for (int phase = 0; phase < 3; ++phase) ST_TRY(launch_recorded(e, g, slot->dev, phase, ln));
         HIP_TRY(hipEventRecord(e->ev_core[gi], ln));
         ST_TRY(launch_recorded(e, g, slot->dev, 4, ln));
@@ -725,9 +734,11 @@ isvd_status run_groups(isvd_engine* e, std::vector<Group>& groups, hipStream_t s
     // the tick ends on the rotation lane once every lane is through it
     HIP_TRY(hipEventRecord(e->ev_main, st));
     HIP_TRY(hipStreamWaitEvent(e->rot_lane, e->ev_main, 0));
-    if (use_b) {
+    if (use_rb) {
         HIP_TRY(hipEventRecord(e->ev_rot_b, e->rot_lane_b));
         HIP_TRY(hipStreamWaitEvent(e->rot_lane, e->ev_rot_b, 0));
+    }
+    if (use_b) {
         HIP_TRY(hipEventRecord(e->ev_b_end, e->lane_b));
         HIP_TRY(hipStreamWaitEvent(e->rot_lane, e->ev_b_end, 0));
         // lane b reads the caller's payloads (projections, V rotations): the

@@ -405,56 +405,94 @@ __global__ void __launch_bounds__(CoreShape<KC>::J::NT) k_core(const Req* __rest
     if constexpr (!WITH_J) {
         if (wd) {
             // W, W^-1: KC x KC row-major; A = U_K[0:k, 0:k] and b = U_K[k, 0:k]
-            // with A^T A + b^T b = I, so A^-1 = (I + b^T b / (1 - |b|^2)) A^T
+            // with A^T A + b^T b = I, so A^-1 = (I + b^T b / (1 - |b|^2)) A^T.
+            // A[c][j] = f_j Kv[perm_j][c] with f_j = sgn_j / sigma_j (Kv: the
+            // columns of K V in LDS).  Each k x k operand read in a product is
+            // first staged in the V_K region of LDS (free once QV is written),
+            // row stride k + 1.
             const int wp = hdr->wpar;
             const double* Wo = rq.Wd[wp];
             const double* Wio = rq.Wdi[wp];
+            double* stg = J;
+            const int lds_s = k + 1;
             __syncthreads();
             for (int j = tid; j < kout; j += nt) sgn[j] = sgn[j] / sig[j];
-            __syncthreads();
-            auto Aat = [&](int c, int j) { return sgn[j] * W[(size_t)perm[j] * ldw + c]; };
+            auto stage = [&](const double* src) {
+                for (int e = tid; e < k * k; e += nt) stg[(e / k) * lds_s + e % k] = src[(size_t)(e / k) * KC + e % k];
+            };
             if (defer) {
-                // new row of U0: u0 = b A^-1 W^-1 = (b A^T) W^-1 / (1 - |b|^2)
                 const double bb = s_sc[4];
+                stage(Wio);
+                __syncthreads();
+                // v = b A^T: v_c = sum_j b_j A[c][j]
                 for (int c = tid; c < k; c += nt) {
                     double a = 0.0;
-                    for (int j = 0; j < k; ++j) a += Aat(k, j) * Aat(c, j);
+                    for (int j = 0; j < k; ++j) {
+                        const double* wj = W + (size_t)perm[j] * ldw;
+                        a += (sgn[j] * wj[k]) * (sgn[j] * wj[c]);
+                    }
                     su[c] = a;
                 }
                 __syncthreads();
+                // new row of U0: u0 = v W^-1 / (1 - |b|^2)
                 for (int j = tid; j < ld; j += nt) {
                     double a = 0.0;
                     if (j < k) {
-                        for (int c = 0; c < k; ++c) a += su[c] * Wio[(size_t)c * KC + j];
+                        for (int c = 0; c < k; ++c) a += su[c] * stg[c * lds_s + j];
                         a /= 1.0 - bb;
                         dcol[j] = a;
                     }
                     ((T*)rq.U[cur])[uvo(rq.m, j, ld)] = (T)a;
                 }
                 __syncthreads();
-                // W' = W A and (W A)^-1 = A^T W^-1 + b^T u0, into the other buffers
-                double* Wn = rq.Wd[wp ^ 1];
+                // (W A)^-1 = A^T W^-1 + b^T u0
                 double* Win = rq.Wdi[wp ^ 1];
                 for (int e = tid; e < k * k; e += nt) {
                     const int r = e / k, j = e - (e / k) * k;
-                    double a = 0.0, t = 0.0;
-                    for (int c = 0; c < k; ++c) {
-                        a += Wo[(size_t)r * KC + c] * Aat(c, j);
-                        t += Aat(c, r) * Wio[(size_t)c * KC + j];
+                    const double* wr = W + (size_t)perm[r] * ldw;
+                    double t0 = 0.0, t1 = 0.0;
+                    int c = 0;
+                    for (; c + 1 < k; c += 2) {
+                        t0 += wr[c] * stg[c * lds_s + j];
+                        t1 += wr[c + 1] * stg[(c + 1) * lds_s + j];
                     }
-                    Wn[(size_t)r * KC + j] = a;
-                    Win[(size_t)r * KC + j] = t + Aat(k, r) * dcol[j];
+                    if (c < k) t0 += wr[c] * stg[c * lds_s + j];
+                    Win[(size_t)r * KC + j] = sgn[r] * (t0 + t1) + (sgn[r] * wr[k]) * dcol[j];
+                }
+                __syncthreads();
+                // W' = W A
+                stage(Wo);
+                __syncthreads();
+                // adjacent lanes take adjacent rows r: Kv[perm_j] is read as a
+                // broadcast and the staged rows at the odd stride k + 1
+                double* Wn = rq.Wd[wp ^ 1];
+                for (int e = tid; e < k * k; e += nt) {
+                    const int j = e / k, r = e - (e / k) * k;
+                    const double* wj = W + (size_t)perm[j] * ldw;
+                    const double* sr = stg + r * lds_s;
+                    double a0 = 0.0, a1 = 0.0;
+                    int c = 0;
+                    for (; c + 1 < k; c += 2) {
+                        a0 += sr[c] * wj[c];
+                        a1 += sr[c + 1] * wj[c + 1];
+                    }
+                    if (c < k) a0 += sr[c] * wj[c];
+                    Wn[(size_t)r * KC + j] = sgn[j] * (a0 + a1);
                 }
             } else {
                 // explicit: U's rotation takes W A, and W, W^-1 return to I
-                for (int e = tid; e < k * ldo; e += nt) {
-                    const int r = e / ldo, j = e - (e / ldo) * ldo;
-                    double a = 0.0;
-                    if (j < kout)
-                        for (int c = 0; c < k; ++c) a += Wo[(size_t)r * KC + c] * Aat(c, j);
-                    QU[e] = (T)a;
-                }
+                stage(Wo);
                 __syncthreads();
+                for (int e = tid; e < k * ldo; e += nt) {
+                    const int j = e / k, r = e - (e / k) * k;   // adjacent lanes: adjacent rows
+                    double a = 0.0;
+                    if (j < kout) {
+                        const double* wj = W + (size_t)perm[j] * ldw;
+                        for (int c = 0; c < k; ++c) a += stg[r * lds_s + c] * wj[c];
+                        a *= sgn[j];
+                    }
+                    QU[r * ldo + j] = (T)a;
+                }
                 for (int e = tid; e < KC * KC; e += nt) {
                     const double v = (e / KC == e - (e / KC) * KC) ? 1.0 : 0.0;
                     rq.Wd[wp][e] = v;
