@@ -58,9 +58,14 @@ def rot_u_bytes(m, k, esz):
     return esz * 2 * m * k
 
 
-def tick_bytes(m, n, k, esz):
+def tick_bytes(m, n, k, esz, deferred=False):
     # whole row append: the projected basis V is read once more, x once more for the projection
-    return rot_bytes(m, n, k, esz) + esz * n * k + esz * n
+    full = rot_bytes(m, n, k, esz) + esz * n * k + esz * n
+    if not deferred:
+        return full
+    # deferred U: U is read and written once per explicit append, every m / (8 k)-th
+    period = max(1, min(256, int(m) // (8 * k)))
+    return full - rot_u_bytes(m, k, esz) + rot_u_bytes(m, k, esz) / period
 
 
 PMC_RECORD = os.path.join(ROOT, "profiles", "rotate_u_kc64_tick512_pmc.md")
@@ -448,26 +453,32 @@ def main():
     tune = eng32.autotune(stream=dev_stream)
     log("rotation autotune (bucket: variant): %s" % {kc: v for kc, (v, _) in tune.items()})
     rot_lane = torch.cuda.ExternalStream(eng32.rotation_stream())
+    # a tick ends on the rotation stream, or, with deferred U (no rotation
+    # lanes), on the caller's stream
+    end_lane = dev_stream if not args.explicit_u else rot_lane
     for t in range(W):
         eng32.tick_raw(reqs[t], stream=dev_stream)
     eng32.sync(stream=dev_stream)
     torch.cuda.synchronize()
-    # per tick: start on the caller's stream, end when the engine's rotation
-    # stream (which finishes every tick) has passed it
+    # per tick: start on the caller's stream, end when the stream that
+    # finishes every tick has passed it
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    host_s = 0.0
     for q in range(K):
         evs[q][0].record(dev_stream)
+        h0 = time.perf_counter()
         eng32.tick_raw(reqs[W + q], stream=dev_stream)
-        evs[q][1].record(rot_lane)
+        host_s += time.perf_counter() - h0
+        evs[q][1].record(end_lane)
     eng32.sync(stream=dev_stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     tick_ms = [a.elapsed_time(b) for a, b in evs]
     value = len(params) * K / wall
-    log("batched FP32: %.0f updates/s, tick latency p50 %.3f ms p99 %.3f ms" % (value, pctl(tick_ms, 50),
-                                                                                 pctl(tick_ms, 99)))
+    log("batched FP32: %.0f updates/s, tick latency p50 %.3f ms p99 %.3f ms; host %.3f ms per tick call"
+        % (value, pctl(tick_ms, 50), pctl(tick_ms, 99), host_s / K * 1e3))
 
 
 
@@ -522,23 +533,56 @@ def main():
     for (ph, kc), v in by_launch.items():
         phase_ms.setdefault(ph, 0.0)
         phase_ms[ph] += float(np.sum(v)) / Kp
-    # dominant kernel: the U rotation of the widest bucket (HBM-bound)
-    kdom = max(kc for (ph, kc) in by_launch if ph == 3)
-    dom_ms = float(np.mean(by_launch[(3, kdom)]))
     mid = W + K + (Kp - 1) / 2.0
     bucket = lambda k: 8 if k <= 8 else 16 if k <= 16 else 32 if k <= 32 else 64 if k <= 64 else 128
-    dom_bytes = sum(rot_u_bytes(m0 + mid, k, 4) for (m0, n0, k) in params if bucket(k) == kdom)
     mid_all = W + (K - 1) / 2.0
-    all_tick_bytes = sum(tick_bytes(m0 + mid_all, n0, k, 4) for (m0, n0, k) in params)
-    achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
-    dom_ratio = recorded_traffic_ratio(tune[kdom][0]) if kdom in tune else None
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": (int(dom_ratio * dom_bytes) if dom_ratio is not None and kdom == 64 else None),
-                "traffic_note": "HBM bytes per launch: rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated, "
-                                "ratio to algorithmic bytes from profiles/rotate_u_kc64_tick512_pmc.md",
-                "kernel": "k_rotate_mfma_t<%d> (U rotation, variant %d)" % (kdom, tune[kdom][0] if kdom in tune else -1),
-                "launch_ms": round(dom_ms, 4), "bytes_per_launch": int(dom_bytes)}
+    deferred = not args.explicit_u
+    all_tick_bytes = sum(tick_bytes(m0 + mid_all, n0, k, 4, deferred) for (m0, n0, k) in params)
+    if not deferred:
+        # dominant kernel: the U rotation of the widest bucket (HBM-bound)
+        kdom = max(kc for (ph, kc) in by_launch if ph == 3)
+        dom_ms = float(np.mean(by_launch[(3, kdom)]))
+        dom_bytes = sum(rot_u_bytes(m0 + mid, k, 4) for (m0, n0, k) in params if bucket(k) == kdom)
+        achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
+        dom_ratio = recorded_traffic_ratio(tune[kdom][0]) if kdom in tune else None
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": (int(dom_ratio * dom_bytes) if dom_ratio is not None and kdom == 64 else None),
+                    "traffic_note": "HBM bytes per launch: rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated, "
+                                    "ratio to algorithmic bytes from profiles/rotate_u_kc64_tick512_pmc.md",
+                    "kernel": "k_rotate_mfma_t<%d> (U rotation, variant %d)" % (kdom, tune[kdom][0] if kdom in tune else -1),
+                    "launch_ms": round(dom_ms, 4), "bytes_per_launch": int(dom_bytes)}
+    else:
+        # dominant kernel: the longest launch of the tick -- with deferred U
+        # the append core of the widest bucket (one workgroup per stream,
+        # FP64), priced by its W update: W A and A^T W^-1, 4 k^3 flops per append
+        (ph, kdom) = max(by_launch, key=lambda key: float(np.mean(by_launch[key])))
+        dom_ms = float(np.mean(by_launch[(ph, kdom)]))
+        names = {0: "k_proj (pass 1)", 1: "k_proj (pass 2)", 2: "k_core", 3: "k_rotate_mfma_t (U)",
+                 4: "k_rotate_mfma_t (V)"}
+        sel = [(m0, n0, k) for (m0, n0, k) in params if bucket(k) == kdom]
+        if ph == 2:
+            flops = sum(4.0 * k ** 3 for (m0, n0, k) in sel)
+            achieved = flops / (dom_ms * 1e-3) / 1e12
+            roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": round(achieved / FP64_PEAK_TFLOPS, 5), "traffic": None,
+                        "kernel": "k_core<float, %d> (append core: secular SVD + deferred-U update, FP64)" % kdom,
+                        "launch_ms": round(dom_ms, 4), "flops_per_launch": flops,
+                        "note": "latency-bound: one workgroup per stream; flops counted: the W update's two "
+                                "k x k products per append"}
+        else:
+            if ph == 4:
+                byts = sum(4.0 * 2 * n0 * k + 8.0 * n0 for (m0, n0, k) in sel)
+            elif ph == 3:
+                byts = sum(rot_u_bytes(m0 + mid, k, 4) / max(1, min(256, int(m0 + mid) // (8 * k)))
+                           for (m0, n0, k) in sel)
+            else:
+                byts = sum(4.0 * n0 * k + 4.0 * n0 for (m0, n0, k) in sel)
+            achieved = byts / (dom_ms * 1e-3) / 1e9
+            roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                        "kernel": "%s, bucket %d" % (names[ph], kdom), "launch_ms": round(dom_ms, 4),
+                        "bytes_per_launch": int(byts)}
     tick_gbs = all_tick_bytes / (wall / K) / 1e9
     if args.calibrate_copy:
         src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)

@@ -233,13 +233,20 @@ struct isvd_engine {
     // caller's stream (the assignment depends on the bucket only, so a
     // stream's updates stay on one lane)
     hipStream_t lane_b = nullptr;
+    // first update lane (the wider buckets).  Both update lanes are the
+    // engine's own streams, created one after the other so that they land on
+    // different hardware queues whatever queue the caller's stream shares.
+    hipStream_t lane_a = nullptr;
     hipEvent_t ev_fork = nullptr;      // the tick's request upload is done
     hipEvent_t ev_b_end = nullptr;     // lane b's part of a tick is done
     std::vector<hipEvent_t> ev_core;   // per group of a tick: its core is done
-    hipEvent_t ev_main = nullptr;      // the caller-stream part of a tick is done
+    hipEvent_t ev_main = nullptr;      // lane a's part of a tick is done
     hipEvent_t ev_rot = nullptr;       // join point of the rotation lane
     hipEvent_t ev_tick_end[2] = {nullptr, nullptr};   // by tick parity
     uint64_t ticks = 0;
+    int lane_ticks = 0;                // consecutive ticks run without the rotation lanes
+    std::vector<uint64_t> seen_stamp;  // per stream id: the tick call that last named it
+    uint64_t stamp = 0;
     bool rot_pending = false;
     bool pipelining = true;            // isvd_set_pipelining
     bool defer_u = false;              // isvd_set_deferred_u
@@ -598,8 +605,9 @@ isvd_status next_event(isvd_engine* e, hipEvent_t* out) {
 
 isvd_status ensure_lanes(isvd_engine* e) {
     if (e->rot_lane) return ISVD_OK;
-    HIP_TRY(hipStreamCreateWithFlags(&e->rot_lane, hipStreamNonBlocking));
+    HIP_TRY(hipStreamCreateWithFlags(&e->lane_a, hipStreamNonBlocking));
     HIP_TRY(hipStreamCreateWithFlags(&e->lane_b, hipStreamNonBlocking));
+    HIP_TRY(hipStreamCreateWithFlags(&e->rot_lane, hipStreamNonBlocking));
     HIP_TRY(hipStreamCreateWithFlags(&e->rot_lane_b, hipStreamNonBlocking));
     HIP_TRY(hipEventCreateWithFlags(&e->ev_rot_b, hipEventDisableTiming));
     HIP_TRY(hipEventCreateWithFlags(&e->ev_fork, hipEventDisableTiming));
@@ -641,9 +649,10 @@ isvd_status launch_recorded(isvd_engine* e, const Group& g, const char* dev, int
 }
 
 // Lay out groups in a slot, upload, and launch one tick (or one immediate
-// update).  Per group, on its update lane (the caller's stream for buckets
-// of 64 and wider -- 32 and wider with deferred U --, lane b for the
-// others): the two projection passes, the
+// update).  The caller's stream uploads the requests and forks the update
+// lanes.  Per group, on its update lane (lane a for buckets of 64 and
+// wider -- 32 and wider with deferred U --, lane b for the others): the two
+// projection passes, the
 // core, then V's rotation; after the group's core, U's rotation on a
 // rotation lane (rotation lane b for the buckets below 64, the rotation lane
 // for the others, so the two overlap).
@@ -697,7 +706,12 @@ isvd_status run_groups(isvd_engine* e, std::vector<Group>& groups, hipStream_t s
         memcpy(slot->host + g.off_pru, g.pre_rotU.data(), sizeof(int) * (na + 1));
         memcpy(slot->host + g.off_prv, g.pre_rotV.data(), sizeof(int) * (na + 1));
     }
-    if (e->ticks >= 2) HIP_TRY(hipStreamWaitEvent(st, e->ev_tick_end[e->ticks & 1], 0));
+    // With deferred U the U rotations are mostly skipped and run on the
+    // group's own update lane after its V rotation; the whole tick then ends
+    // on the caller's stream (no rotation lanes, two cross-stream waits).
+    const bool own_lanes = e->defer_u;
+    if (e->ticks >= 2 && !(own_lanes && e->lane_ticks >= 2))
+        HIP_TRY(hipStreamWaitEvent(st, e->ev_tick_end[e->ticks & 1], 0));
     ST_TRY(upload_slot(slot, off, st));
     while (e->ev_core.size() < groups.size()) {
         hipEvent_t ev;
@@ -709,22 +723,44 @@ isvd_status run_groups(isvd_engine* e, std::vector<Group>& groups, hipStream_t s
     // the 32-column bucket joins the caller's stream; otherwise the U
     // rotations do, and only the widest bucket stays there.
     const int split = e->defer_u ? 32 : 64;
-    bool use_b = false, use_rb = false;
+    bool use_a = false, use_b = false, use_rb = false;
     for (const Group& g : groups) {
+        use_a = use_a || g.kc >= split;
         use_b = use_b || g.kc < split;
         use_rb = use_rb || g.kc < 64;
     }
-    if (use_b) {
-        HIP_TRY(hipEventRecord(e->ev_fork, st));
-        HIP_TRY(hipStreamWaitEvent(e->lane_b, e->ev_fork, 0));
-    }
+    HIP_TRY(hipEventRecord(e->ev_fork, st));
+    if (use_a) HIP_TRY(hipStreamWaitEvent(e->lane_a, e->ev_fork, 0));
+    if (use_b) HIP_TRY(hipStreamWaitEvent(e->lane_b, e->ev_fork, 0));
     for (size_t gi = 0; gi < groups.size(); ++gi) {
         const Group& g = groups[gi];
-        hipStream_t ln = g.kc >= split ? st : e->lane_b;
+        hipStream_t ln = g.kc >= split ? e->lane_a : e->lane_b;
         for (int phase = 0; phase < 3; ++phase) ST_TRY(launch_recorded(e, g, slot->dev, phase, ln));
-        HIP_TRY(hipEventRecord(e->ev_core[gi], ln));
+        if (!own_lanes) HIP_TRY(hipEventRecord(e->ev_core[gi], ln));
         ST_TRY(launch_recorded(e, g, slot->dev, 4, ln));
+        if (own_lanes) ST_TRY(launch_recorded(e, g, slot->dev, 3, ln));
     }
+    // the update lanes read the caller's payloads (projections, V
+    // rotations): the caller's stream passes the tick only after them, so a
+    // payload freed in that stream's order is never overwritten while read
+    if (use_a) {
+        HIP_TRY(hipEventRecord(e->ev_main, e->lane_a));
+        HIP_TRY(hipStreamWaitEvent(st, e->ev_main, 0));
+    }
+    if (use_b) {
+        HIP_TRY(hipEventRecord(e->ev_b_end, e->lane_b));
+        HIP_TRY(hipStreamWaitEvent(st, e->ev_b_end, 0));
+    }
+    if (own_lanes) {
+        HIP_TRY(hipEventRecord(slot->ev, st));
+        slot->used = true;
+        HIP_TRY(hipEventRecord(e->ev_tick_end[e->ticks & 1], st));
+        e->ticks += 1;
+        e->lane_ticks += 1;
+        if (!pipelined) ST_TRY(join(e, st));   // rotation-lane work of earlier ticks
+        return ISVD_OK;
+    }
+    e->lane_ticks = 0;
     for (size_t gi = 0; gi < groups.size(); ++gi) {
         const Group& g = groups[gi];
         hipStream_t rl = g.kc >= 64 ? e->rot_lane : e->rot_lane_b;
@@ -732,20 +768,12 @@ isvd_status run_groups(isvd_engine* e, std::vector<Group>& groups, hipStream_t s
         ST_TRY(launch_recorded(e, g, slot->dev, 3, rl));
     }
     // the tick ends on the rotation lane once every lane is through it
-    HIP_TRY(hipEventRecord(e->ev_main, st));
-    HIP_TRY(hipStreamWaitEvent(e->rot_lane, e->ev_main, 0));
+    if (use_a) HIP_TRY(hipStreamWaitEvent(e->rot_lane, e->ev_main, 0));
     if (use_rb) {
         HIP_TRY(hipEventRecord(e->ev_rot_b, e->rot_lane_b));
         HIP_TRY(hipStreamWaitEvent(e->rot_lane, e->ev_rot_b, 0));
     }
-    if (use_b) {
-        HIP_TRY(hipEventRecord(e->ev_b_end, e->lane_b));
-        HIP_TRY(hipStreamWaitEvent(e->rot_lane, e->ev_b_end, 0));
-        // lane b reads the caller's payloads (projections, V rotations): the
-        // caller's stream passes the tick only after them, so a payload freed
-        // in that stream's order is never overwritten while still being read
-        HIP_TRY(hipStreamWaitEvent(st, e->ev_b_end, 0));
-    }
+    if (use_b) HIP_TRY(hipStreamWaitEvent(e->rot_lane, e->ev_b_end, 0));
     HIP_TRY(hipEventRecord(slot->ev, e->rot_lane));
     slot->used = true;
     HIP_TRY(hipEventRecord(e->ev_tick_end[e->ticks & 1], e->rot_lane));
@@ -1752,6 +1780,7 @@ isvd_status isvd_engine_destroy(isvd_engine* e) {
     if (e->ev_fork) (void)hipEventDestroy(e->ev_fork);
     if (e->ev_b_end) (void)hipEventDestroy(e->ev_b_end);
     if (e->lane_b) (void)hipStreamDestroy(e->lane_b);
+    if (e->lane_a) (void)hipStreamDestroy(e->lane_a);
     if (e->ev_rot) (void)hipEventDestroy(e->ev_rot);
     for (hipEvent_t ev : e->ev_tick_end)
         if (ev) (void)hipEventDestroy(ev);
@@ -2488,13 +2517,14 @@ isvd_status isvd_tick(isvd_engine* e, int32_t count, const isvd_request* reqs, v
     if (!e || (count > 0 && !reqs)) return fail(ISVD_E_INVAL, "null engine or requests");
     if (count <= 0) return ISVD_OK;
     std::vector<Stream*> ss(count);
-    std::map<isvd_id, int> seen;
+    if (e->seen_stamp.size() < e->streams.size()) e->seen_stamp.resize(e->streams.size(), 0);
+    const uint64_t stamp = ++e->stamp;
     for (int q = 0; q < count; ++q) {
         const isvd_request& r = reqs[q];
         ST_TRY(get_stream(e, r.id, &ss[q]));
         Stream* s = ss[q];
-        if (seen.count(r.id)) return fail(ISVD_E_INVAL, "stream %lld appears twice in one tick", (long long)r.id);
-        seen[r.id] = q;
+        if (e->seen_stamp[r.id] == stamp) return fail(ISVD_E_INVAL, "stream %lld appears twice in one tick", (long long)r.id);
+        e->seen_stamp[r.id] = stamp;
         if (r.kind == ISVD_ROW) {
             if (r.len != s->n) return fail(ISVD_E_SHAPE, "request %d: row length %lld != n %lld", q, (long long)r.len, (long long)s->n);
             if (s->m >= s->cfg.m_cap) return fail(ISVD_E_CAPACITY, "request %d: row capacity reached", q);
