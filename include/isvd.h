@@ -283,14 +283,20 @@ isvd_status isvd_release(isvd_engine* eng, isvd_id id);
  * stream's storage dtype.  Validation happens for all requests before any
  * work is enqueued; on error nothing is applied.  Does not wait for the
  * device unless a policy needs device metrics.
- * Pipelining: the U rotations run on the engine's rotation stream.  When
+ * Lanes: hip_stream uploads the requests and forks two update lanes (the
+ * engine's own streams): the projections, cores and V rotations of the
+ * wider rank buckets run on one, the narrower ones' on the other, and
+ * hip_stream joins both before its next operation.
+ * Pipelining: the U rotations run on the engine's rotation streams.  When
  * every request is a row append of a stream without a refresh policy, they
  * may still run after hip_stream has passed the call, overlapping the next
  * tick's projections and cores; every call that reads or replaces stream
  * state (metrics, factors, matrix, refresh, single updates, a tick that
  * reads U) first orders its stream after them, and isvd_sync does so
  * explicitly.  Otherwise the tick joins them into hip_stream before
- * returning.  Every read of a payload is ordered before hip_stream's next
+ * returning.  With deferred U (isvd_set_deferred_u) each group's U rotation
+ * follows its V rotation on its update lane instead, and the whole tick
+ * ends on hip_stream.  Every read of a payload is ordered before hip_stream's next
  * operation (row payloads are not read by U rotations), so a payload may be
  * freed or overwritten in hip_stream's order as soon as the call returns.
  * Refreshes: the refreshes that a tick's policies fire (periodic, angle,
@@ -342,7 +348,8 @@ isvd_status isvd_set_deferred_u(isvd_engine* eng, int32_t enable, void* hip_stre
 
 /* The engine's rotation stream (a hipStream_t), e.g. to record an event
  * after the last tick's work: every update of a tick is done when that
- * stream has passed it (refreshes it fired may still run; see isvd_tick). */
+ * stream has passed it (refreshes it fired may still run; see isvd_tick).
+ * With deferred U a tick does not use it and ends on the caller's stream. */
 isvd_status isvd_rotation_stream(isvd_engine* eng, void** out);
 
 /* GPU time of one kernel launch of the update sequence, collected while
