@@ -237,6 +237,9 @@ struct isvd_engine {
     // engine's own streams, created one after the other so that they land on
     // different hardware queues whatever queue the caller's stream shares.
     hipStream_t lane_a = nullptr;
+    // third update lane (deferred U: the 16- and 8-column buckets)
+    hipStream_t lane_c = nullptr;
+    hipEvent_t ev_c_end = nullptr;     // lane c's part of a tick is done
     hipEvent_t ev_fork = nullptr;      // the tick's request upload is done
     hipEvent_t ev_b_end = nullptr;     // lane b's part of a tick is done
     std::vector<hipEvent_t> ev_core;   // per group of a tick: its core is done
@@ -607,7 +610,9 @@ isvd_status ensure_lanes(isvd_engine* e) {
     if (e->rot_lane) return ISVD_OK;
     HIP_TRY(hipStreamCreateWithFlags(&e->lane_a, hipStreamNonBlocking));
     HIP_TRY(hipStreamCreateWithFlags(&e->lane_b, hipStreamNonBlocking));
+    HIP_TRY(hipStreamCreateWithFlags(&e->lane_c, hipStreamNonBlocking));
     HIP_TRY(hipStreamCreateWithFlags(&e->rot_lane, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&e->ev_c_end, hipEventDisableTiming));
     HIP_TRY(hipStreamCreateWithFlags(&e->rot_lane_b, hipStreamNonBlocking));
     HIP_TRY(hipEventCreateWithFlags(&e->ev_rot_b, hipEventDisableTiming));
     HIP_TRY(hipEventCreateWithFlags(&e->ev_fork, hipEventDisableTiming));
@@ -651,8 +656,8 @@ isvd_status launch_recorded(isvd_engine* e, const Group& g, const char* dev, int
 // Lay out groups in a slot, upload, and launch one tick (or one immediate
 // update).  The caller's stream uploads the requests and forks the update
 // lanes.  Per group, on its update lane (lane a for buckets of 64 and
-// wider -- 32 and wider with deferred U --, lane b for the others): the two
-// projection passes, the
+// wider; lane b for the others, or with deferred U lane b for bucket 32 and
+// lane c for the narrower ones): the two projection passes, the
 // core, then V's rotation; after the group's core, U's rotation on a
 // rotation lane (rotation lane b for the buckets below 64, the rotation lane
 // for the others, so the two overlap).
@@ -718,23 +723,29 @@ isvd_status run_groups(isvd_engine* e, std::vector<Group>& groups, hipStream_t s
         HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
         e->ev_core.push_back(ev);
     }
-    // update lanes: buckets of `split` and wider on the caller's stream, the
-    // others on lane b.  With deferred U the cores (W updates) dominate and
-    // the 32-column bucket joins the caller's stream; otherwise the U
-    // rotations do, and only the widest bucket stays there.
-    const int split = e->defer_u ? 32 : 64;
-    bool use_a = false, use_b = false, use_rb = false;
+    // Update lanes.  Explicit U: lane a for the 64-column bucket and wider,
+    // lane b for the others (the U rotations dominate, on the rotation
+    // lanes).  Deferred U: the cores dominate, and the 64-, 32- and 16/8-column
+    // buckets get a lane each.
+    auto lane_of = [&](const Group& g) -> int {
+        if (g.kc >= 64) return 0;
+        if (!own_lanes) return 1;
+        return g.kc >= 32 ? 1 : 2;
+    };
+    hipStream_t lanes[3] = {e->lane_a, e->lane_b, e->lane_c};
+    hipEvent_t lane_end[3] = {e->ev_main, e->ev_b_end, e->ev_c_end};
+    bool used[3] = {false, false, false};
+    bool use_rb = false;
     for (const Group& g : groups) {
-        use_a = use_a || g.kc >= split;
-        use_b = use_b || g.kc < split;
+        used[lane_of(g)] = true;
         use_rb = use_rb || g.kc < 64;
     }
     HIP_TRY(hipEventRecord(e->ev_fork, st));
-    if (use_a) HIP_TRY(hipStreamWaitEvent(e->lane_a, e->ev_fork, 0));
-    if (use_b) HIP_TRY(hipStreamWaitEvent(e->lane_b, e->ev_fork, 0));
+    for (int l = 0; l < 3; ++l)
+        if (used[l]) HIP_TRY(hipStreamWaitEvent(lanes[l], e->ev_fork, 0));
     for (size_t gi = 0; gi < groups.size(); ++gi) {
         const Group& g = groups[gi];
-        hipStream_t ln = g.kc >= split ? e->lane_a : e->lane_b;
+        hipStream_t ln = lanes[lane_of(g)];
         for (int phase = 0; phase < 3; ++phase) ST_TRY(launch_recorded(e, g, slot->dev, phase, ln));
         if (!own_lanes) HIP_TRY(hipEventRecord(e->ev_core[gi], ln));
         ST_TRY(launch_recorded(e, g, slot->dev, 4, ln));
@@ -743,14 +754,11 @@ isvd_status run_groups(isvd_engine* e, std::vector<Group>& groups, hipStream_t s
     // the update lanes read the caller's payloads (projections, V
     // rotations): the caller's stream passes the tick only after them, so a
     // payload freed in that stream's order is never overwritten while read
-    if (use_a) {
-        HIP_TRY(hipEventRecord(e->ev_main, e->lane_a));
-        HIP_TRY(hipStreamWaitEvent(st, e->ev_main, 0));
-    }
-    if (use_b) {
-        HIP_TRY(hipEventRecord(e->ev_b_end, e->lane_b));
-        HIP_TRY(hipStreamWaitEvent(st, e->ev_b_end, 0));
-    }
+    for (int l = 0; l < 3; ++l)
+        if (used[l]) {
+            HIP_TRY(hipEventRecord(lane_end[l], lanes[l]));
+            HIP_TRY(hipStreamWaitEvent(st, lane_end[l], 0));
+        }
     if (own_lanes) {
         HIP_TRY(hipEventRecord(slot->ev, st));
         slot->used = true;
@@ -768,12 +776,12 @@ isvd_status run_groups(isvd_engine* e, std::vector<Group>& groups, hipStream_t s
         ST_TRY(launch_recorded(e, g, slot->dev, 3, rl));
     }
     // the tick ends on the rotation lane once every lane is through it
-    if (use_a) HIP_TRY(hipStreamWaitEvent(e->rot_lane, e->ev_main, 0));
+    for (int l = 0; l < 3; ++l)
+        if (used[l]) HIP_TRY(hipStreamWaitEvent(e->rot_lane, lane_end[l], 0));
     if (use_rb) {
         HIP_TRY(hipEventRecord(e->ev_rot_b, e->rot_lane_b));
         HIP_TRY(hipStreamWaitEvent(e->rot_lane, e->ev_rot_b, 0));
     }
-    if (use_b) HIP_TRY(hipStreamWaitEvent(e->rot_lane, e->ev_b_end, 0));
     HIP_TRY(hipEventRecord(slot->ev, e->rot_lane));
     slot->used = true;
     HIP_TRY(hipEventRecord(e->ev_tick_end[e->ticks & 1], e->rot_lane));
@@ -1781,6 +1789,8 @@ isvd_status isvd_engine_destroy(isvd_engine* e) {
     if (e->ev_b_end) (void)hipEventDestroy(e->ev_b_end);
     if (e->lane_b) (void)hipStreamDestroy(e->lane_b);
     if (e->lane_a) (void)hipStreamDestroy(e->lane_a);
+    if (e->lane_c) (void)hipStreamDestroy(e->lane_c);
+    if (e->ev_c_end) (void)hipEventDestroy(e->ev_c_end);
     if (e->ev_rot) (void)hipEventDestroy(e->ev_rot);
     for (hipEvent_t ev : e->ev_tick_end)
         if (ev) (void)hipEventDestroy(ev);
