@@ -199,6 +199,7 @@ struct Group {
     std::vector<int> pre_rotV; // ... V tiles only
     size_t off_all = 0, off_proj = 0, off_pp = 0, off_pr = 0, off_pru = 0, off_prv = 0;
     int core_lds_n = 0;
+    bool proj_alias = false;   // the projection list is the whole list (no entry update)
 };
 
 }  // namespace
@@ -693,7 +694,10 @@ isvd_status run_groups(isvd_engine* e, std::vector<Group>& groups, hipStream_t s
             g.pre_rotV[q + 1] = g.pre_rotV[q] + tv;
         }
         g.off_all = take(sizeof(Req) * na);
-        g.off_proj = take(sizeof(Req) * g.proj.size());
+        // the projection list equals the whole list when every request is an
+        // append (no entry update): then it is the same upload
+        g.proj_alias = g.proj.size() == na;
+        g.off_proj = g.proj_alias ? g.off_all : take(sizeof(Req) * g.proj.size());
         g.off_pp = take(sizeof(int) * g.pre_proj.size());
         g.off_pr = take(sizeof(int) * (na + 1));
         g.off_pru = take(sizeof(int) * (na + 1));
@@ -705,7 +709,8 @@ isvd_status run_groups(isvd_engine* e, std::vector<Group>& groups, hipStream_t s
     for (Group& g : groups) {
         const size_t na = g.all.size();
         if (na) memcpy(slot->host + g.off_all, g.all.data(), sizeof(Req) * na);
-        if (!g.proj.empty()) memcpy(slot->host + g.off_proj, g.proj.data(), sizeof(Req) * g.proj.size());
+        if (!g.proj.empty() && !g.proj_alias)
+            memcpy(slot->host + g.off_proj, g.proj.data(), sizeof(Req) * g.proj.size());
         memcpy(slot->host + g.off_pp, g.pre_proj.data(), sizeof(int) * g.pre_proj.size());
         memcpy(slot->host + g.off_pr, g.pre_rot.data(), sizeof(int) * (na + 1));
         memcpy(slot->host + g.off_pru, g.pre_rotU.data(), sizeof(int) * (na + 1));
@@ -732,16 +737,17 @@ isvd_status run_groups(isvd_engine* e, std::vector<Group>& groups, hipStream_t s
         if (!own_lanes) return 1;
         return g.kc >= 32 ? 1 : 2;
     };
-    hipStream_t lanes[3] = {e->lane_a, e->lane_b, e->lane_c};
-    hipEvent_t lane_end[3] = {e->ev_main, e->ev_b_end, e->ev_c_end};
-    bool used[3] = {false, false, false};
+    constexpr int kLanes = 3;
+    hipStream_t lanes[kLanes] = {e->lane_a, e->lane_b, e->lane_c};
+    hipEvent_t lane_end[kLanes] = {e->ev_main, e->ev_b_end, e->ev_c_end};
+    bool used[kLanes] = {false, false, false};
     bool use_rb = false;
     for (const Group& g : groups) {
         used[lane_of(g)] = true;
         use_rb = use_rb || g.kc < 64;
     }
     HIP_TRY(hipEventRecord(e->ev_fork, st));
-    for (int l = 0; l < 3; ++l)
+    for (int l = 0; l < kLanes; ++l)
         if (used[l]) HIP_TRY(hipStreamWaitEvent(lanes[l], e->ev_fork, 0));
     for (size_t gi = 0; gi < groups.size(); ++gi) {
         const Group& g = groups[gi];
@@ -754,7 +760,7 @@ isvd_status run_groups(isvd_engine* e, std::vector<Group>& groups, hipStream_t s
     // the update lanes read the caller's payloads (projections, V
     // rotations): the caller's stream passes the tick only after them, so a
     // payload freed in that stream's order is never overwritten while read
-    for (int l = 0; l < 3; ++l)
+    for (int l = 0; l < kLanes; ++l)
         if (used[l]) {
             HIP_TRY(hipEventRecord(lane_end[l], lanes[l]));
             HIP_TRY(hipStreamWaitEvent(st, lane_end[l], 0));
@@ -776,7 +782,7 @@ isvd_status run_groups(isvd_engine* e, std::vector<Group>& groups, hipStream_t s
         ST_TRY(launch_recorded(e, g, slot->dev, 3, rl));
     }
     // the tick ends on the rotation lane once every lane is through it
-    for (int l = 0; l < 3; ++l)
+    for (int l = 0; l < kLanes; ++l)
         if (used[l]) HIP_TRY(hipStreamWaitEvent(e->rot_lane, lane_end[l], 0));
     if (use_rb) {
         HIP_TRY(hipEventRecord(e->ev_rot_b, e->rot_lane_b));
