@@ -283,10 +283,12 @@ isvd_status isvd_release(isvd_engine* eng, isvd_id id);
  * stream's storage dtype.  Validation happens for all requests before any
  * work is enqueued; on error nothing is applied.  Does not wait for the
  * device unless a policy needs device metrics.
- * Lanes: hip_stream uploads the requests and forks two update lanes (the
+ * Lanes: hip_stream uploads the requests and forks the update lanes (the
  * engine's own streams): the projections, cores and V rotations of the
- * wider rank buckets run on one, the narrower ones' on the other, and
- * hip_stream joins both before its next operation.
+ * 64-column rank bucket (and wider) run on one, the narrower ones' on
+ * another -- with deferred U, the 32-column bucket on a second and the
+ * 16- and 8-column ones on a third -- and hip_stream joins them all before
+ * its next operation.
  * Pipelining: the U rotations run on the engine's rotation streams.  When
  * every request is a row append of a stream without a refresh policy, they
  * may still run after hip_stream has passed the call, overlapping the next
