@@ -166,6 +166,8 @@ __global__ void __launch_bounds__(kThreads) k_proj(const Req* __restrict__ reqs,
 // kept triplet has sigma >= 1e-4 sigma_1; it leaves V_K in J and W = K V_K.
 // One block per request; dynamic LDS = (matrices N ldw + small arrays) doubles
 // with ldw the bucket's padded column stride, N <= kMaxCore (core_lds_doubles).
+typedef double core_v4d __attribute__((ext_vector_type(4)));
+
 template <int KC>
 struct CoreShape {
     static constexpr int NMAX = (KC < kMaxCore - 1 ? KC : kMaxCore - 1) + 1;
@@ -445,39 +447,56 @@ __global__ void __launch_bounds__(CoreShape<KC>::J::NT) k_core(const Req* __rest
                     ((T*)rq.U[cur])[uvo(rq.m, j, ld)] = (T)a;
                 }
                 __syncthreads();
-                // (W A)^-1 = A^T W^-1 + b^T u0
+                // (W A)^-1 = A^T W^-1 + b^T u0 and W' = W A on the FP64 matrix
+                // cores (v_mfma_f64_16x16x4f64: lane l holds A[l%16][l/16] and
+                // B[l/16][l%16]; D[4r + l/16][l%16] is the lane's r-th value):
+                // each wave takes 16 x 16 output tiles, operands past k are zero
+                const int lane = tid & 63, wave = tid >> 6, nwave = nt >> 6;
+                const int li = lane & 15, lq = lane >> 4;
+                const int kt = (k + 15) / 16, ksteps = (k + 3) / 4;
                 double* Win = rq.Wdi[wp ^ 1];
-                for (int e = tid; e < k * k; e += nt) {
-                    const int r = e / k, j = e - (e / k) * k;
-                    const double* wr = W + (size_t)perm[r] * ldw;
-                    double t0 = 0.0, t1 = 0.0;
-                    int c = 0;
-                    for (; c + 1 < k; c += 2) {
-                        t0 += wr[c] * stg[c * lds_s + j];
-                        t1 += wr[c + 1] * stg[(c + 1) * lds_s + j];
+                for (int t = wave; t < kt * kt; t += nwave) {
+                    const int r0 = (t / kt) * 16, j0 = (t % kt) * 16;
+                    const int ra = r0 + li, jb = j0 + li;
+                    const bool rav = ra < k, jbv = jb < k;
+                    const double fa = rav ? sgn[ra] : 0.0;
+                    const double* kva = W + (size_t)(rav ? perm[ra] : 0) * ldw;
+                    core_v4d acc = {0.0, 0.0, 0.0, 0.0};
+                    for (int s4 = 0; s4 < ksteps; ++s4) {
+                        const int c = 4 * s4 + lq;
+                        const double a = (rav && c < k) ? fa * kva[c] : 0.0;          // A^T[ra][c]
+                        const double b = (jbv && c < k) ? stg[c * lds_s + jb] : 0.0;  // W^-1[c][jb]
+                        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
                     }
-                    if (c < k) t0 += wr[c] * stg[c * lds_s + j];
-                    Win[(size_t)r * KC + j] = sgn[r] * (t0 + t1) + (sgn[r] * wr[k]) * dcol[j];
+                    for (int r = 0; r < 4; ++r) {
+                        const int row = r0 + 4 * r + lq;
+                        if (row < k && jbv) {
+                            const double br = sgn[row] * W[(size_t)perm[row] * ldw + k];
+                            Win[(size_t)row * KC + jb] = acc[r] + br * dcol[jb];
+                        }
+                    }
                 }
                 __syncthreads();
-                // W' = W A
                 stage(Wo);
                 __syncthreads();
-                // adjacent lanes take adjacent rows r: Kv[perm_j] is read as a
-                // broadcast and the staged rows at the odd stride k + 1
                 double* Wn = rq.Wd[wp ^ 1];
-                for (int e = tid; e < k * k; e += nt) {
-                    const int j = e / k, r = e - (e / k) * k;
-                    const double* wj = W + (size_t)perm[j] * ldw;
-                    const double* sr = stg + r * lds_s;
-                    double a0 = 0.0, a1 = 0.0;
-                    int c = 0;
-                    for (; c + 1 < k; c += 2) {
-                        a0 += sr[c] * wj[c];
-                        a1 += sr[c + 1] * wj[c + 1];
+                for (int t = wave; t < kt * kt; t += nwave) {
+                    const int r0 = (t / kt) * 16, j0 = (t % kt) * 16;
+                    const int ra = r0 + li, jb = j0 + li;
+                    const bool rav = ra < k, jbv = jb < k;
+                    const double fb = jbv ? sgn[jb] : 0.0;
+                    const double* kvb = W + (size_t)(jbv ? perm[jb] : 0) * ldw;
+                    core_v4d acc = {0.0, 0.0, 0.0, 0.0};
+                    for (int s4 = 0; s4 < ksteps; ++s4) {
+                        const int c = 4 * s4 + lq;
+                        const double a = (rav && c < k) ? stg[ra * lds_s + c] : 0.0;  // W[ra][c]
+                        const double b = (jbv && c < k) ? fb * kvb[c] : 0.0;          // A[c][jb]
+                        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
                     }
-                    if (c < k) a0 += sr[c] * wj[c];
-                    Wn[(size_t)r * KC + j] = sgn[j] * (a0 + a1);
+                    for (int r = 0; r < 4; ++r) {
+                        const int row = r0 + 4 * r + lq;
+                        if (row < k && jbv) Wn[(size_t)row * KC + jb] = acc[r];
+                    }
                 }
             } else {
                 // explicit: U's rotation takes W A, and W, W^-1 return to I
