@@ -19,7 +19,7 @@ from .svd import truncated_svd, singular_values
 
 
 class OracleEngine:
-    def __init__(self, A0, k, tol_rel=1e-10, policy=None, cgs2=False):
+    def __init__(self, A0, k, tol_rel=1e-10, policy=None, cgs2=False, drift=False):
         self.A = np.array(A0, dtype=np.float64, copy=True)
         self.k = int(k)
         self.policy = policy or Policy()
@@ -35,9 +35,16 @@ class OracleEngine:
         self.grow_pending = False
         self.last_novelty = float("nan")
         self.refresh_ticks = []
+        self._init_drift(drift)
+
+    def _init_drift(self, drift):
+        # drift signals of the last update (Sections 3.2-3.3), formed when asked for
+        self.drift = bool(drift)
+        self.last_step_angle_U = self.last_step_angle_V = float("nan")
+        self.last_spectrum_change = float("nan")
 
     @classmethod
-    def from_state(cls, A, U, s, V, tol_rel=1e-10, policy=None, cgs2=False):
+    def from_state(cls, A, U, s, V, tol_rel=1e-10, policy=None, cgs2=False, drift=False):
         """Start from a given state (A_t, U, Sigma, V) instead of TruncatedSVD(A_0, k)."""
         eng = cls.__new__(cls)
         eng.A = np.array(A, dtype=np.float64, copy=True)
@@ -55,6 +62,7 @@ class OracleEngine:
         eng.grow_pending = False
         eng.last_novelty = float("nan")
         eng.refresh_ticks = []
+        eng._init_drift(drift)
         return eng
 
     # ----------------------------------------------------------------- state
@@ -79,6 +87,7 @@ class OracleEngine:
         """One Brand update (no policy)."""
         self.t += 1
         novelty = float("nan")
+        U0, s0, V0 = self.U, self.s, self.V
         if ev.kind == ROW:
             x = np.asarray(ev.vec, dtype=np.float64)
             self.A = np.vstack([self.A, x[None, :]])
@@ -104,6 +113,12 @@ class OracleEngine:
             self.k = len(self.s)
             self.grow_pending = False
         self.last_novelty = novelty
+        if self.drift:
+            # largest principal angles between the previous spans (zero-padded
+            # to the new rows) and the new ones; the spectrum's relative change
+            self.last_step_angle_U = metrics.theta_max(U0, self.U)
+            self.last_step_angle_V = metrics.theta_max(V0, self.V)
+            self.last_spectrum_change = metrics.spectrum_change(s0, self.s)
 
     def decide(self, ev_kind):
         """Evaluate the policy after the update at tick t; may change k."""

@@ -15,6 +15,9 @@
   weight of about sqrt(rows added / rows) outside the zero-padded reference
   however little the subspace turned, so the padded angle measures growth,
   not drift; on the reference rows it measures drift alone.
+* drift signals that need no A (the surrogates of Sections 3.2-3.3): the
+  step angles theta_max(U_{t-1}, U_t), theta_max(V_{t-1}, V_t) of one
+  update, and spectrum_change = ||sigma_t - sigma_{t-1}|| / ||sigma_{t-1}||.
 * the default angle scope is the leading gap-separated subspace: the j < k
   with the largest relative gap (s_j - s_{j+1}) / s_j, if that gap is at
   least 5%, else all k columns.
@@ -81,6 +84,19 @@ def theta_max(Q1, Q2):
         smax = float(svd(R)[1].max()) if R.size else 0.0
         theta = float(np.arcsin(min(smax, 1.0)))
     return theta
+
+
+def spectrum_change(s_prev, s_new):
+    """||sigma_t - sigma_{t-1}||_2 / ||sigma_{t-1}||_2, the shorter vector
+    zero-padded: the spectrum-change surrogate of the error-based refresh
+    (Section 3.2).  NaN when sigma_{t-1} is zero."""
+    n = max(len(s_prev), len(s_new))
+    a = np.zeros(n)
+    b = np.zeros(n)
+    a[:len(s_prev)] = s_prev
+    b[:len(s_new)] = s_new
+    den = float(np.linalg.norm(a))
+    return float(np.linalg.norm(b - a)) / den if den > 0.0 else float("nan")
 
 
 def theta_ref(U_ref, U_t):
