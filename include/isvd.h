@@ -145,6 +145,17 @@ typedef struct {
                                angle scope (Section 2.4.2); tracked every update for
                                ISVD_POL_ANGLE streams, formed directly with compute_exact,
                                else NaN */
+    /* Drift signals of the last applied update, formed by the update itself
+       without reading A (the cheap surrogates of the error- and angle-based
+       refresh, Sections 3.2-3.3; NaN before the first update):
+       step_angle_U: largest principal angle, radians, between span(U_{t-1})
+                     (zero-padded to the new rows) and span(U_t); 0 when the
+                     rank grew (the new span contains the old) and for entry
+                     updates (both spans are kept);
+       step_angle_V: the same for V;
+       spectrum_change: ||sigma_t - sigma_{t-1}||_2 / ||sigma_{t-1}||_2, the
+                     shorter vector zero-padded (NaN if sigma_{t-1} = 0). */
+    double step_angle_U, step_angle_V, spectrum_change;
 } isvd_metrics_t;
 
 /* One request of a batched tick. */

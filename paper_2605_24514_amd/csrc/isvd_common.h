@@ -68,6 +68,11 @@ struct DevHeader {
     int32_t wpar;         // deferred U: which of the two W / W^-1 buffers is current
     int64_t ref_m;        // its rows
     double angle_ref;     // theta_ref (angle-threshold streams), radians
+    // drift signals of the last applied update (no access to A needed):
+    // largest principal angle between the previous and the new span of U
+    // (the previous one zero-padded to the new rows), the same for V, and
+    // ||sigma_t - sigma_{t-1}||_2 / ||sigma_{t-1}||_2 (zero-padded)
+    double step_angle_u, step_angle_v, spec_change;
 };
 
 // Written by the core kernel of a request, read by its rotation kernel.

@@ -2288,6 +2288,9 @@ isvd_status isvd_metrics(isvd_engine* e, isvd_id id, int32_t compute_exact, void
     m.evr = h.N > 0.0 ? s2 / h.N : nan;
     m.rho = h.rho;
     m.novelty = h.novelty;
+    m.step_angle_U = h.t > 0 ? h.step_angle_u : nan;
+    m.step_angle_V = h.t > 0 ? h.step_angle_v : nan;
+    m.spectrum_change = h.t > 0 ? h.spec_change : nan;
     m.frob_error = m.frob_opt = m.frob_gap = m.frob_ratio = nan;
     m.ortho_U = m.ortho_V = nan;
     m.angle_ref = s->angle ? h.angle_ref : nan;

@@ -358,6 +358,30 @@ __global__ void __launch_bounds__(CoreShape<KC>::J::NT) k_core(const Req* __rest
         while (kout > 0 && sig[kout - 1] == 0.0) --kout;
     }
     const int ldo = round4(kout);
+    // Drift signals (Sections 3.2-3.3): U_K, V_K have orthonormal columns, so the
+    // cosines of the principal angles between the previous span (zero-padded)
+    // and the new one are the singular values of the rotation's first k rows,
+    // and for kout <= k the smallest is sqrt(1 - |last row|^2).  A grown rank
+    // contains the previous span; a rank-one update keeps both spans.  For a
+    // column append U's rotation is V_K and V's is U_K.  Wave 0 reduces; tid 0
+    // keeps the squared sines.
+    double sin2_u = 0.0, sin2_v = 0.0;
+    if (kind != kEntry && kout <= k && tid < 64) {
+        double bu = 0.0, bv = 0.0;
+        for (int j = tid; j < kout; j += 64) {
+            const int c = perm[j];
+            const double uk = sig[j] > 0.0 ? W[(size_t)c * ldw + k] / sig[j] : 0.0;
+            const double vk = vraw(k, c);
+            bu += uk * uk;
+            bv += vk * vk;
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            bu += __shfl_xor(bu, o);
+            bv += __shfl_xor(bv, o);
+        }
+        sin2_u = kind == kRow ? bu : bv;
+        sin2_v = kind == kRow ? bv : bu;
+    }
     T* QU = (T*)rq.QU;
     T* QV = (T*)rq.QV;
     // Deferred U (U = U0 W, Brand): a row append whose rank stays k and whose
@@ -548,9 +572,18 @@ __global__ void __launch_bounds__(CoreShape<KC>::J::NT) k_core(const Req* __rest
         hdr->N += dN;
         hdr->sweeps = sweeps;
         hdr->last_kind = kind;
-        double s2 = 0.0;
-        for (int j = 0; j < kout; ++j) s2 += sig[j] * sig[j];
+        double s2 = 0.0, ds = 0.0, so = 0.0;
+        const int kmax = kout > k ? kout : k;
+        for (int j = 0; j < kmax; ++j) {
+            const double sn = j < kout ? sig[j] : 0.0, sv = j < k ? sS[j] : 0.0;
+            s2 += sn * sn;
+            ds += (sn - sv) * (sn - sv);
+            so += sv * sv;
+        }
         hdr->sigma2 = s2;
+        hdr->step_angle_u = asin(sqrt(fmin(sin2_u, 1.0)));
+        hdr->step_angle_v = asin(sqrt(fmin(sin2_v, 1.0)));
+        hdr->spec_change = so > 0.0 ? sqrt(ds / so) : __builtin_nan("");
         hdr->sigma_last = kout > 0 ? sig[kout - 1] : 0.0;
         if (kind != kEntry) {
             hdr->rho = rho;

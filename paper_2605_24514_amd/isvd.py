@@ -51,7 +51,8 @@ class CMetrics(ctypes.Structure):
                 ("sweeps", ctypes.c_int32), ("new_direction", ctypes.c_int32)] + [
         (f, ctypes.c_double) for f in ("fro2_A", "sigma2_sum", "evr", "rho", "novelty", "frob_error",
                                        "frob_opt", "frob_gap", "frob_ratio", "ortho_U", "ortho_V",
-                                       "update_time_us", "opt_time_us", "angle_ref")]
+                                       "update_time_us", "opt_time_us", "angle_ref", "step_angle_U",
+                                       "step_angle_V", "spectrum_change")]
 
 
 class CRequest(ctypes.Structure):
