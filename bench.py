@@ -68,27 +68,36 @@ def tick_bytes(m, n, k, esz, deferred=False):
     return full - rot_u_bytes(m, k, esz) + rot_u_bytes(m, k, esz) / period
 
 
-PMC_RECORD = os.path.join(ROOT, "profiles", "rotate_u_kc64_tick512_pmc.md")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2605_24514_amd", "csrc", f) for f in ("isvd_common.h", "isvd_update.h")]
+CSRC = os.path.join(ROOT, "paper_2605_24514_amd", "csrc")
+PMC_ROTATE = (os.path.join(ROOT, "profiles", "rotate_u_kc64_tick512_pmc.md"),
+              [os.path.join(CSRC, f) for f in ("isvd_common.h", "isvd_update.h")])
+PMC_CORE = (os.path.join(ROOT, "profiles", "core_kc64_tick512_pmc.md"),
+            [os.path.join(CSRC, f) for f in ("isvd_common.h", "isvd_update.h", "isvd_secular.h", "isvd_jacobi.h")])
 
 
-def recorded_traffic_ratio(variant):
-    """HBM traffic / algorithmic bytes of the dominant kernel in rotation block
-    shape `variant`, from the committed counter record, or None once the kernel
-    sources differ from the profiled ones."""
+def core_bytes(k):
+    # deferred row append in the core: W and W^-1 (k x k, FP64) read and
+    # written, V's (k + 1) x k FP32 rotation written
+    return 32.0 * k * k + 4.0 * k * (k + 1)
+
+
+def recorded_traffic_ratio(record, key):
+    """HBM traffic / algorithmic bytes under `key` in a committed counter
+    record, or None once the kernel sources differ from the profiled ones."""
     import hashlib
+    path, sources = record
     try:
-        text = open(PMC_RECORD).read()
+        text = open(path).read()
     except OSError:
         return None
     ratio = sha = None
     for line in text.splitlines():
-        if line.startswith("traffic_over_algorithmic_variant_%d:" % variant):
+        if line.startswith(key + ":"):
             ratio = float(line.split(":")[1])
         if line.startswith("kernel_source_sha256:"):
             sha = line.split(":")[1].strip()
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in sources:
         h.update(open(f, "rb").read())
     return ratio if (ratio is not None and sha == h.hexdigest()) else None
 
@@ -544,7 +553,8 @@ def main():
         dom_ms = float(np.mean(by_launch[(3, kdom)]))
         dom_bytes = sum(rot_u_bytes(m0 + mid, k, 4) for (m0, n0, k) in params if bucket(k) == kdom)
         achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
-        dom_ratio = recorded_traffic_ratio(tune[kdom][0]) if kdom in tune else None
+        dom_ratio = (recorded_traffic_ratio(PMC_ROTATE, "traffic_over_algorithmic_variant_%d" % tune[kdom][0])
+                     if kdom in tune else None)
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4),
                     "traffic": (int(dom_ratio * dom_bytes) if dom_ratio is not None and kdom == 64 else None),
@@ -564,10 +574,15 @@ def main():
         if ph == 2:
             flops = sum(4.0 * k ** 3 for (m0, n0, k) in sel)
             achieved = flops / (dom_ms * 1e-3) / 1e12
+            cbytes = sum(core_bytes(k) for (m0, n0, k) in sel)
+            cratio = recorded_traffic_ratio(PMC_CORE, "traffic_over_algorithmic") if kdom == 64 else None
             roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                        "frac": round(achieved / FP64_PEAK_TFLOPS, 5), "traffic": None,
+                        "frac": round(achieved / FP64_PEAK_TFLOPS, 5),
+                        "traffic": int(cratio * cbytes) if cratio is not None else None,
+                        "traffic_note": "HBM bytes per launch: rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated, "
+                                        "ratio to algorithmic bytes from profiles/core_kc64_tick512_pmc.md",
                         "kernel": "k_core<float, %d> (append core: secular SVD + deferred-U update, FP64)" % kdom,
-                        "launch_ms": round(dom_ms, 4), "flops_per_launch": flops,
+                        "launch_ms": round(dom_ms, 4), "flops_per_launch": flops, "bytes_per_launch": int(cbytes),
                         "note": "latency-bound: one workgroup per stream; flops counted: the W update's two "
                                 "k x k products per append"}
         else:
