@@ -392,11 +392,7 @@ __global__ void __launch_bounds__(CoreShape<KC>::J::NT) k_core(const Req* __rest
         wd = kind == kRow && rq.Wd[0] != nullptr;
         if (wd) {
             if (tid == 0) {
-                double bb = 0.0;
-                for (int j = 0; j < kout; ++j) {
-                    const double b = sig[j] > 0.0 ? sgn[j] * W[(size_t)perm[j] * ldw + k] / sig[j] : 0.0;
-                    bb += b * b;
-                }
+                const double bb = sin2_u;   // |b|^2: the last row of U_K, reduced by wave 0 above
                 s_i[2] = (rq.defer && kout == k && ldo == ld && bb <= 0.5) ? 1 : 0;
                 s_sc[4] = bb;
             }
@@ -443,8 +439,26 @@ __global__ void __launch_bounds__(CoreShape<KC>::J::NT) k_core(const Req* __rest
             const int lds_s = k + 1;
             __syncthreads();
             for (int j = tid; j < kout; j += nt) sgn[j] = sgn[j] / sig[j];
+            // deferred streams have KC <= 64: all of a thread's loads are
+            // issued before its LDS stores
+            constexpr int NTB = CoreShape<KC>::J::NT;
+            constexpr int SIT = (KC * KC + NTB - 1) / NTB;
             auto stage = [&](const double* src) {
-                for (int e = tid; e < k * k; e += nt) stg[(e / k) * lds_s + e % k] = src[(size_t)(e / k) * KC + e % k];
+                if constexpr (KC <= 64) {
+                    double v[SIT];
+#pragma unroll
+                    for (int q = 0; q < SIT; ++q) {
+                        const int e = tid + q * NTB;
+                        v[q] = e < k * k ? src[(size_t)(e / k) * KC + e % k] : 0.0;
+                    }
+#pragma unroll
+                    for (int q = 0; q < SIT; ++q) {
+                        const int e = tid + q * NTB;
+                        if (e < k * k) stg[(e / k) * lds_s + e % k] = v[q];
+                    }
+                } else {
+                    for (int e = tid; e < k * k; e += nt) stg[(e / k) * lds_s + e % k] = src[(size_t)(e / k) * KC + e % k];
+                }
             };
             if (defer) {
                 const double bb = s_sc[4];
@@ -477,7 +491,7 @@ __global__ void __launch_bounds__(CoreShape<KC>::J::NT) k_core(const Req* __rest
                 // each wave takes 16 x 16 output tiles, operands past k are zero
                 const int lane = tid & 63, wave = tid >> 6, nwave = nt >> 6;
                 const int li = lane & 15, lq = lane >> 4;
-                const int kt = (k + 15) / 16, ksteps = (k + 3) / 4;
+                const int kt = (k + 15) / 16;
                 double* Win = rq.Wdi[wp ^ 1];
                 for (int t = wave; t < kt * kt; t += nwave) {
                     const int r0 = (t / kt) * 16, j0 = (t % kt) * 16;
@@ -486,7 +500,8 @@ __global__ void __launch_bounds__(CoreShape<KC>::J::NT) k_core(const Req* __rest
                     const double fa = rav ? sgn[ra] : 0.0;
                     const double* kva = W + (size_t)(rav ? perm[ra] : 0) * ldw;
                     core_v4d acc = {0.0, 0.0, 0.0, 0.0};
-                    for (int s4 = 0; s4 < ksteps; ++s4) {
+#pragma unroll
+                    for (int s4 = 0; s4 < KC / 4; ++s4) {   // steps past k read zeros
                         const int c = 4 * s4 + lq;
                         const double a = (rav && c < k) ? fa * kva[c] : 0.0;          // A^T[ra][c]
                         const double b = (jbv && c < k) ? stg[c * lds_s + jb] : 0.0;  // W^-1[c][jb]
@@ -511,7 +526,8 @@ __global__ void __launch_bounds__(CoreShape<KC>::J::NT) k_core(const Req* __rest
                     const double fb = jbv ? sgn[jb] : 0.0;
                     const double* kvb = W + (size_t)(jbv ? perm[jb] : 0) * ldw;
                     core_v4d acc = {0.0, 0.0, 0.0, 0.0};
-                    for (int s4 = 0; s4 < ksteps; ++s4) {
+#pragma unroll
+                    for (int s4 = 0; s4 < KC / 4; ++s4) {   // steps past k read zeros
                         const int c = 4 * s4 + lq;
                         const double a = (rav && c < k) ? stg[ra * lds_s + c] : 0.0;  // W[ra][c]
                         const double b = (jbv && c < k) ? fb * kvb[c] : 0.0;          // A[c][jb]
@@ -544,6 +560,22 @@ __global__ void __launch_bounds__(CoreShape<KC>::J::NT) k_core(const Req* __rest
             }
         }
     }
+    // sums over the kept / previous spectrum, reduced by wave 0
+    double s2 = 0.0, ds = 0.0, so = 0.0;
+    if (tid < 64) {
+        const int kmax = kout > k ? kout : k;
+        for (int j = tid; j < kmax; j += 64) {
+            const double sn = j < kout ? sig[j] : 0.0, sv = j < k ? sS[j] : 0.0;
+            s2 += sn * sn;
+            ds += (sn - sv) * (sn - sv);
+            so += sv * sv;
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            s2 += __shfl_xor(s2, o);
+            ds += __shfl_xor(ds, o);
+            so += __shfl_xor(so, o);
+        }
+    }
     if (tid == 0) {
         double dN = 0.0;
         if (kind == kEntry) {
@@ -572,14 +604,6 @@ __global__ void __launch_bounds__(CoreShape<KC>::J::NT) k_core(const Req* __rest
         hdr->N += dN;
         hdr->sweeps = sweeps;
         hdr->last_kind = kind;
-        double s2 = 0.0, ds = 0.0, so = 0.0;
-        const int kmax = kout > k ? kout : k;
-        for (int j = 0; j < kmax; ++j) {
-            const double sn = j < kout ? sig[j] : 0.0, sv = j < k ? sS[j] : 0.0;
-            s2 += sn * sn;
-            ds += (sn - sv) * (sn - sv);
-            so += sv * sv;
-        }
         hdr->sigma2 = s2;
         hdr->step_angle_u = asin(sqrt(fmin(sin2_u, 1.0)));
         hdr->step_angle_v = asin(sqrt(fmin(sin2_v, 1.0)));
