@@ -1,0 +1,71 @@
+"""The synthetic experiments of Section 4 through the engine (FP64 storage),
+checkpoint by checkpoint against the FP64 oracle, and the same sanity bands
+as the oracle's (E1 drift near 1.12 without refresh and a sawtooth with a
+refresh every 1000 updates, E2 ratio rising with k on the noisy matrix, E3
+within 1.0-1.02 with a refresh every 50).  Bar: |ratio_gpu - ratio_oracle| <= 1e-6 at every
+checkpoint (both FP64; the refresh blocks span all columns, so both refreshes
+are exact)."""
+import numpy as np
+import pytest
+
+from oracle.engine import OracleEngine
+from oracle.policies import Policy
+from synth import ROW, COL
+from tests.experiments import E1_CHECK, e1_stream, e3_stream
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def isvd():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2605_24514_amd import isvd as mod
+    return mod
+
+
+def _run(isvd, A0, k, events, period, every, oversample=64):
+    o = OracleEngine(A0, k, policy=Policy.periodic(period) if period else None)
+    pol = isvd.Policy(kind=isvd.POL_PERIODIC, period=period) if period else None
+    m, n = A0.shape
+    rows = sum(ev.kind == ROW for ev in events)
+    cols = sum(ev.kind == COL for ev in events)
+    got, want = [], []
+    with isvd.Engine() as eng:
+        kw = {"policy": pol} if pol is not None else {}
+        sid = eng.init(A0, k, "fp64", m_cap=m + rows, n_cap=n + cols, oversample=oversample, **kw)
+        for q, ev in enumerate(events):
+            if ev.kind == ROW:
+                eng.append_row(sid, ev.vec)
+            elif ev.kind == COL:
+                eng.append_col(sid, ev.vec)
+            else:
+                eng.update_entry(sid, ev.i, ev.j, ev.delta)
+            o.step(ev)
+            if (q + 1) % every == 0:
+                got.append(eng.metrics(sid, exact=True)["frob_ratio"])
+                want.append(o.exact_metrics()["frob_ratio"])
+    got, want = np.array(got), np.array(want)
+    assert np.abs(got - want).max() <= 1e-6, (got, want)
+    return got
+
+
+def test_e1_e2(isvd):
+    A0, ev = e1_stream()
+    none = _run(isvd, A0, 5, ev, 0, E1_CHECK)
+    saw = _run(isvd, A0, 5, ev, 1000, E1_CHECK)
+    assert 1.05 <= none[-1] <= 1.2 and none.max() <= 1.25
+    assert np.all(np.abs(saw[(1000 // E1_CHECK) - 1::1000 // E1_CHECK] - 1.0) <= 1e-9)
+    assert saw.mean() < none.mean()
+    A2, ev2 = e1_stream(4000, noise=0.1)
+    ends = [_run(isvd, A2, k, ev2, 0, len(ev2))[-1] for k in (5, 8, 12)]
+    assert ends[0] < ends[1] < ends[2]
+    print("E1 none end %.4f, refresh-1000 mean %.4f; E2 k=5/8/12 ends %s" % (none[-1], saw.mean(), np.round(ends, 4)))
+
+
+def test_e3(isvd):
+    A0, ev = e3_stream()
+    r = _run(isvd, A0, 4, ev, 50, 10, oversample=92)
+    assert np.all((r >= 1.0 - 1e-9) & (r <= 1.02))
+    print("E3 ratios", np.round(r, 4))
