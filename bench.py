@@ -259,7 +259,8 @@ def refresh_main(args):
     from paper_2605_24514_amd import isvd
     from synth import device as sdev
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    m, n, k, iters = 100000, 2000, 64, args.refresh_iters
+    m, n, k = 100000, 2000, 64
+    iters = -1 if args.refresh_iters is None else args.refresh_iters
     st = torch.cuda.Stream()
     A0 = torch.empty((m, n), dtype=torch.float32, device="cuda")
     sdev.rows_into(A0, 0, m, n, SEED, 0, 20)
@@ -279,16 +280,27 @@ def refresh_main(args):
             ts.append(e0.elapsed_time(e1))
         met = eng.metrics(sid, exact=True, stream=st)
     b = min(n, k + max(8, k // 2), 96)
-    gemm_flop = 2.0 * m * n * b * (2 * iters + 1)      # iters x (A X, A^T Q) + final A X
     ms = float(np.median(ts))
+    if iters < 0:
+        form = ("Gram form: G = A^T A on the FP64 matrix cores, Chebyshev-filtered subspace iteration with "
+                "locking until every leading Ritz residual <= 1e-10 theta_1, block b = %d, then A L, CholQR2, "
+                "FP64 Rayleigh-Ritz" % b)
+        gram_flop = 1.0 * m * n * (n + 64)      # the upper 64 x 64 tiles of A^T A, 2 flops per product
+        extra = {"gram_tflops_equivalent": round(gram_flop / (ms * 1e-3) / 1e12, 1),
+                 "refresh_rounds": met["refresh_rounds"], "refresh_converged": met["refresh_converged"]}
+    else:
+        form = ("A form: block b = %d, %d subspace iterations, CholQR2 / FP64 Gram, FP64 Rayleigh-Ritz"
+                % (b, iters))
+        gemm_flop = 2.0 * m * n * b * (2 * iters + 1)      # iters x (A X, A^T Q) + final A X
+        extra = {"gemm_equivalent_tflops": round(gemm_flop / (ms * 1e-3) / 1e12, 1)}
     out = {"metric": "refresh time: TruncatedSVD(A_t, k) of one stream", "value": round(ms, 3), "unit": "ms",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": False, "dtype": "f32",
            "data": "synthetic",
-           "config": {"workload": "one factor-model stream, A 100000 x 2000 FP32 (20 factors), k = 64, block "
-                                  "b = %d, %d subspace iterations, CholQR2 / FP64 Gram, FP64 Rayleigh-Ritz" % (b, iters)},
+           "config": {"workload": "one factor-model stream, A 100000 x 2000 FP32 (20 factors), k = 64, " + form},
            "ms_min": round(min(ts), 3), "ms_p99": round(pctl(ts, 99), 3),
-           "gemm_equivalent_tflops": round(gemm_flop / (ms * 1e-3) / 1e12, 1),
-           "frob_ratio": met["frob_ratio"], "ortho_U": met["ortho_U"], "ortho_V": met["ortho_V"]}
+           "frob_ratio": met["frob_ratio"], "frob_opt": met["frob_opt"], "ortho_U": met["ortho_U"],
+           "ortho_V": met["ortho_V"]}
+    out.update(extra)
     print(json.dumps(out), flush=True)
 
 
@@ -375,7 +387,9 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--streams", type=int, default=512)
-    ap.add_argument("--refresh-iters", type=int, default=2)
+    ap.add_argument("--refresh-iters", type=int, default=None,
+                    help="subspace iterations of the A-form refresh (default: the Gram form with its stopping "
+                         "rule in --refresh mode, 2 for the initial SVDs of the tick workload)")
     ap.add_argument("--compare-streams", type=int, default=32)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -432,7 +446,7 @@ def main():
         for s, (m0, n0, k) in enumerate(params):
             A0 = tmp[:m0 * n0].view(m0, n0)
             sdev.rows_into(A0, 0, m0, n0, SEED, s, K_FACTORS, hip_stream=sp)
-            sid64.append(eng64.init(A0, k, "fp64", m_cap=m0 + T, n_cap=n0, refresh_iters=args.refresh_iters,
+            sid64.append(eng64.init(A0, k, "fp64", m_cap=m0 + T, n_cap=n0, refresh_iters=2 if args.refresh_iters is None else args.refresh_iters,
                                     stream=dev_stream))
             U, S, V = eng64.factors(sid64[-1], stream=dev_stream)
             sid32.append(eng32.init_from_factors(A0, U, S, V, "fp32", m_cap=m0 + T + PROF_TICKS, n_cap=n0,

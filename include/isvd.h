@@ -118,9 +118,15 @@ typedef struct {
     int32_t k;              /* target rank, 1 <= k <= min(m0, n0, 96) */
     int32_t precision;      /* ISVD_FP64 / ISVD_FP32 / ISVD_BF16ROT */
     double tol_rel;         /* new direction iff rho > tol_rel * ||x|| (0 = 1e-10 FP64, 1e-5 FP32) */
-    int32_t refresh_iters;  /* subspace iterations per refresh (-1 = default) */
+    int32_t refresh_iters;  /* -1 (default): a stream of at most 4096 columns refreshes in Gram form
+                               until every leading Ritz pair meets refresh_tol (a stopping rule);
+                               wider streams, and any value >= 0, run that many block subspace
+                               iterations on A (8 at init, 3 otherwise when -1) */
     int32_t oversample;     /* refresh block size = min(n, k + oversample) (-1 = default) */
     isvd_policy policy;
+    double refresh_tol;     /* Gram-form stopping rule: Ritz residual ||G v - theta v|| <= refresh_tol
+                               * theta_1 for the leading k pairs, G = A^T A (0 = 2e-14 FP64, 1e-10
+                               otherwise) */
 } isvd_config;
 
 typedef struct {
@@ -135,7 +141,8 @@ typedef struct {
     double evr;             /* eq. evr */
     double rho, novelty;    /* last append: ||z|| and ||z|| / ||x|| */
     double frob_error;      /* E_inc = ||A_t - U S V^T||_F      (NaN unless compute_exact) */
-    double frob_opt;        /* E_opt from the refresh's Ritz values (NaN unless compute_exact) */
+    double frob_opt;        /* E_opt = sqrt(N_t - sum of the refresh's k leading Ritz values sigma^2) (NaN
+                               unless compute_exact) */
     double frob_gap, frob_ratio;   /* eq. frob-ratio; NaN if undefined or not computed */
     double ortho_U, ortho_V;       /* ||Q^T Q - I||_2 (NaN unless compute_exact) */
     double update_time_us;  /* wall-clock of the last immediate-mode update (host-timed) */
@@ -156,6 +163,10 @@ typedef struct {
        spectrum_change: ||sigma_t - sigma_{t-1}||_2 / ||sigma_{t-1}||_2, the
                      shorter vector zero-padded (NaN if sigma_{t-1} = 0). */
     double step_angle_U, step_angle_V, spectrum_change;
+    /* Last refresh (or initial SVD): Rayleigh-Ritz rounds of the Gram form (0 for the
+       A form), and 1 if the stopping rule held (always 1 for the A form, whose
+       iteration count is fixed). */
+    int32_t refresh_rounds, refresh_converged;
 } isvd_metrics_t;
 
 /* One request of a batched tick. */

@@ -29,6 +29,7 @@
 #include "isvd_common.h"
 #include "isvd_update.h"
 #include "isvd_refresh.h"
+#include "isvd_gcf.h"
 #include "isvd_track.h"
 #include "isvd_finance.h"
 
@@ -131,6 +132,8 @@ struct Stream {
     bool grow_pending = false;   // adaptive rank: the next append keeps one more triplet
     bool angle = false;          // angle-threshold policy: trackers follow every update
     double last_ratio = 0.0;     // error policy: frob_ratio at its last check
+    int refresh_rounds = 0;      // last refresh: Gram-form rounds (0: A form)
+    bool refresh_converged = true;
 };
 
 // Leading dimension of A: n_cap rounded up to a multiple of 4, so that rows
@@ -1051,7 +1054,298 @@ struct RefreshPlan {
     int k = 0, b = 0, ldo = 0, cur = 0;
     int64_t m = 0, n = 0;
     WsLayout w{};
+    int rounds = 0;          // Gram form: Rayleigh-Ritz rounds until the stopping rule held
+    bool converged = true;   // Gram form: all k Ritz pairs met the residual tolerance
+    // Gram form: sum of the leading k Ritz values of G = A^T A (sigma^2, from
+    // exact FP64 products; E_opt^2 = ||A||^2 minus it), else NaN
+    double gram_top = std::nan("");
 };
+
+// Workspace of the Gram-form refresh, placed after the A-form layout of
+// its final step (block = k).
+struct GcfLayout {
+    size_t G, Gp, X, Xn, W, Wn, Y0, Y1, Y2, L, Hp, C, H, R, Rinv, P, PU, sig, theta, res, flag, sweeps, total;
+    int ldg = 0, nchunk = 1, nxty = 1;
+};
+
+GcfLayout gcf_layout(int64_t m, int64_t n, size_t base) {
+    GcfLayout g{};
+    size_t off = align_up(base, 256);
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align_up(off + bytes, 256);
+        return o;
+    };
+    g.ldg = (int)round64(n);
+    const int ntile = ata_tiles(n);
+    g.nchunk = (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(1024, ntile), cdiv(m, 256)));
+    g.nxty = (int)cdiv(g.ldg, 256);
+    const size_t blk = sizeof(double) * (size_t)g.ldg * kMaxBlock;
+    const size_t sq = sizeof(double) * kMaxBlock * kMaxBlock;
+    g.G = take(sizeof(double) * (size_t)g.ldg * g.ldg);
+    g.Gp = take(sizeof(double) * (size_t)g.nchunk * ntile * 4096);
+    g.X = take(blk);
+    g.Xn = take(blk);
+    g.W = take(blk);
+    g.Wn = take(blk);
+    g.Y0 = take(blk);
+    g.Y1 = take(blk);
+    g.Y2 = take(blk);
+    g.L = take(blk);
+    g.Hp = take(sq * (size_t)std::max<int64_t>(g.nxty, gram_parts_max(g.ldg)));
+    g.C = take(sq);
+    g.H = take(sq);
+    g.R = take(sq);
+    g.Rinv = take(sq);
+    g.P = take(sq);
+    g.PU = take(sq);
+    g.sig = take(sizeof(double) * kMaxBlock);
+    g.theta = take(sizeof(double) * kMaxBlock);
+    g.res = take(sizeof(double) * kMaxBlock);
+    g.flag = take(sizeof(int) * 4);
+    g.sweeps = take(sizeof(int) * 4);
+    g.total = off;
+    return g;
+}
+
+// Y (rows x w, FP64, leading dimension w) <- CholQR2(Y): Gram on the FP64
+// matrix cores, Cholesky and R^{-1} in one block, Y R^{-1}, twice.  Zero
+// columns stay zero (their pivots are dropped).
+isvd_status gcf_orth(char* ws, const GcfLayout& g, double* Y, int64_t rows, int w, hipStream_t st) {
+    double* Gp = (double*)(ws + g.Hp);
+    double* Hg = (double*)(ws + g.H);
+    double* R = (double*)(ws + g.R);
+    double* Rinv = (double*)(ws + g.Rinv);
+    int* flag = (int*)(ws + g.flag);
+    const int nchunk = (int)gram_parts(rows);
+    for (int pass = 0; pass < 2; ++pass) {
+        k_gram_mfma<double><<<nchunk, kThreads, 0, st>>>(Y, w, rows, w, gram_rpb(rows), Gp);
+        k_gram_sum<<<(int)cdiv(gram_tiles(w) * 256, 32), 256, 0, st>>>(Gp, nchunk, w, Hg);
+        k_chol_inv<double><<<1, kCholThreads, 0, st>>>(Hg, w, R, Rinv, flag);
+        k_rotate_plain<double, 128><<<(int)cdiv(rows, 16), kThreads, 0, st>>>(Y, w, Y, w, rows, w, Rinv);
+    }
+    HIP_TRY(hipGetLastError());
+    return ISVD_OK;
+}
+
+// FP64 storage iterates down to rounding level (the stagnation clause of the
+// stopping rule ends it there); FP32 storage, whose factors carry 2^-24
+// rounding anyway, stops at 1e-10 theta_1.
+double gcf_default_tol(const Stream& s) {
+    if (s.cfg.refresh_tol > 0.0) return s.cfg.refresh_tol;
+    return s.esz == 8 ? 1e-16 : 1e-10;
+}
+
+constexpr int kGcfMaxRounds = 40;
+constexpr double kGcfBig = 16.0;       // a Ritz value this far above the cut is deflated once converged
+constexpr double kGcfLockTol = 1e-14;  // ... to this residual (relative to theta_1) at the least
+constexpr int kGcfMaxDegree = 24;
+constexpr double kGcfGrowth = 1e6;   // largest growth of an active Ritz value per filter
+
+// Gram-form TruncatedSVD (see isvd_gcf.h): right vectors by Chebyshev-
+// filtered subspace iteration on G = A^T A with locking, until the leading k
+// Ritz residuals are at most tol * theta_1; then Y = A L, CholQR2 and the
+// Rayleigh-Ritz SVD of R as in the A form, with block k.  The host reads the
+// Ritz values and residuals once per round to lock, stop and pick the filter.
+template <typename T>
+isvd_status refresh_compute_gcf(isvd_engine* e, Stream& s, bool init, hipStream_t st, RefreshPlan* plan,
+                                const DevHeader& h, int k, int b, WsBuf& wb, int* sweeps_dev) {
+    const int64_t m = s.m, n = s.n;
+    const WsLayout w = ws_layout(m, n, b, (int)sizeof(T));
+    const GcfLayout g = gcf_layout(m, n, w.total);
+    ST_TRY(ensure_ws(wb, g.total));
+    char* ws = wb.p;
+    const T* A = (const T*)s.A;
+    const int64_t lda = lda_of(s.cfg);
+    const int ldg = g.ldg;
+    double* G = (double*)(ws + g.G);
+    double* X = (double*)(ws + g.X);
+    double* Xn = (double*)(ws + g.Xn);
+    double* W = (double*)(ws + g.W);
+    double* Wn = (double*)(ws + g.Wn);
+    double* Yb[3] = {(double*)(ws + g.Y0), (double*)(ws + g.Y1), (double*)(ws + g.Y2)};
+    double* L = (double*)(ws + g.L);
+    double* Hp = (double*)(ws + g.Hp);
+    double* C = (double*)(ws + g.C);
+    double* H = (double*)(ws + g.H);
+    double* R = (double*)(ws + g.R);
+    double* Rinv = (double*)(ws + g.Rinv);
+    double* P = (double*)(ws + g.P);
+    double* PU = (double*)(ws + g.PU);
+    double* sig = (double*)(ws + g.sig);
+    double* theta = (double*)(ws + g.theta);
+    double* res = (double*)(ws + g.res);
+    int* flag = (int*)(ws + g.flag);
+    int* gsweeps = (int*)(ws + g.sweeps);
+    const int kL = kMaxBlock;
+    const double tol = gcf_default_tol(s);
+    // G = A^T A
+    const int ntile = ata_tiles(n);
+    k_ata_mfma<T><<<dim3((unsigned)ntile, (unsigned)g.nchunk), kThreads, 0, st>>>(A, lda, m, n, cdiv(m, g.nchunk),
+                                                                                   (double*)(ws + g.Gp));
+    k_ata_sum<<<(int)cdiv((int64_t)ldg * ldg, 256), 256, 0, st>>>((const double*)(ws + g.Gp), g.nchunk, n, ldg, G);
+    // start block
+    int ba = b, wa = (int)round16(b);
+    const int kw = init ? 0 : std::min(h.k, b);
+    k_gcf_start<T><<<(int)cdiv((int64_t)ldg * wa, 256), 256, 0, st>>>(
+        X, wa, n, ldg, b, (const T*)s.V[init ? 0 : h.cur], init ? 4 : h.ld, kw, 0x5eedull + (uint64_t)s.t);
+    ST_TRY(gcf_orth(ws, g, X, ldg, wa, st));
+    const size_t svd_lds = core_lds_bytes(kMaxBlock, JacobiShape<kMaxBlock + 1>::LDW, true);
+    std::vector<double> hbuf(2 * kMaxBlock + 1);
+    int nlk = 0, rounds = 0, nl_last = 0;
+    double th1 = 0.0, prev_rmax = HUGE_VAL;
+    bool converged = false;
+    const double lock_tol = std::max(tol, kGcfLockTol);
+    std::vector<double> locked_theta;
+    double gram_top = std::nan("");
+    for (;;) {
+        ++rounds;
+        // Rayleigh-Ritz on the active block
+        k_symm_cheb<<<dim3((unsigned)(ldg / 16), (unsigned)cdiv(wa, 32)), kThreads, 0, st>>>(G, ldg, X, nullptr, W,
+                                                                                            wa, wa, 1.0, 0.0, 0.0);
+        k_xty_partial<<<g.nxty, kThreads, 0, st>>>(X, wa, wa, W, wa, wa, ldg, 256, Hp);
+        k_sum_sym<<<(int)cdiv(wa * wa, 256), 256, 0, st>>>(Hp, g.nxty, wa, H);
+        k_chol_inv<double><<<1, kCholThreads, 0, st>>>(H, wa, R, Rinv, flag);
+        k_svd_small<double><<<1, JacobiShape<kMaxBlock + 1>::NT, svd_lds, st>>>(R, wa, wa, sig, PU, P, wa, gsweeps);
+        k_rotate_plain<double, 128><<<ldg / 16, kThreads, 0, st>>>(X, wa, Xn, wa, ldg, wa, P);
+        k_rotate_plain<double, 128><<<ldg / 16, kThreads, 0, st>>>(W, wa, Wn, wa, ldg, wa, P);
+        std::swap(X, Xn);
+        std::swap(W, Wn);
+        k_ritz_res<<<wa, kThreads, 0, st>>>(W, X, wa, ldg, sig, theta, res);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(hbuf.data(), theta, sizeof(double) * wa, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(hbuf.data() + kMaxBlock, res, sizeof(double) * wa, hipMemcpyDeviceToHost, st));
+        int rr_sweeps = 0;
+        HIP_TRY(hipMemcpyAsync(&rr_sweeps, gsweeps, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if (rr_sweeps < 0) return fail(ISVD_E_CONVERGE, "Gram-form Rayleigh-Ritz Jacobi did not converge");
+        const double* hth = hbuf.data();
+        const double* hres = hbuf.data() + kMaxBlock;
+        if (rounds == 1) th1 = hth[0];
+        if (!(th1 > 0.0)) {
+            // A = 0: every Ritz value is zero; the block is as good as any
+            th1 = 1.0;
+        }
+        // stopping rule: the leading k pairs still in the active block meet
+        // the tolerance, or their largest residual stopped falling (halving
+        // per round) within 1e3 of it: rounding level
+        double rmax = 0.0;
+        for (int i = 0; i < k - nlk; ++i) rmax = std::max(rmax, hres[i]);
+        rmax /= th1;
+        const bool conv = rmax <= tol || (rmax <= 1e3 * tol && rmax > 0.5 * prev_rmax);
+        prev_rmax = rmax;
+        // deflate the converged pairs far above the cut (the factor directions):
+        // they would otherwise limit the filter degree; pairs inside the bulk
+        // stay active, so they keep improving until the whole set stops
+        const double cut = hth[ba - 1];
+        int nl = 0;
+        while (nl < ba && nlk + nl < k && hres[nl] <= lock_tol * th1 && hth[nl] >= kGcfBig * cut) ++nl;
+        if (conv || nlk + nl >= k || rounds >= kGcfMaxRounds) {
+            gram_top = 0.0;
+            for (int i = 0; i < k - nlk; ++i) gram_top += hth[i];
+            for (double t : locked_theta) gram_top += t;
+        }
+        for (int i = 0; i < nl; ++i) locked_theta.push_back(hth[i]);
+        if (nl > 0) {
+            k_copy2d<double, double><<<(int)cdiv((int64_t)ldg * nl, 256), 256, 0, st>>>(X, wa, L + nlk, kL, ldg, nl);
+            const int nt16 = ldg / 16;
+            k_deflate<<<nt16 * (nt16 + 1) / 2, kThreads, 0, st>>>(G, ldg, X, W, wa, nl, theta);
+            nlk += nl;
+        }
+        nl_last = nl;
+        if (conv || nlk >= k) {
+            converged = true;
+            break;
+        }
+        if (rounds >= kGcfMaxRounds) break;
+        const double top = hth[nl];
+        if (nl > 0) {
+            const int wn = (int)round16(ba - nl);
+            k_take_cols<<<(int)cdiv((int64_t)ldg * wn, 256), 256, 0, st>>>(X, wa, nl, ba - nl, Xn, wn, ldg);
+            std::swap(X, Xn);
+            ba -= nl;
+            wa = wn;
+        }
+        // Chebyshev filter on [0, cut]
+        double alpha1, beta1, alpha2, beta2;
+        int d;
+        if (cut > 1e-14 * th1) {
+            const double ec = 0.5 * cut;
+            const double xt = 2.0 * top / cut - 1.0;
+            d = xt > 1.0 + 1e-12 ? (int)std::floor(std::acosh(kGcfGrowth) / std::acosh(xt)) : kGcfMaxDegree;
+            d = std::max(1, std::min(kGcfMaxDegree, d));
+            alpha1 = 1.0 / ec;
+            beta1 = -1.0;
+            alpha2 = 2.0 / ec;
+            beta2 = -2.0;
+        } else {
+            // the active block reaches the null space of A: plain power steps
+            d = 1;
+            alpha1 = top > 0.0 ? 1.0 / top : 1.0;
+            beta1 = 0.0;
+            alpha2 = beta2 = 0.0;
+        }
+        const dim3 grid((unsigned)(ldg / 16), (unsigned)cdiv(wa, 32));
+        double* y0 = X;
+        double* y1 = Yb[0];
+        k_symm_cheb<<<grid, kThreads, 0, st>>>(G, ldg, y0, nullptr, y1, wa, wa, alpha1, beta1, 0.0);
+        int nxt = 1;
+        for (int j = 2; j <= d; ++j) {
+            double* y2 = (y0 == X) ? Yb[nxt] : y0;
+            if (y0 == X) nxt = 2;
+            k_symm_cheb<<<grid, kThreads, 0, st>>>(G, ldg, y1, y0, y2, wa, wa, alpha2, beta2, -1.0);
+            y0 = y1;
+            y1 = y2;
+        }
+        // remove what the filter left of the locked directions (twice), then CholQR2
+        for (int pass = 0; pass < 2 && nlk > 0; ++pass) {
+            k_xty_partial<<<g.nxty, kThreads, 0, st>>>(L, kL, nlk, y1, wa, wa, ldg, 256, Hp);
+            k_sum_parts<double><<<(int)cdiv(nlk * wa, 256), 256, 0, st>>>(Hp, g.nxty, (int64_t)nlk * wa,
+                                                                          (int64_t)nlk * wa, C);
+            k_sub_lc<<<(int)cdiv((int64_t)ldg * wa, 256), 256, 0, st>>>(y1, wa, wa, L, kL, nlk, C, ldg);
+        }
+        ST_TRY(gcf_orth(ws, g, y1, ldg, wa, st));
+        if (y1 != X) {
+            // the filtered block becomes X (X's buffer is one of the three)
+            std::swap(X, (y1 == Yb[0] ? Yb[0] : (y1 == Yb[1] ? Yb[1] : Yb[2])));
+        }
+    }
+    // Final step in A form on the whole block: the locked vectors and the
+    // leading remaining active ones (b columns, orthonormal).  The Rayleigh-
+    // Ritz SVD of R resolves the directions near the cut at the accuracy of
+    // A itself, where G = A^T A, whose rounding is relative to sigma_1^2, can
+    // only resolve them to about eps64 sigma_1^2 / (sigma_k (sigma_k -
+    // sigma_k+1)) in angle.
+    T* Xf = (T*)(ws + w.X);
+    T* Y = (T*)(ws + w.Y);
+    k_copy2d<double, T><<<(int)cdiv(n * nlk, 256), 256, 0, st>>>(L, kL, Xf, b, n, nlk);
+    k_copy2d<double, T><<<(int)cdiv(n * (b - nlk), 256), 256, 0, st>>>(X + nl_last, wa, Xf + nlk, b, n, b - nlk);
+    k_start_flags<<<1, 64, 0, st>>>((int*)(ws + w.flag));
+    gemm_nn<T>(A, lda, Xf, Y, m, n, b, st);
+    const double* Rfin = nullptr;
+    ST_TRY(cholqr<T>(ws, w, Y, m, b, true, 2, st, &Rfin));
+    const int ldo = round4(k);
+    if constexpr (sizeof(T) == 4)
+        k_svd_small_noj<T><<<1, RRShape::NT, sizeof(double) * svd_noj_lds_doubles(), st>>>(
+            Rfin, b, k, (double*)(ws + w.Sr), (T*)(ws + w.QU), (T*)(ws + w.QV), ldo,
+            sweeps_dev ? sweeps_dev : (int*)(ws + w.sweeps));
+    else
+        k_svd_small<T><<<1, JacobiShape<kMaxBlock + 1>::NT, svd_lds, st>>>(
+            Rfin, b, k, (double*)(ws + w.Sr), (T*)(ws + w.QU), (T*)(ws + w.QV), ldo,
+            sweeps_dev ? sweeps_dev : (int*)(ws + w.sweeps));
+    HIP_TRY(hipGetLastError());
+    plan->k = k;
+    plan->b = b;
+    plan->ldo = ldo;
+    plan->cur = init ? 0 : h.cur;
+    plan->m = m;
+    plan->n = n;
+    plan->w = w;
+    plan->rounds = rounds;
+    plan->converged = converged;
+    plan->gram_top = gram_top;
+    return ISVD_OK;
+}
 
 // Block subspace iteration up to the Rayleigh-Ritz SVD: Ritz values in ws.Sr,
 // left / right rotations of the block in ws.QU / ws.QV, block bases in
@@ -1075,7 +1369,9 @@ isvd_status refresh_compute(isvd_engine* e, Stream& s, bool init, hipStream_t st
     b = (int)std::min<int64_t>(b, m);
     if (b < k) return fail(ISVD_E_INVAL, "refresh block %d smaller than rank %d", b, k);
     const bool exact = (b == n);
-    const int iters = exact ? 0 : (s.cfg.refresh_iters >= 0 ? s.cfg.refresh_iters : (init ? 8 : 3));
+    if (!exact && n <= kGcfMaxN && s.cfg.refresh_iters < 0)
+        return refresh_compute_gcf<T>(e, s, init, st, plan, h, k, b, wb, sweeps_dev);
+    const int iters = exact ? 0 : s.cfg.refresh_iters >= 0 ? s.cfg.refresh_iters : (init ? 8 : 3);
     WsLayout w = ws_layout(m, n, b, (int)sizeof(T));
     ST_TRY(ensure_ws(wb, w.total));
     char* ws = wb.p;
@@ -1281,6 +1577,8 @@ isvd_status do_refresh(isvd_engine* e, Stream& s, bool init, bool store_ref, hip
         if (rc != ISVD_OK) return rc;
     }
     const bool deferred = sweeps_dev != nullptr && computed == nullptr;
+    s.refresh_rounds = plan.rounds;
+    s.refresh_converged = plan.converged;
     rc = s.esz == 8 ? refresh_commit<double>(e, s, plan, store_ref, st, deferred, wk)
                     : refresh_commit<float>(e, s, plan, store_ref, st, deferred, wk);
     if (rc != ISVD_OK) return rc;
@@ -1396,8 +1694,14 @@ isvd_status exact_metrics_t(isvd_engine* e, Stream& s, hipStream_t st, Exact* ou
     HIP_TRY(hipStreamSynchronize(st));
     out->fro2 = hs[0];
     out->e_inc = std::sqrt(std::max(hs[1], 0.0));
+    // the Gram form's Ritz values come from exact FP64 products of A's
+    // entries, the A form's from products in the storage type
     double top = 0.0;
-    for (int q = 0; q < plan->k; ++q) top += sr[q] * sr[q];
+    if (std::isfinite(plan->gram_top)) {
+        top = plan->gram_top;
+    } else {
+        for (int q = 0; q < plan->k; ++q) top += sr[q] * sr[q];
+    }
     out->e_opt = std::sqrt(std::max(hs[0] - top, 0.0));
     out->gap = out->e_inc - out->e_opt;
     out->ratio = out->e_opt > 1e-14 * std::sqrt(hs[0]) ? out->e_inc / out->e_opt : std::nan("");
@@ -2291,6 +2595,8 @@ isvd_status isvd_metrics(isvd_engine* e, isvd_id id, int32_t compute_exact, void
     m.step_angle_U = h.t > 0 ? h.step_angle_u : nan;
     m.step_angle_V = h.t > 0 ? h.step_angle_v : nan;
     m.spectrum_change = h.t > 0 ? h.spec_change : nan;
+    m.refresh_rounds = s->refresh_rounds;
+    m.refresh_converged = s->refresh_converged ? 1 : 0;
     m.frob_error = m.frob_opt = m.frob_gap = m.frob_ratio = nan;
     m.ortho_U = m.ortho_V = nan;
     m.angle_ref = s->angle ? h.angle_ref : nan;

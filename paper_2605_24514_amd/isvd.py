@@ -41,7 +41,7 @@ class CConfig(ctypes.Structure):
     _fields_ = [("m0", ctypes.c_int64), ("n0", ctypes.c_int64), ("m_cap", ctypes.c_int64),
                 ("n_cap", ctypes.c_int64), ("k", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("tol_rel", ctypes.c_double), ("refresh_iters", ctypes.c_int32),
-                ("oversample", ctypes.c_int32), ("policy", CPolicy)]
+                ("oversample", ctypes.c_int32), ("policy", CPolicy), ("refresh_tol", ctypes.c_double)]
 
 
 class CMetrics(ctypes.Structure):
@@ -52,7 +52,8 @@ class CMetrics(ctypes.Structure):
         (f, ctypes.c_double) for f in ("fro2_A", "sigma2_sum", "evr", "rho", "novelty", "frob_error",
                                        "frob_opt", "frob_gap", "frob_ratio", "ortho_U", "ortho_V",
                                        "update_time_us", "opt_time_us", "angle_ref", "step_angle_U",
-                                       "step_angle_V", "spectrum_change")]
+                                       "step_angle_V", "spectrum_change")] + [
+        ("refresh_rounds", ctypes.c_int32), ("refresh_converged", ctypes.c_int32)]
 
 
 class CRequest(ctypes.Structure):
@@ -272,16 +273,17 @@ class Engine:
 
     @staticmethod
     def config(m0, n0, k, precision="fp32", m_cap=None, n_cap=None, tol_rel=0.0, policy=None,
-               refresh_iters=-1, oversample=-1):
+               refresh_iters=-1, oversample=-1, refresh_tol=0.0):
         prec = {"fp32": ISVD_FP32, "fp64": ISVD_FP64, "bf16rot": ISVD_BF16ROT}[precision]
         pol = (policy or Policy()).to_c()
-        return CConfig(m0, n0, m_cap or m0, n_cap or n0, k, prec, tol_rel, refresh_iters, oversample, pol)
+        return CConfig(m0, n0, m_cap or m0, n_cap or n0, k, prec, tol_rel, refresh_iters, oversample, pol,
+                       refresh_tol)
 
     def stream_bytes(self, cfg):
         return int(self._lib.isvd_stream_bytes(ctypes.byref(cfg)))
 
     def init(self, A0, k, precision="fp32", m_cap=None, n_cap=None, tol_rel=0.0, policy=None,
-             refresh_iters=-1, oversample=-1, stream=None):
+             refresh_iters=-1, oversample=-1, stream=None, refresh_tol=0.0):
         if hasattr(A0, "data_ptr"):
             m0, n0 = A0.shape
             ptr, _, code, dev, keep = _payload(A0)
@@ -291,7 +293,8 @@ class Engine:
             m0, n0 = a.shape
             ptr, _, code, dev, keep = _payload(a)
             lda = n0
-        cfg = self.config(m0, n0, k, precision, m_cap, n_cap, tol_rel, policy, refresh_iters, oversample)
+        cfg = self.config(m0, n0, k, precision, m_cap, n_cap, tol_rel, policy, refresh_iters, oversample,
+                          refresh_tol)
         sid = ctypes.c_int64()
         self._check(self._lib.isvd_init(self._h, ctypes.byref(cfg), ptr, lda, code, dev, _stream_ptr(stream),
                                         ctypes.byref(sid)), "isvd_init")
@@ -299,7 +302,7 @@ class Engine:
         return sid.value
 
     def init_from_factors(self, A0, U, S, V, precision="fp32", m_cap=None, n_cap=None, tol_rel=0.0, policy=None,
-                          refresh_iters=-1, oversample=-1, stream=None):
+                          refresh_iters=-1, oversample=-1, stream=None, refresh_tol=0.0):
         """Start a stream from given FP64 factors (U m0 x k, S k, V n0 x k) and A0."""
         U = np.ascontiguousarray(U, dtype=np.float64)
         S = np.ascontiguousarray(S, dtype=np.float64)
@@ -314,7 +317,8 @@ class Engine:
             m0, n0 = a.shape
             ptr, _, code, dev, keep = _payload(a)
             lda = n0
-        cfg = self.config(m0, n0, k, precision, m_cap, n_cap, tol_rel, policy, refresh_iters, oversample)
+        cfg = self.config(m0, n0, k, precision, m_cap, n_cap, tol_rel, policy, refresh_iters, oversample,
+                          refresh_tol)
         sid = ctypes.c_int64()
         dp = ctypes.POINTER(ctypes.c_double)
         self._check(self._lib.isvd_init_from_factors(self._h, ctypes.byref(cfg), ptr, lda, code, dev,

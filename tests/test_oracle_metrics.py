@@ -97,3 +97,22 @@ def test_theta_ref_ignores_row_growth_but_sees_rotation():
     P = np.vstack([Q[:, :3].T, np.cos(a) * Q[:, 3] + np.sin(a) * np.linalg.qr(
         np.column_stack([Q, rng.standard_normal(30)]))[0][:, 4]]).T
     assert abs(metrics.theta_ref(Q, P) - a) < 1e-12
+
+
+def test_orthogonality_known_answer():
+    """||Q^T Q - I||_2 for Q = O diag(d) P^T (O with orthonormal columns, P
+    orthogonal) is max_i |d_i^2 - 1|: the spectral norm, not the Frobenius
+    norm (0.2315 here) nor the largest entry of the rotated Gram residual."""
+    from oracle.metrics import orthogonality
+    rng = np.random.default_rng(5)
+    d = np.array([1.1, 0.95, 1.0, 1.0 + 1e-9])
+    O, _ = np.linalg.qr(rng.standard_normal((30, 4)))
+    P, _ = np.linalg.qr(rng.standard_normal((4, 4)))
+    Q = O @ np.diag(d) @ P.T
+    assert abs(orthogonality(Q) - 0.21) <= 1e-14
+    E = Q.T @ Q - np.eye(4)
+    assert abs(np.linalg.norm(E) - 0.21) > 1e-2          # Frobenius differs
+    assert np.max(np.abs(E)) < 0.21 - 1e-3               # so does the largest entry
+    # an exactly orthonormal basis has zero residual; a scaled one |c^2 - 1|
+    assert orthogonality(O) <= 1e-15
+    assert abs(orthogonality(1.5 * O) - 1.25) <= 1e-14
