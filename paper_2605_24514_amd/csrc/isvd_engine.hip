@@ -462,6 +462,7 @@ isvd_status set_lds_limits() {
     ST_TRY(allow_lds(k_svd_small<float>, svd_lds));
     ST_TRY(allow_lds(k_svd_small<double>, svd_lds));
     ST_TRY(allow_lds(k_svd_small_noj<float>, sizeof(double) * svd_noj_lds_doubles()));
+    ST_TRY(allow_lds(k_svd_small_noj<double>, sizeof(double) * svd_noj_lds_doubles()));
     ST_TRY(allow_lds(k_sym_norm2, sym_norm2_lds(kMaxBlock)));
     ST_TRY(allow_lds(k_track<float>, sizeof(double) * 2 * kMaxCore * kMaxBlock));
     ST_TRY(allow_lds(k_track<double>, sizeof(double) * 2 * kMaxCore * kMaxBlock));
@@ -1061,8 +1062,32 @@ struct RefreshPlan {
     double gram_top = std::nan("");
 };
 
+// Row chunks of the Gram product: the grid (tiles x chunks) is sized to
+// whole waves of two 256-thread blocks per compute unit (a partial last
+// wave of blocks would idle most of the chip for a block's duration),
+// chunks of at least 256 rows, at most 2048 partial tiles (256 MB).
+constexpr int kXtyRows = 64;   // rows per block of the small cross products X^T Y
+int ata_chunks(int64_t m, int ntile) {
+    const int64_t cap = 2 * 256;
+    int best = 1;
+    double best_cost = 1e300;
+    for (int c = 1; c <= 64; ++c) {
+        if (c > 1 && (cdiv(m, c) < 256 || (int64_t)ntile * c > 2048)) break;
+        const int64_t blocks = (int64_t)ntile * c;
+        const double waves = (double)cdiv(blocks, cap);
+        // time ~ whole waves of blocks, each 1 / c of the rows; a small
+        // charge per chunk for its partial tile
+        const double cost = waves / c + 0.0005 * c;
+        if (cost < best_cost) {
+            best_cost = cost;
+            best = c;
+        }
+    }
+    return best;
+}
+
 // Workspace of the Gram-form refresh, placed after the A-form layout of
-// its final step (block = k).
+// its final step.
 struct GcfLayout {
     size_t G, Gp, X, Xn, W, Wn, Y0, Y1, Y2, L, Hp, C, H, R, Rinv, P, PU, sig, theta, res, flag, sweeps, total;
     int ldg = 0, nchunk = 1, nxty = 1;
@@ -1078,12 +1103,12 @@ GcfLayout gcf_layout(int64_t m, int64_t n, size_t base) {
     };
     g.ldg = (int)round64(n);
     const int ntile = ata_tiles(n);
-    g.nchunk = (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(1024, ntile), cdiv(m, 256)));
-    g.nxty = (int)cdiv(g.ldg, 256);
+    g.nchunk = ata_chunks(m, ntile);
+    g.nxty = (int)cdiv(g.ldg, kXtyRows);
     const size_t blk = sizeof(double) * (size_t)g.ldg * kMaxBlock;
     const size_t sq = sizeof(double) * kMaxBlock * kMaxBlock;
     g.G = take(sizeof(double) * (size_t)g.ldg * g.ldg);
-    g.Gp = take(sizeof(double) * (size_t)g.nchunk * ntile * 4096);
+    g.Gp = take(sizeof(double) * (size_t)g.nchunk * ntile * kAtaTile * kAtaTile);
     g.X = take(blk);
     g.Xn = take(blk);
     g.W = take(blk);
@@ -1203,10 +1228,14 @@ isvd_status refresh_compute_gcf(isvd_engine* e, Stream& s, bool init, hipStream_
         // Rayleigh-Ritz on the active block
         k_symm_cheb<<<dim3((unsigned)(ldg / 16), (unsigned)cdiv(wa, 32)), kThreads, 0, st>>>(G, ldg, X, nullptr, W,
                                                                                             wa, wa, 1.0, 0.0, 0.0);
-        k_xty_partial<<<g.nxty, kThreads, 0, st>>>(X, wa, wa, W, wa, wa, ldg, 256, Hp);
+        k_xty_partial<<<g.nxty, kThreads, 0, st>>>(X, wa, wa, W, wa, wa, ldg, kXtyRows, Hp);
         k_sum_sym<<<(int)cdiv(wa * wa, 256), 256, 0, st>>>(Hp, g.nxty, wa, H);
         k_chol_inv<double><<<1, kCholThreads, 0, st>>>(H, wa, R, Rinv, flag);
-        k_svd_small<double><<<1, JacobiShape<kMaxBlock + 1>::NT, svd_lds, st>>>(R, wa, wa, sig, PU, P, wa, gsweeps);
+        // right vectors P of R (the eigenvectors of H) from the rotated columns
+        // of R^T, without accumulating the rotations: their orthogonality loss,
+        // about b eps64 (theta_1 / theta_j)^(1/2), stays near rounding level
+        k_svd_small_noj<double><<<1, RRShape::NT, sizeof(double) * svd_noj_lds_doubles(), st>>>(R, wa, wa, sig,
+                                                                                               PU, P, wa, gsweeps);
         k_rotate_plain<double, 128><<<ldg / 16, kThreads, 0, st>>>(X, wa, Xn, wa, ldg, wa, P);
         k_rotate_plain<double, 128><<<ldg / 16, kThreads, 0, st>>>(W, wa, Wn, wa, ldg, wa, P);
         std::swap(X, Xn);
@@ -1299,7 +1328,7 @@ isvd_status refresh_compute_gcf(isvd_engine* e, Stream& s, bool init, hipStream_
         }
         // remove what the filter left of the locked directions (twice), then CholQR2
         for (int pass = 0; pass < 2 && nlk > 0; ++pass) {
-            k_xty_partial<<<g.nxty, kThreads, 0, st>>>(L, kL, nlk, y1, wa, wa, ldg, 256, Hp);
+            k_xty_partial<<<g.nxty, kThreads, 0, st>>>(L, kL, nlk, y1, wa, wa, ldg, kXtyRows, Hp);
             k_sum_parts<double><<<(int)cdiv(nlk * wa, 256), 256, 0, st>>>(Hp, g.nxty, (int64_t)nlk * wa,
                                                                           (int64_t)nlk * wa, C);
             k_sub_lc<<<(int)cdiv((int64_t)ldg * wa, 256), 256, 0, st>>>(y1, wa, wa, L, kL, nlk, C, ldg);

@@ -58,16 +58,17 @@
 namespace isvd {
 
 constexpr int kGcfMaxN = 4096;     // widest stream refreshed in Gram form
-constexpr int kAtaStage = 32;      // rows of A per LDS stage of the Gram product
-constexpr int kAtaLd = 2 * 64 + 4; // LDS row stride (doubles) of a stage
+constexpr int kAtaTile = 128;     // Gram tile edge
+constexpr int kAtaStage = 16;     // rows of A per LDS stage of the Gram product
+constexpr int kAtaLd = 2 * kAtaTile + 4;   // LDS row stride (doubles) of a stage
 
 __host__ __device__ inline int64_t round64(int64_t v) { return (v + 63) & ~(int64_t)63; }
-__host__ __device__ inline int ata_panels(int64_t n) { return (int)((n + 63) / 64); }
+__host__ __device__ inline int ata_panels(int64_t n) { return (int)((n + kAtaTile - 1) / kAtaTile); }
 __host__ __device__ inline int ata_tiles(int64_t n) {
     const int p = ata_panels(n);
     return p * (p + 1) / 2;
 }
-// tile t of the upper triangle of 64 x 64 tiles, row by row
+// tile t of the upper triangle of tiles, row by row
 __device__ inline void ata_tile(int t, int np, int* ip, int* jp) {
     int i = 0;
     while (t >= np - i) {
@@ -78,24 +79,25 @@ __device__ inline void ata_tile(int t, int np, int* ip, int* jp) {
     *jp = i + t;
 }
 
-// Partial Gram tiles: Gp[chunk][tile][64 x 64] = sum over the rows of the
-// chunk of A[r][64 ip + a] A[r][64 jp + c].  grid (tiles, chunks), 256
-// threads; a stage of 32 rows of the two 64-column panels is held in LDS as
-// FP64 (the next stage prefetched into registers); wave w owns the 32 x 32
-// quadrant (w / 2, w % 2) of the tile, four 16 x 16 FP64 MFMA tiles.
-// MFMA operands: lane l gives A_op[l % 16][l / 16] = A[r0 + l / 16][64 ip + ...]
-// and B_op[l / 16][l % 16] = A[r0 + l / 16][64 jp + ...], so D = A_op B_op is
-// the (ip, jp) tile of A^T A.
+// Partial Gram tiles: Gp[chunk][tile][128 x 128] = sum over the rows of the
+// chunk of A[r][128 ip + a] A[r][128 jp + c].  grid (tiles, chunks), 256
+// threads; a stage of 16 rows of the two 128-column panels is held in LDS
+// as FP64 (the next stage prefetched into registers); wave w owns the
+// 64 x 64 quadrant (w / 2, w % 2) of the tile, sixteen 16 x 16 FP64 MFMA
+// tiles, so each LDS operand read feeds four MFMAs.
+// MFMA operands: lane l gives A_op[l % 16][l / 16] = A[r0 + l / 16][128 ip + ...]
+// and B_op[l / 16][l % 16] = A[r0 + l / 16][128 jp + ...], so D = A_op B_op is
+// a block of the (ip, jp) tile of A^T A.
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_ata_mfma(const T* __restrict__ A, int64_t lda, int64_t m,
                                                        int64_t n, int64_t rpc, double* __restrict__ Gp) {
-    constexpr int PER = kAtaStage * 128 / kThreads;
+    constexpr int PER = kAtaStage * 2 * kAtaTile / kThreads;   // 16
     __shared__ double sA[kAtaStage][kAtaLd];
     const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int npan = ata_panels(n), ntile = npan * (npan + 1) / 2;
     int ip, jp;
     ata_tile(blockIdx.x, npan, &ip, &jp);
-    const int64_t ci = (int64_t)ip * 64, cj = (int64_t)jp * 64;
+    const int64_t ci = (int64_t)ip * kAtaTile, cj = (int64_t)jp * kAtaTile;
     const int64_t ra = (int64_t)blockIdx.y * rpc;
     const int64_t rb = min(m, ra + rpc);
     T pre[PER];
@@ -103,49 +105,54 @@ __global__ void __launch_bounds__(kThreads) k_ata_mfma(const T* __restrict__ A, 
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             const int e = threadIdx.x + kThreads * q;
-            const int rr = e >> 7, cc = e & 127;
-            const int64_t col = cc < 64 ? ci + cc : cj + cc - 64;
+            const int rr = e >> 8, cc = e & 255;
+            const int64_t col = cc < kAtaTile ? ci + cc : cj + cc - kAtaTile;
             const int64_t r = r0 + rr;
             pre[q] = (r < rb && col < n) ? A[r * lda + col] : (T)0;
         }
     };
-    mm_v4d acc[2][2];
+    mm_v4d acc[4][4];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int c = 0; c < 2; ++c) acc[a][c] = (mm_v4d){0.0, 0.0, 0.0, 0.0};
-    const int oi = (w >> 1) * 32 + (l & 15), oj = 64 + (w & 1) * 32 + (l & 15);
+        for (int c = 0; c < 4; ++c) acc[a][c] = (mm_v4d){0.0, 0.0, 0.0, 0.0};
+    const int oi = (w >> 1) * 64 + (l & 15), oj = kAtaTile + (w & 1) * 64 + (l & 15);
     if (ra < rb) fetch(ra);
     for (int64_t r0 = ra; r0 < rb; r0 += kAtaStage) {
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             const int e = threadIdx.x + kThreads * q;
-            sA[e >> 7][e & 127] = (double)pre[q];
+            sA[e >> 8][e & 255] = (double)pre[q];
         }
         __syncthreads();
         if (r0 + kAtaStage < rb) fetch(r0 + kAtaStage);
 #pragma unroll
         for (int kk = 0; kk < kAtaStage / 4; ++kk) {
             const int rr = 4 * kk + (l >> 4);
-            const double a0 = sA[rr][oi], a1 = sA[rr][oi + 16];
-            const double b0 = sA[rr][oj], b1 = sA[rr][oj + 16];
-            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+            double av[4], bv[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                av[a] = sA[rr][oi + 16 * a];
+                bv[a] = sA[rr][oj + 16 * a];
+            }
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    acc[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[c], acc[a][c], 0, 0, 0);
         }
         __syncthreads();
     }
-    double* out = Gp + ((int64_t)blockIdx.y * ntile + blockIdx.x) * 4096;
+    double* out = Gp + ((int64_t)blockIdx.y * ntile + blockIdx.x) * (kAtaTile * kAtaTile);
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int c = 0; c < 2; ++c)
+        for (int c = 0; c < 4; ++c)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int row = (w >> 1) * 32 + 16 * a + 4 * r + (l >> 4);
-                const int col = (w & 1) * 32 + 16 * c + (l & 15);
-                out[row * 64 + col] = acc[a][c][r];
+                const int row = (w >> 1) * 64 + 16 * a + 4 * r + (l >> 4);
+                const int col = (w & 1) * 64 + 16 * c + (l & 15);
+                out[row * kAtaTile + col] = acc[a][c][r];
             }
 }
 
@@ -161,18 +168,19 @@ __global__ void k_ata_sum(const double* __restrict__ Gp, int nchunk, int64_t n, 
         G[e] = 0.0;
         return;
     }
-    if (i / 64 > j / 64 || (i / 64 == j / 64 && i > j)) {
+    if (i / kAtaTile > j / kAtaTile || (i / kAtaTile == j / kAtaTile && i > j)) {
         const int64_t t = i;
         i = j;
         j = t;
     }
+    constexpr int64_t TT = (int64_t)kAtaTile * kAtaTile;
     const int npan = ata_panels(n), ntile = npan * (npan + 1) / 2;
-    const int ip = (int)(i / 64), jp = (int)(j / 64);
+    const int ip = (int)(i / kAtaTile), jp = (int)(j / kAtaTile);
     // index of tile (ip, jp) in the row-by-row upper triangle
     const int tile = ip * npan - ip * (ip - 1) / 2 + (jp - ip);
-    const double* P = Gp + (int64_t)tile * 4096 + (i % 64) * 64 + (j % 64);
+    const double* P = Gp + (int64_t)tile * TT + (i % kAtaTile) * kAtaTile + (j % kAtaTile);
     double s = 0.0;
-    for (int c = 0; c < nchunk; ++c) s += P[(int64_t)c * ntile * 4096];
+    for (int c = 0; c < nchunk; ++c) s += P[(int64_t)c * ntile * TT];
     G[e] = s;
 }
 
