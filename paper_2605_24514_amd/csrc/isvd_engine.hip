@@ -1347,7 +1347,7 @@ isvd_status refresh_compute_gcf(isvd_engine* e, Stream& s, bool init, hipStream_
     // sigma_k+1)) in angle.
     T* Xf = (T*)(ws + w.X);
     T* Y = (T*)(ws + w.Y);
-    k_copy2d<double, T><<<(int)cdiv(n * nlk, 256), 256, 0, st>>>(L, kL, Xf, b, n, nlk);
+    if (nlk > 0) k_copy2d<double, T><<<(int)cdiv(n * nlk, 256), 256, 0, st>>>(L, kL, Xf, b, n, nlk);
     k_copy2d<double, T><<<(int)cdiv(n * (b - nlk), 256), 256, 0, st>>>(X + nl_last, wa, Xf + nlk, b, n, b - nlk);
     k_start_flags<<<1, 64, 0, st>>>((int*)(ws + w.flag));
     gemm_nn<T>(A, lda, Xf, Y, m, n, b, st);
