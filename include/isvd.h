@@ -229,6 +229,25 @@ isvd_status isvd_update_entry(isvd_engine* eng, isvd_id id, int64_t i, int64_t j
  * columns); store_reference != 0 also sets U_ref = U.  Waits for the device. */
 isvd_status isvd_refresh(isvd_engine* eng, isvd_id id, int32_t store_reference, void* hip_stream);
 
+/* For callers that cannot allocate device memory (serving loops and harnesses
+ * that forbid hipMalloc after start-up): isvd_refresh with its whole workspace
+ * in a static device array of ISVD_NOALLOC_SCRATCH_BYTES that the library
+ * holds on each GPU it runs on until the process ends (its address is looked
+ * up when an engine is created on that GPU).  Same computation, same results
+ * bit for bit, same ordering on hip_stream; the call still waits on the host
+ * for the Gram form's per-round decisions, as isvd_refresh does.
+ * The array is shared by every engine and call on that GPU and keeps the
+ * last call's contents: calls that overlap on one GPU (two host threads, or
+ * two streams whose refreshes are in flight together) race on it.
+ * Errors: as isvd_refresh; NOMEM when the stream's refresh needs more
+ * workspace than the array holds (nothing is enqueued; about m x (k + os)
+ * elements of the storage type plus, in the Gram form, 8 n^2 bytes and the
+ * blocks); INVAL for store_reference = 0 on an angle-policy stream (keeping
+ * the old reference needs tracker workspace that only isvd_refresh
+ * allocates). */
+#define ISVD_NOALLOC_SCRATCH_BYTES (64u << 20)
+isvd_status isvd_refresh_noalloc(isvd_engine* eng, isvd_id id, int32_t store_reference, void* hip_stream);
+
 /* Metrics of the stream.  Waits for the device.  compute_exact != 0 adds
  * E_inc (one pass over A), E_opt = sqrt(||A||_F^2 - sum of the k leading
  * squared Ritz values of a refresh-style subspace iteration that does not

@@ -19,6 +19,7 @@
 #include <cstddef>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -34,6 +35,13 @@
 #include "isvd_finance.h"
 
 using namespace isvd;
+
+// Workspace of isvd_refresh_noalloc: one static device array per GPU the
+// library runs on, held until the process ends.  In host code its name is
+// not a device address; its address on each device comes from
+// hipGetSymbolAddress (noalloc_scratch_ptr).
+constexpr size_t kNoAllocScratchBytes = (size_t)ISVD_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
 
 namespace {
 
@@ -89,6 +97,7 @@ struct WsBuf {
     char* p = nullptr;
     size_t bytes = 0;
     bool defer_free = false;
+    bool fixed = false;    // caller-provided memory: never grown or freed
     std::vector<char*> retired;
 };
 
@@ -302,6 +311,24 @@ namespace {
 
 isvd_status ensure_device(isvd_engine* e) {
     HIP_TRY(hipSetDevice(e->device));
+    return ISVD_OK;
+}
+
+// Device address of `scratch` on each device, looked up once per device
+// with that device current (engine creation).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {};
+
+isvd_status noalloc_scratch_setup(int device) {
+    if (device < 0 || device >= kMaxDevices) return fail(ISVD_E_INVAL, "device %d", device);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return ISVD_OK;
+    void* ptr = nullptr;
+    const hipError_t err = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (err != hipSuccess || !ptr)
+        return fail(ISVD_E_DEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", device, hipGetErrorString(err));
+    g_scratch_ptr[device] = (char*)ptr;
     return ISVD_OK;
 }
 
@@ -917,6 +944,7 @@ WsLayout ws_layout(int64_t m, int64_t n, int b, int esz) {
 
 isvd_status ensure_ws(WsBuf& w, size_t bytes) {
     if (w.bytes >= bytes) return ISVD_OK;
+    if (w.fixed) return fail(ISVD_E_NOMEM, "refresh workspace of %zu bytes exceeds the fixed %zu", bytes, w.bytes);
     if (w.p) {
         if (w.defer_free) {
             w.retired.push_back(w.p);
@@ -1049,6 +1077,20 @@ void gemm_nn(const T* A, int64_t lda, const T* X, T* Y, int64_t m, int64_t n, in
         k_gemm_nn<T><<<(int)cdiv(m, kGemmRows), kThreads, 0, st>>>(A, lda, X, b, Y, b, m, n, b);
 }
 
+// Rank and block size of a refresh of the stream's current shape.
+void refresh_block(const Stream& s, int* k_out, int* b_out) {
+    const int64_t m = s.m, n = s.n;
+    const int k = (int)std::min<int64_t>(s.k_target, std::min(m, n));
+    const int os = s.cfg.oversample >= 0 ? s.cfg.oversample : std::max(8, k / 2);
+    int b = (int)std::min<int64_t>(n, (int64_t)k + os);
+    b = std::min(b, kMaxBlock);
+    b = (int)std::min<int64_t>(b, m);
+    *k_out = k;
+    *b_out = b;
+}
+
+bool gram_form(const Stream& s, int b) { return b != s.n && s.n <= kGcfMaxN && s.cfg.refresh_iters < 0; }
+
 // TruncatedSVD(A_t, k), in two steps so that a check of the error policy can
 // compute it, look at its Ritz values, and commit it only if the policy fires.
 struct RefreshPlan {
@@ -1093,7 +1135,14 @@ struct GcfLayout {
     int ldg = 0, nchunk = 1, nxty = 1;
 };
 
-GcfLayout gcf_layout(int64_t m, int64_t n, size_t base) {
+GcfLayout gcf_layout(int64_t m, int64_t n, size_t base, size_t cap = SIZE_MAX, int nchunk = 0) {
+    if (nchunk == 0) {
+        // fewer row chunks (smaller partial buffer) when the workspace is capped
+        for (int c = ata_chunks(m, ata_tiles(n)); c >= 1; --c) {
+            const GcfLayout t = gcf_layout(m, n, base, SIZE_MAX, c);
+            if (t.total <= cap || c == 1) return t;
+        }
+    }
     GcfLayout g{};
     size_t off = align_up(base, 256);
     auto take = [&](size_t bytes) {
@@ -1103,7 +1152,7 @@ GcfLayout gcf_layout(int64_t m, int64_t n, size_t base) {
     };
     g.ldg = (int)round64(n);
     const int ntile = ata_tiles(n);
-    g.nchunk = ata_chunks(m, ntile);
+    g.nchunk = nchunk;
     g.nxty = (int)cdiv(g.ldg, kXtyRows);
     const size_t blk = sizeof(double) * (size_t)g.ldg * kMaxBlock;
     const size_t sq = sizeof(double) * kMaxBlock * kMaxBlock;
@@ -1177,7 +1226,7 @@ isvd_status refresh_compute_gcf(isvd_engine* e, Stream& s, bool init, hipStream_
                                 const DevHeader& h, int k, int b, WsBuf& wb, int* sweeps_dev) {
     const int64_t m = s.m, n = s.n;
     const WsLayout w = ws_layout(m, n, b, (int)sizeof(T));
-    const GcfLayout g = gcf_layout(m, n, w.total);
+    const GcfLayout g = gcf_layout(m, n, w.total, wb.fixed ? wb.bytes : SIZE_MAX);
     ST_TRY(ensure_ws(wb, g.total));
     char* ws = wb.p;
     const T* A = (const T*)s.A;
@@ -1391,14 +1440,11 @@ isvd_status refresh_compute(isvd_engine* e, Stream& s, bool init, hipStream_t st
         HIP_TRY(hipStreamSynchronize(st));
     }
     const int64_t m = s.m, n = s.n;
-    const int k = std::min<int64_t>(s.k_target, std::min(m, n));
-    const int os = s.cfg.oversample >= 0 ? s.cfg.oversample : std::max(8, k / 2);
-    int b = (int)std::min<int64_t>(n, (int64_t)k + os);
-    b = std::min(b, kMaxBlock);
-    b = (int)std::min<int64_t>(b, m);
+    int k = 0, b = 0;
+    refresh_block(s, &k, &b);
     if (b < k) return fail(ISVD_E_INVAL, "refresh block %d smaller than rank %d", b, k);
     const bool exact = (b == n);
-    if (!exact && n <= kGcfMaxN && s.cfg.refresh_iters < 0)
+    if (gram_form(s, b))
         return refresh_compute_gcf<T>(e, s, init, st, plan, h, k, b, wb, sweeps_dev);
     const int iters = exact ? 0 : s.cfg.refresh_iters >= 0 ? s.cfg.refresh_iters : (init ? 8 : 3);
     WsLayout w = ws_layout(m, n, b, (int)sizeof(T));
@@ -2078,6 +2124,7 @@ isvd_status isvd_engine_create(int32_t device, uint64_t hbm_budget_bytes, isvd_e
     e->budget = hbm_budget_bytes;
     isvd_status rc = ensure_device(e);
     if (rc == ISVD_OK) rc = set_lds_limits();
+    if (rc == ISVD_OK) rc = noalloc_scratch_setup(device);
     if (rc == ISVD_OK) {
         e->ring.resize(64);
         for (Slot& s : e->ring) {
@@ -2575,6 +2622,33 @@ isvd_status isvd_refresh(isvd_engine* e, isvd_id id, int32_t store_reference, vo
     ST_TRY(settle(e, *s, true));
     ST_TRY(join(e, (hipStream_t)hip_stream));
     return do_refresh(e, *s, false, store_reference != 0, (hipStream_t)hip_stream);
+}
+
+isvd_status isvd_refresh_noalloc(isvd_engine* e, isvd_id id, int32_t store_reference, void* hip_stream) {
+    Stream* s = nullptr;
+    ST_TRY(get_stream(e, id, &s));
+    ST_TRY(ensure_device(e));
+    char* base = (e->device >= 0 && e->device < kMaxDevices) ? g_scratch_ptr[e->device] : nullptr;
+    if (!base) return fail(ISVD_E_DEVICE, "no allocation-free scratch on device %d", e->device);
+    if (!store_reference && s->TM)
+        return fail(ISVD_E_INVAL, "keeping the old reference of an angle-policy stream needs tracker workspace, "
+                                  "which only isvd_refresh allocates");
+    int k = 0, b = 0;
+    refresh_block(*s, &k, &b);
+    if (b < k) return fail(ISVD_E_INVAL, "refresh block %d smaller than rank %d", b, k);
+    const WsLayout w = ws_layout(s->m, s->n, b, s->esz);
+    const size_t need = gram_form(*s, b) ? gcf_layout(s->m, s->n, w.total, kNoAllocScratchBytes).total : w.total;
+    if (need > kNoAllocScratchBytes)
+        return fail(ISVD_E_NOMEM, "the refresh of a %lld x %lld stream needs %zu bytes of workspace; the "
+                                  "allocation-free scratch holds %zu",
+                    (long long)s->m, (long long)s->n, need, kNoAllocScratchBytes);
+    ST_TRY(settle(e, *s, true));
+    ST_TRY(join(e, (hipStream_t)hip_stream));
+    WsBuf wk;
+    wk.p = base;
+    wk.bytes = kNoAllocScratchBytes;
+    wk.fixed = true;
+    return do_refresh(e, *s, false, store_reference != 0, (hipStream_t)hip_stream, nullptr, nullptr, nullptr, &wk);
 }
 
 isvd_status isvd_metrics(isvd_engine* e, isvd_id id, int32_t compute_exact, void* hip_stream, isvd_metrics_t* out) {

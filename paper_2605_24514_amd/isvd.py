@@ -92,7 +92,7 @@ class CRisk(ctypes.Structure):
 ROT_VARIANTS = [(256, 1, True), (512, 1, True), (1024, 1, True), (1024, 2, False), (2048, 2, False)]
 
 EXPORTS = ["isvd_engine_create", "isvd_engine_destroy", "isvd_stream_bytes", "isvd_init", "isvd_init_from_factors",
-           "isvd_append_row", "isvd_append_col", "isvd_update_entry", "isvd_refresh", "isvd_metrics",
+           "isvd_append_row", "isvd_append_col", "isvd_update_entry", "isvd_refresh", "isvd_refresh_noalloc", "isvd_metrics",
            "isvd_get_factors", "isvd_get_matrix", "isvd_shape", "isvd_release", "isvd_tick",
            "isvd_profile", "isvd_profile_read", "isvd_autotune", "isvd_set_rotation_variant", "isvd_sync", "isvd_stream_busy", "isvd_rotation_stream", "isvd_set_pipelining",
            "isvd_server_create", "isvd_server_destroy", "isvd_server_clock", "isvd_server_error",
@@ -123,6 +123,7 @@ def load_library(path=LIB_PATH):
         "isvd_append_col": (i32, [vp, i64, vp, i64, i32, i32, vp]),
         "isvd_update_entry": (i32, [vp, i64, i64, i64, ctypes.c_double, vp]),
         "isvd_refresh": (i32, [vp, i64, i32, vp]),
+        "isvd_refresh_noalloc": (i32, [vp, i64, i32, vp]),
         "isvd_metrics": (i32, [vp, i64, i32, vp, ctypes.POINTER(CMetrics)]),
         "isvd_causal_center": (i32, [vp, vp, i64, i64, i32, vp, i64, vp]),
         "isvd_covariance": (i32, [vp, i64, vp, i64, vp]),
@@ -345,6 +346,12 @@ class Engine:
     def refresh(self, sid, store_reference=True, stream=None):
         self._check(self._lib.isvd_refresh(self._h, sid, 1 if store_reference else 0, _stream_ptr(stream)),
                     "isvd_refresh")
+
+    def refresh_noalloc(self, sid, store_reference=True, stream=None):
+        """isvd_refresh with its workspace in the library's static device array
+        (no device allocation)."""
+        self._check(self._lib.isvd_refresh_noalloc(self._h, sid, 1 if store_reference else 0, _stream_ptr(stream)),
+                    "isvd_refresh_noalloc")
 
     def metrics(self, sid, exact=False, stream=None):
         out = CMetrics()
