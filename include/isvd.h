@@ -389,10 +389,12 @@ isvd_status isvd_set_pipelining(isvd_engine* eng, int32_t enable);
  * streams when enabling.  Errors: INVAL, DEVICE. */
 isvd_status isvd_set_deferred_u(isvd_engine* eng, int32_t enable, void* hip_stream);
 
-/* The engine's rotation stream (a hipStream_t), e.g. to record an event
- * after the last tick's work: every update of a tick is done when that
- * stream has passed it (refreshes it fired may still run; see isvd_tick).
- * With deferred U a tick does not use it and ends on the caller's stream. */
+/* The engine's rotation stream (a hipStream_t).  A pipelined tick (explicit
+ * U, row appends of streams without a refresh policy) leaves its U rotations
+ * on it; every other tick -- deferred U included -- ends on the caller's
+ * stream.  So a tick's updates are all done once both the caller's stream
+ * and this stream have passed it: record an event on each (refreshes the
+ * tick fired may still run; see isvd_tick). */
 isvd_status isvd_rotation_stream(isvd_engine* eng, void** out);
 
 /* GPU time of one kernel launch of the update sequence, collected while

@@ -14,6 +14,7 @@
 // reference event taken when the server was created.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cstring>
 #include <deque>
@@ -44,8 +45,12 @@ struct Ticket {
     std::deque<Pending> queue;
 };
 
+// A tick's work ends on the rotation lane (U rotations left pending by a
+// pipelined tick) or on the server's stream (every other form, deferred U
+// included): its completion is the later of two events, one on each.
 struct InFlight {
-    hipEvent_t done = nullptr;
+    hipEvent_t done = nullptr;    // on the rotation lane
+    hipEvent_t done2 = nullptr;   // on the server's stream
     double launch_s = 0.0;
     std::vector<Pending> reqs;
     std::vector<int64_t> tickets;
@@ -82,6 +87,17 @@ isvd_status sfail(isvd_server* s, isvd_status st, const char* msg) {
     return st;
 }
 
+// A stream that has completed its lifetime of requests (successful or not)
+// and has nothing queued releases its HBM.
+isvd_status retire_if_done(isvd_server* s, Ticket& t) {
+    if (t.lifetime > 0 && t.completed >= t.lifetime && t.queue.empty() && t.state == 1) {
+        if (isvd_release(s->eng, t.id) != ISVD_OK) return ISVD_E_DEVICE;
+        t.state = 2;
+        s->used -= t.bytes;
+    }
+    return ISVD_OK;
+}
+
 void complete(isvd_server* s, const Pending& p, int64_t ticket, int32_t status, double launch_s, double done_s) {
     isvd_completion c{};
     c.req = p.req;
@@ -100,24 +116,24 @@ isvd_status finish_oldest(isvd_server* s, bool block, bool* finished) {
     *finished = false;
     if (s->inflight.empty()) return ISVD_OK;
     InFlight& f = s->inflight.front();
-    hipError_t q = block ? hipEventSynchronize(f.done) : hipEventQuery(f.done);
-    if (q == hipErrorNotReady) return ISVD_OK;
-    if (q != hipSuccess) return sfail(s, ISVD_E_DEVICE, "tick completion event failed");
     float ms = 0.f;
-    if (hipEventElapsedTime(&ms, s->ref, f.done) != hipSuccess) return sfail(s, ISVD_E_DEVICE, "event timing failed");
+    for (hipEvent_t ev : {f.done, f.done2}) {
+        hipError_t q = block ? hipEventSynchronize(ev) : hipEventQuery(ev);
+        if (q == hipErrorNotReady) return ISVD_OK;
+        if (q != hipSuccess) return sfail(s, ISVD_E_DEVICE, "tick completion event failed");
+        float e_ms = 0.f;
+        if (hipEventElapsedTime(&e_ms, s->ref, ev) != hipSuccess) return sfail(s, ISVD_E_DEVICE, "event timing failed");
+        ms = std::max(ms, e_ms);
+    }
     const double done_s = s->ref_s + 1e-3 * ms;
     for (size_t q2 = 0; q2 < f.reqs.size(); ++q2) {
         complete(s, f.reqs[q2], f.tickets[q2], ISVD_OK, f.launch_s, done_s);
         Ticket& t = s->tickets[f.tickets[q2]];
         t.completed += 1;
-        if (t.lifetime > 0 && t.completed >= t.lifetime && t.queue.empty() && t.state == 1) {
-            // lifetime complete: release the stream and its HBM
-            if (isvd_release(s->eng, t.id) != ISVD_OK) return sfail(s, ISVD_E_DEVICE, "release failed");
-            t.state = 2;
-            s->used -= t.bytes;
-        }
+        if (retire_if_done(s, t) != ISVD_OK) return sfail(s, ISVD_E_DEVICE, "release failed");
     }
     s->free_events.push_back(f.done);
+    s->free_events.push_back(f.done2);
     s->inflight.pop_front();
     *finished = true;
     return ISVD_OK;
@@ -159,8 +175,10 @@ isvd_status isvd_server_create(isvd_engine* eng, const isvd_server_config* cfg, 
 isvd_status isvd_server_destroy(isvd_server* s) {
     if (!s) return ISVD_OK;
     for (InFlight& f : s->inflight) {
-        (void)hipEventSynchronize(f.done);
-        (void)hipEventDestroy(f.done);
+        for (hipEvent_t ev : {f.done, f.done2}) {
+            (void)hipEventSynchronize(ev);
+            (void)hipEventDestroy(ev);
+        }
     }
     for (hipEvent_t ev : s->free_events) (void)hipEventDestroy(ev);
     if (s->ref) (void)hipEventDestroy(s->ref);
@@ -267,6 +285,8 @@ isvd_status isvd_server_step(isvd_server* s, int32_t* launched) {
         t.queue.pop_front();
         if (!shape_ok(s, t, p.r)) {
             complete(s, p, (int64_t)ti, ISVD_E_SHAPE, tnow, tnow);
+            t.completed += 1;
+            if (retire_if_done(s, t) != ISVD_OK) return sfail(s, ISVD_E_DEVICE, "release failed");
             continue;
         }
         p.r.id = t.id;
@@ -278,19 +298,26 @@ isvd_status isvd_server_step(isvd_server* s, int32_t* launched) {
     if (batch.empty()) return ISVD_OK;
     isvd_status rc = isvd_tick(s->eng, (int32_t)batch.size(), batch.data(), s->st);
     if (rc != ISVD_OK) {
-        for (size_t q = 0; q < f.reqs.size(); ++q) complete(s, f.reqs[q], f.tickets[q], rc, tnow, tnow);
+        for (size_t q = 0; q < f.reqs.size(); ++q) {
+            complete(s, f.reqs[q], f.tickets[q], rc, tnow, tnow);
+            Ticket& t = s->tickets[f.tickets[q]];
+            t.completed += 1;
+            (void)retire_if_done(s, t);
+        }
         return sfail(s, rc, "tick failed");
     }
-    if (s->free_events.empty()) {
+    while (s->free_events.size() < 2) {
         hipEvent_t ev;
         if (hipEventCreate(&ev) != hipSuccess) return sfail(s, ISVD_E_DEVICE, "event creation failed");
         s->free_events.push_back(ev);
     }
     f.done = s->free_events.back();
     s->free_events.pop_back();
+    f.done2 = s->free_events.back();
+    s->free_events.pop_back();
     void* lane = nullptr;
     if (isvd_rotation_stream(s->eng, &lane) != ISVD_OK ||
-        hipEventRecord(f.done, (hipStream_t)lane) != hipSuccess)
+        hipEventRecord(f.done, (hipStream_t)lane) != hipSuccess || hipEventRecord(f.done2, s->st) != hipSuccess)
         return sfail(s, ISVD_E_DEVICE, "tick event failed");
     f.launch_s = tnow;
     if (launched) *launched = (int32_t)batch.size();

@@ -490,8 +490,9 @@ class Engine:
                     "isvd_set_deferred_u")
 
     def rotation_stream(self):
-        """Handle (int) of the engine's rotation stream; wrap it with
-        torch.cuda.ExternalStream to record events after a tick's last work."""
+        """Handle (int) of the engine's rotation stream.  A tick's updates are
+        done once both the caller's stream and this stream have passed it
+        (wrap it with torch.cuda.ExternalStream and record an event on each)."""
         out = ctypes.c_void_p()
         self._check(self._lib.isvd_rotation_stream(self._h, ctypes.byref(out)), "isvd_rotation_stream")
         return out.value or 0

@@ -142,3 +142,28 @@ def test_disable_makes_u_explicit(isvd):
             _apply(eng, sid, ev)
             o.step(ev)
         _check(eng, sid, o, "after disable")
+
+
+def test_longest_deferral_period(isvd):
+    """k = 8 on 16400 rows: the flush period m / (8 k) reaches its cap of
+    256, so up to 255 row appends pile up in W before an explicit rotation.
+    600 batched row-append ticks (more than two full periods, the bench's
+    regime) against the oracle, with U orthonormal to 1e-5 at the end and
+    after each period."""
+    import torch
+    k, m0, n0, T = 8, 16400, 40, 600
+    fs = FactorStream(seed=61, stream=0, n0=n0, K=5)
+    A0 = fs.initial(m0)
+    events = fs.materialize([ROW] * T, m0=m0)
+    o = OracleEngine(A0, k, tol_rel=1e-5, cgs2=True)
+    with isvd.Engine() as eng:
+        eng.set_deferred_u(True)
+        sid = eng.init(A0, k, "fp32", m_cap=m0 + T, n_cap=n0, oversample=64)
+        pays = [torch.tensor(ev.vec, dtype=torch.float32, device="cuda") for ev in events]
+        for t, ev in enumerate(events):
+            eng.tick([(sid, isvd.ROW, pays[t])])
+            o.step(ev)
+            if t in (254, 511):
+                _check(eng, sid, o, "after %d rows" % (t + 1))
+        c = _check(eng, sid, o, "end")
+        print(c)

@@ -146,3 +146,79 @@ def test_mismatched_request_completes_with_shape_error(env):
         srv.drain()
         comp = sorted(srv.poll(), key=lambda c: c["req"])
         assert [c["status"] for c in comp] == [-2, 0]
+
+
+def test_completion_waits_for_the_tick_under_deferred_u(env):
+    """With deferred U a tick's work ends on the server's stream, not on the
+    rotation lane: a completion the server reports must find that stream
+    idle (nothing else was queued on it after the tick)."""
+    torch, isvd = env
+    nst, m0, n0, k = 24, 20000, 600, 64
+    st = torch.cuda.Stream()
+    with isvd.Engine() as eng:
+        eng.set_deferred_u(True)
+        with isvd.Server(eng, max_inflight=4, stream=st) as srv:
+            tickets = []
+            for s in range(nst):
+                A0 = torch.randn((m0, n0), generator=torch.Generator(device="cuda").manual_seed(100 + s),
+                                 device="cuda", dtype=torch.float32)
+                tickets.append(srv.add_stream(A0, k, m_cap=m0 + 8, n_cap=n0, oversample=96))
+            rows = [torch.randn(n0, device="cuda", dtype=torch.float32) for _ in range(nst)]
+            # admit and initialise every stream first
+            t0 = srv.clock()
+            for s in range(nst):
+                srv.submit(tickets[s], ROW, rows[s], t0)
+            while srv.stats()["queued"] > 0:
+                srv.step()
+            srv.drain()
+            srv.poll()
+            st.synchronize()
+            # one tick of nst row appends, then poll without blocking
+            t0 = srv.clock()
+            for s in range(nst):
+                srv.submit(tickets[s], ROW, rows[s], t0)
+            srv.step()
+            seen = []
+            for _ in range(200_000):
+                srv.step()                  # nothing queued: only stamps finished ticks
+                seen = srv.poll()
+                if seen:
+                    break
+            assert seen, "no completion"
+            assert st.query(), "completion reported while the tick still ran on the server's stream"
+            srv.drain()
+
+
+def test_stream_with_a_rejected_request_retires(env):
+    """A request that completes with an error still counts toward the
+    stream's lifetime, so the stream retires and frees its budget for the
+    next one (FIFO admission would otherwise stall)."""
+    torch, isvd = env
+    data = _workload(3, seed=14)
+    (A0, k, evs), (B0, kb, evb) = data[0], data[1]
+    with isvd.Engine() as eng:
+        ca = isvd.Engine.config(A0.shape[0], A0.shape[1], k, "fp32", m_cap=A0.shape[0] + 4, n_cap=A0.shape[1] + 4,
+                                oversample=96)
+        cb = isvd.Engine.config(B0.shape[0], B0.shape[1], kb, "fp32", m_cap=B0.shape[0] + 4, n_cap=B0.shape[1] + 4,
+                                oversample=96)
+        budget = max(eng.stream_bytes(ca), eng.stream_bytes(cb))      # one stream at a time
+        with isvd.Server(eng, hbm_budget=budget) as srv:
+            ta = srv.add_stream(torch.tensor(A0, dtype=torch.float32, device="cuda"), k, m_cap=A0.shape[0] + 4,
+                                n_cap=A0.shape[1] + 4, lifetime=2, oversample=96)
+            tb = srv.add_stream(torch.tensor(B0, dtype=torch.float32, device="cuda"), kb, m_cap=B0.shape[0] + 4,
+                                n_cap=B0.shape[1] + 4, lifetime=1, oversample=96)
+            bad = torch.zeros(A0.shape[1] + 3, dtype=torch.float32, device="cuda")
+            good = torch.tensor(FactorStream(seed=12, stream=0, n0=A0.shape[1], K=5).row(A0.shape[0], A0.shape[1]),
+                                dtype=torch.float32, device="cuda")
+            t0 = srv.clock()
+            srv.submit(ta, ROW, bad, t0)
+            srv.submit(ta, ROW, good, t0)
+            srv.submit(tb, ENTRY, (0, 0, 0.5), t0)
+            for _ in range(1000):
+                srv.step()
+                if srv.stats()["retired"] == 2:
+                    break
+            srv.drain()
+            comp = sorted(srv.poll(), key=lambda c: c["req"])
+            assert srv.stats()["retired"] == 2
+            assert [c["status"] for c in comp] == [-2, 0, 0]
