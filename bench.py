@@ -28,9 +28,11 @@ import numpy as np
 METRIC = "batched rank-k updates/sec + p99 tick latency vs plain path at rel err ≤2e-5"
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
 K_FACTORS = 5
 SEED = 3
 PROF_TICKS = 20      # extra profiled ticks (per-launch times) after the comparison
+CPU_MAX_ROUNDS = 2000   # cap of the oracle baseline's rounds (its time budget ends it first)
 
 
 def log(*a):
@@ -107,23 +109,29 @@ def pctl(a, q):
 
 
 def cpu_baseline(params, seconds, torch):
-    """Time the FP64 oracle (as it stands) on a bounded sample of the workload."""
+    """Time the FP64 oracle's row append (Alg. A1, oracle.brand.row_append, as
+    it stands) on a bounded sample of the workload, with A pre-reserved: each
+    appended row is written into a preallocated m_cap x n array, as the GPU
+    engine does, instead of the oracle engine loop's np.vstack of the dense A
+    (which copies all of A on every append and would dominate the time)."""
     from threadpoolctl import threadpool_info
-    from oracle.engine import OracleEngine
-    from synth import device as sdev, ROW, Event
+    from oracle import brand
+    from synth import device as sdev
     sample = list(range(min(8, len(params))))
     rng = np.random.default_rng(0)
-    engines, rows = [], []
+    states, rows, bufs = [], [], []
     for s in sample:
         m0, n0, k = params[s]
         A = torch.empty((m0, n0), dtype=torch.float64, device="cuda")
         sdev.rows_into(A, 0, m0, n0, SEED, s, K_FACTORS)
-        Ah = A.cpu().numpy()
+        Abuf = np.empty((m0 + CPU_MAX_ROUNDS, n0))
+        Abuf[:m0] = A.cpu().numpy()
         del A
         U, _ = np.linalg.qr(rng.standard_normal((m0, k)))
         V, _ = np.linalg.qr(rng.standard_normal((n0, k)))
         sig = np.sort(rng.uniform(1.0, 100.0, k))[::-1]
-        engines.append(OracleEngine.from_state(Ah, U, sig, V, cgs2=True))
+        states.append([U, sig, V, m0, k])
+        bufs.append(Abuf)
         R = torch.empty((64, n0), dtype=torch.float64, device="cuda")
         sdev.rows_into(R, m0, 64, n0, SEED, s, K_FACTORS)
         rows.append(R.cpu().numpy())
@@ -131,20 +139,26 @@ def cpu_baseline(params, seconds, torch):
     c0 = time.process_time()
     r = 0
     while True:
-        for q, eng in enumerate(engines):
-            eng.apply(Event(ROW, eng.t + 1, vec=rows[q][r % 64]))
+        for q, st in enumerate(states):
+            U, sig, V, m, k = st
+            x = rows[q][r % 64]
+            bufs[q][m] = x
+            U, sig, V, _ = brand.row_append(U, sig, V, x, k, 1e-10, cgs2=True)
+            st[:] = [U, sig, V, m + 1, k]
             done += 1
         r += 1
-        if time.perf_counter() - t0 > seconds or r >= 64:
+        if time.perf_counter() - t0 > seconds or r >= CPU_MAX_ROUNDS:
             break
     wall = time.perf_counter() - t0
     cpu = time.process_time() - c0
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     mean_m = float(np.mean([params[s][0] for s in sample]))
     return {"value": done / wall, "unit": "updates/s", "cores": int(threads), "kind": "oracle",
-            "sample": "%d row appends over the first %d streams of the workload (%d rounds, mean m %.0f), "
-                      "FP64 oracle engine loop incl. its dense A append; started from random orthonormal "
-                      "factors of each stream's shape (update cost does not depend on their values)"
+            "sample": "%d row appends over the first %d streams of the workload (%d rounds, mean m %.0f; the 64 "
+                      "generated rows of each stream appended in turn): the "
+                      "FP64 oracle's Alg. A1 row append (oracle.brand.row_append, CGS2) with A pre-reserved "
+                      "(each row written in place); started from random orthonormal factors of each stream's "
+                      "shape (the update's cost does not depend on their values); cores = BLAS threads"
                       % (done, len(sample), r, mean_m),
             "wall_s": wall, "cpu_s": cpu, "nproc": os.cpu_count()}
 
@@ -402,6 +416,8 @@ def main():
     ap.add_argument("--finance", action="store_true", help="time the finance readout of a 60-asset returns stream")
     ap.add_argument("--explicit-u", action="store_true",
                     help="rotate U on every row append (no deferred U = U0 W)")
+    ap.add_argument("--no-explicit", action="store_true",
+                    help="skip the explicit-U comparison that follows the deferred headline")
     ap.add_argument("--serve-streams", type=int, default=1024)
     ap.add_argument("--serve-lifetime", type=int, default=200)
     ap.add_argument("--serve-rate", type=float, default=200000.0)
@@ -433,6 +449,10 @@ def main():
     params = stream_params(args.streams)
     W, K = args.warmup, args.steps
     T = W + K
+    # the explicit-U comparison runs W + K more ticks (plus a profiled pass)
+    # on the same streams after the chosen form, with fresh rows
+    TX = 0 if (args.explicit_u or args.no_explicit) else W + K
+    T_pay = T + TX
     log("streams %d, ticks %d (+%d warmup)" % (len(params), K, W))
 
     eng64 = isvd.Engine()
@@ -449,7 +469,7 @@ def main():
             sid64.append(eng64.init(A0, k, "fp64", m_cap=m0 + T, n_cap=n0, refresh_iters=2 if args.refresh_iters is None else args.refresh_iters,
                                     stream=dev_stream))
             U, S, V = eng64.factors(sid64[-1], stream=dev_stream)
-            sid32.append(eng32.init_from_factors(A0, U, S, V, "fp32", m_cap=m0 + T + PROF_TICKS, n_cap=n0,
+            sid32.append(eng32.init_from_factors(A0, U, S, V, "fp32", m_cap=m0 + T_pay + 2 * PROF_TICKS, n_cap=n0,
                                                  stream=dev_stream))
             if s % 64 == 63:
                 log("  init %d/%d streams (%.1fs)" % (s + 1, len(params), time.perf_counter() - t_init))
@@ -459,13 +479,13 @@ def main():
     # row payloads for every tick, resident in HBM before timing
     pay32, pay64 = [], []
     for s, (m0, n0, k) in enumerate(params):
-        p64 = torch.empty((T, n0), dtype=torch.float64, device="cuda")
-        sdev.rows_into(p64, m0, T, n0, SEED, s, K_FACTORS)
+        p64 = torch.empty((T_pay, n0), dtype=torch.float64, device="cuda")
+        sdev.rows_into(p64, m0, T_pay, n0, SEED, s, K_FACTORS)
         pay64.append(p64)
         pay32.append(p64.to(torch.float32))
     torch.cuda.synchronize()
     reqs = [isvd.Engine.tick_requests([(sid32[s], isvd.ROW, pay32[s][t]) for s in range(len(params))])
-            for t in range(T)]
+            for t in range(T_pay)]
     log("init %.1fs; payloads ready" % init_s)
 
     # ---------------------------------------------------- chosen form: batched FP32
@@ -476,34 +496,37 @@ def main():
     tune = eng32.autotune(stream=dev_stream)
     log("rotation autotune (bucket: variant): %s" % {kc: v for kc, (v, _) in tune.items()})
     rot_lane = torch.cuda.ExternalStream(eng32.rotation_stream())
-    # a tick ends on the rotation stream, or, with deferred U (no rotation
-    # lanes), on the caller's stream
-    end_lane = dev_stream if not args.explicit_u else rot_lane
-    for t in range(W):
-        eng32.tick_raw(reqs[t], stream=dev_stream)
-    eng32.sync(stream=dev_stream)
-    torch.cuda.synchronize()
-    # per tick: start on the caller's stream, end when the stream that
-    # finishes every tick has passed it
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    host_s = 0.0
-    for q in range(K):
-        evs[q][0].record(dev_stream)
-        h0 = time.perf_counter()
-        eng32.tick_raw(reqs[W + q], stream=dev_stream)
-        host_s += time.perf_counter() - h0
-        evs[q][1].record(end_lane)
-    eng32.sync(stream=dev_stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    tick_ms = [a.elapsed_time(b) for a, b in evs]
+
+    def timed_ticks(first, deferred_form):
+        """W warm-up and K timed ticks of requests reqs[first:]; per tick from
+        an event on the caller's stream before it to events on both streams a
+        tick can end on (the caller's stream; the rotation lane, where a
+        pipelined explicit-U tick leaves its U rotations)."""
+        for t in range(W):
+            eng32.tick_raw(reqs[first + t], stream=dev_stream)
+        eng32.sync(stream=dev_stream)
+        torch.cuda.synchronize()
+        evs = [tuple(torch.cuda.Event(enable_timing=True) for _ in range(3)) for _ in range(K)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        host_s = 0.0
+        for q in range(K):
+            evs[q][0].record(dev_stream)
+            h0 = time.perf_counter()
+            eng32.tick_raw(reqs[first + W + q], stream=dev_stream)
+            host_s += time.perf_counter() - h0
+            evs[q][1].record(dev_stream)
+            evs[q][2].record(rot_lane)
+        eng32.sync(stream=dev_stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        tick_ms = [max(a.elapsed_time(b), a.elapsed_time(c)) for a, b, c in evs]
+        return wall, tick_ms, host_s / K
+
+    wall, tick_ms, host_per_tick = timed_ticks(0, not args.explicit_u)
     value = len(params) * K / wall
     log("batched FP32: %.0f updates/s, tick latency p50 %.3f ms p99 %.3f ms; host %.3f ms per tick call"
-        % (value, pctl(tick_ms, 50), pctl(tick_ms, 99), host_s / K * 1e3))
-
-
+        % (value, pctl(tick_ms, 50), pctl(tick_ms, 99), host_per_tick * 1e3))
 
     # ------------------------------------------------------- plain form: FP64, one stream per launch
     plain = None
@@ -537,81 +560,117 @@ def main():
         err["streams_compared"] = int(len(pick))
         log("FP32 vs FP64 after %d ticks: %s" % (T, err))
 
-    # per-launch GPU times from a separate profiled pass of PROF_TICKS more
-    # ticks (after the comparison; the events around each launch add a little
-    # time of their own)
-    eng32.profile(True)
-    for q in range(PROF_TICKS):
-        eng32.tick_raw(reqs[W + q % K], stream=dev_stream)
-    eng32.sync(stream=dev_stream)
-    torch.cuda.synchronize()
-    eng32.profile(False)
-    prof = eng32.profile_read()
-    Kp = PROF_TICKS
-    # roofline of the dominant kernel: the rotation launch of the widest bucket
-    by_launch = {}
-    for r in prof:
-        by_launch.setdefault((r["phase"], r["kc"]), []).append(r["ms"])
-    phase_ms = {}
-    for (ph, kc), v in by_launch.items():
-        phase_ms.setdefault(ph, 0.0)
-        phase_ms[ph] += float(np.sum(v)) / Kp
-    mid = W + K + (Kp - 1) / 2.0
+    names = {0: "k_proj (pass 1)", 1: "k_proj (pass 2)", 2: "k_core", 3: "k_rotate_mfma_t (U)",
+             4: "k_rotate_mfma_t (V)"}
     bucket = lambda k: 8 if k <= 8 else 16 if k <= 16 else 32 if k <= 32 else 64 if k <= 64 else 128
-    mid_all = W + (K - 1) / 2.0
-    deferred = not args.explicit_u
-    all_tick_bytes = sum(tick_bytes(m0 + mid_all, n0, k, 4, deferred) for (m0, n0, k) in params)
-    if not deferred:
-        # dominant kernel: the U rotation of the widest bucket (HBM-bound)
-        kdom = max(kc for (ph, kc) in by_launch if ph == 3)
-        dom_ms = float(np.mean(by_launch[(3, kdom)]))
-        dom_bytes = sum(rot_u_bytes(m0 + mid, k, 4) for (m0, n0, k) in params if bucket(k) == kdom)
-        achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
-        dom_ratio = (recorded_traffic_ratio(PMC_ROTATE, "traffic_over_algorithmic_variant_%d" % tune[kdom][0])
-                     if kdom in tune else None)
-        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": (int(dom_ratio * dom_bytes) if dom_ratio is not None and kdom == 64 else None),
-                    "traffic_note": "HBM bytes per launch: rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated, "
-                                    "ratio to algorithmic bytes from profiles/rotate_u_kc64_tick512_pmc.md",
-                    "kernel": "k_rotate_mfma_t<%d> (U rotation, variant %d)" % (kdom, tune[kdom][0] if kdom in tune else -1),
-                    "launch_ms": round(dom_ms, 4), "bytes_per_launch": int(dom_bytes)}
-    else:
-        # dominant kernel: the longest launch of the tick -- with deferred U
-        # the append core of the widest bucket (one workgroup per stream,
-        # FP64), priced by its W update: W A and A^T W^-1, 4 k^3 flops per append
+
+    def bound_of(byts, flops, flops_peak_tf, ms):
+        """Roofline of one launch by the max(bytes / BW, flops / peak) rule."""
+        t_b = byts / (HBM_PEAK_GBS * 1e9)
+        t_f = flops / (flops_peak_tf * 1e12)
+        if t_b >= t_f:
+            ach = byts / (ms * 1e-3) / 1e9
+            return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(t_b / (ms * 1e-3), 5)}
+        ach = flops / (ms * 1e-3) / 1e12
+        return {"bound": "mfma", "achieved": round(ach, 3), "peak": flops_peak_tf, "unit": "TFLOP/s",
+                "frac": round(t_f / (ms * 1e-3), 5)}
+
+    def profile_pass(first, deferred_form, m_off):
+        """PROF_TICKS more ticks with per-launch HIP events (requests
+        reqs[first + q % K]); the dominant launch's roofline and the mean time
+        per tick of each phase.  m_off: rows appended before the pass."""
+        eng32.profile(True)
+        for q in range(PROF_TICKS):
+            eng32.tick_raw(reqs[first + q % K], stream=dev_stream)
+        eng32.sync(stream=dev_stream)
+        torch.cuda.synchronize()
+        eng32.profile(False)
+        prof = eng32.profile_read()
+        by_launch = {}
+        for r in prof:
+            by_launch.setdefault((r["phase"], r["kc"]), []).append(r["ms"])
+        phase_ms = {}
+        for (ph, kc), v in by_launch.items():
+            phase_ms.setdefault(ph, 0.0)
+            phase_ms[ph] += float(np.sum(v)) / PROF_TICKS
+        mid = m_off + (PROF_TICKS - 1) / 2.0
+        if not deferred_form:
+            # dominant kernel: the U rotation of the widest bucket (HBM-bound:
+            # 16 flop/B at k = 64 against the FP32 balance of 19.7)
+            kdom = max(kc for (ph, kc) in by_launch if ph == 3)
+            dom_ms = float(np.mean(by_launch[(3, kdom)]))
+            sel = [(m0, n0, k) for (m0, n0, k) in params if bucket(k) == kdom]
+            dom_bytes = sum(rot_u_bytes(m0 + mid, k, 4) for (m0, n0, k) in sel)
+            dom_flops = sum(2.0 * (m0 + mid) * k * k for (m0, n0, k) in sel)
+            roof = bound_of(dom_bytes, dom_flops, FP32_PEAK_TFLOPS, dom_ms)
+            dom_ratio = (recorded_traffic_ratio(PMC_ROTATE, "traffic_over_algorithmic_variant_%d" % tune[kdom][0])
+                         if kdom in tune else None)
+            roof.update({"traffic": (int(dom_ratio * dom_bytes) if dom_ratio is not None and kdom == 64 else None),
+                         "traffic_note": "HBM bytes per launch: rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated, "
+                                         "ratio to algorithmic bytes from profiles/rotate_u_kc64_tick512_pmc.md",
+                         "kernel": "k_rotate_mfma_t<%d> (U rotation, variant %d)"
+                                   % (kdom, tune[kdom][0] if kdom in tune else -1),
+                         "launch_ms": round(dom_ms, 4), "bytes_per_launch": int(dom_bytes),
+                         "flops_per_launch": dom_flops})
+            return roof, phase_ms
+        # deferred U: the longest launch of the tick
         (ph, kdom) = max(by_launch, key=lambda key: float(np.mean(by_launch[key])))
         dom_ms = float(np.mean(by_launch[(ph, kdom)]))
-        names = {0: "k_proj (pass 1)", 1: "k_proj (pass 2)", 2: "k_core", 3: "k_rotate_mfma_t (U)",
-                 4: "k_rotate_mfma_t (V)"}
         sel = [(m0, n0, k) for (m0, n0, k) in params if bucket(k) == kdom]
         if ph == 2:
+            # the append core: its W update (W A and A^T W^-1, 4 k^3 flops per
+            # append on the FP64 matrix cores) and its bytes (W, W^-1 read and
+            # written, V's rotation written)
             flops = sum(4.0 * k ** 3 for (m0, n0, k) in sel)
-            achieved = flops / (dom_ms * 1e-3) / 1e12
             cbytes = sum(core_bytes(k) for (m0, n0, k) in sel)
+            roof = bound_of(cbytes, flops, FP64_PEAK_TFLOPS, dom_ms)
             cratio = recorded_traffic_ratio(PMC_CORE, "traffic_over_algorithmic") if kdom == 64 else None
-            roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                        "frac": round(achieved / FP64_PEAK_TFLOPS, 5),
-                        "traffic": int(cratio * cbytes) if cratio is not None else None,
-                        "traffic_note": "HBM bytes per launch: rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated, "
-                                        "ratio to algorithmic bytes from profiles/core_kc64_tick512_pmc.md",
-                        "kernel": "k_core<float, %d> (append core: secular SVD + deferred-U update, FP64)" % kdom,
-                        "launch_ms": round(dom_ms, 4), "flops_per_launch": flops, "bytes_per_launch": int(cbytes),
-                        "note": "latency-bound: one workgroup per stream; flops counted: the W update's two "
-                                "k x k products per append"}
+            roof.update({"traffic": int(cratio * cbytes) if cratio is not None else None,
+                         "traffic_note": "HBM bytes per launch: rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated, "
+                                         "ratio to algorithmic bytes from profiles/core_kc64_tick512_pmc.md",
+                         "kernel": "k_core<float, %d> (append core: secular SVD + deferred-U update, FP64)" % kdom,
+                         "launch_ms": round(dom_ms, 4), "flops_per_launch": flops, "bytes_per_launch": int(cbytes),
+                         "note": "one workgroup per stream; bound by max(bytes / 8 TB/s, flops / FP64 matrix peak)"})
+            return roof, phase_ms
+        if ph == 4:
+            byts = sum(4.0 * 2 * n0 * k + 8.0 * n0 for (m0, n0, k) in sel)
+        elif ph == 3:
+            byts = sum(rot_u_bytes(m0 + mid, k, 4) / max(1, min(256, int(m0 + mid) // (8 * k)))
+                       for (m0, n0, k) in sel)
         else:
-            if ph == 4:
-                byts = sum(4.0 * 2 * n0 * k + 8.0 * n0 for (m0, n0, k) in sel)
-            elif ph == 3:
-                byts = sum(rot_u_bytes(m0 + mid, k, 4) / max(1, min(256, int(m0 + mid) // (8 * k)))
-                           for (m0, n0, k) in sel)
-            else:
-                byts = sum(4.0 * n0 * k + 4.0 * n0 for (m0, n0, k) in sel)
-            achieved = byts / (dom_ms * 1e-3) / 1e9
-            roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                        "kernel": "%s, bucket %d" % (names[ph], kdom), "launch_ms": round(dom_ms, 4),
-                        "bytes_per_launch": int(byts)}
+            byts = sum(4.0 * n0 * k + 4.0 * n0 for (m0, n0, k) in sel)
+        roof = bound_of(byts, 0.0, FP32_PEAK_TFLOPS, dom_ms)
+        roof.update({"traffic": None, "kernel": "%s, bucket %d" % (names[ph], kdom), "launch_ms": round(dom_ms, 4),
+                     "bytes_per_launch": int(byts)})
+        return roof, phase_ms
+
+    deferred = not args.explicit_u
+    roofline, phase_ms = profile_pass(W, deferred, W + K)
+    mid_all = W + (K - 1) / 2.0
+    all_tick_bytes = sum(tick_bytes(m0 + mid_all, n0, k, 4, deferred) for (m0, n0, k) in params)
+
+    # ---------------------------------------- the same streams with U rotated on every append
+    explicit = None
+    if TX:
+        eng32.set_deferred_u(False, stream=dev_stream)
+        xwall, xtick_ms, xhost = timed_ticks(T, False)
+        xvalue = len(params) * K / xwall
+        base = T + PROF_TICKS
+        xroof, xphase = profile_pass(T + W, False, base + W + K)
+        xmid = base + W + (K - 1) / 2.0
+        xbytes = sum(tick_bytes(m0 + xmid, n0, k, 4, False) for (m0, n0, k) in params)
+        explicit = {"value": round(xvalue, 1), "unit": "updates/s", "ms_per_step": round(xwall / K * 1e3, 4),
+                    "p50_tick_ms": round(pctl(xtick_ms, 50), 4), "p99_tick_ms": round(pctl(xtick_ms, 99), 4),
+                    "host_ms_per_tick": round(xhost * 1e3, 4),
+                    "tick_algorithmic_GBps": round(xbytes / (xwall / K) / 1e9, 1),
+                    "phase_ms_per_tick": {["proj1", "proj2", "core", "rotate_U", "rotate_V"][p]: round(v, 4)
+                                          for p, v in sorted(xphase.items())},
+                    "roofline": xroof,
+                    "form": "Alg. A1 as written: U = [[U, 0], [0, 1]] U_K on every append, same streams, "
+                            "measured after the deferred form in the same run"}
+        log("explicit U: %.0f updates/s, tick p50 %.3f ms p99 %.3f ms; U rotation %s"
+            % (xvalue, pctl(xtick_ms, 50), pctl(xtick_ms, 99), xroof))
     tick_gbs = all_tick_bytes / (wall / K) / 1e9
     if args.calibrate_copy:
         src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
@@ -657,6 +716,8 @@ def main():
         "phase_ms_per_tick": {["proj1", "proj2", "core", "rotate_U", "rotate_V"][p]: round(v, 4)
                               for p, v in sorted(phase_ms.items())},
         "roofline": roofline,
+        "explicit_u": explicit,
+        "speedup_vs_plain_explicit_u": round(explicit["value"] / plain["value"], 2) if (plain and explicit) else None,
         "cpu_baseline": cpu,
         "init_s": round(init_s, 1),
     }
