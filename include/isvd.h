@@ -79,7 +79,7 @@ enum { ISVD_DTYPE_F32 = 0, ISVD_DTYPE_F64 = 1 };
 enum {
     ISVD_FP64 = 0,          /* A, U, V and all products in FP64 */
     ISVD_FP32 = 1,          /* A, U, V, projections and rotations in FP32 */
-    ISVD_BF16ROT = 2        /* as ISVD_FP32, but the U / V rotations of ranks up to 64 on the
+    ISVD_BF16ROT = 2        /* as ISVD_FP32, but the U / V rotations on the
                                BF16 matrix cores (operands rounded to BF16, FP32 accumulation):
                                faster, with an orthogonality drift of about 2^-8 per update
                                that refreshes repair */
@@ -115,7 +115,7 @@ typedef struct {
 typedef struct {
     int64_t m0, n0;         /* shape of A_0 */
     int64_t m_cap, n_cap;   /* capacity: largest m_t / n_t the stream may reach (>= m0, n0) */
-    int32_t k;              /* target rank, 1 <= k <= min(m0, n0, 96) */
+    int32_t k;              /* target rank, 1 <= k <= min(m0, n0, 128) */
     int32_t precision;      /* ISVD_FP64 / ISVD_FP32 / ISVD_BF16ROT */
     double tol_rel;         /* new direction iff rho > tol_rel * ||x|| (0 = 1e-10 FP64, 1e-5 FP32) */
     int32_t refresh_iters;  /* -1 (default): a stream of at most 4096 columns refreshes in Gram form

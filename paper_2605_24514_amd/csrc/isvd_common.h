@@ -18,8 +18,9 @@ constexpr int kMfmaRotRows = 512;
 struct RotVariant { int rows, rt, pf; };
 constexpr int kRotVariants = 5;
 constexpr RotVariant kRotVariant[kRotVariants] = {{256, 1, 1}, {512, 1, 1}, {1024, 1, 1}, {1024, 2, 0}, {2048, 2, 0}};
-constexpr int kMaxCore = 97;       // largest core order held in LDS (k <= 96)
-constexpr int kMaxBlock = 96;      // largest refresh block size b
+constexpr int kMaxRank = 128;      // largest rank k of a stream
+constexpr int kMaxCore = kMaxRank + 1;   // largest core order (an append's (k + 1) x (k + 1))
+constexpr int kMaxBlock = 128;     // largest refresh block size b
 
 __host__ __device__ inline int round4(int k) { return (k + 3) & ~3; }
 
@@ -111,6 +112,10 @@ struct Req {
     double* Wdi[2];
     int32_t defer;
     int32_t pad;
+    // FP64 cores of the widest bucket: the accumulated Jacobi rotations J
+    // (CoreShape<128>::NMAX x LDW doubles, column-major) in global memory,
+    // since K and J together exceed the LDS
+    double* Jg;
 };
 
 enum { kRow = 0, kCol = 1, kEntry = 2 };

@@ -84,7 +84,7 @@ int bucket_for(int kmax) {
 
 // ------------------------------------------------------------------ streams
 struct Layout {
-    size_t hdr, rs, S, p, partials, partials2, QU, QV, stage, U0, U1, V0, V1, Uref, TM, TH, TP, A, total;
+    size_t hdr, rs, S, p, partials, partials2, QU, QV, stage, U0, U1, V0, V1, Uref, TM, TH, TP, TS, Jg, A, total;
     size_t rs_b, p_b, q_b;   // bytes of one copy of the double-buffered rs, p and QU / QV
 };
 
@@ -124,6 +124,8 @@ struct Stream {
     double *S = nullptr, *partials = nullptr, *partials2 = nullptr;
     void *stage = nullptr, *A = nullptr, *Uref = nullptr;
     double *TM = nullptr, *TH = nullptr, *TP = nullptr;   // angle trackers M, H and column-pass sums
+    double* TS = nullptr;   // angle trackers: (kc + 1) x kc scratch of their updates
+    double* Jg = nullptr;   // FP64 cores of bucket 128: their accumulated rotations
     void* U[2] = {nullptr, nullptr};
     void* V[2] = {nullptr, nullptr};
     hipEvent_t ev_u0 = nullptr, ev_u1 = nullptr, ev_r0 = nullptr, ev_r1 = nullptr;
@@ -181,6 +183,8 @@ Layout make_layout(const isvd_config& c, int esz, int kc, int64_t* ntiles_max) {
     L.TM = take(angle ? sizeof(double) * kc * kc : 0);
     L.TH = take(angle ? sizeof(double) * kc * kc : 0);
     L.TP = take(angle ? sizeof(double) * (size_t)cdiv(c.m_cap, kTrackRows) * (2 * kc + 1) : 0);
+    L.TS = take(angle ? sizeof(double) * (size_t)(kc + 1) * kc : 0);   // tracker scratch
+    L.Jg = take(esz == 8 ? sizeof(double) * core_jg_doubles(kc) : 0);
     L.A = take((size_t)esz * c.m_cap * lda_of(c));
     L.total = off;
     return L;
@@ -210,7 +214,6 @@ struct Group {
     std::vector<int> pre_rotU; // ... U tiles only
     std::vector<int> pre_rotV; // ... V tiles only
     size_t off_all = 0, off_proj = 0, off_pp = 0, off_pr = 0, off_pru = 0, off_prv = 0;
-    int core_lds_n = 0;
     bool proj_alias = false;   // the projection list is the whole list (no entry update)
 };
 
@@ -347,12 +350,8 @@ isvd_status allow_lds(K kern, size_t bytes) {
     return ISVD_OK;
 }
 
-// dynamic LDS of a core of order N in a bucket whose padded column stride is ldw
-size_t core_lds_bytes(int N, int ldw, bool with_j) {
-    return sizeof(double) * (size_t)((with_j ? 2 : 1) * N * ldw + (with_j ? 6 : 8) * N);
-}
 
-size_t sym_norm2_lds(int k) { return sizeof(double) * (size_t)((k + 1) * JacobiShape<kMaxBlock + 1>::LDW + k); }
+size_t sym_norm2_lds(int k) { return sizeof(double) * (size_t)((k + 1) * WideShape::LDW + k); }
 
 // Acquire a staging slot of at least `bytes`; waits for its previous use.
 // Upload of a slot: the GPU reads the pinned host arena directly.  A kernel
@@ -440,7 +439,10 @@ isvd_status launch_group_phase(const Group& g, const char* dev, int phase, hipSt
                 default: k_rotate_mfma_t<KC, 512, 1, true><<<nb, kThreads, 0, st>>>(all, pr, na, part); break;
             }
         } else if constexpr (sizeof(T) == 4) {
-            k_rotate_mfma<KC><<<nb, kThreads, 0, st>>>(all, pr, na, part);
+            if (g.bf16)   // BF16 products, transposed form (Q^T in registers as BF16)
+                k_rotate_mfma_t<KC, kMfmaRotRows, 1, true, true><<<nb, kThreads, 0, st>>>(all, pr, na, part);
+            else
+                k_rotate_mfma<KC><<<nb, kThreads, 0, st>>>(all, pr, na, part);
         } else {
             k_rotate<T, KC><<<nb, kThreads, 0, st>>>(all, pr, na, part);
         }
@@ -485,14 +487,11 @@ isvd_status set_lds_limits() {
     ST_TRY((set_lds_limits_for<double, 32>()));
     ST_TRY((set_lds_limits_for<double, 64>()));
     ST_TRY((set_lds_limits_for<double, 128>()));
-    const size_t svd_lds = core_lds_bytes(kMaxBlock, JacobiShape<kMaxBlock + 1>::LDW, true);
-    ST_TRY(allow_lds(k_svd_small<float>, svd_lds));
-    ST_TRY(allow_lds(k_svd_small<double>, svd_lds));
     ST_TRY(allow_lds(k_svd_small_noj<float>, sizeof(double) * svd_noj_lds_doubles()));
     ST_TRY(allow_lds(k_svd_small_noj<double>, sizeof(double) * svd_noj_lds_doubles()));
     ST_TRY(allow_lds(k_sym_norm2, sym_norm2_lds(kMaxBlock)));
-    ST_TRY(allow_lds(k_track<float>, sizeof(double) * 2 * kMaxCore * kMaxBlock));
-    ST_TRY(allow_lds(k_track<double>, sizeof(double) * 2 * kMaxCore * kMaxBlock));
+    ST_TRY(allow_lds(k_track<float>, sizeof(double) * track_lds_doubles()));
+    ST_TRY(allow_lds(k_track<double>, sizeof(double) * track_lds_doubles()));
     ST_TRY(allow_lds(k_theta_tracks, sizeof(double) * theta_lds_doubles()));
     ST_TRY(allow_lds(k_theta_direct, sizeof(double) * theta_lds_doubles()));
     return ISVD_OK;
@@ -539,6 +538,7 @@ Req make_req(const isvd_engine* e, Stream& s, int kind, const void* payload, int
     r.partials2 = s.partials2;
     r.QU = s.QU[par];
     r.QV = s.QV[par];
+    r.Jg = s.Jg;
     r.payload = payload;
     if (s.wbuf && e->defer_u) {
         const size_t w = (size_t)s.kc * s.kc;
@@ -733,7 +733,6 @@ isvd_status run_groups(isvd_engine* e, std::vector<Group>& groups, hipStream_t s
         g.off_pr = take(sizeof(int) * (na + 1));
         g.off_pru = take(sizeof(int) * (na + 1));
         g.off_prv = take(sizeof(int) * (na + 1));
-        g.core_lds_n = std::min(g.kc, 96) + 1;
     }
     Slot* slot = nullptr;
     ST_TRY(acquire_slot(e, off, &slot));
@@ -848,6 +847,7 @@ Track make_track(const Stream& s, int kind, const void* payload) {
     t.M = s.TM;
     t.H = s.TH;
     t.part = s.TP;
+    t.scr = s.TS;
     return t;
 }
 
@@ -856,10 +856,10 @@ isvd_status launch_tracks(const char* dev, size_t off_all, size_t off_col, size_
                           int col_blocks, hipStream_t st) {
     const Track* all = reinterpret_cast<const Track*>(dev + off_all);
     if (ncol > 0)
-        k_track_col<T><<<col_blocks, kThreads, 0, st>>>(reinterpret_cast<const Track*>(dev + off_col),
+        k_track_col<T><<<col_blocks, kTrackColThreads, 0, st>>>(reinterpret_cast<const Track*>(dev + off_col),
                                                        reinterpret_cast<const int*>(dev + off_pre), ncol);
-    k_track<T><<<nall, kThreads, sizeof(double) * 2 * kMaxCore * kMaxBlock, st>>>(all);
-    k_theta_tracks<<<nall, kThreads, sizeof(double) * theta_lds_doubles(), st>>>(all);
+    k_track<T><<<nall, kThreads, sizeof(double) * track_lds_doubles(), st>>>(all);
+    k_theta_tracks<<<nall, WideShape::NT, sizeof(double) * theta_lds_doubles(), st>>>(all);
     HIP_TRY(hipGetLastError());
     return ISVD_OK;
 }
@@ -1004,7 +1004,9 @@ void gemm_nn_rb(const float* A, int64_t lda, const float* X, float* Y, int ldy, 
         case 3: ISVD_NN(3); break;
         case 4: ISVD_NN(4); break;
         case 5: ISVD_NN(5); break;
-        default: ISVD_NN(6); break;
+        case 6: ISVD_NN(6); break;
+        case 7: ISVD_NN(7); break;
+        default: ISVD_NN(8); break;
     }
 #undef ISVD_NN
 }
@@ -1026,7 +1028,9 @@ void gemm_tn_f32(const float* A, int64_t lda, const float* Q, float* Zp, int64_t
         case 3: ISVD_TN(3); break;
         case 4: ISVD_TN(4); break;
         case 5: ISVD_TN(5); break;
-        default: ISVD_TN(6); break;
+        case 6: ISVD_TN(6); break;
+        case 7: ISVD_TN(7); break;
+        default: ISVD_TN(8); break;
     }
 #undef ISVD_TN
 }
@@ -1264,7 +1268,6 @@ isvd_status refresh_compute_gcf(isvd_engine* e, Stream& s, bool init, hipStream_
     k_gcf_start<T><<<(int)cdiv((int64_t)ldg * wa, 256), 256, 0, st>>>(
         X, wa, n, ldg, b, (const T*)s.V[init ? 0 : h.cur], init ? 4 : h.ld, kw, 0x5eedull + (uint64_t)s.t);
     ST_TRY(gcf_orth(ws, g, X, ldg, wa, st));
-    const size_t svd_lds = core_lds_bytes(kMaxBlock, JacobiShape<kMaxBlock + 1>::LDW, true);
     std::vector<double> hbuf(2 * kMaxBlock + 1);
     int nlk = 0, rounds = 0, nl_last = 0;
     double th1 = 0.0, prev_rmax = HUGE_VAL;
@@ -1338,10 +1341,16 @@ isvd_status refresh_compute_gcf(isvd_engine* e, Stream& s, bool init, hipStream_
         if (rounds >= kGcfMaxRounds) break;
         const double top = hth[nl];
         if (nl > 0) {
-            const int wn = (int)round16(ba - nl);
-            k_take_cols<<<(int)cdiv((int64_t)ldg * wn, 256), 256, 0, st>>>(X, wa, nl, ba - nl, Xn, wn, ldg);
+            // drop the locked columns, then refill the block with fresh ones
+            const int keep = ba - nl;
+            const int target = (int)std::max<int64_t>(keep, std::min<int64_t>(b, n - nlk));
+            const int wn = (int)round16(target);
+            k_take_cols<<<(int)cdiv((int64_t)ldg * wn, 256), 256, 0, st>>>(X, wa, nl, keep, Xn, wn, ldg);
             std::swap(X, Xn);
-            ba -= nl;
+            if (target > keep)
+                k_gcf_fill<<<(int)cdiv(n * (target - keep), 256), 256, 0, st>>>(
+                    X, wn, n, keep, target, 0x5eedull + (uint64_t)s.t + 0x1000ull * (uint64_t)rounds);
+            ba = target;
             wa = wn;
         }
         // Chebyshev filter on [0, cut]
@@ -1403,14 +1412,13 @@ isvd_status refresh_compute_gcf(isvd_engine* e, Stream& s, bool init, hipStream_
     const double* Rfin = nullptr;
     ST_TRY(cholqr<T>(ws, w, Y, m, b, true, 2, st, &Rfin));
     const int ldo = round4(k);
-    if constexpr (sizeof(T) == 4)
-        k_svd_small_noj<T><<<1, RRShape::NT, sizeof(double) * svd_noj_lds_doubles(), st>>>(
-            Rfin, b, k, (double*)(ws + w.Sr), (T*)(ws + w.QU), (T*)(ws + w.QV), ldo,
-            sweeps_dev ? sweeps_dev : (int*)(ws + w.sweeps));
-    else
-        k_svd_small<T><<<1, JacobiShape<kMaxBlock + 1>::NT, svd_lds, st>>>(
-            Rfin, b, k, (double*)(ws + w.Sr), (T*)(ws + w.QU), (T*)(ws + w.QV), ldo,
-            sweeps_dev ? sweeps_dev : (int*)(ws + w.sweeps));
+    // Rayleigh-Ritz SVD of R without accumulated rotations (an order-129
+    // Jacobi with its rotations does not fit in LDS); the vectors' loss of
+    // orthogonality, about b eps64 sigma_1 / sigma_j, is far below the FP32
+    // rounding and within the FP64 bars for the kept triplets
+    k_svd_small_noj<T><<<1, RRShape::NT, sizeof(double) * svd_noj_lds_doubles(), st>>>(
+        Rfin, b, k, (double*)(ws + w.Sr), (T*)(ws + w.QU), (T*)(ws + w.QV), ldo,
+        sweeps_dev ? sweeps_dev : (int*)(ws + w.sweeps));
     HIP_TRY(hipGetLastError());
     plan->k = k;
     plan->b = b;
@@ -1481,13 +1489,7 @@ isvd_status refresh_compute(isvd_engine* e, Stream& s, bool init, hipStream_t st
     const double* Rfin = nullptr;
     ST_TRY(cholqr<T>(ws, w, Y, m, b, true, 2, st, &Rfin));
     const int ldo = round4(k);
-    if constexpr (sizeof(T) == 4)
-        k_svd_small_noj<T><<<1, RRShape::NT, sizeof(double) * svd_noj_lds_doubles(), st>>>(
-            Rfin, b, k, (double*)(ws + w.Sr), (T*)(ws + w.QU), (T*)(ws + w.QV), ldo,
-            sweeps_dev ? sweeps_dev : (int*)(ws + w.sweeps));
-    else
-        k_svd_small<T><<<1, JacobiShape<kMaxBlock + 1>::NT,
-                     core_lds_bytes(kMaxBlock, JacobiShape<kMaxBlock + 1>::LDW, true), st>>>(
+    k_svd_small_noj<T><<<1, RRShape::NT, sizeof(double) * svd_noj_lds_doubles(), st>>>(
         Rfin, b, k, (double*)(ws + w.Sr), (T*)(ws + w.QU), (T*)(ws + w.QV), ldo,
         sweeps_dev ? sweeps_dev : (int*)(ws + w.sweeps));
     HIP_TRY(hipGetLastError());
@@ -1570,7 +1572,7 @@ isvd_status direct_trackers_t(isvd_engine* e, Stream& s, hipStream_t st, double*
     const int64_t mref = std::min<int64_t>(h.ref_m, h.m);
     const int64_t chunk = 1024;
     const int64_t nch = std::max<int64_t>(1, cdiv(mref, chunk));
-    const size_t need = sizeof(double) * (size_t)(nch * (kref * k + k * k) + kref * k + k * k + 8);
+    const size_t need = sizeof(double) * (size_t)(nch * (kref * k + k * k) + kref * k + 2 * k * k + 16);
     ST_TRY(ensure_mws(e, need));
     double* cp = (double*)e->mws;
     double* hp = cp + nch * kref * k;
@@ -1583,9 +1585,10 @@ isvd_status direct_trackers_t(isvd_engine* e, Stream& s, hipStream_t st, double*
                                                                  (int64_t)kref * k, Md);
     k_sum_parts<double><<<(int)cdiv(k * k, 256), 256, 0, st>>>(hp, (int)nch, (int64_t)k * k, (int64_t)k * k, Hd);
     double* thd = Hd + k * k;
+    double* Rg = thd + 8;   // j x j Cholesky factor of the theta kernel
     if (theta)
-        k_theta_direct<<<1, kThreads, sizeof(double) * theta_lds_doubles(), st>>>(
-            Md, Hd, k, kref, s.S, s.cfg.policy.kind == ISVD_POL_ANGLE ? s.cfg.policy.angle_scope : 0, thd);
+        k_theta_direct<<<1, WideShape::NT, sizeof(double) * theta_lds_doubles(), st>>>(
+            Md, Hd, k, kref, s.S, s.cfg.policy.kind == ISVD_POL_ANGLE ? s.cfg.policy.angle_scope : 0, thd, Rg);
     if (M) {
         k_copy2d<double, double><<<(int)cdiv(kref * k, 256), 256, 0, st>>>(Md, k, M, ldo, kref, k);
         k_copy2d<double, double><<<(int)cdiv(k * k, 256), 256, 0, st>>>(Hd, k, H, ldo, k, k);
@@ -1756,7 +1759,7 @@ isvd_status exact_metrics_t(isvd_engine* e, Stream& s, hipStream_t st, Exact* ou
         k_gram_sum<<<(int)cdiv(gsz, 32), 256, 0, st>>>(gu_p, (int)ngu, k, GU);
         k_gram_mfma<T, true><<<(int)ngv, kThreads, 0, st>>>(V, ld, n, k, gram_rpb(n), gv_p);
         k_gram_sum<<<(int)cdiv(gsz, 32), 256, 0, st>>>(gv_p, (int)ngv, k, GV);
-        const int nt = JacobiShape<kMaxBlock + 1>::NT;
+        const int nt = WideShape::NT;
         k_sym_norm2<<<1, nt, sym_norm2_lds(k), st>>>(GU, k, scal + 2, sw);
         k_sym_norm2<<<1, nt, sym_norm2_lds(k), st>>>(GV, k, scal + 3, sw + 1);
     } else {
@@ -2096,8 +2099,8 @@ isvd_status validate_cfg(const isvd_config* c) {
     if (c->precision != ISVD_FP64 && c->precision != ISVD_FP32 && c->precision != ISVD_BF16ROT)
         return fail(ISVD_E_INVAL, "bad precision %d", c->precision);
     int kmax = std::max(c->k, c->policy.k_max);
-    if (c->k < 1 || c->k > std::min<int64_t>(c->m0, c->n0) || kmax > 96)
-        return fail(ISVD_E_INVAL, "k = %d outside [1, min(m0, n0, 96)]", c->k);
+    if (c->k < 1 || c->k > std::min<int64_t>(c->m0, c->n0) || kmax > kMaxRank)
+        return fail(ISVD_E_INVAL, "k = %d outside [1, min(m0, n0, %d)]", c->k, kMaxRank);
     if (c->policy.kind < ISVD_POL_NONE || c->policy.kind > ISVD_POL_ADAPTIVE)
         return fail(ISVD_E_INVAL, "bad policy kind %d", c->policy.kind);
     if (c->policy.kind == ISVD_POL_ANGLE && c->policy.angle_scope < 0)
@@ -2489,7 +2492,9 @@ static isvd_status init_common(isvd_engine* e, const isvd_config* cfg, const voi
         s->TM = (double*)(b + s->L.TM);
         s->TH = (double*)(b + s->L.TH);
         s->TP = (double*)(b + s->L.TP);
+        s->TS = (double*)(b + s->L.TS);
     }
+    if (core_jg_doubles(s->kc) > 0 && s->esz == 8) s->Jg = (double*)(b + s->L.Jg);
     s->A = b + s->L.A;
     s->live = true;
     e->streams.push_back(s);

@@ -22,7 +22,9 @@
 //       G_d <- (I - L L^T) G_d (I - L L^T)   (a symmetric rank-2 update);
 //       pairs inside the bulk stay active and keep improving: a pair frozen
 //       as soon as it met the tolerance would keep an error of its residual
-//       over its (tiny) gap
+//       over its (tiny) gap; the active block is refilled with fresh
+//       columns to min(b, n - locked), so the locked vectors and the block
+//       together can reach past b (k up to 128 with a block of at most 128)
 //     Chebyshev filter of degree d on [0, theta_cut] (theta_cut the smallest
 //       active Ritz value): Y_{j+1} = (2/e)(G_d - c) Y_j - Y_{j-1},
 //       c = e = theta_cut / 2, so the unwanted part of the spectrum stays
@@ -432,6 +434,21 @@ __global__ void k_gcf_start(double* __restrict__ X, int w, int64_t n, int64_t ro
         }
     }
     X[e] = v;
+}
+
+// Refill of the active block: columns [c0, c1) of X (leading dimension w)
+// get fresh pseudo-random values on rows < n (the same hash as the start
+// block, keyed by column index and `seed`); the filter, the projection
+// against the locked vectors and CholQR2 that follow orthonormalise them.
+__global__ void k_gcf_fill(double* __restrict__ X, int w, int64_t n, int c0, int c1, uint64_t seed) {
+    const int nc = c1 - c0;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * nc) return;
+    const int64_t r = e / nc;
+    const int j = c0 + (int)(e % nc);
+    uint64_t h = seed ^ ((uint64_t)r * 0x9E3779B97F4A7C15ull) ^ ((uint64_t)(j + 1) * 0xC2B2AE3D27D4EB4Full);
+    h ^= h >> 33; h *= 0xff51afd7ed558ccdull; h ^= h >> 33; h *= 0xc4ceb9fe1a85ec53ull; h ^= h >> 33;
+    X[r * w + j] = (double)(h >> 11) * (2.0 / 9007199254740992.0) - 1.0;
 }
 
 __global__ void k_start_flags(int* __restrict__ flags) {

@@ -53,6 +53,11 @@ struct JacobiShape {
                                    : EPT * TPP;
 };
 
+// Shape of the block-wide Jacobi on matrices of order up to kMaxBlock + 1
+// (the refresh's Rayleigh-Ritz, the orthogonality norm, the reference angle):
+// eight lanes per pair keep each lane's share of a column pair in registers.
+typedef JacobiShape<kMaxBlock + 1, 8> WideShape;
+
 // Sum over aligned groups of TPP (2, 4, 8 or 16) lanes with DPP row moves:
 // quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_half_mirror, row_mirror.
 template <int CTRL>

@@ -119,13 +119,13 @@ __global__ void __launch_bounds__(kThreads) k_gemm_tn_partial(const T* __restric
 }
 
 // ---------------------------------------------------------------------------
-// Matrix-core versions of the refresh products (b <= 96 columns).
+// Matrix-core versions of the refresh products (b <= kMaxBlock columns).
 // v_mfma_f32_16x16x4f32 / v_mfma_f64_16x16x4f64 lane layout: A[l%16][l/16],
 // B[l/16][l%16]; FP32 D[4(l/16)+r][l%16], FP64 D[4r+l/16][l%16].
 typedef float mm_v4f __attribute__((ext_vector_type(4)));
 typedef double mm_v4d __attribute__((ext_vector_type(4)));
 
-// Y[m x b] = A[m x n] X[n x b], FP32 in and FP32 accumulation (b <= 96).  A
+// Y[m x b] = A[m x n] X[n x b], FP32 in and FP32 accumulation (b <= kMaxBlock).  A
 // wave owns RB 16-row MFMA blocks and runs over all of n; a block's four
 // waves share X, staged KCH rows at a time in double-buffered LDS, and each
 // wave prefetches its next KCH columns of A into registers while the matrix
@@ -267,7 +267,7 @@ __global__ void __launch_bounds__(kThreads, 2) k_gemm_nn_mfma(const float* A, in
         }
 }
 
-// Partials of Z = A^T Q (n x b, b <= 96), computed as Z^T = Q^T A on the
+// Partials of Z = A^T Q (n x b, b <= kMaxBlock), computed as Z^T = Q^T A on the
 // matrix cores (A operand Q^T, B operand A).  Block (x, y) covers columns
 // [256 x, 256 x + 256) -- wave w the 64 from 256 x + 64 w -- over the rows
 // of chunk y.  The four waves share the chunk's rows of Q, staged 32 at a
@@ -275,12 +275,12 @@ __global__ void __launch_bounds__(kThreads, 2) k_gemm_nn_mfma(const float* A, in
 // of A into registers.  Per 4-row slab lane l loads one float4 of A -- row
 // r0 + l/16, columns c0 + 4 (l%16) + 0..3 -- and feeds element j to the MFMA
 // of column set j (columns c0 + 4 n + j).  FP32 accumulation; each lane
-// stores its accumulators as they sit in the registers (96 floats per lane,
+// stores its accumulators as they sit in the registers (b rounded to 16 floats per lane,
 // coalesced), and k_tn_sum adds the chunks in FP64 and scatters them to Z.
 // Q is m x b with leading dimension b; lda % 4 == 0.
 constexpr int kTnCols = 256;
 constexpr int kTnRows = 16;
-constexpr int kTnDump = 4 * 96 * 64;   // floats per block of the partial dump
+constexpr int kTnDump = 4 * kMaxBlock * 64;   // floats per block of the partial dump
 inline int64_t tn_chunks(int64_t m, int64_t n) {
     const int64_t ncb = (n + kTnCols - 1) / kTnCols;
     const int64_t want = (512 + ncb - 1) / ncb;
@@ -355,7 +355,7 @@ __global__ void __launch_bounds__(kThreads, 2) k_gemm_tn_mfma(const float* __res
         __syncthreads();
     }
     // acc[q][j][r] = Z[c0 + 4 (l%16) + j][16 q + 4 (l/16) + r]
-    float* out = Zp + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * kTnDump + (int64_t)w * 96 * 64 + l;
+    float* out = Zp + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * kTnDump + (int64_t)w * kMaxBlock * 64 + l;
 #pragma unroll
     for (int q = 0; q < NB; ++q)
 #pragma unroll
@@ -372,8 +372,8 @@ __global__ void __launch_bounds__(256) k_tn_sum(const float* __restrict__ Zp, in
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= per_chunk) return;
     const int lane = (int)(idx & 63), r = (int)((idx >> 6) & 3);
-    const int qj = (int)((idx >> 8) % 24);
-    const int64_t wq = idx / (96 * 64);
+    const int qj = (int)((idx >> 8) % (kMaxBlock / 4));
+    const int64_t wq = idx / (kMaxBlock * 64);
     const int64_t c = wq * 64 + 4 * (lane & 15) + (qj & 3);
     const int jj = 16 * (qj >> 2) + 4 * (lane >> 4) + r;
     if (c >= n || jj >= b) return;
@@ -388,7 +388,7 @@ __global__ void __launch_bounds__(256) k_tn_sum(const float* __restrict__ Zp, in
     Z[c * ldz + jj] = (float)(((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7])));
 }
 
-// Gram matrix G = Y^T Y (b x b, b <= 96) on the FP64 matrix cores, in two
+// Gram matrix G = Y^T Y (b x b, b <= kMaxBlock) on the FP64 matrix cores, in two
 // launches.  k_gram_mfma: block p takes rows [p rpb, (p + 1) rpb) (rpb a
 // multiple of 64, sized by gram_rpb so the grid covers the chip) and writes
 // the upper 16 x 16 tiles (ib <= jb, row-major over the upper triangle) of
@@ -406,7 +406,7 @@ inline int64_t gram_rpb(int64_t rows) {
 inline int64_t gram_parts(int64_t rows) { return std::max<int64_t>(1, (rows + gram_rpb(rows) - 1) / gram_rpb(rows)); }
 // an upper bound of gram_parts(r) for every r <= rows
 inline int64_t gram_parts_max(int64_t rows) { return std::max<int64_t>(1, std::min<int64_t>(512, (rows + kGramStage - 1) / kGramStage)); }
-__host__ __device__ inline int gram_tiles(int b) { return ((b + 15) / 16) * ((b + 15) / 16 + 1) / 2; }
+__host__ __device__ constexpr int gram_tiles(int b) { return ((b + 15) / 16) * ((b + 15) / 16 + 1) / 2; }
 __device__ inline void gram_tile(int t, int nb, int* ib, int* jb) {
     int i = 0;
     while (t >= nb - i) { t -= nb - i; ++i; }
@@ -414,6 +414,7 @@ __device__ inline void gram_tile(int t, int nb, int* ib, int* jb) {
     *jb = i + t;
 }
 
+constexpr int kGramAcc = (gram_tiles(kMaxBlock) + 3) / 4;   // upper tiles per wave
 template <typename T, bool TILED = false>
 __global__ void __launch_bounds__(kThreads) k_gram_mfma(const T* __restrict__ Y, int ldy, int64_t rows, int b,
                                                         int64_t rpb, double* __restrict__ Gp) {
@@ -421,9 +422,9 @@ __global__ void __launch_bounds__(kThreads) k_gram_mfma(const T* __restrict__ Y,
     __shared__ double sY[kGramStage][kMaxBlock + 1];
     const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int nb = (b + 15) / 16, ntile = gram_tiles(b);
-    int tib[6], tjb[6];
+    int tib[kGramAcc], tjb[kGramAcc];
 #pragma unroll
-    for (int s = 0; s < 6; ++s) {
+    for (int s = 0; s < kGramAcc; ++s) {
         const int t = w + 4 * s;
         if (t < ntile) gram_tile(t, nb, &tib[s], &tjb[s]);
         else tib[s] = tjb[s] = 0;
@@ -440,9 +441,9 @@ __global__ void __launch_bounds__(kThreads) k_gram_mfma(const T* __restrict__ Y,
             pre[q] = (r < rb && j < b) ? Y[TILED ? uvo(r, j, ldy) : r * ldy + j] : (T)0;
         }
     };
-    mm_v4d acc[6];
+    mm_v4d acc[kGramAcc];
 #pragma unroll
-    for (int s = 0; s < 6; ++s) acc[s] = (mm_v4d){0.0, 0.0, 0.0, 0.0};
+    for (int s = 0; s < kGramAcc; ++s) acc[s] = (mm_v4d){0.0, 0.0, 0.0, 0.0};
     fetch(ra);
     for (int64_t r0 = ra; r0 < rb; r0 += kGramStage) {
 #pragma unroll
@@ -456,7 +457,7 @@ __global__ void __launch_bounds__(kThreads) k_gram_mfma(const T* __restrict__ Y,
         for (int kk = 0; kk < kGramStage / 4; ++kk) {
             const int rr = 4 * kk + (l >> 4);
 #pragma unroll
-            for (int s = 0; s < 6; ++s) {
+            for (int s = 0; s < kGramAcc; ++s) {
                 if (w + 4 * s < ntile)
                     acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(sY[rr][16 * tib[s] + (l & 15)],
                                                                   sY[rr][16 * tjb[s] + (l & 15)], acc[s], 0, 0, 0);
@@ -465,7 +466,7 @@ __global__ void __launch_bounds__(kThreads) k_gram_mfma(const T* __restrict__ Y,
         __syncthreads();
     }
 #pragma unroll
-    for (int s = 0; s < 6; ++s) {
+    for (int s = 0; s < kGramAcc; ++s) {
         const int t = w + 4 * s;
         if (t >= ntile) continue;
         double* out = Gp + ((int64_t)blockIdx.x * ntile + t) * 256;
@@ -535,15 +536,17 @@ __global__ void k_sum_parts(const double* __restrict__ P, int nparts, int64_t st
 // every row below j has its column-j entry eliminated, so the left half ends
 // as D L^T (row j = pivot d_j times row j of L^T) and the right half as
 // L^{-1}.  Then R = D^{-1/2} (D L^T) and R^{-1} = L^{-T} D^{-1/2}.  The
-// 96 x 192 augmented matrix lives in registers: thread (ty, tx) of a 16 x 16
-// grid owns rows ty + 16 p and columns tx + 16 q; step j publishes row j
-// through a double-buffered LDS row, so one barrier per step suffices.
-constexpr int kCholThreads = 256;
+// b x 2b augmented matrix (b <= kMaxBlock) lives in registers: thread
+// (ty, tx) of a 32 x 16 grid owns rows ty + 32 p and columns tx + 16 q; step
+// j publishes row j through a double-buffered LDS row, so one barrier per
+// step suffices.
+constexpr int kCholThreads = 512;
+constexpr int kCholTY = kCholThreads / 16;   // row groups of the thread grid
 template <typename T>
 __global__ void __launch_bounds__(kCholThreads) k_chol_inv(const double* __restrict__ G, int b,
                                                        double* __restrict__ Rout, T* __restrict__ RinvT,
                                                        int* __restrict__ flag) {
-    constexpr int NP = kMaxBlock / 16, NQ = 2 * kMaxBlock / 16;
+    constexpr int NP = (kMaxBlock + kCholTY - 1) / kCholTY, NQ = 2 * kMaxBlock / 16;
     __shared__ double s_row[2][2 * kMaxBlock];
     __shared__ double s_g[kMaxBlock];
     __shared__ double s_d[kMaxBlock];
@@ -552,7 +555,7 @@ __global__ void __launch_bounds__(kCholThreads) k_chol_inv(const double* __restr
     double g[NP][NQ];
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
-        const int i = ty + 16 * p;
+        const int i = ty + kCholTY * p;
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
             const int c = tx + 16 * q;
@@ -579,8 +582,8 @@ __global__ void __launch_bounds__(kCholThreads) k_chol_inv(const double* __restr
         for (int q = 0; q < NQ; ++q) rc[q] = row[tx + 16 * q];
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
-            const int i = ty + 16 * p;
-            const double f = i > j ? row[i] * inv_d : 0.0;
+            const int i = ty + kCholTY * p;
+            const double f = (i > j && i < b) ? row[i] * inv_d : 0.0;
 #pragma unroll
             for (int q = 0; q < NQ; ++q) g[p][q] -= f * rc[q];
         }
@@ -590,10 +593,10 @@ __global__ void __launch_bounds__(kCholThreads) k_chol_inv(const double* __restr
             if (drop) atomicOr(flag, 1);
         }
         const int jn = j + 1;
-        if (jn < b && ty == (jn & 15)) {
+        if (jn < b && ty == jn % kCholTY) {
 #pragma unroll
             for (int p = 0; p < NP; ++p)
-                if (p == (jn >> 4)) {
+                if (p == jn / kCholTY) {
 #pragma unroll
                     for (int q = 0; q < NQ; ++q) s_row[jn & 1][tx + 16 * q] = g[p][q];
                 }
@@ -603,7 +606,7 @@ __global__ void __launch_bounds__(kCholThreads) k_chol_inv(const double* __restr
     // R = D^{-1/2} (D L^T) (upper, dropped rows zero); R^{-1}[c][i] = L^{-1}[i][c] / sqrt(d_i)
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
-        const int i = ty + 16 * p;
+        const int i = ty + kCholTY * p;
         if (i >= b) continue;
         const double sc = s_drop[i] ? 0.0 : 1.0 / sqrt(s_d[i]);
 #pragma unroll
@@ -660,50 +663,9 @@ __global__ void __launch_bounds__(kThreads) k_rotate_plain(const T* in, int ldi,
     }
 }
 
-// Rayleigh-Ritz core: SVD of the b x b FP64 R (row-major) by the block Jacobi;
-// QU = W[:, :k] (left vectors), QV = H[:, :k] (right vectors), both b x ldo in
-// the storage type with zero padding; S = sigma[:k].  Dynamic LDS (2 b ldw + 6 b) doubles.
-template <typename T>
-__global__ void __launch_bounds__(JacobiShape<kMaxBlock + 1>::NT) k_svd_small(const double* __restrict__ R, int b, int k,
-                                                        double* __restrict__ S, T* __restrict__ QU,
-                                                        T* __restrict__ QV, int ldo,
-                                                        int* __restrict__ sweeps_out) {
-    extern __shared__ double smem[];
-    const int N = b;
-    const int ldw = JacobiShape<kMaxBlock + 1>::LDW;
-    double* W = smem;
-    double* J = W + (size_t)N * ldw;
-    double* nrm = J + (size_t)N * ldw;
-    double* sig = nrm + N;
-    double* sgn = sig + N;
-    double* tmp = sgn + N;
-    int* perm = (int*)(tmp + N);
-    for (int e = threadIdx.x; e < N * ldw; e += blockDim.x) {
-        int col = e / ldw, row = e % ldw;
-        W[e] = row < N ? R[row * N + col] : 0.0;
-        J[e] = row == col ? 1.0 : 0.0;
-    }
-    __syncthreads();
-    int sweeps = jacobi_block<kMaxBlock + 1, true>(W, J, N, ldw, 60);
-    jacobi_finish(W, J, N, ldw, sig, perm, sgn, tmp);
-    for (int e = threadIdx.x; e < N * ldo; e += blockDim.x) {
-        int row = e / ldo, j = e % ldo;
-        double uk = 0.0, vk = 0.0;
-        if (j < k) {
-            int c = perm[j];
-            double s = sig[j];
-            uk = s > 0.0 ? sgn[j] * W[(size_t)c * ldw + row] / s : 0.0;
-            vk = sgn[j] * J[(size_t)c * ldw + row];
-        }
-        QU[e] = (T)uk;
-        QV[e] = (T)vk;
-    }
-    for (int j = threadIdx.x; j < k; j += blockDim.x) S[j] = sig[j];
-    if (threadIdx.x == 0) *sweeps_out = sweeps;
-}
-
-// FP32-storage Rayleigh-Ritz core: the same SVD of R without accumulating the
-// rotations (half the LDS, so eight lanes per pair fit).  The columns rotated
+// Rayleigh-Ritz core: SVD of the b x b FP64 R (row-major) by one-sided
+// Jacobi in LDS, without accumulating the rotations (an order-129 matrix and
+// its rotations would not fit in LDS together; eight lanes per pair).  The columns rotated
 // are those of R^T (for a triangular R the one-sided Jacobi needs fewer
 // sweeps on R^T than on R): W = R^T J with orthogonal columns w_j =
 // sigma_j v_j, so the right vectors are v_j = w_j / sigma_j and the left ones
@@ -711,7 +673,7 @@ __global__ void __launch_bounds__(JacobiShape<kMaxBlock + 1>::NT) k_svd_small(co
 // Their loss of orthogonality, about the rotation threshold (b eps64) times
 // sigma_1 / sigma_j, stays far below FP32 rounding for the kept triplets; a
 // coarser threshold would be amplified the same way, so the FP64 one stays.
-typedef JacobiShape<kMaxBlock + 1, 8> RRShape;
+typedef WideShape RRShape;
 template <typename T>
 __global__ void __launch_bounds__(RRShape::NT) k_svd_small_noj(const double* __restrict__ R, int b, int k,
                                                               double* __restrict__ S, T* __restrict__ QU,
@@ -887,11 +849,11 @@ __global__ void __launch_bounds__(kThreads) k_resid2_partial(const T* __restrict
 // ||G - I||_2 for a symmetric k x k G (an orthogonality residual Q^T Q - I):
 // one-sided Jacobi on E = G - I; the largest column norm of the result is the
 // largest |eigenvalue| of E.
-__global__ void __launch_bounds__(JacobiShape<kMaxBlock + 1>::NT) k_sym_norm2(const double* __restrict__ G, int k,
+__global__ void __launch_bounds__(WideShape::NT) k_sym_norm2(const double* __restrict__ G, int k,
                                                                             double* __restrict__ out,
                                                                             int* __restrict__ sweeps_out) {
     extern __shared__ double smem[];
-    const int ldw = JacobiShape<kMaxBlock + 1>::LDW;
+    const int ldw = WideShape::LDW;
     // k + 1 columns: for odd k the idle pair of each round reads column k
     double* W = smem;
     double* red = W + (size_t)(k + 1) * ldw;
@@ -900,7 +862,7 @@ __global__ void __launch_bounds__(JacobiShape<kMaxBlock + 1>::NT) k_sym_norm2(co
         W[e] = (row < k && col < k) ? G[row * k + col] - (row == col ? 1.0 : 0.0) : 0.0;
     }
     __syncthreads();
-    const int sweeps = jacobi_block<kMaxBlock + 1, false>(W, nullptr, k, ldw, 60);
+    const int sweeps = jacobi_block<kMaxBlock + 1, false, WideShape::TPP>(W, nullptr, k, ldw, 60);
     for (int c = threadIdx.x; c < k; c += blockDim.x) {
         double s = 0.0;
         for (int e = 0; e < k; ++e) s += W[(size_t)c * ldw + e] * W[(size_t)c * ldw + e];

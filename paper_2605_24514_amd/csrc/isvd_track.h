@@ -40,16 +40,19 @@ struct Track {
     double* M;
     double* H;
     double* part;         // column append: per-block sums, stride 2 kc + 1
+    double* scr;          // (kc + 1) x kc scratch: the product T of k_track, R of theta
 };
 
 constexpr int kTrackRows = 1024;   // reference rows per block of the column pass
+// threads of the column pass: lanes [0, 128) a, [128, 256) b, lane 256 zeta
+constexpr int kTrackColThreads = 320;
 
 // Column append: per block of reference rows, a = U_ref^T z^, b = U^T z^ and
 // zeta = z^^T z^ (FP64).  Rows are taken 64 at a time: four lanes form each
 // row's z^, then lane c < k_ref sums U_ref[:, c] z^, lane 128 + c < k_in sums
-// U[:, c] z^ and lane 255 sums z^^2 (coalesced row reads across lanes).
+// U[:, c] z^ and lane 256 sums z^^2 (coalesced row reads across lanes).
 template <typename T>
-__global__ void __launch_bounds__(kThreads) k_track_col(const Track* __restrict__ trs, const int* __restrict__ prefix,
+__global__ void __launch_bounds__(kTrackColThreads) k_track_col(const Track* __restrict__ trs, const int* __restrict__ prefix,
                                                         int ntr) {
     __shared__ double sz[64];
     __shared__ double sp[kMaxCore];
@@ -71,7 +74,7 @@ __global__ void __launch_bounds__(kThreads) k_track_col(const Track* __restrict_
     const T* U = (const T*)tr.U[rs->in_idx];
     const T* Ur = (const T*)tr.Uref;
     const T* y = (const T*)tr.payload;
-    for (int c = threadIdx.x; c < kin; c += kThreads) sp[c] = tr.p[c];
+    for (int c = threadIdx.x; c < kin; c += blockDim.x) sp[c] = tr.p[c];
     __syncthreads();
     const int t = threadIdx.x;
     double acc = 0.0;
@@ -79,7 +82,7 @@ __global__ void __launch_bounds__(kThreads) k_track_col(const Track* __restrict_
     const int64_t r1 = min(mref, r0 + kTrackRows);
     if (!rs->skip && inv_rho != 0.0) {
         for (int64_t rb = r0; rb < r1; rb += 64) {
-            {
+            if (t < 256) {
                 const int rr = t >> 2, q = t & 3;
                 const int64_t r = rb + rr;
                 double d = 0.0;
@@ -93,17 +96,17 @@ __global__ void __launch_bounds__(kThreads) k_track_col(const Track* __restrict_
             const int nr = (int)min((int64_t)64, r1 - rb);
             if (t < kref) {
                 for (int rr = 0; rr < nr; ++rr) acc += (double)Ur[uvo(rb + rr, t, ldr)] * sz[rr];
-            } else if (t >= 128 && t - 128 < kin) {
+            } else if (t >= 128 && t < 256 && t - 128 < kin) {
                 for (int rr = 0; rr < nr; ++rr) acc += (double)U[uvo(rb + rr, t - 128, ldi)] * sz[rr];
-            } else if (t == kThreads - 1) {
+            } else if (t == 256) {
                 for (int rr = 0; rr < nr; ++rr) acc += sz[rr] * sz[rr];
             }
             __syncthreads();
         }
     }
     if (t < tr.kc) out[t] = t < kref ? acc : 0.0;
-    if (t >= 128 && t - 128 < tr.kc) out[tr.kc + (t - 128)] = t - 128 < kin ? acc : 0.0;
-    if (t == kThreads - 1) out[2 * tr.kc] = acc;
+    if (t >= 128 && t < 256 && t - 128 < tr.kc) out[tr.kc + (t - 128)] = t - 128 < kin ? acc : 0.0;
+    if (t == 256) out[2 * tr.kc] = acc;
 }
 
 // Leading gap-separated scope of a descending spectrum (Section 3.3 reading):
@@ -118,19 +121,20 @@ __device__ inline int gap_scope(const double* S, int k) {
     return best_gap >= 0.05 ? best : k;
 }
 
-// LDS doubles of block_theta for scope up to kMaxBlock (about 150 KB)
+// LDS doubles of block_theta for scope up to kMaxBlock (about 137 KB)
 __host__ __device__ constexpr size_t theta_lds_doubles() {
-    return (size_t)(kMaxBlock + 1) * JacobiShape<kMaxBlock + 1>::LDW + kMaxBlock * kMaxBlock + 2 * kMaxBlock;
+    return (size_t)(kMaxBlock + 1) * WideShape::LDW + 2 * kMaxBlock;
 }
 
 // theta_ref on the leading j columns from M (k_ref x k, row stride ldm) and
-// H (k x k, row stride ldh) in global memory.  Whole block; returns the angle
-// on every thread.
-__device__ inline double block_theta(const double* M, int ldm, const double* H, int ldh, int j, double* lds) {
-    const int ldw = JacobiShape<kMaxBlock + 1>::LDW;
+// H (k x k, row stride ldh) in global memory; R (j x j) is formed in the
+// global scratch `Rg`.  Whole block; returns the angle on every thread.
+__device__ inline double block_theta(const double* M, int ldm, const double* H, int ldh, int j, double* lds,
+                                     double* Rg) {
+    const int ldw = WideShape::LDW;
     double* W = lds;                                   // C column-major, (j + 1) columns
-    double* R = W + (size_t)(kMaxBlock + 1) * ldw;    // j x j, row-major
-    double* red = R + kMaxBlock * kMaxBlock;
+    double* R = Rg;                                    // j x j, row-major
+    double* red = W + (size_t)(kMaxBlock + 1) * ldw;
     int* s_drop = (int*)(red + kMaxBlock);
     const int tid = threadIdx.x, nt = blockDim.x;
     for (int e = tid; e < j * j; e += nt) R[e] = H[(e / j) * ldh + (e % j)];
@@ -171,7 +175,7 @@ __device__ inline double block_theta(const double* M, int ldm, const double* H, 
         }
     }
     __syncthreads();
-    jacobi_block<kMaxBlock + 1, false>(W, nullptr, j, ldw, 60);
+    jacobi_block<kMaxBlock + 1, false, WideShape::TPP>(W, nullptr, j, ldw, 60);
     for (int c = tid; c < j; c += nt) {
         double s = 0.0;
         for (int e = 0; e < j; ++e) s += W[(size_t)c * ldw + e] * W[(size_t)c * ldw + e];
@@ -186,11 +190,19 @@ __device__ inline double block_theta(const double* M, int ldm, const double* H, 
 }
 
 // One block per angle-policy stream after its update: M' and H' through the
-// core's rotation of U.  Dynamic LDS: 2 kMaxCore kMaxBlock doubles.
+// core's rotation of U.  The rotation Q (nq x kout) sits in LDS; M' = [M, a] Q
+// is formed in chunks of kTrackChunk rows (row i of M' needs only row i of
+// M, so each chunk is written back in place once computed); T = [[H, b],
+// [b^T, zeta]] Q goes to the stream's global scratch, then H' = Q^T T.
+// Dynamic LDS: track_lds_doubles().
+constexpr int kTrackChunk = 24;
+__host__ __device__ constexpr size_t track_lds_doubles() {
+    return (size_t)kMaxCore * kMaxBlock + (size_t)kTrackChunk * kMaxBlock;
+}
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_track(const Track* __restrict__ trs) {
     extern __shared__ double lds[];
-    __shared__ double s_vec[2 * kMaxCore + 1];     // a [0, 97), b [97, 194), zeta
+    __shared__ double s_vec[2 * kMaxCore + 1];     // a [0, kMaxCore), b [kMaxCore, 2 kMaxCore), zeta
     const Track& tr = trs[blockIdx.x];
     const ReqScratch* rs = tr.rs;
     DevHeader* hdr = tr.hdr;
@@ -200,8 +212,8 @@ __global__ void __launch_bounds__(kThreads) k_track(const Track* __restrict__ tr
     const int kref = hdr->ref_k, kc = tr.kc;
     const bool col = tr.kind == kCol;
     const int nq = kin + (col ? 1 : 0);
-    double* sQ = lds;                        // nq x kout
-    double* sT = lds + kMaxCore * kMaxBlock; // kref x kout, then nq x kout
+    double* sQ = lds;                           // nq x kout
+    double* sT = lds + kMaxCore * kMaxBlock;    // kTrackChunk x kout
     const T* Q = (const T*)tr.QU;
     for (int e = tid; e < nq * kout; e += nt) {
         const int l = e / kout, c = e % kout;
@@ -219,18 +231,22 @@ __global__ void __launch_bounds__(kThreads) k_track(const Track* __restrict__ tr
         }
     }
     __syncthreads();
-    // M' = [M, a] Q
-    for (int e = tid; e < kref * kout; e += nt) {
-        const int i = e / kout, c = e % kout;
-        double s = 0.0;
-        for (int l = 0; l < kin; ++l) s += tr.M[i * kc + l] * sQ[l * kout + c];
-        if (col) s += s_vec[i] * sQ[kin * kout + c];
-        sT[e] = s;
+    // M' = [M, a] Q, kTrackChunk rows at a time
+    for (int r0 = 0; r0 < kref; r0 += kTrackChunk) {
+        const int nr = min(kTrackChunk, kref - r0);
+        for (int e = tid; e < nr * kout; e += nt) {
+            const int i = r0 + e / kout, c = e % kout;
+            double s = 0.0;
+            for (int l = 0; l < kin; ++l) s += tr.M[i * kc + l] * sQ[l * kout + c];
+            if (col) s += s_vec[i] * sQ[kin * kout + c];
+            sT[e] = s;
+        }
+        __syncthreads();
+        for (int e = tid; e < nr * kout; e += nt) tr.M[(r0 + e / kout) * kc + (e % kout)] = sT[e];
+        __syncthreads();
     }
-    __syncthreads();
-    for (int e = tid; e < kref * kout; e += nt) tr.M[(e / kout) * kc + (e % kout)] = sT[e];
-    __syncthreads();
-    // T = [[H, b], [b^T, zeta]] Q, then H' = Q^T T
+    // T = [[H, b], [b^T, zeta]] Q into the scratch (row stride kc), then H' = Q^T T
+    double* Tg = tr.scr;
     for (int e = tid; e < nq * kout; e += nt) {
         const int i = e / kout, c = e % kout;
         double s = 0.0;
@@ -241,13 +257,13 @@ __global__ void __launch_bounds__(kThreads) k_track(const Track* __restrict__ tr
             for (int l = 0; l < kin; ++l) s += s_vec[kMaxCore + l] * sQ[l * kout + c];
             s += s_vec[2 * kMaxCore] * sQ[kin * kout + c];
         }
-        sT[e] = s;
+        Tg[i * kc + c] = s;
     }
     __syncthreads();
     for (int e = tid; e < kout * kout; e += nt) {
         const int i = e / kout, c = e % kout;
         double s = 0.0;
-        for (int l = 0; l < nq; ++l) s += sQ[l * kout + i] * sT[l * kout + c];
+        for (int l = 0; l < nq; ++l) s += sQ[l * kout + i] * Tg[l * kc + c];
         tr.H[i * kc + c] = s;
     }
 }
@@ -255,7 +271,7 @@ __global__ void __launch_bounds__(kThreads) k_track(const Track* __restrict__ tr
 // theta_ref of each tracked stream from its updated M and H (a launch of its
 // own, so that the tracker writes of k_track are visible).  Dynamic LDS:
 // theta_lds_doubles().
-__global__ void __launch_bounds__(kThreads) k_theta_tracks(const Track* __restrict__ trs) {
+__global__ void __launch_bounds__(WideShape::NT) k_theta_tracks(const Track* __restrict__ trs) {
     extern __shared__ double lds[];
     const Track& tr = trs[blockIdx.x];
     DevHeader* hdr = tr.hdr;
@@ -263,7 +279,7 @@ __global__ void __launch_bounds__(kThreads) k_theta_tracks(const Track* __restri
     const int k = hdr->k, kref = hdr->ref_k;
     int j = tr.scope > 0 ? tr.scope : gap_scope(tr.S, k);
     j = min(j, min(k, kref));
-    const double th = block_theta(tr.M, tr.kc, tr.H, tr.kc, j, lds);
+    const double th = block_theta(tr.M, tr.kc, tr.H, tr.kc, j, lds, tr.scr);
     if (threadIdx.x == 0) hdr->angle_ref = th;
 }
 
@@ -285,13 +301,13 @@ __global__ void k_track_reset(DevHeader* hdr, double* M, double* H, int kc) {
 }
 
 // theta_ref from directly formed M (k_ref x k) and H (k x k), row stride k.
-__global__ void __launch_bounds__(kThreads) k_theta_direct(const double* M, const double* H, int k, int kref,
-                                                           const double* S, int scope, double* out) {
+__global__ void __launch_bounds__(WideShape::NT) k_theta_direct(const double* M, const double* H, int k, int kref,
+                                                           const double* S, int scope, double* out, double* Rg) {
     extern __shared__ double lds[];
     int j = scope > 0 ? scope : gap_scope(S, k);
     j = min(j, min(k, kref));
-    // M has row stride k (k_ref rows), H row stride k
-    const double th = block_theta(M, k, H, k, j, lds);
+    // M has row stride k (k_ref rows), H row stride k; Rg: j x j scratch
+    const double th = block_theta(M, k, H, k, j, lds, Rg);
     if (threadIdx.x == 0) *out = th;
 }
 
@@ -306,9 +322,9 @@ __global__ void __launch_bounds__(kThreads) k_cross_partial(const T* __restrict_
     const int64_t ra = (int64_t)blockIdx.x * chunk_rows;
     const int64_t rb = min(rows, ra + chunk_rows);
     const int nout = kx * ky;
-    double acc[36];
+    double acc[kMaxBlock * kMaxBlock / kThreads];
 #pragma unroll
-    for (int q = 0; q < 36; ++q) acc[q] = 0.0;
+    for (int q = 0; q < kMaxBlock * kMaxBlock / kThreads; ++q) acc[q] = 0.0;
     for (int64_t r0 = ra; r0 < rb; r0 += 16) {
         for (int e = threadIdx.x; e < 16 * kMaxBlock; e += kThreads) {
             const int rr = e / kMaxBlock, c = e % kMaxBlock;
@@ -318,7 +334,7 @@ __global__ void __launch_bounds__(kThreads) k_cross_partial(const T* __restrict_
         }
         __syncthreads();
 #pragma unroll
-        for (int q = 0; q < 36; ++q) {
+        for (int q = 0; q < kMaxBlock * kMaxBlock / kThreads; ++q) {
             const int e = threadIdx.x + q * kThreads;
             if (e < nout) {
                 const int i = e / ky, c = e % ky;
@@ -331,7 +347,7 @@ __global__ void __launch_bounds__(kThreads) k_cross_partial(const T* __restrict_
     }
     double* out = Gp + (int64_t)blockIdx.x * nout;
 #pragma unroll
-    for (int q = 0; q < 36; ++q) {
+    for (int q = 0; q < kMaxBlock * kMaxBlock / kThreads; ++q) {
         const int e = threadIdx.x + q * kThreads;
         if (e < nout) out[e] = acc[q];
     }

@@ -171,28 +171,40 @@ typedef double core_v4d __attribute__((ext_vector_type(4)));
 template <int KC>
 struct CoreShape {
     static constexpr int NMAX = (KC < kMaxCore - 1 ? KC : kMaxCore - 1) + 1;
-    // eight lanes per pair for the 33- and 65-column cores (shorter rounds);
-    // the widest keeps four so that its FP64 core and J fit in LDS
-    typedef JacobiShape<NMAX, (KC == 32 || KC == 64) ? 8 : 4> J;
+    // eight lanes per pair for the 33-, 65- and 129-column cores (shorter
+    // rounds; at order 129 also a lane's share of a column pair that fits in
+    // registers)
+    typedef JacobiShape<NMAX, (KC == 32 || KC == 64 || KC == 128) ? 8 : 4> J;
 };
 
 // the FP32 cores of buckets up to 64 can take the secular path
 template <int KC, bool WITH_J>
 __host__ __device__ constexpr bool core_secular() { return !WITH_J && KC <= 64; }
 
+// FP64 cores of the widest bucket keep the accumulated rotations J in global
+// memory (Req::Jg): K and J of order 129 (2 x 133 KB) exceed the LDS
+template <int KC, bool WITH_J>
+__host__ __device__ constexpr bool core_j_global() { return WITH_J && KC > 64; }
+
 // dynamic LDS (doubles) of a core block of bucket KC
 template <int KC, bool WITH_J>
 __host__ __device__ constexpr size_t core_lds_doubles() {
     constexpr bool SEC = core_secular<KC, WITH_J>();
-    return (size_t)((WITH_J || SEC) ? 2 : 1) * CoreShape<KC>::NMAX * CoreShape<KC>::J::LDW +
+    constexpr bool JLDS = (WITH_J && !core_j_global<KC, WITH_J>()) || SEC;
+    return (size_t)(JLDS ? 2 : 1) * CoreShape<KC>::NMAX * CoreShape<KC>::J::LDW +
            (size_t)(WITH_J ? 6 : 8) * CoreShape<KC>::NMAX +
            (size_t)(SEC ? secular_scratch_doubles(CoreShape<KC>::NMAX) : 0);
+}
+// global doubles of Req::Jg for a stream of bucket KC
+__host__ __device__ constexpr size_t core_jg_doubles(int KC) {
+    return KC > 64 ? (size_t)CoreShape<128>::NMAX * CoreShape<128>::J::LDW : 0;
 }
 
 template <typename T, int KC>
 __global__ void __launch_bounds__(CoreShape<KC>::J::NT) k_core(const Req* __restrict__ reqs) {
     constexpr bool WITH_J = sizeof(T) == 8;
     constexpr bool SEC = core_secular<KC, WITH_J>();
+    constexpr bool JG = core_j_global<KC, WITH_J>();
     extern __shared__ double smem[];
     __shared__ double s_sc[8];
     __shared__ int s_i[4];
@@ -206,8 +218,9 @@ __global__ void __launch_bounds__(CoreShape<KC>::J::NT) k_core(const Req* __rest
     const int tid = threadIdx.x, nt = blockDim.x;
     const int ldw = CoreShape<KC>::J::LDW;
     double* W = smem;
-    double* J = W + (size_t)N * ldw;                 // V_K: WITH_J, or the secular path
-    double* sS = J + ((WITH_J || SEC) ? (size_t)N * ldw : 0); // Sigma (k)
+    // V_K: WITH_J (in global memory for the widest FP64 cores), or the secular path
+    double* J = JG ? rq.Jg : W + (size_t)N * ldw;
+    double* sS = W + (size_t)N * ldw + (((WITH_J && !JG) || SEC) ? (size_t)N * ldw : 0); // Sigma (k)
     double* sp = sS + N;                           // p (row / column) or s_v (rank-1)
     double* sig = sp + N;
     double* sgn = sig + N;
