@@ -318,6 +318,91 @@ def refresh_main(args):
     print(json.dumps(out), flush=True)
 
 
+SWEEP_SEED = 2
+
+
+def precision_sweep(args, torch, isvd, appends, log_prefix="sweep"):
+    """The precision sweep on one stream: a 1,000,000 x 512 factor-model panel
+    (40 factors), k = 128, `appends` row appends, in three forms started from
+    the same FP64 initial factors: FP64 throughout; FP32 storage, projections
+    and rotations with the FP64 core and re-orthogonalisation; BF16 matrix-core
+    rotations (FP32 accumulation) with the angle-threshold refresh at 1e-3 rad
+    (Section 3.3).  Each form's error against the FP64 form after the run
+    (the FP64 engine itself is held to the oracle by the rank-128 and full-size
+    parity tests), updates/s and per-append latency."""
+    from synth import device as sdev
+    from tests.parity import compare
+    m0, n, nf, k = 1_000_000, 512, 40, 128
+    T = appends
+    st = torch.cuda.Stream()
+    A0 = torch.empty((m0, n), dtype=torch.float64, device="cuda")
+    sdev.rows_into(A0, 0, m0, n, SWEEP_SEED, 0, nf)
+    rows = torch.empty((T, n), dtype=torch.float64, device="cuda")
+    sdev.rows_into(rows, m0, T, n, SWEEP_SEED, 0, nf)
+    rows32 = rows.to(torch.float32)
+    torch.cuda.synchronize()
+    out = {"workload": "one stream, A 1,000,000 x 512 (40 factors), k = 128, %d row appends" % T}
+    with isvd.Engine() as e64, isvd.Engine() as e32, isvd.Engine() as eb:
+        t0 = time.perf_counter()
+        s64 = e64.init(A0, k, "fp64", m_cap=m0 + T, n_cap=n, stream=st)
+        st.synchronize()
+        init_ms = (time.perf_counter() - t0) * 1e3
+        met0 = e64.metrics(s64, stream=st)
+        U, S, V = e64.factors(s64, stream=st)
+        A32 = A0.to(torch.float32)
+        s32 = e32.init_from_factors(A32, U, S, V, "fp32", m_cap=m0 + T, n_cap=n, stream=st)
+        pol = isvd.Policy(kind=isvd.POL_ANGLE, theta_max=1e-3, t_min=1)
+        sb = eb.init_from_factors(A32, U, S, V, "bf16rot", m_cap=m0 + T, n_cap=n, policy=pol, stream=st)
+        del A32, U, V
+        st.synchronize()
+        forms = []
+        for name, eng, sid, pay in (("fp64", e64, s64, rows), ("fp32_core64", e32, s32, rows32),
+                                    ("bf16rot_angle_refresh", eb, sb, rows32)):
+            evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(T)]
+            st.synchronize()
+            w0 = time.perf_counter()
+            for t in range(T):
+                evs[t][0].record(st)
+                eng.append_row(sid, pay[t], stream=st)
+                evs[t][1].record(st)
+            st.synchronize()
+            wall = time.perf_counter() - w0
+            lat = [a.elapsed_time(b) for a, b in evs]
+            met = eng.metrics(sid, stream=st)
+            forms.append((name, eng, sid, {"updates_per_s": round(T / wall, 1),
+                                           "p50_update_ms": round(pctl(lat, 50), 4),
+                                           "p99_update_ms": round(pctl(lat, 99), 4),
+                                           "refreshes": int(met["n_refresh"])}))
+            log("%s %s: %.1f appends/s, p50 %.3f ms, p99 %.3f ms, %d refreshes"
+                % (log_prefix, name, T / wall, pctl(lat, 50), pctl(lat, 99), met["n_refresh"]))
+        ref = e64.factors(s64, stream=st)
+        for name, eng, sid, rec in forms:
+            if name != "fp64":
+                c = compare(eng.factors(sid, stream=st), ref)
+                rec["error_vs_fp64"] = {q: float("%.3g" % c[q]) for q in
+                                        ("recon", "sigma", "angle_U", "angle_V", "angle_U_full", "ortho_U")}
+                rec["error_vs_fp64"]["angle_scope"] = int(c["angle_scope"])
+            out[name] = rec
+        out["init_ms_fp64"] = round(init_ms, 1)
+        out["init_refresh_rounds"] = int(met0["refresh_rounds"])
+    del A0, rows, rows32
+    torch.cuda.synchronize()
+    return out
+
+
+def sweep_main(args):
+    """Precision sweep run (one JSON line)."""
+    import torch
+    from paper_2605_24514_amd import isvd
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    res = precision_sweep(args, torch, isvd, args.sweep_appends)
+    out = {"metric": "precision sweep: appends/s and error against FP64 per form", "value":
+           res["fp32_core64"]["updates_per_s"], "unit": "updates/s", "n_gpus": 1, "steps": args.sweep_appends,
+           "warmup": 0, "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": res["workload"]}, "forms": res}
+    print(json.dumps(out), flush=True)
+
+
 def finance_main(args):
     """Finance readout (Section 5): a 60-asset returns stream (the paper's ETF
     universe size, synthetic five-factor returns in place of its price data),
@@ -414,8 +499,14 @@ def main():
     ap.add_argument("--serve", action="store_true", help="run the serving loop instead of the batched tick")
     ap.add_argument("--refresh", action="store_true", help="time the refresh of one 100000 x 2000 stream instead")
     ap.add_argument("--finance", action="store_true", help="time the finance readout of a 60-asset returns stream")
+    ap.add_argument("--sweep", action="store_true",
+                    help="run the precision sweep (1,000,000 x 512, k = 128) instead")
+    ap.add_argument("--sweep-appends", type=int, default=5000)
+    ap.add_argument("--sweep-default", type=int, default=300,
+                    help="row appends of the shortened precision sweep added to the default line (0: none)")
     ap.add_argument("--explicit-u", action="store_true",
                     help="rotate U on every row append (no deferred U = U0 W)")
+    ap.add_argument("--no-graphs", action="store_true", help="launch every tick from the host (no captured graph)")
     ap.add_argument("--no-explicit", action="store_true",
                     help="skip the explicit-U comparison that follows the deferred headline")
     ap.add_argument("--serve-streams", type=int, default=1024)
@@ -431,6 +522,9 @@ def main():
         return
     if args.finance and args.gpus == 1:
         finance_main(args)
+        return
+    if args.sweep and args.gpus == 1:
+        sweep_main(args)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: the streams are independent and would shard by stream across "
@@ -469,7 +563,7 @@ def main():
             sid64.append(eng64.init(A0, k, "fp64", m_cap=m0 + T, n_cap=n0, refresh_iters=2 if args.refresh_iters is None else args.refresh_iters,
                                     stream=dev_stream))
             U, S, V = eng64.factors(sid64[-1], stream=dev_stream)
-            sid32.append(eng32.init_from_factors(A0, U, S, V, "fp32", m_cap=m0 + T_pay + 2 * PROF_TICKS, n_cap=n0,
+            sid32.append(eng32.init_from_factors(A0, U, S, V, "fp32", m_cap=m0 + T_pay + 2 * PROF_TICKS + 8, n_cap=n0,
                                                  stream=dev_stream))
             if s % 64 == 63:
                 log("  init %d/%d streams (%.1fs)" % (s + 1, len(params), time.perf_counter() - t_init))
@@ -493,6 +587,8 @@ def main():
     # Brand's deferred left basis U = U0 W for the row appends (explicit U
     # rotation every m / (8 k) appends, staggered over the streams)
     eng32.set_deferred_u(not args.explicit_u, stream=dev_stream)
+    # deferred-U row-append ticks replay a captured HIP graph (captured during the warm-up)
+    eng32.set_tick_graphs(not args.explicit_u and not args.no_graphs)
     tune = eng32.autotune(stream=dev_stream)
     log("rotation autotune (bucket: variant): %s" % {kc: v for kc, (v, _) in tune.items()})
     rot_lane = torch.cuda.ExternalStream(eng32.rotation_stream())
@@ -645,14 +741,28 @@ def main():
                      "bytes_per_launch": int(byts)})
         return roof, phase_ms
 
+    # the host's own cost per tick call, with the device busy so that no call
+    # waits for it: a bounded spin kernel first, then 6 ticks issued behind it
+    # (re-using already-applied payloads: only the host side is of interest)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(dev_stream):
+        torch.cuda._sleep(200_000_000)
+    h0 = time.perf_counter()
+    for q in range(6):
+        eng32.tick_raw(reqs[W + q], stream=dev_stream)
+    host_unthrottled = (time.perf_counter() - h0) / 6
+    eng32.sync(stream=dev_stream)
+    torch.cuda.synchronize()
+    log("host cost per tick call with the device busy: %.3f ms" % (host_unthrottled * 1e3))
     deferred = not args.explicit_u
-    roofline, phase_ms = profile_pass(W, deferred, W + K)
+    roofline, phase_ms = profile_pass(W, deferred, W + K + 6)
     mid_all = W + (K - 1) / 2.0
     all_tick_bytes = sum(tick_bytes(m0 + mid_all, n0, k, 4, deferred) for (m0, n0, k) in params)
 
     # ---------------------------------------- the same streams with U rotated on every append
     explicit = None
     if TX:
+        eng32.set_tick_graphs(False)
         eng32.set_deferred_u(False, stream=dev_stream)
         xwall, xtick_ms, xhost = timed_ticks(T, False)
         xvalue = len(params) * K / xwall
@@ -704,10 +814,14 @@ def main():
                                % len(params),
                    "streams": len(params), "rows_total": int(sum(p[0] for p in params)),
                    "cols_total": int(sum(p[1] for p in params)),
+                   "tick": ("one replay of a captured HIP graph per tick" if not (args.explicit_u or args.no_graphs)
+                            else "launched from the host"),
                    "left_basis": ("explicit: U rotated on every append" if args.explicit_u else
                                   "deferred U = U0 W (Brand), explicit rotation every m/(8k) appends per stream")},
         "p50_tick_ms": round(pctl(tick_ms, 50), 4),
         "p99_tick_ms": round(pctl(tick_ms, 99), 4),
+        "host_ms_per_tick": round(host_per_tick * 1e3, 4),
+        "host_ms_per_tick_device_busy": round(host_unthrottled * 1e3, 4),
         "plain_fp64": plain,
         "speedup_vs_plain": round(value / plain["value"], 2) if plain else None,
         "p99_vs_plain": round(plain["p99_tick_ms"] / pctl(tick_ms, 99), 2) if plain else None,
@@ -721,9 +835,14 @@ def main():
         "cpu_baseline": cpu,
         "init_s": round(init_s, 1),
     }
-    print(json.dumps(out), flush=True)
     eng32.close()
     eng64.close()
+    del pay32, pay64, reqs
+    torch.cuda.synchronize()
+    if args.sweep_default > 0:
+        # the precision sweep (1,000,000 x 512, k = 128), shortened; --sweep runs all 5000 appends
+        out["precision_sweep"] = precision_sweep(args, torch, isvd, args.sweep_default)
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

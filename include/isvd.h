@@ -371,6 +371,18 @@ isvd_status isvd_stream_busy(isvd_engine* eng, isvd_id id, int32_t* busy);
  * returning, for the shortest tick latency. */
 isvd_status isvd_set_pipelining(isvd_engine* eng, int32_t enable);
 
+/* Captured ticks (off by default).  With deferred U on, a tick whose
+ * requests are all row appends of streams without a refresh policy is run
+ * as one replay of a HIP graph that records its whole launch sequence (the
+ * request upload, every bucket's projections, core and rotations on the
+ * engine's update lanes, the joins).  The first tick of a request set --
+ * the same streams in the same order -- captures the graph (a few ms); later
+ * ticks of that set write their request records into the graph's pinned
+ * buffer and launch it once, so the host's cost per tick is one launch.
+ * Results are bit for bit those of the uncaptured tick.  A few request sets
+ * are cached; other ticks run as before.  Disabling frees the cache. */
+isvd_status isvd_set_tick_graphs(isvd_engine* eng, int32_t enable);
+
 /* Deferred U (Brand's factorised update of the left basis, U = U0 W, W a
  * k x k FP64 matrix kept with W^-1): enable != 0 lets row appends of
  * eligible streams (FP32 storage, rank up to 64, no angle / error / adaptive

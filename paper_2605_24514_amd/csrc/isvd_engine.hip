@@ -215,6 +215,29 @@ struct Group {
     std::vector<int> pre_rotV; // ... V tiles only
     size_t off_all = 0, off_proj = 0, off_pp = 0, off_pr = 0, off_pru = 0, off_prv = 0;
     bool proj_alias = false;   // the projection list is the whole list (no entry update)
+    std::vector<isvd_id> ids;  // the requests' streams (the key of a captured tick)
+    int rotU_cap = 0;          // U-rotation blocks at the streams' row capacity
+    int grid_u = 0;            // > 0: U-rotation grid of a captured tick (extra blocks idle)
+};
+
+// A captured tick: the launch sequence of one set of row-append requests
+// (streams, buckets, block shapes) recorded once as a HIP graph, replayed
+// every tick with that tick's request records.  kTickGraphBufs buffers
+// (pinned host and device) and as many graphs rotate, so that the host
+// writes the records of later ticks while earlier ones still run.  Grids come from the streams'
+// capacity (U rotation) or fixed shapes (projections, cores, V rotation).
+constexpr int kTickGraphBufs = 8;   // ticks a host may run ahead of the device
+struct TickGraph {
+    std::vector<int64_t> key;
+    size_t bytes = 0;
+    char* host[kTickGraphBufs] = {};
+    char* dev[kTickGraphBufs] = {};
+    hipGraph_t graph[kTickGraphBufs] = {};
+    hipGraphExec_t exec[kTickGraphBufs] = {};
+    hipEvent_t done[kTickGraphBufs] = {};
+    bool launched[kTickGraphBufs] = {};
+    int next = 0;
+    uint64_t last_use = 0;
 };
 
 }  // namespace
@@ -308,6 +331,10 @@ struct isvd_engine {
     // rank bucket (8, 16, 32, 64; the widest bucket uses the LDS-staged
     // kernel), chosen by isvd_autotune
     int rot_var_f32[4] = {1, 1, 1, 1};
+    // captured ticks (isvd_set_tick_graphs): cache of a few request sets
+    bool tick_graphs = false;
+    hipStream_t capture_st = nullptr;
+    std::vector<TickGraph*> tgraphs;
 };
 
 namespace {
@@ -422,7 +449,8 @@ isvd_status launch_group_phase(const Group& g, const char* dev, int phase, hipSt
         // 3: U tiles, 4: V tiles, 5: both
         const int part = phase == 3 ? 1 : phase == 4 ? 2 : 0;
         const int* pr = reinterpret_cast<const int*>(dev + (part == 1 ? g.off_pru : part == 2 ? g.off_prv : g.off_pr));
-        const int nb = (part == 1 ? g.pre_rotU : part == 2 ? g.pre_rotV : g.pre_rot)[na];
+        const int nb = (part == 1 && g.grid_u > 0) ? g.grid_u
+                                                    : (part == 1 ? g.pre_rotU : part == 2 ? g.pre_rotV : g.pre_rot)[na];
         if (nb == 0) return ISVD_OK;
         if constexpr (sizeof(T) == 4 && KC <= 64) {
             static_assert(kRotVariants == 5, "variant dispatch");
@@ -700,8 +728,9 @@ isvd_status launch_recorded(isvd_engine* e, const Group& g, const char* dev, int
 // never runs more than one tick behind: a tick's first launch waits for the
 // lane's end of the tick before last, whose scratch copy this tick's cores
 // overwrite.
-isvd_status run_groups(isvd_engine* e, std::vector<Group>& groups, hipStream_t st, bool pipelined) {
-    ST_TRY(ensure_lanes(e));
+// Layout of a tick's groups in one upload buffer: block prefixes and offsets
+// (groups sorted by bucket, widest first).  Returns the buffer's bytes.
+size_t layout_groups(std::vector<Group>& groups) {
     std::sort(groups.begin(), groups.end(), [](const Group& a, const Group& b) {
         return a.kc != b.kc ? a.kc > b.kc : (a.fp64 && !b.fp64);
     });
@@ -734,18 +763,146 @@ isvd_status run_groups(isvd_engine* e, std::vector<Group>& groups, hipStream_t s
         g.off_pru = take(sizeof(int) * (na + 1));
         g.off_prv = take(sizeof(int) * (na + 1));
     }
+    return off;
+}
+
+// The groups' request records and prefixes into an upload buffer.
+void fill_groups(const std::vector<Group>& groups, char* host) {
+    for (const Group& g : groups) {
+        const size_t na = g.all.size();
+        if (na) memcpy(host + g.off_all, g.all.data(), sizeof(Req) * na);
+        if (!g.proj.empty() && !g.proj_alias) memcpy(host + g.off_proj, g.proj.data(), sizeof(Req) * g.proj.size());
+        memcpy(host + g.off_pp, g.pre_proj.data(), sizeof(int) * g.pre_proj.size());
+        memcpy(host + g.off_pr, g.pre_rot.data(), sizeof(int) * (na + 1));
+        memcpy(host + g.off_pru, g.pre_rotU.data(), sizeof(int) * (na + 1));
+        memcpy(host + g.off_prv, g.pre_rotV.data(), sizeof(int) * (na + 1));
+    }
+}
+
+// Deferred U (own lanes): the launch sequence of one tick whose records are
+// uploaded from `host` to `dev` by the first launch on `st`: the update
+// lanes fork from `st`, each group runs its projections, core, V and U
+// rotations on its lane, and the lanes join back into `st`.
+isvd_status own_lane_sequence(isvd_engine* e, const std::vector<Group>& groups, const char* host, char* dev,
+                              size_t bytes, hipStream_t st) {
+    const size_t n16 = align_up(bytes, 16) / 16;
+    if (n16 > 0)
+        k_upload<<<(int)std::min<size_t>(cdiv(n16, 256), 64), 256, 0, st>>>(reinterpret_cast<const uint4*>(host),
+                                                                          reinterpret_cast<uint4*>(dev), n16);
+    HIP_TRY(hipGetLastError());
+    auto lane_of = [&](const Group& g) -> int { return g.kc >= 64 ? 0 : g.kc >= 32 ? 1 : 2; };
+    constexpr int kLanes = 3;
+    hipStream_t lanes[kLanes] = {e->lane_a, e->lane_b, e->lane_c};
+    hipEvent_t lane_end[kLanes] = {e->ev_main, e->ev_b_end, e->ev_c_end};
+    bool used[kLanes] = {false, false, false};
+    for (const Group& g : groups) used[lane_of(g)] = true;
+    HIP_TRY(hipEventRecord(e->ev_fork, st));
+    for (int l = 0; l < kLanes; ++l)
+        if (used[l]) HIP_TRY(hipStreamWaitEvent(lanes[l], e->ev_fork, 0));
+    for (const Group& g : groups) {
+        hipStream_t ln = lanes[lane_of(g)];
+        for (int phase = 0; phase < 3; ++phase) ST_TRY(launch_recorded(e, g, dev, phase, ln));
+        ST_TRY(launch_recorded(e, g, dev, 4, ln));
+        ST_TRY(launch_recorded(e, g, dev, 3, ln));
+    }
+    for (int l = 0; l < kLanes; ++l)
+        if (used[l]) {
+            HIP_TRY(hipEventRecord(lane_end[l], lanes[l]));
+            HIP_TRY(hipStreamWaitEvent(st, lane_end[l], 0));
+        }
+    return ISVD_OK;
+}
+
+void free_tick_graph(TickGraph* tg) {
+    for (int b = 0; b < kTickGraphBufs; ++b) {
+        if (tg->done[b]) (void)hipEventSynchronize(tg->done[b]);
+        if (tg->exec[b]) (void)hipGraphExecDestroy(tg->exec[b]);
+        if (tg->graph[b]) (void)hipGraphDestroy(tg->graph[b]);
+        if (tg->done[b]) (void)hipEventDestroy(tg->done[b]);
+        if (tg->host[b]) (void)hipHostFree(tg->host[b]);
+        if (tg->dev[b]) (void)hipFree(tg->dev[b]);
+    }
+    delete tg;
+}
+
+constexpr size_t kMaxTickGraphs = 4;
+
+// A deferred-U tick of row appends as one replay of a captured graph (see
+// TickGraph); the first tick of a request set captures it.
+isvd_status run_groups_graph(isvd_engine* e, std::vector<Group>& groups, hipStream_t st, bool pipelined) {
+    ST_TRY(ensure_lanes(e));
+    const size_t off = layout_groups(groups);
+    std::vector<int64_t> key;
+    for (const Group& g : groups) {
+        key.insert(key.end(), {(int64_t)g.kc, (int64_t)(g.fp64 * 2 + g.bf16), (int64_t)g.var, (int64_t)g.rows,
+                               (int64_t)g.all.size(), (int64_t)g.proj.size(), (int64_t)g.rotU_cap});
+        key.insert(key.end(), g.ids.begin(), g.ids.end());
+    }
+    TickGraph* tg = nullptr;
+    for (TickGraph* c : e->tgraphs)
+        if (c->key == key) tg = c;
+    if (!tg) {
+        if (!e->capture_st) HIP_TRY(hipStreamCreateWithFlags(&e->capture_st, hipStreamNonBlocking));
+        if (e->tgraphs.size() >= kMaxTickGraphs) {
+            auto it = std::min_element(e->tgraphs.begin(), e->tgraphs.end(),
+                                       [](const TickGraph* a, const TickGraph* b) { return a->last_use < b->last_use; });
+            free_tick_graph(*it);
+            e->tgraphs.erase(it);
+        }
+        tg = new TickGraph();
+        tg->key = key;
+        tg->bytes = std::max<size_t>(off, 64);
+        isvd_status rc = ISVD_OK;
+        for (int b = 0; b < kTickGraphBufs && rc == ISVD_OK; ++b) {
+            if (hipHostMalloc((void**)&tg->host[b], tg->bytes, hipHostMallocDefault) != hipSuccess ||
+                hipMalloc((void**)&tg->dev[b], tg->bytes) != hipSuccess ||
+                hipEventCreateWithFlags(&tg->done[b], hipEventDisableTiming) != hipSuccess) {
+                rc = fail(ISVD_E_NOMEM, "captured tick buffers");
+                break;
+            }
+            // U-rotation grids sized for the streams' capacity: the captured
+            // grid serves every later tick of this request set
+            for (Group& g : groups) g.grid_u = g.rotU_cap;
+            if (hipStreamBeginCapture(e->capture_st, hipStreamCaptureModeRelaxed) != hipSuccess) {
+                rc = fail(ISVD_E_DEVICE, "tick capture failed to begin");
+                break;
+            }
+            rc = own_lane_sequence(e, groups, tg->host[b], tg->dev[b], off, e->capture_st);
+            const hipError_t ce = hipStreamEndCapture(e->capture_st, &tg->graph[b]);
+            for (Group& g : groups) g.grid_u = 0;
+            if (rc == ISVD_OK && ce != hipSuccess) rc = fail(ISVD_E_DEVICE, "tick capture failed");
+            if (rc == ISVD_OK && hipGraphInstantiate(&tg->exec[b], tg->graph[b], nullptr, nullptr, 0) != hipSuccess)
+                rc = fail(ISVD_E_DEVICE, "tick graph instantiation failed");
+        }
+        if (rc != ISVD_OK) {
+            free_tick_graph(tg);
+            return rc;
+        }
+        e->tgraphs.push_back(tg);
+    }
+    tg->last_use = e->ticks;
+    const int b = tg->next;
+    tg->next = (tg->next + 1) % kTickGraphBufs;
+    // the buffer's previous tick (kTickGraphBufs ticks ago) has read it
+    if (tg->launched[b]) HIP_TRY(hipEventSynchronize(tg->done[b]));
+    fill_groups(groups, tg->host[b]);
+    if (e->ticks >= 2 && e->lane_ticks < 2) HIP_TRY(hipStreamWaitEvent(st, e->ev_tick_end[e->ticks & 1], 0));
+    HIP_TRY(hipGraphLaunch(tg->exec[b], st));
+    HIP_TRY(hipEventRecord(tg->done[b], st));
+    tg->launched[b] = true;
+    HIP_TRY(hipEventRecord(e->ev_tick_end[e->ticks & 1], st));
+    e->ticks += 1;
+    e->lane_ticks += 1;
+    if (!pipelined) ST_TRY(join(e, st));   // rotation-lane work of earlier ticks
+    return ISVD_OK;
+}
+
+isvd_status run_groups(isvd_engine* e, std::vector<Group>& groups, hipStream_t st, bool pipelined) {
+    ST_TRY(ensure_lanes(e));
+    const size_t off = layout_groups(groups);
     Slot* slot = nullptr;
     ST_TRY(acquire_slot(e, off, &slot));
-    for (Group& g : groups) {
-        const size_t na = g.all.size();
-        if (na) memcpy(slot->host + g.off_all, g.all.data(), sizeof(Req) * na);
-        if (!g.proj.empty() && !g.proj_alias)
-            memcpy(slot->host + g.off_proj, g.proj.data(), sizeof(Req) * g.proj.size());
-        memcpy(slot->host + g.off_pp, g.pre_proj.data(), sizeof(int) * g.pre_proj.size());
-        memcpy(slot->host + g.off_pr, g.pre_rot.data(), sizeof(int) * (na + 1));
-        memcpy(slot->host + g.off_pru, g.pre_rotU.data(), sizeof(int) * (na + 1));
-        memcpy(slot->host + g.off_prv, g.pre_rotV.data(), sizeof(int) * (na + 1));
-    }
+    fill_groups(groups, slot->host);
     // With deferred U the U rotations are mostly skipped and run on the
     // group's own update lane after its V rotation; the whole tick then ends
     // on the caller's stream (no rotation lanes, two cross-stream waits).
@@ -1819,6 +1976,7 @@ struct Deferred {
 // With `defer`, a refresh that the policy fires, or an adaptive shrink, is
 // appended to it (the caller runs the tick's actions together) instead of
 // running here.
+constexpr int64_t kBf16AngleCheck = 32;   // BF16-rotation streams: updates between direct angle measurements
 isvd_status after_update(isvd_engine* e, Stream& s, hipStream_t st, const DevHeader* h,
                          Deferred* defer = nullptr) {
     const isvd_policy& p = s.cfg.policy;
@@ -1844,6 +2002,15 @@ isvd_status after_update(isvd_engine* e, Stream& s, hipStream_t st, const DevHea
     }
     if (p.kind == ISVD_POL_ANGLE) {
         if (s.t - s.t_last < std::max<int64_t>(p.t_min, 1)) return ISVD_OK;
+        if (s.bf16 && s.t % kBf16AngleCheck == 0) {
+            // The trackers follow the core's exact rotations, not the BF16
+            // rounding the stored bases take on: every kBf16AngleCheck updates
+            // the angle is measured from the stored U (and M, H restart from it)
+            double theta = 0.0;
+            ST_TRY(direct_trackers(e, s, st, &theta, s.TM, s.TH, s.kc));
+            if (theta > p.theta_max) return refresh();
+            return ISVD_OK;
+        }
         DevHeader hh;
         if (!h) {
             ST_TRY(read_header(s, st, &hh));
@@ -2156,6 +2323,9 @@ isvd_status isvd_engine_destroy(isvd_engine* e) {
     for (Slot& s : e->ring)
         if (s.ev) (void)hipEventDestroy(s.ev);
     if (e->ring_host) (void)hipHostFree(e->ring_host);
+    for (TickGraph* tg : e->tgraphs) free_tick_graph(tg);
+    e->tgraphs.clear();
+    if (e->capture_st) (void)hipStreamDestroy(e->capture_st);
     if (e->ring_dev) (void)hipFree(e->ring_dev);
     if (e->ws.p) (void)hipFree(e->ws.p);
     free_retired(e->ws);
@@ -2234,6 +2404,17 @@ isvd_status isvd_set_deferred_u(isvd_engine* e, int32_t enable, void* hip_stream
         }
     }
     e->defer_u = enable != 0;
+    return ISVD_OK;
+}
+
+isvd_status isvd_set_tick_graphs(isvd_engine* e, int32_t enable) {
+    if (!e) return fail(ISVD_E_INVAL, "null engine");
+    ST_TRY(ensure_device(e));
+    e->tick_graphs = enable != 0;
+    if (!e->tick_graphs) {
+        for (TickGraph* tg : e->tgraphs) free_tick_graph(tg);
+        e->tgraphs.clear();
+    }
     return ISVD_OK;
 }
 
@@ -3013,8 +3194,18 @@ isvd_status isvd_tick(isvd_engine* e, int32_t count, const isvd_request* reqs, v
         Req rq = make_req(e, s, r.kind, r.payload, r.i, r.j, r.delta, k_keep_for(s, r.kind));
         g.all.push_back(rq);
         if (r.kind != ISVD_ENTRY) g.proj.push_back(rq);
+        g.ids.push_back(r.id);
+        g.rotU_cap += (int)cdiv(s.cfg.m_cap, g.rows);
     }
-    ST_TRY(run_groups(e, groups, st, pipelined));
+    // deferred-U ticks of row appends without policies replay a captured graph
+    bool graph = e->tick_graphs && e->defer_u && !e->profiling;
+    for (int q = 0; q < count && graph; ++q)
+        graph = reqs[q].kind == ISVD_ROW && ss[q]->cfg.policy.kind == ISVD_POL_NONE && !ss[q]->angle &&
+                !ss[q]->refreshing;
+    if (graph)
+        ST_TRY(run_groups_graph(e, groups, st, pipelined));
+    else
+        ST_TRY(run_groups(e, groups, st, pipelined));
     std::vector<Track> tracks;
     std::vector<char> tfp;
     for (int q = 0; q < count; ++q)

@@ -54,6 +54,9 @@ __global__ void __launch_bounds__(kThreads) k_proj(const Req* __restrict__ reqs,
     constexpr int UNR = 4;                       // row steps in flight per lane
     __shared__ double sacc[RPB][SP];
     __shared__ double sp1[KC];
+    // a grid sized for more tiles than this launch has (a captured tick,
+    // sized for the streams' capacity) leaves the extra blocks idle
+    if ((int)blockIdx.x >= prefix[nreq]) return;
     const int ri = find_req(prefix, nreq, blockIdx.x);
     const Req& rq = reqs[ri];
     const int tile = blockIdx.x - prefix[ri];
@@ -649,6 +652,9 @@ __global__ void __launch_bounds__(kThreads) k_rotate(const Req* __restrict__ req
     __shared__ T sX[RT * KC];
     __shared__ double sz[RT];
     __shared__ double sp[KC];
+    // a grid sized for more tiles than this launch has (a captured tick,
+    // sized for the streams' capacity) leaves the extra blocks idle
+    if ((int)blockIdx.x >= prefix[nreq]) return;
     const int ri = find_req(prefix, nreq, blockIdx.x);
     const Req& rq = reqs[ri];
     const ReqScratch* rs = rq.rs;
@@ -735,6 +741,9 @@ __global__ void __launch_bounds__(kThreads) k_rotate_mfma(const Req* __restrict_
     __shared__ float sX[4][16 * XP];
     __shared__ float sO[4][16 * OP];
     __shared__ double sp[KC];
+    // a grid sized for more tiles than this launch has (a captured tick,
+    // sized for the streams' capacity) leaves the extra blocks idle
+    if ((int)blockIdx.x >= prefix[nreq]) return;
     const int ri = find_req(prefix, nreq, blockIdx.x);
     const Req& rq = reqs[ri];
     const ReqScratch* rs = rq.rs;
@@ -905,6 +914,9 @@ __global__ void __launch_bounds__(kThreads) k_rotate_mfma_t(const Req* __restric
     constexpr int TSTEPS = ROWS / SROWS;
     __shared__ double sp[16 * NQ];
     __shared__ float sqz[16 * NB];
+    // a grid sized for more tiles than this launch has (a captured tick,
+    // sized for the streams' capacity) leaves the extra blocks idle
+    if ((int)blockIdx.x >= prefix[nreq]) return;
     const int ri = find_req(prefix, nreq, blockIdx.x);
     const Req& rq = reqs[ri];
     const ReqScratch* rs = rq.rs;

@@ -94,7 +94,7 @@ ROT_VARIANTS = [(256, 1, True), (512, 1, True), (1024, 1, True), (1024, 2, False
 EXPORTS = ["isvd_engine_create", "isvd_engine_destroy", "isvd_stream_bytes", "isvd_init", "isvd_init_from_factors",
            "isvd_append_row", "isvd_append_col", "isvd_update_entry", "isvd_refresh", "isvd_refresh_noalloc", "isvd_metrics",
            "isvd_get_factors", "isvd_get_matrix", "isvd_shape", "isvd_release", "isvd_tick",
-           "isvd_profile", "isvd_profile_read", "isvd_autotune", "isvd_set_rotation_variant", "isvd_sync", "isvd_stream_busy", "isvd_rotation_stream", "isvd_set_pipelining",
+           "isvd_profile", "isvd_profile_read", "isvd_autotune", "isvd_set_rotation_variant", "isvd_sync", "isvd_stream_busy", "isvd_rotation_stream", "isvd_set_pipelining", "isvd_set_tick_graphs",
            "isvd_server_create", "isvd_server_destroy", "isvd_server_clock", "isvd_server_error",
            "isvd_server_add_stream", "isvd_server_submit", "isvd_server_submit_many", "isvd_server_step", "isvd_server_drain",
            "isvd_server_poll", "isvd_server_stats", "isvd_server_stream", "isvd_last_error",
@@ -140,6 +140,7 @@ def load_library(path=LIB_PATH):
         "isvd_sync": (i32, [vp, vp]),
         "isvd_stream_busy": (i32, [vp, i64, ctypes.POINTER(i32)]),
         "isvd_set_pipelining": (i32, [vp, i32]),
+        "isvd_set_tick_graphs": (i32, [vp, i32]),
         "isvd_set_deferred_u": (i32, [vp, i32, vp]),
         "isvd_server_create": (i32, [vp, ctypes.POINTER(CServerConfig), vp, ctypes.POINTER(vp)]),
         "isvd_server_destroy": (i32, [vp]),
@@ -482,6 +483,10 @@ class Engine:
 
     def set_pipelining(self, enable):
         self._check(self._lib.isvd_set_pipelining(self._h, 1 if enable else 0), "isvd_set_pipelining")
+
+    def set_tick_graphs(self, enable):
+        """Replay deferred-U row-append ticks as captured HIP graphs."""
+        self._check(self._lib.isvd_set_tick_graphs(self._h, 1 if enable else 0), "isvd_set_tick_graphs")
 
     def set_deferred_u(self, enable, stream=None):
         """Brand's deferred left basis U = U0 W for the row appends of eligible
