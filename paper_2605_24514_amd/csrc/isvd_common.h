@@ -38,6 +38,17 @@ __host__ __device__ inline int round4(int k) { return (k + 3) & ~3; }
 __host__ __device__ inline int64_t uvo(int64_t r, int c, int ld) {
     return (r >> 4) * 16 * (int64_t)ld + (c >> 4) * 256 + ((c & 15) >> 2) * 64 + (r & 15) * 4 + (c & 3);
 }
+// Global-memory view of a pointer taken from a request or header record.
+// Loads and stores through generic pointers are flat accesses, which count
+// against the LDS wait counter as well: every wait for an LDS result would
+// also wait for them.  Through these the compiler emits global accesses.
+#define ISVD_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ inline ISVD_GLOBAL T* gmem(T* p) { return (ISVD_GLOBAL T*)p; }
+// plain vector types for loads through such pointers
+typedef float gvec_f4 __attribute__((ext_vector_type(4)));
+typedef double gvec_d2 __attribute__((ext_vector_type(2)));
+typedef double gvec_d4 __attribute__((ext_vector_type(4)));
 // (row, column) inside a tile of element e of that tile
 __host__ __device__ inline void uv_tile_rc(int e, int* r, int* c) {
     const int rem = e & 255;

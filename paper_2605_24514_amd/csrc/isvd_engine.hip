@@ -444,7 +444,7 @@ isvd_status launch_group_phase(const Group& g, const char* dev, int phase, hipSt
         k_proj<T, KC, 2><<<g.pre_proj[np], kThreads, 0, st>>>(proj, pp, np);
     } else if (phase == 2 && na > 0) {
         size_t lds = sizeof(double) * core_lds_doubles<KC, sizeof(T) == 8>();
-        k_core<T, KC><<<na, CoreShape<KC>::J::NT, lds, st>>>(all);
+        k_core<T, KC><<<na, core_nt<KC, sizeof(T) == 8>(), lds, st>>>(all);
     } else if (phase >= 3 && na > 0) {
         // 3: U tiles, 4: V tiles, 5: both
         const int part = phase == 3 ? 1 : phase == 4 ? 2 : 0;

@@ -67,6 +67,27 @@ __device__ inline double dpp_move(double x) {
     return __hiloint2double(hi, lo);
 }
 
+template <int CTRL>
+__device__ inline int dpp_move_int(int x) {
+    return __builtin_amdgcn_update_dpp(0, x, CTRL, 0xF, 0xF, false);
+}
+
+// Largest v over an aligned group of G lanes, ties to the lowest i; every
+// lane of the group ends with the same pair.
+template <int G>
+__device__ inline void dpp_group_argmax(double& v, int& i) {
+    auto take = [&](double ov, int oi) {
+        if (ov > v || (ov == v && oi < i)) {
+            v = ov;
+            i = oi;
+        }
+    };
+    if constexpr (G >= 2) take(dpp_move<0xB1>(v), dpp_move_int<0xB1>(i));
+    if constexpr (G >= 4) take(dpp_move<0x4E>(v), dpp_move_int<0x4E>(i));
+    if constexpr (G >= 8) take(dpp_move<0x141>(v), dpp_move_int<0x141>(i));
+    if constexpr (G >= 16) take(dpp_move<0x140>(v), dpp_move_int<0x140>(i));
+}
+
 template <int TPP>
 __device__ inline double dpp_group_sum(double v) {
     if constexpr (TPP >= 2) v += dpp_move<0xB1>(v);

@@ -275,20 +275,27 @@ __device__ inline bool secular_append_core(const double* s, const double* p, dou
     }
     __syncthreads();
     // take this path only if every kept triplet is well above sigma_1's resolution
-    if (tid == 0) {
+    if (tid < 64) {
+        // reduced by the first wave
         double lmax = 0.0;
         bool finite = true;
-        for (int c = 0; c < N; ++c) {
+        for (int c = tid; c < N; c += 64) {
             finite = finite && isfinite(lam[c]);
             lmax = fmax(lmax, lam[c]);
         }
+        for (int o = 32; o > 0; o >>= 1) lmax = fmax(lmax, __shfl_xor(lmax, o));
+        finite = __ballot(!finite) == 0ull;
         int npos = 0, nbig = 0;
-        for (int c = 0; c < N; ++c) {
+        for (int c = tid; c < N; c += 64) {
             npos += lam[c] > 0.0 ? 1 : 0;
             nbig += lam[c] >= kSecularMinRatio * kSecularMinRatio * lmax ? 1 : 0;
         }
+        for (int o = 32; o > 0; o >>= 1) {
+            npos += __shfl_xor(npos, o);
+            nbig += __shfl_xor(nbig, o);
+        }
         const int kexp = kkeep < npos ? kkeep : npos;
-        s_cnt[3] = (finite && lmax > 0.0 && nbig >= kexp) ? 1 : 0;
+        if (tid == 0) s_cnt[3] = (finite && lmax > 0.0 && nbig >= kexp) ? 1 : 0;
     }
     __syncthreads();
     if (!s_cnt[3]) return false;
@@ -350,11 +357,13 @@ __device__ inline bool secular_append_core(const double* s, const double* p, dou
         const int c = e / k, r = e % k;
         W[(size_t)c * ldw + r] = s[r] * V[(size_t)c * ldw + r];
     }
-    for (int c = tid; c < N; c += NT) {
+    // row k of W (the appended row of K times V): one G-lane group per column
+    for (int c = gid; c < N; c += NT / G) {
         const double* vc = V + (size_t)c * ldw;
-        double t = rho * vc[k];
-        for (int j = 0; j < k; ++j) t += p[j] * vc[j];
-        W[(size_t)c * ldw + k] = t;
+        double t = 0.0;
+        for (int j = sub; j < k; j += G) t += p[j] * vc[j];
+        t = dpp_group_sum<G>(t);
+        if (sub == 0) W[(size_t)c * ldw + k] = t + rho * vc[k];
     }
     __syncthreads();
     return true;

@@ -18,6 +18,14 @@ __device__ inline void load4(const T* p, double out[4]) {
     typename V4<T>::type v = *reinterpret_cast<const typename V4<T>::type*>(p);
     out[0] = (double)v.x; out[1] = (double)v.y; out[2] = (double)v.z; out[3] = (double)v.w;
 }
+template <typename T> struct GV4;
+template <> struct GV4<float> { typedef gvec_f4 type; };
+template <> struct GV4<double> { typedef gvec_d4 type; };
+template <typename T>
+__device__ inline void load4(const ISVD_GLOBAL T* p, double out[4]) {
+    typename GV4<T>::type v = *reinterpret_cast<const ISVD_GLOBAL typename GV4<T>::type*>(p);
+    out[0] = (double)v.x; out[1] = (double)v.y; out[2] = (double)v.z; out[3] = (double)v.w;
+}
 
 // Request owning block b: the last r with prefix[r] <= b.
 __device__ inline int find_req(const int* prefix, int nreq, int b) {
@@ -60,17 +68,18 @@ __global__ void __launch_bounds__(kThreads) k_proj(const Req* __restrict__ reqs,
     const int ri = find_req(prefix, nreq, blockIdx.x);
     const Req& rq = reqs[ri];
     const int tile = blockIdx.x - prefix[ri];
-    const int k = rq.hdr->k, ld = rq.hdr->ld, cur = rq.hdr->cur;
+    const ISVD_GLOBAL DevHeader* hdr = gmem(rq.hdr);
+    const int k = hdr->k, ld = hdr->ld, cur = hdr->cur;
     const bool useU = rq.kind == kCol;
-    const T* X = (const T*)basis_cur(rq, useU, cur);
+    const ISVD_GLOBAL T* X = gmem((const T*)basis_cur(rq, useU, cur));
     const int64_t rows = useU ? rq.m : rq.n;
-    const T* y = (const T*)rq.payload;
+    const ISVD_GLOBAL T* y = gmem((const T*)rq.payload);
     if (PASS == 2) {
         // p1: pass 1's partials in block order
         for (int c = threadIdx.x; c < KC; c += kThreads) {
             double s1 = 0.0;
             if (c < k)
-                for (int t = 0; t < rq.proj_tiles; ++t) s1 += rq.partials[(size_t)t * SP + c];
+                for (int t = 0; t < rq.proj_tiles; ++t) s1 += gmem(rq.partials)[(size_t)t * SP + c];
             sp1[c] = s1;
         }
         __syncthreads();
@@ -137,7 +146,7 @@ __global__ void __launch_bounds__(kThreads) k_proj(const Req* __restrict__ reqs,
         sacc[grp][KC + 1] = bad;
     }
     __syncthreads();
-    double* part = (PASS == 1 ? rq.partials : rq.partials2) + (size_t)tile * SP;
+    ISVD_GLOBAL double* part = gmem(PASS == 1 ? rq.partials : rq.partials2) + (size_t)tile * SP;
     for (int c = threadIdx.x; c < SP; c += kThreads) {
         double s1 = 0.0;
         for (int gg = 0; gg < RPB; ++gg) s1 += sacc[gg][c];
@@ -189,14 +198,36 @@ __host__ __device__ constexpr bool core_secular() { return !WITH_J && KC <= 64; 
 template <int KC, bool WITH_J>
 __host__ __device__ constexpr bool core_j_global() { return WITH_J && KC > 64; }
 
-// dynamic LDS (doubles) of a core block of bucket KC
+// threads of a core block: the Jacobi shape's, or for the secular path
+// eight lanes per pole (roots, weights, norms, sort and sign take one lane
+// group per column)
 template <int KC, bool WITH_J>
-__host__ __device__ constexpr size_t core_lds_doubles() {
+__host__ __device__ constexpr int core_nt() {
+    constexpr int NJ = CoreShape<KC>::J::NT;
+    constexpr int NS = (8 * CoreShape<KC>::NMAX + 63) / 64 * 64;
+    return core_secular<KC, WITH_J>() && NS > NJ ? NS : NJ;
+}
+
+// Row stride (doubles) of W and W^-1 staged in LDS for the deferred-U
+// products: KC + 2 spreads the rows of a 16-row operand over the banks.
+template <int KC>
+__host__ __device__ constexpr int core_wst() { return KC + 2; }
+
+// dynamic LDS (doubles) of a core block of bucket KC; the secular (FP32
+// append) cores also stage W and W^-1 after it (and A^T in the V_K region)
+template <int KC, bool WITH_J>
+__host__ __device__ constexpr size_t core_lds_base() {
     constexpr bool SEC = core_secular<KC, WITH_J>();
     constexpr bool JLDS = (WITH_J && !core_j_global<KC, WITH_J>()) || SEC;
     return (size_t)(JLDS ? 2 : 1) * CoreShape<KC>::NMAX * CoreShape<KC>::J::LDW +
            (size_t)(WITH_J ? 6 : 8) * CoreShape<KC>::NMAX +
            (size_t)(SEC ? secular_scratch_doubles(CoreShape<KC>::NMAX) : 0);
+}
+template <int KC, bool WITH_J>
+__host__ __device__ constexpr size_t core_lds_doubles() {
+    static_assert(KC * core_wst<KC>() <= CoreShape<KC>::NMAX * CoreShape<KC>::J::LDW, "A^T fits the V_K region");
+    // (+1: room to align the region to 16 bytes)
+    return core_lds_base<KC, WITH_J>() + (core_secular<KC, WITH_J>() ? (size_t)2 * KC * core_wst<KC>() : 0) + 1;
 }
 // global doubles of Req::Jg for a stream of bucket KC
 __host__ __device__ constexpr size_t core_jg_doubles(int KC) {
@@ -204,17 +235,20 @@ __host__ __device__ constexpr size_t core_jg_doubles(int KC) {
 }
 
 template <typename T, int KC>
-__global__ void __launch_bounds__(CoreShape<KC>::J::NT) k_core(const Req* __restrict__ reqs) {
+__global__ void __launch_bounds__((core_nt<KC, sizeof(T) == 8>())) k_core(const Req* __restrict__ reqs) {
     constexpr bool WITH_J = sizeof(T) == 8;
     constexpr bool SEC = core_secular<KC, WITH_J>();
     constexpr bool JG = core_j_global<KC, WITH_J>();
-    extern __shared__ double smem[];
+    // the dynamic region starts where the static one ends, 8-byte aligned;
+    // the deferred-U products move pairs of doubles, which need 16 bytes
+    extern __shared__ double smem_raw[];
+    double* smem = smem_raw + (((uintptr_t)smem_raw & 15) ? 1 : 0);
     __shared__ double s_sc[8];
     __shared__ int s_i[4];
     __shared__ int s_sec[4];
     const Req& rq = reqs[blockIdx.x];
-    DevHeader* hdr = rq.hdr;
-    ReqScratch* rs = rq.rs;
+    ISVD_GLOBAL DevHeader* hdr = gmem(rq.hdr);
+    ISVD_GLOBAL ReqScratch* rs = gmem(rq.rs);
     const int k = hdr->k, ld = hdr->ld, cur = hdr->cur;
     const int kind = rq.kind;
     const int N = kind == kEntry ? k : k + 1;
@@ -234,13 +268,13 @@ __global__ void __launch_bounds__(CoreShape<KC>::J::NT) k_core(const Req* __rest
     double* xsec = dcol + N;                       // secular scratch
 
     // projection sums of an append: the k_proj partials added in block order
-    const size_t total = core_lds_doubles<KC, WITH_J>();
+    const size_t total = core_lds_doubles<KC, WITH_J>() - 1;   // past the alignment slack
     double* src1 = smem + total - 2 * (KC + 2);
     double* src2 = src1 + (KC + 2);
     if (kind != kEntry) {
         for (int c = tid; c < 2 * (KC + 2); c += nt) {
             const int cc = c < KC + 2 ? c : c - (KC + 2);
-            const double* part = c < KC + 2 ? rq.partials : rq.partials2;
+            const ISVD_GLOBAL double* part = gmem(c < KC + 2 ? rq.partials : rq.partials2);
             double s1 = 0.0;
             if (cc < k || cc >= KC)
                 for (int t = 0; t < rq.proj_tiles; ++t) s1 += part[(size_t)t * (KC + 2) + cc];
@@ -250,14 +284,18 @@ __global__ void __launch_bounds__(CoreShape<KC>::J::NT) k_core(const Req* __rest
     }
     double pc = 0.0;
     if (kind != kEntry && tid < k) pc = src1[tid] + src2[tid];
+    // ||p2||^2, reduced by wave 0
+    double p2sq = 0.0;
+    if (kind != kEntry && tid < 64) {
+        for (int c = tid; c < k; c += 64) p2sq += src2[c] * src2[c];
+        for (int o = 32; o > 0; o >>= 1) p2sq += __shfl_xor(p2sq, o);
+    }
     if (tid == 0) {
         int skip = hdr->status != 0 ? 1 : 0;
         double rho = 0.0, xnorm = 0.0, inv_rho = 0.0;
         int newdir = 0;
         if (kind != kEntry) {
             if (src1[KC + 1] > 0.0) skip = 1;
-            double p2sq = 0.0;
-            for (int c = 0; c < k; ++c) p2sq += src2[c] * src2[c];
             const double z1sq = src2[KC];
             const double ysq = src1[KC];
             const double r2 = z1sq - p2sq;
@@ -289,13 +327,13 @@ __global__ void __launch_bounds__(CoreShape<KC>::J::NT) k_core(const Req* __rest
     const double rho = s_sc[0];
     // p = p1 + p2 (also kept in global memory for the rotation, which recomputes z^ per row)
     for (int c = tid; c < k; c += nt) {
-        sS[c] = rq.S[c];
+        sS[c] = gmem(rq.S)[c];
         if (kind != kEntry) {
             sp[c] = pc;
-            rq.p[c] = pc;
+            gmem(rq.p)[c] = pc;
         } else {
-            if constexpr (!WITH_J) su[c] = (double)((const T*)rq.U[cur])[uvo(rq.i, c, ld)];
-            sp[c] = (double)((const T*)rq.V[cur])[uvo(rq.j, c, ld)];
+            if constexpr (!WITH_J) su[c] = (double)gmem((const T*)rq.U[cur])[uvo(rq.i, c, ld)];
+            sp[c] = (double)gmem((const T*)rq.V[cur])[uvo(rq.j, c, ld)];
         }
     }
     __syncthreads();
@@ -309,7 +347,7 @@ __global__ void __launch_bounds__(CoreShape<KC>::J::NT) k_core(const Req* __rest
             continue;
         }
         if (kind == kEntry) {
-            const double uu = WITH_J ? (double)((const T*)rq.U[cur])[uvo(rq.i, row, ld)] : su[row];
+            const double uu = WITH_J ? (double)gmem((const T*)rq.U[cur])[uvo(rq.i, row, ld)] : su[row];
             v = (row == col ? sS[row] : 0.0) + rq.delta * uu * sp[col];
         } else {
             if (row < k) v = (row == col) ? sS[row] : 0.0;
@@ -321,14 +359,58 @@ __global__ void __launch_bounds__(CoreShape<KC>::J::NT) k_core(const Req* __rest
     __syncthreads();
     bool use_sec = false;
     if constexpr (SEC) {
-        if (kind != kEntry) use_sec = secular_append_core<CoreShape<KC>::NMAX, CoreShape<KC>::J::NT>(sS, sp, rho, k, rq.k_keep < N ? rq.k_keep : N, W, J, ldw,
+        if (kind != kEntry) use_sec = secular_append_core<CoreShape<KC>::NMAX, core_nt<KC, WITH_J>()>(sS, sp, rho, k, rq.k_keep < N ? rq.k_keep : N, W, J, ldw,
                                                           xsec, s_sec);
     }
     // FP32 storage rounds U_K, V_K to 6e-8: columns orthogonal to 1e-10 suffice
     const int sweeps = use_sec ? 0
                                : jacobi_block<CoreShape<KC>::NMAX, WITH_J, CoreShape<KC>::J::TPP>(
                                      W, J, N, ldw, 40, WITH_J ? 0.0 : 1e-10);
-    jacobi_sort(W, N, ldw, sig, perm, tmp);
+    constexpr int NTC = core_nt<KC, WITH_J>();
+    // a deferred-U stream's W and W^-1 (current parity, KC x KC each): the
+    // loads are issued here and complete during the sort, the signs and the
+    // rotation outputs; they are staged in LDS for the products
+    constexpr int PF = SEC ? (KC * KC + NTC - 1) / NTC : 1;   // pairs of doubles of both matrices per thread
+    gvec_d2 pf[PF];
+    if constexpr (SEC) {
+        if (kind == kRow && rq.Wd[0] != nullptr) {
+            const int wp0 = hdr->wpar;
+            const ISVD_GLOBAL gvec_d2* w2 = gmem((const gvec_d2*)rq.Wd[wp0]);
+            const ISVD_GLOBAL gvec_d2* wi2 = gmem((const gvec_d2*)rq.Wdi[wp0]);
+#pragma unroll
+            for (int q = 0; q < PF; ++q) {
+                const int e = tid + q * NTC;   // [0, KC^2 / 2): W, then W^-1
+                if (e < KC * KC / 2) pf[q] = w2[e];
+                else if (e < KC * KC) pf[q] = wi2[e - KC * KC / 2];
+            }
+        }
+    }
+    // singular values: the column norms of W, one GS-lane group per column,
+    // sorted non-increasing (ties: lower column first)
+    constexpr int GS = sec_lanes(CoreShape<KC>::NMAX, NTC);
+    const int gs = tid / GS, ls = tid % GS;
+    for (int c = gs; c < N; c += NTC / GS) {
+        const double* w = W + (size_t)c * ldw;
+        double s2 = 0.0;
+        for (int e = ls; e < N; e += GS) s2 += w[e] * w[e];
+        s2 = dpp_group_sum<GS>(s2);
+        if (ls == 0) tmp[c] = sqrt(s2);
+    }
+    __syncthreads();
+    for (int c = gs; c < N; c += NTC / GS) {
+        const double sc = tmp[c];
+        double r = 0.0;
+        for (int d = ls; d < N; d += GS) {
+            const double sd = tmp[d];
+            r += (sd > sc || (sd == sc && d < c)) ? 1.0 : 0.0;
+        }
+        r = dpp_group_sum<GS>(r);
+        if (ls == 0) {
+            perm[(int)r] = c;
+            sig[(int)r] = sc;
+        }
+    }
+    __syncthreads();
     if constexpr (!WITH_J) {
         if (kind == kEntry) {
             for (int c = tid; c < N; c += nt) {
@@ -355,15 +437,22 @@ __global__ void __launch_bounds__(CoreShape<KC>::J::NT) k_core(const Req* __rest
             return kw / s2;
         }
     };
-    for (int jj = tid; jj < N; jj += nt) {
+    // signs: the largest-magnitude entry of each right vector positive (the
+    // first one on ties), one GS-lane group per vector
+    for (int jj = gs; jj < N; jj += NTC / GS) {
         const int c = perm[jj];
-        int imax = 0;
-        double vmax = fabs(vraw(0, c));
-        for (int e = 1; e < N; ++e) {
+        int imax = N;
+        double vmax = -1.0;
+        for (int e = ls; e < N; e += GS) {
             const double a = fabs(vraw(e, c));
-            if (a > vmax) { vmax = a; imax = e; }
+            if (a > vmax) {
+                vmax = a;
+                imax = e;
+            }
         }
-        sgn[jj] = vraw(imax, c) < 0.0 ? -1.0 : 1.0;
+        dpp_group_argmax<GS>(vmax, imax);
+        if (imax >= N) imax = 0;
+        if (ls == 0) sgn[jj] = vraw(imax, c) < 0.0 ? -1.0 : 1.0;
     }
     __syncthreads();
     int kout;
@@ -398,8 +487,8 @@ __global__ void __launch_bounds__(CoreShape<KC>::J::NT) k_core(const Req* __rest
         sin2_u = kind == kRow ? bu : bv;
         sin2_v = kind == kRow ? bv : bu;
     }
-    T* QU = (T*)rq.QU;
-    T* QV = (T*)rq.QV;
+    ISVD_GLOBAL T* QU = gmem((T*)rq.QU);
+    ISVD_GLOBAL T* QV = gmem((T*)rq.QV);
     // Deferred U (U = U0 W, Brand): a row append whose rank stays k and whose
     // new row b = U_K[k, :k] has |b|^2 <= 1/2 is applied to W alone when the
     // host asks for it; otherwise W is folded into the rotation of U.
@@ -417,161 +506,209 @@ __global__ void __launch_bounds__(CoreShape<KC>::J::NT) k_core(const Req* __rest
         }
     }
     // U_K(e, j) = sgn_j W[e, perm_j] / sigma_j ;  V_K(e, j) = sgn_j vraw(e, perm_j)
+    double* fsg = su;   // sgn_j / sigma_j (s_u is no longer needed)
+    for (int j = tid; j < kout; j += nt) fsg[j] = sig[j] > 0.0 ? sgn[j] / sig[j] : 0.0;
+    __syncthreads();
     for (int e = tid; e < N * ldo; e += nt) {
         const int row = e / ldo, j = e % ldo;
         double uk = 0.0, vk = 0.0;
         if (j < kout) {
             const int c = perm[j];
-            const double sv = sig[j];
-            uk = sv > 0.0 ? sgn[j] * W[(size_t)c * ldw + row] / sv : 0.0;
+            uk = fsg[j] * W[(size_t)c * ldw + row];
             vk = sgn[j] * vraw(row, c);
         }
         if (kind == kEntry) {
             QU[e] = (T)uk;
             QV[e] = (T)vk;
         } else if (kind == kRow) {
-            if (row < k) QU[e] = (T)uk;
-            else if (!defer) ((T*)rq.U[cur ^ 1])[uvo(rq.m, j, ldo)] = (T)uk;
+            if (row < k) {
+                if (!wd) QU[e] = (T)uk;   // with W, QU is W A (explicit) or unused (deferred)
+            }
+            else if (!defer) gmem((T*)rq.U[cur ^ 1])[uvo(rq.m, j, ldo)] = (T)uk;
             QV[e] = (T)vk;
         } else {
             QU[e] = (T)vk;
             if (row < k) QV[e] = (T)uk;
-            else ((T*)rq.V[cur ^ 1])[uvo(rq.n, j, ldo)] = (T)uk;
+            else gmem((T*)rq.V[cur ^ 1])[uvo(rq.n, j, ldo)] = (T)uk;
         }
     }
-    for (int j = tid; j < kout; j += nt) rq.S[j] = sig[j];
-    if constexpr (!WITH_J) {
+    for (int j = tid; j < kout; j += nt) gmem(rq.S)[j] = sig[j];
+    if constexpr (SEC) {
         if (wd) {
-            // W, W^-1: KC x KC row-major; A = U_K[0:k, 0:k] and b = U_K[k, 0:k]
-            // with A^T A + b^T b = I, so A^-1 = (I + b^T b / (1 - |b|^2)) A^T.
-            // A[c][j] = f_j Kv[perm_j][c] with f_j = sgn_j / sigma_j (Kv: the
-            // columns of K V in LDS).  Each k x k operand read in a product is
-            // first staged in the V_K region of LDS (free once QV is written),
-            // row stride k + 1.
+            // W, W^-1: KC x KC row-major (entries past k are never read).  With
+            // A = U_K[0:k, 0:k], b = U_K[k, 0:k] (A^T A + b^T b = I) and
+            // f_j = sgn_j / sigma_j: A[c][j] = f_j Kv[perm_j][c], b_j =
+            // f_j Kv[perm_j][k] (Kv: the columns of K V in LDS).
+            //   deferred: W' = W A and W'^-1 = A^-1 W^-1 with A^-1 =
+            //     (I + b^T b / (1 - |b|^2)) A^T, i.e. A^-1[r][c] = A[c][r] +
+            //     b_r v_c for v = b A^T / (1 - |b|^2); the new row of U0 is
+            //     u0 = b W'^-1 = v W^-1.
+            //   explicit: U's rotation takes W A, and W, W^-1 return to I.
+            // The products run on the FP64 matrix cores
+            // (v_mfma_f64_16x16x4f64: lane l holds A[l%16][l/16] and
+            // B[l/16][l%16]; D[4r + l/16][l%16] is the lane's r-th value), one
+            // 16 x 16 output tile per wave at a time (at most eight waves, two
+            // per SIMD); lane quarter q takes the contraction indices
+            // [q KC/4, (q+1) KC/4), so each lane reads its operands from LDS
+            // as contiguous runs: rows of W, of W^-1's transpose, and of A^T,
+            // first gathered from K V in sorted order.
             const int wp = hdr->wpar;
-            const double* Wo = rq.Wd[wp];
-            const double* Wio = rq.Wdi[wp];
-            double* stg = J;
-            const int lds_s = k + 1;
+            double* bv = xsec;                                  // b (k)
+            double* gv = xsec + CoreShape<KC>::NMAX;            // f_j b_j (k)
+            double* vv = xsec + 2 * CoreShape<KC>::NMAX;        // v (k)
+            constexpr int WST = core_wst<KC>();
+            static_assert(core_lds_base<KC, WITH_J>() % 2 == 0 && WST % 2 == 0, "16-byte rows");
+            double* At = J;                                      // A^T (the V_K region is free now)
+            double* Wl = smem + core_lds_base<KC, WITH_J>();    // W
+            double* Wil = Wl + KC * WST;                        // W^-1, transposed
             __syncthreads();
-            for (int j = tid; j < kout; j += nt) sgn[j] = sgn[j] / sig[j];
-            // deferred streams have KC <= 64: all of a thread's loads are
-            // issued before its LDS stores
-            constexpr int NTB = CoreShape<KC>::J::NT;
-            constexpr int SIT = (KC * KC + NTB - 1) / NTB;
-            auto stage = [&](const double* src) {
-                if constexpr (KC <= 64) {
-                    double v[SIT];
 #pragma unroll
-                    for (int q = 0; q < SIT; ++q) {
-                        const int e = tid + q * NTB;
-                        v[q] = e < k * k ? src[(size_t)(e / k) * KC + e % k] : 0.0;
+            for (int q = 0; q < PF; ++q) {
+                const int e = tid + q * NTC;
+                if (e < KC * KC / 2) {
+                    *(gvec_d2*)(Wl + (2 * e / KC) * WST + 2 * e % KC) = pf[q];
+                } else if (e < KC * KC) {
+                    const int e2 = 2 * (e - KC * KC / 2), r = e2 / KC, c = e2 % KC;
+                    Wil[c * WST + r] = pf[q].x;
+                    Wil[(c + 1) * WST + r] = pf[q].y;
+                }
+            }
+            for (int j = tid; j < kout; j += nt) {
+                const double f = sgn[j] / sig[j];
+                const double kb = W[(size_t)perm[j] * ldw + k];
+                sgn[j] = f;
+                bv[j] = f * kb;
+                gv[j] = f * f * kb;
+            }
+            __syncthreads();
+            // A^T[j][c] = f_j Kv[perm_j][c], j < kout, c < k
+            for (int e = tid; e < kout * k; e += nt) {
+                const int j = e / k, c = e - (e / k) * k;
+                At[j * WST + c] = sgn[j] * W[(size_t)perm[j] * ldw + c];
+            }
+            __syncthreads();
+            if (defer) {
+                const double ib = 1.0 / (1.0 - s_sc[4]);
+                for (int c = gs; c < k; c += NTC / GS) {
+                    double a = 0.0;
+                    for (int j = ls; j < k; j += GS) a += gv[j] * W[(size_t)perm[j] * ldw + c];
+                    a = dpp_group_sum<GS>(a);
+                    if (ls == 0) vv[c] = a * ib;
+                }
+                __syncthreads();
+            }
+            constexpr int S = KC / 4;
+            const int lane = tid & 63, wave = tid >> 6;
+            const int twv = (nt >> 6) < 8 ? (nt >> 6) : 8;     // waves on the products
+            const int li = lane & 15, lq = lane >> 4;
+            const int c0 = lq * S;
+            const int kt = (k + 15) / 16;
+            const int jt = defer ? kt : (ldo + 15) / 16;
+            const int ntile = defer ? 2 * kt * kt : kt * jt;
+            ISVD_GLOBAL double* Wn = gmem(rq.Wd[wp ^ 1]);
+            ISVD_GLOBAL double* Win = gmem(rq.Wdi[wp ^ 1]);
+            ISVD_GLOBAL T* U0 = gmem((T*)rq.U[cur]);
+            for (int t = wave; t < ntile && wave < twv; t += twv) {
+                const int inv = t >= kt * jt ? 1 : 0;       // 0: W A (or U's rotation), 1: A^-1 W^-1
+                const int tt = t - inv * kt * jt;
+                const int r0 = (tt / jt) * 16, j0 = (tt % jt) * 16;
+                const int ra = r0 + li, jb = j0 + li;
+                const int jlim = defer ? k : kout;
+                double av[S], bw[S];
+                if (!inv) {
+                    // A operand: row ra of W; B operand: column jb of A (row jb of A^T)
+                    if (ra < k) {
+                        const double2* src = (const double2*)(Wl + ra * WST + c0);
+#pragma unroll
+                        for (int s2 = 0; s2 < S / 2; ++s2) {
+                            const double2 x = src[s2];
+                            av[2 * s2] = x.x;
+                            av[2 * s2 + 1] = x.y;
+                        }
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < S; ++q) av[q] = 0.0;
                     }
+                    if (jb < jlim) {
+                        const double2* ar = (const double2*)(At + jb * WST + c0);
 #pragma unroll
-                    for (int q = 0; q < SIT; ++q) {
-                        const int e = tid + q * NTB;
-                        if (e < k * k) stg[(e / k) * lds_s + e % k] = v[q];
+                        for (int s2 = 0; s2 < S / 2; ++s2) {
+                            const double2 x = ar[s2];
+                            bw[2 * s2] = x.x;
+                            bw[2 * s2 + 1] = x.y;
+                        }
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < S; ++q) bw[q] = 0.0;
                     }
                 } else {
-                    for (int e = tid; e < k * k; e += nt) stg[(e / k) * lds_s + e % k] = src[(size_t)(e / k) * KC + e % k];
-                }
-            };
-            if (defer) {
-                const double bb = s_sc[4];
-                stage(Wio);
-                __syncthreads();
-                // v = b A^T: v_c = sum_j b_j A[c][j]
-                for (int c = tid; c < k; c += nt) {
-                    double a = 0.0;
-                    for (int j = 0; j < k; ++j) {
-                        const double* wj = W + (size_t)perm[j] * ldw;
-                        a += (sgn[j] * wj[k]) * (sgn[j] * wj[c]);
-                    }
-                    su[c] = a;
-                }
-                __syncthreads();
-                // new row of U0: u0 = v W^-1 / (1 - |b|^2)
-                for (int j = tid; j < ld; j += nt) {
-                    double a = 0.0;
-                    if (j < k) {
-                        for (int c = 0; c < k; ++c) a += su[c] * stg[c * lds_s + j];
-                        a /= 1.0 - bb;
-                        dcol[j] = a;
-                    }
-                    ((T*)rq.U[cur])[uvo(rq.m, j, ld)] = (T)a;
-                }
-                __syncthreads();
-                // (W A)^-1 = A^T W^-1 + b^T u0 and W' = W A on the FP64 matrix
-                // cores (v_mfma_f64_16x16x4f64: lane l holds A[l%16][l/16] and
-                // B[l/16][l%16]; D[4r + l/16][l%16] is the lane's r-th value):
-                // each wave takes 16 x 16 output tiles, operands past k are zero
-                const int lane = tid & 63, wave = tid >> 6, nwave = nt >> 6;
-                const int li = lane & 15, lq = lane >> 4;
-                const int kt = (k + 15) / 16;
-                double* Win = rq.Wdi[wp ^ 1];
-                for (int t = wave; t < kt * kt; t += nwave) {
-                    const int r0 = (t / kt) * 16, j0 = (t % kt) * 16;
-                    const int ra = r0 + li, jb = j0 + li;
-                    const bool rav = ra < k, jbv = jb < k;
-                    const double fa = rav ? sgn[ra] : 0.0;
-                    const double* kva = W + (size_t)(rav ? perm[ra] : 0) * ldw;
-                    core_v4d acc = {0.0, 0.0, 0.0, 0.0};
+                    // A operand: row ra of A^-1; B operand: column jb of W^-1 (a row of its transpose)
+                    if (ra < k) {
+                        const double br = bv[ra];
+                        const double2* ar = (const double2*)(At + ra * WST + c0);
+                        const double2* vp = (const double2*)(vv + c0);
 #pragma unroll
-                    for (int s4 = 0; s4 < KC / 4; ++s4) {   // steps past k read zeros
-                        const int c = 4 * s4 + lq;
-                        const double a = (rav && c < k) ? fa * kva[c] : 0.0;          // A^T[ra][c]
-                        const double b = (jbv && c < k) ? stg[c * lds_s + jb] : 0.0;  // W^-1[c][jb]
-                        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
-                    }
-                    for (int r = 0; r < 4; ++r) {
-                        const int row = r0 + 4 * r + lq;
-                        if (row < k && jbv) {
-                            const double br = sgn[row] * W[(size_t)perm[row] * ldw + k];
-                            Win[(size_t)row * KC + jb] = acc[r] + br * dcol[jb];
+                        for (int s2 = 0; s2 < S / 2; ++s2) {
+                            const double2 x = ar[s2], y = vp[s2];
+                            av[2 * s2] = x.x + br * y.x;
+                            av[2 * s2 + 1] = x.y + br * y.y;
                         }
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < S; ++q) av[q] = 0.0;
+                    }
+                    if (jb < k) {
+                        const double2* wr = (const double2*)(Wil + jb * WST + c0);
+#pragma unroll
+                        for (int s2 = 0; s2 < S / 2; ++s2) {
+                            const double2 x = wr[s2];
+                            bw[2 * s2] = x.x;
+                            bw[2 * s2 + 1] = x.y;
+                        }
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < S; ++q) bw[q] = 0.0;
                     }
                 }
-                __syncthreads();
-                stage(Wo);
-                __syncthreads();
-                double* Wn = rq.Wd[wp ^ 1];
-                for (int t = wave; t < kt * kt; t += nwave) {
-                    const int r0 = (t / kt) * 16, j0 = (t % kt) * 16;
-                    const int ra = r0 + li, jb = j0 + li;
-                    const bool rav = ra < k, jbv = jb < k;
-                    const double fb = jbv ? sgn[jb] : 0.0;
-                    const double* kvb = W + (size_t)(jbv ? perm[jb] : 0) * ldw;
-                    core_v4d acc = {0.0, 0.0, 0.0, 0.0};
+                // contraction indices past k are zero
 #pragma unroll
-                    for (int s4 = 0; s4 < KC / 4; ++s4) {   // steps past k read zeros
-                        const int c = 4 * s4 + lq;
-                        const double a = (rav && c < k) ? stg[ra * lds_s + c] : 0.0;  // W[ra][c]
-                        const double b = (jbv && c < k) ? fb * kvb[c] : 0.0;          // A[c][jb]
-                        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+                for (int q = 0; q < S; ++q) {
+                    if (c0 + q >= k) {
+                        av[q] = 0.0;
+                        bw[q] = 0.0;
                     }
+                }
+                core_v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int q = 0; q < S; ++q) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q], bw[q], acc, 0, 0, 0);
+                if (!defer) {
                     for (int r = 0; r < 4; ++r) {
                         const int row = r0 + 4 * r + lq;
-                        if (row < k && jbv) Wn[(size_t)row * KC + jb] = acc[r];
+                        if (row < k && jb < ldo) QU[row * ldo + jb] = (T)acc[r];
+                    }
+                } else {
+                    ISVD_GLOBAL double* out = inv ? Win : Wn;
+                    for (int r = 0; r < 4; ++r) {
+                        const int row = r0 + 4 * r + lq;
+                        if (row < k && jb < k) out[(size_t)row * KC + jb] = acc[r];
+                    }
+                    if (inv && r0 == 0) {
+                        // u0[jb] = v W^-1[:, jb]: this lane's contraction indices, then the four quarters
+                        double up = 0.0;
+#pragma unroll
+                        for (int q = 0; q < S; ++q) up += (c0 + q < k ? vv[c0 + q] : 0.0) * bw[q];
+                        up += __shfl_xor(up, 16);
+                        up += __shfl_xor(up, 32);
+                        if (lq == 0 && jb < ld) U0[uvo(rq.m, jb, ld)] = (T)(jb < k ? up : 0.0);
                     }
                 }
-            } else {
-                // explicit: U's rotation takes W A, and W, W^-1 return to I
-                stage(Wo);
+            }
+            if (!defer) {
                 __syncthreads();
-                for (int e = tid; e < k * ldo; e += nt) {
-                    const int j = e / k, r = e - (e / k) * k;   // adjacent lanes: adjacent rows
-                    double a = 0.0;
-                    if (j < kout) {
-                        const double* wj = W + (size_t)perm[j] * ldw;
-                        for (int c = 0; c < k; ++c) a += stg[r * lds_s + c] * wj[c];
-                        a *= sgn[j];
-                    }
-                    QU[r * ldo + j] = (T)a;
-                }
                 for (int e = tid; e < KC * KC; e += nt) {
                     const double v = (e / KC == e - (e / KC) * KC) ? 1.0 : 0.0;
-                    rq.Wd[wp][e] = v;
-                    rq.Wdi[wp][e] = v;
+                    gmem(rq.Wd[wp])[e] = v;
+                    gmem(rq.Wdi[wp])[e] = v;
                 }
             }
         }
@@ -595,7 +732,7 @@ __global__ void __launch_bounds__(CoreShape<KC>::J::NT) k_core(const Req* __rest
     if (tid == 0) {
         double dN = 0.0;
         if (kind == kEntry) {
-            T* A = (T*)rq.A;
+            ISVD_GLOBAL T* A = gmem((T*)rq.A);
             const double aold = (double)A[rq.i * rq.lda + rq.j];
             A[rq.i * rq.lda + rq.j] = (T)(aold + rq.delta);
             dN = 2.0 * rq.delta * aold + rq.delta * rq.delta;
