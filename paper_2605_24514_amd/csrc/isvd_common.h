@@ -18,6 +18,10 @@ constexpr int kMfmaRotRows = 512;
 struct RotVariant { int rows, rt, pf; };
 constexpr int kRotVariants = 5;
 constexpr RotVariant kRotVariant[kRotVariants] = {{256, 1, 1}, {512, 1, 1}, {1024, 1, 1}, {1024, 2, 0}, {2048, 2, 0}};
+// V rotations of a tick (FP32, buckets up to 64) take 128 rows per block
+// (two steps per wave): V has at most a few thousand rows, so the U shapes
+// would leave a handful of blocks per stream, each walking its rows in turn
+constexpr int kRotRowsV = 128;
 constexpr int kMaxRank = 128;      // largest rank k of a stream
 constexpr int kMaxCore = kMaxRank + 1;   // largest core order (an append's (k + 1) x (k + 1))
 constexpr int kMaxBlock = 128;     // largest refresh block size b

@@ -206,6 +206,7 @@ struct Group {
     bool bf16 = false;         // FP32 storage, BF16 rotation products
     int kc;
     int rows = 0;              // rotation rows per block
+    int rows_v() const { return (!fp64 && !bf16 && kc <= 64) ? kRotRowsV : rows; }   // ... of V-only launches
     int var = 1;               // FP32 rotation block shape (kRotVariant index)
     std::vector<Req> all;      // core + rotation list
     std::vector<Req> proj;     // row / column appends
@@ -456,6 +457,11 @@ isvd_status launch_group_phase(const Group& g, const char* dev, int phase, hipSt
             static_assert(kRotVariants == 5, "variant dispatch");
             if (g.bf16) {
                 k_rotate_mfma_t<KC, 512, 1, true, true><<<nb, kThreads, 0, st>>>(all, pr, na, part);
+                HIP_TRY(hipGetLastError());
+                return ISVD_OK;
+            }
+            if (part == 2) {
+                k_rotate_mfma_t<KC, kRotRowsV, 1, true><<<nb, kThreads, 0, st>>>(all, pr, na, part);
                 HIP_TRY(hipGetLastError());
                 return ISVD_OK;
             }
@@ -751,7 +757,7 @@ size_t layout_groups(std::vector<Group>& groups) {
             const int tu = g.all[q].rot_tiles_u, tv = (int)cdiv(g.all[q].n, g.rows);
             g.pre_rot[q + 1] = g.pre_rot[q] + tu + tv;
             g.pre_rotU[q + 1] = g.pre_rotU[q] + tu;
-            g.pre_rotV[q + 1] = g.pre_rotV[q] + tv;
+            g.pre_rotV[q + 1] = g.pre_rotV[q] + (int)cdiv(g.all[q].n, g.rows_v());
         }
         g.off_all = take(sizeof(Req) * na);
         // the projection list equals the whole list when every request is an

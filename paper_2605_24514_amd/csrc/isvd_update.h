@@ -220,7 +220,7 @@ __host__ __device__ constexpr size_t core_lds_base() {
     constexpr bool SEC = core_secular<KC, WITH_J>();
     constexpr bool JLDS = (WITH_J && !core_j_global<KC, WITH_J>()) || SEC;
     return (size_t)(JLDS ? 2 : 1) * CoreShape<KC>::NMAX * CoreShape<KC>::J::LDW +
-           (size_t)(WITH_J ? 6 : 8) * CoreShape<KC>::NMAX +
+           (size_t)8 * CoreShape<KC>::NMAX +
            (size_t)(SEC ? secular_scratch_doubles(CoreShape<KC>::NMAX) : 0);
 }
 template <int KC, bool WITH_J>
@@ -263,7 +263,7 @@ __global__ void __launch_bounds__((core_nt<KC, sizeof(T) == 8>())) k_core(const 
     double* sgn = sig + N;
     double* tmp = sgn + N;
     int* perm = (int*)(tmp + N);
-    double* su = tmp + 2 * N;                      // s_u (rank-1, no J)
+    double* su = tmp + 2 * N;                      // s_u (rank-1, no J); then sgn_j / sigma_j
     double* dcol = su + N;                         // s_u . W[:, c] (rank-1, no J)
     double* xsec = dcol + N;                       // secular scratch
 
@@ -565,12 +565,18 @@ __global__ void __launch_bounds__((core_nt<KC, sizeof(T) == 8>())) k_core(const 
 #pragma unroll
             for (int q = 0; q < PF; ++q) {
                 const int e = tid + q * NTC;
+                // entries outside the leading k x k block are stored as zeros, so
+                // the products need no masks
                 if (e < KC * KC / 2) {
-                    *(gvec_d2*)(Wl + (2 * e / KC) * WST + 2 * e % KC) = pf[q];
+                    const int r = 2 * e / KC, c = 2 * e % KC;
+                    gvec_d2 v = pf[q];
+                    v.x = (r < k && c < k) ? v.x : 0.0;
+                    v.y = (r < k && c + 1 < k) ? v.y : 0.0;
+                    *(gvec_d2*)(Wl + r * WST + c) = v;
                 } else if (e < KC * KC) {
                     const int e2 = 2 * (e - KC * KC / 2), r = e2 / KC, c = e2 % KC;
-                    Wil[c * WST + r] = pf[q].x;
-                    Wil[(c + 1) * WST + r] = pf[q].y;
+                    Wil[c * WST + r] = (r < k && c < k) ? pf[q].x : 0.0;
+                    Wil[(c + 1) * WST + r] = (r < k && c + 1 < k) ? pf[q].y : 0.0;
                 }
             }
             for (int j = tid; j < kout; j += nt) {
@@ -581,22 +587,29 @@ __global__ void __launch_bounds__((core_nt<KC, sizeof(T) == 8>())) k_core(const 
                 gv[j] = f * f * kb;
             }
             __syncthreads();
-            // A^T[j][c] = f_j Kv[perm_j][c], j < kout, c < k
-            for (int e = tid; e < kout * k; e += nt) {
-                const int j = e / k, c = e - (e / k) * k;
-                At[j * WST + c] = sgn[j] * W[(size_t)perm[j] * ldw + c];
+            // A^T[j][c] = f_j Kv[perm_j][c] for j < kout, c < k; zero elsewhere in KC x KC
+            for (int e = tid; e < KC * KC; e += nt) {
+                const int j = e / KC, c = e % KC;
+                At[j * WST + c] = (j < kout && c < k) ? sgn[j] * W[(size_t)perm[j] * ldw + c] : 0.0;
             }
-            __syncthreads();
             if (defer) {
+                // v (zero past k) and b (zero past k)
                 const double ib = 1.0 / (1.0 - s_sc[4]);
-                for (int c = gs; c < k; c += NTC / GS) {
+                for (int c = gs; c < KC; c += NTC / GS) {
                     double a = 0.0;
-                    for (int j = ls; j < k; j += GS) a += gv[j] * W[(size_t)perm[j] * ldw + c];
+                    if (c < k)
+                        for (int j = ls; j < k; j += GS) a += gv[j] * W[(size_t)perm[j] * ldw + c];
                     a = dpp_group_sum<GS>(a);
                     if (ls == 0) vv[c] = a * ib;
                 }
-                __syncthreads();
+                for (int j = k + tid; j < KC; j += nt) bv[j] = 0.0;
+            } else {
+                for (int c = tid; c < KC; c += nt) {
+                    vv[c] = 0.0;
+                    bv[c] = 0.0;
+                }
             }
+            __syncthreads();
             constexpr int S = KC / 4;
             const int lane = tid & 63, wave = tid >> 6;
             const int twv = (nt >> 6) < 8 ? (nt >> 6) : 8;     // waves on the products
@@ -613,70 +626,27 @@ __global__ void __launch_bounds__((core_nt<KC, sizeof(T) == 8>())) k_core(const 
                 const int tt = t - inv * kt * jt;
                 const int r0 = (tt / jt) * 16, j0 = (tt % jt) * 16;
                 const int ra = r0 + li, jb = j0 + li;
-                const int jlim = defer ? k : kout;
                 double av[S], bw[S];
+                // operand rows past k (or past k_out) are zero in LDS
+                const double2* pa;
+                const double2* pb;
+                double br = 0.0;
                 if (!inv) {
-                    // A operand: row ra of W; B operand: column jb of A (row jb of A^T)
-                    if (ra < k) {
-                        const double2* src = (const double2*)(Wl + ra * WST + c0);
-#pragma unroll
-                        for (int s2 = 0; s2 < S / 2; ++s2) {
-                            const double2 x = src[s2];
-                            av[2 * s2] = x.x;
-                            av[2 * s2 + 1] = x.y;
-                        }
-                    } else {
-#pragma unroll
-                        for (int q = 0; q < S; ++q) av[q] = 0.0;
-                    }
-                    if (jb < jlim) {
-                        const double2* ar = (const double2*)(At + jb * WST + c0);
-#pragma unroll
-                        for (int s2 = 0; s2 < S / 2; ++s2) {
-                            const double2 x = ar[s2];
-                            bw[2 * s2] = x.x;
-                            bw[2 * s2 + 1] = x.y;
-                        }
-                    } else {
-#pragma unroll
-                        for (int q = 0; q < S; ++q) bw[q] = 0.0;
-                    }
+                    pa = (const double2*)(Wl + ra * WST + c0);    // row ra of W
+                    pb = (const double2*)(At + jb * WST + c0);    // column jb of A (row jb of A^T)
                 } else {
-                    // A operand: row ra of A^-1; B operand: column jb of W^-1 (a row of its transpose)
-                    if (ra < k) {
-                        const double br = bv[ra];
-                        const double2* ar = (const double2*)(At + ra * WST + c0);
-                        const double2* vp = (const double2*)(vv + c0);
-#pragma unroll
-                        for (int s2 = 0; s2 < S / 2; ++s2) {
-                            const double2 x = ar[s2], y = vp[s2];
-                            av[2 * s2] = x.x + br * y.x;
-                            av[2 * s2 + 1] = x.y + br * y.y;
-                        }
-                    } else {
-#pragma unroll
-                        for (int q = 0; q < S; ++q) av[q] = 0.0;
-                    }
-                    if (jb < k) {
-                        const double2* wr = (const double2*)(Wil + jb * WST + c0);
-#pragma unroll
-                        for (int s2 = 0; s2 < S / 2; ++s2) {
-                            const double2 x = wr[s2];
-                            bw[2 * s2] = x.x;
-                            bw[2 * s2 + 1] = x.y;
-                        }
-                    } else {
-#pragma unroll
-                        for (int q = 0; q < S; ++q) bw[q] = 0.0;
-                    }
+                    pa = (const double2*)(At + ra * WST + c0);    // row ra of A^-1 = A^T + b^T v ...
+                    pb = (const double2*)(Wil + jb * WST + c0);   // column jb of W^-1 (a row of its transpose)
+                    br = bv[ra];
                 }
-                // contraction indices past k are zero
+                const double2* vp = (const double2*)(vv + c0);    // ... + b_ra v
 #pragma unroll
-                for (int q = 0; q < S; ++q) {
-                    if (c0 + q >= k) {
-                        av[q] = 0.0;
-                        bw[q] = 0.0;
-                    }
+                for (int s2 = 0; s2 < S / 2; ++s2) {
+                    const double2 x = pa[s2], y = pb[s2], z = vp[s2];
+                    av[2 * s2] = x.x + br * z.x;
+                    av[2 * s2 + 1] = x.y + br * z.y;
+                    bw[2 * s2] = y.x;
+                    bw[2 * s2 + 1] = y.y;
                 }
                 core_v4d acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -696,7 +666,7 @@ __global__ void __launch_bounds__((core_nt<KC, sizeof(T) == 8>())) k_core(const 
                         // u0[jb] = v W^-1[:, jb]: this lane's contraction indices, then the four quarters
                         double up = 0.0;
 #pragma unroll
-                        for (int q = 0; q < S; ++q) up += (c0 + q < k ? vv[c0 + q] : 0.0) * bw[q];
+                        for (int q = 0; q < S; ++q) up += vv[c0 + q] * bw[q];
                         up += __shfl_xor(up, 16);
                         up += __shfl_xor(up, 32);
                         if (lq == 0 && jb < ld) U0[uvo(rq.m, jb, ld)] = (T)(jb < k ? up : 0.0);
