@@ -1,0 +1,177 @@
+// Merged launches of a tick whose requests all belong to the FP32 buckets
+// that take the secular core (ranks up to 64): one launch per phase covers
+// every bucket, so the tick is a chain of kernels on one stream
+//   upload -> projection pass 1 -> pass 2 -> cores -> V rotations
+//          -> U plan -> U rotations
+// instead of one chain per bucket on parallel lanes.  The merged launch of a
+// phase gives each bucket a range of its blocks; the work of a block is the
+// same code (and the same bits) as in the bucket's own launch.  The U
+// rotations are planned on the device after the cores: only the requests
+// whose append was not applied to W (deferred U) rotate U, and the plan
+// lists exactly their row blocks, so the U launch has a fixed grid that
+// loops over the planned blocks.
+#pragma once
+#include "isvd_update.h"
+
+namespace isvd {
+
+constexpr int kChainMax = 4;          // buckets 8, 16, 32, 64
+constexpr int kChainRowsU = 512;      // U rows per block of the planned U rotations
+constexpr int kChainUGrid = 2048;     // blocks of the U-rotation launch (loop past that)
+constexpr int kChainPlanThreads = 1024;
+
+// The request lists of one merged launch, one entry per bucket, in launch
+// order; bucket q owns blocks [begin[q], begin[q + 1]).  prefix[q]: the
+// bucket's block prefix over its requests (projections, rotations), unused
+// by the cores (one block per request).
+struct MultiGroup {
+    int n = 0;
+    int kc[kChainMax];
+    const Req* reqs[kChainMax];
+    const int* prefix[kChainMax];
+    int nreq[kChainMax];
+    int begin[kChainMax + 1];
+};
+
+// ints of the device plan of a tick's U rotations for up to `reqs` requests:
+// [0] planned blocks, [1, reqs + 2) block prefix, then one code per request
+__host__ __device__ constexpr size_t chain_plan_ints(int reqs) { return 2 + 2 * (size_t)reqs + 2; }
+
+__device__ inline int chain_pick(const MultiGroup& mg, int* bid) {
+    int q = 0;
+    while (q + 1 < mg.n && (int)blockIdx.x >= mg.begin[q + 1]) ++q;
+    *bid = (int)blockIdx.x - mg.begin[q];
+    return q;
+}
+
+__host__ __device__ constexpr int chain_proj_lds() {
+    return proj_lds_doubles<8>() > proj_lds_doubles<16>()
+               ? (proj_lds_doubles<8>() > proj_lds_doubles<32>() ? proj_lds_doubles<8>() : proj_lds_doubles<32>())
+               : (proj_lds_doubles<16>() > proj_lds_doubles<32>() ? proj_lds_doubles<16>() : proj_lds_doubles<32>());
+}
+
+template <int PASS>
+__global__ void __launch_bounds__(kThreads) k_proj_chain(MultiGroup mg) {
+    constexpr int L = chain_proj_lds() > proj_lds_doubles<64>() ? chain_proj_lds() : proj_lds_doubles<64>();
+    __shared__ double lds[L];
+    int bid;
+    const int q = chain_pick(mg, &bid);
+    switch (mg.kc[q]) {
+        case 8: proj_block<float, 8, PASS>(mg.reqs[q], mg.prefix[q], mg.nreq[q], bid, lds); break;
+        case 16: proj_block<float, 16, PASS>(mg.reqs[q], mg.prefix[q], mg.nreq[q], bid, lds); break;
+        case 32: proj_block<float, 32, PASS>(mg.reqs[q], mg.prefix[q], mg.nreq[q], bid, lds); break;
+        default: proj_block<float, 64, PASS>(mg.reqs[q], mg.prefix[q], mg.nreq[q], bid, lds); break;
+    }
+}
+
+// dynamic LDS (doubles) of the merged core launch: the widest bucket's
+__host__ __device__ constexpr size_t chain_core_lds() { return core_lds_doubles<64, false>(); }
+
+__global__ void __launch_bounds__(kSecCoreThreads) k_core_chain(MultiGroup mg) {
+    int bid;
+    const int q = chain_pick(mg, &bid);
+    switch (mg.kc[q]) {
+        case 8: core_block<float, 8>(mg.reqs[q] + bid); break;
+        case 16: core_block<float, 16>(mg.reqs[q] + bid); break;
+        case 32: core_block<float, 32>(mg.reqs[q] + bid); break;
+        default: core_block<float, 64>(mg.reqs[q] + bid); break;
+    }
+}
+
+// V tiles (part 2) of every bucket, kRotRowsV rows per block
+__global__ void __launch_bounds__(kThreads) k_rotv_chain(MultiGroup mg) {
+    int bid;
+    const int q = chain_pick(mg, &bid);
+    const int* prefix = mg.prefix[q];
+    if (bid >= prefix[mg.nreq[q]]) return;
+    const int ri = find_req(prefix, mg.nreq[q], bid);
+    const Req* rq = mg.reqs[q] + ri;
+    const int tile = bid - prefix[ri];
+    switch (mg.kc[q]) {
+        case 8: rotate_mfma_t_block<8, kRotRowsV, 1, true>(rq, tile, 2); break;
+        case 16: rotate_mfma_t_block<16, kRotRowsV, 1, true>(rq, tile, 2); break;
+        case 32: rotate_mfma_t_block<32, kRotRowsV, 1, true>(rq, tile, 2); break;
+        default: rotate_mfma_t_block<64, kRotRowsV, 1, true>(rq, tile, 2); break;
+    }
+}
+
+// Plan of the U rotations (one block of kChainPlanThreads): request g (over
+// the buckets in order) rotates U in ceil(m / kChainRowsU) blocks unless its
+// core skipped it or applied its append to W.  Writes the planned blocks,
+// their prefix over the requests and the request codes (bucket << 24 | index).
+__global__ void __launch_bounds__(kChainPlanThreads) k_uplan_chain(MultiGroup mg, int* __restrict__ plan) {
+    __shared__ int ssum[kChainPlanThreads];
+    const int tid = threadIdx.x;
+    int G = 0;
+    for (int q = 0; q < mg.n; ++q) G += mg.nreq[q];
+    int* prefix = plan + 1;
+    int* code = plan + 2 + G;
+    const int per = (G + kChainPlanThreads - 1) / kChainPlanThreads;
+    const int g0 = tid * per, g1 = g0 + per < G ? g0 + per : G;
+    auto locate = [&](int g, int* qq) {
+        int q = 0, base = 0;
+        while (g >= base + mg.nreq[q]) {
+            base += mg.nreq[q];
+            ++q;
+        }
+        *qq = q;
+        return g - base;
+    };
+    auto blocks_of = [&](int q, int ri) {
+        const Req& rq = mg.reqs[q][ri];
+        const ISVD_GLOBAL ReqScratch* rs = gmem(rq.rs);
+        return (rs->skip || rs->deferred) ? 0 : (int)((rq.m + kChainRowsU - 1) / kChainRowsU);
+    };
+    int local = 0;
+    for (int g = g0; g < g1; ++g) {
+        int q;
+        const int ri = locate(g, &q);
+        local += blocks_of(q, ri);
+    }
+    ssum[tid] = local;
+    __syncthreads();
+    for (int off = 1; off < kChainPlanThreads; off <<= 1) {
+        const int v = tid >= off ? ssum[tid - off] : 0;
+        __syncthreads();
+        ssum[tid] += v;
+        __syncthreads();
+    }
+    int run = tid > 0 ? ssum[tid - 1] : 0;
+    for (int g = g0; g < g1; ++g) {
+        int q;
+        const int ri = locate(g, &q);
+        prefix[g] = run;
+        code[g] = (q << 24) | ri;
+        run += blocks_of(q, ri);
+    }
+    if (tid == kChainPlanThreads - 1) {
+        plan[0] = ssum[tid];
+        prefix[G] = ssum[tid];
+    }
+}
+
+// The planned U-rotation blocks: a fixed grid, each block taking planned
+// blocks blockIdx.x, blockIdx.x + gridDim.x, ...
+__global__ void __launch_bounds__(kThreads) k_rotu_chain(MultiGroup mg, const int* __restrict__ plan) {
+    int G = 0;
+    for (int q = 0; q < mg.n; ++q) G += mg.nreq[q];
+    const int total = plan[0];
+    const int* prefix = plan + 1;
+    const int* code = plan + 2 + G;
+    for (int t = blockIdx.x; t < total; t += gridDim.x) {
+        const int g = find_req(prefix, G, t);
+        const int c = code[g];
+        const int q = c >> 24, ri = c & 0xFFFFFF;
+        const Req* rq = mg.reqs[q] + ri;
+        const int tile = t - prefix[g];
+        switch (mg.kc[q]) {
+            case 8: rotate_mfma_t_block<8, kChainRowsU, 1, true>(rq, tile, 1); break;
+            case 16: rotate_mfma_t_block<16, kChainRowsU, 1, true>(rq, tile, 1); break;
+            case 32: rotate_mfma_t_block<32, kChainRowsU, 1, true>(rq, tile, 1); break;
+            default: rotate_mfma_t_block<64, kChainRowsU, 1, true>(rq, tile, 1); break;
+        }
+        __syncthreads();   // the block's LDS (projection data) is reused by its next planned block
+    }
+}
+
+}  // namespace isvd

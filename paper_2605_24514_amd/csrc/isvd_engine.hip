@@ -29,6 +29,7 @@
 #include "../../include/isvd.h"
 #include "isvd_common.h"
 #include "isvd_update.h"
+#include "isvd_chain.h"
 #include "isvd_refresh.h"
 #include "isvd_gcf.h"
 #include "isvd_track.h"
@@ -326,6 +327,7 @@ struct isvd_engine {
     // so that a tick reads them back with one copy into the pinned mirror
     DevHeader* hdr_dev = nullptr;
     DevHeader* hdr_mirror = nullptr;
+    int* chain_plan = nullptr;       // device plan of a merged tick's U rotations
     int hdr_hi = 0;                  // slots [0, hdr_hi) have been handed out
     std::vector<int> hdr_free;
     // block shape (kRotVariant index) of the FP32 matrix-core rotation per
@@ -521,6 +523,7 @@ isvd_status set_lds_limits() {
     ST_TRY((set_lds_limits_for<double, 32>()));
     ST_TRY((set_lds_limits_for<double, 64>()));
     ST_TRY((set_lds_limits_for<double, 128>()));
+    ST_TRY(allow_lds(k_core_chain, sizeof(double) * chain_core_lds()));
     ST_TRY(allow_lds(k_svd_small_noj<float>, sizeof(double) * svd_noj_lds_doubles()));
     ST_TRY(allow_lds(k_svd_small_noj<double>, sizeof(double) * svd_noj_lds_doubles()));
     ST_TRY(allow_lds(k_sym_norm2, sym_norm2_lds(kMaxBlock)));
@@ -819,6 +822,98 @@ isvd_status own_lane_sequence(isvd_engine* e, const std::vector<Group>& groups, 
     return ISVD_OK;
 }
 
+// ------------------------------------------------ merged (chain) ticks
+// A tick takes the merged launches (isvd_chain.h) when U is deferred and
+// every group is an FP32 bucket of ranks up to 64: the tick is then one
+// chain of kernels on the caller's stream, with no lanes to fork and join.
+bool chain_ok(const isvd_engine* e, const std::vector<Group>& groups) {
+    if (!e->defer_u || groups.empty() || groups.size() > (size_t)kChainMax) return false;
+    for (const Group& g : groups)
+        if (g.fp64 || g.bf16 || g.kc > 64) return false;
+    return true;
+}
+
+isvd_status ensure_chain_plan(isvd_engine* e) {
+    if (!e->chain_plan)
+        HIP_TRY(hipMalloc((void**)&e->chain_plan, sizeof(int) * chain_plan_ints(kMaxLiveStreams)));
+    return ISVD_OK;
+}
+
+// The request lists of one phase (0, 1: projection passes, 2: cores, 3: U,
+// 4: V) of the groups laid out in `dev`, in the groups' order (widest bucket
+// first); *blocks: the blocks of the merged launch.
+MultiGroup chain_args(const std::vector<Group>& groups, const char* dev, int phase, int* blocks) {
+    MultiGroup mg{};
+    mg.begin[0] = 0;
+    for (const Group& g : groups) {
+        const int np = (int)g.proj.size(), na = (int)g.all.size();
+        const int nreq = phase < 2 ? np : na;
+        const int nb = phase < 2 ? g.pre_proj[np] : phase == 2 ? na : phase == 4 ? g.pre_rotV[na] : 0;
+        if (nreq == 0 || (phase != 3 && nb == 0)) continue;
+        const int q = mg.n++;
+        mg.kc[q] = g.kc;
+        mg.reqs[q] = reinterpret_cast<const Req*>(dev + (phase < 2 ? g.off_proj : g.off_all));
+        mg.prefix[q] = reinterpret_cast<const int*>(dev + (phase < 2 ? g.off_pp : g.off_prv));
+        mg.nreq[q] = nreq;
+        mg.begin[q + 1] = mg.begin[q] + nb;
+    }
+    *blocks = mg.begin[mg.n];
+    return mg;
+}
+
+// One merged launch, timed per launch when profiling (kc 0: all buckets).
+isvd_status chain_launch(isvd_engine* e, const std::vector<Group>& groups, const char* dev, int phase,
+                         hipStream_t st) {
+    int blocks = 0;
+    const MultiGroup mg = chain_args(groups, dev, phase, &blocks);
+    if (mg.n == 0) return ISVD_OK;
+    LaunchRec rec{};
+    if (e->profiling) {
+        ST_TRY(next_event(e, &rec.b));
+        ST_TRY(next_event(e, &rec.e));
+        HIP_TRY(hipEventRecord(rec.b, st));
+    }
+    switch (phase) {
+        case 0: k_proj_chain<1><<<blocks, kThreads, 0, st>>>(mg); break;
+        case 1: k_proj_chain<2><<<blocks, kThreads, 0, st>>>(mg); break;
+        case 2: k_core_chain<<<blocks, kSecCoreThreads, sizeof(double) * chain_core_lds(), st>>>(mg); break;
+        case 4: k_rotv_chain<<<blocks, kThreads, 0, st>>>(mg); break;
+        default:
+            k_uplan_chain<<<1, kChainPlanThreads, 0, st>>>(mg, e->chain_plan);
+            HIP_TRY(hipGetLastError());
+            k_rotu_chain<<<kChainUGrid, kThreads, 0, st>>>(mg, e->chain_plan);
+            break;
+    }
+    HIP_TRY(hipGetLastError());
+    if (e->profiling) {
+        HIP_TRY(hipEventRecord(rec.e, st));
+        rec.phase = phase;
+        rec.kc = 0;
+        rec.fp64 = 0;
+        int nreq = 0;
+        for (int q = 0; q < mg.n; ++q) nreq += mg.nreq[q];
+        rec.nreq = nreq;
+        rec.blocks = phase == 3 ? kChainUGrid : blocks;
+        e->prof.push_back(rec);
+    }
+    return ISVD_OK;
+}
+
+// A merged tick: (upload,) projections, cores, V rotations, the U plan and
+// the planned U rotations, all on `st`.
+isvd_status chain_sequence(isvd_engine* e, const std::vector<Group>& groups, const char* host, char* dev,
+                           size_t bytes, hipStream_t st, bool upload) {
+    if (upload) {
+        const size_t n16 = align_up(bytes, 16) / 16;
+        if (n16 > 0)
+            k_upload<<<(int)std::min<size_t>(cdiv(n16, 256), 64), 256, 0, st>>>(
+                reinterpret_cast<const uint4*>(host), reinterpret_cast<uint4*>(dev), n16);
+        HIP_TRY(hipGetLastError());
+    }
+    for (int phase : {0, 1, 2, 4, 3}) ST_TRY(chain_launch(e, groups, dev, phase, st));
+    return ISVD_OK;
+}
+
 void free_tick_graph(TickGraph* tg) {
     for (int b = 0; b < kTickGraphBufs; ++b) {
         if (tg->done[b]) (void)hipEventSynchronize(tg->done[b]);
@@ -844,6 +939,8 @@ isvd_status run_groups_graph(isvd_engine* e, std::vector<Group>& groups, hipStre
                                (int64_t)g.all.size(), (int64_t)g.proj.size(), (int64_t)g.rotU_cap});
         key.insert(key.end(), g.ids.begin(), g.ids.end());
     }
+    const bool chain = chain_ok(e, groups);
+    if (chain) ST_TRY(ensure_chain_plan(e));
     TickGraph* tg = nullptr;
     for (TickGraph* c : e->tgraphs)
         if (c->key == key) tg = c;
@@ -873,7 +970,8 @@ isvd_status run_groups_graph(isvd_engine* e, std::vector<Group>& groups, hipStre
                 rc = fail(ISVD_E_DEVICE, "tick capture failed to begin");
                 break;
             }
-            rc = own_lane_sequence(e, groups, tg->host[b], tg->dev[b], off, e->capture_st);
+            rc = chain ? chain_sequence(e, groups, tg->host[b], tg->dev[b], off, e->capture_st, true)
+                       : own_lane_sequence(e, groups, tg->host[b], tg->dev[b], off, e->capture_st);
             const hipError_t ce = hipStreamEndCapture(e->capture_st, &tg->graph[b]);
             for (Group& g : groups) g.grid_u = 0;
             if (rc == ISVD_OK && ce != hipSuccess) rc = fail(ISVD_E_DEVICE, "tick capture failed");
@@ -909,6 +1007,19 @@ isvd_status run_groups(isvd_engine* e, std::vector<Group>& groups, hipStream_t s
     Slot* slot = nullptr;
     ST_TRY(acquire_slot(e, off, &slot));
     fill_groups(groups, slot->host);
+    if (chain_ok(e, groups)) {
+        ST_TRY(ensure_chain_plan(e));
+        if (e->ticks >= 2 && e->lane_ticks < 2) HIP_TRY(hipStreamWaitEvent(st, e->ev_tick_end[e->ticks & 1], 0));
+        ST_TRY(upload_slot(slot, off, st));
+        ST_TRY(chain_sequence(e, groups, slot->host, slot->dev, off, st, false));
+        HIP_TRY(hipEventRecord(slot->ev, st));
+        slot->used = true;
+        HIP_TRY(hipEventRecord(e->ev_tick_end[e->ticks & 1], st));
+        e->ticks += 1;
+        e->lane_ticks += 1;
+        if (!pipelined) ST_TRY(join(e, st));   // rotation-lane work of earlier ticks
+        return ISVD_OK;
+    }
     // With deferred U the U rotations are mostly skipped and run on the
     // group's own update lane after its V rotation; the whole tick then ends
     // on the caller's stream (no rotation lanes, two cross-stream waits).
@@ -2337,6 +2448,7 @@ isvd_status isvd_engine_destroy(isvd_engine* e) {
     free_retired(e->ws);
     if (e->mws) (void)hipFree(e->mws);
     if (e->hdr_dev) (void)hipFree(e->hdr_dev);
+    if (e->chain_plan) (void)hipFree(e->chain_plan);
     if (e->hdr_mirror) (void)hipHostFree(e->hdr_mirror);
     for (auto& l : e->rlanes) {
         if (l.ws.p) (void)hipFree(l.ws.p);

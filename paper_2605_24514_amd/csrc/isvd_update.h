@@ -53,21 +53,27 @@ __device__ inline const void* basis_cur(const Req& rq, bool useU, int cur) {
 // KC + 2: [0, k) the projection, [KC] the squared norm, [KC + 1] the
 // non-finite count); the next launch adds the partials in block order
 // (deterministic, independent of the batch), so no block waits for another.
+// LDS (doubles) of one projection block of bucket KC
+template <int KC>
+__host__ __device__ constexpr int proj_lds_doubles() { return (kThreads / (KC / 4)) * (KC + 2) + KC; }
+
+// One block's part of a projection launch: block `bid` of the request list
+// (reqs, prefix, nreq); lds: proj_lds_doubles<KC>() doubles.
 template <typename T, int KC, int PASS>
-__global__ void __launch_bounds__(kThreads) k_proj(const Req* __restrict__ reqs, const int* __restrict__ prefix,
-                                                   int nreq) {
+__device__ __attribute__((always_inline)) inline void proj_block(const Req* __restrict__ reqs, const int* __restrict__ prefix, int nreq, int bid,
+                                  double* lds) {
     constexpr int TPR = KC / 4;                  // lanes per row (4 columns each)
     constexpr int RPB = kThreads / TPR;          // rows per block step
     constexpr int SP = KC + 2;
     constexpr int UNR = 4;                       // row steps in flight per lane
-    __shared__ double sacc[RPB][SP];
-    __shared__ double sp1[KC];
+    double (*sacc)[SP] = reinterpret_cast<double (*)[SP]>(lds);
+    double* sp1 = lds + RPB * SP;
     // a grid sized for more tiles than this launch has (a captured tick,
     // sized for the streams' capacity) leaves the extra blocks idle
-    if ((int)blockIdx.x >= prefix[nreq]) return;
-    const int ri = find_req(prefix, nreq, blockIdx.x);
+    if (bid >= prefix[nreq]) return;
+    const int ri = find_req(prefix, nreq, bid);
     const Req& rq = reqs[ri];
-    const int tile = blockIdx.x - prefix[ri];
+    const int tile = bid - prefix[ri];
     const ISVD_GLOBAL DevHeader* hdr = gmem(rq.hdr);
     const int k = hdr->k, ld = hdr->ld, cur = hdr->cur;
     const bool useU = rq.kind == kCol;
@@ -154,6 +160,13 @@ __global__ void __launch_bounds__(kThreads) k_proj(const Req* __restrict__ reqs,
     }
 }
 
+template <typename T, int KC, int PASS>
+__global__ void __launch_bounds__(kThreads) k_proj(const Req* __restrict__ reqs, const int* __restrict__ prefix,
+                                                   int nreq) {
+    __shared__ double lds[proj_lds_doubles<KC>()];
+    proj_block<T, KC, PASS>(reqs, prefix, nreq, blockIdx.x, lds);
+}
+
 // ---------------------------------------------------------------------------
 // Core: assemble K, its FP64 SVD, sort, sign, truncate, and the rotation
 // matrices for U and V.
@@ -198,14 +211,15 @@ __host__ __device__ constexpr bool core_secular() { return !WITH_J && KC <= 64; 
 template <int KC, bool WITH_J>
 __host__ __device__ constexpr bool core_j_global() { return WITH_J && KC > 64; }
 
-// threads of a core block: the Jacobi shape's, or for the secular path
-// eight lanes per pole (roots, weights, norms, sort and sign take one lane
-// group per column)
+// threads of a core block: the Jacobi shape's, or for the secular (FP32
+// append) cores of every bucket kSecCoreThreads, which gives eight lanes per
+// pole at order 65 (roots, weights, norms, sort and sign take one lane group
+// per column) and lets one launch hold the cores of all those buckets
+constexpr int kSecCoreThreads = 576;
 template <int KC, bool WITH_J>
 __host__ __device__ constexpr int core_nt() {
-    constexpr int NJ = CoreShape<KC>::J::NT;
-    constexpr int NS = (8 * CoreShape<KC>::NMAX + 63) / 64 * 64;
-    return core_secular<KC, WITH_J>() && NS > NJ ? NS : NJ;
+    static_assert(8 * CoreShape<64>::NMAX <= kSecCoreThreads, "eight lanes per pole");
+    return core_secular<KC, WITH_J>() ? kSecCoreThreads : CoreShape<KC>::J::NT;
 }
 
 // Row stride (doubles) of W and W^-1 staged in LDS for the deferred-U
@@ -234,8 +248,11 @@ __host__ __device__ constexpr size_t core_jg_doubles(int KC) {
     return KC > 64 ? (size_t)CoreShape<128>::NMAX * CoreShape<128>::J::LDW : 0;
 }
 
+// The core of one request, one block (core_nt<KC, T == double>() threads,
+// core_lds_doubles<KC, ...>() doubles of dynamic LDS).
 template <typename T, int KC>
-__global__ void __launch_bounds__((core_nt<KC, sizeof(T) == 8>())) k_core(const Req* __restrict__ reqs) {
+__device__ __attribute__((always_inline)) inline void core_block(const Req* __restrict__ rqp) {
+    const Req& rq = *rqp;
     constexpr bool WITH_J = sizeof(T) == 8;
     constexpr bool SEC = core_secular<KC, WITH_J>();
     constexpr bool JG = core_j_global<KC, WITH_J>();
@@ -246,7 +263,6 @@ __global__ void __launch_bounds__((core_nt<KC, sizeof(T) == 8>())) k_core(const 
     __shared__ double s_sc[8];
     __shared__ int s_i[4];
     __shared__ int s_sec[4];
-    const Req& rq = reqs[blockIdx.x];
     ISVD_GLOBAL DevHeader* hdr = gmem(rq.hdr);
     ISVD_GLOBAL ReqScratch* rs = gmem(rq.rs);
     const int k = hdr->k, ld = hdr->ld, cur = hdr->cur;
@@ -742,6 +758,11 @@ __global__ void __launch_bounds__((core_nt<KC, sizeof(T) == 8>())) k_core(const 
     }
 }
 
+template <typename T, int KC>
+__global__ void __launch_bounds__((core_nt<KC, sizeof(T) == 8>())) k_core(const Req* __restrict__ reqs) {
+    core_block<T, KC>(reqs + blockIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // Rotation (the "update singular vectors" step): X'[r, :] = X[r, 0:k] Q[0:k, :]
 // (+ z^_r Q[k, :] for the projected basis of an append, with
@@ -1011,9 +1032,11 @@ __global__ void __launch_bounds__(kThreads) k_rotate_mfma(const Req* __restrict_
 // operands rounded to nearest BF16, FP32 accumulation): lane l holds the 4
 // k values 16 q + 4 (l/16) + 0..3 of a panel, which is exactly that
 // instruction's operand layout, so one MFMA covers a whole panel.
+// One block of rows (tile_all-th of the request, counted over U then V when
+// part = 0) of one request.
 template <int KC, int ROWS, int RT, bool PF, bool BF16 = false>
-__global__ void __launch_bounds__(kThreads) k_rotate_mfma_t(const Req* __restrict__ reqs,
-                                                            const int* __restrict__ prefix, int nreq, int part) {
+__device__ __attribute__((always_inline)) inline void rotate_mfma_t_block(const Req* __restrict__ rqp, int tile_all, int part) {
+    const Req& rq = *rqp;
     constexpr int NQ = (KC + 15) / 16;           // panels (loads per lane per tile)
     constexpr int STEPS = 4 * NQ;                // MFMA k-steps per output block
     constexpr int NB = NQ;                       // 16-column output blocks
@@ -1021,14 +1044,8 @@ __global__ void __launch_bounds__(kThreads) k_rotate_mfma_t(const Req* __restric
     constexpr int TSTEPS = ROWS / SROWS;
     __shared__ double sp[16 * NQ];
     __shared__ float sqz[16 * NB];
-    // a grid sized for more tiles than this launch has (a captured tick,
-    // sized for the streams' capacity) leaves the extra blocks idle
-    if ((int)blockIdx.x >= prefix[nreq]) return;
-    const int ri = find_req(prefix, nreq, blockIdx.x);
-    const Req& rq = reqs[ri];
-    const ReqScratch* rs = rq.rs;
+    const ISVD_GLOBAL ReqScratch* rs = gmem(rq.rs);
     if (rs->skip) return;
-    const int tile_all = blockIdx.x - prefix[ri];
     const bool isU = part == 1 || (part == 0 && tile_all < rq.rot_tiles_u);
     const int tile = (part != 0 || isU) ? tile_all : tile_all - rq.rot_tiles_u;
     // a row append applied to W (deferred U) rotates no U tile and V in
@@ -1043,7 +1060,7 @@ __global__ void __launch_bounds__(kThreads) k_rotate_mfma_t(const Req* __restric
     gcfloat* Q = (gcfloat*)(isU ? rq.QU : rq.QV);
     const bool projected = (rq.kind == kRow && !isU) || (rq.kind == kCol && isU);
     if (projected) {
-        for (int c = threadIdx.x; c < 16 * NQ; c += kThreads) sp[c] = c < kin ? rq.p[c] : 0.0;
+        for (int c = threadIdx.x; c < 16 * NQ; c += kThreads) sp[c] = c < kin ? gmem(rq.p)[c] : 0.0;
         for (int c = threadIdx.x; c < 16 * NB; c += kThreads) sqz[c] = c < ldo ? Q[kin * ldo + c] : 0.0f;
     }
     const int l = threadIdx.x & 63;
@@ -1079,7 +1096,7 @@ __global__ void __launch_bounds__(kThreads) k_rotate_mfma_t(const Req* __restric
             }
         }
     };
-    const float* yv_base = (const float*)rq.payload;
+    const ISVD_GLOBAL float* yv_base = gmem((const float*)rq.payload);
     const double inv_rho = rs->inv_rho;
     int64_t row0 = (int64_t)tile * ROWS + wave * 16 * RT;
     fetch(row0, b);
@@ -1160,6 +1177,16 @@ __global__ void __launch_bounds__(kThreads) k_rotate_mfma_t(const Req* __restric
         }
         row0 = nrow0;
     }
+}
+
+template <int KC, int ROWS, int RT, bool PF, bool BF16 = false>
+__global__ void __launch_bounds__(kThreads) k_rotate_mfma_t(const Req* __restrict__ reqs,
+                                                            const int* __restrict__ prefix, int nreq, int part) {
+    // a grid sized for more tiles than this launch has (a captured tick,
+    // sized for the streams' capacity) leaves the extra blocks idle
+    if ((int)blockIdx.x >= prefix[nreq]) return;
+    const int ri = find_req(prefix, nreq, blockIdx.x);
+    rotate_mfma_t_block<KC, ROWS, RT, PF, BF16>(reqs + ri, blockIdx.x - prefix[ri], part);
 }
 
 // ---------------------------------------------------------------------------
