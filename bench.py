@@ -73,8 +73,9 @@ def tick_bytes(m, n, k, esz, deferred=False):
 CSRC = os.path.join(ROOT, "paper_2605_24514_amd", "csrc")
 PMC_ROTATE = (os.path.join(ROOT, "profiles", "rotate_u_kc64_tick512_pmc.md"),
               [os.path.join(CSRC, f) for f in ("isvd_common.h", "isvd_update.h")])
-PMC_CORE = (os.path.join(ROOT, "profiles", "core_kc64_tick512_pmc.md"),
-            [os.path.join(CSRC, f) for f in ("isvd_common.h", "isvd_update.h", "isvd_secular.h", "isvd_jacobi.h")])
+PMC_CORE = (os.path.join(ROOT, "profiles", "core_chain_tick512_pmc.md"),
+            [os.path.join(CSRC, f) for f in ("isvd_common.h", "isvd_update.h", "isvd_secular.h", "isvd_jacobi.h",
+                                             "isvd_chain.h")])
 
 
 def core_bytes(k):
@@ -803,10 +804,12 @@ def main():
                          "launch_ms": round(dom_ms, 4), "bytes_per_launch": int(dom_bytes),
                          "flops_per_launch": dom_flops})
             return roof, phase_ms
-        # deferred U: the longest launch of the tick
+        # deferred U: the longest launch of the tick (bucket 0: a merged
+        # launch over every bucket)
         (ph, kdom) = max(by_launch, key=lambda key: float(np.mean(by_launch[key])))
         dom_ms = float(np.mean(by_launch[(ph, kdom)]))
-        sel = [(m0, n0, k) for (m0, n0, k) in params if bucket(k) == kdom]
+        sel = [(m0, n0, k) for (m0, n0, k) in params if kdom == 0 or bucket(k) == kdom]
+        what = "all buckets" if kdom == 0 else "bucket %d" % kdom
         if ph == 2:
             # the append core: its W update (W A and A^T W^-1, 4 k^3 flops per
             # append on the FP64 matrix cores) and its bytes (W, W^-1 read and
@@ -814,11 +817,13 @@ def main():
             flops = sum(4.0 * k ** 3 for (m0, n0, k) in sel)
             cbytes = sum(core_bytes(k) for (m0, n0, k) in sel)
             roof = bound_of(cbytes, flops, FP64_PEAK_TFLOPS, dom_ms)
-            cratio = recorded_traffic_ratio(PMC_CORE, "traffic_over_algorithmic") if kdom == 64 else None
+            cratio = recorded_traffic_ratio(PMC_CORE, "traffic_over_algorithmic") if kdom == 0 else None
             roof.update({"traffic": int(cratio * cbytes) if cratio is not None else None,
                          "traffic_note": "HBM bytes per launch: rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated, "
-                                         "ratio to algorithmic bytes from profiles/core_kc64_tick512_pmc.md",
-                         "kernel": "k_core<float, %d> (append core: secular SVD + deferred-U update, FP64)" % kdom,
+                                         "ratio to algorithmic bytes from profiles/core_chain_tick512_pmc.md",
+                         "kernel": ("k_core_chain (append cores of every bucket: secular SVD + deferred-U update, FP64)"
+                                    if kdom == 0 else
+                                    "k_core<float, %d> (append core: secular SVD + deferred-U update, FP64)" % kdom),
                          "launch_ms": round(dom_ms, 4), "flops_per_launch": flops, "bytes_per_launch": int(cbytes),
                          "note": "one workgroup per stream; bound by max(bytes / 8 TB/s, flops / FP64 matrix peak)"})
             return roof, phase_ms
@@ -830,7 +835,10 @@ def main():
         else:
             byts = sum(4.0 * n0 * k + 4.0 * n0 for (m0, n0, k) in sel)
         roof = bound_of(byts, 0.0, FP32_PEAK_TFLOPS, dom_ms)
-        roof.update({"traffic": None, "kernel": "%s, bucket %d" % (names[ph], kdom), "launch_ms": round(dom_ms, 4),
+        chain_names = {0: "k_proj_chain<1>", 1: "k_proj_chain<2>", 3: "k_uplan_chain + k_rotu_chain (U)",
+                       4: "k_rotv_chain (V)"}
+        roof.update({"traffic": None, "kernel": "%s, %s" % (chain_names[ph] if kdom == 0 else names[ph], what),
+                     "launch_ms": round(dom_ms, 4),
                      "bytes_per_launch": int(byts)})
         return roof, phase_ms
 
@@ -842,7 +850,7 @@ def main():
         torch.cuda._sleep(200_000_000)
     h0 = time.perf_counter()
     for q in range(6):
-        eng32.tick_raw(reqs[W + q], stream=dev_stream)
+        eng32.tick_raw(reqs[(W + q) % len(reqs)], stream=dev_stream)
     host_unthrottled = (time.perf_counter() - h0) / 6
     eng32.sync(stream=dev_stream)
     torch.cuda.synchronize()

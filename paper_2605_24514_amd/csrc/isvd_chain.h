@@ -21,14 +21,15 @@ constexpr int kChainUGrid = 2048;     // blocks of the U-rotation launch (loop p
 constexpr int kChainPlanThreads = 1024;
 
 // The request lists of one merged launch, one entry per bucket, in launch
-// order; bucket q owns blocks [begin[q], begin[q + 1]).  prefix[q]: the
-// bucket's block prefix over its requests (projections, rotations), unused
-// by the cores (one block per request).
+// order; bucket q owns blocks [begin[q], begin[q + 1]).  tbl[q]: request and
+// tile of each of the bucket's blocks (projections, V rotations), written by
+// the host with the records; unused by the cores (one block per request) and
+// the planned U rotations.
 struct MultiGroup {
     int n = 0;
     int kc[kChainMax];
     const Req* reqs[kChainMax];
-    const int* prefix[kChainMax];
+    const BlockRef* tbl[kChainMax];
     int nreq[kChainMax];
     int begin[kChainMax + 1];
 };
@@ -56,11 +57,13 @@ __global__ void __launch_bounds__(kThreads) k_proj_chain(MultiGroup mg) {
     __shared__ double lds[L];
     int bid;
     const int q = chain_pick(mg, &bid);
+    const BlockRef br = mg.tbl[q][bid];
+    const Req* rq = mg.reqs[q] + br.req;
     switch (mg.kc[q]) {
-        case 8: proj_block<float, 8, PASS>(mg.reqs[q], mg.prefix[q], mg.nreq[q], bid, lds); break;
-        case 16: proj_block<float, 16, PASS>(mg.reqs[q], mg.prefix[q], mg.nreq[q], bid, lds); break;
-        case 32: proj_block<float, 32, PASS>(mg.reqs[q], mg.prefix[q], mg.nreq[q], bid, lds); break;
-        default: proj_block<float, 64, PASS>(mg.reqs[q], mg.prefix[q], mg.nreq[q], bid, lds); break;
+        case 8: proj_tile<float, 8, PASS>(rq, br.tile, lds); break;
+        case 16: proj_tile<float, 16, PASS>(rq, br.tile, lds); break;
+        case 32: proj_tile<float, 32, PASS>(rq, br.tile, lds); break;
+        default: proj_tile<float, 64, PASS>(rq, br.tile, lds); break;
     }
 }
 
@@ -79,14 +82,12 @@ __global__ void __launch_bounds__(kSecCoreThreads) k_core_chain(MultiGroup mg) {
 }
 
 // V tiles (part 2) of every bucket, kRotRowsV rows per block
-__global__ void __launch_bounds__(kThreads) k_rotv_chain(MultiGroup mg) {
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) k_rotv_chain(MultiGroup mg) {
     int bid;
     const int q = chain_pick(mg, &bid);
-    const int* prefix = mg.prefix[q];
-    if (bid >= prefix[mg.nreq[q]]) return;
-    const int ri = find_req(prefix, mg.nreq[q], bid);
-    const Req* rq = mg.reqs[q] + ri;
-    const int tile = bid - prefix[ri];
+    const BlockRef br = mg.tbl[q][bid];
+    const Req* rq = mg.reqs[q] + br.req;
+    const int tile = br.tile;
     switch (mg.kc[q]) {
         case 8: rotate_mfma_t_block<8, kRotRowsV, 1, true>(rq, tile, 2); break;
         case 16: rotate_mfma_t_block<16, kRotRowsV, 1, true>(rq, tile, 2); break;
@@ -99,54 +100,60 @@ __global__ void __launch_bounds__(kThreads) k_rotv_chain(MultiGroup mg) {
 // the buckets in order) rotates U in ceil(m / kChainRowsU) blocks unless its
 // core skipped it or applied its append to W.  Writes the planned blocks,
 // their prefix over the requests and the request codes (bucket << 24 | index).
+constexpr int kChainPlanPer = 16;   // requests per thread at most (16384 / 1024)
 __global__ void __launch_bounds__(kChainPlanThreads) k_uplan_chain(MultiGroup mg, int* __restrict__ plan) {
-    __shared__ int ssum[kChainPlanThreads];
-    const int tid = threadIdx.x;
+    __shared__ int wsum[kChainPlanThreads / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     int G = 0;
     for (int q = 0; q < mg.n; ++q) G += mg.nreq[q];
     int* prefix = plan + 1;
     int* code = plan + 2 + G;
     const int per = (G + kChainPlanThreads - 1) / kChainPlanThreads;
-    const int g0 = tid * per, g1 = g0 + per < G ? g0 + per : G;
-    auto locate = [&](int g, int* qq) {
-        int q = 0, base = 0;
-        while (g >= base + mg.nreq[q]) {
-            base += mg.nreq[q];
-            ++q;
-        }
-        *qq = q;
-        return g - base;
-    };
-    auto blocks_of = [&](int q, int ri) {
-        const Req& rq = mg.reqs[q][ri];
-        const ISVD_GLOBAL ReqScratch* rs = gmem(rq.rs);
-        return (rs->skip || rs->deferred) ? 0 : (int)((rq.m + kChainRowsU - 1) / kChainRowsU);
-    };
+    const int g0 = tid * per;
+    int bl[kChainPlanPer], cd[kChainPlanPer];
     int local = 0;
-    for (int g = g0; g < g1; ++g) {
-        int q;
-        const int ri = locate(g, &q);
-        local += blocks_of(q, ri);
+#pragma unroll
+    for (int i = 0; i < kChainPlanPer; ++i) {
+        bl[i] = 0;
+        cd[i] = 0;
+        const int g = g0 + i;
+        if (i < per && g < G) {
+            int q = 0, base = 0;
+            while (g >= base + mg.nreq[q]) {
+                base += mg.nreq[q];
+                ++q;
+            }
+            const int ri = g - base;
+            const Req& rq = mg.reqs[q][ri];
+            const ISVD_GLOBAL ReqScratch* rs = gmem(rq.rs);
+            bl[i] = (rs->skip || rs->deferred) ? 0 : (int)((rq.m + kChainRowsU - 1) / kChainRowsU);
+            cd[i] = (q << 24) | ri;
+            local += bl[i];
+        }
     }
-    ssum[tid] = local;
+    // exclusive prefix of `local` over the block: within the wave, then over the waves
+    int incl = local;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int v = __shfl_up(incl, o);
+        if (lane >= o) incl += v;
+    }
+    if (lane == 63) wsum[wave] = incl;
     __syncthreads();
-    for (int off = 1; off < kChainPlanThreads; off <<= 1) {
-        const int v = tid >= off ? ssum[tid - off] : 0;
-        __syncthreads();
-        ssum[tid] += v;
-        __syncthreads();
-    }
-    int run = tid > 0 ? ssum[tid - 1] : 0;
-    for (int g = g0; g < g1; ++g) {
-        int q;
-        const int ri = locate(g, &q);
-        prefix[g] = run;
-        code[g] = (q << 24) | ri;
-        run += blocks_of(q, ri);
+    int wbase = 0;
+    for (int w = 0; w < wave; ++w) wbase += wsum[w];
+    int run = wbase + incl - local;
+#pragma unroll
+    for (int i = 0; i < kChainPlanPer; ++i) {
+        const int g = g0 + i;
+        if (i < per && g < G) {
+            prefix[g] = run;
+            code[g] = cd[i];
+            run += bl[i];
+        }
     }
     if (tid == kChainPlanThreads - 1) {
-        plan[0] = ssum[tid];
-        prefix[G] = ssum[tid];
+        plan[0] = run;
+        prefix[G] = run;
     }
 }
 

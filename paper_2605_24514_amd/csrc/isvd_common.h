@@ -18,10 +18,10 @@ constexpr int kMfmaRotRows = 512;
 struct RotVariant { int rows, rt, pf; };
 constexpr int kRotVariants = 5;
 constexpr RotVariant kRotVariant[kRotVariants] = {{256, 1, 1}, {512, 1, 1}, {1024, 1, 1}, {1024, 2, 0}, {2048, 2, 0}};
-// V rotations of a tick (FP32, buckets up to 64) take 128 rows per block
-// (two steps per wave): V has at most a few thousand rows, so the U shapes
+// V rotations of a tick (FP32, buckets up to 64) take 256 rows per block
+// (four steps per wave): V has at most a few thousand rows, so the U shapes
 // would leave a handful of blocks per stream, each walking its rows in turn
-constexpr int kRotRowsV = 128;
+constexpr int kRotRowsV = 256;
 constexpr int kMaxRank = 128;      // largest rank k of a stream
 constexpr int kMaxCore = kMaxRank + 1;   // largest core order (an append's (k + 1) x (k + 1))
 constexpr int kMaxBlock = 128;     // largest refresh block size b
@@ -101,6 +101,11 @@ struct ReqScratch {
 
 // One update request as the kernels see it.  Geometry is the pre-update
 // shape (known exactly on the host); the rank comes from the DevHeader.
+// The request (index in its list) and tile of one block of a merged launch.
+struct BlockRef {
+    int req, tile;
+};
+
 struct Req {
     int64_t m, n, lda;
     int64_t i, j;

@@ -215,6 +215,8 @@ struct Group {
     std::vector<int> pre_rot;  // block prefix of the rotation list, U and V (size all+1)
     std::vector<int> pre_rotU; // ... U tiles only
     std::vector<int> pre_rotV; // ... V tiles only
+    std::vector<BlockRef> tproj, trotv;   // merged launches: request and tile of each block
+    size_t off_tp = 0, off_tv = 0;
     size_t off_all = 0, off_proj = 0, off_pp = 0, off_pr = 0, off_pru = 0, off_prv = 0;
     bool proj_alias = false;   // the projection list is the whole list (no entry update)
     std::vector<isvd_id> ids;  // the requests' streams (the key of a captured tick)
@@ -739,7 +741,7 @@ isvd_status launch_recorded(isvd_engine* e, const Group& g, const char* dev, int
 // overwrite.
 // Layout of a tick's groups in one upload buffer: block prefixes and offsets
 // (groups sorted by bucket, widest first).  Returns the buffer's bytes.
-size_t layout_groups(std::vector<Group>& groups) {
+size_t layout_groups(std::vector<Group>& groups, bool tables = false) {
     std::sort(groups.begin(), groups.end(), [](const Group& a, const Group& b) {
         return a.kc != b.kc ? a.kc > b.kc : (a.fp64 && !b.fp64);
     });
@@ -771,6 +773,16 @@ size_t layout_groups(std::vector<Group>& groups) {
         g.off_pr = take(sizeof(int) * (na + 1));
         g.off_pru = take(sizeof(int) * (na + 1));
         g.off_prv = take(sizeof(int) * (na + 1));
+        g.tproj.clear();
+        g.trotv.clear();
+        if (tables) {
+            for (size_t q = 0; q < g.proj.size(); ++q)
+                for (int t = 0; t < g.proj[q].proj_tiles; ++t) g.tproj.push_back({(int)q, t});
+            for (size_t q = 0; q < na; ++q)
+                for (int t = 0; t < g.pre_rotV[q + 1] - g.pre_rotV[q]; ++t) g.trotv.push_back({(int)q, t});
+            g.off_tp = take(sizeof(BlockRef) * g.tproj.size());
+            g.off_tv = take(sizeof(BlockRef) * g.trotv.size());
+        }
     }
     return off;
 }
@@ -785,6 +797,8 @@ void fill_groups(const std::vector<Group>& groups, char* host) {
         memcpy(host + g.off_pr, g.pre_rot.data(), sizeof(int) * (na + 1));
         memcpy(host + g.off_pru, g.pre_rotU.data(), sizeof(int) * (na + 1));
         memcpy(host + g.off_prv, g.pre_rotV.data(), sizeof(int) * (na + 1));
+        if (!g.tproj.empty()) memcpy(host + g.off_tp, g.tproj.data(), sizeof(BlockRef) * g.tproj.size());
+        if (!g.trotv.empty()) memcpy(host + g.off_tv, g.trotv.data(), sizeof(BlockRef) * g.trotv.size());
     }
 }
 
@@ -828,9 +842,12 @@ isvd_status own_lane_sequence(isvd_engine* e, const std::vector<Group>& groups, 
 // chain of kernels on the caller's stream, with no lanes to fork and join.
 bool chain_ok(const isvd_engine* e, const std::vector<Group>& groups) {
     if (!e->defer_u || groups.empty() || groups.size() > (size_t)kChainMax) return false;
-    for (const Group& g : groups)
+    size_t nreq = 0;
+    for (const Group& g : groups) {
         if (g.fp64 || g.bf16 || g.kc > 64) return false;
-    return true;
+        nreq += g.all.size();
+    }
+    return nreq <= (size_t)kChainPlanPer * kChainPlanThreads;
 }
 
 isvd_status ensure_chain_plan(isvd_engine* e) {
@@ -853,7 +870,7 @@ MultiGroup chain_args(const std::vector<Group>& groups, const char* dev, int pha
         const int q = mg.n++;
         mg.kc[q] = g.kc;
         mg.reqs[q] = reinterpret_cast<const Req*>(dev + (phase < 2 ? g.off_proj : g.off_all));
-        mg.prefix[q] = reinterpret_cast<const int*>(dev + (phase < 2 ? g.off_pp : g.off_prv));
+        mg.tbl[q] = reinterpret_cast<const BlockRef*>(dev + (phase < 2 ? g.off_tp : g.off_tv));
         mg.nreq[q] = nreq;
         mg.begin[q + 1] = mg.begin[q] + nb;
     }
@@ -932,14 +949,14 @@ constexpr size_t kMaxTickGraphs = 4;
 // TickGraph); the first tick of a request set captures it.
 isvd_status run_groups_graph(isvd_engine* e, std::vector<Group>& groups, hipStream_t st, bool pipelined) {
     ST_TRY(ensure_lanes(e));
-    const size_t off = layout_groups(groups);
+    const bool chain = chain_ok(e, groups);
+    const size_t off = layout_groups(groups, chain);
     std::vector<int64_t> key;
     for (const Group& g : groups) {
         key.insert(key.end(), {(int64_t)g.kc, (int64_t)(g.fp64 * 2 + g.bf16), (int64_t)g.var, (int64_t)g.rows,
                                (int64_t)g.all.size(), (int64_t)g.proj.size(), (int64_t)g.rotU_cap});
         key.insert(key.end(), g.ids.begin(), g.ids.end());
     }
-    const bool chain = chain_ok(e, groups);
     if (chain) ST_TRY(ensure_chain_plan(e));
     TickGraph* tg = nullptr;
     for (TickGraph* c : e->tgraphs)
@@ -1003,11 +1020,12 @@ isvd_status run_groups_graph(isvd_engine* e, std::vector<Group>& groups, hipStre
 
 isvd_status run_groups(isvd_engine* e, std::vector<Group>& groups, hipStream_t st, bool pipelined) {
     ST_TRY(ensure_lanes(e));
-    const size_t off = layout_groups(groups);
+    const bool chain = chain_ok(e, groups);
+    const size_t off = layout_groups(groups, chain);
     Slot* slot = nullptr;
     ST_TRY(acquire_slot(e, off, &slot));
     fill_groups(groups, slot->host);
-    if (chain_ok(e, groups)) {
+    if (chain) {
         ST_TRY(ensure_chain_plan(e));
         if (e->ticks >= 2 && e->lane_ticks < 2) HIP_TRY(hipStreamWaitEvent(st, e->ev_tick_end[e->ticks & 1], 0));
         ST_TRY(upload_slot(slot, off, st));

@@ -57,23 +57,16 @@ __device__ inline const void* basis_cur(const Req& rq, bool useU, int cur) {
 template <int KC>
 __host__ __device__ constexpr int proj_lds_doubles() { return (kThreads / (KC / 4)) * (KC + 2) + KC; }
 
-// One block's part of a projection launch: block `bid` of the request list
-// (reqs, prefix, nreq); lds: proj_lds_doubles<KC>() doubles.
+// Projection tile `tile` (rows [tile kProjTile, ...)) of one request.
 template <typename T, int KC, int PASS>
-__device__ __attribute__((always_inline)) inline void proj_block(const Req* __restrict__ reqs, const int* __restrict__ prefix, int nreq, int bid,
-                                  double* lds) {
+__device__ __attribute__((always_inline)) inline void proj_tile(const Req* __restrict__ rqp, int tile, double* lds) {
     constexpr int TPR = KC / 4;                  // lanes per row (4 columns each)
     constexpr int RPB = kThreads / TPR;          // rows per block step
     constexpr int SP = KC + 2;
     constexpr int UNR = 4;                       // row steps in flight per lane
+    const Req& rq = *rqp;
     double (*sacc)[SP] = reinterpret_cast<double (*)[SP]>(lds);
     double* sp1 = lds + RPB * SP;
-    // a grid sized for more tiles than this launch has (a captured tick,
-    // sized for the streams' capacity) leaves the extra blocks idle
-    if (bid >= prefix[nreq]) return;
-    const int ri = find_req(prefix, nreq, bid);
-    const Req& rq = reqs[ri];
-    const int tile = bid - prefix[ri];
     const ISVD_GLOBAL DevHeader* hdr = gmem(rq.hdr);
     const int k = hdr->k, ld = hdr->ld, cur = hdr->cur;
     const bool useU = rq.kind == kCol;
@@ -158,6 +151,19 @@ __device__ __attribute__((always_inline)) inline void proj_block(const Req* __re
         for (int gg = 0; gg < RPB; ++gg) s1 += sacc[gg][c];
         part[c] = s1;
     }
+}
+
+// One block's part of a projection launch: block `bid` of the request list
+// (reqs, prefix, nreq); lds: proj_lds_doubles<KC>() doubles.
+template <typename T, int KC, int PASS>
+__device__ __attribute__((always_inline)) inline void proj_block(const Req* __restrict__ reqs,
+                                                                 const int* __restrict__ prefix, int nreq, int bid,
+                                                                 double* lds) {
+    // a grid sized for more tiles than this launch has (a captured tick,
+    // sized for the streams' capacity) leaves the extra blocks idle
+    if (bid >= prefix[nreq]) return;
+    const int ri = find_req(prefix, nreq, bid);
+    proj_tile<T, KC, PASS>(reqs + ri, bid - prefix[ri], lds);
 }
 
 template <typename T, int KC, int PASS>
@@ -1081,9 +1087,12 @@ __device__ __attribute__((always_inline)) inline void rotate_mfma_t_block(const 
         }
     __syncthreads();
     mfma_v4f b[RT][NQ], bn[PF ? RT : 1][NQ];
+    float yb[RT], ybn[PF ? RT : 1];
+    const ISVD_GLOBAL float* yv_base = gmem((const float*)rq.payload);
     // the B operand of a step's tiles: panel q, 4-column group g, row n (zero
-    // past the basis' rows or columns)
-    auto fetch = [&](int64_t s0, mfma_v4f (*dst)[NQ]) {
+    // past the basis' rows or columns), and for the projected basis the
+    // payload entry of row n, fetched with it
+    auto fetch = [&](int64_t s0, mfma_v4f (*dst)[NQ], float* ydst) {
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt) {
             const int64_t t0 = s0 + 16 * rt;
@@ -1094,18 +1103,18 @@ __device__ __attribute__((always_inline)) inline void rotate_mfma_t_block(const 
                 else
                     dst[rt][q] = (mfma_v4f){0.f, 0.f, 0.f, 0.f};
             }
+            ydst[rt] = (projected && t0 + n < rows) ? yv_base[t0 + n] : 0.0f;
         }
     };
-    const ISVD_GLOBAL float* yv_base = gmem((const float*)rq.payload);
     const double inv_rho = rs->inv_rho;
     int64_t row0 = (int64_t)tile * ROWS + wave * 16 * RT;
-    fetch(row0, b);
+    fetch(row0, b, yb);
 #pragma unroll 1
     for (int t = 0; t < TSTEPS; ++t) {
         if (row0 >= rows) break;
         const int64_t nrow0 = row0 + SROWS;
         if constexpr (PF) {
-            if (t + 1 < TSTEPS) fetch(nrow0, bn);
+            if (t + 1 < TSTEPS) fetch(nrow0, bn, ybn);
         }
         mfma_v4f acc[RT][NB];
 #pragma unroll
@@ -1149,7 +1158,7 @@ __device__ __attribute__((always_inline)) inline void rotate_mfma_t_block(const 
                     d += (double)b[rt][s4 >> 2][s4 & 3] * sp[16 * (s4 >> 2) + 4 * g + (s4 & 3)];
                 d += __shfl_xor(d, 16);
                 d += __shfl_xor(d, 32);
-                const float yv = live ? yv_base[row] : 0.0f;
+                const float yv = live ? yb[rt] : 0.0f;
                 const float z = (float)(((double)yv - d) * inv_rho);
                 if (live && g == 0) {
                     gfloat* A = (gfloat*)rq.A;
@@ -1169,11 +1178,13 @@ __device__ __attribute__((always_inline)) inline void rotate_mfma_t_block(const 
         }
         if constexpr (PF) {
 #pragma unroll
-            for (int rt = 0; rt < RT; ++rt)
+            for (int rt = 0; rt < RT; ++rt) {
 #pragma unroll
                 for (int q = 0; q < NQ; ++q) b[rt][q] = bn[rt][q];
+                yb[rt] = ybn[rt];
+            }
         } else {
-            if (t + 1 < TSTEPS) fetch(nrow0, b);
+            if (t + 1 < TSTEPS) fetch(nrow0, b, yb);
         }
         row0 = nrow0;
     }
