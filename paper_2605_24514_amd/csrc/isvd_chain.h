@@ -70,7 +70,7 @@ __global__ void __launch_bounds__(kThreads) k_proj_chain(MultiGroup mg) {
 // dynamic LDS (doubles) of the merged core launch: the widest bucket's
 __host__ __device__ constexpr size_t chain_core_lds() { return core_lds_doubles<64, false>(); }
 
-__global__ void __launch_bounds__(kSecCoreThreads) k_core_chain(MultiGroup mg) {
+__global__ void __launch_bounds__(kSecCoreThreads) __attribute__((amdgpu_waves_per_eu(3))) k_core_chain(MultiGroup mg) {
     int bid;
     const int q = chain_pick(mg, &bid);
     switch (mg.kc[q]) {

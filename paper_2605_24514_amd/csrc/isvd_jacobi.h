@@ -108,7 +108,9 @@ __device__ inline double dpp_group_sum(double v) {
 // ldw = JacobiShape<NMAX, TPP>::LDW with zero rows from N up to the stride.
 // WITH_J: accumulate the rotations into J (= I on entry); without it only W
 // is rotated.
-template <int NMAX, bool WITH_J, int TPP = 4>
+// GUARD: the column stride is below the shape's EPT x TPP, so lanes touch
+// rows below N only.
+template <int NMAX, bool WITH_J, int TPP = 4, bool GUARD = false>
 __device__ inline int jacobi_block(double* W, double* J, int N, int ldw, int max_sweeps, double tol_min = 0.0) {
     typedef JacobiShape<NMAX, TPP> S;
     const int tid = threadIdx.x;
@@ -140,11 +142,12 @@ __device__ inline int jacobi_block(double* W, double* J, int N, int ldw, int max
 #pragma unroll
             for (int i = 0; i < S::EPT; ++i) {
                 const int e = lane + i * S::TPP;
-                x[i] = wp[e];
-                y[i] = wq[e];
+                const bool in = !GUARD || e < N;
+                x[i] = in ? wp[e] : 0.0;
+                y[i] = in ? wq[e] : 0.0;
                 if constexpr (WITH_J) {
-                    u[i] = jp[e];
-                    v[i] = jq[e];
+                    u[i] = in ? jp[e] : 0.0;
+                    v[i] = in ? jq[e] : 0.0;
                 }
             }
             double alpha = 0.0, beta = 0.0, gam = 0.0;
@@ -168,6 +171,7 @@ __device__ inline int jacobi_block(double* W, double* J, int N, int ldw, int max
 #pragma unroll
                 for (int i = 0; i < S::EPT; ++i) {
                     const int e = lane + i * S::TPP;
+                    if (GUARD && e >= N) continue;
                     wp[e] = c * x[i] - sn * y[i];
                     wq[e] = sn * x[i] + c * y[i];
                     if constexpr (WITH_J) {

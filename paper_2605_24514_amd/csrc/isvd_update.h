@@ -218,14 +218,23 @@ template <int KC, bool WITH_J>
 __host__ __device__ constexpr bool core_j_global() { return WITH_J && KC > 64; }
 
 // threads of a core block: the Jacobi shape's, or for the secular (FP32
-// append) cores of every bucket kSecCoreThreads, which gives eight lanes per
-// pole at order 65 (roots, weights, norms, sort and sign take one lane group
-// per column) and lets one launch hold the cores of all those buckets
-constexpr int kSecCoreThreads = 576;
+// append) cores of every bucket kSecCoreThreads: four lanes per pole at order
+// 65 (roots, weights, norms, sort and sign take one lane group per column),
+// one launch for the cores of all those buckets, and two blocks of the
+// widest bucket per compute unit (registers and LDS)
+constexpr int kSecCoreThreads = 384;
 template <int KC, bool WITH_J>
 __host__ __device__ constexpr int core_nt() {
-    static_assert(8 * CoreShape<64>::NMAX <= kSecCoreThreads, "eight lanes per pole");
     return core_secular<KC, WITH_J>() ? kSecCoreThreads : CoreShape<KC>::J::NT;
+}
+
+// Column stride (doubles) of the core's matrices in LDS: the Jacobi shape's,
+// or for the secular cores the order rounded up to even (their Jacobi
+// fallback then guards its rows), which keeps the widest one within half of
+// a compute unit's LDS so that two cores share it.
+template <int KC, bool WITH_J>
+__host__ __device__ constexpr int core_ldw() {
+    return core_secular<KC, WITH_J>() ? CoreShape<KC>::NMAX + (CoreShape<KC>::NMAX & 1) : CoreShape<KC>::J::LDW;
 }
 
 // Row stride (doubles) of W and W^-1 staged in LDS for the deferred-U
@@ -234,20 +243,20 @@ template <int KC>
 __host__ __device__ constexpr int core_wst() { return KC + 2; }
 
 // dynamic LDS (doubles) of a core block of bucket KC; the secular (FP32
-// append) cores also stage W and W^-1 after it (and A^T in the V_K region)
+// append) cores stage A^T in the V_K region and W, then W^-1, in the K V one
 template <int KC, bool WITH_J>
 __host__ __device__ constexpr size_t core_lds_base() {
     constexpr bool SEC = core_secular<KC, WITH_J>();
     constexpr bool JLDS = (WITH_J && !core_j_global<KC, WITH_J>()) || SEC;
-    return (size_t)(JLDS ? 2 : 1) * CoreShape<KC>::NMAX * CoreShape<KC>::J::LDW +
+    return (size_t)(JLDS ? 2 : 1) * CoreShape<KC>::NMAX * core_ldw<KC, WITH_J>() +
            (size_t)8 * CoreShape<KC>::NMAX +
            (size_t)(SEC ? secular_scratch_doubles(CoreShape<KC>::NMAX) : 0);
 }
 template <int KC, bool WITH_J>
 __host__ __device__ constexpr size_t core_lds_doubles() {
-    static_assert(KC * core_wst<KC>() <= CoreShape<KC>::NMAX * CoreShape<KC>::J::LDW, "A^T fits the V_K region");
+    static_assert(KC * core_wst<KC>() <= CoreShape<KC>::NMAX * core_ldw<KC, WITH_J>(), "A^T, W fit a matrix region");
     // (+1: room to align the region to 16 bytes)
-    return core_lds_base<KC, WITH_J>() + (core_secular<KC, WITH_J>() ? (size_t)2 * KC * core_wst<KC>() : 0) + 1;
+    return core_lds_base<KC, WITH_J>() + 1;
 }
 // global doubles of Req::Jg for a stream of bucket KC
 __host__ __device__ constexpr size_t core_jg_doubles(int KC) {
@@ -275,11 +284,14 @@ __device__ __attribute__((always_inline)) inline void core_block(const Req* __re
     const int kind = rq.kind;
     const int N = kind == kEntry ? k : k + 1;
     const int tid = threadIdx.x, nt = blockDim.x;
-    const int ldw = CoreShape<KC>::J::LDW;
+    const int ldw = core_ldw<KC, WITH_J>();
     double* W = smem;
     // V_K: WITH_J (in global memory for the widest FP64 cores), or the secular path
-    double* J = JG ? rq.Jg : W + (size_t)N * ldw;
-    double* sS = W + (size_t)N * ldw + (((WITH_J && !JG) || SEC) ? (size_t)N * ldw : 0); // Sigma (k)
+    // regions at fixed offsets (the bucket's largest order), so that each
+    // matrix region holds a KC x KC operand of the deferred-U products
+    constexpr size_t MREG = (size_t)CoreShape<KC>::NMAX * core_ldw<KC, WITH_J>();
+    double* J = JG ? rq.Jg : W + MREG;
+    double* sS = W + MREG + (((WITH_J && !JG) || SEC) ? MREG : 0); // Sigma (k)
     double* sp = sS + N;                           // p (row / column) or s_v (rank-1)
     double* sig = sp + N;
     double* sgn = sig + N;
@@ -386,7 +398,7 @@ __device__ __attribute__((always_inline)) inline void core_block(const Req* __re
     }
     // FP32 storage rounds U_K, V_K to 6e-8: columns orthogonal to 1e-10 suffice
     const int sweeps = use_sec ? 0
-                               : jacobi_block<CoreShape<KC>::NMAX, WITH_J, CoreShape<KC>::J::TPP>(
+                               : jacobi_block<CoreShape<KC>::NMAX, WITH_J, CoreShape<KC>::J::TPP, SEC>(
                                      W, J, N, ldw, 40, WITH_J ? 0.0 : 1e-10);
     constexpr int NTC = core_nt<KC, WITH_J>();
     // a deferred-U stream's W and W^-1 (current parity, KC x KC each): the
@@ -569,7 +581,7 @@ __device__ __attribute__((always_inline)) inline void core_block(const Req* __re
             // The products run on the FP64 matrix cores
             // (v_mfma_f64_16x16x4f64: lane l holds A[l%16][l/16] and
             // B[l/16][l%16]; D[4r + l/16][l%16] is the lane's r-th value), one
-            // 16 x 16 output tile per wave at a time (at most eight waves, two
+            // 16 x 16 output tile per wave at a time (at most four waves, one
             // per SIMD); lane quarter q takes the contraction indices
             // [q KC/4, (q+1) KC/4), so each lane reads its operands from LDS
             // as contiguous runs: rows of W, of W^-1's transpose, and of A^T,
@@ -579,28 +591,11 @@ __device__ __attribute__((always_inline)) inline void core_block(const Req* __re
             double* gv = xsec + CoreShape<KC>::NMAX;            // f_j b_j (k)
             double* vv = xsec + 2 * CoreShape<KC>::NMAX;        // v (k)
             constexpr int WST = core_wst<KC>();
-            static_assert(core_lds_base<KC, WITH_J>() % 2 == 0 && WST % 2 == 0, "16-byte rows");
-            double* At = J;                                      // A^T (the V_K region is free now)
-            double* Wl = smem + core_lds_base<KC, WITH_J>();    // W
-            double* Wil = Wl + KC * WST;                        // W^-1, transposed
+            static_assert(core_lds_base<KC, WITH_J>() % 2 == 0 && WST % 2 == 0 && core_ldw<KC, WITH_J>() % 2 == 0,
+                          "16-byte rows");
+            double* At = J;        // A^T (the V_K region is free once the outputs are written)
+            double* Wst = W;       // W, then W^-1 transposed (the K V region, once A^T and v are formed)
             __syncthreads();
-#pragma unroll
-            for (int q = 0; q < PF; ++q) {
-                const int e = tid + q * NTC;
-                // entries outside the leading k x k block are stored as zeros, so
-                // the products need no masks
-                if (e < KC * KC / 2) {
-                    const int r = 2 * e / KC, c = 2 * e % KC;
-                    gvec_d2 v = pf[q];
-                    v.x = (r < k && c < k) ? v.x : 0.0;
-                    v.y = (r < k && c + 1 < k) ? v.y : 0.0;
-                    *(gvec_d2*)(Wl + r * WST + c) = v;
-                } else if (e < KC * KC) {
-                    const int e2 = 2 * (e - KC * KC / 2), r = e2 / KC, c = e2 % KC;
-                    Wil[c * WST + r] = (r < k && c < k) ? pf[q].x : 0.0;
-                    Wil[(c + 1) * WST + r] = (r < k && c + 1 < k) ? pf[q].y : 0.0;
-                }
-            }
             for (int j = tid; j < kout; j += nt) {
                 const double f = sgn[j] / sig[j];
                 const double kb = W[(size_t)perm[j] * ldw + k];
@@ -632,66 +627,94 @@ __device__ __attribute__((always_inline)) inline void core_block(const Req* __re
                 }
             }
             __syncthreads();
+            // stage one of the prefetched matrices (entries outside the leading
+            // k x k block as zeros, so the products need no masks): W row-major,
+            // or W^-1 transposed
+            auto stage = [&](bool inverse) {
+#pragma unroll
+                for (int q = 0; q < PF; ++q) {
+                    const int e = tid + q * NTC;
+                    if (!inverse && e < KC * KC / 2) {
+                        const int r = 2 * e / KC, c = 2 * e % KC;
+                        gvec_d2 v = pf[q];
+                        v.x = (r < k && c < k) ? v.x : 0.0;
+                        v.y = (r < k && c + 1 < k) ? v.y : 0.0;
+                        *(gvec_d2*)(Wst + r * WST + c) = v;
+                    } else if (inverse && e >= KC * KC / 2 && e < KC * KC) {
+                        const int e2 = 2 * (e - KC * KC / 2), r = e2 / KC, c = e2 % KC;
+                        Wst[c * WST + r] = (r < k && c < k) ? pf[q].x : 0.0;
+                        Wst[(c + 1) * WST + r] = (r < k && c + 1 < k) ? pf[q].y : 0.0;
+                    }
+                }
+            };
+            stage(false);
+            __syncthreads();
             constexpr int S = KC / 4;
             const int lane = tid & 63, wave = tid >> 6;
-            const int twv = (nt >> 6) < 8 ? (nt >> 6) : 8;     // waves on the products
+            const int twv = (nt >> 6) < 4 ? (nt >> 6) : 4;     // waves on the products (one per SIMD)
             const int li = lane & 15, lq = lane >> 4;
             const int c0 = lq * S;
             const int kt = (k + 15) / 16;
             const int jt = defer ? kt : (ldo + 15) / 16;
-            const int ntile = defer ? 2 * kt * kt : kt * jt;
             ISVD_GLOBAL double* Wn = gmem(rq.Wd[wp ^ 1]);
             ISVD_GLOBAL double* Win = gmem(rq.Wdi[wp ^ 1]);
             ISVD_GLOBAL T* U0 = gmem((T*)rq.U[cur]);
-            for (int t = wave; t < ntile && wave < twv; t += twv) {
-                const int inv = t >= kt * jt ? 1 : 0;       // 0: W A (or U's rotation), 1: A^-1 W^-1
-                const int tt = t - inv * kt * jt;
-                const int r0 = (tt / jt) * 16, j0 = (tt % jt) * 16;
-                const int ra = r0 + li, jb = j0 + li;
-                double av[S], bw[S];
-                // operand rows past k (or past k_out) are zero in LDS
-                const double2* pa;
-                const double2* pb;
-                double br = 0.0;
-                if (!inv) {
-                    pa = (const double2*)(Wl + ra * WST + c0);    // row ra of W
-                    pb = (const double2*)(At + jb * WST + c0);    // column jb of A (row jb of A^T)
-                } else {
-                    pa = (const double2*)(At + ra * WST + c0);    // row ra of A^-1 = A^T + b^T v ...
-                    pb = (const double2*)(Wil + jb * WST + c0);   // column jb of W^-1 (a row of its transpose)
-                    br = bv[ra];
+            // inv = 0: W A (or, explicit, U's rotation); inv = 1: A^-1 W^-1 and u0
+            for (int inv = 0; inv < (defer ? 2 : 1); ++inv) {
+                if (inv) {
+                    __syncthreads();   // every read of W is done
+                    stage(true);
+                    __syncthreads();
                 }
-                const double2* vp = (const double2*)(vv + c0);    // ... + b_ra v
-#pragma unroll
-                for (int s2 = 0; s2 < S / 2; ++s2) {
-                    const double2 x = pa[s2], y = pb[s2], z = vp[s2];
-                    av[2 * s2] = x.x + br * z.x;
-                    av[2 * s2 + 1] = x.y + br * z.y;
-                    bw[2 * s2] = y.x;
-                    bw[2 * s2 + 1] = y.y;
-                }
-                core_v4d acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                for (int q = 0; q < S; ++q) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q], bw[q], acc, 0, 0, 0);
-                if (!defer) {
-                    for (int r = 0; r < 4; ++r) {
-                        const int row = r0 + 4 * r + lq;
-                        if (row < k && jb < ldo) QU[row * ldo + jb] = (T)acc[r];
+                for (int t = wave; t < kt * jt && wave < twv; t += twv) {
+                    const int r0 = (t / jt) * 16, j0 = (t % jt) * 16;
+                    const int ra = r0 + li, jb = j0 + li;
+                    double av[S], bw[S];
+                    // operand rows past k (or past k_out) are zero in LDS
+                    const double2* pa;
+                    const double2* pb;
+                    double br = 0.0;
+                    if (!inv) {
+                        pa = (const double2*)(Wst + ra * WST + c0);   // row ra of W
+                        pb = (const double2*)(At + jb * WST + c0);    // column jb of A (row jb of A^T)
+                    } else {
+                        pa = (const double2*)(At + ra * WST + c0);    // row ra of A^-1 = A^T + b^T v ...
+                        pb = (const double2*)(Wst + jb * WST + c0);   // column jb of W^-1 (a row of its transpose)
+                        br = bv[ra];
                     }
-                } else {
-                    ISVD_GLOBAL double* out = inv ? Win : Wn;
-                    for (int r = 0; r < 4; ++r) {
-                        const int row = r0 + 4 * r + lq;
-                        if (row < k && jb < k) out[(size_t)row * KC + jb] = acc[r];
-                    }
-                    if (inv && r0 == 0) {
-                        // u0[jb] = v W^-1[:, jb]: this lane's contraction indices, then the four quarters
-                        double up = 0.0;
+                    const double2* vp = (const double2*)(vv + c0);    // ... + b_ra v
 #pragma unroll
-                        for (int q = 0; q < S; ++q) up += vv[c0 + q] * bw[q];
-                        up += __shfl_xor(up, 16);
-                        up += __shfl_xor(up, 32);
-                        if (lq == 0 && jb < ld) U0[uvo(rq.m, jb, ld)] = (T)(jb < k ? up : 0.0);
+                    for (int s2 = 0; s2 < S / 2; ++s2) {
+                        const double2 x = pa[s2], y = pb[s2], z = vp[s2];
+                        av[2 * s2] = x.x + br * z.x;
+                        av[2 * s2 + 1] = x.y + br * z.y;
+                        bw[2 * s2] = y.x;
+                        bw[2 * s2 + 1] = y.y;
+                    }
+                    core_v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                    for (int q = 0; q < S; ++q)
+                        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q], bw[q], acc, 0, 0, 0);
+                    if (!defer) {
+                        for (int r = 0; r < 4; ++r) {
+                            const int row = r0 + 4 * r + lq;
+                            if (row < k && jb < ldo) QU[row * ldo + jb] = (T)acc[r];
+                        }
+                    } else {
+                        ISVD_GLOBAL double* out = inv ? Win : Wn;
+                        for (int r = 0; r < 4; ++r) {
+                            const int row = r0 + 4 * r + lq;
+                            if (row < k && jb < k) out[(size_t)row * KC + jb] = acc[r];
+                        }
+                        if (inv && r0 == 0) {
+                            // u0[jb] = v W^-1[:, jb]: this lane's contraction indices, then the four quarters
+                            double up = 0.0;
+#pragma unroll
+                            for (int q = 0; q < S; ++q) up += vv[c0 + q] * bw[q];
+                            up += __shfl_xor(up, 16);
+                            up += __shfl_xor(up, 32);
+                            if (lq == 0 && jb < ld) U0[uvo(rq.m, jb, ld)] = (T)(jb < k ? up : 0.0);
+                        }
                     }
                 }
             }
