@@ -55,10 +55,18 @@ def svd(A, max_sweeps=60):
     return U, s, V
 
 
+# Singular values at or below RANK_TOL * sigma_1 count as zero: a matrix whose
+# spectrum ends there has that numerical rank, and TruncatedSVD(A, k) keeps
+# min(k, numerical rank) triplets (the directions past it are arbitrary at
+# FP64 rounding).  The engine's refresh uses the same threshold.
+RANK_TOL = 1e-12
+
+
 def truncated_svd(A, k):
-    """TruncatedSVD(A, k): the leading min(k, rank) triplets (sigma > 0)."""
+    """TruncatedSVD(A, k) (Sec. 2.4.1): the leading min(k, numerical rank)
+    triplets, sigma > RANK_TOL * sigma_1."""
     U, s, V = svd(A)
-    r = int(min(k, np.count_nonzero(s > 0.0)))
+    r = int(min(k, np.count_nonzero(s > RANK_TOL * (s[0] if s.size else 0.0)))) if s.size and s[0] > 0 else 0
     return U[:, :r].copy(), s[:r].copy(), V[:, :r].copy()
 
 

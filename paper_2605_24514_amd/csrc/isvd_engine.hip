@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <functional>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -1395,9 +1396,10 @@ struct RefreshPlan {
     WsLayout w{};
     int rounds = 0;          // Gram form: Rayleigh-Ritz rounds until the stopping rule held
     bool converged = true;   // Gram form: all k Ritz pairs met the residual tolerance
-    // Gram form: sum of the leading k Ritz values of G = A^T A (sigma^2, from
-    // exact FP64 products; E_opt^2 = ||A||^2 minus it), else NaN
-    double gram_top = std::nan("");
+    // Gram form: the leading k Ritz values of G = A^T A (sigma^2, from exact
+    // FP64 products), non-increasing; E_opt^2 = ||A||^2 minus the sum of the
+    // first (model rank) of them.  Empty in the A form.
+    std::vector<double> gram_theta;
 };
 
 // Row chunks of the Gram product: the grid (tiles x chunks) is sized to
@@ -1566,7 +1568,7 @@ isvd_status refresh_compute_gcf(isvd_engine* e, Stream& s, bool init, hipStream_
     bool converged = false;
     const double lock_tol = std::max(tol, kGcfLockTol);
     std::vector<double> locked_theta;
-    double gram_top = std::nan("");
+    std::vector<double> gram_theta;
     for (;;) {
         ++rounds;
         // Rayleigh-Ritz on the active block
@@ -1614,9 +1616,9 @@ isvd_status refresh_compute_gcf(isvd_engine* e, Stream& s, bool init, hipStream_
         int nl = 0;
         while (nl < ba && nlk + nl < k && hres[nl] <= lock_tol * th1 && hth[nl] >= kGcfBig * cut) ++nl;
         if (conv || nlk + nl >= k || rounds >= kGcfMaxRounds) {
-            gram_top = 0.0;
-            for (int i = 0; i < k - nlk; ++i) gram_top += hth[i];
-            for (double t : locked_theta) gram_top += t;
+            gram_theta.assign(locked_theta.begin(), locked_theta.end());
+            for (int i = 0; i < k - nlk; ++i) gram_theta.push_back(hth[i]);
+            std::sort(gram_theta.begin(), gram_theta.end(), std::greater<double>());
         }
         for (int i = 0; i < nl; ++i) locked_theta.push_back(hth[i]);
         if (nl > 0) {
@@ -1721,7 +1723,7 @@ isvd_status refresh_compute_gcf(isvd_engine* e, Stream& s, bool init, hipStream_
     plan->w = w;
     plan->rounds = rounds;
     plan->converged = converged;
-    plan->gram_top = gram_top;
+    plan->gram_theta = gram_theta;
     return ISVD_OK;
 }
 
@@ -1796,13 +1798,15 @@ isvd_status refresh_compute(isvd_engine* e, Stream& s, bool init, hipStream_t st
 }
 
 // Header after a refresh: the rank is the number of Ritz values above
-// 8 b eps64 sigma_1 (at least one): directions the block does not resolve
-// (A of numerical rank below k) are left out, and appends bring the rank back.
-// Also copies the Ritz values Sr into the stream's S.
-__global__ void k_commit_header(DevHeader* hdr, double* S_out, const double* S, int k, int ld, int b) {
+// kRankTol sigma_1 (at least one), the numerical rank of A when it is below
+// k: directions past it are arbitrary at FP64 rounding and are left out, and
+// appends bring the rank back.  Also copies the Ritz values Sr into the
+// stream's S.
+constexpr double kRankTol = 1e-12;
+__global__ void k_commit_header(DevHeader* hdr, double* S_out, const double* S, int k, int ld) {
     for (int j = threadIdx.x; j < k; j += blockDim.x) S_out[j] = S[j];
     if (threadIdx.x == 0) {
-        const double cut = 8.0 * b * 2.220446049250313e-16 * S[0];
+        const double cut = kRankTol * S[0];
         int kr = 1;
         while (kr < k && S[kr] > cut) ++kr;
         double s2 = 0.0;
@@ -1913,7 +1917,7 @@ isvd_status refresh_commit(isvd_engine* e, Stream& s, const RefreshPlan& plan, b
         store_ref ? (T*)s.Uref : nullptr);
     k_rotate_plain<T, 128, true><<<(int)cdiv(plan.n, 16), kThreads, 0, st>>>((T*)(ws + w.X), plan.b, (T*)s.V[nxt],
                                                                       plan.ldo, plan.n, plan.b, (T*)(ws + w.QV));
-    k_commit_header<<<1, 64, 0, st>>>(s.hdr, s.S, (const double*)(ws + w.Sr), plan.k, plan.ldo, plan.b);
+    k_commit_header<<<1, 64, 0, st>>>(s.hdr, s.S, (const double*)(ws + w.Sr), plan.k, plan.ldo);
     ST_TRY(defer_after_refresh(s, st));
     if (store_ref) {
         k_track_reset<<<1, kThreads, 0, st>>>(s.hdr, s.TM, s.TH, s.kc);
@@ -2064,13 +2068,14 @@ isvd_status exact_metrics_t(isvd_engine* e, Stream& s, hipStream_t st, Exact* ou
     HIP_TRY(hipStreamSynchronize(st));
     out->fro2 = hs[0];
     out->e_inc = std::sqrt(std::max(hs[1], 0.0));
-    // the Gram form's Ritz values come from exact FP64 products of A's
-    // entries, the A form's from products in the storage type
+    // E_opt: the best approximation of the model's rank k (at most the
+    // refresh's); the Gram form's Ritz values come from exact FP64 products
+    // of A's entries, the A form's from products in the storage type
     double top = 0.0;
-    if (std::isfinite(plan->gram_top)) {
-        top = plan->gram_top;
+    if (!plan->gram_theta.empty()) {
+        for (int q = 0; q < std::min<int>(k, (int)plan->gram_theta.size()); ++q) top += plan->gram_theta[q];
     } else {
-        for (int q = 0; q < plan->k; ++q) top += sr[q] * sr[q];
+        for (int q = 0; q < std::min(k, plan->k); ++q) top += sr[q] * sr[q];
     }
     out->e_opt = std::sqrt(std::max(hs[0] - top, 0.0));
     out->gap = out->e_inc - out->e_opt;

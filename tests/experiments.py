@@ -9,8 +9,8 @@ E1_CHECK = 250      # checkpoint spacing of the rank-1 runs
 
 def e1_stream(n_updates=10000, noise=0.0):
     """50 x 40 of rank 5 (exactly, without noise), rank-1 updates delta ~ N(0, 0.05^2).
-    E2 takes noise 0.1: with k above the numerical rank the engine keeps the
-    numerical rank while the oracle keeps arbitrary directions of sigma ~ 1e-15."""
+    E2's k-sweep takes noise 0.1, so that every k is within the numerical
+    rank; on the exact matrix a k above 5 keeps rank 5 (both sides)."""
     fs = FactorStream(seed=5, stream=0, n0=40, K=5, noise=noise)
     A0 = fs.initial(50)
     return A0, fs.materialize([ENTRY] * n_updates, m0=50, delta_std=0.05)

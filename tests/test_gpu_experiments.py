@@ -64,6 +64,17 @@ def test_e1_e2(isvd):
     print("E1 none end %.4f, refresh-1000 mean %.4f; E2 k=5/8/12 ends %s" % (none[-1], saw.mean(), np.round(ends, 4)))
 
 
+def test_e2_exact_rank_with_k_above_the_rank(isvd):
+    """E2 on the exact rank-5 matrix with k = 8 and 12: TruncatedSVD keeps the
+    numerical rank on both sides (singular values at or below 1e-12 sigma_1
+    are zero) and a rank-one update keeps the rank, so engine and oracle stay
+    at rank 5 and follow each other at every checkpoint."""
+    A0, ev = e1_stream(1000)
+    for k in (8, 12):
+        r = _run(isvd, A0, k, ev, 0, E1_CHECK)
+        print("E2 exact rank, k = %d: ratios %s" % (k, np.round(r, 4)))
+
+
 def test_e3(isvd):
     A0, ev = e3_stream()
     r = _run(isvd, A0, 4, ev, 50, 10, oversample=92)

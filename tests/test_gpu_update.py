@@ -175,6 +175,11 @@ def test_rank_deficient_input(isvd, precision, bar):
         sid2 = eng.init(A0, 5, precision=precision, m_cap=50, n_cap=30, oversample=64)
         met = eng.metrics(sid2, exact=True)
         assert met["k"] == 3, met["k"]
+        # the oracle's TruncatedSVD keeps the numerical rank as well
+        o5 = OracleEngine(A0, 5)
+        assert len(o5.s) == 3
+        c5 = compare(eng.factors(sid2), _oracle_state(o5))
+        assert c5["recon"] <= bar and c5["sigma"] <= bar, c5
         assert np.all(np.isfinite([met["frob_error"], met["ortho_U"], met["ortho_V"]]))
         assert met["frob_error"] <= 10 * bar * np.linalg.norm(A0)
         U, S, V = eng.factors(sid2)

@@ -93,3 +93,26 @@ def test_eckart_young_truncation():
         U, s, V = truncated_svd(A, k)
         err2 = np.linalg.norm(A - (U * s) @ V.T) ** 2
         assert abs(err2 - np.sum(s_all[k:] ** 2)) <= 1e-12 * np.sum(s_all ** 2)
+
+
+def test_truncated_svd_keeps_the_numerical_rank():
+    """Reading of TruncatedSVD(A, k) (Sec. 2.4.1) at FP64 rounding: singular
+    values at or below RANK_TOL sigma_1 are zero, so k above the numerical
+    rank keeps the numerical rank.  Spectra built from orthogonal factors put
+    values on both sides of the cut; a product of rank 5 keeps 5 at any k."""
+    from oracle.svd import RANK_TOL
+    rng = np.random.default_rng(21)
+    Q1, _ = np.linalg.qr(rng.standard_normal((30, 6)))
+    Q2, _ = np.linalg.qr(rng.standard_normal((20, 6)))
+    s_true = np.array([2.0, 1.0, 0.5, 2.0 * 50 * RANK_TOL, 2.0 * 0.02 * RANK_TOL, 0.0])
+    A = (Q1 * s_true) @ Q2.T
+    for k in (3, 4, 5, 6):
+        U, s, V = truncated_svd(A, k)
+        assert len(s) == min(k, 4), (k, s)
+        assert np.max(np.abs(s - s_true[:len(s)])) <= 1e-14
+    B = rng.standard_normal((50, 5)) @ rng.standard_normal((5, 40))
+    for k in (5, 8, 12):
+        U, s, V = truncated_svd(B, k)
+        assert len(s) == 5
+        assert np.linalg.norm(B - (U * s) @ V.T) <= 1e-13 * np.linalg.norm(B)
+    assert truncated_svd(np.zeros((4, 3)), 2)[1].size == 0
