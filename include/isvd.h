@@ -93,11 +93,17 @@ enum {
     ISVD_POL_ERROR = 2,     /* at t = 0 mod check_every: refresh iff frob_ratio > gamma
                                and t - t_last >= t_min (eq. error-refresh-rule) */
     ISVD_POL_ANGLE = 3,     /* refresh iff theta_ref > theta_max (Section 3.3) */
-    ISVD_POL_ADAPTIVE = 4   /* EVR / novelty rank rule + periodic refresh (Section 3.4):
+    ISVD_POL_ADAPTIVE = 4,  /* EVR / novelty rank rule + periodic refresh (Section 3.4):
                                grow by one on the next append when EVR < tau - band or
                                the append had rho / ||x|| > eta; otherwise shrink by one
                                when EVR without the last triplet >= tau + band; rank in
                                [max(k_min, 1), k_max] */
+    ISVD_POL_DRIFT = 5      /* drift surrogate without A (Sections 3.2-3.3): refresh once the
+                               step angles of U accumulated since the last refresh exceed
+                               theta_max and t - t_last >= t_min.  The largest principal
+                               angle satisfies the triangle inequality, so the sum bounds
+                               the angle between the span at the last refresh (zero-padded)
+                               and the current one, as long as the rank does not change */
 };
 
 typedef struct {
@@ -105,9 +111,9 @@ typedef struct {
     int32_t angle_scope;    /* columns the angle is measured on; 0 = leading gap-separated */
     int64_t period;         /* PERIODIC / ADAPTIVE refresh period (0 = none) */
     int64_t check_every;    /* ERROR: evaluation cadence */
-    int64_t t_min;          /* ERROR / ANGLE: minimum spacing between refreshes */
+    int64_t t_min;          /* ERROR / ANGLE / DRIFT: minimum spacing between refreshes */
     double gamma;           /* ERROR threshold on frob_ratio */
-    double theta_max;       /* ANGLE threshold, radians */
+    double theta_max;       /* ANGLE / DRIFT threshold, radians */
     double tau, band, eta;  /* ADAPTIVE: EVR target, hysteresis band, novelty threshold */
     int32_t k_min, k_max;   /* ADAPTIVE rank bounds (k_max also sizes the buffers) */
 } isvd_policy;
@@ -125,8 +131,12 @@ typedef struct {
     int32_t oversample;     /* refresh block size = min(n, k + oversample) (-1 = default) */
     isvd_policy policy;
     double refresh_tol;     /* Gram-form stopping rule: Ritz residual ||G v - theta v|| <= refresh_tol
-                               * theta_1 for the leading k pairs, G = A^T A (0 = 2e-14 FP64, 1e-10
-                               otherwise) */
+                               * theta_1 for the leading k pairs, G = A^T A (0 = 1e-16 FP64, i.e.
+                               until the residuals stop falling at rounding level; 1e-10 otherwise) */
+    int32_t a_on_host;      /* 1: the stored matrix A lives in pinned host memory mapped into the
+                               device's address space, not in HBM; updates write it and refreshes
+                               and exact metrics read it over the host link (for streams whose
+                               refreshes are rare, e.g. under ISVD_POL_DRIFT).  0: in HBM */
 } isvd_config;
 
 typedef struct {
@@ -141,8 +151,9 @@ typedef struct {
     double evr;             /* eq. evr */
     double rho, novelty;    /* last append: ||z|| and ||z|| / ||x|| */
     double frob_error;      /* E_inc = ||A_t - U S V^T||_F      (NaN unless compute_exact) */
-    double frob_opt;        /* E_opt = sqrt(N_t - sum of the refresh's k leading Ritz values sigma^2) (NaN
-                               unless compute_exact) */
+    double frob_opt;        /* E_opt = sqrt(N_t - sum of the leading Ritz values sigma^2 of a
+                               refresh, as many as the model's rank): the error of the best
+                               approximation of that rank (NaN unless compute_exact) */
     double frob_gap, frob_ratio;   /* eq. frob-ratio; NaN if undefined or not computed */
     double ortho_U, ortho_V;       /* ||Q^T Q - I||_2 (NaN unless compute_exact) */
     double update_time_us;  /* wall-clock of the last immediate-mode update (host-timed) */
@@ -167,6 +178,9 @@ typedef struct {
        A form), and 1 if the stopping rule held (always 1 for the A form, whose
        iteration count is fixed). */
     int32_t refresh_rounds, refresh_converged;
+    /* Step angles of U summed since the last refresh (the ISVD_POL_DRIFT
+       quantity; NaN for streams whose policy does not track it). */
+    double drift_U;
 } isvd_metrics_t;
 
 /* One request of a batched tick. */

@@ -14,7 +14,7 @@ import numpy as np
 
 from synth.factor_model import ROW, COL, ENTRY
 from . import brand, metrics
-from .policies import Policy, NONE, PERIODIC, ERROR, ANGLE, ADAPTIVE
+from .policies import Policy, NONE, PERIODIC, ERROR, ANGLE, ADAPTIVE, DRIFT
 from .svd import truncated_svd, singular_values
 
 
@@ -38,8 +38,10 @@ class OracleEngine:
         self._init_drift(drift)
 
     def _init_drift(self, drift):
-        # drift signals of the last update (Sections 3.2-3.3), formed when asked for
-        self.drift = bool(drift)
+        # drift signals of the last update (Sections 3.2-3.3), formed when asked
+        # for or when the policy adds them up
+        self.drift = bool(drift) or self.policy.kind == DRIFT
+        self.drift_acc = 0.0
         self.last_step_angle_U = self.last_step_angle_V = float("nan")
         self.last_spectrum_change = float("nan")
 
@@ -76,6 +78,7 @@ class OracleEngine:
             self.U_ref = self.U.copy()
         self.t_last = self.t
         self.n_refresh += 1
+        self.drift_acc = 0.0
 
     # ---------------------------------------------------------------- update
     def _k_keep(self):
@@ -137,6 +140,10 @@ class OracleEngine:
             if t - self.t_last < max(p.t_min, 1):
                 return False
             return bool(self.angle_ref(p.angle_scope) > p.theta_max)
+        if p.kind == DRIFT:
+            if np.isfinite(self.last_step_angle_U):
+                self.drift_acc += self.last_step_angle_U
+            return t - self.t_last >= max(p.t_min, 1) and self.drift_acc > p.theta_max
         if p.kind == ADAPTIVE:
             s2 = float(np.dot(self.s, self.s))
             low = s2 / self.N < p.tau - p.band

@@ -21,10 +21,18 @@
   last triplet at once) when the model without its last triplet still
   explains >= tau + b.  Rank stays in [k_min, k_max]; a periodic refresh
   every ``period`` ticks runs at the current rank.
+* Drift surrogate (Sections 3.2-3.3; the paper names the angle between
+  successive subspaces as a cheap trigger but gives no rule): add up the
+  step angle of U (the largest principal angle between span(U_{t-1}),
+  zero-padded to the new rows, and span(U_t)) after every update and
+  refresh iff the sum since the last refresh exceeds theta_max and
+  t - t_last >= t_min.  The largest principal angle is a metric on subspaces
+  of one dimension, so while the rank holds the sum bounds the angle between
+  the span at the last refresh and the current one; no A is read.
 """
 from dataclasses import dataclass
 
-NONE, PERIODIC, ERROR, ANGLE, ADAPTIVE = 0, 1, 2, 3, 4
+NONE, PERIODIC, ERROR, ANGLE, ADAPTIVE, DRIFT = 0, 1, 2, 3, 4, 5
 
 
 @dataclass
@@ -54,6 +62,10 @@ class Policy:
     @staticmethod
     def angle(theta_max=1e-3, scope=0, t_min=1):
         return Policy(kind=ANGLE, theta_max=theta_max, angle_scope=scope, t_min=t_min)
+
+    @staticmethod
+    def drift(theta_max=1e-2, t_min=1):
+        return Policy(kind=DRIFT, theta_max=theta_max, t_min=t_min)
 
     @staticmethod
     def adaptive(tau=0.95, band=0.01, eta=0.5, k_min=1, k_max=0, period=500):

@@ -87,6 +87,7 @@ int bucket_for(int kmax) {
 // ------------------------------------------------------------------ streams
 struct Layout {
     size_t hdr, rs, S, p, partials, partials2, QU, QV, stage, U0, U1, V0, V1, Uref, TM, TH, TP, TS, Jg, A, total;
+    size_t a_bytes = 0;      // A's bytes; with a_on_host, outside `total` (the device allocation)
     size_t rs_b, p_b, q_b;   // bytes of one copy of the double-buffered rs, p and QU / QV
 };
 
@@ -147,6 +148,8 @@ struct Stream {
     double last_ratio = 0.0;     // error policy: frob_ratio at its last check
     int refresh_rounds = 0;      // last refresh: Gram-form rounds (0: A form)
     bool refresh_converged = true;
+    double drift_acc = 0.0;      // drift policy: step angles of U since the last refresh
+    void* a_host = nullptr;      // A in pinned host memory (a_on_host)
 };
 
 // Leading dimension of A: n_cap rounded up to a multiple of 4, so that rows
@@ -189,6 +192,8 @@ Layout make_layout(const isvd_config& c, int esz, int kc, int64_t* ntiles_max) {
     L.Jg = take(esz == 8 ? sizeof(double) * core_jg_doubles(kc) : 0);
     L.A = take((size_t)esz * c.m_cap * lda_of(c));
     L.total = off;
+    L.a_bytes = L.total - L.A;
+    if (c.a_on_host) L.total = L.A;
     return L;
 }
 
@@ -1962,6 +1967,7 @@ isvd_status do_refresh(isvd_engine* e, Stream& s, bool init, bool store_ref, hip
         s.n_refresh += 1;
         s.t_last = s.t;
     }
+    s.drift_acc = 0.0;
     return ISVD_OK;
 }
 
@@ -2102,7 +2108,8 @@ isvd_status read_header(Stream& s, hipStream_t st, DevHeader* h) {
 }
 
 bool policy_needs_header(const Stream& s) {
-    return s.cfg.policy.kind == ISVD_POL_ADAPTIVE || s.cfg.policy.kind == ISVD_POL_ANGLE;
+    return s.cfg.policy.kind == ISVD_POL_ADAPTIVE || s.cfg.policy.kind == ISVD_POL_ANGLE ||
+           s.cfg.policy.kind == ISVD_POL_DRIFT;
 }
 
 // Policy evaluation after the update at tick t (Algorithm 1; Section 3).
@@ -2138,6 +2145,17 @@ isvd_status after_update(isvd_engine* e, Stream& s, hipStream_t st, const DevHea
         ST_TRY(exact_metrics(e, s, st, &ex, &plan, false));
         s.last_ratio = ex.ratio;
         if (ex.ratio > p.gamma) return do_refresh(e, s, false, true, st, &plan);
+        return ISVD_OK;
+    }
+    if (p.kind == ISVD_POL_DRIFT) {
+        // the step angle of U of the update just applied, from the header
+        DevHeader hh;
+        if (!h) {
+            ST_TRY(read_header(s, st, &hh));
+            h = &hh;
+        }
+        if (std::isfinite(h->step_angle_u)) s.drift_acc += h->step_angle_u;
+        if (s.t - s.t_last >= std::max<int64_t>(p.t_min, 1) && s.drift_acc > p.theta_max) return refresh();
         return ISVD_OK;
     }
     if (p.kind == ISVD_POL_ANGLE) {
@@ -2395,6 +2413,8 @@ void free_stream(isvd_engine* e, Stream* s) {
     if (s->ev_ready) (void)hipEventDestroy(s->ev_ready);
     if (s->wbuf) (void)hipFree(s->wbuf);
     s->wbuf = nullptr;
+    if (s->a_host) (void)hipHostFree(s->a_host);
+    s->a_host = nullptr;
     s->base = nullptr;
     s->live = false;
 }
@@ -2408,7 +2428,7 @@ isvd_status validate_cfg(const isvd_config* c) {
     int kmax = std::max(c->k, c->policy.k_max);
     if (c->k < 1 || c->k > std::min<int64_t>(c->m0, c->n0) || kmax > kMaxRank)
         return fail(ISVD_E_INVAL, "k = %d outside [1, min(m0, n0, %d)]", c->k, kMaxRank);
-    if (c->policy.kind < ISVD_POL_NONE || c->policy.kind > ISVD_POL_ADAPTIVE)
+    if (c->policy.kind < ISVD_POL_NONE || c->policy.kind > ISVD_POL_DRIFT)
         return fail(ISVD_E_INVAL, "bad policy kind %d", c->policy.kind);
     if (c->policy.kind == ISVD_POL_ANGLE && c->policy.angle_scope < 0)
         return fail(ISVD_E_INVAL, "negative angle scope");
@@ -2817,7 +2837,24 @@ static isvd_status init_common(isvd_engine* e, const isvd_config* cfg, const voi
         s->TS = (double*)(b + s->L.TS);
     }
     if (core_jg_doubles(s->kc) > 0 && s->esz == 8) s->Jg = (double*)(b + s->L.Jg);
-    s->A = b + s->L.A;
+    if (cfg->a_on_host) {
+        if (hipHostMalloc(&s->a_host, s->L.a_bytes, hipHostMallocDefault) != hipSuccess) {
+            s->a_host = nullptr;
+            free_stream(e, s);
+            delete s;
+            return fail(ISVD_E_NOMEM, "pinned host A of %zu bytes", s->L.a_bytes);
+        }
+        std::memset(s->a_host, 0, s->L.a_bytes);
+        void* dptr = nullptr;
+        if (hipHostGetDevicePointer(&dptr, s->a_host, 0) != hipSuccess) {
+            free_stream(e, s);
+            delete s;
+            return fail(ISVD_E_DEVICE, "device view of the host A");
+        }
+        s->A = (char*)dptr;
+    } else {
+        s->A = b + s->L.A;
+    }
     s->live = true;
     e->streams.push_back(s);
     const isvd_id id = (isvd_id)e->streams.size() - 1;
@@ -2837,7 +2874,7 @@ static isvd_status init_common(isvd_engine* e, const isvd_config* cfg, const voi
     // A is zeroed whole: entries outside the current m x n stay zero (the
     // refresh products read the padding columns of a row)
     if (hipMemsetAsync(s->base, 0, s->L.U0, st) != hipSuccess ||
-        hipMemsetAsync(s->A, 0, s->L.total - s->L.A, st) != hipSuccess ||
+        (!cfg->a_on_host && hipMemsetAsync(s->A, 0, s->L.a_bytes, st) != hipSuccess) ||
         hipMemcpyAsync(s->hdr, &h0, sizeof(h0), hipMemcpyHostToDevice, st) != hipSuccess)
         return bail(fail(ISVD_E_DEVICE, "header initialisation failed"));
     // A_0 into A (leading dimension lda_of), converting to the storage type
@@ -3027,6 +3064,7 @@ isvd_status isvd_metrics(isvd_engine* e, isvd_id id, int32_t compute_exact, void
     m.spectrum_change = h.t > 0 ? h.spec_change : nan;
     m.refresh_rounds = s->refresh_rounds;
     m.refresh_converged = s->refresh_converged ? 1 : 0;
+    m.drift_U = s->cfg.policy.kind == ISVD_POL_DRIFT ? s->drift_acc : nan;
     m.frob_error = m.frob_opt = m.frob_gap = m.frob_ratio = nan;
     m.ortho_U = m.ortho_V = nan;
     m.angle_ref = s->angle ? h.angle_ref : nan;

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libisvd.so")
 ISVD_FP64, ISVD_FP32, ISVD_BF16ROT = 0, 1, 2
 DTYPE_F32, DTYPE_F64 = 0, 1
 ROW, COL, ENTRY = 0, 1, 2
-POL_NONE, POL_PERIODIC, POL_ERROR, POL_ANGLE, POL_ADAPTIVE = 0, 1, 2, 3, 4
+POL_NONE, POL_PERIODIC, POL_ERROR, POL_ANGLE, POL_ADAPTIVE, POL_DRIFT = 0, 1, 2, 3, 4, 5
 
 STATUS = {0: "OK", -1: "E_INVAL", -2: "E_SHAPE", -3: "E_RANGE", -4: "E_NONFINITE", -5: "E_NOMEM",
           -6: "E_BUDGET", -7: "E_DEVICE", -8: "E_STATE", -9: "E_CONVERGE", -10: "E_CAPACITY"}
@@ -41,7 +41,8 @@ class CConfig(ctypes.Structure):
     _fields_ = [("m0", ctypes.c_int64), ("n0", ctypes.c_int64), ("m_cap", ctypes.c_int64),
                 ("n_cap", ctypes.c_int64), ("k", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("tol_rel", ctypes.c_double), ("refresh_iters", ctypes.c_int32),
-                ("oversample", ctypes.c_int32), ("policy", CPolicy), ("refresh_tol", ctypes.c_double)]
+                ("oversample", ctypes.c_int32), ("policy", CPolicy), ("refresh_tol", ctypes.c_double),
+                ("a_on_host", ctypes.c_int32)]
 
 
 class CMetrics(ctypes.Structure):
@@ -53,7 +54,7 @@ class CMetrics(ctypes.Structure):
                                        "frob_opt", "frob_gap", "frob_ratio", "ortho_U", "ortho_V",
                                        "update_time_us", "opt_time_us", "angle_ref", "step_angle_U",
                                        "step_angle_V", "spectrum_change")] + [
-        ("refresh_rounds", ctypes.c_int32), ("refresh_converged", ctypes.c_int32)]
+        ("refresh_rounds", ctypes.c_int32), ("refresh_converged", ctypes.c_int32), ("drift_U", ctypes.c_double)]
 
 
 class CRequest(ctypes.Structure):
@@ -275,17 +276,17 @@ class Engine:
 
     @staticmethod
     def config(m0, n0, k, precision="fp32", m_cap=None, n_cap=None, tol_rel=0.0, policy=None,
-               refresh_iters=-1, oversample=-1, refresh_tol=0.0):
+               refresh_iters=-1, oversample=-1, refresh_tol=0.0, a_on_host=False):
         prec = {"fp32": ISVD_FP32, "fp64": ISVD_FP64, "bf16rot": ISVD_BF16ROT}[precision]
         pol = (policy or Policy()).to_c()
         return CConfig(m0, n0, m_cap or m0, n_cap or n0, k, prec, tol_rel, refresh_iters, oversample, pol,
-                       refresh_tol)
+                       refresh_tol, 1 if a_on_host else 0)
 
     def stream_bytes(self, cfg):
         return int(self._lib.isvd_stream_bytes(ctypes.byref(cfg)))
 
     def init(self, A0, k, precision="fp32", m_cap=None, n_cap=None, tol_rel=0.0, policy=None,
-             refresh_iters=-1, oversample=-1, stream=None, refresh_tol=0.0):
+             refresh_iters=-1, oversample=-1, stream=None, refresh_tol=0.0, a_on_host=False):
         if hasattr(A0, "data_ptr"):
             m0, n0 = A0.shape
             ptr, _, code, dev, keep = _payload(A0)
@@ -296,7 +297,7 @@ class Engine:
             ptr, _, code, dev, keep = _payload(a)
             lda = n0
         cfg = self.config(m0, n0, k, precision, m_cap, n_cap, tol_rel, policy, refresh_iters, oversample,
-                          refresh_tol)
+                          refresh_tol, a_on_host)
         sid = ctypes.c_int64()
         self._check(self._lib.isvd_init(self._h, ctypes.byref(cfg), ptr, lda, code, dev, _stream_ptr(stream),
                                         ctypes.byref(sid)), "isvd_init")

@@ -98,3 +98,61 @@ def test_drift_off_leaves_nan():
     o = OracleEngine(np.eye(3), 2)
     o.apply(_Ev(ROW, np.ones(3)))
     assert np.isnan(o.last_step_angle_U) and np.isnan(o.last_spectrum_change)
+
+
+def test_drift_sum_bounds_the_angle_from_the_last_refresh():
+    """The drift policy's quantity (Sections 3.2-3.3 surrogate): the step
+    angles of U added up since the last refresh bound, by the triangle
+    inequality of the largest principal angle, the angle between the span
+    stored at the last refresh (zero-padded) and the current one, at every
+    update of a mixed row / column run whose rank stays k."""
+    from oracle import metrics
+    from oracle.policies import Policy
+    from synth import FactorStream
+    fs = FactorStream(seed=41, stream=0, n0=30, K=5)
+    A0 = fs.initial(120)
+    events = fs.materialize([ROW, ROW, COL, ROW] * 12, m0=120)
+    o = OracleEngine(A0, 6, policy=Policy.drift(theta_max=1e9), cgs2=True)
+    U_ref = o.U.copy()
+    worst = 0.0
+    for ev in events:
+        o.step(ev)
+        assert len(o.s) == 6
+        theta = metrics.theta_max(U_ref, o.U)
+        assert theta <= o.drift_acc + 1e-12, (ev.t, theta, o.drift_acc)
+        worst = max(worst, theta / o.drift_acc)
+    assert o.n_refresh == 0 and 0.0 < worst <= 1.0
+
+
+def test_drift_policy_refreshes_where_the_sum_crosses():
+    """Refresh after the update at which the running sum of step angles first
+    exceeds theta_max (spacing t_min); the sum restarts after each refresh,
+    and a refresh restores TruncatedSVD(A_t, k)."""
+    from oracle.policies import Policy
+    from oracle.svd import truncated_svd
+    from synth import FactorStream
+    fs = FactorStream(seed=43, stream=0, n0=25, K=4)
+    A0 = fs.initial(80)
+    kinds = [ROW, COL, ROW, ENTRY] * 15
+    events = fs.materialize(kinds, m0=80)
+    probe = OracleEngine(A0, 5, drift=True, cgs2=True)
+    steps = []
+    for ev in events:
+        probe.step(ev)
+        steps.append(probe.last_step_angle_U)
+    theta_max = 0.5 * sum(steps[:20])
+    o = OracleEngine(A0, 5, policy=Policy.drift(theta_max=theta_max, t_min=3), cgs2=True)
+    want = []
+    for ev in events:
+        fired = o.step(ev)
+        assert o.last_step_angle_U >= 0.0
+        if fired:
+            want.append(ev.t)
+            U, s, V = truncated_svd(o.A, 5)
+            assert np.allclose(np.abs(o.s), s, rtol=0, atol=1e-12 * s[0])
+            assert o.drift_acc == 0.0
+    # the first refresh is the first tick whose running sum (same run until
+    # then) exceeds theta_max
+    first = next(i for i in range(len(steps)) if sum(steps[:i + 1]) > theta_max) + 1
+    assert want and want[0] == max(first, 3), (want, first)
+    assert all(b - a >= 3 for a, b in zip(want, want[1:]))
