@@ -181,6 +181,11 @@ typedef struct {
     /* Step angles of U summed since the last refresh (the ISVD_POL_DRIFT
        quantity; NaN for streams whose policy does not track it). */
     double drift_U;
+    /* theta_opt, radians: largest principal angle between span(U_t) and the
+       span of the leading (model rank) left singular vectors of A_t (the
+       angle metric to the optimal subspace, Section 3.3), from the refresh
+       the exact metrics compute (NaN unless compute_exact). */
+    double angle_opt;
 } isvd_metrics_t;
 
 /* One request of a batched tick. */

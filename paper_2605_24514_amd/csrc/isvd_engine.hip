@@ -1990,6 +1990,7 @@ isvd_status ensure_mws(isvd_engine* e, size_t bytes) {
 
 struct Exact {
     double fro2 = 0, e_inc = 0, e_opt = 0, gap = 0, ratio = 0, ortho_u = 0, ortho_v = 0;
+    double angle_opt = std::nan("");
 };
 
 // out = sum of P[0:n]: thread t adds a contiguous range in order, the ranges'
@@ -2091,6 +2092,38 @@ isvd_status exact_metrics_t(isvd_engine* e, Stream& s, hipStream_t st, Exact* ou
     if (sweeps[0] < 0 || sweeps[1] < 0) return fail(ISVD_E_CONVERGE, "orthogonality norm did not converge");
     out->ortho_u = hs[2];
     out->ortho_v = hs[3];
+    if (ortho && k > 0) {
+        // theta_opt (the angle metric to the optimal subspace): the largest
+        // principal angle between span(U_t) and the leading min(k, k_refresh)
+        // left singular vectors of A_t, U_opt = Q_Y W from the refresh just
+        // computed: M = W^T (Q_Y^T U_t), H = U_t^T U_t, theta from M and H as
+        // for theta_ref (on all of U_opt's columns)
+        const int b = plan->b, kq = std::min(k, plan->k);
+        const int64_t chunk = 1024, nch = std::max<int64_t>(1, cdiv(m, chunk));
+        const size_t need2 = sizeof(double) * (size_t)(nch * ((size_t)b * k + (size_t)k * k) + (size_t)b * k +
+                                                       2 * (size_t)k * k + 16);
+        ST_TRY(ensure_mws(e, need2));
+        double* pp = (double*)e->mws;
+        double* hp = pp + nch * b * k;
+        double* Pd = hp + nch * k * k;
+        double* Md = Pd + (size_t)b * k;
+        double* Hd = Md + (size_t)kq * k;
+        double* thd = Hd + (size_t)k * k;
+        double* Rg = thd + 8;
+        const T* Yq = (const T*)(e->ws.p + plan->w.Y);
+        k_cross_partial<T, true><<<(int)nch, kThreads, 0, st>>>(Yq, b, b, U, ld, k, m, chunk, pp);
+        k_cross_partial<T><<<(int)nch, kThreads, 0, st>>>(U, ld, k, U, ld, k, m, chunk, hp);
+        k_sum_parts<double><<<(int)cdiv((int64_t)b * k, 256), 256, 0, st>>>(pp, (int)nch, (int64_t)b * k,
+                                                                          (int64_t)b * k, Pd);
+        k_sum_parts<double><<<(int)cdiv((int64_t)k * k, 256), 256, 0, st>>>(hp, (int)nch, (int64_t)k * k,
+                                                                          (int64_t)k * k, Hd);
+        k_tn_small<T><<<1, kThreads, 0, st>>>((const T*)(e->ws.p + plan->w.QU), plan->ldo, b, kq, Pd, k, Md);
+        k_theta_direct<<<1, WideShape::NT, sizeof(double) * theta_lds_doubles(), st>>>(Md, Hd, k, kq, s.S, k, thd,
+                                                                                       Rg);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(&out->angle_opt, thd, sizeof(double), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+    }
     return ISVD_OK;
 }
 
@@ -3067,6 +3100,7 @@ isvd_status isvd_metrics(isvd_engine* e, isvd_id id, int32_t compute_exact, void
     m.drift_U = s->cfg.policy.kind == ISVD_POL_DRIFT ? s->drift_acc : nan;
     m.frob_error = m.frob_opt = m.frob_gap = m.frob_ratio = nan;
     m.ortho_U = m.ortho_V = nan;
+    m.angle_opt = nan;
     m.angle_ref = s->angle ? h.angle_ref : nan;
     m.update_time_us = nan;
     m.opt_time_us = nan;
@@ -3083,6 +3117,7 @@ isvd_status isvd_metrics(isvd_engine* e, isvd_id id, int32_t compute_exact, void
         m.frob_ratio = ex.ratio;
         m.ortho_U = ex.ortho_u;
         m.ortho_V = ex.ortho_v;
+        m.angle_opt = ex.angle_opt;
         ST_TRY(direct_trackers(e, *s, st, &m.angle_ref, nullptr, nullptr, 0));
     }
     *out = m;

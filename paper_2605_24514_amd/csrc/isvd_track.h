@@ -312,8 +312,8 @@ __global__ void __launch_bounds__(WideShape::NT) k_theta_direct(const double* M,
 }
 
 // Gp[chunk] = X[rows of chunk]^T Y[rows of chunk]  (kx x ky, FP64, row stride ky);
-// X and Y in the tiled basis layout
-template <typename T>
+// Y in the tiled basis layout, X too or (XROW) row-major with row stride ldx
+template <typename T, bool XROW = false>
 __global__ void __launch_bounds__(kThreads) k_cross_partial(const T* __restrict__ X, int ldx, int kx,
                                                             const T* __restrict__ Y, int ldy, int ky, int64_t rows,
                                                             int64_t chunk_rows, double* __restrict__ Gp) {
@@ -329,7 +329,7 @@ __global__ void __launch_bounds__(kThreads) k_cross_partial(const T* __restrict_
         for (int e = threadIdx.x; e < 16 * kMaxBlock; e += kThreads) {
             const int rr = e / kMaxBlock, c = e % kMaxBlock;
             const int64_t r = r0 + rr;
-            sX[rr][c] = (r < rb && c < kx) ? (double)X[uvo(r, c, ldx)] : 0.0;
+            sX[rr][c] = (r < rb && c < kx) ? (double)X[XROW ? r * ldx + c : uvo(r, c, ldx)] : 0.0;
             sY[rr][c] = (r < rb && c < ky) ? (double)Y[uvo(r, c, ldy)] : 0.0;
         }
         __syncthreads();
@@ -350,6 +350,19 @@ __global__ void __launch_bounds__(kThreads) k_cross_partial(const T* __restrict_
     for (int q = 0; q < kMaxBlock * kMaxBlock / kThreads; ++q) {
         const int e = threadIdx.x + q * kThreads;
         if (e < nout) out[e] = acc[q];
+    }
+}
+
+// C = Q[:, 0:kq]^T P  (kq x ky, row stride ky): Q b x kq in the storage type
+// (row stride ldq), P b x ky FP64 (row stride ky); one block
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_tn_small(const T* __restrict__ Q, int ldq, int b, int kq,
+                                                       const double* __restrict__ P, int ky, double* __restrict__ C) {
+    for (int e = threadIdx.x; e < kq * ky; e += kThreads) {
+        const int i = e / ky, c = e % ky;
+        double s = 0.0;
+        for (int r = 0; r < b; ++r) s += (double)Q[r * ldq + i] * P[r * ky + c];
+        C[e] = s;
     }
 }
 

@@ -54,7 +54,7 @@ class CMetrics(ctypes.Structure):
                                        "frob_opt", "frob_gap", "frob_ratio", "ortho_U", "ortho_V",
                                        "update_time_us", "opt_time_us", "angle_ref", "step_angle_U",
                                        "step_angle_V", "spectrum_change")] + [
-        ("refresh_rounds", ctypes.c_int32), ("refresh_converged", ctypes.c_int32), ("drift_U", ctypes.c_double)]
+        ("refresh_rounds", ctypes.c_int32), ("refresh_converged", ctypes.c_int32), ("drift_U", ctypes.c_double), ("angle_opt", ctypes.c_double)]
 
 
 class CRequest(ctypes.Structure):
