@@ -407,6 +407,63 @@ def sweep_main(args):
 C1_SEED = 1
 
 
+def c0_main(args):
+    """The 500 x 50 FP64 stream (5 factors, seed 0): 1000 row appends and 200
+    rank-1 updates in the seeded interleaving, k = 10, periodic refresh every
+    200 updates (six refreshes).  Per-update latency of the immediate-mode
+    calls (one synchronised update at a time) against the same updates sent
+    as one-request ticks, each form run on its own engine from A_0; prints
+    one JSON line."""
+    import torch
+    from paper_2605_24514_amd import isvd
+    from synth import FactorStream, event_schedule_c0, ROW
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    fs = FactorStream(seed=0, stream=0, n0=50, K=5)
+    A0 = fs.initial(500)
+    events = fs.materialize(event_schedule_c0(0, 0, 1000, 200), m0=500)
+    st = torch.cuda.Stream()
+    pays = [torch.tensor(ev.vec, dtype=torch.float64, device="cuda") if ev.kind == ROW else None for ev in events]
+    torch.cuda.synchronize()
+    pol = isvd.Policy(kind=isvd.POL_PERIODIC, period=200)
+    forms = {}
+    for form in ("immediate", "tick"):
+        with isvd.Engine() as eng:
+            sid = eng.init(A0, 10, "fp64", m_cap=1500, n_cap=50, oversample=64, policy=pol, stream=st)
+            st.synchronize()
+            lat, refresh_lat = [], []
+            w0 = time.perf_counter()
+            for ev, pay in zip(events, pays):
+                a = time.perf_counter()
+                if form == "immediate":
+                    if ev.kind == ROW:
+                        eng.append_row(sid, pay, stream=st)
+                    else:
+                        eng.update_entry(sid, ev.i, ev.j, ev.delta, stream=st)
+                else:
+                    if ev.kind == ROW:
+                        eng.tick([(sid, isvd.ROW, pay)], stream=st)
+                    else:
+                        eng.tick([(sid, isvd.ENTRY, (ev.i, ev.j, ev.delta))], stream=st)
+                st.synchronize()
+                (refresh_lat if ev.t % 200 == 0 else lat).append((time.perf_counter() - a) * 1e3)
+            wall = time.perf_counter() - w0
+            met = eng.metrics(sid, stream=st)
+            forms[form] = {"updates_per_s": round(len(events) / wall, 1), "p50_update_ms": round(pctl(lat, 50), 4),
+                           "p99_update_ms": round(pctl(lat, 99), 4),
+                           "refresh_tick_ms_mean": round(float(np.mean(refresh_lat)), 3),
+                           "refreshes": int(met["n_refresh"])}
+        log("C0 %s: %s" % (form, forms[form]))
+    out = {"metric": "per-update latency of one FP64 stream, immediate calls against one-request ticks",
+           "value": forms["immediate"]["updates_per_s"], "unit": "updates/s", "n_gpus": 1,
+           "steps": len(events), "warmup": 0, "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "one stream, A_0 500 x 50 (5 factors, seed 0), 1000 row appends + 200 "
+                                  "rank-1 updates interleaved, k = 10, periodic refresh every 200"},
+           "forms": forms,
+           "note": "host-timed, a synchronisation after every update; parity with the oracle (<= 1e-10 at every "
+                   "25th update, A bitwise) is tests/test_gpu_update.py"}
+    print(json.dumps(out))
+
+
 def c1_main(args):
     """The single large stream at spec: A_0 100000 x 2000 (20 factors), k = 64,
     FP32 storage with the FP64 core, T i.i.d. ticks of 80 % row appends, 10 %
@@ -590,6 +647,8 @@ def main():
     ap.add_argument("--c1", action="store_true",
                     help="run the single large stream (100000 x 2000, k = 64, error-threshold refresh) instead")
     ap.add_argument("--c1-ticks", type=int, default=10000)
+    ap.add_argument("--c0", action="store_true",
+                    help="per-update latency of the 500 x 50 FP64 stream: immediate calls against one-request ticks")
     ap.add_argument("--sweep", action="store_true",
                     help="run the precision sweep (1,000,000 x 512, k = 128) instead")
     ap.add_argument("--sweep-appends", type=int, default=5000)
@@ -619,6 +678,9 @@ def main():
         return
     if args.c1 and args.gpus == 1:
         c1_main(args)
+        return
+    if args.c0 and args.gpus == 1:
+        c0_main(args)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: the streams are independent and would shard by stream across "
