@@ -185,64 +185,97 @@ def serve_main(args):
     eng = isvd.Engine()
     srv = isvd.Server(eng, hbm_budget=int(args.serve_budget_gb * 1e9), max_inflight=2, stream=dev_stream)
     log("serving: %d streams, lifetime %d, %.0f requests/s, budget %.0f GB" % (N, L, rate, args.serve_budget_gb))
-    A0s, tickets, rows_pool, cols, reqs, arrivals, owner = [], [], [], [], [], [], []
-    for s, (m0, n0, k) in enumerate(params):
-        A0 = torch.empty((m0, n0), dtype=torch.float32, device="cuda")
-        sdev.rows_into(A0, 0, m0, n0, SEED, s, K_FACTORS)
-        A0s.append(A0)
-        pk = int(pol_kind[s])
-        kk = min(k, n0)
-        tickets.append(srv.add_stream(A0, kk, m_cap=m0 + L, n_cap=n0 + L, lifetime=L, policy=policies[pk],
-                                      refresh_iters=1))
-        R = torch.empty((16, n0 + L), dtype=torch.float32, device="cuda")
-        sdev.rows_into(R, m0, 16, n0 + L, SEED, s, K_FACTORS)
-        rows_pool.append(R)
-        cols.append(torch.randn(m0 + L, dtype=torch.float32, device="cuda"))
-        kinds = rng.choice([0, 1, 2], size=L, p=[0.7, 0.15, 0.15])
-        t = np.cumsum(rng.exponential(N / rate, size=L))
-        m, n = m0, n0
-        for q in range(L):
-            r = isvd.CRequest()
-            r.kind = int(kinds[q])
-            if r.kind == isvd.ROW:
-                r.payload = ctypes.c_void_p(rows_pool[-1][q % 16].data_ptr())
-                r.len, r.dtype = n, isvd.DTYPE_F32
-                m += 1
-            elif r.kind == isvd.COL:
-                r.payload = ctypes.c_void_p(cols[-1].data_ptr())
-                r.len, r.dtype = m, isvd.DTYPE_F32
-                n += 1
-            else:
-                r.i, r.j, r.delta = int(rng.integers(m)), int(rng.integers(n)), float(rng.normal(0, 0.5))
-                r.dtype = isvd.DTYPE_F32
-            reqs.append(r)
-            arrivals.append(t[q])
-            owner.append(tickets[-1])
+    # Every stream's requests are drawn up front; its A0 (about 105 MB on
+    # average, 428 GB for 4096 streams) is generated when the stream joins the
+    # admission queue, and at most `window` streams wait in that queue with
+    # their A0 in memory.  Requests of a stream that has not joined yet are
+    # held here and submitted with their own arrival times when it joins, so
+    # the admission order is that of a server that registered every stream at
+    # once (the waits include generating A0 on the device).
+    rows_pool, cols, reqs, arrivals, owner = [], [], [], [], []
+    with torch.cuda.stream(dev_stream):
+        for s, (m0, n0, k) in enumerate(params):
+            R = torch.empty((16, n0 + L), dtype=torch.float32, device="cuda")
+            sdev.rows_into(R, m0, 16, n0 + L, SEED, s, K_FACTORS)
+            rows_pool.append(R)
+            cols.append(torch.randn(m0 + L, dtype=torch.float32, device="cuda"))
+            kinds = rng.choice([0, 1, 2], size=L, p=[0.7, 0.15, 0.15])
+            t = np.cumsum(rng.exponential(N / rate, size=L))
+            m, n = m0, n0
+            for q in range(L):
+                r = isvd.CRequest()
+                r.kind = int(kinds[q])
+                if r.kind == isvd.ROW:
+                    r.payload = ctypes.c_void_p(R[q % 16].data_ptr())
+                    r.len, r.dtype = n, isvd.DTYPE_F32
+                    m += 1
+                elif r.kind == isvd.COL:
+                    r.payload = ctypes.c_void_p(cols[-1].data_ptr())
+                    r.len, r.dtype = m, isvd.DTYPE_F32
+                    n += 1
+                else:
+                    r.i, r.j, r.delta = int(rng.integers(m)), int(rng.integers(n)), float(rng.normal(0, 0.5))
+                    r.dtype = isvd.DTYPE_F32
+                reqs.append(r)
+                arrivals.append(t[q])
+                owner.append(s)
     torch.cuda.synchronize()
     order = np.argsort(np.asarray(arrivals), kind="stable")
     arr = np.asarray(arrivals)[order]
     own = np.asarray(owner, dtype=np.int64)[order]
     creq = (isvd.CRequest * len(order))(*[reqs[i] for i in order])
+    raw = np.frombuffer(creq, dtype=np.dtype((np.void, ctypes.sizeof(isvd.CRequest))))
     total = len(order)
+    del reqs
+    ticket = np.full(N, -1, dtype=np.int64)
+    window = args.serve_window
+
+    def join(s):
+        m0, n0, k = params[s]
+        with torch.cuda.stream(dev_stream):
+            A0 = torch.empty((m0, n0), dtype=torch.float32, device="cuda")
+            sdev.rows_into(A0, 0, m0, n0, SEED, s, K_FACTORS)
+            ticket[s] = srv.add_stream(A0, min(k, n0), m_cap=m0 + L, n_cap=n0 + L, lifetime=L,
+                                       policy=policies[int(pol_kind[s])], refresh_iters=1)
+
+    def submit(idx):
+        if len(idx) == 0:
+            return
+        g = np.ascontiguousarray(raw[idx])
+        srv.submit_many(ticket[own[idx]], ctypes.cast(g.ctypes.data, ctypes.POINTER(isvd.CRequest)),
+                        arr[idx] + t_start)
+
     log("serving: %d requests prepared" % total)
     t_start = srv.clock()
-    pos, done = 0, []
+    pos, joined, done = 0, 0, []
+    held = np.zeros(0, dtype=np.int64)
     last = time.perf_counter()
     while len(done) < total:
+        grew = False
+        while joined < N and srv.held_a0() < window:
+            join(joined)
+            joined += 1
+            grew = True
+        if grew and len(held):
+            ok_now = ticket[own[held]] >= 0
+            submit(held[ok_now])
+            held = held[~ok_now]
         now = srv.clock() - t_start
         hi = int(np.searchsorted(arr, now, side="right"))
         if hi > pos:
-            sub = (isvd.CRequest * (hi - pos)).from_buffer(creq, pos * ctypes.sizeof(isvd.CRequest))
-            srv.submit_many(own[pos:hi], sub, arr[pos:hi] + t_start)
+            idx = np.arange(pos, hi)
+            ok_now = ticket[own[idx]] >= 0
+            submit(idx[ok_now])
+            held = np.concatenate([held, idx[~ok_now]])
             pos = hi
         srv.step()
         done += srv.poll()
-        if pos >= total and srv.stats()["queued"] == 0:
+        if pos >= total and len(held) == 0 and srv.stats()["queued"] == 0:
             srv.drain()
             done += srv.poll()
         if time.perf_counter() - last > 10:
             last = time.perf_counter()
-            log("  %d / %d requests done, %s" % (len(done), total, srv.stats()))
+            log("  %d / %d requests done, %d streams joined, %s" % (len(done), total, joined, srv.stats()))
     wall = srv.clock() - t_start
     ok = [c for c in done if c["status"] == 0]
     lat = np.array([c["done_s"] - c["arrival_s"] for c in ok]) * 1e3
@@ -261,6 +294,10 @@ def serve_main(args):
            "latency_ms": {"p50": round(pctl(lat, 50), 3), "p99": round(pctl(lat, 99), 3)},
            "after_admission_ms": {"p50": round(pctl(served, 50), 3), "p99": round(pctl(served, 99), 3)},
            "admission_wait_ms": {"p50": round(pctl(wait, 50), 3), "p99": round(pctl(wait, 99), 3)}}
+    st = srv.stats()
+    out["server"] = {"ticks": st["ticks"], "requests_per_tick": round(st["tick_requests"] / max(st["ticks"], 1), 1),
+                     "host_s": {"admission": round(st["host_admit_s"], 3), "tick_calls": round(st["host_tick_s"], 3),
+                                "waits": round(st["host_wait_s"], 3)}}
     print(json.dumps(out), flush=True)
     srv.close()
     eng.close()
@@ -625,7 +662,7 @@ def finance_main(args):
     print(json.dumps(out), flush=True)
 
 
-def main():
+def parse_args(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
@@ -663,7 +700,13 @@ def main():
     ap.add_argument("--serve-lifetime", type=int, default=200)
     ap.add_argument("--serve-rate", type=float, default=200000.0)
     ap.add_argument("--serve-budget-gb", type=float, default=50.0)
-    args = ap.parse_args()
+    ap.add_argument("--serve-window", type=int, default=32,
+                    help="streams waiting for admission with their A0 in memory")
+    return ap.parse_args(argv)
+
+
+def main():
+    args = parse_args()
     if args.serve and args.gpus == 1:
         serve_main(args)
         return
@@ -684,7 +727,7 @@ def main():
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: the streams are independent and would shard by stream across "
-              "GPUs with no communication; runs on %d GPUs are not part of this build" % args.gpus,
+              "GPUs with no communication; runs on %d GPUs are not implemented" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
 

@@ -509,6 +509,10 @@ typedef struct {
     int64_t queued;                        /* requests not yet launched */
     uint64_t hbm_used;                     /* footprint of the admitted streams */
     int32_t inflight_ticks, pad;
+    int64_t ticks, tick_requests;          /* ticks launched and the requests they carried */
+    double host_admit_s;                   /* host seconds in admissions (isvd_init) */
+    double host_tick_s;                    /* host seconds in isvd_tick (policy decisions included) */
+    double host_wait_s;                    /* host seconds blocked on in-flight ticks */
 } isvd_server_stats_t;
 
 /* hip_stream: the stream the server's ticks and admissions run on. */

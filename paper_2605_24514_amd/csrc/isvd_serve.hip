@@ -73,6 +73,8 @@ struct isvd_server {
     std::chrono::steady_clock::time_point t0;
     int64_t next_req = 0;
     size_t rr = 0;
+    int64_t ticks = 0, tick_requests = 0;
+    double t_admit = 0.0, t_tick = 0.0, t_wait = 0.0;
     std::string err;
 };
 
@@ -118,7 +120,9 @@ isvd_status finish_oldest(isvd_server* s, bool block, bool* finished) {
     InFlight& f = s->inflight.front();
     float ms = 0.f;
     for (hipEvent_t ev : {f.done, f.done2}) {
+        const double w0 = block ? now_s(s) : 0.0;
         hipError_t q = block ? hipEventSynchronize(ev) : hipEventQuery(ev);
+        if (block) s->t_wait += now_s(s) - w0;
         if (q == hipErrorNotReady) return ISVD_OK;
         if (q != hipSuccess) return sfail(s, ISVD_E_DEVICE, "tick completion event failed");
         float e_ms = 0.f;
@@ -250,7 +254,9 @@ isvd_status isvd_server_step(isvd_server* s, int32_t* launched) {
         Ticket& t = s->tickets[s->waiting.front()];
         if (s->cfg.hbm_budget && s->used + t.bytes > s->cfg.hbm_budget) break;
         isvd_id id = -1;
+        const double a0 = now_s(s);
         isvd_status rc = isvd_init(s->eng, &t.cfg, t.A0, t.lda, t.dtype, 1, s->st, &id);
+        s->t_admit += now_s(s) - a0;
         if (rc != ISVD_OK) return sfail(s, rc, "admission failed");
         t.id = id;
         t.state = 1;
@@ -296,7 +302,11 @@ isvd_status isvd_server_step(isvd_server* s, int32_t* launched) {
     }
     if (nt) s->rr = (s->rr + 1) % nt;
     if (batch.empty()) return ISVD_OK;
+    const double k0 = now_s(s);
     isvd_status rc = isvd_tick(s->eng, (int32_t)batch.size(), batch.data(), s->st);
+    s->t_tick += now_s(s) - k0;
+    s->ticks += 1;
+    s->tick_requests += (int64_t)batch.size();
     if (rc != ISVD_OK) {
         for (size_t q = 0; q < f.reqs.size(); ++q) {
             complete(s, f.reqs[q], f.tickets[q], rc, tnow, tnow);
@@ -355,6 +365,11 @@ isvd_status isvd_server_stats(isvd_server* s, isvd_server_stats_t* out) {
     }
     st.inflight_ticks = (int32_t)s->inflight.size();
     st.hbm_used = s->used;
+    st.ticks = s->ticks;
+    st.tick_requests = s->tick_requests;
+    st.host_admit_s = s->t_admit;
+    st.host_tick_s = s->t_tick;
+    st.host_wait_s = s->t_wait;
     *out = st;
     return ISVD_OK;
 }

@@ -5,6 +5,7 @@ this module converts numpy arrays / torch tensors into pointers and checks
 status codes.  It fails loudly if the library is missing: there is no
 fallback implementation.
 """
+import collections
 import ctypes
 import os
 from dataclasses import dataclass
@@ -76,7 +77,8 @@ class CCompletion(ctypes.Structure):
 class CServerStats(ctypes.Structure):
     _fields_ = [("waiting", ctypes.c_int64), ("admitted", ctypes.c_int64), ("retired", ctypes.c_int64),
                 ("queued", ctypes.c_int64), ("hbm_used", ctypes.c_uint64), ("inflight_ticks", ctypes.c_int32),
-                ("pad", ctypes.c_int32)]
+                ("pad", ctypes.c_int32), ("ticks", ctypes.c_int64), ("tick_requests", ctypes.c_int64),
+                ("host_admit_s", ctypes.c_double), ("host_tick_s", ctypes.c_double), ("host_wait_s", ctypes.c_double)]
 
 
 class CLaunchTime(ctypes.Structure):
@@ -520,6 +522,7 @@ class Server:
                     "isvd_server_create")
         self._h = h
         self._keep = {}
+        self._pending = collections.deque()   # tickets whose A0 is held, in admission (FIFO) order
 
     def _check(self, st, where):
         if st != 0:
@@ -542,7 +545,9 @@ class Server:
 
     def add_stream(self, A0, k, precision="fp32", m_cap=None, n_cap=None, lifetime=0, policy=None, tol_rel=0.0,
                    refresh_iters=-1, oversample=-1):
-        """A0: a device tensor kept alive by the server until the stream is admitted."""
+        """A0: a device tensor kept alive by the server until the stream is
+        admitted (admission copies it on the server's stream; allocate it on
+        that stream so that its memory is reused only after the copy)."""
         m0, n0 = A0.shape
         ptr, _, code, dev, keep = _payload(A0)
         if not dev:
@@ -552,6 +557,7 @@ class Server:
         self._check(self._lib.isvd_server_add_stream(self._h, ctypes.byref(cfg), ptr, A0.stride(0), code,
                                                      int(lifetime), ctypes.byref(t)), "isvd_server_add_stream")
         self._keep[("A0", t.value)] = keep
+        self._pending.append(t.value)
         return t.value
 
     def submit(self, ticket, kind, payload, arrival_s):
@@ -590,7 +596,14 @@ class Server:
     def step(self):
         n = ctypes.c_int32()
         self._check(self._lib.isvd_server_step(self._h, ctypes.byref(n)), "isvd_server_step")
+        # admission is FIFO: release the A0 of the admitted head of the queue
+        while self._pending and self.stream(self._pending[0])[1] != 0:
+            self._keep.pop(("A0", self._pending.popleft()), None)
         return n.value
+
+    def held_a0(self):
+        """Streams whose A0 the server still holds (not yet admitted)."""
+        return len(self._pending)
 
     def drain(self):
         self._check(self._lib.isvd_server_drain(self._h), "isvd_server_drain")
