@@ -168,6 +168,11 @@ def serve_main(args):
     """Serving run: streams of the batched workload's sizes arrive as requests
     (Poisson, mixed row / column / entry updates, per-stream policies) and are
     admitted under an HBM budget; prints one JSON line."""
+    print(json.dumps(serve_run(args)), flush=True)
+
+
+def serve_run(args):
+    """The serving run of serve_main; returns its record."""
     import torch
     from paper_2605_24514_amd import isvd
     from synth import device as sdev, uniforms
@@ -247,10 +252,10 @@ def serve_main(args):
 
     log("serving: %d requests prepared" % total)
     t_start = srv.clock()
-    pos, joined, done = 0, 0, []
+    pos, joined, ndone, done = 0, 0, 0, []
     held = np.zeros(0, dtype=np.int64)
     last = time.perf_counter()
-    while len(done) < total:
+    while ndone < total:
         grew = False
         while joined < N and srv.held_a0() < window:
             join(joined)
@@ -269,18 +274,24 @@ def serve_main(args):
             held = np.concatenate([held, idx[~ok_now]])
             pos = hi
         srv.step()
-        done += srv.poll()
+        c = srv.poll_array()
+        if len(c):
+            done.append(c)
+            ndone += len(c)
         if pos >= total and len(held) == 0 and srv.stats()["queued"] == 0:
             srv.drain()
-            done += srv.poll()
+            c = srv.poll_array()
+            done.append(c)
+            ndone += len(c)
         if time.perf_counter() - last > 10:
             last = time.perf_counter()
-            log("  %d / %d requests done, %d streams joined, %s" % (len(done), total, joined, srv.stats()))
+            log("  %d / %d requests done, %d streams joined, %s" % (ndone, total, joined, srv.stats()))
     wall = srv.clock() - t_start
-    ok = [c for c in done if c["status"] == 0]
-    lat = np.array([c["done_s"] - c["arrival_s"] for c in ok]) * 1e3
-    wait = np.array([max(0.0, c["admit_s"] - c["arrival_s"]) for c in ok]) * 1e3
-    served = np.array([c["done_s"] - max(c["arrival_s"], c["admit_s"]) for c in ok]) * 1e3
+    done = np.concatenate(done)
+    ok = done[done["status"] == 0]
+    lat = (ok["done_s"] - ok["arrival_s"]) * 1e3
+    wait = np.maximum(0.0, ok["admit_s"] - ok["arrival_s"]) * 1e3
+    served = (ok["done_s"] - np.maximum(ok["arrival_s"], ok["admit_s"])) * 1e3
     out = {"metric": "serving updates/s with p50/p99 arrival-to-completion latency (mixed requests, "
                      "per-stream policies, HBM-budget admission)",
            "value": round(len(ok) / wall, 1), "unit": "updates/s", "n_gpus": 1, "higher_is_better": True,
@@ -297,10 +308,10 @@ def serve_main(args):
     st = srv.stats()
     out["server"] = {"ticks": st["ticks"], "requests_per_tick": round(st["tick_requests"] / max(st["ticks"], 1), 1),
                      "host_s": {"admission": round(st["host_admit_s"], 3), "tick_calls": round(st["host_tick_s"], 3),
-                                "waits": round(st["host_wait_s"], 3)}}
-    print(json.dumps(out), flush=True)
+                                "waits": round(st["host_wait_s"], 3), "releases": round(st["host_release_s"], 3)}}
     srv.close()
     eng.close()
+    return out
 
 
 def refresh_main(args):
@@ -700,6 +711,8 @@ def parse_args(argv=None):
     ap.add_argument("--serve-lifetime", type=int, default=200)
     ap.add_argument("--serve-rate", type=float, default=200000.0)
     ap.add_argument("--serve-budget-gb", type=float, default=50.0)
+    ap.add_argument("--serve-default", type=int, default=4096,
+                    help="streams of the serving run added to the default line (0: none)")
     ap.add_argument("--serve-window", type=int, default=32,
                     help="streams waiting for admission with their A0 in memory")
     return ap.parse_args(argv)
@@ -1048,6 +1061,16 @@ def main():
     if args.sweep_default > 0:
         # the precision sweep (1,000,000 x 512, k = 128), shortened; --sweep runs all 5000 appends
         out["precision_sweep"] = precision_sweep(args, torch, isvd, args.sweep_default)
+    if args.serve_default > 0:
+        # the serving workload at full size: 4096 streams, 200 GB, 200 k requests/s
+        torch.cuda.empty_cache()
+        sargs = argparse.Namespace(**vars(args))
+        sargs.serve_streams, sargs.serve_budget_gb, sargs.serve_rate = args.serve_default, 200.0, 200000.0
+        sargs.serve_lifetime = 200
+        srec = serve_run(sargs)
+        out["serving"] = {q: srec[q] for q in ("metric", "value", "unit", "config", "requests", "completed_ok",
+                                               "wall_s", "latency_ms", "after_admission_ms", "admission_wait_ms",
+                                               "server")}
     print(json.dumps(out), flush=True)
 
 

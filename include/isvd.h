@@ -402,6 +402,16 @@ isvd_status isvd_set_pipelining(isvd_engine* eng, int32_t enable);
  * are cached; other ticks run as before.  Disabling frees the cache. */
 isvd_status isvd_set_tick_graphs(isvd_engine* eng, int32_t enable);
 
+/* Segmented refresh batches (on by default): the refreshes that the
+ * policies of one tick fire (Sec. 3: periodic, angle, adaptive rank; the
+ * TruncatedSVD of Sec. 2.4.1), for FP32 streams whose refresh runs in the A
+ * form (a block spanning all columns, or refresh_iters >= 0), are computed
+ * together: one launch per refresh phase covers all of them, each stream's
+ * workspace in its own region of one engine buffer.  Every stream's result
+ * is bit for bit that of its own refresh.  enable = 0 refreshes them one by
+ * one on the refresh lanes.  Errors: INVAL. */
+isvd_status isvd_set_segmented_refresh(isvd_engine* eng, int32_t enable);
+
 /* Deferred U (Brand's factorised update of the left basis, U = U0 W, W a
  * k x k FP64 matrix kept with W^-1): enable != 0 lets row appends of
  * eligible streams (FP32 storage, rank up to 64, no angle / error / adaptive
@@ -513,6 +523,7 @@ typedef struct {
     double host_admit_s;                   /* host seconds in admissions (isvd_init) */
     double host_tick_s;                    /* host seconds in isvd_tick (policy decisions included) */
     double host_wait_s;                    /* host seconds blocked on in-flight ticks */
+    double host_release_s;                 /* host seconds releasing retired streams */
 } isvd_server_stats_t;
 
 /* hip_stream: the stream the server's ticks and admissions run on. */

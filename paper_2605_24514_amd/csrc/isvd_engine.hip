@@ -31,6 +31,7 @@
 #include "isvd_common.h"
 #include "isvd_update.h"
 #include "isvd_chain.h"
+#include "isvd_segment.h"
 #include "isvd_refresh.h"
 #include "isvd_gcf.h"
 #include "isvd_track.h"
@@ -331,6 +332,19 @@ struct isvd_engine {
     hipEvent_t ev_policies = nullptr;
     int* dsweeps = nullptr;          // device: Rayleigh-Ritz sweep count per header slot
     int* rsweeps = nullptr;          // pinned copy
+    // segmented refresh batches (isvd_set_segmented_refresh): the A-form
+    // refreshes of FP32 streams that one tick fires, one launch per phase
+    bool seg_refresh = true;
+    WsBuf seg_ws;                    // the batch's refresh workspaces, one region per stream
+    WsBuf seg_jobs;                  // device job tables of the batch's launches
+    struct SegSlot {
+        char* host = nullptr;        // pinned staging of the job tables
+        size_t bytes = 0;
+        hipEvent_t ev = nullptr;     // after the copy out of it
+        bool used = false;
+    };
+    SegSlot seg_slot[4];
+    int seg_next = 0;
     // the device headers of all live streams, one array (a slot per stream),
     // so that a tick reads them back with one copy into the pinned mirror
     DevHeader* hdr_dev = nullptr;
@@ -534,6 +548,7 @@ isvd_status set_lds_limits() {
     ST_TRY(allow_lds(k_core_chain, sizeof(double) * chain_core_lds()));
     ST_TRY(allow_lds(k_svd_small_noj<float>, sizeof(double) * svd_noj_lds_doubles()));
     ST_TRY(allow_lds(k_svd_small_noj<double>, sizeof(double) * svd_noj_lds_doubles()));
+    ST_TRY(allow_lds(k_seg_svd, sizeof(double) * svd_noj_lds_doubles()));
     ST_TRY(allow_lds(k_sym_norm2, sym_norm2_lds(kMaxBlock)));
     ST_TRY(allow_lds(k_track<float>, sizeof(double) * track_lds_doubles()));
     ST_TRY(allow_lds(k_track<double>, sizeof(double) * track_lds_doubles()));
@@ -1808,7 +1823,7 @@ isvd_status refresh_compute(isvd_engine* e, Stream& s, bool init, hipStream_t st
 // appends bring the rank back.  Also copies the Ritz values Sr into the
 // stream's S.
 constexpr double kRankTol = 1e-12;
-__global__ void k_commit_header(DevHeader* hdr, double* S_out, const double* S, int k, int ld) {
+__device__ inline void commit_header_body(DevHeader* hdr, double* S_out, const double* S, int k, int ld) {
     for (int j = threadIdx.x; j < k; j += blockDim.x) S_out[j] = S[j];
     if (threadIdx.x == 0) {
         const double cut = kRankTol * S[0];
@@ -1822,6 +1837,31 @@ __global__ void k_commit_header(DevHeader* hdr, double* S_out, const double* S, 
         hdr->sigma2 = s2;
         hdr->sigma_last = S[kr - 1];
     }
+}
+__global__ void k_commit_header(DevHeader* hdr, double* S_out, const double* S, int k, int ld) {
+    commit_header_body(hdr, S_out, S, k, ld);
+}
+
+// The commit of a segmented refresh batch, one block (256 threads) per
+// stream: the header (as k_commit_header), W and W^-1 of deferred-U streams
+// back to I (as k_defer_reset), the reference trackers of angle streams reset
+// (as k_track_reset), in that order.
+struct SjCommit {
+    DevHeader* hdr;
+    double* S_out;
+    const double* S;
+    double* W[4];
+    double* TM;
+    double* TH;
+    int k, ld, kcw, kct;
+};
+__global__ void __launch_bounds__(256) k_seg_commit(const SjCommit* __restrict__ jobs) {
+    const SjCommit a = jobs[blockIdx.x];
+    commit_header_body(a.hdr, a.S_out, a.S, a.k, a.ld);
+    __syncthreads();
+    if (a.W[0]) defer_reset_body(a.hdr, a.W[0], a.W[1], a.W[2], a.W[3], a.kcw, 0);
+    __syncthreads();
+    track_reset_body(a.hdr, a.TM, a.TH, a.kct);
 }
 
 __global__ void k_sigma_trackers(DevHeader* hdr, const double* S, int k) {
@@ -2255,6 +2295,9 @@ isvd_status ensure_refresh_lanes(isvd_engine* e) {
         HIP_TRY(hipEventCreateWithFlags(&l.ev, hipEventDisableTiming));
         l.ws.defer_free = true;
     }
+    e->seg_ws.defer_free = true;
+    e->seg_jobs.defer_free = true;
+    for (auto& q : e->seg_slot) HIP_TRY(hipEventCreateWithFlags(&q.ev, hipEventDisableTiming));
     HIP_TRY(hipEventCreateWithFlags(&e->ev_policies, hipEventDisableTiming));
     HIP_TRY(hipMalloc((void**)&e->dsweeps, sizeof(int) * kMaxLiveStreams));
     HIP_TRY(hipHostMalloc((void**)&e->rsweeps, sizeof(int) * kMaxLiveStreams, hipHostMallocDefault));
@@ -2280,9 +2323,344 @@ isvd_status init_on_lane(isvd_engine* e, Stream& s, hipStream_t st) {
     return ISVD_OK;
 }
 
-isvd_status refresh_batch(isvd_engine* e, const std::vector<Stream*>& list, hipStream_t st) {
-    const int cnt = (int)list.size();
+// ------------------------------------------------- segmented refresh batches
+// The tick-fired A-form refreshes of FP32 streams, phase by phase: each
+// phase is one launch over every stream of the batch (split by the block
+// width NB where the kernel is specialised on it), with each stream's
+// workspace in its own region of one buffer.  The per-stream steps are those
+// of refresh_compute and refresh_commit (with the reference stored), so the
+// results are bitwise theirs.
+enum SegKind { kSegStart, kSegGram, kSegGramSum, kSegChol, kSegNN, kSegTN, kSegTnSum, kSegSmall, kSegRot,
+               kSegRotTiled, kSegSvd, kSegCommit };
+
+struct SegProgram {
+    struct L {
+        int kind, variant, njobs, blocks;
+        size_t jobs, begin;
+    };
+    std::vector<char> host;
+    std::vector<L> launches;
+    size_t put(const void* p, size_t bytes) {
+        const size_t o = align_up(host.size(), 16);
+        host.resize(o + bytes);
+        std::memcpy(host.data() + o, p, bytes);
+        return o;
+    }
+    template <class J>
+    void add(int kind, int variant, const std::vector<J>& jobs, const std::vector<int>& blocks) {
+        if (jobs.empty()) return;
+        std::vector<int> begin(jobs.size() + 1, 0);
+        for (size_t q = 0; q < jobs.size(); ++q) begin[q + 1] = begin[q] + blocks[q];
+        L l{kind, variant, (int)jobs.size(), begin.back(), 0, 0};
+        l.jobs = put(jobs.data(), sizeof(J) * jobs.size());
+        l.begin = put(begin.data(), sizeof(int) * begin.size());
+        launches.push_back(l);
+    }
+};
+
+struct SegRef {
+    Stream* s;
+    int k, b, ldo, cur, kw, iters;
+    bool exact;
+    int64_t m, n, lda;
+    int ld;
+    WsLayout w;
+    size_t off;
+    char* ws = nullptr;
+};
+
+// CholQR passes on the block `Y(r)` (rows(r) x b) of every ref, as cholqr()
+void seg_cholqr(SegProgram& P, std::vector<SegRef>& g, const std::function<float*(SegRef&)>& Y,
+                const std::function<int64_t(SegRef&)>& rows, int passes, bool want_R) {
+    for (int pass = 0; pass < passes; ++pass) {
+        std::vector<SjGram> gj;
+        std::vector<SjGramSum> sj;
+        std::vector<SjChol> cj;
+        std::vector<SjSmallGemm> mj;
+        std::vector<SjRot> rj;
+        std::vector<int> gb, sb, ones, rb, mb;
+        std::vector<SjNN> nj[9];
+        std::vector<int> nbk[9];
+        for (SegRef& r : g) {
+            const int64_t rw = rows(r);
+            char* ws = r.ws;
+            float* y = Y(r);
+            const int nparts = (int)gram_parts(rw);
+            gj.push_back(SjGram{y, (double*)(ws + r.w.Gp), rw, gram_rpb(rw), r.b, r.b});
+            gb.push_back(nparts);
+            sj.push_back(SjGramSum{(const double*)(ws + r.w.Gp), (double*)(ws + r.w.G), nparts, r.b});
+            sb.push_back((int)cdiv(gram_tiles(r.b) * 256, 32));
+            cj.push_back(SjChol{(const double*)(ws + r.w.G), (double*)(ws + (want_R && pass == 0 ? r.w.Racc : r.w.R)),
+                                (float*)(ws + r.w.RinvT), (int*)(ws + r.w.flag), r.b});
+            ones.push_back(1);
+            if (r.b % 4 == 0) {
+                const int nb = std::min(8, (r.b + 15) / 16);
+                nj[nb].push_back(SjNN{y, (const float*)(ws + r.w.RinvT), y, r.b, rw, r.b, r.b, r.b});
+                nbk[nb].push_back((int)cdiv(rw, 128));
+            } else {
+                rj.push_back(SjRot{y, y, (const float*)(ws + r.w.RinvT), nullptr, rw, r.b, r.b, r.b});
+                rb.push_back((int)cdiv(rw, 16));
+            }
+            if (want_R && pass == 1) {
+                mj.push_back(SjSmallGemm{(const double*)(ws + r.w.R), (const double*)(ws + r.w.Racc),
+                                         (double*)(ws + r.w.Rtmp), r.b});
+                mb.push_back((int)cdiv(r.b * r.b, 256));
+            }
+        }
+        P.add(kSegGram, 0, gj, gb);
+        P.add(kSegGramSum, 0, sj, sb);
+        P.add(kSegChol, 0, cj, ones);
+        for (int nb = 1; nb <= 8; ++nb) P.add(kSegNN, nb, nj[nb], nbk[nb]);
+        P.add(kSegRot, 0, rj, rb);
+        P.add(kSegSmall, 0, mj, mb);
+    }
+}
+
+// A X -> Y for every ref (rows m, inner n)
+void seg_ax(SegProgram& P, std::vector<SegRef>& g) {
+    std::vector<SjNN> nj[9];
+    std::vector<int> nbk[9];
+    for (SegRef& r : g) {
+        const int nb = std::min(8, (r.b + 15) / 16);
+        nj[nb].push_back(SjNN{(const float*)r.s->A, (const float*)(r.ws + r.w.X), (float*)(r.ws + r.w.Y), r.lda, r.m,
+                              r.n, r.b, r.b});
+        nbk[nb].push_back((int)cdiv(r.m, 128));
+    }
+    for (int nb = 1; nb <= 8; ++nb) P.add(kSegNN, nb, nj[nb], nbk[nb]);
+}
+
+// One group of refs sharing (exact, iters): the launches of refresh_compute<float>
+// in the A form and of refresh_commit<float> with the reference stored.
+void seg_group(isvd_engine* e, SegProgram& P, std::vector<SegRef>& g) {
+    if (g.empty()) return;
+    const bool exact = g[0].exact;
+    const int iters = g[0].iters;
+    auto X = [](SegRef& r) { return (float*)(r.ws + r.w.X); };
+    auto Y = [](SegRef& r) { return (float*)(r.ws + r.w.Y); };
+    auto nrows = [](SegRef& r) { return r.n; };
+    auto mrows = [](SegRef& r) { return r.m; };
+    {
+        std::vector<SjStart> j;
+        std::vector<int> bl;
+        for (SegRef& r : g) {
+            j.push_back(SjStart{X(r), (const float*)r.s->V[r.cur], (int*)(r.ws + r.w.flag), r.n,
+                                0x5eedull + (uint64_t)r.s->t, r.b, r.b, r.ld, r.kw, exact ? 1 : 0});
+            bl.push_back((int)cdiv(r.n * r.b, 256));
+        }
+        P.add(kSegStart, 0, j, bl);
+    }
+    if (!exact) seg_cholqr(P, g, X, nrows, iters > 0 ? 1 : 2, false);
+    for (int it = 0; it < iters; ++it) {
+        seg_ax(P, g);
+        seg_cholqr(P, g, Y, mrows, 1, false);
+        std::vector<SjTN> tj[9];
+        std::vector<int> tb[9];
+        std::vector<SjTnSum> sj;
+        std::vector<int> sb;
+        for (SegRef& r : g) {
+            const int64_t ncb = cdiv(r.n, kTnCols), nch = tn_chunks(r.m, r.n), per = ncb * kTnDump;
+            const int nb = std::min(8, (r.b + 15) / 16);
+            tj[nb].push_back(SjTN{(const float*)r.s->A, Y(r), (float*)(r.ws + r.w.Zp), r.lda, r.m, r.n,
+                                  cdiv(r.m, nch), r.b, (int)ncb});
+            tb[nb].push_back((int)(ncb * nch));
+            sj.push_back(SjTnSum{(const float*)(r.ws + r.w.Zp), X(r), per, r.n, (int)nch, r.b, r.b});
+            sb.push_back((int)cdiv(per, 256));
+        }
+        for (int nb = 1; nb <= 8; ++nb) P.add(kSegTN, nb, tj[nb], tb[nb]);
+        P.add(kSegTnSum, 0, sj, sb);
+        seg_cholqr(P, g, X, nrows, it + 1 == iters ? 2 : 1, false);
+    }
+    seg_ax(P, g);
+    seg_cholqr(P, g, Y, mrows, 2, true);
+    {
+        std::vector<SjSvd> j;
+        std::vector<int> ones;
+        for (SegRef& r : g) {
+            j.push_back(SjSvd{(const double*)(r.ws + r.w.Rtmp), (double*)(r.ws + r.w.Sr), (float*)(r.ws + r.w.QU),
+                              (float*)(r.ws + r.w.QV), e->dsweeps + r.s->slot, r.b, r.k, r.ldo});
+            ones.push_back(1);
+        }
+        P.add(kSegSvd, 0, j, ones);
+    }
+    {
+        std::vector<SjRot> j;
+        std::vector<int> bl;
+        for (SegRef& r : g) {
+            const int nxt = r.cur ^ 1;
+            j.push_back(SjRot{Y(r), (float*)r.s->U[nxt], (const float*)(r.ws + r.w.QU), (float*)r.s->Uref, r.m, r.b,
+                              r.ldo, r.b});
+            bl.push_back((int)cdiv(r.m, 16));
+            j.push_back(SjRot{X(r), (float*)r.s->V[nxt], (const float*)(r.ws + r.w.QV), nullptr, r.n, r.b, r.ldo,
+                              r.b});
+            bl.push_back((int)cdiv(r.n, 16));
+        }
+        P.add(kSegRotTiled, 0, j, bl);
+    }
+    {
+        std::vector<SjCommit> j;
+        std::vector<int> ones;
+        for (SegRef& r : g) {
+            Stream& s = *r.s;
+            SjCommit c{};
+            c.hdr = s.hdr;
+            c.S_out = s.S;
+            c.S = (const double*)(r.ws + r.w.Sr);
+            if (s.wbuf) {
+                const size_t w = (size_t)s.kc * s.kc;
+                c.W[0] = s.wbuf;
+                c.W[1] = s.wbuf + w;
+                c.W[2] = s.wbuf + 2 * w;
+                c.W[3] = s.wbuf + 3 * w;
+            }
+            c.TM = s.TM;
+            c.TH = s.TH;
+            c.k = r.k;
+            c.ld = r.ldo;
+            c.kcw = s.kc;
+            c.kct = s.kc;
+            j.push_back(c);
+            ones.push_back(1);
+        }
+        P.add(kSegCommit, 0, j, ones);
+    }
+}
+
+isvd_status seg_launch(const SegProgram::L& l, char* dev, hipStream_t st) {
+    const void* jobs = dev + l.jobs;
+    const int* begin = (const int*)(dev + l.begin);
+    const int n = l.njobs, B = l.blocks;
+    switch (l.kind) {
+        case kSegStart: k_seg_start<<<B, 256, 0, st>>>((const SjStart*)jobs, begin, n); break;
+        case kSegGram: k_seg_gram<<<B, kThreads, 0, st>>>((const SjGram*)jobs, begin, n); break;
+        case kSegGramSum: k_seg_gram_sum<<<B, 256, 0, st>>>((const SjGramSum*)jobs, begin, n); break;
+        case kSegChol: k_seg_chol<<<n, kCholThreads, 0, st>>>((const SjChol*)jobs); break;
+        case kSegNN:
+            switch (l.variant) {
+#define ISVD_SNN(NB) case NB: k_seg_nn<NB><<<B, kThreads, 0, st>>>((const SjNN*)jobs, begin, n); break;
+                ISVD_SNN(1) ISVD_SNN(2) ISVD_SNN(3) ISVD_SNN(4) ISVD_SNN(5) ISVD_SNN(6) ISVD_SNN(7) ISVD_SNN(8)
+#undef ISVD_SNN
+                default: return fail(ISVD_E_INVAL, "segmented product width %d", l.variant);
+            }
+            break;
+        case kSegTN:
+            switch (l.variant) {
+#define ISVD_STN(NB) case NB: k_seg_tn<NB><<<B, kThreads, 0, st>>>((const SjTN*)jobs, begin, n); break;
+                ISVD_STN(1) ISVD_STN(2) ISVD_STN(3) ISVD_STN(4) ISVD_STN(5) ISVD_STN(6) ISVD_STN(7) ISVD_STN(8)
+#undef ISVD_STN
+                default: return fail(ISVD_E_INVAL, "segmented product width %d", l.variant);
+            }
+            break;
+        case kSegTnSum: k_seg_tn_sum<<<B, 256, 0, st>>>((const SjTnSum*)jobs, begin, n); break;
+        case kSegSmall: k_seg_small_gemm<<<B, 256, 0, st>>>((const SjSmallGemm*)jobs, begin, n); break;
+        case kSegRot: k_seg_rot<false><<<B, kThreads, 0, st>>>((const SjRot*)jobs, begin, n); break;
+        case kSegRotTiled: k_seg_rot<true><<<B, kThreads, 0, st>>>((const SjRot*)jobs, begin, n); break;
+        case kSegSvd:
+            k_seg_svd<<<n, RRShape::NT, sizeof(double) * svd_noj_lds_doubles(), st>>>((const SjSvd*)jobs);
+            break;
+        case kSegCommit: k_seg_commit<<<n, 256, 0, st>>>((const SjCommit*)jobs); break;
+        default: return fail(ISVD_E_INVAL, "segmented launch kind %d", l.kind);
+    }
+    HIP_TRY(hipGetLastError());
+    return ISVD_OK;
+}
+
+// Can stream s take the segmented batch?  FP32 storage (BF16 rotations
+// included: the refresh works on A) and the A form.
+bool seg_eligible(const Stream& s) {
+    if (s.esz != 4) return false;
+    int k = 0, b = 0;
+    refresh_block(s, &k, &b);
+    return k >= 1 && b >= k && !gram_form(s, b);
+}
+
+// The refreshes of `list` (all seg_eligible, distinct, their headers in
+// e->hdr_mirror) as one segmented batch on `lane`, after what `lane` holds.
+isvd_status refresh_segmented(isvd_engine* e, const std::vector<Stream*>& list, hipStream_t lane) {
+    std::vector<SegRef> refs;
+    size_t total = 0;
+    for (Stream* sp : list) {
+        Stream& s = *sp;
+        const DevHeader& h = e->hdr_mirror[s.slot];
+        SegRef r{};
+        r.s = sp;
+        refresh_block(s, &r.k, &r.b);
+        r.m = s.m;
+        r.n = s.n;
+        r.lda = lda_of(s.cfg);
+        r.exact = r.b == r.n;
+        r.iters = r.exact ? 0 : s.cfg.refresh_iters >= 0 ? s.cfg.refresh_iters : 3;
+        r.ldo = round4(r.k);
+        r.cur = h.cur;
+        r.ld = h.ld;
+        r.kw = std::min(h.k, r.b);
+        r.w = ws_layout(r.m, r.n, r.b, 4);
+        r.off = total;
+        total = align_up(total + r.w.total, 256);
+        refs.push_back(r);
+    }
+    if (!e->seg_ws.retired.empty() && hipStreamQuery(lane) == hipSuccess) free_retired(e->seg_ws);
+    if (!e->seg_jobs.retired.empty() && hipStreamQuery(lane) == hipSuccess) free_retired(e->seg_jobs);
+    ST_TRY(ensure_ws(e->seg_ws, std::max<size_t>(total, 256)));
+    for (SegRef& r : refs) r.ws = e->seg_ws.p + r.off;
+    // groups of equal (exact, iters): the same launch sequence
+    std::map<std::pair<int, int>, std::vector<SegRef>> groups;
+    for (SegRef& r : refs) groups[{r.exact ? 1 : 0, r.iters}].push_back(r);
+    SegProgram P;
+    for (auto& kv : groups) seg_group(e, P, kv.second);
+    // job tables: pinned staging slot -> device, one copy
+    const size_t bytes = std::max<size_t>(P.host.size(), 16);
+    auto& slot = e->seg_slot[e->seg_next];
+    e->seg_next = (e->seg_next + 1) % 4;
+    if (slot.used) HIP_TRY(hipEventSynchronize(slot.ev));
+    if (slot.bytes < bytes) {
+        if (slot.host) HIP_TRY(hipHostFree(slot.host));
+        slot.host = nullptr;
+        slot.bytes = 0;
+        const size_t want = bytes + bytes / 2;
+        HIP_TRY(hipHostMalloc((void**)&slot.host, want, hipHostMallocDefault));
+        slot.bytes = want;
+    }
+    std::memcpy(slot.host, P.host.data(), P.host.size());
+    ST_TRY(ensure_ws(e->seg_jobs, bytes));
+    HIP_TRY(hipMemcpyAsync(e->seg_jobs.p, slot.host, P.host.size(), hipMemcpyHostToDevice, lane));
+    HIP_TRY(hipEventRecord(slot.ev, lane));
+    slot.used = true;
+    for (Stream* sp : list) HIP_TRY(hipEventRecord(sp->ev_r0, lane));
+    for (const auto& l : P.launches) ST_TRY(seg_launch(l, e->seg_jobs.p, lane));
+    // host state, as do_refresh / refresh_commit / defer_after_refresh
+    for (SegRef& r : refs) {
+        Stream& s = *r.s;
+        s.refresh_rounds = 0;
+        s.refresh_converged = true;
+        s.k_target = r.k;
+        if (s.wbuf) {
+            s.defer_pending = 0;
+            s.defer_period = defer_period_for(s);
+        }
+        HIP_TRY(hipEventRecord(s.ev_r1, lane));
+        s.have_refresh_time = true;
+        s.n_refresh += 1;
+        s.t_last = s.t;
+        s.drift_acc = 0.0;
+        HIP_TRY(hipMemcpyAsync(e->rsweeps + s.slot, e->dsweeps + s.slot, sizeof(int), hipMemcpyDeviceToHost, lane));
+        HIP_TRY(hipEventRecord(s.ev_ready, lane));
+        s.refreshing = true;
+    }
+    return ISVD_OK;
+}
+
+isvd_status refresh_batch(isvd_engine* e, const std::vector<Stream*>& all, hipStream_t st) {
     ST_TRY(ensure_refresh_lanes(e));
+    // FP32 streams refreshing in the A form go as one segmented batch on
+    // lane 0 (when there are at least two of them), the rest one by one on
+    // the lanes
+    std::vector<Stream*> seg, list;
+    for (Stream* sp : all) (e->seg_refresh && seg_eligible(*sp) ? seg : list).push_back(sp);
+    if (seg.size() < 2) {
+        list = all;
+        seg.clear();
+    }
+    const int cnt = (int)list.size();
     // buffers retired by workspace growth go once their lane has drained
     for (auto& l : e->rlanes)
         if (!l.ws.retired.empty() && hipStreamQuery(l.st) == hipSuccess) free_retired(l.ws);
@@ -2290,6 +2668,14 @@ isvd_status refresh_batch(isvd_engine* e, const std::vector<Stream*>& list, hipS
     HIP_TRY(hipMemcpyAsync(e->hdr_mirror, e->hdr_dev, sizeof(DevHeader) * e->hdr_hi, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     HIP_TRY(hipEventRecord(e->ev_policies, st));
+    if (!seg.empty()) {
+        auto& lane = e->rlanes[0];
+        HIP_TRY(hipStreamWaitEvent(lane.st, e->ev_policies, 0));
+        ST_TRY(refresh_segmented(e, seg, lane.st));
+        HIP_TRY(hipEventRecord(lane.ev, lane.st));
+        lane.pending = true;
+    }
+    if (cnt == 0) return ISVD_OK;
     const int used = std::min(cnt, kRefreshLanes);
     for (int l = 0; l < used; ++l) HIP_TRY(hipStreamWaitEvent(e->rlanes[l].st, e->ev_policies, 0));
     // each lane's refreshes are queued by a host thread of its own (the
@@ -2526,6 +2912,14 @@ isvd_status isvd_engine_destroy(isvd_engine* e) {
     if (e->hdr_dev) (void)hipFree(e->hdr_dev);
     if (e->chain_plan) (void)hipFree(e->chain_plan);
     if (e->hdr_mirror) (void)hipHostFree(e->hdr_mirror);
+    if (e->seg_ws.p) (void)hipFree(e->seg_ws.p);
+    free_retired(e->seg_ws);
+    if (e->seg_jobs.p) (void)hipFree(e->seg_jobs.p);
+    free_retired(e->seg_jobs);
+    for (auto& q : e->seg_slot) {
+        if (q.host) (void)hipHostFree(q.host);
+        if (q.ev) (void)hipEventDestroy(q.ev);
+    }
     for (auto& l : e->rlanes) {
         if (l.ws.p) (void)hipFree(l.ws.p);
         free_retired(l.ws);
@@ -2598,6 +2992,12 @@ isvd_status isvd_set_deferred_u(isvd_engine* e, int32_t enable, void* hip_stream
         }
     }
     e->defer_u = enable != 0;
+    return ISVD_OK;
+}
+
+isvd_status isvd_set_segmented_refresh(isvd_engine* e, int32_t enable) {
+    if (!e) return fail(ISVD_E_INVAL, "null engine");
+    e->seg_refresh = enable != 0;
     return ISVD_OK;
 }
 

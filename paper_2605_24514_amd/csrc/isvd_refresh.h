@@ -175,17 +175,18 @@ struct StageCopy {
 
 constexpr int kNnChunk = 16;   // default columns of A per pipeline stage
 template <int RB, int NB, int KCH = kNnChunk>
-__global__ void __launch_bounds__(kThreads, 2) k_gemm_nn_mfma(const float* A, int64_t lda,
+__device__ __attribute__((always_inline)) inline void k_gemm_nn_mfma_body(const float* A, int64_t lda,
                                                            const float* __restrict__ X,
                                                            float* Y, int ldy,
-                                                           int64_t m, int64_t n, int b) {
+                                                           int64_t m, int64_t n, int b, const int bx_, const int by_,
+    const int gx_) {
     typedef __attribute__((address_space(1))) const mm_v4f gc4;
     constexpr int SL = KCH / 16;                         // 16-column slabs per chunk
     constexpr int XW = 16 * NB;                                // staged columns of X
     __shared__ float sX[2][KCH * kStageLd];
     const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int g = l >> 4, c16 = l & 15;
-    const int64_t r0 = ((int64_t)blockIdx.x * 4 + w) * (16 * RB);
+    const int64_t r0 = ((int64_t)bx_ * 4 + w) * (16 * RB);
     const int nch = (int)((n + KCH - 1) / KCH);
     StageCopy<KCH, XW> xn;
     xn.init(b);
@@ -267,6 +268,14 @@ __global__ void __launch_bounds__(kThreads, 2) k_gemm_nn_mfma(const float* A, in
         }
 }
 
+template <int RB, int NB, int KCH = kNnChunk>
+__global__ void __launch_bounds__(kThreads, 2) k_gemm_nn_mfma(const float* A, int64_t lda,
+                                                           const float* __restrict__ X,
+                                                           float* Y, int ldy,
+                                                           int64_t m, int64_t n, int b) {
+    k_gemm_nn_mfma_body<RB, NB, KCH>(A, lda, X, Y, ldy, m, n, b, (int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x);
+}
+
 // Partials of Z = A^T Q (n x b, b <= kMaxBlock), computed as Z^T = Q^T A on the
 // matrix cores (A operand Q^T, B operand A).  Block (x, y) covers columns
 // [256 x, 256 x + 256) -- wave w the 64 from 256 x + 64 w -- over the rows
@@ -287,18 +296,19 @@ inline int64_t tn_chunks(int64_t m, int64_t n) {
     return std::max<int64_t>(1, std::min<int64_t>(want, (m + 2 * kTnRows - 1) / (2 * kTnRows)));
 }
 template <int NB, int RCH = kTnRows>
-__global__ void __launch_bounds__(kThreads, 2) k_gemm_tn_mfma(const float* __restrict__ A, int64_t lda,
+__device__ __attribute__((always_inline)) inline void k_gemm_tn_mfma_body(const float* __restrict__ A, int64_t lda,
                                                            const float* __restrict__ Q,
                                                            float* __restrict__ Zp, int64_t m, int64_t n, int b,
-                                                           int64_t rows_per_chunk) {
+                                                           int64_t rows_per_chunk, const int bx_, const int by_,
+    const int gx_) {
     typedef __attribute__((address_space(1))) const mm_v4f gc4;
     constexpr int SLABS = RCH / 4;
     constexpr int QW = 16 * NB;
     __shared__ float sQ[2][RCH * kStageLd];
     const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int g = l >> 4, c16 = l & 15;
-    const int64_t cc = (int64_t)blockIdx.x * kTnCols + 64 * w + 4 * c16;
-    const int64_t ra = (int64_t)blockIdx.y * rows_per_chunk;
+    const int64_t cc = (int64_t)bx_ * kTnCols + 64 * w + 4 * c16;
+    const int64_t ra = (int64_t)by_ * rows_per_chunk;
     const int64_t rb = min(m, ra + rows_per_chunk);
     const int nch = rb > ra ? (int)((rb - ra + RCH - 1) / RCH) : 0;
     StageCopy<RCH, QW> qn;
@@ -355,7 +365,7 @@ __global__ void __launch_bounds__(kThreads, 2) k_gemm_tn_mfma(const float* __res
         __syncthreads();
     }
     // acc[q][j][r] = Z[c0 + 4 (l%16) + j][16 q + 4 (l/16) + r]
-    float* out = Zp + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * kTnDump + (int64_t)w * kMaxBlock * 64 + l;
+    float* out = Zp + ((int64_t)by_ * gx_ + bx_) * kTnDump + (int64_t)w * kMaxBlock * 64 + l;
 #pragma unroll
     for (int q = 0; q < NB; ++q)
 #pragma unroll
@@ -364,12 +374,21 @@ __global__ void __launch_bounds__(kThreads, 2) k_gemm_tn_mfma(const float* __res
             for (int r = 0; r < 4; ++r) out[((q * 4 + j) * 4 + r) * 64] = acc[q][j][r];
 }
 
+template <int NB, int RCH = kTnRows>
+__global__ void __launch_bounds__(kThreads, 2) k_gemm_tn_mfma(const float* __restrict__ A, int64_t lda,
+                                                           const float* __restrict__ Q,
+                                                           float* __restrict__ Zp, int64_t m, int64_t n, int b,
+                                                           int64_t rows_per_chunk) {
+    k_gemm_tn_mfma_body<NB, RCH>(A, lda, Q, Zp, m, n, b, rows_per_chunk, (int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x);
+}
+
 // Z[c][jj] = sum over the nchunk partial dumps of k_gemm_tn_mfma, in chunk
 // order in FP64 (eight interleaved accumulators, added in a fixed order),
 // rounded once to FP32.  One thread per dump position (ncb kTnDump of them).
-__global__ void __launch_bounds__(256) k_tn_sum(const float* __restrict__ Zp, int nchunk, int64_t per_chunk,
-                                                int64_t n, int b, float* __restrict__ Z, int ldz) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __attribute__((always_inline)) inline void k_tn_sum_body(const float* __restrict__ Zp, int nchunk, int64_t per_chunk,
+                                                int64_t n, int b, float* __restrict__ Z, int ldz, const int bx_, const int by_,
+    const int gx_) {
+    const int64_t idx = (int64_t)bx_ * blockDim.x + threadIdx.x;
     if (idx >= per_chunk) return;
     const int lane = (int)(idx & 63), r = (int)((idx >> 6) & 3);
     const int qj = (int)((idx >> 8) % (kMaxBlock / 4));
@@ -386,6 +405,11 @@ __global__ void __launch_bounds__(256) k_tn_sum(const float* __restrict__ Zp, in
     }
     for (; p < nchunk; ++p) s[0] += (double)P[(int64_t)p * per_chunk];
     Z[c * ldz + jj] = (float)(((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7])));
+}
+
+__global__ void __launch_bounds__(256) k_tn_sum(const float* __restrict__ Zp, int nchunk, int64_t per_chunk,
+                                                int64_t n, int b, float* __restrict__ Z, int ldz) {
+    k_tn_sum_body(Zp, nchunk, per_chunk, n, b, Z, ldz, (int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x);
 }
 
 // Gram matrix G = Y^T Y (b x b, b <= kMaxBlock) on the FP64 matrix cores, in two
@@ -416,8 +440,9 @@ __device__ inline void gram_tile(int t, int nb, int* ib, int* jb) {
 
 constexpr int kGramAcc = (gram_tiles(kMaxBlock) + 3) / 4;   // upper tiles per wave
 template <typename T, bool TILED = false>
-__global__ void __launch_bounds__(kThreads) k_gram_mfma(const T* __restrict__ Y, int ldy, int64_t rows, int b,
-                                                        int64_t rpb, double* __restrict__ Gp) {
+__device__ __attribute__((always_inline)) inline void k_gram_mfma_body(const T* __restrict__ Y, int ldy, int64_t rows, int b,
+                                                        int64_t rpb, double* __restrict__ Gp, const int bx_, const int by_,
+    const int gx_) {
     constexpr int PER = kGramStage * kMaxBlock / kThreads;   // staged elements per thread
     __shared__ double sY[kGramStage][kMaxBlock + 1];
     const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -429,7 +454,7 @@ __global__ void __launch_bounds__(kThreads) k_gram_mfma(const T* __restrict__ Y,
         if (t < ntile) gram_tile(t, nb, &tib[s], &tjb[s]);
         else tib[s] = tjb[s] = 0;
     }
-    const int64_t ra = (int64_t)blockIdx.x * rpb;
+    const int64_t ra = (int64_t)bx_ * rpb;
     const int64_t rb = min(rows, ra + rpb);
     T pre[PER];
     auto fetch = [&](int64_t r0) {
@@ -469,23 +494,30 @@ __global__ void __launch_bounds__(kThreads) k_gram_mfma(const T* __restrict__ Y,
     for (int s = 0; s < kGramAcc; ++s) {
         const int t = w + 4 * s;
         if (t >= ntile) continue;
-        double* out = Gp + ((int64_t)blockIdx.x * ntile + t) * 256;
+        double* out = Gp + ((int64_t)bx_ * ntile + t) * 256;
 #pragma unroll
         for (int r = 0; r < 4; ++r) out[(4 * r + (l >> 4)) * 16 + (l & 15)] = acc[s][r];
     }
+}
+
+template <typename T, bool TILED = false>
+__global__ void __launch_bounds__(kThreads) k_gram_mfma(const T* __restrict__ Y, int ldy, int64_t rows, int b,
+                                                        int64_t rpb, double* __restrict__ Gp) {
+    k_gram_mfma_body<T, TILED>(Y, ldy, rows, b, rpb, Gp, (int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x);
 }
 
 // G = sum over the nparts partials of k_gram_mfma.  A block takes 32
 // consecutive tile entries; thread group g (of 8) adds partials g, g + 8, ...
 // in increasing order into four accumulators, and the groups' sums are added
 // in group order: the result does not depend on timing.
-__global__ void __launch_bounds__(256) k_gram_sum(const double* __restrict__ Gp, int nparts, int b,
-                                                  double* __restrict__ G) {
+__device__ __attribute__((always_inline)) inline void k_gram_sum_body(const double* __restrict__ Gp, int nparts, int b,
+                                                  double* __restrict__ G, const int bx_, const int by_,
+    const int gx_) {
     __shared__ double red[8][33];
     const int nb = (b + 15) / 16, ntile = gram_tiles(b);
     const int total = ntile * 256;
     const int o = threadIdx.x & 31, g = threadIdx.x >> 5;
-    const int e = blockIdx.x * 32 + o;
+    const int e = bx_ * 32 + o;
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
     if (e < total) {
         const double* P = Gp + e;
@@ -510,6 +542,11 @@ __global__ void __launch_bounds__(256) k_gram_sum(const double* __restrict__ Gp,
     if (a >= b || c >= b || (ib == jb && a > c)) return;
     G[a * b + c] = s;
     G[c * b + a] = s;
+}
+
+__global__ void __launch_bounds__(256) k_gram_sum(const double* __restrict__ Gp, int nparts, int b,
+                                                  double* __restrict__ G) {
+    k_gram_sum_body(Gp, nparts, b, G, (int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x);
 }
 
 // out[e] = sum_p P[p * stride + e] in part order; converted to Tout
@@ -543,9 +580,10 @@ __global__ void k_sum_parts(const double* __restrict__ P, int nparts, int64_t st
 constexpr int kCholThreads = 512;
 constexpr int kCholTY = kCholThreads / 16;   // row groups of the thread grid
 template <typename T>
-__global__ void __launch_bounds__(kCholThreads) k_chol_inv(const double* __restrict__ G, int b,
+__device__ __attribute__((always_inline)) inline void k_chol_inv_body(const double* __restrict__ G, int b,
                                                        double* __restrict__ Rout, T* __restrict__ RinvT,
-                                                       int* __restrict__ flag) {
+                                                       int* __restrict__ flag, const int bx_, const int by_,
+    const int gx_) {
     constexpr int NP = (kMaxBlock + kCholTY - 1) / kCholTY, NQ = 2 * kMaxBlock / 16;
     __shared__ double s_row[2][2 * kMaxBlock];
     __shared__ double s_g[kMaxBlock];
@@ -622,10 +660,18 @@ __global__ void __launch_bounds__(kCholThreads) k_chol_inv(const double* __restr
     }
 }
 
+template <typename T>
+__global__ void __launch_bounds__(kCholThreads) k_chol_inv(const double* __restrict__ G, int b,
+                                                       double* __restrict__ Rout, T* __restrict__ RinvT,
+                                                       int* __restrict__ flag) {
+    k_chol_inv_body<T>(G, b, Rout, RinvT, flag, (int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x);
+}
+
 // C = A B for b x b FP64 matrices, one output per thread (grid ceil(b^2 / blockDim))
-__global__ void k_small_gemm(const double* __restrict__ A, const double* __restrict__ B,
-                             double* __restrict__ C, int b) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __attribute__((always_inline)) inline void k_small_gemm_body(const double* __restrict__ A, const double* __restrict__ B,
+                             double* __restrict__ C, int b, const int bx_, const int by_,
+    const int gx_) {
+    const int e = bx_ * blockDim.x + threadIdx.x;
     if (e >= b * b) return;
     const int i = e / b, j = e % b;
     double s0 = 0.0, s1 = 0.0;
@@ -638,18 +684,24 @@ __global__ void k_small_gemm(const double* __restrict__ A, const double* __restr
     C[e] = s0 + s1;
 }
 
+__global__ void k_small_gemm(const double* __restrict__ A, const double* __restrict__ B,
+                             double* __restrict__ C, int b) {
+    k_small_gemm_body(A, B, C, b, (int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x);
+}
+
 // out[r, 0:ldo] = in[r, 0:kin] Q[0:kin, 0:ldo]   (may run in place when ldi == ldo);
 // `in` row-major, `out` row-major or, when TILED_OUT, in the tiled basis layout;
 // out2 (optional) receives a second copy
 template <typename T, int KC, bool TILED_OUT = false>
-__global__ void __launch_bounds__(kThreads) k_rotate_plain(const T* in, int ldi, T* out, int ldo,
+__device__ __attribute__((always_inline)) inline void k_rotate_plain_body(const T* in, int ldi, T* out, int ldo,
                                                            int64_t rows, int kin,
-                                                           const T* __restrict__ Q, T* out2 = nullptr) {
+                                                           const T* __restrict__ Q, T* out2, const int bx_, const int by_,
+    const int gx_) {
     constexpr int RT = KC <= 64 ? 64 : 16;
     __shared__ T sQ[KC * KC];
     __shared__ T sX[RT * KC];
     for (int e = threadIdx.x; e < kin * ldo; e += kThreads) sQ[e] = Q[e];
-    const int64_t r0 = (int64_t)blockIdx.x * RT;
+    const int64_t r0 = (int64_t)bx_ * RT;
     const int nr = (int)min((int64_t)RT, rows - r0);
     for (int e = threadIdx.x; e < nr * ldi; e += kThreads) sX[e] = in[r0 * ldi + e];
     __syncthreads();
@@ -661,6 +713,13 @@ __global__ void __launch_bounds__(kThreads) k_rotate_plain(const T* in, int ldi,
         out[o] = acc;
         if (out2) out2[o] = acc;
     }
+}
+
+template <typename T, int KC, bool TILED_OUT = false>
+__global__ void __launch_bounds__(kThreads) k_rotate_plain(const T* in, int ldi, T* out, int ldo,
+                                                           int64_t rows, int kin,
+                                                           const T* __restrict__ Q, T* out2 = nullptr) {
+    k_rotate_plain_body<T, KC, TILED_OUT>(in, ldi, out, ldo, rows, kin, Q, out2, (int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x);
 }
 
 // Rayleigh-Ritz core: SVD of the b x b FP64 R (row-major) by one-sided
@@ -675,11 +734,9 @@ __global__ void __launch_bounds__(kThreads) k_rotate_plain(const T* in, int ldi,
 // coarser threshold would be amplified the same way, so the FP64 one stays.
 typedef WideShape RRShape;
 template <typename T>
-__global__ void __launch_bounds__(RRShape::NT) k_svd_small_noj(const double* __restrict__ R, int b, int k,
-                                                              double* __restrict__ S, T* __restrict__ QU,
-                                                              T* __restrict__ QV, int ldo,
-                                                              int* __restrict__ sweeps_out) {
-    extern __shared__ double smem[];
+__device__ __attribute__((always_inline)) inline void k_svd_small_noj_body(
+    const double* __restrict__ R, int b, int k, double* __restrict__ S, T* __restrict__ QU, T* __restrict__ QV,
+    int ldo, int* __restrict__ sweeps_out, double* smem) {
     const int N = b;
     const int ldw = RRShape::LDW;
     double* W = smem;                                   // (N + 1) columns
@@ -727,6 +784,15 @@ __global__ void __launch_bounds__(RRShape::NT) k_svd_small_noj(const double* __r
     if (threadIdx.x == 0) *sweeps_out = sweeps;
 }
 
+template <typename T>
+__global__ void __launch_bounds__(RRShape::NT) k_svd_small_noj(const double* __restrict__ R, int b, int k,
+                                                              double* __restrict__ S, T* __restrict__ QU,
+                                                              T* __restrict__ QV, int ldo,
+                                                              int* __restrict__ sweeps_out) {
+    extern __shared__ double smem[];
+    k_svd_small_noj_body<T>(R, b, k, S, QU, QV, ldo, sweeps_out, smem);
+}
+
 // dynamic LDS of k_svd_small_noj for b <= kMaxBlock
 __host__ __device__ constexpr size_t svd_noj_lds_doubles() {
     return (size_t)(kMaxBlock + 1) * RRShape::LDW + 6 * kMaxBlock;
@@ -736,9 +802,10 @@ __host__ __device__ constexpr size_t svd_noj_lds_doubles() {
 // deterministic hash in [-1, 1); identity when `ident` (b = n).  Also clears
 // the four flag words of the refresh.
 template <typename T>
-__global__ void k_start_block(T* __restrict__ X, int ldx, int64_t n, int b, const T* __restrict__ V,
-                              int ldv, int kw, uint64_t seed, int ident, int* __restrict__ flags) {
-    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __attribute__((always_inline)) inline void k_start_block_body(T* __restrict__ X, int ldx, int64_t n, int b, const T* __restrict__ V,
+                              int ldv, int kw, uint64_t seed, int ident, int* __restrict__ flags, const int bx_, const int by_,
+    const int gx_) {
+    int64_t e = (int64_t)bx_ * blockDim.x + threadIdx.x;
     if (e < 4) flags[e] = 0;
     if (e >= n * b) return;
     int64_t r = e / b;
@@ -754,6 +821,12 @@ __global__ void k_start_block(T* __restrict__ X, int ldx, int64_t n, int b, cons
         v = (T)((double)(h >> 11) * (2.0 / 9007199254740992.0) - 1.0);
     }
     X[r * ldx + j] = v;
+}
+
+template <typename T>
+__global__ void k_start_block(T* __restrict__ X, int ldx, int64_t n, int b, const T* __restrict__ V,
+                              int ldv, int kw, uint64_t seed, int ident, int* __restrict__ flags) {
+    k_start_block_body<T>(X, ldx, n, b, V, ldv, kw, seed, ident, flags, (int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x);
 }
 
 template <typename Tin, typename Tout>

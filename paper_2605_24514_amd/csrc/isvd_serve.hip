@@ -74,7 +74,7 @@ struct isvd_server {
     int64_t next_req = 0;
     size_t rr = 0;
     int64_t ticks = 0, tick_requests = 0;
-    double t_admit = 0.0, t_tick = 0.0, t_wait = 0.0;
+    double t_admit = 0.0, t_tick = 0.0, t_wait = 0.0, t_release = 0.0;
     std::string err;
 };
 
@@ -93,7 +93,10 @@ isvd_status sfail(isvd_server* s, isvd_status st, const char* msg) {
 // and has nothing queued releases its HBM.
 isvd_status retire_if_done(isvd_server* s, Ticket& t) {
     if (t.lifetime > 0 && t.completed >= t.lifetime && t.queue.empty() && t.state == 1) {
-        if (isvd_release(s->eng, t.id) != ISVD_OK) return ISVD_E_DEVICE;
+        const double r0 = now_s(s);
+        const isvd_status rc = isvd_release(s->eng, t.id);
+        s->t_release += now_s(s) - r0;
+        if (rc != ISVD_OK) return ISVD_E_DEVICE;
         t.state = 2;
         s->used -= t.bytes;
     }
@@ -370,6 +373,7 @@ isvd_status isvd_server_stats(isvd_server* s, isvd_server_stats_t* out) {
     st.host_admit_s = s->t_admit;
     st.host_tick_s = s->t_tick;
     st.host_wait_s = s->t_wait;
+    st.host_release_s = s->t_release;
     *out = st;
     return ISVD_OK;
 }

@@ -284,7 +284,7 @@ __global__ void __launch_bounds__(WideShape::NT) k_theta_tracks(const Track* __r
 }
 
 // Reference reset (refresh that stores U_ref, stream start): M = H = I.
-__global__ void k_track_reset(DevHeader* hdr, double* M, double* H, int kc) {
+__device__ inline void track_reset_body(DevHeader* hdr, double* M, double* H, int kc) {
     const int k = hdr->k;
     for (int e = threadIdx.x; e < kc * kc; e += blockDim.x) {
         const int r = e / kc, c = e % kc;
@@ -299,6 +299,7 @@ __global__ void k_track_reset(DevHeader* hdr, double* M, double* H, int kc) {
         hdr->angle_ref = 0.0;
     }
 }
+__global__ void k_track_reset(DevHeader* hdr, double* M, double* H, int kc) { track_reset_body(hdr, M, H, kc); }
 
 // theta_ref from directly formed M (k_ref x k) and H (k x k), row stride k.
 __global__ void __launch_bounds__(WideShape::NT) k_theta_direct(const double* M, const double* H, int k, int kref,

@@ -1257,8 +1257,8 @@ __global__ void __launch_bounds__(256) k_defer_materialize(const DevHeader* __re
 
 // After a materialisation or a refresh: W and W^-1 of the current parity back
 // to I (flip = 1 would also switch the current U / V buffers).
-__global__ void __launch_bounds__(256) k_defer_reset(DevHeader* hdr, double* W0, double* W1, double* Wi0, double* Wi1,
-                                                     int kc, int flip) {
+__device__ inline void defer_reset_body(DevHeader* hdr, double* W0, double* W1, double* Wi0, double* Wi1, int kc,
+                                        int flip) {
     const int wp = hdr->wpar;
     double* W = wp ? W1 : W0;
     double* Wi = wp ? Wi1 : Wi0;
@@ -1269,6 +1269,10 @@ __global__ void __launch_bounds__(256) k_defer_reset(DevHeader* hdr, double* W0,
     }
     __syncthreads();
     if (flip && threadIdx.x == 0) hdr->cur ^= 1;
+}
+__global__ void __launch_bounds__(256) k_defer_reset(DevHeader* hdr, double* W0, double* W1, double* Wi0, double* Wi1,
+                                                     int kc, int flip) {
+    defer_reset_body(hdr, W0, W1, Wi0, Wi1, kc, flip);
 }
 
 }  // namespace isvd

@@ -74,11 +74,18 @@ class CCompletion(ctypes.Structure):
                 ("launch_s", ctypes.c_double), ("done_s", ctypes.c_double)]
 
 
+COMPLETION_DTYPE = np.dtype([("req", np.int64), ("ticket", np.int64), ("kind", np.int32), ("status", np.int32),
+                             ("arrival_s", np.float64), ("admit_s", np.float64), ("launch_s", np.float64),
+                             ("done_s", np.float64)], align=True)
+assert COMPLETION_DTYPE.itemsize == ctypes.sizeof(CCompletion)
+
+
 class CServerStats(ctypes.Structure):
     _fields_ = [("waiting", ctypes.c_int64), ("admitted", ctypes.c_int64), ("retired", ctypes.c_int64),
                 ("queued", ctypes.c_int64), ("hbm_used", ctypes.c_uint64), ("inflight_ticks", ctypes.c_int32),
                 ("pad", ctypes.c_int32), ("ticks", ctypes.c_int64), ("tick_requests", ctypes.c_int64),
-                ("host_admit_s", ctypes.c_double), ("host_tick_s", ctypes.c_double), ("host_wait_s", ctypes.c_double)]
+                ("host_admit_s", ctypes.c_double), ("host_tick_s", ctypes.c_double), ("host_wait_s", ctypes.c_double),
+                ("host_release_s", ctypes.c_double)]
 
 
 class CLaunchTime(ctypes.Structure):
@@ -97,7 +104,7 @@ ROT_VARIANTS = [(256, 1, True), (512, 1, True), (1024, 1, True), (1024, 2, False
 EXPORTS = ["isvd_engine_create", "isvd_engine_destroy", "isvd_stream_bytes", "isvd_init", "isvd_init_from_factors",
            "isvd_append_row", "isvd_append_col", "isvd_update_entry", "isvd_refresh", "isvd_refresh_noalloc", "isvd_metrics",
            "isvd_get_factors", "isvd_get_matrix", "isvd_shape", "isvd_release", "isvd_tick",
-           "isvd_profile", "isvd_profile_read", "isvd_autotune", "isvd_set_rotation_variant", "isvd_sync", "isvd_stream_busy", "isvd_rotation_stream", "isvd_set_pipelining", "isvd_set_tick_graphs",
+           "isvd_profile", "isvd_profile_read", "isvd_autotune", "isvd_set_rotation_variant", "isvd_sync", "isvd_stream_busy", "isvd_rotation_stream", "isvd_set_pipelining", "isvd_set_tick_graphs", "isvd_set_segmented_refresh",
            "isvd_server_create", "isvd_server_destroy", "isvd_server_clock", "isvd_server_error",
            "isvd_server_add_stream", "isvd_server_submit", "isvd_server_submit_many", "isvd_server_step", "isvd_server_drain",
            "isvd_server_poll", "isvd_server_stats", "isvd_server_stream", "isvd_last_error",
@@ -144,6 +151,7 @@ def load_library(path=LIB_PATH):
         "isvd_stream_busy": (i32, [vp, i64, ctypes.POINTER(i32)]),
         "isvd_set_pipelining": (i32, [vp, i32]),
         "isvd_set_tick_graphs": (i32, [vp, i32]),
+        "isvd_set_segmented_refresh": (i32, [vp, i32]),
         "isvd_set_deferred_u": (i32, [vp, i32, vp]),
         "isvd_server_create": (i32, [vp, ctypes.POINTER(CServerConfig), vp, ctypes.POINTER(vp)]),
         "isvd_server_destroy": (i32, [vp]),
@@ -487,6 +495,11 @@ class Engine:
     def set_pipelining(self, enable):
         self._check(self._lib.isvd_set_pipelining(self._h, 1 if enable else 0), "isvd_set_pipelining")
 
+    def set_segmented_refresh(self, enable):
+        """Compute the refreshes one tick fires as one segmented batch (see
+        isvd_set_segmented_refresh in include/isvd.h)."""
+        self._check(self._lib.isvd_set_segmented_refresh(self._h, 1 if enable else 0), "isvd_set_segmented_refresh")
+
     def set_tick_graphs(self, enable):
         """Replay deferred-U row-append ticks as captured HIP graphs."""
         self._check(self._lib.isvd_set_tick_graphs(self._h, 1 if enable else 0), "isvd_set_tick_graphs")
@@ -615,6 +628,20 @@ class Server:
         out = [{f: getattr(arr[q], f) for f, _ in CCompletion._fields_} for q in range(n.value)]
         for c in out:
             self._keep.pop(c["req"], None)
+        return out
+
+    def poll_array(self, cap=1 << 16):
+        """Completion records as a numpy structured array (COMPLETION_DTYPE),
+        oldest first."""
+        if getattr(self, "_pbuf", None) is None or len(self._pbuf) < cap:
+            self._pbuf = (CCompletion * cap)()
+        arr = self._pbuf
+        n = ctypes.c_int32()
+        self._check(self._lib.isvd_server_poll(self._h, arr, cap, ctypes.byref(n)), "isvd_server_poll")
+        out = np.frombuffer(arr, dtype=COMPLETION_DTYPE, count=n.value).copy()
+        if len(self._keep) > len(self._pending):
+            for rid in out["req"].tolist():
+                self._keep.pop(rid, None)
         return out
 
     def stats(self):
