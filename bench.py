@@ -188,6 +188,9 @@ def serve_run(args):
     rng = np.random.default_rng(17)
     dev_stream = torch.cuda.Stream()
     eng = isvd.Engine()
+    # released streams' blocks are reused by later admissions (no device-wide
+    # wait per release, no allocation per admission)
+    eng.set_block_cache(int(args.serve_cache_gb * 1e9))
     srv = isvd.Server(eng, hbm_budget=int(args.serve_budget_gb * 1e9), max_inflight=2, stream=dev_stream)
     log("serving: %d streams, lifetime %d, %.0f requests/s, budget %.0f GB" % (N, L, rate, args.serve_budget_gb))
     # Every stream's requests are drawn up front; its A0 (about 105 MB on
@@ -713,6 +716,8 @@ def parse_args(argv=None):
     ap.add_argument("--serve-budget-gb", type=float, default=50.0)
     ap.add_argument("--serve-default", type=int, default=4096,
                     help="streams of the serving run added to the default line (0: none)")
+    ap.add_argument("--serve-cache-gb", type=float, default=24.0,
+                    help="device blocks of released streams kept for later admissions")
     ap.add_argument("--serve-window", type=int, default=32,
                     help="streams waiting for admission with their A0 in memory")
     return ap.parse_args(argv)

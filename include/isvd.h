@@ -333,8 +333,24 @@ isvd_status isvd_get_matrix(isvd_engine* eng, isvd_id id, double* A, int64_t lda
 /* Current shape and rank (host-side view; no device access). */
 isvd_status isvd_shape(isvd_engine* eng, isvd_id id, int64_t* m, int64_t* n, int32_t* k);
 
-/* Free the stream's device memory; the id becomes invalid. */
+/* Free the stream's device memory; the id becomes invalid.  Waits for the
+ * device, unless the block cache keeps the memory (isvd_set_block_cache). */
 isvd_status isvd_release(isvd_engine* eng, isvd_id id);
+
+/* Block cache for engines that create and release many streams (serving):
+ * with bytes > 0, isvd_release keeps a stream's device block (up to `bytes`
+ * in all) instead of freeing it, after waiting for the stream's own refresh
+ * and recording an event on each of the engine's streams; a later isvd_init
+ * whose block needs at most that size and at least four fifths of it reuses
+ * the block, its work on the caller's stream ordered after those events.
+ * Neither call then waits for the whole device.  The caller must have
+ * completed, or ordered before that later isvd_init's stream, any work it
+ * queued on its own streams that touches the released stream.  Streams with
+ * deferred U or A in host memory are freed as before.  bytes = 0 (the
+ * default) frees every release at once; lowering the cap below what is
+ * cached frees the cache.  When a new block does not fit the device, the
+ * cache is freed and the allocation tried again.  Errors: INVAL. */
+isvd_status isvd_set_block_cache(isvd_engine* eng, uint64_t bytes);
 
 /* Batched tick: apply `count` requests to `count` distinct streams as one
  * sequence of batched launches on hip_stream (per-stream order is the order

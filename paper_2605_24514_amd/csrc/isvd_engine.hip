@@ -115,6 +115,7 @@ struct Stream {
     int64_t n_refresh = 0, t_last = 0;
     int64_t ntiles_max = 0;
     char* base = nullptr;
+    size_t base_bytes = 0;      // size of the block holding base (a reused block may be larger)
     Layout L{};
     DevHeader* hdr = nullptr;   // the stream's entry of the engine's header array
     int slot = -1;              // its index there
@@ -345,6 +346,15 @@ struct isvd_engine {
     };
     SegSlot seg_slot[4];
     int seg_next = 0;
+    WsBuf seg_cws, seg_cjobs;        // the batched error checks' workspaces and job tables
+    double* chk_host = nullptr;      // pinned: their E_inc, ||A||^2 and Ritz values
+    size_t chk_host_n = 0;
+    // block cache (isvd_set_block_cache): device blocks of released streams,
+    // by size, reused by later streams; each release records an event on
+    // every engine stream, and a reusing stream creation waits for them
+    size_t bcache_cap = 0, bcache_bytes = 0;
+    std::multimap<size_t, char*> bcache;
+    std::vector<hipEvent_t> ev_rel;
     // the device headers of all live streams, one array (a slot per stream),
     // so that a tick reads them back with one copy into the pinned mirror
     DevHeader* hdr_dev = nullptr;
@@ -2191,7 +2201,9 @@ bool policy_needs_header(const Stream& s) {
 struct Deferred {
     std::vector<Stream*> refresh;   // fired refreshes
     std::vector<Stream*> shrink;    // adaptive-rank shrinks
+    std::vector<Stream*> checks;    // error-policy checks due (batched)
 };
+bool seg_eligible(const Stream& s);
 
 // With `defer`, a refresh that the policy fires, or an adaptive shrink, is
 // appended to it (the caller runs the tick's actions together) instead of
@@ -2213,6 +2225,10 @@ isvd_status after_update(isvd_engine* e, Stream& s, hipStream_t st, const DevHea
     }
     if (p.kind == ISVD_POL_ERROR) {
         if (p.check_every <= 0 || s.t % p.check_every != 0 || s.t - s.t_last < p.t_min) return ISVD_OK;
+        if (defer && e->seg_refresh && seg_eligible(s)) {
+            defer->checks.push_back(&s);
+            return ISVD_OK;
+        }
         Exact ex;
         RefreshPlan plan;
         ST_TRY(exact_metrics(e, s, st, &ex, &plan, false));
@@ -2297,6 +2313,8 @@ isvd_status ensure_refresh_lanes(isvd_engine* e) {
     }
     e->seg_ws.defer_free = true;
     e->seg_jobs.defer_free = true;
+    e->seg_cws.defer_free = true;
+    e->seg_cjobs.defer_free = true;
     for (auto& q : e->seg_slot) HIP_TRY(hipEventCreateWithFlags(&q.ev, hipEventDisableTiming));
     HIP_TRY(hipEventCreateWithFlags(&e->ev_policies, hipEventDisableTiming));
     HIP_TRY(hipMalloc((void**)&e->dsweeps, sizeof(int) * kMaxLiveStreams));
@@ -2430,8 +2448,8 @@ void seg_ax(SegProgram& P, std::vector<SegRef>& g) {
 }
 
 // One group of refs sharing (exact, iters): the launches of refresh_compute<float>
-// in the A form and of refresh_commit<float> with the reference stored.
-void seg_group(isvd_engine* e, SegProgram& P, std::vector<SegRef>& g) {
+// in the A form (the Rayleigh-Ritz sweep counts into e->dsweeps).
+void seg_compute(isvd_engine* e, SegProgram& P, std::vector<SegRef>& g) {
     if (g.empty()) return;
     const bool exact = g[0].exact;
     const int iters = g[0].iters;
@@ -2482,6 +2500,13 @@ void seg_group(isvd_engine* e, SegProgram& P, std::vector<SegRef>& g) {
         }
         P.add(kSegSvd, 0, j, ones);
     }
+}
+
+// The launches of refresh_commit<float> with the reference stored, for refs
+// whose refresh seg_compute has left in their workspace regions.
+void seg_commit(SegProgram& P, std::vector<SegRef>& g) {
+    auto X = [](SegRef& r) { return (float*)(r.ws + r.w.X); };
+    auto Y = [](SegRef& r) { return (float*)(r.ws + r.w.Y); };
     {
         std::vector<SjRot> j;
         std::vector<int> bl;
@@ -2573,41 +2598,31 @@ bool seg_eligible(const Stream& s) {
     return k >= 1 && b >= k && !gram_form(s, b);
 }
 
-// The refreshes of `list` (all seg_eligible, distinct, their headers in
-// e->hdr_mirror) as one segmented batch on `lane`, after what `lane` holds.
-isvd_status refresh_segmented(isvd_engine* e, const std::vector<Stream*>& list, hipStream_t lane) {
-    std::vector<SegRef> refs;
-    size_t total = 0;
-    for (Stream* sp : list) {
-        Stream& s = *sp;
-        const DevHeader& h = e->hdr_mirror[s.slot];
-        SegRef r{};
-        r.s = sp;
-        refresh_block(s, &r.k, &r.b);
-        r.m = s.m;
-        r.n = s.n;
-        r.lda = lda_of(s.cfg);
-        r.exact = r.b == r.n;
-        r.iters = r.exact ? 0 : s.cfg.refresh_iters >= 0 ? s.cfg.refresh_iters : 3;
-        r.ldo = round4(r.k);
-        r.cur = h.cur;
-        r.ld = h.ld;
-        r.kw = std::min(h.k, r.b);
-        r.w = ws_layout(r.m, r.n, r.b, 4);
-        r.off = total;
-        total = align_up(total + r.w.total, 256);
-        refs.push_back(r);
-    }
-    if (!e->seg_ws.retired.empty() && hipStreamQuery(lane) == hipSuccess) free_retired(e->seg_ws);
-    if (!e->seg_jobs.retired.empty() && hipStreamQuery(lane) == hipSuccess) free_retired(e->seg_jobs);
-    ST_TRY(ensure_ws(e->seg_ws, std::max<size_t>(total, 256)));
-    for (SegRef& r : refs) r.ws = e->seg_ws.p + r.off;
-    // groups of equal (exact, iters): the same launch sequence
-    std::map<std::pair<int, int>, std::vector<SegRef>> groups;
-    for (SegRef& r : refs) groups[{r.exact ? 1 : 0, r.iters}].push_back(r);
-    SegProgram P;
-    for (auto& kv : groups) seg_group(e, P, kv.second);
-    // job tables: pinned staging slot -> device, one copy
+// The refresh of stream s as a batch entry, its header from e->hdr_mirror;
+// its workspace region starts at *total, which moves past it.
+SegRef seg_ref(isvd_engine* e, Stream& s, size_t* total) {
+    const DevHeader& h = e->hdr_mirror[s.slot];
+    SegRef r{};
+    r.s = &s;
+    refresh_block(s, &r.k, &r.b);
+    r.m = s.m;
+    r.n = s.n;
+    r.lda = lda_of(s.cfg);
+    r.exact = r.b == r.n;
+    r.iters = r.exact ? 0 : s.cfg.refresh_iters >= 0 ? s.cfg.refresh_iters : 3;
+    r.ldo = round4(r.k);
+    r.cur = h.cur;
+    r.ld = h.ld;
+    r.kw = std::min(h.k, r.b);
+    r.w = ws_layout(r.m, r.n, r.b, 4);
+    r.off = *total;
+    *total = align_up(*total + r.w.total, 256);
+    return r;
+}
+
+// The job tables of P to the device buffer `dev` (grown as needed), through
+// the next pinned staging slot, on stream q.
+isvd_status seg_upload(isvd_engine* e, const SegProgram& P, WsBuf& dev, hipStream_t q) {
     const size_t bytes = std::max<size_t>(P.host.size(), 16);
     auto& slot = e->seg_slot[e->seg_next];
     e->seg_next = (e->seg_next + 1) % 4;
@@ -2621,30 +2636,154 @@ isvd_status refresh_segmented(isvd_engine* e, const std::vector<Stream*>& list, 
         slot.bytes = want;
     }
     std::memcpy(slot.host, P.host.data(), P.host.size());
-    ST_TRY(ensure_ws(e->seg_jobs, bytes));
-    HIP_TRY(hipMemcpyAsync(e->seg_jobs.p, slot.host, P.host.size(), hipMemcpyHostToDevice, lane));
-    HIP_TRY(hipEventRecord(slot.ev, lane));
+    ST_TRY(ensure_ws(dev, bytes));
+    HIP_TRY(hipMemcpyAsync(dev.p, slot.host, P.host.size(), hipMemcpyHostToDevice, q));
+    HIP_TRY(hipEventRecord(slot.ev, q));
     slot.used = true;
+    return ISVD_OK;
+}
+
+// Host state after a committed refresh, as do_refresh / refresh_commit /
+// defer_after_refresh leave it.
+void seg_host_commit(Stream& s, const SegRef& r) {
+    s.refresh_rounds = 0;
+    s.refresh_converged = true;
+    s.k_target = r.k;
+    if (s.wbuf) {
+        s.defer_pending = 0;
+        s.defer_period = defer_period_for(s);
+    }
+    s.have_refresh_time = true;
+    s.n_refresh += 1;
+    s.t_last = s.t;
+    s.drift_acc = 0.0;
+}
+
+// The refreshes of `list` (all seg_eligible, distinct, their headers in
+// e->hdr_mirror) as one segmented batch on `lane`, after what `lane` holds.
+isvd_status refresh_segmented(isvd_engine* e, const std::vector<Stream*>& list, hipStream_t lane) {
+    std::vector<SegRef> refs;
+    size_t total = 0;
+    for (Stream* sp : list) refs.push_back(seg_ref(e, *sp, &total));
+    if (!e->seg_ws.retired.empty() && hipStreamQuery(lane) == hipSuccess) free_retired(e->seg_ws);
+    if (!e->seg_jobs.retired.empty() && hipStreamQuery(lane) == hipSuccess) free_retired(e->seg_jobs);
+    ST_TRY(ensure_ws(e->seg_ws, std::max<size_t>(total, 256)));
+    for (SegRef& r : refs) r.ws = e->seg_ws.p + r.off;
+    // groups of equal (exact, iters): the same launch sequence
+    std::map<std::pair<int, int>, std::vector<SegRef>> groups;
+    for (SegRef& r : refs) groups[{r.exact ? 1 : 0, r.iters}].push_back(r);
+    SegProgram P;
+    for (auto& kv : groups) {
+        seg_compute(e, P, kv.second);
+        seg_commit(P, kv.second);
+    }
+    ST_TRY(seg_upload(e, P, e->seg_jobs, lane));
     for (Stream* sp : list) HIP_TRY(hipEventRecord(sp->ev_r0, lane));
     for (const auto& l : P.launches) ST_TRY(seg_launch(l, e->seg_jobs.p, lane));
-    // host state, as do_refresh / refresh_commit / defer_after_refresh
     for (SegRef& r : refs) {
         Stream& s = *r.s;
-        s.refresh_rounds = 0;
-        s.refresh_converged = true;
-        s.k_target = r.k;
-        if (s.wbuf) {
-            s.defer_pending = 0;
-            s.defer_period = defer_period_for(s);
-        }
+        seg_host_commit(s, r);
         HIP_TRY(hipEventRecord(s.ev_r1, lane));
-        s.have_refresh_time = true;
-        s.n_refresh += 1;
-        s.t_last = s.t;
-        s.drift_acc = 0.0;
         HIP_TRY(hipMemcpyAsync(e->rsweeps + s.slot, e->dsweeps + s.slot, sizeof(int), hipMemcpyDeviceToHost, lane));
         HIP_TRY(hipEventRecord(s.ev_ready, lane));
         s.refreshing = true;
+    }
+    return ISVD_OK;
+}
+
+// Error-policy checks of one tick, batched (Sec. 3.2, eq. error-refresh-rule):
+// for the FP32 streams whose refresh runs in the A form, the TruncatedSVD of
+// every check is computed in one segmented batch on the caller's stream, the
+// residual and norm passes follow per stream, one copy and one wait bring
+// every stream's E_inc, ||A||^2 and Ritz values back, and the streams whose
+// ratio exceeds gamma commit their computed refresh in one more segmented
+// batch.  Each step is exact_metrics' and do_refresh's own, so decisions and
+// states are bitwise those of the checks run one by one.
+isvd_status check_batch(isvd_engine* e, const std::vector<Stream*>& list, hipStream_t st) {
+    ST_TRY(ensure_refresh_lanes(e));
+    HIP_TRY(hipMemcpyAsync(e->hdr_mirror, e->hdr_dev, sizeof(DevHeader) * e->hdr_hi, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (!e->seg_cws.retired.empty()) free_retired(e->seg_cws);
+    if (!e->seg_cjobs.retired.empty()) free_retired(e->seg_cjobs);
+    std::vector<SegRef> refs;
+    std::vector<size_t> mo;       // per ref: offset of its metric partials in its region
+    size_t total = 0;
+    for (Stream* sp : list) {
+        SegRef r = seg_ref(e, *sp, &total);
+        const int64_t nres = cdiv(r.m, 64) * cdiv(r.n, 64);
+        mo.push_back(total);
+        total = align_up(total + sizeof(double) * (size_t)(nres + 8), 256);
+        refs.push_back(r);
+    }
+    ST_TRY(ensure_ws(e->seg_cws, std::max<size_t>(total, 256)));
+    for (SegRef& r : refs) r.ws = e->seg_cws.p + r.off;
+    std::map<std::pair<int, int>, std::vector<SegRef>> groups;
+    for (SegRef& r : refs) groups[{r.exact ? 1 : 0, r.iters}].push_back(r);
+    SegProgram P;
+    for (auto& kv : groups) seg_compute(e, P, kv.second);
+    ST_TRY(seg_upload(e, P, e->seg_cjobs, st));
+    for (const auto& l : P.launches) ST_TRY(seg_launch(l, e->seg_cjobs.p, st));
+    // E_inc^2 and ||A||^2 per stream (as exact_metrics), then one copy back
+    const size_t per = 8 + 2 * kMaxBlock;   // doubles per stream in the host buffer
+    if (e->chk_host_n < refs.size() * per) {
+        if (e->chk_host) HIP_TRY(hipHostFree(e->chk_host));
+        e->chk_host = nullptr;
+        e->chk_host_n = 0;
+        HIP_TRY(hipHostMalloc((void**)&e->chk_host, sizeof(double) * refs.size() * per * 2, hipHostMallocDefault));
+        e->chk_host_n = refs.size() * per * 2;
+    }
+    for (size_t q = 0; q < refs.size(); ++q) {
+        SegRef& r = refs[q];
+        Stream& s = *r.s;
+        const DevHeader& h = e->hdr_mirror[s.slot];
+        double* fro_p = (double*)(r.ws + r.w.fro);
+        double* res_p = (double*)(e->seg_cws.p + mo[q]);
+        const int64_t nres = cdiv(r.m, 64) * cdiv(r.n, 64);
+        double* scal = res_p + nres;
+        const float* A = (const float*)s.A;
+        const int64_t nfro = cdiv(r.m, kFroRows);
+        k_fro2_partial<float><<<(int)nfro, kThreads, 0, st>>>(A, r.lda, r.m, r.n, fro_p);
+        k_sum_block<<<1, kThreads, 0, st>>>(fro_p, nfro, scal + 0);
+        dim3 rg((unsigned)cdiv(r.m, 64), (unsigned)cdiv(r.n, 64));
+        k_resid2_partial<float><<<rg, kThreads, 0, st>>>(A, r.lda, (const float*)s.U[h.cur], (const float*)s.V[h.cur],
+                                                        h.ld, s.S, r.m, r.n, h.k, res_p);
+        k_sum_block<<<1, kThreads, 0, st>>>(res_p, nres, scal + 1);
+        HIP_TRY(hipGetLastError());
+        double* hb = e->chk_host + q * per;
+        HIP_TRY(hipMemcpyAsync(hb, scal, sizeof(double) * 2, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(hb + 2, e->dsweeps + s.slot, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(hb + 8, r.ws + r.w.Sr, sizeof(double) * r.k, hipMemcpyDeviceToHost, st));
+    }
+    HIP_TRY(hipStreamSynchronize(st));
+    std::vector<SegRef> fire;
+    for (size_t q = 0; q < refs.size(); ++q) {
+        SegRef& r = refs[q];
+        Stream& s = *r.s;
+        const DevHeader& h = e->hdr_mirror[s.slot];
+        const double* hb = e->chk_host + q * per;
+        const double fro2 = hb[0];
+        const double e_inc = std::sqrt(std::max(hb[1], 0.0));
+        double top = 0.0;
+        for (int j = 0; j < std::min(h.k, r.k); ++j) top += hb[8 + j] * hb[8 + j];
+        const double e_opt = std::sqrt(std::max(fro2 - top, 0.0));
+        const double ratio = e_opt > 1e-14 * std::sqrt(fro2) ? e_inc / e_opt : std::nan("");
+        s.last_ratio = ratio;
+        if (ratio > s.cfg.policy.gamma) {
+            int sweeps = 0;
+            std::memcpy(&sweeps, hb + 2, sizeof(int));
+            if (sweeps < 0) return fail(ISVD_E_CONVERGE, "Rayleigh-Ritz Jacobi did not converge");
+            fire.push_back(r);
+        }
+    }
+    if (fire.empty()) return ISVD_OK;
+    SegProgram C;
+    seg_commit(C, fire);
+    ST_TRY(seg_upload(e, C, e->seg_cjobs, st));
+    for (SegRef& r : fire) HIP_TRY(hipEventRecord(r.s->ev_r0, st));
+    for (const auto& l : C.launches) ST_TRY(seg_launch(l, e->seg_cjobs.p, st));
+    for (SegRef& r : fire) {
+        seg_host_commit(*r.s, r);
+        HIP_TRY(hipEventRecord(r.s->ev_r1, st));
     }
     return ISVD_OK;
 }
@@ -2814,6 +2953,53 @@ isvd_status single_update(isvd_engine* e, Stream& s, int kind, const void* paylo
     return after_update(e, s, st, nullptr);
 }
 
+// The engine's own streams (lanes, rotation lanes, refresh lanes).
+std::vector<hipStream_t> engine_streams(isvd_engine* e) {
+    std::vector<hipStream_t> v;
+    for (hipStream_t q : {e->lane_a, e->lane_b, e->lane_c, e->rot_lane, e->rot_lane_b, e->capture_st})
+        if (q) v.push_back(q);
+    for (auto& l : e->rlanes)
+        if (l.st) v.push_back(l.st);
+    return v;
+}
+
+void bcache_drop_all(isvd_engine* e) {
+    if (e->bcache.empty()) return;
+    (void)hipDeviceSynchronize();
+    for (auto& kv : e->bcache) (void)hipFree(kv.second);
+    e->bcache.clear();
+    e->bcache_bytes = 0;
+}
+
+// A block of at least `bytes` for a new stream whose work runs on `st`:
+// a cached block no more than a quarter larger (st then waits for the engine
+// streams as of the latest release), else a new allocation (after dropping
+// the cache when the device is out of memory).
+isvd_status block_alloc(isvd_engine* e, size_t bytes, hipStream_t st, char** out, size_t* got) {
+    *out = nullptr;
+    if (e->bcache_cap > 0) {
+        auto it = e->bcache.lower_bound(bytes);
+        if (it != e->bcache.end() && it->first <= bytes + bytes / 4) {
+            *out = it->second;
+            *got = it->first;
+            e->bcache_bytes -= it->first;
+            e->bcache.erase(it);
+            for (hipEvent_t ev : e->ev_rel) HIP_TRY(hipStreamWaitEvent(st, ev, 0));
+            return ISVD_OK;
+        }
+    }
+    if (hipMalloc((void**)out, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        bcache_drop_all(e);
+        if (hipMalloc((void**)out, bytes) != hipSuccess) {
+            *out = nullptr;
+            return fail(ISVD_E_NOMEM, "hipMalloc of %zu bytes failed", bytes);
+        }
+    }
+    *got = bytes;
+    return ISVD_OK;
+}
+
 void free_stream(isvd_engine* e, Stream* s) {
     if (!s) return;
     if (s->base) {
@@ -2912,6 +3098,14 @@ isvd_status isvd_engine_destroy(isvd_engine* e) {
     if (e->hdr_dev) (void)hipFree(e->hdr_dev);
     if (e->chain_plan) (void)hipFree(e->chain_plan);
     if (e->hdr_mirror) (void)hipHostFree(e->hdr_mirror);
+    for (auto& kv : e->bcache) (void)hipFree(kv.second);
+    e->bcache.clear();
+    for (hipEvent_t ev : e->ev_rel) (void)hipEventDestroy(ev);
+    if (e->seg_cws.p) (void)hipFree(e->seg_cws.p);
+    free_retired(e->seg_cws);
+    if (e->seg_cjobs.p) (void)hipFree(e->seg_cjobs.p);
+    free_retired(e->seg_cjobs);
+    if (e->chk_host) (void)hipHostFree(e->chk_host);
     if (e->seg_ws.p) (void)hipFree(e->seg_ws.p);
     free_retired(e->seg_ws);
     if (e->seg_jobs.p) (void)hipFree(e->seg_jobs.p);
@@ -2992,6 +3186,14 @@ isvd_status isvd_set_deferred_u(isvd_engine* e, int32_t enable, void* hip_stream
         }
     }
     e->defer_u = enable != 0;
+    return ISVD_OK;
+}
+
+isvd_status isvd_set_block_cache(isvd_engine* e, uint64_t bytes) {
+    if (!e) return fail(ISVD_E_INVAL, "null engine");
+    (void)hipSetDevice(e->device);
+    e->bcache_cap = (size_t)bytes;
+    if (e->bcache_bytes > e->bcache_cap) bcache_drop_all(e);
     return ISVD_OK;
 }
 
@@ -3233,11 +3435,13 @@ static isvd_status init_common(isvd_engine* e, const isvd_config* cfg, const voi
         delete s;
         return fail(ISVD_E_NOMEM, "more than %d live streams", kMaxLiveStreams);
     }
-    if (hipMalloc((void**)&s->base, s->L.total) != hipSuccess) {
-        size_t bytes = s->L.total;
-        s->base = nullptr;
-        delete s;
-        return fail(ISVD_E_NOMEM, "hipMalloc of %zu bytes failed", bytes);
+    {
+        isvd_status rc = block_alloc(e, s->L.total, st, &s->base, &s->base_bytes);
+        if (rc != ISVD_OK) {
+            s->base = nullptr;
+            delete s;
+            return rc;
+        }
     }
     e->used += s->L.total;
     char* b = s->base;
@@ -3735,6 +3939,25 @@ isvd_status isvd_release(isvd_engine* e, isvd_id id) {
     Stream* s = nullptr;
     ST_TRY(get_stream(e, id, &s));
     (void)hipSetDevice(e->device);
+    if (e->bcache_cap > 0 && s->base && !s->wbuf && !s->a_host &&
+        e->bcache_bytes + s->base_bytes <= e->bcache_cap) {
+        // keep the block: its own refresh done, then an event on every
+        // engine stream, which the stream that reuses the block waits for
+        if (s->refreshing) HIP_TRY(hipEventSynchronize(s->ev_ready));
+        const std::vector<hipStream_t> es = engine_streams(e);
+        while (e->ev_rel.size() < es.size()) {
+            hipEvent_t ev;
+            HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+            e->ev_rel.push_back(ev);
+        }
+        for (size_t q = 0; q < es.size(); ++q) HIP_TRY(hipEventRecord(e->ev_rel[q], es[q]));
+        e->bcache.emplace(s->base_bytes, s->base);
+        e->bcache_bytes += s->base_bytes;
+        e->used -= s->L.total;
+        s->base = nullptr;
+        free_stream(e, s);
+        return ISVD_OK;
+    }
     (void)hipDeviceSynchronize();
     e->rot_pending = false;
     free_stream(e, s);
@@ -3854,6 +4077,7 @@ isvd_status isvd_tick(isvd_engine* e, int32_t count, const isvd_request* reqs, v
         k_shrink_many<<<1, kShrinkBatch, 0, st>>>(L);
         HIP_TRY(hipGetLastError());
     }
+    if (!d.checks.empty()) ST_TRY(check_batch(e, d.checks, st));
     if (!d.refresh.empty()) ST_TRY(refresh_batch(e, d.refresh, st));
     return ISVD_OK;
 }

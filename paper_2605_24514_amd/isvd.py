@@ -104,7 +104,7 @@ ROT_VARIANTS = [(256, 1, True), (512, 1, True), (1024, 1, True), (1024, 2, False
 EXPORTS = ["isvd_engine_create", "isvd_engine_destroy", "isvd_stream_bytes", "isvd_init", "isvd_init_from_factors",
            "isvd_append_row", "isvd_append_col", "isvd_update_entry", "isvd_refresh", "isvd_refresh_noalloc", "isvd_metrics",
            "isvd_get_factors", "isvd_get_matrix", "isvd_shape", "isvd_release", "isvd_tick",
-           "isvd_profile", "isvd_profile_read", "isvd_autotune", "isvd_set_rotation_variant", "isvd_sync", "isvd_stream_busy", "isvd_rotation_stream", "isvd_set_pipelining", "isvd_set_tick_graphs", "isvd_set_segmented_refresh",
+           "isvd_profile", "isvd_profile_read", "isvd_autotune", "isvd_set_rotation_variant", "isvd_sync", "isvd_stream_busy", "isvd_rotation_stream", "isvd_set_pipelining", "isvd_set_tick_graphs", "isvd_set_segmented_refresh", "isvd_set_block_cache",
            "isvd_server_create", "isvd_server_destroy", "isvd_server_clock", "isvd_server_error",
            "isvd_server_add_stream", "isvd_server_submit", "isvd_server_submit_many", "isvd_server_step", "isvd_server_drain",
            "isvd_server_poll", "isvd_server_stats", "isvd_server_stream", "isvd_last_error",
@@ -152,6 +152,7 @@ def load_library(path=LIB_PATH):
         "isvd_set_pipelining": (i32, [vp, i32]),
         "isvd_set_tick_graphs": (i32, [vp, i32]),
         "isvd_set_segmented_refresh": (i32, [vp, i32]),
+        "isvd_set_block_cache": (i32, [vp, ctypes.c_uint64]),
         "isvd_set_deferred_u": (i32, [vp, i32, vp]),
         "isvd_server_create": (i32, [vp, ctypes.POINTER(CServerConfig), vp, ctypes.POINTER(vp)]),
         "isvd_server_destroy": (i32, [vp]),
@@ -494,6 +495,11 @@ class Engine:
 
     def set_pipelining(self, enable):
         self._check(self._lib.isvd_set_pipelining(self._h, 1 if enable else 0), "isvd_set_pipelining")
+
+    def set_block_cache(self, nbytes):
+        """Keep released streams' device blocks (up to nbytes) for later
+        streams (see isvd_set_block_cache in include/isvd.h)."""
+        self._check(self._lib.isvd_set_block_cache(self._h, int(nbytes)), "isvd_set_block_cache")
 
     def set_segmented_refresh(self, enable):
         """Compute the refreshes one tick fires as one segmented batch (see
