@@ -219,6 +219,18 @@ uint64_t isvd_stream_bytes(const isvd_config* cfg);
 isvd_status isvd_init(isvd_engine* eng, const isvd_config* cfg, const void* A0, int64_t lda,
                       int32_t dtype, int32_t on_device, void* hip_stream, isvd_id* out);
 
+/* Create `count` streams at once, each as isvd_init with A0[q] on the
+ * device (leading dimension lda[q], dtype[q]): the initial TruncatedSVDs
+ * (Sec. 2.4.1) of the FP32 streams whose SVD runs in the A form go as one
+ * segmented batch (isvd_set_segmented_refresh), the others one by one on the
+ * refresh lanes, as isvd_init does.  ids[q] receives stream q's id.  On an
+ * error while creating stream q the streams before it stay valid and
+ * *created = q; if the batched SVD cannot be queued, every stream of the call
+ * is released and *created = 0.  Errors: those of isvd_init. */
+isvd_status isvd_init_batch(isvd_engine* eng, int32_t count, const isvd_config* cfgs, const void* const* A0,
+                            const int64_t* lda, const int32_t* dtype, void* hip_stream, isvd_id* ids,
+                            int32_t* created);
+
 /* Like isvd_init, but the stream starts from the given factors instead of
  * TruncatedSVD(A_0, k) (checkpoint restore; running two precisions from one
  * state): U (m0 x k, ldu), S (k, non-increasing), V (n0 x k, ldv) are FP64

@@ -2600,8 +2600,13 @@ bool seg_eligible(const Stream& s) {
 
 // The refresh of stream s as a batch entry, its header from e->hdr_mirror;
 // its workspace region starts at *total, which moves past it.
-SegRef seg_ref(isvd_engine* e, Stream& s, size_t* total) {
-    const DevHeader& h = e->hdr_mirror[s.slot];
+SegRef seg_ref(isvd_engine* e, Stream& s, size_t* total, bool init = false) {
+    DevHeader h{};
+    if (init) {
+        h.ld = 4;   // the start block takes no column of V
+    } else {
+        h = e->hdr_mirror[s.slot];
+    }
     SegRef r{};
     r.s = &s;
     refresh_block(s, &r.k, &r.b);
@@ -2609,7 +2614,7 @@ SegRef seg_ref(isvd_engine* e, Stream& s, size_t* total) {
     r.n = s.n;
     r.lda = lda_of(s.cfg);
     r.exact = r.b == r.n;
-    r.iters = r.exact ? 0 : s.cfg.refresh_iters >= 0 ? s.cfg.refresh_iters : 3;
+    r.iters = r.exact ? 0 : s.cfg.refresh_iters >= 0 ? s.cfg.refresh_iters : (init ? 8 : 3);
     r.ldo = round4(r.k);
     r.cur = h.cur;
     r.ld = h.ld;
@@ -2644,8 +2649,8 @@ isvd_status seg_upload(isvd_engine* e, const SegProgram& P, WsBuf& dev, hipStrea
 }
 
 // Host state after a committed refresh, as do_refresh / refresh_commit /
-// defer_after_refresh leave it.
-void seg_host_commit(Stream& s, const SegRef& r) {
+// defer_after_refresh leave it (a stream's initial SVD counts no refresh).
+void seg_host_commit(Stream& s, const SegRef& r, bool init = false) {
     s.refresh_rounds = 0;
     s.refresh_converged = true;
     s.k_target = r.k;
@@ -2654,17 +2659,21 @@ void seg_host_commit(Stream& s, const SegRef& r) {
         s.defer_period = defer_period_for(s);
     }
     s.have_refresh_time = true;
-    s.n_refresh += 1;
-    s.t_last = s.t;
+    if (!init) {
+        s.n_refresh += 1;
+        s.t_last = s.t;
+    }
     s.drift_acc = 0.0;
 }
 
 // The refreshes of `list` (all seg_eligible, distinct, their headers in
-// e->hdr_mirror) as one segmented batch on `lane`, after what `lane` holds.
-isvd_status refresh_segmented(isvd_engine* e, const std::vector<Stream*>& list, hipStream_t lane) {
+// e->hdr_mirror) as one segmented batch on `lane`, after what `lane` holds;
+// with `init`, the initial TruncatedSVDs of new streams (random start block).
+isvd_status refresh_segmented(isvd_engine* e, const std::vector<Stream*>& list, hipStream_t lane,
+                              bool init = false) {
     std::vector<SegRef> refs;
     size_t total = 0;
-    for (Stream* sp : list) refs.push_back(seg_ref(e, *sp, &total));
+    for (Stream* sp : list) refs.push_back(seg_ref(e, *sp, &total, init));
     if (!e->seg_ws.retired.empty() && hipStreamQuery(lane) == hipSuccess) free_retired(e->seg_ws);
     if (!e->seg_jobs.retired.empty() && hipStreamQuery(lane) == hipSuccess) free_retired(e->seg_jobs);
     ST_TRY(ensure_ws(e->seg_ws, std::max<size_t>(total, 256)));
@@ -2682,7 +2691,7 @@ isvd_status refresh_segmented(isvd_engine* e, const std::vector<Stream*>& list, 
     for (const auto& l : P.launches) ST_TRY(seg_launch(l, e->seg_jobs.p, lane));
     for (SegRef& r : refs) {
         Stream& s = *r.s;
-        seg_host_commit(s, r);
+        seg_host_commit(s, r, init);
         HIP_TRY(hipEventRecord(s.ev_r1, lane));
         HIP_TRY(hipMemcpyAsync(e->rsweeps + s.slot, e->dsweeps + s.slot, sizeof(int), hipMemcpyDeviceToHost, lane));
         HIP_TRY(hipEventRecord(s.ev_ready, lane));
@@ -3398,7 +3407,8 @@ static isvd_status install_factors(Stream& s, const GivenFactors& f, hipStream_t
 }
 
 static isvd_status init_common(isvd_engine* e, const isvd_config* cfg, const void* A0, int64_t lda, int32_t dtype,
-                               int32_t on_device, const GivenFactors* given, void* hip_stream, isvd_id* out) {
+                               int32_t on_device, const GivenFactors* given, void* hip_stream, isvd_id* out,
+                               std::vector<Stream*>* batch = nullptr) {
     if (!e || !out) return fail(ISVD_E_INVAL, "null engine or output");
     ST_TRY(validate_cfg(cfg));
     if (!A0) return fail(ISVD_E_INVAL, "null A0");
@@ -3553,7 +3563,12 @@ static isvd_status init_common(isvd_engine* e, const isvd_config* cfg, const voi
         rc = ensure_wbuf(*s, st);
         if (rc != ISVD_OK) return bail(rc);
     }
-    rc = given ? install_factors(*s, *given, st) : init_on_lane(e, *s, st);
+    if (given)
+        rc = install_factors(*s, *given, st);
+    else if (batch && e->seg_refresh && seg_eligible(*s))
+        batch->push_back(s);   // the caller runs the batch's initial SVDs together
+    else
+        rc = init_on_lane(e, *s, st);
     if (tmpdev) {
         (void)hipStreamSynchronize(st);
         (void)hipFree(tmpdev);
@@ -3566,6 +3581,46 @@ static isvd_status init_common(isvd_engine* e, const isvd_config* cfg, const voi
 isvd_status isvd_init(isvd_engine* e, const isvd_config* cfg, const void* A0, int64_t lda, int32_t dtype,
                       int32_t on_device, void* hip_stream, isvd_id* out) {
     return init_common(e, cfg, A0, lda, dtype, on_device, nullptr, hip_stream, out);
+}
+
+isvd_status isvd_init_batch(isvd_engine* e, int32_t count, const isvd_config* cfgs, const void* const* A0,
+                            const int64_t* lda, const int32_t* dtype, void* hip_stream, isvd_id* ids,
+                            int32_t* created) {
+    if (!e || count < 0 || (count > 0 && (!cfgs || !A0 || !lda || !dtype || !ids)))
+        return fail(ISVD_E_INVAL, "null argument");
+    if (created) *created = 0;
+    hipStream_t st = (hipStream_t)hip_stream;
+    std::vector<Stream*> batch;
+    isvd_status rc = ISVD_OK;
+    int32_t q = 0;
+    for (; q < count; ++q) {
+        rc = init_common(e, &cfgs[q], A0[q], lda[q], dtype[q], 1, nullptr, hip_stream, &ids[q], &batch);
+        if (rc != ISVD_OK) break;
+    }
+    // the batched initial SVDs on refresh lane 0, after the copies of A_0 on st
+    if (!batch.empty()) {
+        isvd_status rb = ensure_refresh_lanes(e);
+        if (rb == ISVD_OK) {
+            auto& lane = e->rlanes[0];
+            if (hipEventRecord(e->ev_policies, st) != hipSuccess ||
+                hipStreamWaitEvent(lane.st, e->ev_policies, 0) != hipSuccess)
+                rb = fail(ISVD_E_DEVICE, "batch ordering failed");
+            if (rb == ISVD_OK) rb = refresh_segmented(e, batch, lane.st, true);
+            if (rb == ISVD_OK && hipEventRecord(lane.ev, lane.st) != hipSuccess)
+                rb = fail(ISVD_E_DEVICE, "batch event failed");
+            lane.pending = true;
+        }
+        if (rb != ISVD_OK) {
+            // leave no stream without its initial SVD: release every stream of the call
+            for (int32_t i = 0; i < q; ++i) {
+                (void)isvd_release(e, ids[i]);
+                ids[i] = -1;
+            }
+            return rb;
+        }
+    }
+    if (created) *created = q;
+    return rc;
 }
 
 isvd_status isvd_init_from_factors(isvd_engine* e, const isvd_config* cfg, const void* A0, int64_t lda,

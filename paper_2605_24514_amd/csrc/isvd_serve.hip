@@ -252,20 +252,47 @@ isvd_status isvd_server_step(isvd_server* s, int32_t* launched) {
         isvd_status rc = finish_oldest(s, false, &fin);
         if (rc != ISVD_OK) return rc;
     }
-    // admission: FIFO while the footprint fits
-    while (!s->waiting.empty()) {
-        Ticket& t = s->tickets[s->waiting.front()];
-        if (s->cfg.hbm_budget && s->used + t.bytes > s->cfg.hbm_budget) break;
-        isvd_id id = -1;
-        const double a0 = now_s(s);
-        isvd_status rc = isvd_init(s->eng, &t.cfg, t.A0, t.lda, t.dtype, 1, s->st, &id);
-        s->t_admit += now_s(s) - a0;
-        if (rc != ISVD_OK) return sfail(s, rc, "admission failed");
-        t.id = id;
-        t.state = 1;
-        t.admit_s = now_s(s);
-        s->used += t.bytes;
-        s->waiting.pop_front();
+    // admission: FIFO while the footprint fits, the admitted streams created
+    // in one call (their initial SVDs batched)
+    {
+        std::vector<int64_t> adm;
+        uint64_t used = s->used;
+        for (int64_t ti : s->waiting) {
+            const Ticket& t = s->tickets[ti];
+            if (s->cfg.hbm_budget && used + t.bytes > s->cfg.hbm_budget) break;
+            used += t.bytes;
+            adm.push_back(ti);
+        }
+        if (!adm.empty()) {
+            const size_t na = adm.size();
+            std::vector<isvd_config> cfgs(na);
+            std::vector<const void*> a0(na);
+            std::vector<int64_t> lda(na);
+            std::vector<int32_t> dt(na);
+            std::vector<isvd_id> ids(na, -1);
+            for (size_t q = 0; q < na; ++q) {
+                const Ticket& t = s->tickets[adm[q]];
+                cfgs[q] = t.cfg;
+                a0[q] = t.A0;
+                lda[q] = t.lda;
+                dt[q] = t.dtype;
+            }
+            int32_t made = 0;
+            const double a0s = now_s(s);
+            isvd_status rc = isvd_init_batch(s->eng, (int32_t)na, cfgs.data(), a0.data(), lda.data(), dt.data(),
+                                             s->st, ids.data(), &made);
+            const double a1s = now_s(s);
+            s->t_admit += a1s - a0s;
+            for (int32_t q = 0; q < made; ++q) {
+                Ticket& t = s->tickets[adm[q]];
+                t.id = ids[q];
+                t.state = 1;
+                t.admit_s = a1s;
+                s->used += t.bytes;
+                s->waiting.pop_front();
+            }
+            if (rc != ISVD_OK) return sfail(s, rc, "admission failed");
+        }
     }
     // at most max_inflight ticks on the device
     while ((int)s->inflight.size() >= s->cfg.max_inflight) {

@@ -104,7 +104,7 @@ ROT_VARIANTS = [(256, 1, True), (512, 1, True), (1024, 1, True), (1024, 2, False
 EXPORTS = ["isvd_engine_create", "isvd_engine_destroy", "isvd_stream_bytes", "isvd_init", "isvd_init_from_factors",
            "isvd_append_row", "isvd_append_col", "isvd_update_entry", "isvd_refresh", "isvd_refresh_noalloc", "isvd_metrics",
            "isvd_get_factors", "isvd_get_matrix", "isvd_shape", "isvd_release", "isvd_tick",
-           "isvd_profile", "isvd_profile_read", "isvd_autotune", "isvd_set_rotation_variant", "isvd_sync", "isvd_stream_busy", "isvd_rotation_stream", "isvd_set_pipelining", "isvd_set_tick_graphs", "isvd_set_segmented_refresh", "isvd_set_block_cache",
+           "isvd_profile", "isvd_profile_read", "isvd_autotune", "isvd_set_rotation_variant", "isvd_sync", "isvd_stream_busy", "isvd_rotation_stream", "isvd_set_pipelining", "isvd_set_tick_graphs", "isvd_set_segmented_refresh", "isvd_set_block_cache", "isvd_init_batch",
            "isvd_server_create", "isvd_server_destroy", "isvd_server_clock", "isvd_server_error",
            "isvd_server_add_stream", "isvd_server_submit", "isvd_server_submit_many", "isvd_server_step", "isvd_server_drain",
            "isvd_server_poll", "isvd_server_stats", "isvd_server_stream", "isvd_last_error",
@@ -153,6 +153,8 @@ def load_library(path=LIB_PATH):
         "isvd_set_tick_graphs": (i32, [vp, i32]),
         "isvd_set_segmented_refresh": (i32, [vp, i32]),
         "isvd_set_block_cache": (i32, [vp, ctypes.c_uint64]),
+        "isvd_init_batch": (i32, [vp, i32, ctypes.POINTER(CConfig), ctypes.POINTER(vp), ctypes.POINTER(i64),
+                                  ctypes.POINTER(i32), vp, ctypes.POINTER(i64), ctypes.POINTER(i32)]),
         "isvd_set_deferred_u": (i32, [vp, i32, vp]),
         "isvd_server_create": (i32, [vp, ctypes.POINTER(CServerConfig), vp, ctypes.POINTER(vp)]),
         "isvd_server_destroy": (i32, [vp]),
@@ -314,6 +316,32 @@ class Engine:
                                         ctypes.byref(sid)), "isvd_init")
         del keep
         return sid.value
+
+    def init_batch(self, A0s, ks, precision="fp32", m_caps=None, n_caps=None, policy=None, refresh_iters=-1,
+                   oversample=-1, stream=None):
+        """Streams from device tensors A0s (one isvd_init_batch call); returns their ids."""
+        n = len(A0s)
+        cfgs = (CConfig * n)()
+        ptrs = (ctypes.c_void_p * n)()
+        ldas = (ctypes.c_int64 * n)()
+        dts = (ctypes.c_int32 * n)()
+        keep = []
+        for q, A0 in enumerate(A0s):
+            m0, n0 = A0.shape
+            ptr, _, code, dev, k = _payload(A0)
+            if not dev:
+                raise ValueError("init_batch takes device tensors")
+            keep.append(k)
+            cfgs[q] = self.config(m0, n0, ks[q], precision, m_caps[q] if m_caps else None,
+                                  n_caps[q] if n_caps else None, 0.0, policy, refresh_iters, oversample)
+            ptrs[q] = ptr
+            ldas[q] = A0.stride(0)
+            dts[q] = code
+        ids = (ctypes.c_int64 * n)()
+        made = ctypes.c_int32()
+        self._check(self._lib.isvd_init_batch(self._h, n, cfgs, ptrs, ldas, dts, _stream_ptr(stream), ids,
+                                              ctypes.byref(made)), "isvd_init_batch")
+        return [ids[q] for q in range(n)]
 
     def init_from_factors(self, A0, U, S, V, precision="fp32", m_cap=None, n_cap=None, tol_rel=0.0, policy=None,
                           refresh_iters=-1, oversample=-1, stream=None, refresh_tol=0.0):
