@@ -355,6 +355,7 @@ struct isvd_engine {
     size_t bcache_cap = 0, bcache_bytes = 0;
     std::multimap<size_t, char*> bcache;
     std::vector<hipEvent_t> ev_rel;
+    std::vector<Stream*> releasing;  // released while their refresh still ran: cached once it ends
     // the device headers of all live streams, one array (a slot per stream),
     // so that a tick reads them back with one copy into the pinned mirror
     DevHeader* hdr_dev = nullptr;
@@ -2984,9 +2985,11 @@ void bcache_drop_all(isvd_engine* e) {
 // a cached block no more than a quarter larger (st then waits for the engine
 // streams as of the latest release), else a new allocation (after dropping
 // the cache when the device is out of memory).
+isvd_status release_poll(isvd_engine* e);
 isvd_status block_alloc(isvd_engine* e, size_t bytes, hipStream_t st, char** out, size_t* got) {
     *out = nullptr;
     if (e->bcache_cap > 0) {
+        ST_TRY(release_poll(e));
         auto it = e->bcache.lower_bound(bytes);
         if (it != e->bcache.end() && it->first <= bytes + bytes / 4) {
             *out = it->second;
@@ -3020,11 +3023,10 @@ void free_stream(isvd_engine* e, Stream* s) {
         s->slot = -1;
         s->hdr = nullptr;
     }
-    if (s->ev_u0) (void)hipEventDestroy(s->ev_u0);
-    if (s->ev_u1) (void)hipEventDestroy(s->ev_u1);
-    if (s->ev_r0) (void)hipEventDestroy(s->ev_r0);
-    if (s->ev_r1) (void)hipEventDestroy(s->ev_r1);
-    if (s->ev_ready) (void)hipEventDestroy(s->ev_ready);
+    for (hipEvent_t* ev : {&s->ev_u0, &s->ev_u1, &s->ev_r0, &s->ev_r1, &s->ev_ready}) {
+        if (*ev) (void)hipEventDestroy(*ev);
+        *ev = nullptr;
+    }
     if (s->wbuf) (void)hipFree(s->wbuf);
     s->wbuf = nullptr;
     if (s->a_host) (void)hipHostFree(s->a_host);
@@ -3107,6 +3109,7 @@ isvd_status isvd_engine_destroy(isvd_engine* e) {
     if (e->hdr_dev) (void)hipFree(e->hdr_dev);
     if (e->chain_plan) (void)hipFree(e->chain_plan);
     if (e->hdr_mirror) (void)hipHostFree(e->hdr_mirror);
+    e->releasing.clear();   // their streams are freed with the others above
     for (auto& kv : e->bcache) (void)hipFree(kv.second);
     e->bcache.clear();
     for (hipEvent_t ev : e->ev_rel) (void)hipEventDestroy(ev);
@@ -3990,28 +3993,69 @@ isvd_status isvd_shape(isvd_engine* e, isvd_id id, int64_t* m, int64_t* n, int32
     return ISVD_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Move a released stream's block into the cache: an event on every engine
+// stream (the reusing stream creation waits for them), then the block kept
+// and the rest of the stream freed.  Its refresh, if any, has ended.
+isvd_status bcache_keep(isvd_engine* e, Stream* s) {
+    if (e->bcache_bytes + s->base_bytes > e->bcache_cap) {
+        (void)hipDeviceSynchronize();
+        free_stream(e, s);
+        return ISVD_OK;
+    }
+    const std::vector<hipStream_t> es = engine_streams(e);
+    while (e->ev_rel.size() < es.size()) {
+        hipEvent_t ev;
+        HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        e->ev_rel.push_back(ev);
+    }
+    for (size_t q = 0; q < es.size(); ++q) HIP_TRY(hipEventRecord(e->ev_rel[q], es[q]));
+    e->bcache.emplace(s->base_bytes, s->base);
+    e->bcache_bytes += s->base_bytes;
+    e->used -= s->L.total;
+    s->base = nullptr;
+    free_stream(e, s);
+    return ISVD_OK;
+}
+
+// Released streams whose refresh has ended since: into the cache.
+isvd_status release_poll(isvd_engine* e) {
+    for (size_t q = 0; q < e->releasing.size();) {
+        Stream* s = e->releasing[q];
+        if (hipEventQuery(s->ev_ready) != hipSuccess) {
+            ++q;
+            continue;
+        }
+        e->releasing[q] = e->releasing.back();
+        e->releasing.pop_back();
+        s->refreshing = false;
+        ST_TRY(bcache_keep(e, s));
+    }
+    return ISVD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 isvd_status isvd_release(isvd_engine* e, isvd_id id) {
     Stream* s = nullptr;
     ST_TRY(get_stream(e, id, &s));
     (void)hipSetDevice(e->device);
-    if (e->bcache_cap > 0 && s->base && !s->wbuf && !s->a_host &&
-        e->bcache_bytes + s->base_bytes <= e->bcache_cap) {
-        // keep the block: its own refresh done, then an event on every
-        // engine stream, which the stream that reuses the block waits for
-        if (s->refreshing) HIP_TRY(hipEventSynchronize(s->ev_ready));
-        const std::vector<hipStream_t> es = engine_streams(e);
-        while (e->ev_rel.size() < es.size()) {
-            hipEvent_t ev;
-            HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-            e->ev_rel.push_back(ev);
+    if (e->bcache_cap > 0 && s->base && !s->wbuf && !s->a_host) {
+        ST_TRY(release_poll(e));
+        // a refresh still running keeps the stream (its header slot and
+        // block) until it ends; no wait here
+        if (s->refreshing && hipEventQuery(s->ev_ready) != hipSuccess) {
+            s->live = false;
+            e->releasing.push_back(s);
+            return ISVD_OK;
         }
-        for (size_t q = 0; q < es.size(); ++q) HIP_TRY(hipEventRecord(e->ev_rel[q], es[q]));
-        e->bcache.emplace(s->base_bytes, s->base);
-        e->bcache_bytes += s->base_bytes;
-        e->used -= s->L.total;
-        s->base = nullptr;
-        free_stream(e, s);
-        return ISVD_OK;
+        s->refreshing = false;
+        return bcache_keep(e, s);
     }
     (void)hipDeviceSynchronize();
     e->rot_pending = false;
