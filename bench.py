@@ -237,6 +237,8 @@ def serve_run(args):
     del reqs
     ticket = np.full(N, -1, dtype=np.int64)
     window = args.serve_window
+    # each stream's requests (positions in arrival order), for its join
+    by_stream = np.split(np.argsort(own, kind="stable"), np.cumsum(np.bincount(own, minlength=N))[:-1])
 
     def join(s):
         m0, n0, k = params[s]
@@ -256,32 +258,26 @@ def serve_run(args):
     log("serving: %d requests prepared" % total)
     t_start = srv.clock()
     pos, joined, ndone, done = 0, 0, 0, []
-    held = np.zeros(0, dtype=np.int64)
     last = time.perf_counter()
     while ndone < total:
-        grew = False
         while joined < N and srv.held_a0() < window:
             join(joined)
+            # the requests that arrived before the stream joined
+            mine = by_stream[joined]
+            submit(mine[mine < pos])
             joined += 1
-            grew = True
-        if grew and len(held):
-            ok_now = ticket[own[held]] >= 0
-            submit(held[ok_now])
-            held = held[~ok_now]
         now = srv.clock() - t_start
         hi = int(np.searchsorted(arr, now, side="right"))
         if hi > pos:
             idx = np.arange(pos, hi)
-            ok_now = ticket[own[idx]] >= 0
-            submit(idx[ok_now])
-            held = np.concatenate([held, idx[~ok_now]])
+            submit(idx[ticket[own[idx]] >= 0])
             pos = hi
         srv.step()
         c = srv.poll_array()
         if len(c):
             done.append(c)
             ndone += len(c)
-        if pos >= total and len(held) == 0 and srv.stats()["queued"] == 0:
+        if pos >= total and joined == N and srv.stats()["queued"] == 0:
             srv.drain()
             c = srv.poll_array()
             done.append(c)

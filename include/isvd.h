@@ -351,12 +351,15 @@ isvd_status isvd_release(isvd_engine* eng, isvd_id id);
 
 /* Block cache for engines that create and release many streams (serving):
  * with bytes > 0, isvd_release keeps a stream's device block (up to `bytes`
- * in all) instead of freeing it, after waiting for the stream's own refresh
- * and recording an event on each of the engine's streams; a later isvd_init
+ * in all) instead of freeing it, once the stream's own refresh has ended,
+ * recording then an event on each of the engine's streams; a later isvd_init
  * whose block needs at most that size and at least four fifths of it reuses
  * the block, its work on the caller's stream ordered after those events.
- * Neither call then waits for the whole device.  The caller must have
- * completed, or ordered before that later isvd_init's stream, any work it
+ * Neither call then waits for the whole device, except that blocks past
+ * the cap are freed 32 at a time after one wait.  A release during the
+ * stream's own refresh returns at once; the block joins the cache when that
+ * refresh has ended (checked by later releases and creations).  The caller
+ * must have completed, or ordered before that later isvd_init's stream, any work it
  * queued on its own streams that touches the released stream.  Streams with
  * deferred U or A in host memory are freed as before.  bytes = 0 (the
  * default) frees every release at once; lowering the cap below what is

@@ -356,6 +356,7 @@ struct isvd_engine {
     std::multimap<size_t, char*> bcache;
     std::vector<hipEvent_t> ev_rel;
     std::vector<Stream*> releasing;  // released while their refresh still ran: cached once it ends
+    std::vector<char*> to_free;      // blocks past the cap, freed together after one device wait
     // the device headers of all live streams, one array (a slot per stream),
     // so that a tick reads them back with one copy into the pinned mirror
     DevHeader* hdr_dev = nullptr;
@@ -2974,11 +2975,13 @@ std::vector<hipStream_t> engine_streams(isvd_engine* e) {
 }
 
 void bcache_drop_all(isvd_engine* e) {
-    if (e->bcache.empty()) return;
+    if (e->bcache.empty() && e->to_free.empty()) return;
     (void)hipDeviceSynchronize();
     for (auto& kv : e->bcache) (void)hipFree(kv.second);
     e->bcache.clear();
     e->bcache_bytes = 0;
+    for (char* p : e->to_free) (void)hipFree(p);
+    e->to_free.clear();
 }
 
 // A block of at least `bytes` for a new stream whose work runs on `st`:
@@ -3110,6 +3113,8 @@ isvd_status isvd_engine_destroy(isvd_engine* e) {
     if (e->chain_plan) (void)hipFree(e->chain_plan);
     if (e->hdr_mirror) (void)hipHostFree(e->hdr_mirror);
     e->releasing.clear();   // their streams are freed with the others above
+    for (char* p : e->to_free) (void)hipFree(p);
+    e->to_free.clear();
     for (auto& kv : e->bcache) (void)hipFree(kv.second);
     e->bcache.clear();
     for (hipEvent_t ev : e->ev_rel) (void)hipEventDestroy(ev);
@@ -4000,10 +4005,19 @@ namespace {
 // Move a released stream's block into the cache: an event on every engine
 // stream (the reusing stream creation waits for them), then the block kept
 // and the rest of the stream freed.  Its refresh, if any, has ended.
+constexpr size_t kFreeBatch = 32;   // blocks past the cache's cap freed per device wait
 isvd_status bcache_keep(isvd_engine* e, Stream* s) {
     if (e->bcache_bytes + s->base_bytes > e->bcache_cap) {
-        (void)hipDeviceSynchronize();
+        // past the cap: free it with the next few, after one wait for the device
+        e->to_free.push_back(s->base);
+        e->used -= s->L.total;
+        s->base = nullptr;
         free_stream(e, s);
+        if (e->to_free.size() >= kFreeBatch) {
+            (void)hipDeviceSynchronize();
+            for (char* p : e->to_free) (void)hipFree(p);
+            e->to_free.clear();
+        }
         return ISVD_OK;
     }
     const std::vector<hipStream_t> es = engine_streams(e);
