@@ -86,17 +86,22 @@ __global__ void __launch_bounds__(kTrackColThreads) k_track_col(const Track* __r
                 const int rr = t >> 2, q = t & 3;
                 const int64_t r = rb + rr;
                 double d = 0.0;
-                if (r < r1)
+                if (r < r1) {
+#pragma unroll 8
                     for (int c = q; c < kin; c += 4) d += (double)U[uvo(r, c, ldi)] * sp[c];
+                }
                 d += __shfl_xor(d, 1);
                 d += __shfl_xor(d, 2);
                 if (q == 0) sz[rr] = r < r1 ? ((double)y[r] - d) * inv_rho : 0.0;
             }
             __syncthreads();
             const int nr = (int)min((int64_t)64, r1 - rb);
+            // the loads of a row block issue together (unrolled); the sums run in row order
             if (t < kref) {
+#pragma unroll 16
                 for (int rr = 0; rr < nr; ++rr) acc += (double)Ur[uvo(rb + rr, t, ldr)] * sz[rr];
             } else if (t >= 128 && t < 256 && t - 128 < kin) {
+#pragma unroll 16
                 for (int rr = 0; rr < nr; ++rr) acc += (double)U[uvo(rb + rr, t - 128, ldi)] * sz[rr];
             } else if (t == 256) {
                 for (int rr = 0; rr < nr; ++rr) acc += sz[rr] * sz[rr];
