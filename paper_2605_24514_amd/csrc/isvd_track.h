@@ -242,6 +242,8 @@ __global__ void __launch_bounds__(kThreads) k_track(const Track* __restrict__ tr
         for (int e = tid; e < nr * kout; e += nt) {
             const int i = r0 + e / kout, c = e % kout;
             double s = 0.0;
+            // unrolled so that the loads of M issue together; the sum runs over l in order
+#pragma unroll 8
             for (int l = 0; l < kin; ++l) s += tr.M[i * kc + l] * sQ[l * kout + c];
             if (col) s += s_vec[i] * sQ[kin * kout + c];
             sT[e] = s;
@@ -256,6 +258,7 @@ __global__ void __launch_bounds__(kThreads) k_track(const Track* __restrict__ tr
         const int i = e / kout, c = e % kout;
         double s = 0.0;
         if (i < kin) {
+#pragma unroll 8
             for (int l = 0; l < kin; ++l) s += tr.H[i * kc + l] * sQ[l * kout + c];
             if (col) s += s_vec[kMaxCore + i] * sQ[kin * kout + c];
         } else {
@@ -268,6 +271,7 @@ __global__ void __launch_bounds__(kThreads) k_track(const Track* __restrict__ tr
     for (int e = tid; e < kout * kout; e += nt) {
         const int i = e / kout, c = e % kout;
         double s = 0.0;
+#pragma unroll 8
         for (int l = 0; l < nq; ++l) s += sQ[l * kout + i] * Tg[l * kc + c];
         tr.H[i * kc + c] = s;
     }
