@@ -327,6 +327,7 @@ struct isvd_engine {
         hipEvent_t ev = nullptr;     // recorded after the lane's latest work
         bool pending = false;        // work queued since the last join
         WsBuf ws;
+        WsBuf jobs;                  // job tables of the segmented batches on this lane
     };
     std::vector<RefreshLane> rlanes;
     int next_lane = 0;               // lane of the next stream-creation SVD
@@ -336,8 +337,7 @@ struct isvd_engine {
     // segmented refresh batches (isvd_set_segmented_refresh): the A-form
     // refreshes of FP32 streams that one tick fires, one launch per phase
     bool seg_refresh = true;
-    WsBuf seg_ws;                    // the batch's refresh workspaces, one region per stream
-    WsBuf seg_jobs;                  // device job tables of the batch's launches
+    int seg_lane = 0;                // refresh lane of the next batch (batches rotate over the lanes)
     struct SegSlot {
         char* host = nullptr;        // pinned staging of the job tables
         size_t bytes = 0;
@@ -2312,9 +2312,8 @@ isvd_status ensure_refresh_lanes(isvd_engine* e) {
         HIP_TRY(hipStreamCreateWithFlags(&l.st, hipStreamNonBlocking));
         HIP_TRY(hipEventCreateWithFlags(&l.ev, hipEventDisableTiming));
         l.ws.defer_free = true;
+        l.jobs.defer_free = true;
     }
-    e->seg_ws.defer_free = true;
-    e->seg_jobs.defer_free = true;
     e->seg_cws.defer_free = true;
     e->seg_cjobs.defer_free = true;
     for (auto& q : e->seg_slot) HIP_TRY(hipEventCreateWithFlags(&q.ev, hipEventDisableTiming));
@@ -2669,17 +2668,21 @@ void seg_host_commit(Stream& s, const SegRef& r, bool init = false) {
 }
 
 // The refreshes of `list` (all seg_eligible, distinct, their headers in
-// e->hdr_mirror) as one segmented batch on `lane`, after what `lane` holds;
-// with `init`, the initial TruncatedSVDs of new streams (random start block).
-isvd_status refresh_segmented(isvd_engine* e, const std::vector<Stream*>& list, hipStream_t lane,
+// e->hdr_mirror) as one segmented batch on refresh lane `L` (its workspace
+// holds the streams' regions), after what the lane holds; with `init`, the
+// initial TruncatedSVDs of new streams (random start block).
+isvd_status refresh_segmented(isvd_engine* e, const std::vector<Stream*>& list, isvd_engine::RefreshLane& L,
                               bool init = false) {
+    hipStream_t lane = L.st;
     std::vector<SegRef> refs;
     size_t total = 0;
     for (Stream* sp : list) refs.push_back(seg_ref(e, *sp, &total, init));
-    if (!e->seg_ws.retired.empty() && hipStreamQuery(lane) == hipSuccess) free_retired(e->seg_ws);
-    if (!e->seg_jobs.retired.empty() && hipStreamQuery(lane) == hipSuccess) free_retired(e->seg_jobs);
-    ST_TRY(ensure_ws(e->seg_ws, std::max<size_t>(total, 256)));
-    for (SegRef& r : refs) r.ws = e->seg_ws.p + r.off;
+    if (hipStreamQuery(lane) == hipSuccess) {
+        free_retired(L.ws);
+        free_retired(L.jobs);
+    }
+    ST_TRY(ensure_ws(L.ws, std::max<size_t>(total, 256)));
+    for (SegRef& r : refs) r.ws = L.ws.p + r.off;
     // groups of equal (exact, iters): the same launch sequence
     std::map<std::pair<int, int>, std::vector<SegRef>> groups;
     for (SegRef& r : refs) groups[{r.exact ? 1 : 0, r.iters}].push_back(r);
@@ -2688,9 +2691,9 @@ isvd_status refresh_segmented(isvd_engine* e, const std::vector<Stream*>& list, 
         seg_compute(e, P, kv.second);
         seg_commit(P, kv.second);
     }
-    ST_TRY(seg_upload(e, P, e->seg_jobs, lane));
+    ST_TRY(seg_upload(e, P, L.jobs, lane));
     for (Stream* sp : list) HIP_TRY(hipEventRecord(sp->ev_r0, lane));
-    for (const auto& l : P.launches) ST_TRY(seg_launch(l, e->seg_jobs.p, lane));
+    for (const auto& l : P.launches) ST_TRY(seg_launch(l, L.jobs.p, lane));
     for (SegRef& r : refs) {
         Stream& s = *r.s;
         seg_host_commit(s, r, init);
@@ -2801,9 +2804,9 @@ isvd_status check_batch(isvd_engine* e, const std::vector<Stream*>& list, hipStr
 
 isvd_status refresh_batch(isvd_engine* e, const std::vector<Stream*>& all, hipStream_t st) {
     ST_TRY(ensure_refresh_lanes(e));
-    // FP32 streams refreshing in the A form go as one segmented batch on
-    // lane 0 (when there are at least two of them), the rest one by one on
-    // the lanes
+    // FP32 streams refreshing in the A form go as one segmented batch (when
+    // there are at least two of them) on the next refresh lane in turn, so
+    // the batches of successive ticks overlap; the rest one by one on the lanes
     std::vector<Stream*> seg, list;
     for (Stream* sp : all) (e->seg_refresh && seg_eligible(*sp) ? seg : list).push_back(sp);
     if (seg.size() < 2) {
@@ -2819,9 +2822,10 @@ isvd_status refresh_batch(isvd_engine* e, const std::vector<Stream*>& all, hipSt
     HIP_TRY(hipStreamSynchronize(st));
     HIP_TRY(hipEventRecord(e->ev_policies, st));
     if (!seg.empty()) {
-        auto& lane = e->rlanes[0];
+        auto& lane = e->rlanes[e->seg_lane];
+        e->seg_lane = (e->seg_lane + 1) % kRefreshLanes;
         HIP_TRY(hipStreamWaitEvent(lane.st, e->ev_policies, 0));
-        ST_TRY(refresh_segmented(e, seg, lane.st));
+        ST_TRY(refresh_segmented(e, seg, lane));
         HIP_TRY(hipEventRecord(lane.ev, lane.st));
         lane.pending = true;
     }
@@ -3123,10 +3127,6 @@ isvd_status isvd_engine_destroy(isvd_engine* e) {
     if (e->seg_cjobs.p) (void)hipFree(e->seg_cjobs.p);
     free_retired(e->seg_cjobs);
     if (e->chk_host) (void)hipHostFree(e->chk_host);
-    if (e->seg_ws.p) (void)hipFree(e->seg_ws.p);
-    free_retired(e->seg_ws);
-    if (e->seg_jobs.p) (void)hipFree(e->seg_jobs.p);
-    free_retired(e->seg_jobs);
     for (auto& q : e->seg_slot) {
         if (q.host) (void)hipHostFree(q.host);
         if (q.ev) (void)hipEventDestroy(q.ev);
@@ -3134,6 +3134,8 @@ isvd_status isvd_engine_destroy(isvd_engine* e) {
     for (auto& l : e->rlanes) {
         if (l.ws.p) (void)hipFree(l.ws.p);
         free_retired(l.ws);
+        if (l.jobs.p) (void)hipFree(l.jobs.p);
+        free_retired(l.jobs);
         if (l.ev) (void)hipEventDestroy(l.ev);
         if (l.st) (void)hipStreamDestroy(l.st);
     }
@@ -3605,15 +3607,16 @@ isvd_status isvd_init_batch(isvd_engine* e, int32_t count, const isvd_config* cf
         rc = init_common(e, &cfgs[q], A0[q], lda[q], dtype[q], 1, nullptr, hip_stream, &ids[q], &batch);
         if (rc != ISVD_OK) break;
     }
-    // the batched initial SVDs on refresh lane 0, after the copies of A_0 on st
+    // the batched initial SVDs on the next refresh lane in turn, after the copies of A_0 on st
     if (!batch.empty()) {
         isvd_status rb = ensure_refresh_lanes(e);
         if (rb == ISVD_OK) {
-            auto& lane = e->rlanes[0];
+            auto& lane = e->rlanes[e->seg_lane];
+            e->seg_lane = (e->seg_lane + 1) % kRefreshLanes;
             if (hipEventRecord(e->ev_policies, st) != hipSuccess ||
                 hipStreamWaitEvent(lane.st, e->ev_policies, 0) != hipSuccess)
                 rb = fail(ISVD_E_DEVICE, "batch ordering failed");
-            if (rb == ISVD_OK) rb = refresh_segmented(e, batch, lane.st, true);
+            if (rb == ISVD_OK) rb = refresh_segmented(e, batch, lane, true);
             if (rb == ISVD_OK && hipEventRecord(lane.ev, lane.st) != hipSuccess)
                 rb = fail(ISVD_E_DEVICE, "batch event failed");
             lane.pending = true;
