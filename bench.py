@@ -954,8 +954,8 @@ def main():
         else:
             byts = sum(4.0 * n0 * k + 4.0 * n0 for (m0, n0, k) in sel)
         roof = bound_of(byts, 0.0, FP32_PEAK_TFLOPS, dom_ms)
-        chain_names = {0: "k_proj_chain<1>", 1: "k_proj_chain<2>", 3: "k_uplan_chain + k_rotu_chain (U)",
-                       4: "k_rotv_chain (V)"}
+        chain_names = {0: "k_proj_chain<1>", 1: "k_proj_chain<2>", 3: "k_rotu_chain (U)",
+                       4: "k_rotv_chain (V and the U plan)"}
         roof.update({"traffic": None, "kernel": "%s, %s" % (chain_names[ph] if kdom == 0 else names[ph], what),
                      "launch_ms": round(dom_ms, 4),
                      "bytes_per_launch": int(byts)})

@@ -1,8 +1,8 @@
 // Merged launches of a tick whose requests all belong to the FP32 buckets
 // that take the secular core (ranks up to 64): one launch per phase covers
 // every bucket, so the tick is a chain of kernels on one stream
-//   upload -> projection pass 1 -> pass 2 -> cores -> V rotations
-//          -> U plan -> U rotations
+//   upload -> projection pass 1 -> pass 2 -> cores -> V rotations (and the
+//          U plan) -> U rotations
 // instead of one chain per bucket on parallel lanes.  The merged launch of a
 // phase gives each bucket a range of its blocks; the work of a block is the
 // same code (and the same bits) as in the bucket's own launch.  The U
@@ -18,7 +18,7 @@ namespace isvd {
 constexpr int kChainMax = 4;          // buckets 8, 16, 32, 64
 constexpr int kChainRowsU = 512;      // U rows per block of the planned U rotations
 constexpr int kChainUGrid = 2048;     // blocks of the U-rotation launch (loop past that)
-constexpr int kChainPlanThreads = 1024;
+constexpr int kChainMaxReqs = 16384; // requests of a merged tick at most
 
 // The request lists of one merged launch, one entry per bucket, in launch
 // order; bucket q owns blocks [begin[q], begin[q + 1]).  tbl[q]: request and
@@ -38,10 +38,12 @@ struct MultiGroup {
 // [0] planned blocks, [1, reqs + 2) block prefix, then one code per request
 __host__ __device__ constexpr size_t chain_plan_ints(int reqs) { return 2 + 2 * (size_t)reqs + 2; }
 
-__device__ inline int chain_pick(const MultiGroup& mg, int* bid) {
+// bucket of merged block b (blockIdx.x unless given) and its block in the bucket
+__device__ inline int chain_pick(const MultiGroup& mg, int* bid, int b = -1) {
+    if (b < 0) b = (int)blockIdx.x;
     int q = 0;
-    while (q + 1 < mg.n && (int)blockIdx.x >= mg.begin[q + 1]) ++q;
-    *bid = (int)blockIdx.x - mg.begin[q];
+    while (q + 1 < mg.n && b >= mg.begin[q + 1]) ++q;
+    *bid = b - mg.begin[q];
     return q;
 }
 
@@ -81,55 +83,38 @@ __global__ void __launch_bounds__(kSecCoreThreads) __attribute__((amdgpu_waves_p
     }
 }
 
-// V tiles (part 2) of every bucket, kRotRowsV rows per block
-__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) k_rotv_chain(MultiGroup mg) {
-    int bid;
-    const int q = chain_pick(mg, &bid);
-    const BlockRef br = mg.tbl[q][bid];
-    const Req* rq = mg.reqs[q] + br.req;
-    const int tile = br.tile;
-    switch (mg.kc[q]) {
-        case 8: rotate_mfma_t_block<8, kRotRowsV, 1, true>(rq, tile, 2); break;
-        case 16: rotate_mfma_t_block<16, kRotRowsV, 1, true>(rq, tile, 2); break;
-        case 32: rotate_mfma_t_block<32, kRotRowsV, 1, true>(rq, tile, 2); break;
-        default: rotate_mfma_t_block<64, kRotRowsV, 1, true>(rq, tile, 2); break;
-    }
-}
-
-// Plan of the U rotations (one block of kChainPlanThreads): request g (over
-// the buckets in order) rotates U in ceil(m / kChainRowsU) blocks unless its
-// core skipped it or applied its append to W.  Writes the planned blocks,
-// their prefix over the requests and the request codes (bucket << 24 | index).
-constexpr int kChainPlanPer = 16;   // requests per thread at most (16384 / 1024)
-__global__ void __launch_bounds__(kChainPlanThreads) k_uplan_chain(MultiGroup mg, int* __restrict__ plan) {
-    __shared__ int wsum[kChainPlanThreads / 64];
+// Plan of the U rotations: request g (over the buckets in order) rotates U
+// in ceil(m / kChainRowsU) blocks unless its core skipped it or applied its
+// append to W.  Writes the planned blocks, their prefix over the requests
+// and the request codes (bucket << 24 | index).  Run by one block of
+// kThreads after the cores (the last block of the V launch): each thread
+// takes a run of requests, counts their blocks, and after an exclusive scan
+// over the block writes their prefix entries.
+__device__ inline void chain_plan_block(const MultiGroup& mg, int* __restrict__ plan) {
+    __shared__ int wsum[kThreads / 64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     int G = 0;
     for (int q = 0; q < mg.n; ++q) G += mg.nreq[q];
     int* prefix = plan + 1;
     int* code = plan + 2 + G;
-    const int per = (G + kChainPlanThreads - 1) / kChainPlanThreads;
+    const int per = (G + kThreads - 1) / kThreads;
     const int g0 = tid * per;
-    int bl[kChainPlanPer], cd[kChainPlanPer];
-    int local = 0;
-#pragma unroll
-    for (int i = 0; i < kChainPlanPer; ++i) {
-        bl[i] = 0;
-        cd[i] = 0;
-        const int g = g0 + i;
-        if (i < per && g < G) {
-            int q = 0, base = 0;
-            while (g >= base + mg.nreq[q]) {
-                base += mg.nreq[q];
-                ++q;
-            }
-            const int ri = g - base;
-            const Req& rq = mg.reqs[q][ri];
-            const ISVD_GLOBAL ReqScratch* rs = gmem(rq.rs);
-            bl[i] = (rs->skip || rs->deferred) ? 0 : (int)((rq.m + kChainRowsU - 1) / kChainRowsU);
-            cd[i] = (q << 24) | ri;
-            local += bl[i];
+    auto blocks_of = [&](int g, int* cd) -> int {
+        int q = 0, base = 0;
+        while (g >= base + mg.nreq[q]) {
+            base += mg.nreq[q];
+            ++q;
         }
+        const int ri = g - base;
+        const Req& rq = mg.reqs[q][ri];
+        const ISVD_GLOBAL ReqScratch* rs = gmem(rq.rs);
+        *cd = (q << 24) | ri;
+        return (rs->skip || rs->deferred) ? 0 : (int)((rq.m + kChainRowsU - 1) / kChainRowsU);
+    };
+    int local = 0;
+    for (int i = 0; i < per; ++i) {
+        int cd;
+        if (g0 + i < G) local += blocks_of(g0 + i, &cd);
     }
     // exclusive prefix of `local` over the block: within the wave, then over the waves
     int incl = local;
@@ -142,18 +127,40 @@ __global__ void __launch_bounds__(kChainPlanThreads) k_uplan_chain(MultiGroup mg
     int wbase = 0;
     for (int w = 0; w < wave; ++w) wbase += wsum[w];
     int run = wbase + incl - local;
-#pragma unroll
-    for (int i = 0; i < kChainPlanPer; ++i) {
+    for (int i = 0; i < per; ++i) {
         const int g = g0 + i;
-        if (i < per && g < G) {
-            prefix[g] = run;
-            code[g] = cd[i];
-            run += bl[i];
-        }
+        if (g >= G) break;
+        int cd;
+        const int bl = blocks_of(g, &cd);
+        prefix[g] = run;
+        code[g] = cd;
+        run += bl;
     }
-    if (tid == kChainPlanThreads - 1) {
+    if (tid == kThreads - 1) {
         plan[0] = run;
         prefix[G] = run;
+    }
+}
+
+// V tiles (part 2) of every bucket, kRotRowsV rows per block, after a first
+// block that writes the plan of the U rotations (the cores have run), so
+// that the plan overlaps the V tiles.
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3)))
+k_rotv_chain(MultiGroup mg, int* __restrict__ plan) {
+    if (blockIdx.x == 0) {
+        chain_plan_block(mg, plan);
+        return;
+    }
+    int bid;
+    const int q = chain_pick(mg, &bid, (int)blockIdx.x - 1);
+    const BlockRef br = mg.tbl[q][bid];
+    const Req* rq = mg.reqs[q] + br.req;
+    const int tile = br.tile;
+    switch (mg.kc[q]) {
+        case 8: rotate_mfma_t_block<8, kRotRowsV, 1, true>(rq, tile, 2); break;
+        case 16: rotate_mfma_t_block<16, kRotRowsV, 1, true>(rq, tile, 2); break;
+        case 32: rotate_mfma_t_block<32, kRotRowsV, 1, true>(rq, tile, 2); break;
+        default: rotate_mfma_t_block<64, kRotRowsV, 1, true>(rq, tile, 2); break;
     }
 }
 

@@ -880,7 +880,7 @@ bool chain_ok(const isvd_engine* e, const std::vector<Group>& groups) {
         if (g.fp64 || g.bf16 || g.kc > 64) return false;
         nreq += g.all.size();
     }
-    return nreq <= (size_t)kChainPlanPer * kChainPlanThreads;
+    return nreq <= (size_t)kChainMaxReqs;
 }
 
 isvd_status ensure_chain_plan(isvd_engine* e) {
@@ -927,12 +927,8 @@ isvd_status chain_launch(isvd_engine* e, const std::vector<Group>& groups, const
         case 0: k_proj_chain<1><<<blocks, kThreads, 0, st>>>(mg); break;
         case 1: k_proj_chain<2><<<blocks, kThreads, 0, st>>>(mg); break;
         case 2: k_core_chain<<<blocks, kSecCoreThreads, sizeof(double) * chain_core_lds(), st>>>(mg); break;
-        case 4: k_rotv_chain<<<blocks, kThreads, 0, st>>>(mg); break;
-        default:
-            k_uplan_chain<<<1, kChainPlanThreads, 0, st>>>(mg, e->chain_plan);
-            HIP_TRY(hipGetLastError());
-            k_rotu_chain<<<kChainUGrid, kThreads, 0, st>>>(mg, e->chain_plan);
-            break;
+        case 4: k_rotv_chain<<<blocks + 1, kThreads, 0, st>>>(mg, e->chain_plan); break;
+        default: k_rotu_chain<<<kChainUGrid, kThreads, 0, st>>>(mg, e->chain_plan); break;
     }
     HIP_TRY(hipGetLastError());
     if (e->profiling) {
