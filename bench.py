@@ -240,11 +240,21 @@ def serve_run(args):
     # each stream's requests (positions in arrival order), for its join
     by_stream = np.split(np.argsort(own, kind="stable"), np.cumsum(np.bincount(own, minlength=N))[:-1])
 
+    # A0 of the joining streams in a ring of `window` slots of the largest
+    # size (a slot is reused only after its stream was admitted: at most
+    # `window` streams wait with their A0; admission is in join order), each
+    # generated on the server's stream without a wait, so that the server's
+    # creation of the stream reads it in stream order
+    slot_elems = max(m0 * n0 for (m0, n0, k) in params)
+    with torch.cuda.stream(dev_stream):
+        a0_pool = torch.empty((window, slot_elems), dtype=torch.float32, device="cuda")
+        a0_gen = sdev.AsyncRows(max(p[0] for p in params), max(p[1] for p in params), K_FACTORS)
+
     def join(s):
         m0, n0, k = params[s]
         with torch.cuda.stream(dev_stream):
-            A0 = torch.empty((m0, n0), dtype=torch.float32, device="cuda")
-            sdev.rows_into(A0, 0, m0, n0, SEED, s, K_FACTORS)
+            A0 = a0_pool[s % window, :m0 * n0].view(m0, n0)
+            a0_gen.rows_into(A0, 0, m0, n0, SEED, s, dev_stream.cuda_stream)
             ticket[s] = srv.add_stream(A0, min(k, n0), m_cap=m0 + L, n_cap=n0 + L, lifetime=L,
                                        policy=policies[int(pol_kind[s])], refresh_iters=1)
 
@@ -259,21 +269,31 @@ def serve_run(args):
     t_start = srv.clock()
     pos, joined, ndone, done = 0, 0, 0, []
     last = time.perf_counter()
+    hs = {"join": 0.0, "submit": 0.0, "step": 0.0, "poll": 0.0}   # the harness's own host seconds
     while ndone < total:
+        h0 = time.perf_counter()
         while joined < N and srv.held_a0() < window:
             join(joined)
             # the requests that arrived before the stream joined
             mine = by_stream[joined]
             submit(mine[mine < pos])
             joined += 1
+        h1 = time.perf_counter()
         now = srv.clock() - t_start
         hi = int(np.searchsorted(arr, now, side="right"))
         if hi > pos:
             idx = np.arange(pos, hi)
             submit(idx[ticket[own[idx]] >= 0])
             pos = hi
+        h2 = time.perf_counter()
         srv.step()
+        h3 = time.perf_counter()
         c = srv.poll_array()
+        h4 = time.perf_counter()
+        hs["join"] += h1 - h0
+        hs["submit"] += h2 - h1
+        hs["step"] += h3 - h2
+        hs["poll"] += h4 - h3
         if len(c):
             done.append(c)
             ndone += len(c)
@@ -307,7 +327,8 @@ def serve_run(args):
     st = srv.stats()
     out["server"] = {"ticks": st["ticks"], "requests_per_tick": round(st["tick_requests"] / max(st["ticks"], 1), 1),
                      "host_s": {"admission": round(st["host_admit_s"], 3), "tick_calls": round(st["host_tick_s"], 3),
-                                "waits": round(st["host_wait_s"], 3), "releases": round(st["host_release_s"], 3)}}
+                                "waits": round(st["host_wait_s"], 3), "releases": round(st["host_release_s"], 3)},
+                     "harness_s": {q: round(v, 3) for q, v in hs.items()}}
     srv.close()
     eng.close()
     return out

@@ -99,7 +99,25 @@ extern "C" {
 // Rows [row0, row0 + rows) of stream (seed, stream)'s panel with `cols`
 // columns (entries created by those rows): out is rows x cols, leading
 // dimension ld, float (dtype 0) or double (dtype 1), device memory.
-// lam: K factor variances (host).  Returns 0 or a hipError_t value.
+// F (rows x K), B (cols x K) and L (the K factor variances) are device
+// buffers; the launches are queued on st.
+static hipError_t synth_launch(void* out, int64_t ld, int32_t dtype, int64_t row0, int64_t rows, int64_t cols,
+                               uint32_t seed, uint32_t stream, int32_t K, const double* L, double noise, double* F,
+                               double* B, hipStream_t st) {
+    k_factors<<<(unsigned)((rows * K + 255) / 256), 256, 0, st>>>(F, row0, rows, K, L, seed, stream);
+    k_loadings<<<(unsigned)((cols * K + 255) / 256), 256, 0, st>>>(B, cols, K, seed, stream);
+    const int64_t work = rows * ((cols + 1) / 2);
+    if (dtype == 1)
+        k_rows<double><<<(unsigned)((work + 255) / 256), 256, 0, st>>>((double*)out, ld, F, B, rows, cols, K, noise,
+                                                                      row0, seed, stream);
+    else
+        k_rows<float><<<(unsigned)((work + 255) / 256), 256, 0, st>>>((float*)out, ld, F, B, rows, cols, K, noise,
+                                                                     row0, seed, stream);
+    return hipGetLastError();
+}
+
+// As above; lam: K factor variances (host).  Allocates its buffers and
+// waits for the stream.  Returns 0 or a hipError_t value.
 int synth_rows(void* out, int64_t ld, int32_t dtype, int64_t row0, int64_t rows, int64_t cols, uint32_t seed,
                uint32_t stream, int32_t K, const double* lam, double noise, void* hip_stream) {
     hipStream_t st = (hipStream_t)hip_stream;
@@ -109,23 +127,22 @@ int synth_rows(void* out, int64_t ld, int32_t dtype, int64_t row0, int64_t rows,
     if ((e = hipMalloc(&B, sizeof(double) * cols * K)) != hipSuccess) { (void)hipFree(F); return (int)e; }
     if ((e = hipMalloc(&L, sizeof(double) * K)) != hipSuccess) { (void)hipFree(F); (void)hipFree(B); return (int)e; }
     e = hipMemcpyAsync(L, lam, sizeof(double) * K, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) {
-        k_factors<<<(unsigned)((rows * K + 255) / 256), 256, 0, st>>>(F, row0, rows, K, L, seed, stream);
-        k_loadings<<<(unsigned)((cols * K + 255) / 256), 256, 0, st>>>(B, cols, K, seed, stream);
-        const int64_t work = rows * ((cols + 1) / 2);
-        if (dtype == 1)
-            k_rows<double><<<(unsigned)((work + 255) / 256), 256, 0, st>>>((double*)out, ld, F, B, rows, cols, K,
-                                                                          noise, row0, seed, stream);
-        else
-            k_rows<float><<<(unsigned)((work + 255) / 256), 256, 0, st>>>((float*)out, ld, F, B, rows, cols, K,
-                                                                         noise, row0, seed, stream);
-        e = hipGetLastError();
-    }
+    if (e == hipSuccess) e = synth_launch(out, ld, dtype, row0, rows, cols, seed, stream, K, L, noise, F, B, st);
     hipError_t e2 = hipStreamSynchronize(st);
     (void)hipFree(F);
     (void)hipFree(B);
     (void)hipFree(L);
     return (int)(e != hipSuccess ? e : e2);
+}
+
+// The same rows, queued on hip_stream without allocating or waiting: L_dev
+// (the K factor variances), F_dev (at least rows x K) and B_dev (at least
+// cols x K) are device buffers of the caller, reused only in stream order.
+int synth_rows_async(void* out, int64_t ld, int32_t dtype, int64_t row0, int64_t rows, int64_t cols, uint32_t seed,
+                     uint32_t stream, int32_t K, const double* L_dev, double noise, double* F_dev, double* B_dev,
+                     void* hip_stream) {
+    return (int)synth_launch(out, ld, dtype, row0, rows, cols, seed, stream, K, L_dev, noise, F_dev, B_dev,
+                             (hipStream_t)hip_stream);
 }
 
 }  // extern "C"

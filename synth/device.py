@@ -41,6 +41,11 @@ def _load():
         lib.synth_rows.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
                                    ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int32,
                                    ctypes.POINTER(ctypes.c_double), ctypes.c_double, ctypes.c_void_p]
+        lib.synth_rows_async.restype = ctypes.c_int
+        lib.synth_rows_async.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64,
+                                         ctypes.c_int64, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint32,
+                                         ctypes.c_int32, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_void_p]
         _lib = lib
     return _lib
 
@@ -56,3 +61,30 @@ def rows_into(out, row0, rows, cols, seed, stream, K, noise=0.1, lambdas=None, l
     if rc != 0:
         raise RuntimeError("synth_rows failed with HIP error %d" % rc)
     return out
+
+
+class AsyncRows:
+    """Device rows of panels with at most max_rows x max_cols entries,
+    queued on one HIP stream without allocating or waiting (the buffers are
+    reused in that stream's order)."""
+
+    def __init__(self, max_rows, max_cols, K, lambdas=None, device="cuda"):
+        import torch
+        self.K = K
+        lam = np.ascontiguousarray(lambdas if lambdas is not None else factor_lambdas(K), dtype=np.float64)
+        self.L = torch.tensor(lam, dtype=torch.float64, device=device)
+        self.F = torch.empty(max_rows * K, dtype=torch.float64, device=device)
+        self.B = torch.empty(max_cols * K, dtype=torch.float64, device=device)
+        self.max_rows, self.max_cols = max_rows, max_cols
+
+    def rows_into(self, out, row0, rows, cols, seed, stream, hip_stream, noise=0.1, ld=None):
+        if rows > self.max_rows or cols > self.max_cols:
+            raise ValueError("panel larger than the buffers")
+        dtype = 1 if str(out.dtype) == "torch.float64" else 0
+        rc = _load().synth_rows_async(ctypes.c_void_p(out.data_ptr()), ld or cols, dtype, row0, rows, cols, seed,
+                                      stream, self.K, ctypes.c_void_p(self.L.data_ptr()), noise,
+                                      ctypes.c_void_p(self.F.data_ptr()), ctypes.c_void_p(self.B.data_ptr()),
+                                      ctypes.c_void_p(hip_stream))
+        if rc != 0:
+            raise RuntimeError("synth_rows_async failed with HIP error %d" % rc)
+        return out

@@ -25,3 +25,24 @@ def test_device_rows_match_host_generator():
         ref = fs.row(1000 + r, 75).astype(np.float32)
         got = out32[r].cpu().numpy()
         assert np.max(np.abs(got - ref)) <= 2 * np.finfo(np.float32).eps * np.max(np.abs(ref))
+
+
+@pytest.mark.gpu
+def test_async_rows_match_the_synchronous_generator():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from synth import device
+    st = torch.cuda.Stream()
+    gen = device.AsyncRows(300, 90, 5)
+    # two panels in a row on one stream (the second smaller), the buffers reused in stream order
+    for (row0, rows, cols, s) in [(0, 300, 90, 4), (77, 41, 33, 9)]:
+        ref = torch.empty((rows, cols), dtype=torch.float32, device="cuda")
+        device.rows_into(ref, row0, rows, cols, 3, s, 5)
+        with torch.cuda.stream(st):
+            got = torch.empty((rows, cols), dtype=torch.float32, device="cuda")
+            gen.rows_into(got, row0, rows, cols, 3, s, st.cuda_stream)
+        st.synchronize()
+        assert torch.equal(got, ref)
+    with pytest.raises(ValueError):
+        gen.rows_into(ref, 0, 301, 10, 3, 0, st.cuda_stream)
