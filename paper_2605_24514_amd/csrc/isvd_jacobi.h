@@ -139,6 +139,7 @@ __device__ inline int jacobi_block(double* W, double* J, int N, int ldw, int max
             double* jp = J + (size_t)p * ldw;
             double* jq = J + (size_t)q * ldw;
             double x[S::EPT], y[S::EPT], u[S::EPT], v[S::EPT];
+            if (live) {   // groups without a pair this round issue no LDS traffic
 #pragma unroll
             for (int i = 0; i < S::EPT; ++i) {
                 const int e = lane + i * S::TPP;
@@ -181,6 +182,7 @@ __device__ inline int jacobi_block(double* W, double* J, int N, int ldw, int max
                 }
                 if (lane == 0) s_rot[flag] = 1;
             }
+            }
             __syncthreads();
         }
         const int rotated = s_rot[flag];
@@ -190,6 +192,21 @@ __device__ inline int jacobi_block(double* W, double* J, int N, int ldw, int max
     }
     __syncthreads();
     return sweeps;
+}
+
+// jacobi_block without J on an order-N matrix laid out for the shape of
+// order NMAX_ALL (stride ldw, zero rows from N on): each lane holds only the
+// elements of rows below the smallest of 32, 64, 96 and NMAX_ALL that covers
+// N.  The rows dropped are zero in both columns of every pair, so the dot
+// products lose only terms +-0 and every result is bitwise that of the
+// NMAX_ALL shape, with a fraction of its LDS reads and writes.
+template <int NMAX_ALL, int TPP>
+__device__ inline int jacobi_block_fit(double* W, int N, int ldw, int max_sweeps, double tol_min = 0.0) {
+    static_assert(NMAX_ALL > 96, "shape of the widest order");
+    if (N <= 32) return jacobi_block<32, false, TPP>(W, nullptr, N, ldw, max_sweeps, tol_min);
+    if (N <= 64) return jacobi_block<64, false, TPP>(W, nullptr, N, ldw, max_sweeps, tol_min);
+    if (N <= 96) return jacobi_block<96, false, TPP>(W, nullptr, N, ldw, max_sweeps, tol_min);
+    return jacobi_block<NMAX_ALL, false, TPP>(W, nullptr, N, ldw, max_sweeps, tol_min);
 }
 
 // Singular values of W's columns sorted non-increasing (ties: lower column

@@ -751,7 +751,7 @@ __device__ __attribute__((always_inline)) inline void k_svd_small_noj_body(
         W[e] = (row < N && col < N) ? R[col * N + row] : 0.0;
     }
     __syncthreads();
-    const int sweeps = jacobi_block<kMaxBlock + 1, false, 8>(W, nullptr, N, ldw, 60);
+    const int sweeps = jacobi_block_fit<kMaxBlock + 1, 8>(W, N, ldw, 60);
     jacobi_sort(W, N, ldw, sig, perm, tmp);
     // sign: the largest-magnitude entry of each right vector positive
     for (int j = threadIdx.x; j < k; j += blockDim.x) {
@@ -935,7 +935,7 @@ __global__ void __launch_bounds__(WideShape::NT) k_sym_norm2(const double* __res
         W[e] = (row < k && col < k) ? G[row * k + col] - (row == col ? 1.0 : 0.0) : 0.0;
     }
     __syncthreads();
-    const int sweeps = jacobi_block<kMaxBlock + 1, false, WideShape::TPP>(W, nullptr, k, ldw, 60);
+    const int sweeps = jacobi_block_fit<kMaxBlock + 1, WideShape::TPP>(W, k, ldw, 60);
     for (int c = threadIdx.x; c < k; c += blockDim.x) {
         double s = 0.0;
         for (int e = 0; e < k; ++e) s += W[(size_t)c * ldw + e] * W[(size_t)c * ldw + e];

@@ -180,7 +180,7 @@ __device__ inline double block_theta(const double* M, int ldm, const double* H, 
         }
     }
     __syncthreads();
-    jacobi_block<kMaxBlock + 1, false, WideShape::TPP>(W, nullptr, j, ldw, 60);
+    jacobi_block_fit<kMaxBlock + 1, WideShape::TPP>(W, j, ldw, 60);
     for (int c = tid; c < j; c += nt) {
         double s = 0.0;
         for (int e = 0; e < j; ++e) s += W[(size_t)c * ldw + e] * W[(size_t)c * ldw + e];
