@@ -579,16 +579,15 @@ __global__ void k_sum_parts(const double* __restrict__ P, int nparts, int64_t st
 // step suffices.
 constexpr int kCholThreads = 512;
 constexpr int kCholTY = kCholThreads / 16;   // row groups of the thread grid
-template <typename T>
-__device__ __attribute__((always_inline)) inline void k_chol_inv_body(const double* __restrict__ G, int b,
+template <typename T, int KB>
+__device__ __attribute__((always_inline)) inline void chol_inv_fit(const double* __restrict__ G, int b,
                                                        double* __restrict__ Rout, T* __restrict__ RinvT,
-                                                       int* __restrict__ flag, const int bx_, const int by_,
-    const int gx_) {
-    constexpr int NP = (kMaxBlock + kCholTY - 1) / kCholTY, NQ = 2 * kMaxBlock / 16;
-    __shared__ double s_row[2][2 * kMaxBlock];
-    __shared__ double s_g[kMaxBlock];
-    __shared__ double s_d[kMaxBlock];
-    __shared__ int s_drop[kMaxBlock];
+                                                       int* __restrict__ flag) {
+    constexpr int NP = (KB + kCholTY - 1) / kCholTY, NQ = 2 * KB / 16;
+    __shared__ double s_row[2][2 * KB];
+    __shared__ double s_g[KB];
+    __shared__ double s_d[KB];
+    __shared__ int s_drop[KB];
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
     double g[NP][NQ];
 #pragma unroll
@@ -600,7 +599,7 @@ __device__ __attribute__((always_inline)) inline void k_chol_inv_body(const doub
             if (q < NQ / 2)
                 g[p][q] = (i < b && c < b) ? G[i * b + c] : 0.0;
             else
-                g[p][q] = (i < b && c - kMaxBlock == i) ? 1.0 : 0.0;
+                g[p][q] = (i < b && c - KB == i) ? 1.0 : 0.0;
         }
     }
     for (int j = threadIdx.x; j < b; j += blockDim.x) s_g[j] = G[j * b + j];
@@ -653,11 +652,28 @@ __device__ __attribute__((always_inline)) inline void k_chol_inv_body(const doub
             if (q < NQ / 2) {
                 if (c < b) Rout[i * b + c] = c >= i ? g[p][q] * sc : 0.0;
             } else {
-                const int cc = c - kMaxBlock;
+                const int cc = c - KB;
                 if (cc < b) RinvT[cc * b + i] = (T)(g[p][q] * sc);
             }
         }
     }
+}
+
+
+// The elimination in the register shape of the smallest of 32, 64, 96 and
+// kMaxBlock columns that covers b: every entry of the augmented matrix takes
+// the same operations in the same order in each shape, so the results are
+// bitwise those of the widest one, with fewer registers and FMAs per step.
+template <typename T>
+__device__ __attribute__((always_inline)) inline void k_chol_inv_body(const double* __restrict__ G, int b,
+                                                       double* __restrict__ Rout, T* __restrict__ RinvT,
+                                                       int* __restrict__ flag, const int bx_, const int by_,
+    const int gx_) {
+    static_assert(kMaxBlock > 96, "widest shape");
+    if (b <= 32) chol_inv_fit<T, 32>(G, b, Rout, RinvT, flag);
+    else if (b <= 64) chol_inv_fit<T, 64>(G, b, Rout, RinvT, flag);
+    else if (b <= 96) chol_inv_fit<T, 96>(G, b, Rout, RinvT, flag);
+    else chol_inv_fit<T, kMaxBlock>(G, b, Rout, RinvT, flag);
 }
 
 template <typename T>
