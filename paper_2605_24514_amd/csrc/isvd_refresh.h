@@ -749,12 +749,26 @@ __global__ void __launch_bounds__(kThreads) k_rotate_plain(const T* in, int ldi,
 // sigma_1 / sigma_j, stays far below FP32 rounding for the kept triplets; a
 // coarser threshold would be amplified the same way, so the FP64 one stays.
 typedef WideShape RRShape;
+
+// Column stride of the Rayleigh-Ritz matrix in LDS: for orders up to 96,
+// where the Jacobi runs in a shape covering 32, 64 or 96 rows, the smallest
+// stride = 4 (mod 32) doubles that covers those rows, so that pair groups
+// reading different columns fall on different LDS banks; the order-129
+// shape keeps its own stride.  Only addresses depend on it.
+__host__ __device__ inline int rr_ldw(int N) {
+    if (N > 96) return RRShape::LDW;
+    const int rows = N <= 32 ? 32 : (N <= 64 ? 64 : 96);
+    int st = (N + 27) / 32 * 32 + 4;
+    while (st < rows) st += 32;
+    return st;
+}
+
 template <typename T>
 __device__ __attribute__((always_inline)) inline void k_svd_small_noj_body(
     const double* __restrict__ R, int b, int k, double* __restrict__ S, T* __restrict__ QU, T* __restrict__ QV,
     int ldo, int* __restrict__ sweeps_out, double* smem) {
     const int N = b;
-    const int ldw = RRShape::LDW;
+    const int ldw = rr_ldw(N);
     double* W = smem;                                   // (N + 1) columns
     double* sig = W + (size_t)(N + 1) * ldw;
     double* sgn = sig + N;
