@@ -50,11 +50,23 @@ def _load():
     return _lib
 
 
+def _out_dtype(out, rows, cols, ld):
+    """dtype code of the device tensor `out` after checking that rows x cols
+    entries at leading dimension ld lie inside its storage."""
+    if str(out.dtype) not in ("torch.float32", "torch.float64"):
+        raise TypeError("out must be float32 or float64")
+    if not out.is_cuda or not out.is_contiguous():
+        raise ValueError("out must be a contiguous device tensor")
+    if rows < 0 or cols < 0 or ld < cols or (rows > 0 and (rows - 1) * ld + cols > out.numel()):
+        raise ValueError("rows x cols at leading dimension %d do not fit in out" % ld)
+    return 1 if str(out.dtype) == "torch.float64" else 0
+
+
 def rows_into(out, row0, rows, cols, seed, stream, K, noise=0.1, lambdas=None, ld=None, hip_stream=None):
     """Fill the device tensor `out` (rows x cols, leading dim ld) with rows
     [row0, row0 + rows) of the (seed, stream) panel."""
     lam = np.ascontiguousarray(lambdas if lambdas is not None else factor_lambdas(K), dtype=np.float64)
-    dtype = 1 if str(out.dtype) == "torch.float64" else 0
+    dtype = _out_dtype(out, rows, cols, ld or cols)
     rc = _load().synth_rows(ctypes.c_void_p(out.data_ptr()), ld or cols, dtype, row0, rows, cols, seed, stream, K,
                             lam.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), noise,
                             ctypes.c_void_p(hip_stream) if hip_stream else None)
@@ -80,7 +92,7 @@ class AsyncRows:
     def rows_into(self, out, row0, rows, cols, seed, stream, hip_stream, noise=0.1, ld=None):
         if rows > self.max_rows or cols > self.max_cols:
             raise ValueError("panel larger than the buffers")
-        dtype = 1 if str(out.dtype) == "torch.float64" else 0
+        dtype = _out_dtype(out, rows, cols, ld or cols)
         rc = _load().synth_rows_async(ctypes.c_void_p(out.data_ptr()), ld or cols, dtype, row0, rows, cols, seed,
                                       stream, self.K, ctypes.c_void_p(self.L.data_ptr()), noise,
                                       ctypes.c_void_p(self.F.data_ptr()), ctypes.c_void_p(self.B.data_ptr()),

@@ -2,6 +2,7 @@
 import os
 
 import numpy as np
+import pytest
 
 from synth import philox4x32_10, normals, uniforms, FactorStream, factor_lambdas
 from synth import event_schedule_c0, event_schedule_iid, ROW, COL, ENTRY
@@ -69,3 +70,15 @@ def test_materialize_tracks_shapes():
     assert 0 <= evs[2].i < 21 and 0 <= evs[2].j < 31
     assert evs[3].vec.shape == (31,)
     assert [e.t for e in evs] == [1, 2, 3, 4]
+
+
+def test_device_generator_rejects_outputs_it_cannot_fill():
+    """The device generator's host checks turn an output that is not a
+    contiguous device tensor of the right size into an error before any
+    launch (checked here on the CPU, where no launch can happen)."""
+    torch = pytest.importorskip("torch")
+    from synth import device
+    with pytest.raises(ValueError):
+        device.rows_into(torch.empty((4, 5), dtype=torch.float32), 0, 4, 5, 1, 0, 3)
+    with pytest.raises(TypeError):
+        device.rows_into(torch.empty((4, 5), dtype=torch.int32), 0, 4, 5, 1, 0, 3)
